@@ -1,0 +1,174 @@
+"""Python access to the CPU oracle (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg use this
+package. It loads oracle/liboracle.so (plain C, FP64 brute force; see
+oracle.c for the definitions and the canonical arithmetic it follows) and
+wraps it for numpy arrays. It imports nothing from the GPU package.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+NOPAIR = -2
+DEGENERATE = -4
+
+_i64 = C.c_int64
+_p = C.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(_LIB)
+        L.orc_d2_f32.restype = C.c_double
+        L.orc_d2_f32.argtypes = [_p, _i64, _i64, _i64, _i64]
+        L.orc_d2_f64.restype = C.c_double
+        L.orc_d2_f64.argtypes = [_p, _i64, _i64, _i64, _i64]
+        L.orc_d2_i8.restype = _i64
+        L.orc_d2_i8.argtypes = [_p, _i64, _i64, _i64, _i64]
+        for nm in ("orc_row_d2_f32", "orc_row_d2_f64", "orc_row_d2_i8"):
+            getattr(L, nm).restype = None
+            getattr(L, nm).argtypes = [_p, _i64, _i64, _i64, _i64, _p]
+        L.orc_znorm.restype = C.c_int
+        L.orc_znorm.argtypes = [_p, _i64, _i64, _p, _p, _p]
+        for nm in ("orc_cpp_f32", "orc_cpp_f64", "orc_cpp_i8"):
+            getattr(L, nm).restype = C.c_int
+            getattr(L, nm).argtypes = [_p, _i64, _i64, _i64, _i64, _p, _p, _p]
+        for nm in ("orc_frnn_f32", "orc_frnn_f64", "orc_frnn_i8"):
+            getattr(L, nm).restype = _i64
+            getattr(L, nm).argtypes = [_p, _i64, _i64, _i64, _i64, C.c_double, _p, _p, _i64]
+        L.orc_nn_f32.restype = C.c_int
+        L.orc_nn_f32.argtypes = [_p, _i64, _i64, _i64, _p]
+        L.orc_max_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def _kind(X: np.ndarray) -> str:
+    if X.dtype == np.float32:
+        return "f32"
+    if X.dtype == np.float64:
+        return "f64"
+    if X.dtype == np.int8:
+        return "i8"
+    raise TypeError(f"unsupported dtype {X.dtype}")
+
+
+def _rows(X: np.ndarray):
+    if X.ndim != 2:
+        raise ValueError("expected a 2-D array")
+    if X.strides[1] != X.itemsize or X.strides[0] % X.itemsize:
+        X = np.ascontiguousarray(X)
+    return X, X.shape[0], X.shape[1], X.strides[0] // X.itemsize
+
+
+def max_threads() -> int:
+    return lib().orc_max_threads()
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
+
+
+def d2(X: np.ndarray, i: int, j: int):
+    """Canonical squared distance between rows i and j (float, or int for int8)."""
+    X, n, d, ld = _rows(X)
+    return getattr(lib(), "orc_d2_" + _kind(X))(X.ctypes.data, d, ld, int(i), int(j))
+
+
+def row_d2(X: np.ndarray, i: int) -> np.ndarray:
+    """Canonical squared distance from row i to every row (entry i is 0)."""
+    X, n, d, ld = _rows(X)
+    k = _kind(X)
+    out = np.empty(n, dtype=np.int64 if k == "i8" else np.float64)
+    getattr(lib(), "orc_row_d2_" + k)(X.ctypes.data, n, d, ld, int(i), out.ctypes.data)
+    return out
+
+
+def closest_pair(X: np.ndarray, excl: int = 1):
+    """(i, j, d2) minimising the canonical d2 over i<j, j-i>=excl; ties go to
+    the lexicographically smallest (i, j). None if there is no admissible pair."""
+    X, n, d, ld = _rows(X)
+    oi, oj, od = _i64(), _i64(), C.c_double()
+    rc = getattr(lib(), "orc_cpp_" + _kind(X))(X.ctypes.data, n, d, ld, int(excl),
+                                               C.byref(oi), C.byref(oj), C.byref(od))
+    if rc == NOPAIR:
+        return None
+    if rc != 0:
+        raise RuntimeError(f"oracle closest pair failed: {rc}")
+    if X.dtype == np.int8:
+        return oi.value, oj.value, int(od.value)
+    return oi.value, oj.value, od.value
+
+
+def frnn(X: np.ndarray, R2: float, excl: int = 1):
+    """All pairs i<j (j-i>=excl) with canonical d2 <= R2, sorted by (i, j).
+    Returns (pairs int64 [m,2], d2 [m])."""
+    X, n, d, ld = _rows(X)
+    fn = getattr(lib(), "orc_frnn_" + _kind(X))
+    cap = 1 << 16
+    while True:
+        pairs = np.empty((cap, 2), dtype=np.int64)
+        dd = np.empty(cap, dtype=np.float64)
+        cnt = fn(X.ctypes.data, n, d, ld, int(excl), float(R2), pairs.ctypes.data, dd.ctypes.data, cap)
+        if cnt < 0:
+            raise RuntimeError(f"oracle frnn failed: {cnt}")
+        if cnt <= cap:
+            pairs, dd = pairs[:cnt].copy(), dd[:cnt].copy()
+            if X.dtype == np.int8:
+                dd = dd.astype(np.int64)
+            return pairs, dd
+        cap = int(cnt)
+
+
+def nearest_neighbour_d2(X: np.ndarray) -> np.ndarray:
+    """min over j != i of the canonical d2, for every row i (float32 input)."""
+    X, n, d, ld = _rows(X)
+    if X.dtype != np.float32:
+        raise TypeError("nearest_neighbour_d2 takes float32 points")
+    out = np.empty(n, dtype=np.float64)
+    rc = lib().orc_nn_f32(X.ctypes.data, n, d, ld, out.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"oracle nn failed: {rc}")
+    return out
+
+
+def znorm(T: np.ndarray, ell: int):
+    """Canonical z-normalised windows of T: (Xhat [N, ell] float64, mu, sigma).
+    Raises ValueError if some window has sigma == 0."""
+    T = np.ascontiguousarray(T, dtype=np.float32)
+    N = T.shape[0] - ell + 1
+    if N < 1:
+        raise ValueError("series shorter than the window")
+    Xhat = np.empty((N, ell), dtype=np.float64)
+    mu = np.empty(N, dtype=np.float64)
+    sg = np.empty(N, dtype=np.float64)
+    rc = lib().orc_znorm(T.ctypes.data, T.shape[0], int(ell), Xhat.ctypes.data, mu.ctypes.data, sg.ctypes.data)
+    if rc == DEGENERATE:
+        raise ValueError("a window has zero variance")
+    if rc != 0:
+        raise RuntimeError(f"oracle znorm failed: {rc}")
+    return Xhat, mu, sg
+
+
+def motif(T: np.ndarray, ell: int, excl: int | None = None, R2: float | None = None):
+    """Motif of a series: closest pair of z-normalised windows with j-i >= excl
+    (default excl = ell), plus all admissible pairs with d2 <= R2 if R2 given.
+    Returns (best (i, j, d2) or None, frnn (pairs, d2) or None)."""
+    if excl is None or excl <= 0:
+        excl = ell
+    Xhat, _, _ = znorm(T, ell)
+    best = closest_pair(Xhat, excl)
+    fr = frnn(Xhat, R2, excl) if R2 is not None and R2 >= 0 else None
+    return best, fr

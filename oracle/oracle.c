@@ -1,0 +1,337 @@
+/*
+ * CPU oracle for the exact closest-pair / fixed-radius-neighbour / motif path.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product library calls, links or
+ * loads this file; only the test-suite, the smoke check and the benchmark's
+ * CPU-baseline leg do. It shares no code, header or constant with the GPU path.
+ *
+ * What it computes is the plain definition, by brute force:
+ *
+ *  - Distance (Section 2): d(x,y)^2 = sum_k (x_k - y_k)^2 over the l
+ *    coordinates. The paper's straightforward algorithm evaluates it for every
+ *    pair in O(l) each, O(n^2 l) in total (Section 3, opening paragraph).
+ *  - Closest pair (Section 3, problem statement; MPR step 5 keeps the pair with
+ *    the least distance): the pair i<j of least squared distance. Among exact
+ *    ties the lexicographically smallest (i,j) is reported; iterating i then j
+ *    in ascending order with a strict "<" update yields exactly that pair.
+ *  - Fixed-radius neighbours (Section 3.5, MPR-FRNNS step 5): every pair i<j
+ *    with d <= R, tested on squared values as d^2 <= R2 with R2 given by the
+ *    caller. N(i) is the symmetric closure of this list.
+ *  - Motif (Section 2 l-mers; Section 3): the windows T_i = a_i..a_{i+l-1} are
+ *    z-normalised and a pair is admissible only when j - i >= excl (trivial
+ *    matches of overlapping windows are excluded).
+ *
+ * Canonical arithmetic (makes "exact match" well defined; the GPU verifier is
+ * written independently to the same rules):
+ *  - float32 inputs are promoted exactly to double;
+ *  - d^2 = acc with acc = 0 and, for k = 0..d-1 ascending, acc = fma(t,t,acc),
+ *    t = x_ik - x_jk in double;
+ *  - z-normalisation of window i: mu = (ascending double sum of T_{i+k}) / l;
+ *    v = (ascending fma(e,e,.) with e = T_{i+k} - mu) / l (population
+ *    variance, two passes); sigma = sqrt(v); xhat_k = (T_{i+k} - mu) / sigma.
+ *  - int8 inputs: d^2 = sum_k (x_ik - x_jk)^2 in int64, exact.
+ * Build with -ffp-contract=off and without fast-math so that every operation
+ * is a single IEEE double operation rounded to nearest even.
+ *
+ * Indices are 0-based (the paper's are 1-based).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_NOPAIR (-2)
+#define ORC_DEGENERATE (-4)
+#define ORC_NOMEM (-8)
+
+int orc_abi_version(void) { return 1; }
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* single-pair distances (Section 2)                                         */
+/* ------------------------------------------------------------------------ */
+
+double orc_d2_f32(const float *X, int64_t d, int64_t ld, int64_t i, int64_t j)
+{
+    const float *x = X + i * ld, *y = X + j * ld;
+    double acc = 0.0;
+    for (int64_t k = 0; k < d; ++k) {
+        double t = (double)x[k] - (double)y[k];
+        acc = fma(t, t, acc);
+    }
+    return acc;
+}
+
+double orc_d2_f64(const double *X, int64_t d, int64_t ld, int64_t i, int64_t j)
+{
+    const double *x = X + i * ld, *y = X + j * ld;
+    double acc = 0.0;
+    for (int64_t k = 0; k < d; ++k) {
+        double t = x[k] - y[k];
+        acc = fma(t, t, acc);
+    }
+    return acc;
+}
+
+int64_t orc_d2_i8(const int8_t *X, int64_t d, int64_t ld, int64_t i, int64_t j)
+{
+    const int8_t *x = X + i * ld, *y = X + j * ld;
+    int64_t acc = 0;
+    for (int64_t k = 0; k < d; ++k) {
+        int64_t t = (int64_t)x[k] - (int64_t)y[k];
+        acc += t * t;
+    }
+    return acc;
+}
+
+/* d^2 from row i to every row j (out[i] = 0). Used for sampled checks. */
+void orc_row_d2_f32(const float *X, int64_t n, int64_t d, int64_t ld, int64_t i, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) out[j] = orc_d2_f32(X, d, ld, i, j);
+}
+
+void orc_row_d2_f64(const double *X, int64_t n, int64_t d, int64_t ld, int64_t i, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) out[j] = orc_d2_f64(X, d, ld, i, j);
+}
+
+void orc_row_d2_i8(const int8_t *X, int64_t n, int64_t d, int64_t ld, int64_t i, int64_t *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < n; ++j) out[j] = orc_d2_i8(X, d, ld, i, j);
+}
+
+/* ------------------------------------------------------------------------ */
+/* z-normalised l-mers (Section 2 defines the l-mers; normalisation is the    */
+/* motif-mining convention, canonical two-pass population form above)        */
+/* ------------------------------------------------------------------------ */
+
+int orc_znorm(const float *T, int64_t len, int64_t ell, double *Xhat, double *mu_out, double *sigma_out)
+{
+    if (ell < 1 || len < ell) return ORC_NOPAIR;
+    int64_t N = len - ell + 1;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+    for (int64_t i = 0; i < N; ++i) {
+        double s = 0.0;
+        for (int64_t k = 0; k < ell; ++k) s += (double)T[i + k];
+        double mu = s / (double)ell;
+        double v = 0.0;
+        for (int64_t k = 0; k < ell; ++k) {
+            double e = (double)T[i + k] - mu;
+            v = fma(e, e, v);
+        }
+        v = v / (double)ell;
+        double sigma = sqrt(v);
+        if (mu_out) mu_out[i] = mu;
+        if (sigma_out) sigma_out[i] = sigma;
+        if (!(sigma > 0.0)) { bad = 1; continue; }
+        if (Xhat)
+            for (int64_t k = 0; k < ell; ++k) Xhat[i * ell + k] = ((double)T[i + k] - mu) / sigma;
+    }
+    return bad ? ORC_DEGENERATE : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* closest pair (Section 3 problem; MPR step 5 update rule)                  */
+/* ------------------------------------------------------------------------ */
+
+/* Lexicographic order on (d2, i, j). */
+static int better(double d2a, int64_t ia, int64_t ja, double d2b, int64_t ib, int64_t jb)
+{
+    if (d2a != d2b) return d2a < d2b;
+    if (ia != ib) return ia < ib;
+    return ja < jb;
+}
+
+#define ORC_CPP_BODY(D2EXPR)                                                     \
+    double best = INFINITY;                                                      \
+    int64_t bi = -1, bj = -1;                                                    \
+    _Pragma("omp parallel")                                                      \
+    {                                                                            \
+        double tb = INFINITY;                                                    \
+        int64_t ti = -1, tj = -1;                                                \
+        _Pragma("omp for schedule(dynamic, 8) nowait")                           \
+        for (int64_t i = 0; i < n; ++i) {                                        \
+            for (int64_t j = i + excl; j < n; ++j) {                             \
+                double v = (D2EXPR);                                             \
+                if (ti < 0 || better(v, i, j, tb, ti, tj)) {                     \
+                    tb = v; ti = i; tj = j;                                      \
+                }                                                                \
+            }                                                                    \
+        }                                                                        \
+        _Pragma("omp critical")                                                  \
+        {                                                                        \
+            if (ti >= 0 && (bi < 0 || better(tb, ti, tj, best, bi, bj))) {      \
+                best = tb; bi = ti; bj = tj;                                     \
+            }                                                                    \
+        }                                                                        \
+    }                                                                            \
+    if (bi < 0) return ORC_NOPAIR;                                               \
+    *out_i = bi; *out_j = bj; *out_d2 = best;                                    \
+    return ORC_OK;
+
+/* Every thread keeps the (d2, i, j)-lexicographic minimum of the pairs it
+ * scans and the merge applies the same order, so the result does not depend on
+ * how rows are shared among threads. */
+int orc_cpp_f32(const float *X, int64_t n, int64_t d, int64_t ld, int64_t excl,
+                int64_t *out_i, int64_t *out_j, double *out_d2)
+{
+    if (excl < 1) excl = 1;
+    ORC_CPP_BODY(orc_d2_f32(X, d, ld, i, j))
+}
+
+int orc_cpp_f64(const double *X, int64_t n, int64_t d, int64_t ld, int64_t excl,
+                int64_t *out_i, int64_t *out_j, double *out_d2)
+{
+    if (excl < 1) excl = 1;
+    ORC_CPP_BODY(orc_d2_f64(X, d, ld, i, j))
+}
+
+int orc_cpp_i8(const int8_t *X, int64_t n, int64_t d, int64_t ld, int64_t excl,
+               int64_t *out_i, int64_t *out_j, double *out_d2)
+{
+    if (excl < 1) excl = 1;
+    ORC_CPP_BODY((double)orc_d2_i8(X, d, ld, i, j))
+}
+
+/* ------------------------------------------------------------------------ */
+/* fixed-radius neighbours (Section 3.5, MPR-FRNNS emission d <= R)          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { int64_t i, j; double d2; } orc_rec;
+
+static int rec_cmp(const void *a, const void *b)
+{
+    const orc_rec *x = (const orc_rec *)a, *y = (const orc_rec *)b;
+    if (x->i != y->i) return x->i < y->i ? -1 : 1;
+    if (x->j != y->j) return x->j < y->j ? -1 : 1;
+    return 0;
+}
+
+typedef struct { orc_rec *v; int64_t n, cap; int fail; } orc_vec;
+
+static void vec_push(orc_vec *a, int64_t i, int64_t j, double d2)
+{
+    if (a->fail) return;
+    if (a->n == a->cap) {
+        int64_t nc = a->cap ? a->cap * 2 : 1024;
+        orc_rec *p = (orc_rec *)realloc(a->v, (size_t)nc * sizeof(orc_rec));
+        if (!p) { a->fail = 1; return; }
+        a->v = p; a->cap = nc;
+    }
+    a->v[a->n].i = i; a->v[a->n].j = j; a->v[a->n].d2 = d2; a->n++;
+}
+
+/* Returns the number of pairs (or a negative error). The first min(count, cap)
+ * pairs in (i,j) order are written to pairs (2 int64 per pair) and d2. */
+#define ORC_FRNN_BODY(D2EXPR)                                                    \
+    orc_vec all = {0, 0, 0, 0};                                                  \
+    _Pragma("omp parallel")                                                      \
+    {                                                                            \
+        orc_vec loc = {0, 0, 0, 0};                                              \
+        _Pragma("omp for schedule(dynamic, 8) nowait")                           \
+        for (int64_t i = 0; i < n; ++i)                                          \
+            for (int64_t j = i + excl; j < n; ++j) {                             \
+                double v = (D2EXPR);                                             \
+                if (v <= R2) vec_push(&loc, i, j, v);                            \
+            }                                                                    \
+        _Pragma("omp critical")                                                  \
+        {                                                                        \
+            if (loc.fail) all.fail = 1;                                          \
+            for (int64_t t = 0; t < loc.n; ++t)                                  \
+                vec_push(&all, loc.v[t].i, loc.v[t].j, loc.v[t].d2);             \
+        }                                                                        \
+        free(loc.v);                                                             \
+    }                                                                            \
+    if (all.fail) { free(all.v); return ORC_NOMEM; }                             \
+    if (all.n > 1) qsort(all.v, (size_t)all.n, sizeof(orc_rec), rec_cmp);        \
+    for (int64_t t = 0; t < all.n && t < cap; ++t) {                             \
+        pairs[2 * t] = all.v[t].i; pairs[2 * t + 1] = all.v[t].j;                \
+        if (d2_out) d2_out[t] = all.v[t].d2;                                     \
+    }                                                                            \
+    int64_t cnt = all.n;                                                         \
+    free(all.v);                                                                 \
+    return cnt;
+
+int64_t orc_frnn_f32(const float *X, int64_t n, int64_t d, int64_t ld, int64_t excl, double R2,
+                     int64_t *pairs, double *d2_out, int64_t cap)
+{
+    if (excl < 1) excl = 1;
+    ORC_FRNN_BODY(orc_d2_f32(X, d, ld, i, j))
+}
+
+int64_t orc_frnn_f64(const double *X, int64_t n, int64_t d, int64_t ld, int64_t excl, double R2,
+                     int64_t *pairs, double *d2_out, int64_t cap)
+{
+    if (excl < 1) excl = 1;
+    ORC_FRNN_BODY(orc_d2_f64(X, d, ld, i, j))
+}
+
+int64_t orc_frnn_i8(const int8_t *X, int64_t n, int64_t d, int64_t ld, int64_t excl, double R2,
+                    int64_t *pairs, double *d2_out, int64_t cap)
+{
+    if (excl < 1) excl = 1;
+    ORC_FRNN_BODY((double)orc_d2_i8(X, d, ld, i, j))
+}
+
+/* ------------------------------------------------------------------------ */
+/* nearest-neighbour squared distance of every point (over all j != i).      */
+/* Used only to derive a workload's radius from the data; each unordered     */
+/* pair is evaluated once and updates both endpoints (d^2 is symmetric under */
+/* the canonical arithmetic because t = x_i - x_j only changes sign).        */
+/* ------------------------------------------------------------------------ */
+
+int orc_nn_f32(const float *X, int64_t n, int64_t d, int64_t ld, double *nn_out)
+{
+    int nt = orc_max_threads();
+    double *buf = (double *)malloc((size_t)nt * (size_t)n * sizeof(double));
+    if (!buf) return ORC_NOMEM;
+    for (int64_t t = 0; t < (int64_t)nt * n; ++t) buf[t] = INFINITY;
+#pragma omp parallel
+    {
+#ifdef _OPENMP
+        double *mine = buf + (int64_t)omp_get_thread_num() * n;
+#else
+        double *mine = buf;
+#endif
+#pragma omp for schedule(dynamic, 8)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = i + 1; j < n; ++j) {
+                double v = orc_d2_f32(X, d, ld, i, j);
+                if (v < mine[i]) mine[i] = v;
+                if (v < mine[j]) mine[j] = v;
+            }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double m = INFINITY;
+        for (int t = 0; t < nt; ++t)
+            if (buf[(int64_t)t * n + i] < m) m = buf[(int64_t)t * n + i];
+        nn_out[i] = m;
+    }
+    free(buf);
+    return ORC_OK;
+}

@@ -1,0 +1,355 @@
+"""Pins for the CPU oracle: it is checked here against things other than itself.
+
+The paper prints no distance values, pair indices or neighbour sets for the
+Euclidean path, so the oracle is pinned by mathematics and construction:
+
+* exact rational arithmetic on tiny inputs (the brute-force ground truth the
+  paper uses to verify answers, Section 6.1);
+* special cases that reduce to textbook routines: d=1 (sort + adjacent gaps),
+  d=2 (divide-and-conquer closest pair, the O(n log n) algorithm cited in the
+  introduction), scipy's pdist;
+* planted pairs whose answer is known by construction (the injection
+  methodology of Section 6.1);
+* invariants: symmetry, exclusion zone, radius monotonicity, permutation and
+  power-of-two scaling, z-normalisation identities, the int8 Gram identity.
+
+A plausible mistake in the oracle (a dropped term, a wrong sign or index, a
+sample instead of population variance, an off-by-one exclusion, the wrong tie
+order) fails at least one test here.
+"""
+import itertools
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.spatial.distance as ssd
+
+import oracle
+import workloads as W
+
+U64 = 2.0 ** -53
+
+
+def gamma(m):
+    return m * U64 / (1 - m * U64)
+
+
+def exact_d2(x, y):
+    return sum((Fraction(float(a)) - Fraction(float(b))) ** 2 for a, b in zip(x, y))
+
+
+# --------------------------------------------------------------------------
+# exact rationals
+# --------------------------------------------------------------------------
+
+def _tiny_sets():
+    rng = np.random.default_rng(101)
+    out = []
+    for n, d in [(12, 3), (20, 5), (24, 8), (16, 16)]:
+        X = rng.normal(0, 1, (n, d)).astype(np.float32)
+        X[3] = X[7]                                    # exact duplicate -> d2 = 0
+        X[5] = X[2]
+        X[5, 0] = np.nextafter(X[2, 0], np.float32(np.inf))  # last-ulp difference
+        out.append(X)
+    # wide dynamic range
+    X = (rng.normal(0, 1, (18, 4)) * np.exp2(rng.integers(-20, 20, (18, 4)))).astype(np.float32)
+    out.append(X)
+    return out
+
+
+@pytest.mark.parametrize("X", _tiny_sets())
+def test_d2_against_exact_rationals(X):
+    n, d = X.shape
+    tol = gamma(d + 2)
+    for i, j in itertools.combinations(range(n), 2):
+        ex = exact_d2(X[i], X[j])
+        got = oracle.d2(X, i, j)
+        if ex == 0:
+            assert got == 0.0
+        else:
+            assert abs(Fraction(got) - ex) <= Fraction(tol) * ex, (i, j)
+
+
+@pytest.mark.parametrize("X", _tiny_sets())
+def test_closest_pair_and_frnn_against_exact_enumeration(X):
+    n, d = X.shape
+    exact = {(i, j): exact_d2(X[i], X[j]) for i, j in itertools.combinations(range(n), 2)}
+    best_val = min(exact.values())
+    bi, bj, bd2 = oracle.closest_pair(X)
+    tol = Fraction(gamma(d + 2))
+    # the oracle's winner is an exact minimiser up to the rounding bound ...
+    assert exact[(bi, bj)] <= best_val * (1 + 2 * tol)
+    # ... and wherever the exact minimum is separated, it is the same pair
+    second = sorted(set(exact.values()))
+    if len(second) > 1 and second[1] > best_val * (1 + 4 * tol):
+        winners = sorted(k for k, v in exact.items() if v == best_val)
+        assert (bi, bj) == winners[0]
+    # FRNN at a radius placed between two well-separated exact values
+    vals = sorted(exact.values())
+    gaps = [(vals[k + 1] - vals[k]) / vals[k + 1] for k in range(len(vals) // 3, len(vals) - 1)]
+    k = len(vals) // 3 + int(np.argmax(gaps))
+    R2 = float((vals[k] + vals[k + 1]) / 2)
+    pairs, _ = oracle.frnn(X, R2)
+    want = sorted(p for p, v in exact.items() if v <= Fraction(R2))
+    assert [tuple(p) for p in pairs] == want
+
+
+def test_exact_ties_go_to_lexicographic_minimum():
+    # integer coordinates: every d2 is exact in double, so ties are exact
+    X = np.array([[5, 5], [9, 9], [0, 0], [6, 5], [1, 0], [20, 20], [21, 20]], dtype=np.float32)
+    # pairs at d2=1: (0,3), (2,4), (5,6) -> lexicographic minimum is (0,3)
+    assert oracle.closest_pair(X) == (0, 3, 1.0)
+    Xp = X[[2, 4, 0, 3, 1, 5, 6]]        # now the tied pairs are (0,1), (2,3), (5,6)
+    assert oracle.closest_pair(Xp) == (0, 1, 1.0)
+
+
+# --------------------------------------------------------------------------
+# special cases reducing to textbook routines
+# --------------------------------------------------------------------------
+
+def test_one_dimension_is_sorted_adjacent_gap():
+    rng = np.random.default_rng(7)
+    x = rng.normal(0, 1, 3000).astype(np.float32)
+    X = x.reshape(-1, 1)
+    order = np.argsort(x, kind="stable")
+    xs = x[order].astype(np.float64)
+    gaps = np.diff(xs)                      # exact: differences of nearby float32 values
+    k = int(np.argmin(gaps))
+    assert np.count_nonzero(gaps == gaps[k]) == 1
+    i, j = sorted((int(order[k]), int(order[k + 1])))
+    bi, bj, bd2 = oracle.closest_pair(X)
+    assert (bi, bj) == (i, j)
+    assert bd2 == gaps[k] * gaps[k]
+    # fixed radius in 1-D by a sorted sweep
+    R = 1e-3
+    pairs, _ = oracle.frnn(X, R * R)
+    want = set()
+    for a in range(len(xs)):
+        b = a + 1
+        while b < len(xs) and (xs[b] - xs[a]) * (xs[b] - xs[a]) <= R * R:
+            want.add(tuple(sorted((int(order[a]), int(order[b])))))
+            b += 1
+    assert set(map(tuple, pairs.tolist())) == want
+
+
+def _closest_pair_dc(P):
+    """Divide-and-conquer closest pair in the plane (exact rationals)."""
+    pts = sorted(P, key=lambda p: (p[0], p[1]))
+
+    def rec(lo, hi):
+        if hi - lo <= 3:
+            best = (None, None)
+            for a in range(lo, hi):
+                for b in range(a + 1, hi):
+                    v = (pts[a][0] - pts[b][0]) ** 2 + (pts[a][1] - pts[b][1]) ** 2
+                    if best[0] is None or v < best[0]:
+                        best = (v, (pts[a][2], pts[b][2]))
+            return best
+        mid = (lo + hi) // 2
+        xm = pts[mid][0]
+        l, r = rec(lo, mid), rec(mid, hi)
+        best = l if r[0] is None or (l[0] is not None and l[0] <= r[0]) else r
+        strip = sorted((p for p in pts[lo:hi] if (p[0] - xm) ** 2 < best[0]), key=lambda p: p[1])
+        for a in range(len(strip)):
+            for b in range(a + 1, len(strip)):
+                if (strip[b][1] - strip[a][1]) ** 2 >= best[0]:
+                    break
+                v = (strip[a][0] - strip[b][0]) ** 2 + (strip[a][1] - strip[b][1]) ** 2
+                if v < best[0]:
+                    best = (v, (strip[a][2], strip[b][2]))
+        return best
+
+    return rec(0, len(pts))
+
+
+def test_two_dimensions_against_divide_and_conquer():
+    rng = np.random.default_rng(11)
+    X = rng.uniform(-100, 100, (2500, 2)).astype(np.float32)
+    P = [(Fraction(float(a)), Fraction(float(b)), k) for k, (a, b) in enumerate(X)]
+    v, (a, b) = _closest_pair_dc(P)
+    bi, bj, bd2 = oracle.closest_pair(X)
+    assert (bi, bj) == tuple(sorted((a, b)))
+    assert abs(Fraction(bd2) - v) <= Fraction(gamma(4)) * v
+
+
+def test_against_scipy_pdist():
+    rng = np.random.default_rng(3)
+    X, plant = W.planted_gaussian_points(rng, 1500, 64, 1e-3)
+    ref = ssd.squareform(ssd.pdist(X.astype(np.float64), "sqeuclidean"))
+    for i in (0, 17, plant[0], 1499):
+        row = oracle.row_d2(X, i)
+        np.testing.assert_allclose(row, ref[i], rtol=1e-12, atol=0)
+    iu = np.triu_indices(1500, 1)
+    flat = ref[iu]
+    k = int(np.argmin(flat))
+    assert oracle.closest_pair(X)[:2] == (int(iu[0][k]), int(iu[1][k]))
+    R2 = 64.0
+    pairs, d2 = oracle.frnn(X, R2)
+    sel = flat <= R2
+    margin = np.min(np.abs(flat - R2) / R2)
+    assert margin > 1e-10
+    assert np.array_equal(pairs, np.stack([iu[0][sel], iu[1][sel]], 1))
+    np.testing.assert_allclose(d2, flat[sel], rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# planted answers (known by construction)
+# --------------------------------------------------------------------------
+
+def test_planted_points_full_size():
+    c = W.cfg_points_small()
+    i, j, d2 = oracle.closest_pair(c["X"])
+    assert (i, j) == c["plant"]
+    assert d2 < 1e-3                      # 64 coords of N(0, 1e-3) noise
+    pairs, _ = oracle.frnn(c["X"], c["R2"])
+    assert tuple(c["plant"]) in set(map(tuple, pairs.tolist()))
+
+
+def test_planted_motif_small_series():
+    rng = np.random.default_rng(21)
+    T = W.random_walk(rng, 8192)
+    plant = W.plant_motif(rng, T, 256)
+    best, _ = oracle.motif(T, 256)
+    assert best[:2] == plant
+    assert best[2] < 0.05
+
+
+def test_planted_mixture_small():
+    rng = np.random.default_rng(5)
+    X, plant = W.mixture_points(rng, 3000, 512, plant_dist=1e-2)
+    i, j, d2 = oracle.closest_pair(X)
+    assert (i, j) == plant
+    assert abs(math.sqrt(d2) - 1e-2) < 1e-4   # float32 rounding of the planted row
+
+
+def test_planted_snp_pairs_small():
+    rng = np.random.default_rng(8)
+    X = W.snp_matrix(rng, 1500, 4096)
+    plants = W.plant_snp_pairs(rng, X)
+    best = oracle.closest_pair(X)
+    assert best == (plants[0][0], plants[0][1], 3)
+    pairs, d2 = oracle.frnn(X, 800)
+    assert sorted(map(tuple, pairs.tolist())) == sorted((a, b) for a, b, _ in plants)
+    got = {tuple(p): int(v) for p, v in zip(pairs.tolist(), d2)}
+    for a, b, m in plants:
+        assert got[(a, b)] == m
+
+
+# --------------------------------------------------------------------------
+# invariants
+# --------------------------------------------------------------------------
+
+def test_symmetry_is_bitwise():
+    rng = np.random.default_rng(4)
+    X = rng.normal(0, 3, (200, 37)).astype(np.float32)
+    for i, j in rng.integers(0, 200, (300, 2)):
+        assert oracle.d2(X, i, j) == oracle.d2(X, j, i)
+
+
+def test_power_of_two_scaling_is_exact():
+    rng = np.random.default_rng(12)
+    X = rng.normal(0, 1, (300, 24)).astype(np.float32)
+    base = oracle.closest_pair(X)
+    for k in (-3, 5):
+        Y = (X * np.float32(2.0 ** k)).astype(np.float32)
+        got = oracle.closest_pair(Y)
+        assert got[:2] == base[:2]
+        assert got[2] == base[2] * 4.0 ** k
+        assert oracle.d2(Y, 3, 9) == oracle.d2(X, 3, 9) * 4.0 ** k
+
+
+def test_permutation_maps_the_answer():
+    rng = np.random.default_rng(13)
+    X = rng.normal(0, 1, (700, 16)).astype(np.float32)
+    i, j, d2 = oracle.closest_pair(X)
+    perm = rng.permutation(700)
+    inv = np.argsort(perm)
+    pi, pj, pd2 = oracle.closest_pair(X[perm])
+    assert tuple(sorted((int(inv[i]), int(inv[j])))) == (pi, pj)
+    assert pd2 == d2
+
+
+def test_frnn_radius_monotone_and_contains_closest_pair():
+    rng = np.random.default_rng(14)
+    X = rng.normal(0, 1, (600, 8)).astype(np.float32)
+    i, j, dmin = oracle.closest_pair(X)
+    at, _ = oracle.frnn(X, dmin)
+    assert [tuple(p) for p in at] == [(i, j)] or (i, j) in set(map(tuple, at.tolist()))
+    below, _ = oracle.frnn(X, float(np.nextafter(dmin, 0.0)))
+    assert len(below) == 0
+    prev = set()
+    for R2 in (1.0, 2.0, 4.0, 6.0):
+        cur = set(map(tuple, oracle.frnn(X, R2)[0].tolist()))
+        assert prev <= cur
+        prev = cur
+
+
+def test_exclusion_zone_boundary():
+    # period-P series: windows i and i+P are identical, so d2(i, i+P) == 0.
+    P, ell = 37, 16
+    rng = np.random.default_rng(15)
+    base = rng.normal(0, 1, P).astype(np.float32)
+    T = np.tile(base, 12)
+    best, _ = oracle.motif(T, ell, excl=P)
+    assert best == (0, P, 0.0)
+    best, _ = oracle.motif(T, ell, excl=P + 1)
+    assert best == (0, 2 * P, 0.0)
+    _, (pairs, _) = oracle.motif(T, ell, excl=P + 1, R2=0.0)
+    assert np.all(pairs[:, 1] - pairs[:, 0] >= P + 1)
+    assert len(pairs) > 0 and np.all((pairs[:, 1] - pairs[:, 0]) % P == 0)
+
+
+def test_znorm_against_numpy_and_identities():
+    rng = np.random.default_rng(16)
+    T = W.random_walk(rng, 3000)
+    ell = 128
+    Xhat, mu, sg = oracle.znorm(T, ell)
+    win = np.lib.stride_tricks.sliding_window_view(T.astype(np.float64), ell)
+    np.testing.assert_allclose(mu, win.mean(axis=1), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(sg, win.std(axis=1, ddof=0), rtol=1e-12)   # population sigma
+    np.testing.assert_allclose(Xhat.sum(axis=1), 0.0, atol=1e-9)
+    np.testing.assert_allclose((Xhat ** 2).sum(axis=1), ell, rtol=1e-12)
+    # d2 = 2 l (1 - rho) with rho the Pearson correlation of the raw windows
+    for i, j in [(0, 500), (10, 2000), (1234, 2870), (77, 78)]:
+        rho = np.corrcoef(win[i], win[j])[0, 1]
+        assert abs(oracle.d2(Xhat, i, j) - 2 * ell * (1 - rho)) <= 1e-10 * ell
+
+
+def test_znorm_power_of_two_invariance_is_bitwise():
+    rng = np.random.default_rng(17)
+    T = W.random_walk(rng, 1500)
+    a, mu, sg = oracle.znorm(T, 64)
+    b, mu2, sg2 = oracle.znorm((T * np.float32(8.0)).astype(np.float32), 64)
+    assert np.array_equal(a, b)
+    assert np.array_equal(mu2, mu * 8) and np.array_equal(sg2, sg * 8)
+
+
+def test_znorm_zero_variance_is_reported():
+    T = np.concatenate([np.ones(50, np.float32), np.arange(50, dtype=np.float32)])
+    with pytest.raises(ValueError):
+        oracle.znorm(T, 20)
+
+
+def test_int8_gram_identity_and_float_agreement():
+    rng = np.random.default_rng(18)
+    X = W.snp_matrix(rng, 300, 512)
+    Xi = X.astype(np.int64)
+    s = (Xi * Xi).sum(1)
+    G = Xi @ Xi.T
+    for i, j in rng.integers(0, 300, (200, 2)):
+        assert oracle.d2(X, i, j) == s[i] + s[j] - 2 * G[i, j]
+    assert oracle.closest_pair(X)[:2] == oracle.closest_pair(X.astype(np.float32))[:2]
+    a, da = oracle.frnn(X, 700)
+    b, db = oracle.frnn(X.astype(np.float32), 700.0)
+    assert np.array_equal(a, b) and np.array_equal(da, db.astype(np.int64))
+
+
+def test_no_admissible_pair():
+    X = np.zeros((1, 4), np.float32)
+    assert oracle.closest_pair(X) is None
+    T = W.random_walk(np.random.default_rng(1), 40)
+    best, _ = oracle.motif(T, 20)       # 21 windows, exclusion 20: one admissible pair
+    assert best[:2] == (0, 20)
+    best, _ = oracle.motif(T, 21)       # 20 windows, exclusion 21: none
+    assert best is None
