@@ -1,0 +1,176 @@
+/*
+ * cpmi.h -- exact closest pair, fixed-radius neighbours and time-series motifs
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Problems (Rajasekaran & Pathak, "Efficient Algorithms for the Closest Pair
+ * Problem and Applications", 2014):
+ *   - closest pair (CPP, Section 3): given n points in R^d, the pair at least
+ *     Euclidean distance (distance as defined in Section 2);
+ *   - fixed-radius near neighbours (FRNNP, Section 3.5): for every point, the
+ *     other points within distance R; returned here as the canonical list of
+ *     pairs i<j with d(i,j) <= R, from which N(i) is the symmetric closure;
+ *   - time-series motif (Section 2 l-mers, Section 3 problem statement): the two
+ *     closest l-mers of a series T. Windows are z-normalised and a pair of
+ *     windows (i, j) is admissible only if j - i >= excl (overlapping windows
+ *     are trivial matches).
+ *
+ * Every answer is exact with respect to the canonical FP64 arithmetic below,
+ * whatever the screening precision: a Gram-form screen on the matrix cores
+ * (FP32, BF16 or INT8) is followed by an FP64 re-verification of every pair
+ * whose screening error interval can reach the current minimum or the radius.
+ *
+ *   Canonical squared distance of rows x, y (float input): x_k, y_k promoted to
+ *   double; acc = 0; for k = 0..d-1: t = x_k - y_k; acc = fma(t, t, acc).
+ *   int8 input: sum_k (x_k - y_k)^2 in integers (exact).
+ *   z-normalisation of window i (length l): mu = (sum_{k ascending} T[i+k]) / l,
+ *   v = (sum_{k ascending} fma(e, e, .), e = T[i+k] - mu) / l (population
+ *   variance), sigma = sqrt(v), xhat_k = (T[i+k] - mu) / sigma, all in double.
+ *   Ties in the closest pair go to the lexicographically smallest (i, j).
+ *
+ * Conventions for every call:
+ *   - Indices are 0-based (the paper's are 1-based).
+ *   - Input arrays (points, series) and output arrays named "device" are device
+ *     pointers owned by the caller (for example from torch.empty(device="cuda")).
+ *     The library never frees or retains them after the call returns.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL is the null stream) and
+ *     the call returns after the stream has finished the work it enqueued;
+ *     results in host structs and device arrays are then valid.
+ *   - A context is not thread-safe; use one context per host thread.
+ *   - Return value: CPMI_OK (0) or a negative CPMI_ERR_* code; the message is
+ *     available from cpmi_last_error(ctx). No exception crosses this ABI.
+ */
+#ifndef CPMI_H
+#define CPMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cpmi_ctx cpmi_ctx;
+
+/* return codes */
+enum {
+    CPMI_OK = 0,
+    CPMI_ERR_ARG = -1,        /* invalid argument (shape, stride, dtype, precision, NULL pointer) */
+    CPMI_ERR_NOPAIR = -2,     /* no admissible pair (n < 2, or len < ell + excl for a motif)       */
+    CPMI_ERR_NONFINITE = -3,  /* the input holds NaN or Inf                                         */
+    CPMI_ERR_DEGENERATE = -4, /* a window has zero variance, so it cannot be z-normalised           */
+    CPMI_ERR_CAPACITY = -5,   /* the caller's output array is too small; *count_out holds the need  */
+    CPMI_ERR_HIP = -6,        /* a HIP runtime call failed                                          */
+    CPMI_ERR_RANGE = -7       /* a squared norm is too large for the FP32 screen (>= 2^100)         */
+};
+
+/* element type of the input points */
+enum { CPMI_F32 = 0, CPMI_I8 = 1 };
+
+/* screening precision; every precision returns the same exact answer */
+enum {
+    CPMI_PREC_AUTO = 0, /* the tuned choice for the shape (INT8 for int8 input)          */
+    CPMI_PREC_F32 = 1,  /* FP32 matrix-core screen (plain form)                          */
+    CPMI_PREC_BF16 = 2, /* BF16 operands, FP32 accumulation, rigorous per-tile bound     */
+    CPMI_PREC_I8 = 3    /* int8 operands, int32 accumulation: exact, no bound needed     */
+};
+
+/* Result of a closest-pair search. d2 is the canonical squared distance and d
+ * its correctly rounded square root. screen_err is the largest |screen value -
+ * d2| over the candidates that were re-verified, and screen_bound the largest
+ * error bound that was applied to them (screen_err <= screen_bound always;
+ * both 0 for int8). status is CPMI_OK or the per-item error code. */
+typedef struct {
+    int64_t i, j;
+    double d2;
+    double d;
+    double screen_err;
+    double screen_bound;
+    int32_t status;
+    int32_t reserved;
+} cpmi_pair;
+
+/* Statistics of the last call on a context. */
+typedef struct {
+    int64_t valid_pairs;         /* admissible pairs of the problem                           */
+    int64_t tiles_total;         /* screen tiles evaluated in the first pass                  */
+    int64_t tiles_rescreened;    /* tiles whose lower bound reached the minimum (second pass) */
+    int64_t cpp_candidates;      /* pairs re-verified in FP64 for the closest pair            */
+    int64_t frnn_candidates;     /* pairs re-verified in FP64 for the radius                  */
+    int64_t frnn_pairs;          /* pairs within the radius                                   */
+    int64_t reruns;              /* internal buffer growths that forced a re-run              */
+    double max_err_over_bound;   /* max over verified candidates of |screen - d2| / bound      */
+    double kernel_ms;            /* device time of the enqueued work, HIP events              */
+    int32_t precision;           /* precision actually used (CPMI_PREC_*)                     */
+    int32_t tile;                /* screen tile edge used                                     */
+} cpmi_stats;
+
+/* Create a context on HIP device `device`. tune_cache_path (nullable) names a
+ * JSON file of tuned screen configurations written by the Python autotuner; if
+ * NULL or unreadable the built-in defaults are used. */
+int cpmi_create(cpmi_ctx **out, int device, const char *tune_cache_path);
+
+/* Release the context and its device workspace. NULL is accepted. */
+int cpmi_destroy(cpmi_ctx *ctx);
+
+/* Closest pair of n points (Section 3 problem statement; MPR step 5 keeps the
+ * least distance). pts: device, row-major n x d with row stride ld elements
+ * (ld >= d), dtype CPMI_F32 or CPMI_I8. out: host. Errors: ERR_ARG (n, d, ld,
+ * dtype, precision), ERR_NOPAIR (n < 2), ERR_NONFINITE, ERR_RANGE. */
+int cpmi_closest_pair(cpmi_ctx *ctx, const void *pts, int dtype, int64_t n, int64_t d, int64_t ld,
+                      int precision, void *stream, cpmi_pair *out);
+
+/* Fixed-radius pairs (Section 3.5, MPR-FRNNS emits j into N(i) and i into N(j)
+ * when d <= R): every pair i<j with canonical d2 <= R2, sorted by (i, j).
+ * R2 is the squared radius (callers pass fl(R*R); for int8 data an integer).
+ * pairs: device int64 [cap][2]; d2: device double [cap] or NULL; count_out:
+ * host. If the count exceeds cap, nothing is written to pairs/d2, *count_out
+ * holds the count and ERR_CAPACITY is returned (call again with cap >= count). */
+int cpmi_frnn(cpmi_ctx *ctx, const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, double R2,
+              int precision, void *stream, int64_t *pairs, double *d2, int64_t cap, int64_t *count_out);
+
+/* Closest pair and fixed-radius pairs of the same points from one screening
+ * pass. best (host) may be NULL to skip the closest pair; R2 < 0 skips the
+ * radius search (pairs, d2, count_out may then be NULL). Same errors as above. */
+int cpmi_points(cpmi_ctx *ctx, const void *pts, int dtype, int64_t n, int64_t d, int64_t ld,
+                int precision, double R2, void *stream, cpmi_pair *best,
+                int64_t *pairs, double *d2, int64_t cap, int64_t *count_out);
+
+/* Motif of a series (Section 3: the two closest l-mers of T). series: device
+ * float32 [len]; windows i = 0..len-ell are z-normalised; pairs with
+ * j - i < excl are excluded (excl <= 0 means excl = ell). best: host (may be
+ * NULL to skip). If R2 >= 0, all admissible window pairs with d2 <= R2 are also
+ * returned as for cpmi_frnn. Errors: ERR_ARG (ell < 2, len < ell),
+ * ERR_NOPAIR (len - ell + 1 <= excl), ERR_NONFINITE, ERR_DEGENERATE. */
+int cpmi_motif(cpmi_ctx *ctx, const float *series, int64_t len, int64_t ell, int64_t excl,
+               int precision, double R2, void *stream, cpmi_pair *best,
+               int64_t *pairs, double *d2, int64_t cap, int64_t *count_out);
+
+/* Motifs of many series in one batched launch sequence (one persistent screen
+ * over the tiles of all series, replayed from a captured HIP graph when the
+ * same shapes are seen again). series: host array of nseries device pointers
+ * to float32 series; lens, ells: host arrays; exclusion is ell per series.
+ * best: host [nseries]; best[s].status carries the per-series error code
+ * (ERR_NOPAIR, ERR_NONFINITE, ERR_DEGENERATE) while the call returns CPMI_OK
+ * if the arguments were valid. */
+int cpmi_motif_batch(cpmi_ctx *ctx, const float *const *series, const int64_t *lens, const int64_t *ells,
+                     int64_t nseries, int precision, void *stream, cpmi_pair *best);
+
+/* Message describing the last error on ctx (empty string if none). Valid until
+ * the next call on ctx. */
+const char *cpmi_last_error(cpmi_ctx *ctx);
+
+/* Copy the statistics of the last successful call into *out. */
+int cpmi_last_stats(cpmi_ctx *ctx, cpmi_stats *out);
+
+/* Set the screen configuration used by later calls with `precision` (tile edge
+ * 128 or 256 for the matrix-core screen); 0 restores the default. Used by the
+ * autotuner. Returns ERR_ARG for an unsupported value. */
+int cpmi_set_tile(cpmi_ctx *ctx, int precision, int tile);
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int cpmi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPMI_H */

@@ -1,0 +1,47 @@
+/*
+ * cpmi_debug.h -- diagnostic entry points of the cpmi library, used by the
+ * test-suite to check device behaviour the public calls depend on. Same
+ * conventions as cpmi.h (device pointers owned by the caller, synchronous).
+ */
+#ifndef CPMI_DEBUG_H
+#define CPMI_DEBUG_H
+
+#include <stdint.h>
+
+#include "cpmi.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One 32x32 matrix-core product through the screen's fragment path:
+ * C[r][c] = sum_k A[r][k] * B[c][k] over one 32-byte K slice per row.
+ * A, B: device, 32 rows x 32 bytes (FP32: 8 values, BF16: 16, int8: 32 per
+ * row); C: device float [32][32]. precision: CPMI_PREC_F32, _BF16 or _I8.
+ * Checks the operand/accumulator lane layouts the screen assumes. */
+int cpmi_dbg_mfma_probe(int precision, const void *A, const void *B, float *C, void *stream);
+
+/* Run only the l-mer builder on a series and return the canonical window
+ * means and sigmas (device double [len - ell + 1] each), so that they can be
+ * compared bit for bit with the definition (Section 2 windows, two-pass
+ * population z-normalisation). */
+int cpmi_dbg_znorm(cpmi_ctx *ctx, const float *series, int64_t len, int64_t ell, int precision, double *mu,
+                   double *sigma, void *stream);
+
+/* Host only (no device work): the screen's tile list for one problem of n
+ * rows with exclusion excl and tile edge `tile` (128 or 256). Entries are
+ * packed as problem << 44 | I << 22 | J (block row, block column); unused
+ * slots are all ones. Writes min(count, cap) entries to out (host) and returns
+ * the count, or ERR_ARG. */
+int64_t cpmi_dbg_tile_list(int64_t n, int64_t excl, int tile, uint64_t *out, int64_t cap);
+
+/* Host only: the screening-error bound applied to every pair of a tile whose
+ * row blocks have maxima bI, bJ = (s^, ||x||, ||x~||, ||x - x~||) (4 floats
+ * each), padded dimension kpad, true dimension d, screen precision. */
+double cpmi_dbg_tile_bound(const float *bI, const float *bJ, int32_t kpad, int64_t d, int precision);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPMI_DEBUG_H */

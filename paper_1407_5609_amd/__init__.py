@@ -1,0 +1,321 @@
+"""Exact closest pair, fixed-radius neighbours and time-series motifs on MI355X.
+
+Thin ctypes binding of the cpmi C ABI (include/cpmi.h). Every step of the
+search runs in the HIP library libcpmi.so built from csrc/; this module only
+marshals arguments: it takes torch tensors that already live on the GPU and
+passes their device pointers, shapes and the current HIP stream. There is no
+CPU fallback: importing the package fails if the library is missing.
+
+    from paper_1407_5609_amd import closest_pair, frnn, points, motif, motif_batch
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+__all__ = ["CpmiError", "Pair", "Stats", "Context", "closest_pair", "frnn", "points", "motif", "motif_batch",
+           "PREC_AUTO", "PREC_F32", "PREC_BF16", "PREC_I8", "library_path", "default_context"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libcpmi.so")
+
+OK, ERR_ARG, ERR_NOPAIR, ERR_NONFINITE, ERR_DEGENERATE, ERR_CAPACITY, ERR_HIP, ERR_RANGE = 0, -1, -2, -3, -4, -5, -6, -7
+F32, I8 = 0, 1
+PREC_AUTO, PREC_F32, PREC_BF16, PREC_I8 = 0, 1, 2, 3
+_PREC = {"auto": PREC_AUTO, "f32": PREC_F32, "fp32": PREC_F32, "bf16": PREC_BF16, "i8": PREC_I8, "int8": PREC_I8}
+_ERRNAME = {ERR_ARG: "ERR_ARG", ERR_NOPAIR: "ERR_NOPAIR", ERR_NONFINITE: "ERR_NONFINITE",
+            ERR_DEGENERATE: "ERR_DEGENERATE", ERR_CAPACITY: "ERR_CAPACITY", ERR_HIP: "ERR_HIP", ERR_RANGE: "ERR_RANGE"}
+
+
+class _CPair(C.Structure):
+    _fields_ = [("i", C.c_int64), ("j", C.c_int64), ("d2", C.c_double), ("d", C.c_double),
+                ("screen_err", C.c_double), ("screen_bound", C.c_double), ("status", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class _CStats(C.Structure):
+    _fields_ = [("valid_pairs", C.c_int64), ("tiles_total", C.c_int64), ("tiles_rescreened", C.c_int64),
+                ("cpp_candidates", C.c_int64), ("frnn_candidates", C.c_int64), ("frnn_pairs", C.c_int64),
+                ("reruns", C.c_int64), ("max_err_over_bound", C.c_double), ("kernel_ms", C.c_double),
+                ("precision", C.c_int32), ("tile", C.c_int32)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
+                          " (hipcc, gfx950); there is no CPU fallback")
+    L = C.CDLL(_LIB_PATH)
+    vp, i64, dbl, i32 = C.c_void_p, C.c_int64, C.c_double, C.c_int
+    L.cpmi_create.argtypes = [C.POINTER(vp), i32, C.c_char_p]
+    L.cpmi_destroy.argtypes = [vp]
+    L.cpmi_last_error.argtypes = [vp]
+    L.cpmi_last_error.restype = C.c_char_p
+    L.cpmi_last_stats.argtypes = [vp, C.POINTER(_CStats)]
+    L.cpmi_set_tile.argtypes = [vp, i32, i32]
+    L.cpmi_version.restype = i32
+    L.cpmi_closest_pair.argtypes = [vp, vp, i32, i64, i64, i64, i32, vp, C.POINTER(_CPair)]
+    L.cpmi_frnn.argtypes = [vp, vp, i32, i64, i64, i64, dbl, i32, vp, vp, vp, i64, C.POINTER(i64)]
+    L.cpmi_points.argtypes = [vp, vp, i32, i64, i64, i64, i32, dbl, vp, C.POINTER(_CPair), vp, vp, i64,
+                              C.POINTER(i64)]
+    L.cpmi_motif.argtypes = [vp, vp, i64, i64, i64, i32, dbl, vp, C.POINTER(_CPair), vp, vp, i64, C.POINTER(i64)]
+    L.cpmi_motif_batch.argtypes = [vp, C.POINTER(vp), C.POINTER(i64), C.POINTER(i64), i64, i32, vp,
+                                   C.POINTER(_CPair)]
+    L.cpmi_dbg_mfma_probe.argtypes = [i32, vp, vp, vp, vp]
+    L.cpmi_dbg_znorm.argtypes = [vp, vp, i64, i64, i32, vp, vp, vp]
+    return L
+
+
+_lib = _load()
+
+
+class CpmiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_ERRNAME.get(code, code)}: {msg}")
+        self.code = code
+
+
+@dataclass
+class Pair:
+    i: int
+    j: int
+    d2: float
+    d: float
+    screen_err: float
+    screen_bound: float
+
+
+@dataclass
+class Stats:
+    valid_pairs: int
+    tiles_total: int
+    tiles_rescreened: int
+    cpp_candidates: int
+    frnn_candidates: int
+    frnn_pairs: int
+    reruns: int
+    max_err_over_bound: float
+    kernel_ms: float
+    precision: int
+    tile: int
+
+
+def _prec(p) -> int:
+    if isinstance(p, str):
+        return _PREC[p.lower()]
+    return int(p)
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _pair(cp: _CPair) -> Pair:
+    return Pair(cp.i, cp.j, cp.d2, cp.d, cp.screen_err, cp.screen_bound)
+
+
+class Context:
+    """One cpmi context (device workspace, tuned tiles). Not thread-safe."""
+
+    def __init__(self, device: int | None = None, tune_cache: str | None = None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("cpmi needs a ROCm GPU; none is visible")
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = C.c_void_p()
+        path = tune_cache.encode() if tune_cache else None
+        rc = _lib.cpmi_create(C.byref(h), self.device, path)
+        if rc != OK:
+            raise CpmiError(rc, "cpmi_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.cpmi_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- helpers
+    def _check(self, rc: int):
+        if rc != OK:
+            raise CpmiError(rc, _lib.cpmi_last_error(self._h).decode(errors="replace"))
+
+    def last_error(self) -> str:
+        return _lib.cpmi_last_error(self._h).decode(errors="replace")
+
+    def stats(self) -> Stats:
+        s = _CStats()
+        self._check(_lib.cpmi_last_stats(self._h, C.byref(s)))
+        return Stats(*(getattr(s, f) for f, _ in _CStats._fields_))
+
+    def set_tile(self, precision, tile: int):
+        self._check(_lib.cpmi_set_tile(self._h, _prec(precision), int(tile)))
+
+    @staticmethod
+    def _points_args(pts):
+        import torch
+        if pts.device.type != "cuda":
+            raise ValueError("points must be a GPU tensor")
+        if pts.dim() != 2 or pts.stride(1) != 1:
+            raise ValueError("points must be a 2-D tensor with unit column stride")
+        if pts.dtype == torch.float32:
+            dt = F32
+        elif pts.dtype == torch.int8:
+            dt = I8
+        else:
+            raise TypeError("points must be float32 or int8")
+        return dt, pts.shape[0], pts.shape[1], max(pts.stride(0), pts.shape[1])
+
+    def _radius_call(self, fn, cap):
+        """Two-call capacity protocol: try with `cap`, retry with the count."""
+        import torch
+        cap = max(int(cap), 1)
+        while True:
+            pairs = torch.empty((cap, 2), dtype=torch.int64, device=f"cuda:{self.device}")
+            d2 = torch.empty(cap, dtype=torch.float64, device=f"cuda:{self.device}")
+            cnt = C.c_int64(0)
+            rc = fn(pairs, d2, cap, cnt)
+            if rc == ERR_CAPACITY:
+                cap = int(cnt.value)
+                continue
+            return rc, pairs[:cnt.value], d2[:cnt.value]
+
+    # ---- the calls of cpmi.h
+    def closest_pair(self, pts, precision="auto", stream=None) -> Pair:
+        dt, n, d, ld = self._points_args(pts)
+        out = _CPair()
+        self._check(_lib.cpmi_closest_pair(self._h, C.c_void_p(pts.data_ptr()), dt, n, d, ld, _prec(precision),
+                                           _stream_ptr(stream), C.byref(out)))
+        return _pair(out)
+
+    def frnn(self, pts, R2: float, precision="auto", stream=None, cap: int = 1 << 16):
+        dt, n, d, ld = self._points_args(pts)
+        rc, pairs, d2 = self._radius_call(
+            lambda P, D, k, cnt: _lib.cpmi_frnn(self._h, C.c_void_p(pts.data_ptr()), dt, n, d, ld, float(R2),
+                                                _prec(precision), _stream_ptr(stream), C.c_void_p(P.data_ptr()),
+                                                C.c_void_p(D.data_ptr()), k, C.byref(cnt)), cap)
+        self._check(rc)
+        return pairs, d2
+
+    def points(self, pts, R2: float | None = None, precision="auto", stream=None, cap: int = 1 << 16,
+               want_pair: bool = True):
+        dt, n, d, ld = self._points_args(pts)
+        best = _CPair() if want_pair else None
+        r2 = -1.0 if R2 is None else float(R2)
+        if R2 is None:
+            self._check(_lib.cpmi_points(self._h, C.c_void_p(pts.data_ptr()), dt, n, d, ld, _prec(precision), r2,
+                                         _stream_ptr(stream), C.byref(best), None, None, 0, None))
+            return _pair(best), None
+        rc, pairs, d2 = self._radius_call(
+            lambda P, D, k, cnt: _lib.cpmi_points(self._h, C.c_void_p(pts.data_ptr()), dt, n, d, ld,
+                                                  _prec(precision), r2, _stream_ptr(stream),
+                                                  C.byref(best) if best is not None else None,
+                                                  C.c_void_p(P.data_ptr()), C.c_void_p(D.data_ptr()), k,
+                                                  C.byref(cnt)), cap)
+        self._check(rc)
+        return (_pair(best) if best is not None else None), (pairs, d2)
+
+    def motif(self, series, ell: int, excl: int = 0, R2: float | None = None, precision="auto", stream=None,
+              cap: int = 1 << 16, want_pair: bool = True):
+        import torch
+        if series.device.type != "cuda" or series.dtype != torch.float32 or series.dim() != 1 or \
+                series.stride(0) != 1:
+            raise ValueError("series must be a contiguous 1-D float32 GPU tensor")
+        best = _CPair() if want_pair else None
+        L = series.shape[0]
+        if R2 is None:
+            self._check(_lib.cpmi_motif(self._h, C.c_void_p(series.data_ptr()), L, int(ell), int(excl),
+                                        _prec(precision), -1.0, _stream_ptr(stream), C.byref(best), None, None, 0,
+                                        None))
+            return _pair(best), None
+        rc, pairs, d2 = self._radius_call(
+            lambda P, D, k, cnt: _lib.cpmi_motif(self._h, C.c_void_p(series.data_ptr()), L, int(ell), int(excl),
+                                                 _prec(precision), float(R2), _stream_ptr(stream),
+                                                 C.byref(best) if best is not None else None,
+                                                 C.c_void_p(P.data_ptr()), C.c_void_p(D.data_ptr()), k,
+                                                 C.byref(cnt)), cap)
+        self._check(rc)
+        return (_pair(best) if best is not None else None), (pairs, d2)
+
+    def motif_batch(self, series_list, ells, precision="auto", stream=None):
+        """Per-series motifs; returns a list of Pair or CpmiError (per-series status)."""
+        import torch
+        ns = len(series_list)
+        ptrs = (C.c_void_p * ns)()
+        lens = (C.c_int64 * ns)()
+        ell_arr = (C.c_int64 * ns)()
+        for k, (t, e) in enumerate(zip(series_list, ells)):
+            if t.device.type != "cuda" or t.dtype != torch.float32 or t.dim() != 1 or t.stride(0) != 1:
+                raise ValueError("each series must be a contiguous 1-D float32 GPU tensor")
+            ptrs[k] = t.data_ptr()
+            lens[k] = t.shape[0]
+            ell_arr[k] = int(e)
+        out = (_CPair * ns)()
+        self._check(_lib.cpmi_motif_batch(self._h, ptrs, lens, ell_arr, ns, _prec(precision), _stream_ptr(stream),
+                                          out))
+        res = []
+        for k in range(ns):
+            if out[k].status != OK:
+                res.append(CpmiError(out[k].status, f"series {k}"))
+            else:
+                res.append(_pair(out[k]))
+        return res
+
+    # ---- diagnostics
+    def dbg_znorm(self, series, ell: int, precision="f32", stream=None):
+        import torch
+        N = series.shape[0] - ell + 1
+        mu = torch.empty(N, dtype=torch.float64, device=series.device)
+        sg = torch.empty(N, dtype=torch.float64, device=series.device)
+        self._check(_lib.cpmi_dbg_znorm(self._h, C.c_void_p(series.data_ptr()), series.shape[0], int(ell),
+                                        _prec(precision), C.c_void_p(mu.data_ptr()), C.c_void_p(sg.data_ptr()),
+                                        _stream_ptr(stream)))
+        return mu, sg
+
+
+def dbg_mfma_probe(precision, A, B, C_out, stream=None):
+    rc = _lib.cpmi_dbg_mfma_probe(_prec(precision), C.c_void_p(A.data_ptr()), C.c_void_p(B.data_ptr()),
+                                  C.c_void_p(C_out.data_ptr()), _stream_ptr(stream))
+    if rc != OK:
+        raise CpmiError(rc, "mfma probe failed")
+
+
+_default = None
+
+
+def default_context() -> Context:
+    global _default
+    if _default is None:
+        _default = Context()
+    return _default
+
+
+def closest_pair(pts, precision="auto", stream=None) -> Pair:
+    return default_context().closest_pair(pts, precision, stream)
+
+
+def frnn(pts, R2: float, precision="auto", stream=None):
+    return default_context().frnn(pts, R2, precision, stream)
+
+
+def points(pts, R2=None, precision="auto", stream=None):
+    return default_context().points(pts, R2, precision, stream)
+
+
+def motif(series, ell: int, excl: int = 0, R2=None, precision="auto", stream=None):
+    return default_context().motif(series, ell, excl, R2, precision, stream)
+
+
+def motif_batch(series_list, ells, precision="auto", stream=None):
+    return default_context().motif_batch(series_list, ells, precision, stream)

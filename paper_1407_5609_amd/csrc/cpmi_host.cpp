@@ -1,0 +1,863 @@
+// Host side of the cpmi C ABI: argument checks, workspace, tile lists, the
+// launch sequence of one exact search, buffer growth, HIP-graph replay of the
+// batched motif search, and the tuned-configuration cache.
+//
+// One exact search over a set of problems (point sets or series) enqueues:
+//   reset -> row prep / window builder -> screen pass 1 (tile minima, radius
+//   candidates) -> bound reduction and tile selection -> screen pass 2 on the
+//   selected tiles (closest-pair candidates) -> FP64 verification -> result
+// and synchronises once. Candidate buffers that overflowed are grown and the
+// search is re-run (the screen never writes past a buffer's capacity; its
+// counters keep counting, so the size needed is known after one run).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cpmi.h"
+#include "bound.h"
+#include "cpmi_internal.h"
+
+using namespace cpmi;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+struct HostProb {
+    int64_t n = 0, d = 0, ld = 0;   // rows, dimension, source stride
+    int64_t excl = 1;
+    int motif = 0;
+    int src_i8 = 0;
+    double r2 = -1.0;
+    const void *src = nullptr;      // points, or the series
+    int64_t len = 0;                // series length (motif)
+    int32_t kpad = 0;
+    int64_t npad = 0;
+    // workspace offsets
+    size_t xs_off = 0, sh_off = 0, bm_off = 0, mu_off = 0;
+};
+
+constexpr int NCNT = 4;  // counters: radius candidates, pair candidates, selected tiles, radius pairs
+enum { C_R = 0, C_U = 1, C_SEL = 2, C_OUT = 3 };
+
+}  // namespace
+
+struct cpmi_ctx {
+    int device = 0;
+    std::string err;
+    cpmi_stats stats{};
+    int tile_override[4] = {0, 0, 0, 0};
+    std::vector<std::pair<std::string, int>> tuned;  // ("bf16:k512", tile)
+
+    DevBuf xs, shat, bmax, musg, probs, jobs, tiles, tile_min, sel, candR, candU, cand_d2, keys, vals, cnt, ubits, res;
+    uint32_t capR = 1u << 20, capU = 1u << 18, capOut = 1u << 20;
+
+    // host mirrors
+    void *pinned = nullptr;  // counters + results read back
+    size_t pinned_cap = 0;
+
+    // tile list cache
+    std::vector<int64_t> tiles_key;
+    int64_t ntiles = 0;
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t own = nullptr;
+
+    // captured batch graph
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int64_t> graph_key;
+};
+
+namespace {
+
+int fail(cpmi_ctx *c, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(cpmi_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(c, call)                                                                                  \
+    do {                                                                                                 \
+        hipError_t e_ = (call);                                                                          \
+        if (e_ != hipSuccess) return fail((c), CPMI_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+int ensure(cpmi_ctx *c, DevBuf &b, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    if (b.cap >= bytes) return CPMI_OK;
+    if (b.p) {
+        HIPCHK(c, hipDeviceSynchronize());
+        HIPCHK(c, hipFree(b.p));
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    want = (want + 4095) & ~(size_t)4095;
+    HIPCHK(c, hipMalloc(&b.p, want));
+    b.cap = want;
+    // any captured graph refers to the old addresses
+    if (c->gexec) {
+        hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+        c->graph_key.clear();
+    }
+    return CPMI_OK;
+}
+
+int ensure_pinned(cpmi_ctx *c, size_t bytes)
+{
+    if (c->pinned_cap >= bytes) return CPMI_OK;
+    if (c->pinned) hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    c->pinned_cap = 0;
+    HIPCHK(c, hipHostMalloc(&c->pinned, bytes, hipHostMallocDefault));
+    c->pinned_cap = bytes;
+    return CPMI_OK;
+}
+
+int elem_bytes(int prec) { return prec == P_F32 ? 4 : (prec == P_BF16 ? 2 : 1); }
+
+// Rows are padded to a whole number of 128-byte LDS slices.
+int32_t kpad_for(int prec, int64_t d)
+{
+    const int64_t per = 128 / elem_bytes(prec);
+    return (int32_t)((d + per - 1) / per * per);
+}
+
+const char *prec_name(int prec) { return prec == P_F32 ? "f32" : (prec == P_BF16 ? "bf16" : "i8"); }
+
+int kbucket(int64_t kpad)
+{
+    int b = 64;
+    while (b < kpad && b < 8192) b <<= 1;
+    return b;
+}
+
+int pick_tile(cpmi_ctx *c, int prec, int64_t kpad)
+{
+    if (c->tile_override[prec]) return c->tile_override[prec];
+    char key[64];
+    snprintf(key, sizeof key, "%s:k%d", prec_name(prec), kbucket(kpad));
+    for (auto &kv : c->tuned)
+        if (kv.first == key) return kv.second;
+    return 128;
+}
+
+// Minimal reader of the tuner's JSON object {"bf16:k512": 256, ...}.
+void load_tune_cache(cpmi_ctx *c, const char *path)
+{
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    std::string s;
+    char buf[4096];
+    size_t k;
+    while ((k = fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, k);
+    fclose(f);
+    size_t pos = 0;
+    while ((pos = s.find('"', pos)) != std::string::npos) {
+        size_t e = s.find('"', pos + 1);
+        if (e == std::string::npos) break;
+        std::string key = s.substr(pos + 1, e - pos - 1);
+        size_t colon = s.find(':', e);
+        if (colon == std::string::npos) break;
+        char *end = nullptr;
+        long v = strtol(s.c_str() + colon + 1, &end, 10);
+        if (end != s.c_str() + colon + 1 && (v == 128 || v == 256) && key.find(":k") != std::string::npos)
+            c->tuned.emplace_back(key, (int)v);
+        pos = e + 1;
+    }
+}
+
+int64_t pairs_of(int64_t n, int64_t excl)
+{
+    const int64_t m = n - excl;
+    return m > 0 ? m * (m + 1) / 2 : 0;
+}
+
+// Tile list: upper-triangle tiles holding at least one admissible pair. For a
+// single problem, tiles are ordered in bands of 8 tile rows (column-major in a
+// band, so concurrent work-groups share row and column panels) and the list is
+// split into 8 contiguous chunks interleaved slot by slot, so that the
+// work-groups the dispatcher sends to one XCD (slot % 8) walk one chunk and
+// keep its panels in that XCD's L2. For several problems (uneven costs) the
+// tiles are listed most-expensive problem first and dispatched in order.
+void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t> &out)
+{
+    std::vector<uint64_t> L;
+    std::vector<size_t> order(hp.size());
+    for (size_t p = 0; p < hp.size(); ++p) order[p] = p;
+    if (hp.size() > 1)
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+            return hp[a].kpad > hp[b].kpad || (hp[a].kpad == hp[b].kpad && hp[a].n > hp[b].n);
+        });
+    const int64_t G = 8;
+    for (size_t oi = 0; oi < hp.size(); ++oi) {
+        const size_t p = order[oi];
+        const HostProb &h = hp[p];
+        if (pairs_of(h.n, h.excl) == 0) continue;
+        const int64_t nT = (h.n + tile - 1) / tile;
+        for (int64_t b0 = 0; b0 < nT; b0 += G)
+            for (int64_t J = b0; J < nT; ++J)
+                for (int64_t I = b0; I < std::min(b0 + G, nT) && I <= J; ++I) {
+                    const int64_t maxj = std::min(J * tile + tile - 1, h.n - 1);
+                    if (maxj - I * tile >= h.excl) L.push_back(tile_pack((uint32_t)p, (uint32_t)I, (uint32_t)J));
+                }
+    }
+    out.clear();
+    if (hp.size() == 1) {
+        const int64_t T = (int64_t)L.size();
+        const int64_t C = (T + 7) / 8;
+        out.resize(C * 8, TILE_NONE);
+        for (int64_t s = 0; s < C * 8; ++s) {
+            const int64_t src = (s % 8) * C + s / 8;
+            if (src < T) out[s] = L[src];
+        }
+    } else {
+        out = L;
+    }
+}
+
+struct RunOut {
+    std::vector<ResDev> res;
+    uint32_t cnt[NCNT];
+};
+
+// Launch the whole exact search for the problems in hp; synchronises once.
+int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool want_cpp, bool want_frnn,
+               hipStream_t st, bool batch_graph, RunOut &ro)
+{
+    const int64_t np = (int64_t)hp.size();
+    const int esz = elem_bytes(prec);
+    // ---- workspace layout
+    size_t xs_b = 0, sh_b = 0, bm_b = 0, mu_b = 0;
+    for (auto &h : hp) {
+        h.kpad = kpad_for(prec, h.d);
+        h.npad = (h.n + 255) / 256 * 256;
+        h.xs_off = xs_b;
+        xs_b += (size_t)h.npad * h.kpad * esz;
+        h.sh_off = sh_b;
+        sh_b += (size_t)h.npad * 4;
+        h.bm_off = bm_b;
+        bm_b += (size_t)(h.npad / tile) * sizeof(float4);
+        h.mu_off = mu_b;
+        if (h.motif) mu_b += (size_t)h.npad * 8;
+    }
+    int rc;
+    if ((rc = ensure(c, c->xs, xs_b))) return rc;
+    if ((rc = ensure(c, c->shat, sh_b))) return rc;
+    if ((rc = ensure(c, c->bmax, bm_b))) return rc;
+    if ((rc = ensure(c, c->musg, 2 * mu_b))) return rc;
+    if ((rc = ensure(c, c->probs, np * sizeof(Prob)))) return rc;
+    if ((rc = ensure(c, c->res, np * sizeof(ResDev)))) return rc;
+    if ((rc = ensure(c, c->ubits, np * 8))) return rc;
+    if ((rc = ensure(c, c->cnt, NCNT * 4))) return rc;
+
+    // ---- tile list (cached by shape)
+    std::vector<int64_t> key{(int64_t)tile, np};
+    for (auto &h : hp) {
+        key.push_back(h.n);
+        key.push_back(h.excl);
+        key.push_back(h.kpad);
+    }
+    if (key != c->tiles_key) {
+        std::vector<uint64_t> tl;
+        build_tiles(hp, tile, tl);
+        if ((rc = ensure(c, c->tiles, tl.size() * 8))) return rc;
+        if ((rc = ensure(c, c->tile_min, tl.size() * 4))) return rc;
+        if ((rc = ensure(c, c->sel, tl.size() * 8))) return rc;
+        if (!tl.empty()) HIPCHK(c, hipMemcpy(c->tiles.p, tl.data(), tl.size() * 8, hipMemcpyHostToDevice));
+        c->ntiles = (int64_t)tl.size();
+        c->tiles_key = key;
+    }
+    const int64_t ntiles = c->ntiles;
+
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        if ((rc = ensure(c, c->candR, (size_t)c->capR * sizeof(Cand)))) return rc;
+        if ((rc = ensure(c, c->candU, (size_t)c->capU * sizeof(Cand)))) return rc;
+        if ((rc = ensure(c, c->cand_d2, (size_t)c->capU * 8))) return rc;
+        if ((rc = ensure(c, c->keys, (size_t)c->capOut * 8))) return rc;
+        if ((rc = ensure(c, c->vals, (size_t)c->capOut * 8))) return rc;
+
+        // ---- problem descriptors
+        std::vector<Prob> P(np);
+        std::vector<SeriesJob> jobs;
+        int64_t blk = 0;
+        for (int64_t p = 0; p < np; ++p) {
+            const HostProb &h = hp[p];
+            Prob &q = P[p];
+            memset(&q, 0, sizeof q);
+            q.xs = (char *)c->xs.p + h.xs_off;
+            q.shat = (char *)c->shat.p + h.sh_off;
+            q.bmax = (const float4 *)((char *)c->bmax.p + h.bm_off);
+            q.src = h.src;
+            q.n = h.n;
+            q.d = h.d;
+            q.ld = h.ld;
+            q.kpad = h.kpad;
+            q.excl = (int32_t)h.excl;
+            q.motif = h.motif;
+            q.src_i8 = h.src_i8;
+            q.r2 = h.r2;
+            if (h.motif) {
+                q.mu = (const double *)((char *)c->musg.p + h.mu_off);
+                q.sigma = (const double *)((char *)c->musg.p + mu_b + h.mu_off);
+                SeriesJob j;
+                memset(&j, 0, sizeof j);
+                j.T = (const float *)h.src;
+                j.len = h.len;
+                j.ell = h.d;
+                j.npad = h.npad;
+                j.blk_base = blk;
+                blk += h.npad / 256;
+                j.xs = (void *)q.xs;
+                j.shat = (void *)q.shat;
+                j.bmax = (float4 *)q.bmax;
+                j.mu = (double *)q.mu;
+                j.sigma = (double *)q.sigma;
+                j.flags = &((ResDev *)c->res.p)[p].flags;
+                j.kpad = h.kpad;
+                jobs.push_back(j);
+            }
+        }
+        HIPCHK(c, hipMemcpyAsync(c->probs.p, P.data(), np * sizeof(Prob), hipMemcpyHostToDevice, st));
+        if (!jobs.empty()) {
+            if ((rc = ensure(c, c->jobs, jobs.size() * sizeof(SeriesJob)))) return rc;
+            HIPCHK(c, hipMemcpyAsync(c->jobs.p, jobs.data(), jobs.size() * sizeof(SeriesJob), hipMemcpyHostToDevice,
+                                     st));
+        }
+
+        const Prob *dprobs = (const Prob *)c->probs.p;
+        ResDev *dres = (ResDev *)c->res.p;
+        uint32_t *dcnt = (uint32_t *)c->cnt.p;
+        auto enqueue = [&]() {
+            launch_reset_res(dres, np, st);
+            launch_fill_u32(dcnt, 0u, NCNT, st);
+            launch_fill_u64((uint64_t *)c->ubits.p, 0x7ff0000000000000ull, np, st);
+            launch_fill_u32((uint32_t *)c->bmax.p, 0u, (int64_t)(bm_b / 4), st);
+            if (!jobs.empty()) {
+                launch_prep_series((const SeriesJob *)c->jobs.p, (int64_t)jobs.size(), blk, prec, tile, st);
+            } else {
+                const HostProb &h = hp[0];
+                launch_prep_points(h.src, h.src_i8 ? CPMI_I8 : CPMI_F32, h.n, h.d, h.ld, prec, P[0].xs ? (void *)P[0].xs : nullptr,
+                                   h.kpad, h.npad, (void *)P[0].shat, (float4 *)P[0].bmax, tile, &dres[0].flags, st);
+            }
+            ScreenArgs a;
+            memset(&a, 0, sizeof a);
+            a.probs = dprobs;
+            a.tiles = (const uint64_t *)c->tiles.p;
+            a.ntiles = ntiles;
+            a.tile_min = (uint32_t *)c->tile_min.p;
+            a.candR = (Cand *)c->candR.p;
+            a.cntR = dcnt + C_R;
+            a.capR = c->capR;
+            a.candU = (Cand *)c->candU.p;
+            a.cntU = dcnt + C_U;
+            a.capU = c->capU;
+            launch_screen(prec, tile, want_frnn ? (M_MIN | M_EMIT_R) : M_MIN, a, ntiles, st);
+            if (want_cpp) {
+                launch_reduce_U(dprobs, a.tiles, ntiles, a.tile_min, prec, (unsigned long long *)c->ubits.p, st);
+                launch_select(dprobs, a.tiles, ntiles, a.tile_min, prec, (const unsigned long long *)c->ubits.p,
+                              (uint64_t *)c->sel.p, dcnt + C_SEL, st);
+                ScreenArgs b = a;
+                b.tiles = (const uint64_t *)c->sel.p;
+                b.sel_count = dcnt + C_SEL;
+                b.U = (const double *)c->ubits.p;
+                launch_screen(prec, tile, M_EMIT_U, b, std::min<int64_t>(std::max<int64_t>(ntiles, 1), 2048), st);
+                launch_verify_cpp(dprobs, (const Cand *)c->candU.p, dcnt + C_U, c->capU, prec, tile,
+                                  (double *)c->cand_d2.p, dres, st);
+                launch_pick_cpp((const Cand *)c->candU.p, dcnt + C_U, c->capU, (const double *)c->cand_d2.p, dres,
+                                st);
+            }
+            if (want_frnn)
+                launch_verify_frnn(dprobs, (const Cand *)c->candR.p, dcnt + C_R, c->capR, prec, tile,
+                                   (uint64_t *)c->keys.p, (double *)c->vals.p, dcnt + C_OUT, c->capOut, dres, st);
+        };
+
+        HIPCHK(c, hipEventRecord(c->ev0, st));
+        if (batch_graph) {
+            std::vector<int64_t> gkey = key;
+            gkey.push_back(prec);
+            gkey.push_back((int64_t)c->capR);
+            gkey.push_back((int64_t)c->capU);
+            if (!c->gexec || gkey != c->graph_key) {
+                if (c->gexec) {
+                    hipGraphExecDestroy(c->gexec);
+                    c->gexec = nullptr;
+                }
+                hipGraph_t g = nullptr;
+                HIPCHK(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                enqueue();
+                hipError_t e = hipStreamEndCapture(st, &g);
+                if (e != hipSuccess) return fail(c, CPMI_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+                e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+                hipGraphDestroy(g);
+                if (e != hipSuccess) {
+                    c->gexec = nullptr;
+                    return fail(c, CPMI_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+                }
+                c->graph_key = gkey;
+            }
+            HIPCHK(c, hipGraphLaunch(c->gexec, st));
+        } else {
+            enqueue();
+        }
+        HIPCHK(c, hipGetLastError());
+        const size_t rb = np * sizeof(ResDev) + NCNT * 4;
+        if ((rc = ensure_pinned(c, rb))) return rc;
+        HIPCHK(c, hipMemcpyAsync(c->pinned, c->res.p, np * sizeof(ResDev), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync((char *)c->pinned + np * sizeof(ResDev), c->cnt.p, NCNT * 4, hipMemcpyDeviceToHost,
+                                 st));
+        HIPCHK(c, hipEventRecord(c->ev1, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, c->ev0, c->ev1);
+        c->stats.kernel_ms = ms;
+        ro.res.assign((ResDev *)c->pinned, (ResDev *)c->pinned + np);
+        memcpy(ro.cnt, (char *)c->pinned + np * sizeof(ResDev), sizeof ro.cnt);
+
+        bool again = false;
+        if (ro.cnt[C_R] > c->capR) {
+            c->capR = ro.cnt[C_R] + ro.cnt[C_R] / 2 + 1024;
+            again = true;
+        }
+        if (ro.cnt[C_U] > c->capU) {
+            c->capU = ro.cnt[C_U] + ro.cnt[C_U] / 2 + 1024;
+            again = true;
+        }
+        if (ro.cnt[C_OUT] > c->capOut) {
+            c->capOut = ro.cnt[C_OUT] + ro.cnt[C_OUT] / 2 + 1024;
+            again = true;
+        }
+        // a flagged input makes the candidate counts meaningless; report, don't grow
+        bool flagged = false;
+        for (auto &r : ro.res) flagged |= r.flags != 0;
+        if (again && !flagged) {
+            c->stats.reruns++;
+            continue;
+        }
+        c->stats.tiles_total = ntiles;
+        c->stats.tiles_rescreened = ro.cnt[C_SEL];
+        c->stats.cpp_candidates = ro.cnt[C_U];
+        c->stats.frnn_candidates = ro.cnt[C_R];
+        c->stats.frnn_pairs = ro.cnt[C_OUT];
+        c->stats.precision = prec;
+        c->stats.tile = tile;
+        int64_t vp = 0;
+        for (auto &h : hp) vp += pairs_of(h.n, h.excl);
+        c->stats.valid_pairs = vp;
+        float mr = 0.f;
+        for (auto &r : ro.res) mr = std::max(mr, __builtin_bit_cast(float, r.ratio_bits));
+        c->stats.max_err_over_bound = mr;
+        return CPMI_OK;
+    }
+    return fail(c, CPMI_ERR_HIP, "candidate buffers kept overflowing");
+}
+
+int flags_error(cpmi_ctx *c, uint32_t f)
+{
+    if (f & F_NONFINITE) return fail(c, CPMI_ERR_NONFINITE, "input holds NaN or Inf");
+    if (f & F_DEGENERATE) return fail(c, CPMI_ERR_DEGENERATE, "a window has zero variance");
+    if (f & F_RANGE) return fail(c, CPMI_ERR_RANGE, "a squared norm is too large for the FP32 screen");
+    return CPMI_OK;
+}
+
+void fill_pair(const ResDev &r, cpmi_pair *out)
+{
+    memset(out, 0, sizeof *out);
+    if (r.best_d2 == ~0ull || r.best_ij == ~0ull) {
+        out->i = out->j = -1;
+        out->status = CPMI_ERR_NOPAIR;
+        return;
+    }
+    out->i = (int64_t)(r.best_ij >> 32);
+    out->j = (int64_t)(r.best_ij & 0xffffffffu);
+    memcpy(&out->d2, &r.best_d2, 8);
+    out->d = std::sqrt(out->d2);
+    out->screen_err = __builtin_bit_cast(float, r.err_bits);
+    out->screen_bound = __builtin_bit_cast(float, r.bound_bits);
+    out->status = CPMI_OK;
+}
+
+// Sort the verified radius pairs and copy them to the caller.
+int finish_frnn(cpmi_ctx *c, uint32_t count, hipStream_t st, int64_t *pairs, double *d2, int64_t cap,
+                int64_t *count_out)
+{
+    if (count_out) *count_out = count;
+    if ((int64_t)count > cap) return fail(c, CPMI_ERR_CAPACITY, "%u pairs within the radius, capacity %lld", count, (long long)cap);
+    if (count == 0) return CPMI_OK;
+    int64_t mpad = 1;
+    while (mpad < (int64_t)count) mpad <<= 1;
+    if ((size_t)mpad * 8 > c->keys.cap || (size_t)mpad * 8 > c->vals.cap) {
+        // grow while keeping the verified pairs
+        DevBuf nk, nv;
+        HIPCHK(c, hipMalloc(&nk.p, mpad * 8));
+        HIPCHK(c, hipMalloc(&nv.p, mpad * 8));
+        HIPCHK(c, hipMemcpyAsync(nk.p, c->keys.p, (size_t)count * 8, hipMemcpyDeviceToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(nv.p, c->vals.p, (size_t)count * 8, hipMemcpyDeviceToDevice, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        hipFree(c->keys.p);
+        hipFree(c->vals.p);
+        c->keys.p = nk.p;
+        c->keys.cap = mpad * 8;
+        c->vals.p = nv.p;
+        c->vals.cap = mpad * 8;
+        if (c->gexec) {
+            hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+            c->graph_key.clear();
+        }
+    }
+    launch_sort_pairs((uint64_t *)c->keys.p, (double *)c->vals.p, count, mpad, st);
+    launch_emit_pairs((const uint64_t *)c->keys.p, (const double *)c->vals.p, count, pairs, d2, st);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(st));
+    return CPMI_OK;
+}
+
+int resolve_prec(cpmi_ctx *c, int dtype, int precision)
+{
+    if (dtype == CPMI_I8) {
+        if (precision == CPMI_PREC_AUTO || precision == CPMI_PREC_I8) return P_I8;
+        return fail(c, CPMI_ERR_ARG, "int8 points take CPMI_PREC_I8 (or AUTO)");
+    }
+    if (precision == CPMI_PREC_AUTO || precision == CPMI_PREC_BF16) return P_BF16;
+    if (precision == CPMI_PREC_F32) return P_F32;
+    return fail(c, CPMI_ERR_ARG, "unknown precision %d for float32 input", precision);
+}
+
+int set_device(cpmi_ctx *c)
+{
+    HIPCHK(c, hipSetDevice(c->device));
+    return CPMI_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int cpmi_version(void) { return 10000; }
+
+int cpmi_create(cpmi_ctx **out, int device, const char *tune_cache_path)
+{
+    if (!out) return CPMI_ERR_ARG;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CPMI_ERR_ARG;
+    cpmi_ctx *c = new cpmi_ctx();
+    c->device = device;
+    if (hipSetDevice(device) != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
+        hipEventCreate(&c->ev1) != hipSuccess || hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return CPMI_ERR_HIP;
+    }
+    load_tune_cache(c, tune_cache_path);
+    *out = c;
+    return CPMI_OK;
+}
+
+int cpmi_destroy(cpmi_ctx *c)
+{
+    if (!c) return CPMI_OK;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    if (c->gexec) hipGraphExecDestroy(c->gexec);
+    DevBuf *bufs[] = {&c->xs, &c->shat, &c->bmax, &c->musg, &c->probs, &c->jobs, &c->tiles, &c->tile_min, &c->sel,
+                      &c->candR, &c->candU, &c->cand_d2, &c->keys, &c->vals, &c->cnt, &c->ubits, &c->res};
+    for (DevBuf *b : bufs)
+        if (b->p) hipFree(b->p);
+    if (c->pinned) hipHostFree(c->pinned);
+    if (c->ev0) hipEventDestroy(c->ev0);
+    if (c->ev1) hipEventDestroy(c->ev1);
+    if (c->own) hipStreamDestroy(c->own);
+    delete c;
+    return CPMI_OK;
+}
+
+const char *cpmi_last_error(cpmi_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int cpmi_last_stats(cpmi_ctx *c, cpmi_stats *out)
+{
+    if (!c || !out) return CPMI_ERR_ARG;
+    *out = c->stats;
+    return CPMI_OK;
+}
+
+int cpmi_set_tile(cpmi_ctx *c, int precision, int tile)
+{
+    if (!c || precision < 1 || precision > 3) return CPMI_ERR_ARG;
+    if (tile != 0 && tile != 128 && tile != 256) return fail(c, CPMI_ERR_ARG, "tile must be 0, 128 or 256");
+    c->tile_override[precision] = tile;
+    return CPMI_OK;
+}
+
+int cpmi_points(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, int precision, double R2,
+                void *stream, cpmi_pair *best, int64_t *pairs, double *d2, int64_t cap, int64_t *count_out)
+{
+    if (!c) return CPMI_ERR_ARG;
+    c->err.clear();
+    c->stats = cpmi_stats{};
+    const bool want_frnn = R2 >= 0.0;
+    const bool want_cpp = best != nullptr;
+    if (best) memset(best, 0, sizeof *best);
+    if (count_out) *count_out = 0;
+    if (!pts) return fail(c, CPMI_ERR_ARG, "points pointer is NULL");
+    if (dtype != CPMI_F32 && dtype != CPMI_I8) return fail(c, CPMI_ERR_ARG, "unknown dtype %d", dtype);
+    if (d < 1 || ld < d || n < 0) return fail(c, CPMI_ERR_ARG, "bad shape n=%lld d=%lld ld=%lld", (long long)n, (long long)d, (long long)ld);
+    if (n >= (1ll << 31) - 256) return fail(c, CPMI_ERR_ARG, "n must be below 2^31");
+    if (dtype == CPMI_I8 && d > 32768) return fail(c, CPMI_ERR_ARG, "int8 dimension must be <= 32768 (int32 Gram)");
+    if (d > (1 << 20)) return fail(c, CPMI_ERR_ARG, "dimension must be <= 2^20");
+    if (!want_cpp && !want_frnn) return fail(c, CPMI_ERR_ARG, "nothing requested (best == NULL and R2 < 0)");
+    if (want_frnn && (!pairs || !count_out || cap < 0)) return fail(c, CPMI_ERR_ARG, "radius search needs pairs, cap and count_out");
+    if (std::isnan(R2)) return fail(c, CPMI_ERR_ARG, "R2 is NaN");
+    if (n < 2) {
+        if (best) best->status = CPMI_ERR_NOPAIR, best->i = best->j = -1;
+        return fail(c, CPMI_ERR_NOPAIR, "fewer than two points");
+    }
+    const int prec = resolve_prec(c, dtype, precision);
+    if (prec < 0) return prec;
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<HostProb> hp(1);
+    hp[0].n = n;
+    hp[0].d = d;
+    hp[0].ld = ld;
+    hp[0].excl = 1;
+    hp[0].src = pts;
+    hp[0].src_i8 = dtype == CPMI_I8;
+    hp[0].r2 = want_frnn ? R2 : -1.0;
+    const int tile = pick_tile(c, prec, kpad_for(prec, d));
+    RunOut ro;
+    if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro))) return rc;
+    if ((rc = flags_error(c, ro.res[0].flags))) return rc;
+    if (want_cpp) {
+        fill_pair(ro.res[0], best);
+        if (best->status) return fail(c, best->status, "no admissible pair");
+    }
+    if (want_frnn) return finish_frnn(c, ro.cnt[C_OUT], st, pairs, d2, cap, count_out);
+    return CPMI_OK;
+}
+
+int cpmi_closest_pair(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, int precision,
+                      void *stream, cpmi_pair *out)
+{
+    if (!out) return c ? fail(c, CPMI_ERR_ARG, "out is NULL") : CPMI_ERR_ARG;
+    return cpmi_points(c, pts, dtype, n, d, ld, precision, -1.0, stream, out, nullptr, nullptr, 0, nullptr);
+}
+
+int cpmi_frnn(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, double R2, int precision,
+              void *stream, int64_t *pairs, double *d2, int64_t cap, int64_t *count_out)
+{
+    if (!(R2 >= 0.0)) return c ? fail(c, CPMI_ERR_ARG, "R2 must be >= 0") : CPMI_ERR_ARG;
+    if (c && n < 2 && n >= 0 && d >= 1 && ld >= d && pts) {
+        if (count_out) *count_out = 0;
+        return CPMI_OK;  // no pair can be within the radius
+    }
+    return cpmi_points(c, pts, dtype, n, d, ld, precision, R2, stream, nullptr, pairs, d2, cap, count_out);
+}
+
+int cpmi_motif(cpmi_ctx *c, const float *series, int64_t len, int64_t ell, int64_t excl, int precision, double R2,
+               void *stream, cpmi_pair *best, int64_t *pairs, double *d2, int64_t cap, int64_t *count_out)
+{
+    if (!c) return CPMI_ERR_ARG;
+    c->err.clear();
+    c->stats = cpmi_stats{};
+    const bool want_frnn = R2 >= 0.0;
+    const bool want_cpp = best != nullptr;
+    if (best) memset(best, 0, sizeof *best);
+    if (count_out) *count_out = 0;
+    if (!series) return fail(c, CPMI_ERR_ARG, "series pointer is NULL");
+    if (ell < 2 || len < ell) return fail(c, CPMI_ERR_ARG, "need 2 <= ell <= len (ell=%lld len=%lld)", (long long)ell, (long long)len);
+    if (ell > 8192) return fail(c, CPMI_ERR_ARG, "ell must be <= 8192");
+    if (len >= (1ll << 31) - 256) return fail(c, CPMI_ERR_ARG, "len must be below 2^31");
+    if (!want_cpp && !want_frnn) return fail(c, CPMI_ERR_ARG, "nothing requested (best == NULL and R2 < 0)");
+    if (want_frnn && (!pairs || !count_out || cap < 0)) return fail(c, CPMI_ERR_ARG, "radius search needs pairs, cap and count_out");
+    if (std::isnan(R2)) return fail(c, CPMI_ERR_ARG, "R2 is NaN");
+    if (precision != CPMI_PREC_AUTO && precision != CPMI_PREC_F32 && precision != CPMI_PREC_BF16)
+        return fail(c, CPMI_ERR_ARG, "motif precision must be AUTO, F32 or BF16");
+    if (excl <= 0) excl = ell;
+    const int64_t N = len - ell + 1;
+    if (N <= excl) {
+        if (best) best->status = CPMI_ERR_NOPAIR, best->i = best->j = -1;
+        return fail(c, CPMI_ERR_NOPAIR, "no admissible window pair (windows=%lld, exclusion=%lld)", (long long)N, (long long)excl);
+    }
+    const int prec = resolve_prec(c, CPMI_F32, precision);
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<HostProb> hp(1);
+    hp[0].n = N;
+    hp[0].d = ell;
+    hp[0].ld = 1;
+    hp[0].excl = excl;
+    hp[0].motif = 1;
+    hp[0].src = series;
+    hp[0].len = len;
+    hp[0].r2 = want_frnn ? R2 : -1.0;
+    const int tile = pick_tile(c, prec, kpad_for(prec, ell));
+    RunOut ro;
+    if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro))) return rc;
+    if ((rc = flags_error(c, ro.res[0].flags))) return rc;
+    if (want_cpp) {
+        fill_pair(ro.res[0], best);
+        if (best->status) return fail(c, best->status, "no admissible pair");
+    }
+    if (want_frnn) return finish_frnn(c, ro.cnt[C_OUT], st, pairs, d2, cap, count_out);
+    return CPMI_OK;
+}
+
+int cpmi_motif_batch(cpmi_ctx *c, const float *const *series, const int64_t *lens, const int64_t *ells,
+                     int64_t nseries, int precision, void *stream, cpmi_pair *best)
+{
+    if (!c) return CPMI_ERR_ARG;
+    c->err.clear();
+    c->stats = cpmi_stats{};
+    if (!series || !lens || !ells || !best || nseries < 1) return fail(c, CPMI_ERR_ARG, "bad batch arguments");
+    if (nseries > (1 << 20)) return fail(c, CPMI_ERR_ARG, "at most 2^20 series per batch");
+    if (precision != CPMI_PREC_AUTO && precision != CPMI_PREC_F32 && precision != CPMI_PREC_BF16)
+        return fail(c, CPMI_ERR_ARG, "motif precision must be AUTO, F32 or BF16");
+    const int prec = resolve_prec(c, CPMI_F32, precision);
+    std::vector<HostProb> hp;
+    std::vector<int64_t> idx;  // batch position of each problem
+    int64_t kmax = 0;
+    for (int64_t s = 0; s < nseries; ++s) {
+        memset(&best[s], 0, sizeof best[s]);
+        best[s].i = best[s].j = -1;
+        const int64_t L = lens[s], ell = ells[s];
+        if (!series[s] || ell < 2 || ell > 8192 || L < ell || L >= (1ll << 31) - 256)
+            return fail(c, CPMI_ERR_ARG, "series %lld: bad arguments (len=%lld ell=%lld)", (long long)s, (long long)L, (long long)ell);
+        const int64_t N = L - ell + 1;
+        if (N <= ell) {
+            best[s].status = CPMI_ERR_NOPAIR;
+            continue;
+        }
+        HostProb h;
+        h.n = N;
+        h.d = ell;
+        h.ld = 1;
+        h.excl = ell;
+        h.motif = 1;
+        h.src = series[s];
+        h.len = L;
+        hp.push_back(h);
+        idx.push_back(s);
+        kmax = std::max<int64_t>(kmax, kpad_for(prec, ell));
+    }
+    if (hp.empty()) return CPMI_OK;
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (!st) {
+        // graphs cannot be captured on the null stream: run on the context's
+        // own stream, ordered after the work already queued on the null stream
+        HIPCHK(c, hipEventRecord(c->ev0, nullptr));
+        HIPCHK(c, hipStreamWaitEvent(c->own, c->ev0, 0));
+        st = c->own;
+    }
+    const int tile = pick_tile(c, prec, kmax);
+    RunOut ro;
+    if ((rc = run_search(c, hp, prec, tile, true, false, st, true, ro))) return rc;
+    for (size_t p = 0; p < hp.size(); ++p) {
+        cpmi_pair &b = best[idx[p]];
+        const int fe = flags_error(c, ro.res[p].flags);
+        if (fe) {
+            b.status = fe;
+            continue;
+        }
+        fill_pair(ro.res[p], &b);
+    }
+    c->err.clear();
+    return CPMI_OK;
+}
+
+// ---- debug entry points (declared in cpmi_debug.h) ------------------------
+
+int64_t cpmi_dbg_tile_list(int64_t n, int64_t excl, int tile, uint64_t *out, int64_t cap)
+{
+    if (n < 0 || excl < 1 || (tile != 128 && tile != 256)) return CPMI_ERR_ARG;
+    std::vector<HostProb> hp(1);
+    hp[0].n = n;
+    hp[0].excl = excl;
+    std::vector<uint64_t> tl;
+    build_tiles(hp, tile, tl);
+    for (int64_t k = 0; k < (int64_t)tl.size() && k < cap; ++k) out[k] = tl[k];
+    return (int64_t)tl.size();
+}
+
+double cpmi_dbg_tile_bound(const float *bI, const float *bJ, int32_t kpad, int64_t d, int precision)
+{
+    return tile_bound(make_float4(bI[0], bI[1], bI[2], bI[3]), make_float4(bJ[0], bJ[1], bJ[2], bJ[3]), kpad, d,
+                      precision);
+}
+
+int cpmi_dbg_mfma_probe(int precision, const void *A, const void *B, float *C, void *stream)
+{
+    if (precision < 1 || precision > 3 || !A || !B || !C) return CPMI_ERR_ARG;
+    launch_mfma_probe(precision, A, B, C, (hipStream_t)stream);
+    if (hipGetLastError() != hipSuccess) return CPMI_ERR_HIP;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return CPMI_ERR_HIP;
+    return CPMI_OK;
+}
+
+int cpmi_dbg_znorm(cpmi_ctx *c, const float *series, int64_t len, int64_t ell, int precision, double *mu,
+                   double *sigma, void *stream)
+{
+    if (!c || !series || !mu || !sigma || ell < 2 || len < ell) return CPMI_ERR_ARG;
+    const int prec = resolve_prec(c, CPMI_F32, precision);
+    if (prec < 0) return prec;
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t N = len - ell + 1;
+    const int32_t kpad = kpad_for(prec, ell);
+    const int64_t npad = (N + 255) / 256 * 256;
+    if ((rc = ensure(c, c->xs, (size_t)npad * kpad * elem_bytes(prec)))) return rc;
+    if ((rc = ensure(c, c->shat, (size_t)npad * 4))) return rc;
+    if ((rc = ensure(c, c->bmax, (size_t)(npad / 128) * 16))) return rc;
+    if ((rc = ensure(c, c->res, sizeof(ResDev)))) return rc;
+    if ((rc = ensure(c, c->jobs, sizeof(SeriesJob)))) return rc;
+    SeriesJob j;
+    memset(&j, 0, sizeof j);
+    j.T = series;
+    j.len = len;
+    j.ell = ell;
+    j.npad = npad;
+    j.blk_base = 0;
+    j.xs = c->xs.p;
+    j.shat = c->shat.p;
+    j.bmax = (float4 *)c->bmax.p;
+    j.mu = mu;
+    j.sigma = sigma;
+    j.flags = &((ResDev *)c->res.p)->flags;
+    j.kpad = kpad;
+    HIPCHK(c, hipMemcpyAsync(c->jobs.p, &j, sizeof j, hipMemcpyHostToDevice, st));
+    launch_reset_res((ResDev *)c->res.p, 1, st);
+    launch_fill_u32((uint32_t *)c->bmax.p, 0u, (npad / 128) * 4, st);
+    launch_prep_series((const SeriesJob *)c->jobs.p, 1, npad / 256, prec, 128, st);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(st));
+    return CPMI_OK;
+}
+
+}  // extern "C"

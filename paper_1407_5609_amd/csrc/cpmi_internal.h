@@ -1,0 +1,146 @@
+// Internal declarations shared by the host orchestration and the kernels of
+// the cpmi library (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cpmi {
+
+enum Prec : int { P_F32 = 1, P_BF16 = 2, P_I8 = 3 };
+
+// Screen modes of the Gram kernel (bit set).
+enum Mode : int {
+    M_MIN = 1,     // record the tile minimum of the screen value
+    M_EMIT_R = 2,  // emit pairs whose screen value is within the radius threshold
+    M_EMIT_U = 4   // emit pairs whose screen value is within the closest-pair threshold
+};
+
+// One flag word per problem; set by the builders, read back by the host.
+enum Flag : uint32_t { F_NONFINITE = 1u, F_DEGENERATE = 2u, F_RANGE = 4u };
+
+// A pair emitted by the screen: rows (i, j) of problem p and its screen value.
+struct Cand {
+    int32_t i, j;
+    float dt;
+    uint32_t p;
+};
+
+// Description of one problem (a point set, or the windows of one series).
+struct Prob {
+    const void *xs;        // screen operand: npad rows of kpad elements (FP32, BF16 bits or int8)
+    const void *shat;      // npad row scalars: fp32(||x||^2), or the exact int32 ||x||^2 for int8
+    const float4 *bmax;    // per block of `tile` rows: max of (s^, a, at, r), see bound.h
+    const void *src;       // canonical data: float or int8 points, or the float series
+    const double *mu;      // motif: canonical window means, else null
+    const double *sigma;   // motif: canonical window sigmas, else null
+    int64_t n;             // rows (points or windows)
+    int64_t d;             // true dimension (point dimension or window length)
+    int64_t ld;            // row stride of the point source (elements)
+    int32_t kpad;          // padded dimension (elements) of xs rows
+    int32_t excl;          // a pair is admissible iff j - i >= excl
+    int32_t motif;         // 1 if the rows are z-normalised windows of src
+    int32_t src_i8;        // 1 if src holds int8 points
+    double r2;             // squared radius (negative: no radius search)
+};
+
+// Tile-list entry: problem (20 bits) | block row I (22 bits) | block col J (22 bits).
+__host__ __device__ inline uint64_t tile_pack(uint32_t p, uint32_t I, uint32_t J)
+{
+    return ((uint64_t)p << 44) | ((uint64_t)I << 22) | (uint64_t)J;
+}
+__host__ __device__ inline uint32_t tile_prob(uint64_t t) { return (uint32_t)(t >> 44); }
+__host__ __device__ inline uint32_t tile_I(uint64_t t) { return (uint32_t)(t >> 22) & 0x3fffffu; }
+__host__ __device__ inline uint32_t tile_J(uint64_t t) { return (uint32_t)t & 0x3fffffu; }
+constexpr uint64_t TILE_NONE = ~0ull;
+
+// Arguments of the Gram screen kernel.
+struct ScreenArgs {
+    const Prob *probs;
+    const uint64_t *tiles;     // tile list
+    int64_t ntiles;            // entries (phase 1); phase 2 reads *sel_count
+    const uint32_t *sel_count; // phase 2: number of valid entries of `tiles`
+    uint32_t *tile_min;        // phase 1: per entry, min screen value (float or int32 bits)
+    const double *U;           // phase 2: per problem closest-pair upper bound (>= 0)
+    Cand *candR;               // radius candidates
+    uint32_t *cntR;            // their counter (may exceed capR: the required size)
+    uint32_t capR;
+    Cand *candU;               // closest-pair candidates
+    uint32_t *cntU;
+    uint32_t capU;
+};
+
+// Per-problem result of the verifier (device), reset before each run.
+struct ResDev {
+    unsigned long long best_d2;   // min canonical d2 over candidates (double bits; ~0 = none)
+    unsigned long long best_ij;   // min (i << 32 | j) among candidates at best_d2
+    unsigned int err_bits;        // max |screen - d2| over verified candidates (float bits, rounded up)
+    unsigned int ratio_bits;      // max |screen - d2| / bound (float bits, rounded up)
+    unsigned int bound_bits;      // max bound applied (float bits)
+    unsigned int flags;           // F_* input flags of the problem
+};
+
+// Job of the window builder: one series.
+struct SeriesJob {
+    const float *T;
+    int64_t len;
+    int64_t ell;
+    int64_t npad;       // padded rows (windows) of xs
+    int64_t blk_base;   // first 256-row builder block of this job (prefix sum)
+    void *xs;
+    void *shat;
+    float4 *bmax;
+    double *mu;
+    double *sigma;
+    unsigned int *flags;
+    int32_t kpad;
+    int32_t pad0;
+};
+
+// ---- launchers (defined in the .hip files) --------------------------------
+
+// Fill n words with v (a kernel, so it is safe inside captured graphs).
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
+void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
+void launch_reset_res(ResDev *r, int64_t n, hipStream_t st);
+
+// Row preparation of points (float32 or int8): screen operand, row scalars,
+// per-block maxima (bmax must be zero on entry), flags.
+void launch_prep_points(const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, int prec, void *xs,
+                        int32_t kpad, int64_t npad, void *shat, float4 *bmax, int tile, unsigned int *flags,
+                        hipStream_t st);
+
+// Window builder of many series: canonical mean/sigma, z-normalised screen
+// operand, row scalars, block maxima (zero on entry), flags.
+void launch_prep_series(const SeriesJob *jobs, int64_t njobs, int64_t total_blocks, int prec, int tile,
+                        hipStream_t st);
+
+// Gram screen (grid = work-groups; phase 2 loops over *sel_count entries).
+void launch_screen(int prec, int tile, int mode, const ScreenArgs &a, int64_t grid, hipStream_t st);
+
+// Phase 1 -> phase 2: U[p] = min over tiles of (tile min + bound); then the
+// tiles whose lower bound (tile min - bound) does not exceed U[p].
+void launch_reduce_U(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min, int prec,
+                     unsigned long long *Ubits, hipStream_t st);
+void launch_select(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min, int prec,
+                   const unsigned long long *Ubits, uint64_t *sel, uint32_t *sel_count, hipStream_t st);
+
+// Candidate verification in canonical FP64 (exact int64 for int8).
+void launch_verify_cpp(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec, int tile,
+                       double *cand_d2, ResDev *res, hipStream_t st);
+void launch_pick_cpp(const Cand *cand, const uint32_t *cnt, uint32_t cap, const double *cand_d2, ResDev *res,
+                     hipStream_t st);
+void launch_verify_frnn(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec, int tile,
+                        uint64_t *keys, double *vals, uint32_t *out_cnt, uint32_t out_cap, ResDev *res,
+                        hipStream_t st);
+// Sort m (key, value) pairs by key; arrays hold mpad >= m entries (mpad a power
+// of two), the tail is overwritten with sentinels.
+void launch_sort_pairs(uint64_t *keys, double *vals, int64_t m, int64_t mpad, hipStream_t st);
+// Unpack sorted keys (i << 32 | j) into int64 pairs [m][2] and copy values.
+void launch_emit_pairs(const uint64_t *keys, const double *vals, int64_t m, int64_t *pairs, double *d2,
+                       hipStream_t st);
+
+// Debug: one 32x32 MFMA block through the screen's fragment path.
+void launch_mfma_probe(int prec, const void *A, const void *B, float *C, hipStream_t st);
+
+}  // namespace cpmi

@@ -1,0 +1,285 @@
+// Builders of the screen operands.
+//
+// Points (row preparation): each float32 row x is copied into the screen
+// operand x~ (FP32 as is, BF16 rounded to nearest even) or kept as int8, and
+// the row scalars used by the epilogue and by the error bound are formed:
+// s^ = fp32(||x||^2) and upper bounds of ||x||, ||x~||, ||x - x~||. Block
+// maxima of those four values are accumulated per `tile` rows.
+//
+// Series (l-mer builder): the l-mers T_i = a_i .. a_{i+l-1} (Section 2) are
+// z-normalised with the canonical two-pass FP64 arithmetic (ascending sums,
+// population variance, correctly rounded division and square root), so the
+// verifier can later rebuild the exact canonical window from (T, mu, sigma).
+// The normalised window is then rounded into the screen operand as above.
+//
+// Compiled with -ffp-contract=off: every a*b+c below is either an explicit fma
+// or two separately rounded operations, as the canonical definition requires.
+#include "bound.h"
+#include "cpmi_internal.h"
+
+namespace cpmi {
+
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float x)
+{
+    unsigned int u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Upper bound as float of a non-negative double (covers the double's own
+// rounding with a relative 2^-40 margin).
+__device__ __forceinline__ float up_f32(double x) { return f32_up(x * (1.0 + 0x1p-40)); }
+
+__device__ __forceinline__ void atomic_max_f32(float *p, float v)
+{
+    // non-negative floats order like their bit patterns
+    atomicMax((unsigned int *)p, __float_as_uint(v));
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t v, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void fill_u64_kernel(uint64_t *p, uint64_t v, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void reset_res_kernel(ResDev *r, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        ResDev z;
+        z.best_d2 = ~0ull;
+        z.best_ij = ~0ull;
+        z.err_bits = 0;
+        z.ratio_bits = 0;
+        z.bound_bits = 0;
+        z.flags = 0;
+        r[i] = z;
+    }
+}
+
+static unsigned grid_for(int64_t n, int per)
+{
+    int64_t g = (n + per - 1) / per;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (unsigned)g;
+}
+
+void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, v, n);
+}
+void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, v, n);
+}
+void launch_reset_res(ResDev *r, int64_t n, hipStream_t st)
+{
+    if (n > 0) hipLaunchKernelGGL(reset_res_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, r, n);
+}
+
+// ---------------------------------------------------------------------------
+// points: one wave per row
+// ---------------------------------------------------------------------------
+template <int PREC, bool INT8_IN>
+__global__ __launch_bounds__(256) void prep_points_kernel(const void *pts, int64_t n, int64_t d, int64_t ld,
+                                                          void *xs, int32_t kpad, int64_t npad, void *shat,
+                                                          float4 *bmax, int tile, unsigned int *flags)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= npad) return;
+    const bool real = row < n;
+    if constexpr (INT8_IN) {
+        const signed char *x = (const signed char *)pts + row * ld;
+        signed char *o = (signed char *)xs + row * (int64_t)kpad;
+        int s = 0;
+        for (int64_t k = lane; k < kpad; k += 64) {
+            const signed char v = (real && k < d) ? x[k] : (signed char)0;
+            o[k] = v;
+            s += (int)v * (int)v;
+        }
+#pragma unroll
+        for (int of = 32; of > 0; of >>= 1) s += __shfl_xor(s, of, 64);
+        if (lane == 0) ((int *)shat)[row] = s;
+        return;
+    } else {
+        const float *x = (const float *)pts + row * ld;
+        double s = 0.0, t2 = 0.0, r2 = 0.0;
+        bool bad = false;
+        for (int64_t k = lane; k < kpad; k += 64) {
+            const float v = (real && k < d) ? x[k] : 0.0f;
+            if (!isfinite(v)) bad = true;
+            float vt;
+            if constexpr (PREC == P_BF16) {
+                const unsigned short h = f32_to_bf16_rne(v);
+                ((unsigned short *)xs)[row * (int64_t)kpad + k] = h;
+                vt = bf16_to_f32(h);
+            } else {
+                ((float *)xs)[row * (int64_t)kpad + k] = v;
+                vt = v;
+            }
+            const double vd = (double)v, vtd = (double)vt;
+            s = fma(vd, vd, s);
+            t2 = fma(vtd, vtd, t2);
+            const double df = vd - vtd;  // exact: both are float values
+            r2 = fma(df, df, r2);
+        }
+        s = wave_sum(s);
+        t2 = wave_sum(t2);
+        r2 = wave_sum(r2);
+        const unsigned long long anybad = __ballot(bad);
+        if (lane == 0) {
+            ((float *)shat)[row] = (float)s;
+            const float4 st = make_float4((float)s, up_f32(sqrt(s)), up_f32(sqrt(t2)), up_f32(sqrt(r2)));
+            float *bm = (float *)(bmax + row / tile);
+            atomic_max_f32(bm + 0, f32_up(s));
+            atomic_max_f32(bm + 1, st.y);
+            atomic_max_f32(bm + 2, st.z);
+            atomic_max_f32(bm + 3, st.w);
+            unsigned int f = 0;
+            if (anybad) f |= F_NONFINITE;
+            if (!(s < 0x1p100)) f |= F_RANGE;
+            if (f) atomicOr(flags, f);
+        }
+    }
+}
+
+void launch_prep_points(const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, int prec, void *xs,
+                        int32_t kpad, int64_t npad, void *shat, float4 *bmax, int tile, unsigned int *flags,
+                        hipStream_t st)
+{
+    dim3 g((unsigned)((npad + 3) / 4)), b(256);
+    if (dtype == 1)
+        hipLaunchKernelGGL((prep_points_kernel<P_I8, true>), g, b, 0, st, pts, n, d, ld, xs, kpad, npad, shat, bmax,
+                           tile, flags);
+    else if (prec == P_BF16)
+        hipLaunchKernelGGL((prep_points_kernel<P_BF16, false>), g, b, 0, st, pts, n, d, ld, xs, kpad, npad, shat,
+                           bmax, tile, flags);
+    else
+        hipLaunchKernelGGL((prep_points_kernel<P_F32, false>), g, b, 0, st, pts, n, d, ld, xs, kpad, npad, shat,
+                           bmax, tile, flags);
+}
+
+// ---------------------------------------------------------------------------
+// series: a block of 256 threads builds 256 consecutive windows of one job.
+// Pass A (one thread per window): canonical mean and sigma, sequential in k.
+// Pass B (one wave per window, lanes across k): normalised values, screen
+// operand and row scalars.
+// ---------------------------------------------------------------------------
+template <int PREC>
+__global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs, int64_t njobs, int tile)
+{
+    __shared__ double sh_mu[256];
+    __shared__ double sh_sg[256];
+    // job of this block: last job with blk_base <= blockIdx.x
+    int64_t lo = 0, hi = njobs - 1;
+    const int64_t bid = blockIdx.x;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].blk_base <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    const SeriesJob J = jobs[lo];
+    const int64_t N = J.len - J.ell + 1;          // windows
+    const int64_t w0 = (bid - J.blk_base) * 256;  // first window of the block
+    const int tid = threadIdx.x;
+    const float *T = J.T;
+    const int64_t ell = J.ell;
+
+    {
+        const int64_t w = w0 + tid;
+        double mu = 0.0, sg = 0.0;
+        if (w < N) {
+            double s = 0.0;
+            bool bad = false;
+            for (int64_t k = 0; k < ell; ++k) {
+                const float v = T[w + k];
+                if (!isfinite(v)) bad = true;
+                s += (double)v;
+            }
+            mu = s / (double)ell;
+            double v2 = 0.0;
+            for (int64_t k = 0; k < ell; ++k) {
+                const double e = (double)T[w + k] - mu;
+                v2 = fma(e, e, v2);
+            }
+            v2 = v2 / (double)ell;
+            sg = sqrt(v2);
+            J.mu[w] = mu;
+            J.sigma[w] = sg;
+            unsigned int f = 0;
+            if (bad) f |= F_NONFINITE;
+            if (!(sg > 0.0)) f |= F_DEGENERATE;
+            if (f) atomicOr(J.flags, f);
+        }
+        sh_mu[tid] = mu;
+        sh_sg[tid] = sg;
+    }
+    __syncthreads();
+
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int q = wave; q < 256; q += 4) {
+        const int64_t w = w0 + q;
+        if (w >= J.npad) break;
+        const bool real = w < N && sh_sg[q] > 0.0;
+        const double mu = sh_mu[q], sg = sh_sg[q];
+        double s = 0.0, t2 = 0.0, r2 = 0.0;
+        for (int64_t k = lane; k < J.kpad; k += 64) {
+            double xh = 0.0;
+            if (real && k < ell) xh = ((double)T[w + k] - mu) / sg;
+            float vt;
+            if constexpr (PREC == P_BF16) {
+                const unsigned short h = f32_to_bf16_rne((float)xh);
+                ((unsigned short *)J.xs)[w * (int64_t)J.kpad + k] = h;
+                vt = bf16_to_f32(h);
+            } else {
+                vt = (float)xh;
+                ((float *)J.xs)[w * (int64_t)J.kpad + k] = vt;
+            }
+            const double vtd = (double)vt;
+            s = fma(xh, xh, s);
+            t2 = fma(vtd, vtd, t2);
+            const double df = xh - vtd;
+            r2 = fma(df, df, r2);
+        }
+        s = wave_sum(s);
+        t2 = wave_sum(t2);
+        r2 = wave_sum(r2);
+        if (lane == 0) {
+            ((float *)J.shat)[w] = (float)s;
+            float *bm = (float *)(J.bmax + w / tile);
+            atomic_max_f32(bm + 0, f32_up(s));
+            atomic_max_f32(bm + 1, up_f32(sqrt(s)));
+            atomic_max_f32(bm + 2, up_f32(sqrt(t2)));
+            atomic_max_f32(bm + 3, up_f32(sqrt(r2)));
+        }
+    }
+}
+
+void launch_prep_series(const SeriesJob *jobs, int64_t njobs, int64_t total_blocks, int prec, int tile,
+                        hipStream_t st)
+{
+    if (total_blocks <= 0) return;
+    if (prec == P_BF16)
+        hipLaunchKernelGGL(prep_series_kernel<P_BF16>, dim3((unsigned)total_blocks), dim3(256), 0, st, jobs, njobs,
+                           tile);
+    else
+        hipLaunchKernelGGL(prep_series_kernel<P_F32>, dim3((unsigned)total_blocks), dim3(256), 0, st, jobs, njobs,
+                           tile);
+}
+
+}  // namespace cpmi

@@ -1,0 +1,312 @@
+// From screen to exact answer.
+//
+// 1. reduce_U / select: U[p] = min over tiles of (tile minimum + bound) is a
+//    proven upper bound of the least canonical d^2; a tile can hold the
+//    minimum only if (tile minimum - bound) <= U[p], so only those tiles are
+//    screened a second time (this mirrors the paper's two-phase structure,
+//    Section 3.6: cheap elimination first, exact evaluation of the survivors).
+// 2. verify: every emitted candidate gets its canonical d^2 (ascending-k fma on
+//    double differences; for windows the canonical z-normalised values are
+//    rebuilt from T, mu and sigma; exact int64 for int8) -- the "compute
+//    d(p_i, p_j)" step of MPR and MPR-FRNNS.
+// 3. closest pair: least d^2, ties to the lexicographically smallest (i, j);
+//    radius: keep d^2 <= R^2 (MPR-FRNNS step 5), sort by (i, j).
+//
+// Compiled with -ffp-contract=off so the FP64 sequence matches the canonical
+// definition operation for operation.
+#include "bound.h"
+#include "cpmi_internal.h"
+
+namespace cpmi {
+
+__device__ __forceinline__ double tile_min_value(uint32_t bits, int prec)
+{
+    return prec == P_I8 ? (double)(int)bits : (double)__uint_as_float(bits);
+}
+
+__device__ __forceinline__ double tile_bound_of(const Prob &P, int64_t I, int64_t J, int prec)
+{
+    if (prec == P_I8) return 0.0;
+    return tile_bound(P.bmax[I], P.bmax[J], P.kpad, P.d, prec);
+}
+
+__global__ void reduce_U_kernel(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min,
+                                int prec, unsigned long long *Ubits)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t e = tiles[t];
+        if (e == TILE_NONE) continue;
+        const uint32_t p = tile_prob(e);
+        const Prob &P = probs[p];
+        const double m = tile_min_value(tile_min[t], prec);
+        if (!(m == m) || isinf(m)) continue;
+        const double E = tile_bound_of(P, tile_I(e), tile_J(e), prec);
+        double ub = m + E;
+        ub += add_margin(m, E);
+        if (!(ub > 0.0)) ub = 0.0;
+        atomicMin(&Ubits[p], (unsigned long long)__double_as_longlong(ub));
+    }
+}
+
+__global__ void select_kernel(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min,
+                              int prec, const unsigned long long *Ubits, uint64_t *sel, uint32_t *sel_count)
+{
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t e = tiles[t];
+        if (e == TILE_NONE) continue;
+        const uint32_t p = tile_prob(e);
+        const Prob &P = probs[p];
+        const double m = tile_min_value(tile_min[t], prec);
+        if (!(m == m) || isinf(m)) continue;
+        const double E = tile_bound_of(P, tile_I(e), tile_J(e), prec);
+        double lb = m - E;
+        lb -= add_margin(m, E);
+        const double U = __longlong_as_double((long long)Ubits[p]);
+        if (lb <= U) {
+            const uint32_t k = atomicAdd(sel_count, 1u);
+            sel[k] = e;
+        }
+    }
+}
+
+static unsigned grid_of(int64_t n)
+{
+    int64_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 8192) g = 8192;
+    return (unsigned)g;
+}
+
+void launch_reduce_U(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min, int prec,
+                     unsigned long long *Ubits, hipStream_t st)
+{
+    hipLaunchKernelGGL(reduce_U_kernel, dim3(grid_of(ntiles)), dim3(256), 0, st, probs, tiles, ntiles, tile_min, prec,
+                       Ubits);
+}
+
+void launch_select(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min, int prec,
+                   const unsigned long long *Ubits, uint64_t *sel, uint32_t *sel_count, hipStream_t st)
+{
+    hipLaunchKernelGGL(select_kernel, dim3(grid_of(ntiles)), dim3(256), 0, st, probs, tiles, ntiles, tile_min, prec,
+                       Ubits, sel, sel_count);
+}
+
+// ---------------------------------------------------------------------------
+// canonical squared distance
+// ---------------------------------------------------------------------------
+__device__ double canonical_d2(const Prob &P, int64_t i, int64_t j)
+{
+    const int64_t d = P.d;
+    if (P.motif) {
+        const float *T = (const float *)P.src;
+        const double mi = P.mu[i], si = P.sigma[i], mj = P.mu[j], sj = P.sigma[j];
+        double acc = 0.0;
+        for (int64_t k = 0; k < d; ++k) {
+            const double xi = ((double)T[i + k] - mi) / si;
+            const double xj = ((double)T[j + k] - mj) / sj;
+            const double t = xi - xj;
+            acc = fma(t, t, acc);
+        }
+        return acc;
+    }
+    if (P.src_i8) {
+        const signed char *x = (const signed char *)P.src + i * P.ld;
+        const signed char *y = (const signed char *)P.src + j * P.ld;
+        long long acc = 0;
+        for (int64_t k = 0; k < d; ++k) {
+            const long long t = (long long)x[k] - (long long)y[k];
+            acc += t * t;
+        }
+        return (double)acc;
+    }
+    const float *x = (const float *)P.src + i * P.ld;
+    const float *y = (const float *)P.src + j * P.ld;
+    double acc = 0.0;
+    for (int64_t k = 0; k < d; ++k) {
+        const double t = (double)x[k] - (double)y[k];
+        acc = fma(t, t, acc);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ void record_error(ResDev *r, double dt, double d2, double E)
+{
+    const double err = fabs(dt - d2);
+    atomicMax(&r->err_bits, __float_as_uint(f32_up(err)));
+    if (E > 0.0) {
+        atomicMax(&r->ratio_bits, __float_as_uint(f32_up(err / E)));
+        atomicMax(&r->bound_bits, __float_as_uint(f32_up(E)));
+    }
+}
+
+__global__ void verify_cpp_kernel(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec,
+                                  int tile, double *cand_d2, ResDev *res)
+{
+    const int64_t m = min((int64_t)*cnt, (int64_t)cap);
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < m; c += (int64_t)gridDim.x * blockDim.x) {
+        const Cand cd = cand[c];
+        const Prob &P = probs[cd.p];
+        const double d2 = canonical_d2(P, cd.i, cd.j);
+        cand_d2[c] = d2;
+        atomicMin(&res[cd.p].best_d2, (unsigned long long)__double_as_longlong(d2));
+        record_error(&res[cd.p], (double)cd.dt, d2, tile_bound_of(P, cd.i / tile, cd.j / tile, prec));
+    }
+}
+
+__global__ void pick_cpp_kernel(const Cand *cand, const uint32_t *cnt, uint32_t cap, const double *cand_d2,
+                                ResDev *res)
+{
+    const int64_t m = min((int64_t)*cnt, (int64_t)cap);
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < m; c += (int64_t)gridDim.x * blockDim.x) {
+        const Cand cd = cand[c];
+        if ((unsigned long long)__double_as_longlong(cand_d2[c]) == res[cd.p].best_d2)
+            atomicMin(&res[cd.p].best_ij, ((unsigned long long)(unsigned)cd.i << 32) | (unsigned)cd.j);
+    }
+}
+
+__global__ void verify_frnn_kernel(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec,
+                                   int tile, uint64_t *keys, double *vals, uint32_t *out_cnt, uint32_t out_cap,
+                                   ResDev *res)
+{
+    const int64_t m = min((int64_t)*cnt, (int64_t)cap);
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < m; c += (int64_t)gridDim.x * blockDim.x) {
+        const Cand cd = cand[c];
+        const Prob &P = probs[cd.p];
+        const double d2 = canonical_d2(P, cd.i, cd.j);
+        record_error(&res[cd.p], (double)cd.dt, d2, tile_bound_of(P, cd.i / tile, cd.j / tile, prec));
+        if (d2 <= P.r2) {
+            const uint32_t k = atomicAdd(out_cnt, 1u);
+            if (k < out_cap) {
+                keys[k] = ((uint64_t)(uint32_t)cd.i << 32) | (uint32_t)cd.j;
+                vals[k] = d2;
+            }
+        }
+    }
+}
+
+static unsigned verify_grid() { return 1024; }
+
+void launch_verify_cpp(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec, int tile,
+                       double *cand_d2, ResDev *res, hipStream_t st)
+{
+    hipLaunchKernelGGL(verify_cpp_kernel, dim3(verify_grid()), dim3(64), 0, st, probs, cand, cnt, cap, prec, tile,
+                       cand_d2, res);
+}
+
+void launch_pick_cpp(const Cand *cand, const uint32_t *cnt, uint32_t cap, const double *cand_d2, ResDev *res,
+                     hipStream_t st)
+{
+    hipLaunchKernelGGL(pick_cpp_kernel, dim3(256), dim3(256), 0, st, cand, cnt, cap, cand_d2, res);
+}
+
+void launch_verify_frnn(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec, int tile,
+                        uint64_t *keys, double *vals, uint32_t *out_cnt, uint32_t out_cap, ResDev *res,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL(verify_frnn_kernel, dim3(verify_grid()), dim3(64), 0, st, probs, cand, cnt, cap, prec, tile,
+                       keys, vals, out_cnt, out_cap, res);
+}
+
+// ---------------------------------------------------------------------------
+// bitonic sort of (key, value) pairs; mpad is a power of two. Stages with a
+// partner distance below LOCAL run inside one work-group's LDS.
+// ---------------------------------------------------------------------------
+constexpr int LOCAL = 2048;  // elements per LDS block (1024 threads x 2)
+
+__global__ void pad_sentinel_kernel(uint64_t *keys, double *vals, int64_t m, int64_t mpad)
+{
+    for (int64_t i = m + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < mpad;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        keys[i] = ~0ull;
+        vals[i] = 0.0;
+    }
+}
+
+__global__ void bitonic_global_kernel(uint64_t *keys, double *vals, int64_t mpad, int64_t k, int64_t j)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < mpad; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t l = i ^ j;
+        if (l > i) {
+            const bool up = (i & k) == 0;
+            const uint64_t a = keys[i], b = keys[l];
+            if ((a > b) == up) {
+                keys[i] = b;
+                keys[l] = a;
+                const double t = vals[i];
+                vals[i] = vals[l];
+                vals[l] = t;
+            }
+        }
+    }
+}
+
+// Runs, for a fixed k, all stages j = jstart, jstart/2, ..., 1 on one LDS block.
+__global__ __launch_bounds__(1024) void bitonic_local_kernel(uint64_t *keys, double *vals, int64_t k, int64_t jstart)
+{
+    __shared__ uint64_t sk[LOCAL];
+    __shared__ double sv[LOCAL];
+    const int64_t base = (int64_t)blockIdx.x * LOCAL;
+    for (int q = threadIdx.x; q < LOCAL; q += 1024) {
+        sk[q] = keys[base + q];
+        sv[q] = vals[base + q];
+    }
+    __syncthreads();
+    for (int64_t j = jstart; j > 0; j >>= 1) {
+        for (int q = threadIdx.x; q < LOCAL; q += 1024) {
+            const int l = q ^ (int)j;
+            if (l > q) {
+                const bool up = ((base + q) & k) == 0;
+                const uint64_t a = sk[q], b = sk[l];
+                if ((a > b) == up) {
+                    sk[q] = b;
+                    sk[l] = a;
+                    const double t = sv[q];
+                    sv[q] = sv[l];
+                    sv[l] = t;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int q = threadIdx.x; q < LOCAL; q += 1024) {
+        keys[base + q] = sk[q];
+        vals[base + q] = sv[q];
+    }
+}
+
+void launch_sort_pairs(uint64_t *keys, double *vals, int64_t m, int64_t mpad, hipStream_t st)
+{
+    if (m <= 1) return;
+    if (mpad > m) hipLaunchKernelGGL(pad_sentinel_kernel, dim3(grid_of(mpad - m)), dim3(256), 0, st, keys, vals, m, mpad);
+    for (int64_t k = 2; k <= mpad; k <<= 1) {
+        int64_t j = k >> 1;
+        for (; j >= LOCAL; j >>= 1)
+            hipLaunchKernelGGL(bitonic_global_kernel, dim3(grid_of(mpad)), dim3(256), 0, st, keys, vals, mpad, k, j);
+        if (mpad >= LOCAL) {
+            hipLaunchKernelGGL(bitonic_local_kernel, dim3((unsigned)(mpad / LOCAL)), dim3(1024), 0, st, keys, vals, k, j);
+        } else {
+            for (; j > 0; j >>= 1)
+                hipLaunchKernelGGL(bitonic_global_kernel, dim3(grid_of(mpad)), dim3(256), 0, st, keys, vals, mpad, k, j);
+        }
+    }
+}
+
+__global__ void emit_pairs_kernel(const uint64_t *keys, const double *vals, int64_t m, int64_t *pairs, double *d2)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = keys[i];
+        pairs[2 * i] = (int64_t)(k >> 32);
+        pairs[2 * i + 1] = (int64_t)(k & 0xffffffffu);
+        if (d2) d2[i] = vals[i];
+    }
+}
+
+void launch_emit_pairs(const uint64_t *keys, const double *vals, int64_t m, int64_t *pairs, double *d2,
+                       hipStream_t st)
+{
+    if (m > 0) hipLaunchKernelGGL(emit_pairs_kernel, dim3(grid_of(m)), dim3(256), 0, st, keys, vals, m, pairs, d2);
+}
+
+}  // namespace cpmi

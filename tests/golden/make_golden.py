@@ -1,0 +1,158 @@
+"""Write the expected results of the five workloads, computed by the CPU oracle.
+
+Every value stored under tests/golden/ by this script comes from ``oracle``
+(plain FP64 brute force) applied to the seeded inputs of ``workloads``; nothing
+here touches the GPU library. Floats are stored with ``float.hex`` so that the
+comparison in the tests is exact.
+
+Usage:  python tests/golden/make_golden.py [points|motif|snp|mixture|batch ...]
+        (no argument: all). Threads: ORACLE_THREADS (default: all cores).
+
+Run times on 8 cores (latency-bound scalar FP64): points < 1 s, motif ~4 min,
+snp ~20 min, mixture ~1 h (one nearest-neighbour pass), batch sample ~10 min.
+"""
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+import workloads as W  # noqa: E402
+
+
+def _hex(v):
+    return float(v).hex()
+
+
+def _write(name, obj):
+    path = os.path.join(HERE, name + ".json")
+    with open(path + ".tmp", "w") as f:
+        json.dump(obj, f, indent=1)
+        f.write("\n")
+    os.replace(path + ".tmp", path)
+    print("wrote", path, flush=True)
+
+
+def _frnn_obj(pairs, d2, as_int=False):
+    return {"count": int(len(pairs)),
+            "pairs": [[int(a), int(b)] for a, b in pairs],
+            "d2": [int(v) for v in d2] if as_int else [_hex(v) for v in d2]}
+
+
+def points():
+    c = W.cfg_points_small()
+    t = time.time()
+    i, j, d2 = oracle.closest_pair(c["X"])
+    pairs, dd = oracle.frnn(c["X"], c["R2"])
+    _write(c["name"], {
+        "workload": c["name"], "source": "oracle.closest_pair / oracle.frnn on workloads.cfg_points_small",
+        "plant": list(c["plant"]), "R2": _hex(c["R2"]),
+        "closest_pair": {"i": i, "j": j, "d2": _hex(d2)},
+        "frnn": _frnn_obj(pairs, dd), "oracle_seconds": time.time() - t})
+
+
+def motif():
+    c = W.cfg_motif()
+    t = time.time()
+    best, (pairs, dd) = oracle.motif(c["T"], c["ell"], c["excl"], c["R2"])
+    _write(c["name"], {
+        "workload": c["name"], "source": "oracle.motif on workloads.cfg_motif",
+        "ell": c["ell"], "excl": c["excl"], "plant": list(c["plant"]), "R2": _hex(c["R2"]),
+        "closest_pair": {"i": best[0], "j": best[1], "d2": _hex(best[2])},
+        "frnn": _frnn_obj(pairs, dd), "oracle_seconds": time.time() - t})
+
+
+def snp():
+    c = W.cfg_snp()
+    t = time.time()
+    i, j, d2 = oracle.closest_pair(c["X"])
+    pairs, dd = oracle.frnn(c["X"], c["R2"])
+    _write(c["name"], {
+        "workload": c["name"], "source": "oracle.closest_pair / oracle.frnn on workloads.cfg_snp (int8, exact)",
+        "plants": [list(p) for p in c["plants"]], "R2": c["R2"],
+        "closest_pair": {"i": i, "j": j, "d2": int(d2)},
+        "frnn": _frnn_obj(pairs, dd, as_int=True), "oracle_seconds": time.time() - t})
+
+
+def mixture():
+    """Radius = half the lower-median nearest-neighbour distance (over all n
+    points, planted rows included); closest pair and FRNN set from the same
+    nearest-neighbour pass: a pair (i,j) at squared distance v has nn[i] <= v
+    and nn[j] <= v, so only rows with nn <= the threshold need a row scan."""
+    c = W.cfg_mixture()
+    X = c["X"]
+    n = X.shape[0]
+    t = time.time()
+    nn = oracle.nearest_neighbour_d2(X)
+    med = float(np.sort(nn)[n // 2 - 1])
+    R = 0.5 * math.sqrt(med)
+    R2 = R * R
+    dmin = float(nn.min())
+    best = None
+    for i in np.flatnonzero(nn == dmin):
+        row = oracle.row_d2(X, int(i))
+        js = [j for j in np.flatnonzero(row == dmin) if j > i]
+        if js:
+            best = (int(i), int(js[0]), dmin)
+            break
+    pairs, dd = [], []
+    for i in np.flatnonzero(nn <= R2):
+        row = oracle.row_d2(X, int(i))
+        for j in np.flatnonzero(row <= R2):
+            if j > i:
+                pairs.append((int(i), int(j)))
+                dd.append(float(row[j]))
+    order = sorted(range(len(pairs)), key=lambda k: pairs[k])
+    pairs = [pairs[k] for k in order]
+    dd = [dd[k] for k in order]
+    _write(c["name"], {
+        "workload": c["name"],
+        "source": "oracle.nearest_neighbour_d2 + oracle.row_d2 on workloads.cfg_mixture",
+        "plant": list(c["plant"]), "R": _hex(R), "R2": _hex(R2),
+        "median_nn_d2": _hex(med), "nn_d2_min": _hex(dmin),
+        "nn_d2_quantiles": {q: _hex(np.quantile(nn, float(q))) for q in ("0.001", "0.01", "0.5", "0.99")},
+        "closest_pair": {"i": best[0], "j": best[1], "d2": _hex(best[2])},
+        "frnn": _frnn_obj(pairs, dd), "oracle_seconds": time.time() - t})
+
+
+BATCH_SAMPLE = 12
+
+
+def batch_sample_indices(count=512):
+    rng = np.random.default_rng(W.MASTER_SEED + 4)
+    return sorted(int(v) for v in rng.choice(count, BATCH_SAMPLE, replace=False))
+
+
+def batch():
+    c = W.cfg_batch()
+    t = time.time()
+    out = []
+    for s in batch_sample_indices(len(c["series"])):
+        T, ell = c["series"][s], c["ells"][s]
+        best, _ = oracle.motif(T, ell)
+        out.append({"series": s, "len": int(T.shape[0]), "ell": int(ell),
+                    "plant": list(c["plants"][s]),
+                    "closest_pair": {"i": best[0], "j": best[1], "d2": _hex(best[2])}})
+        print("batch series", s, "done", time.time() - t, flush=True)
+    _write(c["name"], {
+        "workload": c["name"], "source": "oracle.motif on a seeded sample of workloads.cfg_batch series",
+        "sample": out, "oracle_seconds": time.time() - t})
+
+
+JOBS = {"points": points, "motif": motif, "snp": snp, "mixture": mixture, "batch": batch}
+
+if __name__ == "__main__":
+    if os.environ.get("ORACLE_THREADS"):
+        oracle.set_threads(int(os.environ["ORACLE_THREADS"]))
+    names = sys.argv[1:] or list(JOBS)
+    for nm in names:
+        t0 = time.time()
+        JOBS[nm]()
+        print(nm, "took", round(time.time() - t0, 1), "s", flush=True)

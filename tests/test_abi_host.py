@@ -1,0 +1,173 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every declared
+symbol, rejects bad arguments without touching a GPU, builds a tile list that
+covers every admissible pair exactly once, and applies a screening-error bound
+that holds on emulated screens (and is tight enough to matter: a bound 1000x
+smaller is violated).
+"""
+import ctypes as C
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1407_5609_amd as cp
+    L = C.CDLL(cp.library_path())
+    L.cpmi_dbg_tile_list.restype = C.c_int64
+    L.cpmi_dbg_tile_list.argtypes = [C.c_int64, C.c_int64, C.c_int, C.c_void_p, C.c_int64]
+    L.cpmi_dbg_tile_bound.restype = C.c_double
+    L.cpmi_dbg_tile_bound.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_int]
+    return L
+
+
+def declared_functions():
+    names = []
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names += re.findall(r"\b(cpmi_\w+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 14
+    for nm in names:
+        assert hasattr(lib, nm), nm
+
+
+def test_null_context_is_rejected_without_a_gpu(lib):
+    lib.cpmi_last_error.restype = C.c_char_p
+    assert lib.cpmi_last_error(None) == b"null context"
+    assert lib.cpmi_points(None, None, 0, 10, 4, 4, 0, C.c_double(-1.0), None, None, None, None, 0, None) == -1
+    assert lib.cpmi_motif_batch(None, None, None, None, 0, 0, None, None) == -1
+    assert lib.cpmi_destroy(None) == 0
+    assert lib.cpmi_version() == 10000
+
+
+def _tiles(lib, n, excl, tile):
+    cnt = lib.cpmi_dbg_tile_list(n, excl, tile, None, 0)
+    out = np.zeros(max(cnt, 1), dtype=np.uint64)
+    assert lib.cpmi_dbg_tile_list(n, excl, tile, out.ctypes.data, cnt) == cnt
+    out = out[:cnt]
+    return out[out != np.uint64(0xFFFFFFFFFFFFFFFF)]
+
+
+@pytest.mark.parametrize("n,excl,tile", [(1, 1, 128), (2, 1, 128), (300, 1, 128), (1000, 1, 256), (2049, 1, 128),
+                                         (1500, 256, 128), (5000, 512, 256), (700, 650, 128), (700, 700, 128)])
+def test_tile_list_covers_each_admissible_pair_once(lib, n, excl, tile):
+    t = _tiles(lib, n, excl, tile)
+    I = ((t >> np.uint64(22)) & np.uint64(0x3FFFFF)).astype(np.int64)
+    J = (t & np.uint64(0x3FFFFF)).astype(np.int64)
+    assert np.all(I <= J)
+    assert len(set(zip(I.tolist(), J.tolist()))) == len(t)          # no duplicates
+    # count admissible pairs covered: for tile (I,J), pairs i in block I, j in block J, i<j, j-i>=excl, j<n
+    covered = 0
+    for a, b in zip(I.tolist(), J.tolist()):
+        i = np.arange(a * tile, min(a * tile + tile, n))
+        j = np.arange(b * tile, min(b * tile + tile, n))
+        diff = j[None, :] - i[:, None]
+        k = int(np.count_nonzero(diff >= excl))
+        assert k > 0                                                  # no empty tile is listed
+        covered += k
+    m = n - excl
+    assert covered == (m * (m + 1) // 2 if m > 0 else 0)
+    # the XCD interleave keeps a single problem's list in 8 strided chunks
+    assert lib.cpmi_dbg_tile_list(n, excl, tile, None, 0) % 8 == 0 or n < 2
+
+
+def test_tile_list_rejects_bad_arguments(lib):
+    assert lib.cpmi_dbg_tile_list(10, 0, 128, None, 0) == -1
+    assert lib.cpmi_dbg_tile_list(10, 1, 64, None, 0) == -1
+
+
+# --------------------------------------------------------------------------
+# screening-error bound on an emulated screen
+# --------------------------------------------------------------------------
+
+def _bf16(x32):
+    """Round float32 to bfloat16 (nearest even), returned as float32."""
+    u = x32.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32)
+
+
+def _row_stats(Xc, Xt):
+    """(s^, a, at, r) per row as the library defines them (upper bounds)."""
+    s = np.sum(Xc * Xc, axis=1)
+    at = np.sqrt(np.sum(Xt.astype(np.float64) ** 2, axis=1))
+    r = np.sqrt(np.sum((Xc - Xt.astype(np.float64)) ** 2, axis=1))
+    up = lambda v: np.nextafter((v * (1 + 2.0 ** -40)).astype(np.float32), np.float32(np.inf))
+    return s.astype(np.float32), up(np.sqrt(s)), up(at), up(r)
+
+
+def _emulated_screen(Xt, shat):
+    G = Xt @ Xt.T                                         # float32 accumulation (any order is covered)
+    v = (shat[None, :] - np.float32(2) * G).astype(np.float32)
+    return (shat[:, None] + v).astype(np.float32)
+
+
+def _canon(Xc):
+    n = Xc.shape[0]
+    D = np.empty((n, n))
+    for i in range(n):
+        D[i] = oracle.row_d2(Xc, i) if Xc.dtype != np.float64 else oracle.row_d2(Xc, i)
+    return D
+
+
+@pytest.mark.parametrize("kind", ["points_f32", "points_bf16", "mixture_bf16", "windows_f32", "windows_bf16"])
+def test_bound_holds_on_emulated_screens_and_has_teeth(lib, kind):
+    rng = np.random.default_rng(abs(hash(kind)) % 1000)
+    if kind.startswith("points"):
+        X = rng.normal(0, 1, (160, 96)).astype(np.float32)
+        X[5] = (X[9] + rng.normal(0, 1e-3, 96)).astype(np.float32)
+        Xc = X.astype(np.float64)
+        canon_src = X
+    elif kind.startswith("mixture"):
+        X, _ = W.mixture_points(rng, 160, 512)
+        Xc = X.astype(np.float64)
+        canon_src = X
+    else:
+        T = W.random_walk(rng, 600)
+        W.plant_motif(rng, T, 128)
+        Xc, _, _ = oracle.znorm(T, 128)
+        Xc = Xc[:160]
+        canon_src = Xc
+    prec = 1 if kind.endswith("f32") else 2
+    X32 = Xc.astype(np.float32)
+    Xt = X32 if prec == 1 else _bf16(X32)
+    shat, a, at, r = _row_stats(Xc, Xt)
+    D = _emulated_screen(Xt, shat)
+    d = Xc.shape[1]
+    kpad = -(-d // (32 if prec == 1 else 64)) * (32 if prec == 1 else 64)
+    n = Xc.shape[0]
+    canon = np.stack([oracle.row_d2(np.ascontiguousarray(canon_src), i) for i in range(n)])
+    iu = np.triu_indices(n, 1)
+    err = np.abs(D.astype(np.float64) - canon)[iu]
+    # per-pair bound: each pair as its own 1-row "tile"
+    E = np.empty(len(iu[0]))
+    for k, (i, j) in enumerate(zip(*iu)):
+        bI = np.array([shat[i], a[i], at[i], r[i]], np.float32)
+        bJ = np.array([shat[j], a[j], at[j], r[j]], np.float32)
+        E[k] = lib.cpmi_dbg_tile_bound(bI.ctypes.data, bJ.ctypes.data, kpad, d, prec)
+    assert np.all(err <= E), float(np.max(err / E))
+    # tile form (block maxima) is at least as large
+    bI = np.array([shat.max(), a.max(), at.max(), r.max()], np.float32)
+    Et = lib.cpmi_dbg_tile_bound(bI.ctypes.data, bI.ctypes.data, kpad, d, prec)
+    assert Et >= E.max()
+    # teeth: the emulated error reaches more than a thousandth of the bound
+    assert np.max(err / E) > 1e-3
+
+
+def test_int8_bound_is_zero(lib):
+    b = np.ones(4, np.float32)
+    assert lib.cpmi_dbg_tile_bound(b.ctypes.data, b.ctypes.data, 4096, 4096, 3) == 0.0

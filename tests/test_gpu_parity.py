@@ -1,0 +1,304 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Closest-pair indices and radius pair sets must match exactly; because both
+sides follow the same canonical FP64 arithmetic, squared distances must match
+bit for bit (the required tolerance is 1e-9 relative; equality is checked).
+Cases span several tiles with ragged tails, every screening precision, the
+exclusion boundary, exact ties, and the degenerate inputs.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch  # noqa: F401  (imported at collection: the first import on a fresh box is slow)
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests need an MI355X")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    import paper_1407_5609_amd as cp
+    c = cp.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _check_pair(best, want):
+    assert (best.i, best.j) == tuple(want[:2]), (best, want)
+    assert best.d2 == want[2], (best.d2.hex(), float(want[2]).hex())
+    assert abs(best.d2 - want[2]) <= 1e-9 * max(abs(want[2]), 1e-300)
+
+
+def _check_frnn(got, want):
+    gp, gd = got
+    wp, wd = want
+    gp = gp.cpu().numpy()
+    gd = gd.cpu().numpy()
+    assert gp.shape == wp.shape, (gp.shape, wp.shape)
+    assert np.array_equal(gp, wp)
+    assert np.array_equal(gd, wd.astype(np.float64))
+
+
+# ---------------------------------------------------------------------------
+# device behaviour the screen relies on
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f32", "bf16", "i8"])
+def test_mfma_lane_layout(torch_dev, prec):
+    import torch
+
+    import paper_1407_5609_amd as cp
+    rng = np.random.default_rng(1)
+    if prec == "f32":
+        A = rng.normal(size=(32, 8)).astype(np.float32)
+        B = rng.normal(size=(32, 8)).astype(np.float32)
+        want = A.astype(np.float64) @ B.astype(np.float64).T
+        tol = 1e-5
+    elif prec == "bf16":
+        A = rng.integers(-8, 8, (32, 16)).astype(np.float32)   # exact in bf16
+        B = rng.integers(-8, 8, (32, 16)).astype(np.float32)
+        want = A.astype(np.float64) @ B.astype(np.float64).T
+        A = (A.view(np.uint32) >> 16).astype(np.uint16)
+        B = (B.view(np.uint32) >> 16).astype(np.uint16)
+        tol = 0
+    else:
+        A = rng.integers(-128, 128, (32, 32)).astype(np.int8)
+        B = rng.integers(-128, 128, (32, 32)).astype(np.int8)
+        want = A.astype(np.int64) @ B.astype(np.int64).T
+        tol = 0
+    C = torch.zeros((32, 32), dtype=torch.float32, device=torch_dev)
+    cp.dbg_mfma_probe(prec, _dev(A, torch_dev), _dev(B, torch_dev), C)
+    got = C.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - want)) <= tol * np.max(np.abs(want)), np.argwhere(np.abs(got - want) > 1e-3)[:5]
+
+
+@pytest.mark.parametrize("ell", [16, 100, 256, 512])
+def test_window_stats_are_canonical_bitwise(ctx, torch_dev, ell):
+    rng = np.random.default_rng(ell)
+    T = W.random_walk(rng, 5000)
+    mu, sg = ctx.dbg_znorm(_dev(T, torch_dev), ell)
+    _, omu, osg = oracle.znorm(T, ell)
+    assert np.array_equal(mu.cpu().numpy(), omu)
+    assert np.array_equal(sg.cpu().numpy(), osg)
+
+
+# ---------------------------------------------------------------------------
+# points
+# ---------------------------------------------------------------------------
+
+SHAPES = [(2, 1), (3, 5), (129, 7), (300, 64), (1000, 33), (1500, 200), (700, 512), (2300, 96)]
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("n,d", SHAPES)
+def test_points_match_oracle(ctx, torch_dev, prec, n, d):
+    rng = np.random.default_rng(n * 1000 + d)
+    X = rng.normal(0, 1, (n, d)).astype(np.float32)
+    if n > 10:
+        a, b = rng.choice(n, 2, replace=False)
+        X[b] = (X[a] + rng.normal(0, 1e-3, d)).astype(np.float32)
+    R2 = float(d)
+    best, fr = ctx.points(_dev(X, torch_dev), R2=R2, precision=prec)
+    _check_pair(best, oracle.closest_pair(X))
+    _check_frnn(fr, oracle.frnn(X, R2))
+    assert ctx.stats().max_err_over_bound <= 1.0
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_points_strided_rows(ctx, torch_dev, prec):
+    rng = np.random.default_rng(9)
+    Xfull = rng.normal(0, 1, (600, 80)).astype(np.float32)
+    X = Xfull[:, :70]                      # ld = 80 > d = 70
+    import torch
+    t = _dev(Xfull, torch_dev)[:, :70]
+    assert t.stride(0) == 80
+    best, fr = ctx.points(t, R2=70.0, precision=prec)
+    Xc = np.ascontiguousarray(X)
+    _check_pair(best, oracle.closest_pair(Xc))
+    _check_frnn(fr, oracle.frnn(Xc, 70.0))
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_exact_ties_go_to_lexicographic_minimum(ctx, torch_dev, prec):
+    rng = np.random.default_rng(31)
+    X = rng.integers(-50, 50, (900, 12)).astype(np.float32)
+    # several exact duplicates: d2 = 0 ties, lexicographic minimum wins
+    for a, b in [(700, 800), (5, 600), (5, 400), (300, 301)]:
+        X[b] = X[a]
+    best = ctx.closest_pair(_dev(X, torch_dev), precision=prec)
+    assert (best.i, best.j, best.d2) == oracle.closest_pair(X) == (5, 400, 0.0)
+
+
+def test_points_full_size_golden(ctx, torch_dev):
+    g = json.load(open(os.path.join(GOLDEN, "points_n4096_d64.json")))
+    c = W.cfg_points_small()
+    want_pair = (g["closest_pair"]["i"], g["closest_pair"]["j"], float.fromhex(g["closest_pair"]["d2"]))
+    want_fr = (np.array(g["frnn"]["pairs"], dtype=np.int64).reshape(-1, 2),
+               np.array([float.fromhex(v) for v in g["frnn"]["d2"]]))
+    t = _dev(c["X"], torch_dev)
+    for prec in ("f32", "bf16"):
+        best, fr = ctx.points(t, R2=c["R2"], precision=prec)
+        _check_pair(best, want_pair)
+        _check_frnn(fr, want_fr)
+        st = ctx.stats()
+        assert st.valid_pairs == W.valid_pairs_points(4096)
+        assert st.max_err_over_bound <= 1.0
+
+
+@pytest.mark.parametrize("n,d", [(2, 1), (257, 33), (1500, 4096), (1100, 300)])
+def test_int8_points_bit_exact(ctx, torch_dev, n, d):
+    rng = np.random.default_rng(n + d)
+    if d == 4096:
+        X = W.snp_matrix(rng, n, d)
+        W.plant_snp_pairs(rng, X)
+        R2 = 800
+    else:
+        X = rng.integers(-128, 128, (n, d)).astype(np.int8)
+        R2 = int(2 * d * 5461 * 0.9)      # ~ lower tail of 2 d Var(U[-128,127])
+    best, fr = ctx.points(_dev(X, torch_dev), R2=R2, precision="i8")
+    oi, oj, od = oracle.closest_pair(X)
+    assert (best.i, best.j, best.d2) == (oi, oj, float(od))
+    _check_frnn(fr, oracle.frnn(X, R2))
+
+
+# ---------------------------------------------------------------------------
+# motifs
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("length,ell,excl", [(700, 16, 0), (3000, 64, 0), (5000, 100, 50), (6000, 256, 0),
+                                              (4500, 512, 0), (2100, 128, 1)])
+def test_motif_matches_oracle(ctx, torch_dev, prec, length, ell, excl):
+    rng = np.random.default_rng(length + ell)
+    T = W.random_walk(rng, length)
+    W.plant_motif(rng, T, ell)
+    R2 = 0.05 * ell
+    best, fr = ctx.motif(_dev(T, torch_dev), ell, excl=excl, R2=R2, precision=prec)
+    ob, ofr = oracle.motif(T, ell, excl=excl if excl > 0 else ell, R2=R2)
+    _check_pair(best, ob)
+    _check_frnn(fr, ofr)
+    assert ctx.stats().max_err_over_bound <= 1.0
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_motif_exclusion_boundary_and_ties(ctx, torch_dev, prec):
+    P, ell = 37, 16
+    rng = np.random.default_rng(15)
+    T = np.tile(rng.normal(0, 1, P).astype(np.float32), 12)
+    t = _dev(T, torch_dev)
+    best, _ = ctx.motif(t, ell, excl=P, precision=prec)
+    assert (best.i, best.j, best.d2) == (0, P, 0.0)
+    best, _ = ctx.motif(t, ell, excl=P + 1, precision=prec)
+    assert (best.i, best.j, best.d2) == (0, 2 * P, 0.0)
+    _, fr = ctx.motif(t, ell, excl=P + 1, R2=0.0, precision=prec, want_pair=False)
+    _check_frnn(fr, oracle.motif(T, ell, excl=P + 1, R2=0.0)[1])
+
+
+def test_motif_full_size_golden(ctx, torch_dev):
+    g = json.load(open(os.path.join(GOLDEN, "motif_L65536_l256.json")))
+    c = W.cfg_motif()
+    want_pair = (g["closest_pair"]["i"], g["closest_pair"]["j"], float.fromhex(g["closest_pair"]["d2"]))
+    want_fr = (np.array(g["frnn"]["pairs"], dtype=np.int64).reshape(-1, 2),
+               np.array([float.fromhex(v) for v in g["frnn"]["d2"]]))
+    t = _dev(c["T"], torch_dev)
+    for prec in ("f32", "bf16"):
+        best, fr = ctx.motif(t, c["ell"], excl=c["excl"], R2=c["R2"], precision=prec)
+        _check_pair(best, want_pair)
+        _check_frnn(fr, want_fr)
+        st = ctx.stats()
+        assert st.valid_pairs == W.valid_pairs_motif(65536, 256, 256)
+        assert st.max_err_over_bound <= 1.0
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_motif_batch_matches_oracle(ctx, torch_dev, prec):
+    rng = np.random.default_rng(77)
+    series, ells, plants = W.batch_series(rng, 20, 600, 4000, ells=(16, 64, 128, 256))
+    ts = [_dev(T, torch_dev) for T in series]
+    for rep in range(2):                    # second call replays the captured graph
+        res = ctx.motif_batch(ts, ells, precision=prec)
+        for s, (T, ell) in enumerate(zip(series, ells)):
+            ob, _ = oracle.motif(T, ell)
+            if ob is None:
+                assert isinstance(res[s], Exception)
+                continue
+            _check_pair(res[s], ob)
+    assert ctx.stats().valid_pairs == sum(W.valid_pairs_motif(len(T), e, e) for T, e in zip(series, ells))
+
+
+# ---------------------------------------------------------------------------
+# error paths (forced from the host; every kernel still exits normally)
+# ---------------------------------------------------------------------------
+
+def test_error_codes(ctx, torch_dev):
+    import torch
+
+    import paper_1407_5609_amd as cp
+    X = np.random.default_rng(0).normal(size=(300, 8)).astype(np.float32)
+    Xn = X.copy()
+    Xn[123, 4] = np.nan
+    with pytest.raises(cp.CpmiError) as e:
+        ctx.closest_pair(_dev(Xn, torch_dev))
+    assert e.value.code == cp.ERR_NONFINITE
+    Xi = X.copy()
+    Xi[7, 0] = np.inf
+    with pytest.raises(cp.CpmiError) as e:
+        ctx.frnn(_dev(Xi, torch_dev), 1.0, precision="f32")
+    assert e.value.code == cp.ERR_NONFINITE
+    with pytest.raises(cp.CpmiError) as e:
+        ctx.closest_pair(_dev(X[:1], torch_dev))
+    assert e.value.code == cp.ERR_NOPAIR
+    with pytest.raises(cp.CpmiError) as e:
+        ctx.closest_pair(_dev(X.astype(np.int8), torch_dev), precision="bf16")
+    assert e.value.code == cp.ERR_ARG
+    T = W.random_walk(np.random.default_rng(3), 500)
+    T[100:200] = 5.0                        # constant windows: sigma = 0
+    with pytest.raises(cp.CpmiError) as e:
+        ctx.motif(_dev(T, torch_dev), 50)
+    assert e.value.code == cp.ERR_DEGENERATE
+    best, _ = ctx.motif(_dev(T[:90], torch_dev), 45)   # 46 windows, exclusion 45: exactly one pair
+    assert (best.i, best.j) == (0, 45)
+    T2 = W.random_walk(np.random.default_rng(4), 89)
+    with pytest.raises(cp.CpmiError) as e:
+        ctx.motif(_dev(T2, torch_dev), 45)       # 45 windows, exclusion 45 -> none
+    assert e.value.code == cp.ERR_NOPAIR
+    # capacity protocol: the first call reports the size needed
+    import ctypes as C
+    t = _dev(X, torch_dev)
+    pairs = torch.empty((1, 2), dtype=torch.int64, device=torch_dev)
+    d2 = torch.empty(1, dtype=torch.float64, device=torch_dev)
+    cnt = C.c_int64(0)
+    rc = cp._lib.cpmi_frnn(ctx._h, C.c_void_p(t.data_ptr()), cp.F32, 300, 8, 8, 16.0, cp.PREC_F32,
+                           cp._stream_ptr(None), C.c_void_p(pairs.data_ptr()), C.c_void_p(d2.data_ptr()), 1,
+                           C.byref(cnt))
+    want = len(oracle.frnn(X, 16.0)[0])
+    assert want > 1 and rc == cp.ERR_CAPACITY and cnt.value == want
+
+
+def test_repeat_calls_are_deterministic(ctx, torch_dev):
+    c = W.cfg_points_small()
+    t = _dev(c["X"], torch_dev)
+    outs = []
+    for _ in range(3):
+        best, (p, d) = ctx.points(t, R2=c["R2"], precision="bf16")
+        outs.append((best.i, best.j, best.d2, p.cpu().numpy().tobytes(), d.cpu().numpy().tobytes()))
+    assert outs[0] == outs[1] == outs[2]
