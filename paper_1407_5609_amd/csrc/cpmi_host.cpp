@@ -71,7 +71,9 @@ struct cpmi_ctx {
     int64_t ntiles = 0;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t es0 = nullptr, es1 = nullptr;  // around the first screen pass
     hipStream_t own = nullptr;
+    int ncu = 256;
 
     // captured batch graph
     hipGraphExec_t gexec = nullptr;
@@ -157,7 +159,7 @@ int pick_tile(cpmi_ctx *c, int prec, int64_t kpad)
     snprintf(key, sizeof key, "%s:k%d", prec_name(prec), kbucket(kpad));
     for (auto &kv : c->tuned)
         if (kv.first == key) return kv.second;
-    return 128;
+    return 256;
 }
 
 // Minimal reader of the tuner's JSON object {"bf16:k512": 256, ...}.
@@ -371,7 +373,10 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             a.candU = (Cand *)c->candU.p;
             a.cntU = dcnt + C_U;
             a.capU = c->capU;
-            launch_screen(prec, tile, want_frnn ? (M_MIN | M_EMIT_R) : M_MIN, a, ntiles, st);
+            const int64_t grid1 = tile == 256 ? std::min<int64_t>(ntiles, c->ncu) : ntiles;
+            if (!batch_graph) hipEventRecord(c->es0, st);
+            launch_screen(prec, tile, want_frnn ? (M_MIN | M_EMIT_R) : M_MIN, a, grid1, st);
+            if (!batch_graph) hipEventRecord(c->es1, st);
             if (want_cpp) {
                 launch_reduce_U(dprobs, a.tiles, ntiles, a.tile_min, prec, (unsigned long long *)c->ubits.p, st);
                 launch_select(dprobs, a.tiles, ntiles, a.tile_min, prec, (const unsigned long long *)c->ubits.p,
@@ -380,7 +385,8 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
                 b.tiles = (const uint64_t *)c->sel.p;
                 b.sel_count = dcnt + C_SEL;
                 b.U = (const double *)c->ubits.p;
-                launch_screen(prec, tile, M_EMIT_U, b, std::min<int64_t>(std::max<int64_t>(ntiles, 1), 2048), st);
+                launch_screen(prec, tile, M_EMIT_U, b,
+                              std::min<int64_t>(std::max<int64_t>(ntiles, 1), tile == 256 ? c->ncu : 2048), st);
                 launch_verify_cpp(dprobs, (const Cand *)c->candU.p, dcnt + C_U, c->capU, prec, tile,
                                   (double *)c->cand_d2.p, dres, st);
                 launch_pick_cpp((const Cand *)c->candU.p, dcnt + C_U, c->capU, (const double *)c->cand_d2.p, dres,
@@ -430,6 +436,9 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         float ms = 0.f;
         hipEventElapsedTime(&ms, c->ev0, c->ev1);
         c->stats.kernel_ms = ms;
+        ms = 0.f;
+        if (!batch_graph) hipEventElapsedTime(&ms, c->es0, c->es1);
+        c->stats.screen_ms = ms;
         ro.res.assign((ResDev *)c->pinned, (ResDev *)c->pinned + np);
         memcpy(ro.cnt, (char *)c->pinned + np * sizeof(ResDev), sizeof ro.cnt);
 
@@ -567,10 +576,15 @@ int cpmi_create(cpmi_ctx **out, int device, const char *tune_cache_path)
     cpmi_ctx *c = new cpmi_ctx();
     c->device = device;
     if (hipSetDevice(device) != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
-        hipEventCreate(&c->ev1) != hipSuccess || hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
+        hipEventCreate(&c->ev1) != hipSuccess || hipEventCreate(&c->es0) != hipSuccess ||
+        hipEventCreate(&c->es1) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return CPMI_ERR_HIP;
     }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+        c->ncu = ncu;
     load_tune_cache(c, tune_cache_path);
     *out = c;
     return CPMI_OK;
@@ -589,6 +603,8 @@ int cpmi_destroy(cpmi_ctx *c)
     if (c->pinned) hipHostFree(c->pinned);
     if (c->ev0) hipEventDestroy(c->ev0);
     if (c->ev1) hipEventDestroy(c->ev1);
+    if (c->es0) hipEventDestroy(c->es0);
+    if (c->es1) hipEventDestroy(c->es1);
     if (c->own) hipStreamDestroy(c->own);
     delete c;
     return CPMI_OK;

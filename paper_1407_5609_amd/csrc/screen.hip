@@ -260,13 +260,13 @@ static void launch_t(int mode, const ScreenArgs &a, int64_t grid, hipStream_t st
     }
 }
 
+void launch_screen256(int prec, int mode, const ScreenArgs &a, int64_t grid, hipStream_t st);
+
 void launch_screen(int prec, int tile, int mode, const ScreenArgs &a, int64_t grid, hipStream_t st)
 {
     if (grid <= 0) return;
     if (tile == 256) {
-        if (prec == P_F32) launch_t<P_F32, 256>(mode, a, grid, st);
-        else if (prec == P_BF16) launch_t<P_BF16, 256>(mode, a, grid, st);
-        else launch_t<P_I8, 256>(mode, a, grid, st);
+        launch_screen256(prec, mode, a, grid, st);
     } else {
         if (prec == P_F32) launch_t<P_F32, 128>(mode, a, grid, st);
         else if (prec == P_BF16) launch_t<P_BF16, 128>(mode, a, grid, st);

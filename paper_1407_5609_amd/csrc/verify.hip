@@ -30,23 +30,63 @@ __device__ __forceinline__ double tile_bound_of(const Prob &P, int64_t I, int64_
     return tile_bound(P.bmax[I], P.bmax[J], P.kpad, P.d, prec);
 }
 
+// Each wave takes 64 consecutive list entries per step; when they all belong
+// to one problem (always for a single problem, and inside each problem's run
+// of a batched list) the wave reduces in registers and one lane keeps a
+// running minimum, so the global atomic is hit once per wave and problem.
 __global__ void reduce_U_kernel(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min,
                                 int prec, unsigned long long *Ubits)
 {
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntiles;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t e = tiles[t];
-        if (e == TILE_NONE) continue;
-        const uint32_t p = tile_prob(e);
-        const Prob &P = probs[p];
-        const double m = tile_min_value(tile_min[t], prec);
-        if (!(m == m) || isinf(m)) continue;
-        const double E = tile_bound_of(P, tile_I(e), tile_J(e), prec);
-        double ub = m + E;
-        ub += add_margin(m, E);
-        if (!(ub > 0.0)) ub = 0.0;
-        atomicMin(&Ubits[p], (unsigned long long)__double_as_longlong(ub));
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    uint32_t cur_p = 0xffffffffu;
+    unsigned long long cur = ~0ull;  // running min of this wave (lane 0)
+    for (int64_t base = wid * 64; base < ntiles; base += nw * 64) {
+        const int64_t t = base + lane;
+        uint32_t p = 0xffffffffu;
+        unsigned long long ub_bits = ~0ull;
+        if (t < ntiles) {
+            const uint64_t e = tiles[t];
+            if (e != TILE_NONE) {
+                p = tile_prob(e);
+                const double m = tile_min_value(tile_min[t], prec);
+                if (m == m && !isinf(m)) {
+                    const Prob &P = probs[p];
+                    const double E = tile_bound_of(P, tile_I(e), tile_J(e), prec);
+                    double ub = m + E;
+                    ub += add_margin(m, E);
+                    if (!(ub > 0.0)) ub = 0.0;
+                    ub_bits = (unsigned long long)__double_as_longlong(ub);
+                }
+            }
+        }
+        // one problem in the whole wave (entries without one do not count)?
+        uint32_t p0 = p;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) p0 = min(p0, (uint32_t)__shfl_xor((int)p0, o, 64));
+        const bool uniform = __all(p == p0 || p == 0xffffffffu);
+        if (uniform) {
+            unsigned long long m = ub_bits;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const unsigned long long other = __shfl_xor(m, o, 64);
+                m = other < m ? other : m;
+            }
+            if (lane == 0 && p0 != 0xffffffffu) {
+                if (p0 != cur_p) {
+                    if (cur_p != 0xffffffffu && cur != ~0ull) atomicMin(&Ubits[cur_p], cur);
+                    cur_p = p0;
+                    cur = m;
+                } else if (m < cur) {
+                    cur = m;
+                }
+            }
+        } else if (p != 0xffffffffu && ub_bits != ~0ull) {
+            atomicMin(&Ubits[p], ub_bits);
+        }
     }
+    if (lane == 0 && cur_p != 0xffffffffu && cur != ~0ull) atomicMin(&Ubits[cur_p], cur);
 }
 
 __global__ void select_kernel(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min,
@@ -82,7 +122,9 @@ static unsigned grid_of(int64_t n)
 void launch_reduce_U(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min, int prec,
                      unsigned long long *Ubits, hipStream_t st)
 {
-    hipLaunchKernelGGL(reduce_U_kernel, dim3(grid_of(ntiles)), dim3(256), 0, st, probs, tiles, ntiles, tile_min, prec,
+    int64_t g = (ntiles + 256 * 16 - 1) / (256 * 16);   // ~16 steps per wave
+    g = g < 1 ? 1 : (g > 2048 ? 2048 : g);
+    hipLaunchKernelGGL(reduce_U_kernel, dim3((unsigned)g), dim3(256), 0, st, probs, tiles, ntiles, tile_min, prec,
                        Ubits);
 }
 

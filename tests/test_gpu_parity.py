@@ -108,9 +108,18 @@ def test_window_stats_are_canonical_bitwise(ctx, torch_dev, ell):
 SHAPES = [(2, 1), (3, 5), (129, 7), (300, 64), (1000, 33), (1500, 200), (700, 512), (2300, 96)]
 
 
+@pytest.fixture(params=[128, 256])
+def tile(request, ctx):
+    for p in ("f32", "bf16", "i8"):
+        ctx.set_tile(p, request.param)
+    yield request.param
+    for p in ("f32", "bf16", "i8"):
+        ctx.set_tile(p, 0)
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 @pytest.mark.parametrize("n,d", SHAPES)
-def test_points_match_oracle(ctx, torch_dev, prec, n, d):
+def test_points_match_oracle(ctx, torch_dev, tile, prec, n, d):
     rng = np.random.default_rng(n * 1000 + d)
     X = rng.normal(0, 1, (n, d)).astype(np.float32)
     if n > 10:
@@ -138,7 +147,7 @@ def test_points_strided_rows(ctx, torch_dev, prec):
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_exact_ties_go_to_lexicographic_minimum(ctx, torch_dev, prec):
+def test_exact_ties_go_to_lexicographic_minimum(ctx, torch_dev, tile, prec):
     rng = np.random.default_rng(31)
     X = rng.integers(-50, 50, (900, 12)).astype(np.float32)
     # several exact duplicates: d2 = 0 ties, lexicographic minimum wins
@@ -148,7 +157,7 @@ def test_exact_ties_go_to_lexicographic_minimum(ctx, torch_dev, prec):
     assert (best.i, best.j, best.d2) == oracle.closest_pair(X) == (5, 400, 0.0)
 
 
-def test_points_full_size_golden(ctx, torch_dev):
+def test_points_full_size_golden(ctx, torch_dev, tile):
     g = json.load(open(os.path.join(GOLDEN, "points_n4096_d64.json")))
     c = W.cfg_points_small()
     want_pair = (g["closest_pair"]["i"], g["closest_pair"]["j"], float.fromhex(g["closest_pair"]["d2"]))
@@ -165,7 +174,7 @@ def test_points_full_size_golden(ctx, torch_dev):
 
 
 @pytest.mark.parametrize("n,d", [(2, 1), (257, 33), (1500, 4096), (1100, 300)])
-def test_int8_points_bit_exact(ctx, torch_dev, n, d):
+def test_int8_points_bit_exact(ctx, torch_dev, tile, n, d):
     rng = np.random.default_rng(n + d)
     if d == 4096:
         X = W.snp_matrix(rng, n, d)
@@ -187,7 +196,7 @@ def test_int8_points_bit_exact(ctx, torch_dev, n, d):
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 @pytest.mark.parametrize("length,ell,excl", [(700, 16, 0), (3000, 64, 0), (5000, 100, 50), (6000, 256, 0),
                                               (4500, 512, 0), (2100, 128, 1)])
-def test_motif_matches_oracle(ctx, torch_dev, prec, length, ell, excl):
+def test_motif_matches_oracle(ctx, torch_dev, tile, prec, length, ell, excl):
     rng = np.random.default_rng(length + ell)
     T = W.random_walk(rng, length)
     W.plant_motif(rng, T, ell)
@@ -200,7 +209,7 @@ def test_motif_matches_oracle(ctx, torch_dev, prec, length, ell, excl):
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_motif_exclusion_boundary_and_ties(ctx, torch_dev, prec):
+def test_motif_exclusion_boundary_and_ties(ctx, torch_dev, tile, prec):
     P, ell = 37, 16
     rng = np.random.default_rng(15)
     T = np.tile(rng.normal(0, 1, P).astype(np.float32), 12)
@@ -213,7 +222,7 @@ def test_motif_exclusion_boundary_and_ties(ctx, torch_dev, prec):
     _check_frnn(fr, oracle.motif(T, ell, excl=P + 1, R2=0.0)[1])
 
 
-def test_motif_full_size_golden(ctx, torch_dev):
+def test_motif_full_size_golden(ctx, torch_dev, tile):
     g = json.load(open(os.path.join(GOLDEN, "motif_L65536_l256.json")))
     c = W.cfg_motif()
     want_pair = (g["closest_pair"]["i"], g["closest_pair"]["j"], float.fromhex(g["closest_pair"]["d2"]))
@@ -230,7 +239,7 @@ def test_motif_full_size_golden(ctx, torch_dev):
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_motif_batch_matches_oracle(ctx, torch_dev, prec):
+def test_motif_batch_matches_oracle(ctx, torch_dev, tile, prec):
     rng = np.random.default_rng(77)
     series, ells, plants = W.batch_series(rng, 20, 600, 4000, ells=(16, 64, 128, 256))
     ts = [_dev(T, torch_dev) for T in series]
