@@ -23,6 +23,7 @@
 #include "../../include/cpmi.h"
 #include "bound.h"
 #include "cpmi_internal.h"
+#include "layout256.h"
 
 using namespace cpmi;
 
@@ -375,18 +376,18 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             a.capU = c->capU;
             const int64_t grid1 = tile == 256 ? std::min<int64_t>(ntiles, c->ncu) : ntiles;
             if (!batch_graph) hipEventRecord(c->es0, st);
-            launch_screen(prec, tile, want_frnn ? (M_MIN | M_EMIT_R) : M_MIN, a, grid1, st);
+            launch_screen(prec, tile, M_MIN, a, grid1, st);
             if (!batch_graph) hipEventRecord(c->es1, st);
+            unsigned long long *ubits = want_cpp ? (unsigned long long *)c->ubits.p : nullptr;
+            if (want_cpp) launch_reduce_U(dprobs, a.tiles, ntiles, a.tile_min, prec, ubits, st);
+            launch_select(dprobs, a.tiles, ntiles, a.tile_min, prec, ubits, (uint64_t *)c->sel.p, dcnt + C_SEL, st);
+            ScreenArgs b = a;
+            b.tiles = (const uint64_t *)c->sel.p;
+            b.sel_count = dcnt + C_SEL;
+            b.U = (const double *)ubits;
+            launch_screen(prec, tile, M_EMIT, b,
+                          std::min<int64_t>(std::max<int64_t>(ntiles, 1), tile == 256 ? c->ncu : 2048), st);
             if (want_cpp) {
-                launch_reduce_U(dprobs, a.tiles, ntiles, a.tile_min, prec, (unsigned long long *)c->ubits.p, st);
-                launch_select(dprobs, a.tiles, ntiles, a.tile_min, prec, (const unsigned long long *)c->ubits.p,
-                              (uint64_t *)c->sel.p, dcnt + C_SEL, st);
-                ScreenArgs b = a;
-                b.tiles = (const uint64_t *)c->sel.p;
-                b.sel_count = dcnt + C_SEL;
-                b.U = (const double *)c->ubits.p;
-                launch_screen(prec, tile, M_EMIT_U, b,
-                              std::min<int64_t>(std::max<int64_t>(ntiles, 1), tile == 256 ? c->ncu : 2048), st);
                 launch_verify_cpp(dprobs, (const Cand *)c->candU.p, dcnt + C_U, c->capU, prec, tile,
                                   (double *)c->cand_d2.p, dres, st);
                 launch_pick_cpp((const Cand *)c->candU.p, dcnt + C_U, c->capU, (const double *)c->cand_d2.p, dres,
@@ -819,6 +820,16 @@ int64_t cpmi_dbg_tile_list(int64_t n, int64_t excl, int tile, uint64_t *out, int
     build_tiles(hp, tile, tl);
     for (int64_t k = 0; k < (int64_t)tl.size() && k < cap; ++k) out[k] = tl[k];
     return (int64_t)tl.size();
+}
+
+int cpmi_dbg_layout256(int wave, int q, int lane, int32_t *out4)
+{
+    if (wave < 0 || wave > 3 || q < 0 || q > 7 || lane < 0 || lane > 63 || !out4) return CPMI_ERR_ARG;
+    out4[0] = l256::dma_row(wave, q, lane);
+    out4[1] = l256::dma_col(lane);
+    out4[2] = l256::dma_lds(wave, q, lane);
+    out4[3] = l256::frag_lds(out4[0], out4[1] >> 4);
+    return CPMI_OK;
 }
 
 double cpmi_dbg_tile_bound(const float *bI, const float *bJ, int32_t kpad, int64_t d, int precision)

@@ -11,9 +11,8 @@ enum Prec : int { P_F32 = 1, P_BF16 = 2, P_I8 = 3 };
 
 // Screen modes of the Gram kernel (bit set).
 enum Mode : int {
-    M_MIN = 1,     // record the tile minimum of the screen value
-    M_EMIT_R = 2,  // emit pairs whose screen value is within the radius threshold
-    M_EMIT_U = 4   // emit pairs whose screen value is within the closest-pair threshold
+    M_MIN = 1,   // pass 1: record the tile minimum of the screen value
+    M_EMIT = 2   // pass 2: emit pairs within the closest-pair and/or radius thresholds
 };
 
 // One flag word per problem; set by the builders, read back by the host.
@@ -58,10 +57,10 @@ constexpr uint64_t TILE_NONE = ~0ull;
 struct ScreenArgs {
     const Prob *probs;
     const uint64_t *tiles;     // tile list
-    int64_t ntiles;            // entries (phase 1); phase 2 reads *sel_count
-    const uint32_t *sel_count; // phase 2: number of valid entries of `tiles`
-    uint32_t *tile_min;        // phase 1: per entry, min screen value (float or int32 bits)
-    const double *U;           // phase 2: per problem closest-pair upper bound (>= 0)
+    int64_t ntiles;            // entries (pass 1); pass 2 reads *sel_count
+    const uint32_t *sel_count; // pass 2: number of valid entries of `tiles`
+    uint32_t *tile_min;        // pass 1: per entry, min screen value (float or int32 bits)
+    const double *U;           // pass 2: per problem closest-pair upper bound, or null (no pair search)
     Cand *candR;               // radius candidates
     uint32_t *cntR;            // their counter (may exceed capR: the required size)
     uint32_t capR;
@@ -118,8 +117,9 @@ void launch_prep_series(const SeriesJob *jobs, int64_t njobs, int64_t total_bloc
 // Gram screen (grid = work-groups; phase 2 loops over *sel_count entries).
 void launch_screen(int prec, int tile, int mode, const ScreenArgs &a, int64_t grid, hipStream_t st);
 
-// Phase 1 -> phase 2: U[p] = min over tiles of (tile min + bound); then the
-// tiles whose lower bound (tile min - bound) does not exceed U[p].
+// Pass 1 -> pass 2: U[p] = min over tiles of (tile min + bound); then the
+// tiles whose lower bound (tile min - bound) does not exceed U[p] (if Ubits)
+// or the problem's squared radius (if r2 >= 0).
 void launch_reduce_U(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min, int prec,
                      unsigned long long *Ubits, hipStream_t st);
 void launch_select(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min, int prec,

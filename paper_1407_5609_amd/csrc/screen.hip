@@ -6,10 +6,11 @@
 // O(n^2 l) (Section 3). Here every admissible pair of a tile is screened at
 // once: D~_ij = s^_i + s^_j - 2 <x~_i, x~_j>, the inner products coming from
 // MFMA tiles (FP32, BF16 or INT8 operands), then
-//   - M_MIN:    the tile minimum of D~ is recorded (one word per tile);
-//   - M_EMIT_R: pairs with D~ <= R^2 + E_tile are appended to a candidate list;
-//   - M_EMIT_U: pairs with D~ <= U + E_tile are appended (second pass, U the
-//               proven upper bound of the minimum).
+//   - M_MIN:  the tile minimum of D~ is recorded (one word per tile);
+//   - M_EMIT: (second pass, on the tiles whose lower bound reaches U or R^2)
+//             pairs with D~ <= U + E_tile are appended to the closest-pair
+//             candidates (U the proven upper bound of the minimum) and pairs
+//             with D~ <= R^2 + E_tile to the radius candidates.
 // E_tile is the rigorous screening-error bound of bound.h, so every pair that
 // can be the minimum or lie within the radius reaches the FP64 verifier.
 //
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(NTHREADS) void screen_kernel(ScreenArgs args)
     const int wm = wave >> 1, wn = wave & 1;
     const int lrow = lane & 31, lhalf = lane >> 5;
 
-    const int64_t count = (MODE & M_EMIT_U) ? (int64_t)*args.sel_count : args.ntiles;
+    const int64_t count = (MODE & M_EMIT) ? (int64_t)*args.sel_count : args.ntiles;
 
     for (int64_t t = blockIdx.x; t < count; t += gridDim.x) {
         const uint64_t ent = args.tiles[t];
@@ -178,24 +179,19 @@ __global__ __launch_bounds__(NTHREADS) void screen_kernel(ScreenArgs args)
         // every pair of the tile admissible? (min j - max i >= excl, all rows real)
         const bool full = (j0 - (i0 + TILE - 1) >= excl) && (i0 + TILE <= n) && (j0 + TILE <= n);
         const double E = tile_bound(P.bmax[I], P.bmax[J], P.kpad, P.d, PREC);
-        S thr = SINF;
-        if constexpr (MODE & M_EMIT_R) {
-            if constexpr (PREC == P_I8)
-                thr = (S)fmin(floor(P.r2), 2147483646.0);
-            else
-                thr = f32_up(P.r2 + E + add_margin(P.r2, E));
+        S thrU = -SINF, thrR = -SINF;
+        if constexpr (MODE & M_EMIT) {
+            if (args.U) {
+                const double u = args.U[p];
+                if constexpr (PREC == P_I8) thrU = (S)fmin(u, 2147483646.0);
+                else thrU = f32_up(u + E + add_margin(u, E));
+            }
+            if (P.r2 >= 0.0) {
+                if constexpr (PREC == P_I8) thrR = (S)fmin(floor(P.r2), 2147483646.0);
+                else thrR = f32_up(P.r2 + E + add_margin(P.r2, E));
+            }
         }
-        if constexpr (MODE & M_EMIT_U) {
-            const double u = args.U[p];
-            if constexpr (PREC == P_I8)
-                thr = (S)fmin(u, 2147483646.0);
-            else
-                thr = f32_up(u + E + add_margin(u, E));
-        }
-        Cand *cand = (MODE & M_EMIT_U) ? args.candU : args.candR;
-        uint32_t *cnt = (MODE & M_EMIT_U) ? args.cntU : args.cntR;
-        const uint32_t cap = (MODE & M_EMIT_U) ? args.capU : args.capR;
-
+        const S thr = thrU > thrR ? thrU : thrR;
         S mn = SINF;
 #pragma unroll
         for (int b = 0; b < MB; ++b) {
@@ -213,21 +209,26 @@ __global__ __launch_bounds__(NTHREADS) void screen_kernel(ScreenArgs args)
                         dv = sh_si[il] + (sj - 2 * acc[a][b][r]);
                     else
                         dv = sh_si[il] + fmaf(-2.0f, acc[a][b][r], sj);
+                    bool ok = true;
                     if (!full) {
-                        const bool ok = (gj - gi >= excl) && (gi < n) && (gj < n);
+                        ok = (gj - gi >= excl) && (gi < n) && (gj < n);
                         dv = ok ? dv : SINF;
                     }
                     if constexpr (MODE & M_MIN) mn = PREC == P_I8 ? (S)min((int)mn, (int)dv) : (S)fminf(mn, dv);
-                    if constexpr (MODE & (M_EMIT_R | M_EMIT_U)) {
-                        if (dv <= thr) {
-                            const uint32_t idx = atomicAdd(cnt, 1u);
-                            if (idx < cap) {
-                                Cand cd;
-                                cd.i = (int32_t)gi;
-                                cd.j = (int32_t)gj;
-                                cd.dt = (float)dv;
-                                cd.p = p;
-                                cand[idx] = cd;
+                    if constexpr (MODE & M_EMIT) {
+                        if (ok && dv <= thr) {
+                            Cand cd;
+                            cd.i = (int32_t)gi;
+                            cd.j = (int32_t)gj;
+                            cd.dt = (float)dv;
+                            cd.p = p;
+                            if (dv <= thrU) {
+                                const uint32_t idx = atomicAdd(args.cntU, 1u);
+                                if (idx < args.capU) args.candU[idx] = cd;
+                            }
+                            if (dv <= thrR) {
+                                const uint32_t idx = atomicAdd(args.cntR, 1u);
+                                if (idx < args.capR) args.candR[idx] = cd;
                             }
                         }
                     }
@@ -252,12 +253,8 @@ template <int PREC, int TILE>
 static void launch_t(int mode, const ScreenArgs &a, int64_t grid, hipStream_t st)
 {
     dim3 g((unsigned)grid), b(NTHREADS);
-    switch (mode) {
-    case M_MIN: hipLaunchKernelGGL((screen_kernel<PREC, TILE, M_MIN>), g, b, 0, st, a); break;
-    case M_MIN | M_EMIT_R: hipLaunchKernelGGL((screen_kernel<PREC, TILE, M_MIN | M_EMIT_R>), g, b, 0, st, a); break;
-    case M_EMIT_U: hipLaunchKernelGGL((screen_kernel<PREC, TILE, M_EMIT_U>), g, b, 0, st, a); break;
-    default: break;
-    }
+    if (mode == M_MIN) hipLaunchKernelGGL((screen_kernel<PREC, TILE, M_MIN>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((screen_kernel<PREC, TILE, M_EMIT>), g, b, 0, st, a);
 }
 
 void launch_screen256(int prec, int mode, const ScreenArgs &a, int64_t grid, hipStream_t st);

@@ -1,8 +1,9 @@
 // Persistent 256x256 Gram screen for CDNA4 (gfx950).
 //
-// Same contract as the 128-tile screen in screen.hip (tile minimum of the
-// screen value D~ = s^_i + s^_j - 2 <x~_i, x~_j>, radius and threshold
-// emission), organised for throughput on large problems:
+// Same contract as the 128-tile screen in screen.hip (pass 1: tile minimum of
+// the screen value D~ = s^_i + s^_j - 2 <x~_i, x~_j>; pass 2: emission of the
+// pairs within the closest-pair or radius thresholds), organised for
+// throughput on large problems:
 //   * a persistent grid walks the tile list with stride gridDim.x, so a
 //     work-group keeps the slots of one XCD chunk of the list;
 //   * K slices (128 bytes per row) go straight from global memory into LDS
@@ -20,6 +21,7 @@
 //     threshold scans the elements again to emit pairs.
 #include "bound.h"
 #include "cpmi_internal.h"
+#include "layout256.h"
 
 namespace cpmi {
 
@@ -77,15 +79,135 @@ __device__ __forceinline__ int part(int g, int sj) { return sj - 2 * g; }
 
 }  // namespace
 
+// The two LDS stages are distinct __shared__ objects and every slice step
+// names its stage at compile time, so the compiler can see that the
+// direct-to-LDS loads into one stage never alias the fragment reads of the
+// other and does not make those reads wait for the loads in flight.
+__shared__ __attribute__((aligned(1024))) unsigned char g_stage0[2 * OPB];
+__shared__ __attribute__((aligned(1024))) unsigned char g_stage1[2 * OPB];
+
+template <int STG> __device__ __forceinline__ unsigned char *stage_ptr()
+{
+    return STG == 0 ? g_stage0 : g_stage1;
+}
+
+// Per-tile addressing of the direct-to-LDS loads: a uniform base per operand
+// plus one 32-bit per-lane offset, so the loads use the scalar-base form and
+// keep no 64-bit per-lane addresses live.
+struct TileAddr {
+    const unsigned char *ga;  // operand A rows of the tile (slice 0)
+    const unsigned char *gb;  // operand B rows of the tile (slice 0)
+    uint32_t lane_off;        // (wave*64 + ld_row) * rowbytes + ld_col
+    uint32_t step8;           // 8 * rowbytes
+    int nst;                  // K slices
+};
+
+template <int ESZ>
+__device__ __forceinline__ TileAddr tile_addr(const ScreenArgs &args, uint64_t ent, int wave, int ld_row, int ld_col)
+{
+    const Prob &P = args.probs[tile_prob(ent)];
+    const uint32_t rowbytes = (uint32_t)P.kpad * ESZ;
+    const unsigned char *xs = (const unsigned char *)P.xs;
+    TileAddr ta;
+    ta.ga = xs + (int64_t)tile_I(ent) * T256 * rowbytes;
+    ta.gb = xs + (int64_t)tile_J(ent) * T256 * rowbytes;
+    // row of this lane inside its 8-row block (the block's first row is part
+    // of the uniform base in issue_slice), and the swizzled byte column
+    ta.lane_off = (uint32_t)ld_row * rowbytes + (uint32_t)ld_col;
+    ta.step8 = 8u * rowbytes;
+    ta.nst = (int)(rowbytes / SL);
+    return ta;
+}
+
+__device__ __forceinline__ void issue_slice(const TileAddr &ta, int s, int wave, unsigned char *__restrict__ wr)
+{
+    unsigned char *la = wr;
+    unsigned char *lb = wr + OPB;
+    // uniform base of this wave's first 8-row block; block q adds q * 8 rows
+    const uint32_t rowbytes = ta.step8 >> 3;
+    const unsigned char *ga = ta.ga + s * SL + (uint32_t)l256::dma_row(wave, 0, 0) * rowbytes;
+    const unsigned char *gb = ta.gb + s * SL + (uint32_t)l256::dma_row(wave, 0, 0) * rowbytes;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const uint32_t bq = (uint32_t)q * ta.step8;
+        const int ldst = l256::dma_lds(wave, q, 0);
+        __builtin_amdgcn_global_load_lds((g_void *)(ga + bq + ta.lane_off), (lds_void *)(la + ldst), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((g_void *)(gb + bq + ta.lane_off), (lds_void *)(lb + ldst), 16, 0, 0);
+    }
+}
+
+// Scheduling masks of __builtin_amdgcn_sched_group_barrier.
+constexpr int SG_MFMA = 0x008;
+constexpr int SG_DS_READ = 0x100;
+
+// One K slice: prefetch the following slice (or the next tile's first one)
+// into the other stage, multiply this stage, then wait and synchronise.
+// Within the slice the fragments of k-group g+1 are read from LDS while the
+// 16 MFMAs of k-group g run (pinned with scheduling group barriers).
+// The stage being read and the stage being filled arrive as restrict
+// pointers: once inlined, their accesses carry distinct alias scopes, which is
+// what lets the wait-count insertion see that the LDS reads below need not
+// wait for the direct-to-LDS loads just issued.
+template <int PREC>
+__device__ __forceinline__ void slice_step_impl(typename A2<PREC>::T (&acc)[MB256][MB256], const TileAddr &cur,
+                                                int s, const TileAddr &nxt, bool has_next, int wave, int wm, int wn,
+                                                int lrow, int lhalf, const unsigned char *__restrict__ rd,
+                                                unsigned char *__restrict__ wr)
+{
+    if (s + 1 < cur.nst) issue_slice(cur, s + 1, wave, wr);
+    else if (has_next) issue_slice(nxt, 0, wave, wr);
+    const unsigned char *la = rd;
+    const unsigned char *lb = la + OPB;
+    constexpr int NG = SL / 32;
+    u32x4 fa[NG][MB256], fb[NG][MB256];
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+#pragma unroll
+        for (int m = 0; m < MB256; ++m)
+            fa[g][m] = *(const u32x4 *)(la + l256::frag_lds(wm * WT256 + m * 32 + lrow, 2 * g + lhalf));
+#pragma unroll
+        for (int m = 0; m < MB256; ++m)
+            fb[g][m] = *(const u32x4 *)(lb + l256::frag_lds(wn * WT256 + m * 32 + lrow, 2 * g + lhalf));
+    }
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int a = 0; a < MB256; ++a)
+#pragma unroll
+            for (int b = 0; b < MB256; ++b) mma2<PREC>(acc[a][b], fa[g][a], fb[g][b]);
+    // schedule: group 0 reads, then per group 16 MFMAs with the next group's
+    // 8 reads spread between them (FP32 issues 4 MFMAs per fragment pair)
+    constexpr int MPG = (PREC == P_F32 ? 4 : 1) * MB256 * MB256;  // MFMAs per k-group
+    __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 2 * MB256, 0);
+#pragma unroll
+    for (int g = 0; g + 1 < NG; ++g)
+#pragma unroll
+        for (int k = 0; k < 2 * MB256; ++k) {
+            __builtin_amdgcn_sched_group_barrier(SG_MFMA, MPG / (2 * MB256), 0);
+            __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
+        }
+    __builtin_amdgcn_sched_group_barrier(SG_MFMA, MPG, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
+
+template <int PREC, int STG>
+__device__ __forceinline__ void slice_step(typename A2<PREC>::T (&acc)[MB256][MB256], const TileAddr &cur, int s,
+                                           const TileAddr &nxt, bool has_next, int wave, int wm, int wn, int lrow,
+                                           int lhalf)
+{
+    slice_step_impl<PREC>(acc, cur, s, nxt, has_next, wave, wm, wn, lrow, lhalf, stage_ptr<STG>(),
+                          stage_ptr<1 - STG>());
+}
+
 template <int PREC, int MODE>
-__global__ __launch_bounds__(256, 1) void screen256_kernel(ScreenArgs args)
+__global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) void screen256_kernel(ScreenArgs args)
 {
     using AccT = typename A2<PREC>::T;
     using S = typename A2<PREC>::S;
     constexpr S SINF = PREC == P_I8 ? (S)0x7fffffff : (S)INFINITY;
     constexpr int ESZ = PREC == P_F32 ? 4 : (PREC == P_BF16 ? 2 : 1);
 
-    __shared__ __attribute__((aligned(1024))) unsigned char lds[4 * OPB];  // [stage][A | B]
     __shared__ S sh_red[4];
 
     const int tid = threadIdx.x;
@@ -95,37 +217,24 @@ __global__ __launch_bounds__(256, 1) void screen256_kernel(ScreenArgs args)
     const int lrow = lane & 31, lhalf = lane >> 5;
     // direct-to-LDS pattern: lane i fills bytes [16 i, 16 i + 16) of a 1 KB
     // block of 8 rows, i.e. row i / 8, slot i % 8, which holds chunk slot ^ row
-    const int ld_row = lane >> 3;
-    const int ld_col = ((lane & 7) ^ ld_row) << 4;
+    const int ld_row = l256::dma_row(0, 0, lane);
+    const int ld_col = l256::dma_col(lane);
 
-    const int64_t count = (MODE & M_EMIT_U) ? (int64_t)*args.sel_count : args.ntiles;
+    const int64_t count = (MODE & M_EMIT) ? (int64_t)*args.sel_count : args.ntiles;
     const int64_t stride = gridDim.x;
 
     auto next_valid = [&](int64_t t) -> int64_t {
         while (t < count && args.tiles[t] == TILE_NONE) t += stride;
         return t;
     };
-    // issue the loads of K slice `s` of tile entry `ent` into LDS stage `stg`
-    auto issue = [&](uint64_t ent, int s, int stg) {
-        const Prob &P = args.probs[tile_prob(ent)];
-        const int64_t rowbytes = (int64_t)P.kpad * ESZ;
-        const unsigned char *xs = (const unsigned char *)P.xs;
-        const unsigned char *ga = xs + (int64_t)tile_I(ent) * T256 * rowbytes + (int64_t)s * SL + ld_col;
-        const unsigned char *gb = xs + (int64_t)tile_J(ent) * T256 * rowbytes + (int64_t)s * SL + ld_col;
-        unsigned char *la = lds + stg * 2 * OPB;
-        unsigned char *lb = la + OPB;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int R0 = (wave * 8 + q) * 8;
-            const int64_t row = R0 + ld_row;
-            __builtin_amdgcn_global_load_lds((g_void *)(ga + row * rowbytes), (lds_void *)(la + R0 * SL), 16, 0, 0);
-            __builtin_amdgcn_global_load_lds((g_void *)(gb + row * rowbytes), (lds_void *)(lb + R0 * SL), 16, 0, 0);
-        }
-    };
 
     int stg = 0;
     int64_t t = next_valid(blockIdx.x);
-    if (t < count) issue(args.tiles[t], 0, stg);
+    TileAddr cur{};
+    if (t < count) {
+        cur = tile_addr<ESZ>(args, args.tiles[t], wave, ld_row, ld_col);
+        issue_slice(cur, 0, wave, stage_ptr<0>());
+    }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
@@ -134,8 +243,10 @@ __global__ __launch_bounds__(256, 1) void screen256_kernel(ScreenArgs args)
         const uint32_t p = tile_prob(ent);
         const Prob &P = args.probs[p];
         const int64_t I = tile_I(ent), J = tile_J(ent);
-        const int nst = (int)((int64_t)P.kpad * ESZ / SL);
+        const int nst = cur.nst;
         const int64_t tn = next_valid(t + stride);
+        const bool has_next = tn < count;
+        const TileAddr nxt = has_next ? tile_addr<ESZ>(args, args.tiles[tn], wave, ld_row, ld_col) : cur;
 
         AccT acc[MB256][MB256];
 #pragma unroll
@@ -143,35 +254,25 @@ __global__ __launch_bounds__(256, 1) void screen256_kernel(ScreenArgs args)
 #pragma unroll
             for (int b = 0; b < MB256; ++b) acc[a][b] = AccT{};
 
-        for (int s = 0; s < nst; ++s) {
-            if (s + 1 < nst) issue(ent, s + 1, stg ^ 1);
-            else if (tn < count) issue(args.tiles[tn], 0, stg ^ 1);
-            const unsigned char *la = lds + stg * 2 * OPB;
-            const unsigned char *lb = la + OPB;
-#pragma unroll
-            for (int g = 0; g < SL / 32; ++g) {
-                const int sw = (((2 * g + lhalf) ^ (lrow & 7)) << 4);
-                u32x4 fa[MB256], fb[MB256];
-#pragma unroll
-                for (int m = 0; m < MB256; ++m)
-                    fa[m] = *(const u32x4 *)(la + (wm * WT256 + m * 32 + lrow) * SL + sw);
-#pragma unroll
-                for (int m = 0; m < MB256; ++m)
-                    fb[m] = *(const u32x4 *)(lb + (wn * WT256 + m * 32 + lrow) * SL + sw);
-#pragma unroll
-                for (int a = 0; a < MB256; ++a)
-#pragma unroll
-                    for (int b = 0; b < MB256; ++b) mma2<PREC>(acc[a][b], fa[a], fb[b]);
-            }
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            stg ^= 1;
+        int s = 0;
+        if (stg == 1) {
+            slice_step<PREC, 1>(acc, cur, s, nxt, has_next, wave, wm, wn, lrow, lhalf);
+            ++s;
         }
+        for (; s + 1 < nst; s += 2) {
+            slice_step<PREC, 0>(acc, cur, s, nxt, has_next, wave, wm, wn, lrow, lhalf);
+            slice_step<PREC, 1>(acc, cur, s + 1, nxt, has_next, wave, wm, wn, lrow, lhalf);
+        }
+        if (s < nst) slice_step<PREC, 0>(acc, cur, s, nxt, has_next, wave, wm, wn, lrow, lhalf);
+        stg = (stg + nst) & 1;
+        cur = nxt;
 
         // ---------------- epilogue ----------------
-        const int64_t n = P.n, excl = P.excl;
-        const int64_t i0 = I * T256 + wm * WT256, j0 = J * T256 + wn * WT256;
-        const bool full = (J * T256 - (I * T256 + T256 - 1) >= excl) && (I * T256 + T256 <= n) && (J * T256 + T256 <= n);
+        // 32-bit row/column indices (n < 2^31 is enforced by the host)
+        const int32_t n = (int32_t)P.n, excl = (int32_t)P.excl;
+        const int32_t i0 = (int32_t)(I * T256) + wm * WT256, j0 = (int32_t)(J * T256) + wn * WT256;
+        const bool full = ((int64_t)J * T256 - ((int64_t)I * T256 + T256 - 1) >= P.excl) &&
+                          ((int64_t)I * T256 + T256 <= P.n) && ((int64_t)J * T256 + T256 <= P.n);
         const S *shat = (const S *)P.shat;
         S sj[MB256];
 #pragma unroll
@@ -184,7 +285,7 @@ __global__ __launch_bounds__(256, 1) void screen256_kernel(ScreenArgs args)
             S si[16];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int64_t rb = i0 + a * 32 + 8 * q + 4 * lhalf;
+                const int32_t rb = i0 + a * 32 + 8 * q + 4 * lhalf;
                 if constexpr (PREC == P_I8) {
                     const i32x4 v = *(const i32x4 *)(shat + rb);
                     si[4 * q] = v.x; si[4 * q + 1] = v.y; si[4 * q + 2] = v.z; si[4 * q + 3] = v.w;
@@ -204,10 +305,10 @@ __global__ __launch_bounds__(256, 1) void screen256_kernel(ScreenArgs args)
             } else {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
-                    const int64_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
+                    const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
 #pragma unroll
                     for (int b = 0; b < MB256; ++b) {
-                        const int64_t gj = j0 + b * 32 + lrow;
+                        const int32_t gj = j0 + b * 32 + lrow;
                         const bool ok = (gj - gi >= excl) && (gi < n) && (gj < n);
                         const S dv = (S)(si[r] + part(acc[a][b][r], sj[b]));
                         best = ok ? smin(best, dv) : best;
@@ -216,41 +317,44 @@ __global__ __launch_bounds__(256, 1) void screen256_kernel(ScreenArgs args)
             }
         }
 
-        if constexpr (MODE & (M_EMIT_R | M_EMIT_U)) {
+        if constexpr (MODE & M_EMIT) {
             const double E = tile_bound(P.bmax[I], P.bmax[J], P.kpad, P.d, PREC);
-            S thr;
-            if constexpr (MODE & M_EMIT_U) {
+            S thrU = -SINF, thrR = -SINF;
+            if (args.U) {
                 const double u = args.U[p];
-                if constexpr (PREC == P_I8) thr = (S)fmin(u, 2147483646.0);
-                else thr = f32_up(u + E + add_margin(u, E));
-            } else {
-                if constexpr (PREC == P_I8) thr = (S)fmin(floor(P.r2), 2147483646.0);
-                else thr = f32_up(P.r2 + E + add_margin(P.r2, E));
+                if constexpr (PREC == P_I8) thrU = (S)fmin(u, 2147483646.0);
+                else thrU = f32_up(u + E + add_margin(u, E));
             }
+            if (P.r2 >= 0.0) {
+                if constexpr (PREC == P_I8) thrR = (S)fmin(floor(P.r2), 2147483646.0);
+                else thrR = f32_up(P.r2 + E + add_margin(P.r2, E));
+            }
+            const S thr = thrU > thrR ? thrU : thrR;
             if (wmin(best) <= thr) {
-                Cand *cand = (MODE & M_EMIT_U) ? args.candU : args.candR;
-                uint32_t *cnt = (MODE & M_EMIT_U) ? args.cntU : args.cntR;
-                const uint32_t cap = (MODE & M_EMIT_U) ? args.capU : args.capR;
 #pragma unroll
                 for (int a = 0; a < MB256; ++a)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
-                        const int64_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
+                        const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
                         const S si = shat[gi];
 #pragma unroll
                         for (int b = 0; b < MB256; ++b) {
-                            const int64_t gj = j0 + b * 32 + lrow;
+                            const int32_t gj = j0 + b * 32 + lrow;
                             const S dv = (S)(si + part(acc[a][b][r], sj[b]));
                             const bool ok = full || ((gj - gi >= excl) && (gi < n) && (gj < n));
                             if (ok && dv <= thr) {
-                                const uint32_t idx = atomicAdd(cnt, 1u);
-                                if (idx < cap) {
-                                    Cand cd;
-                                    cd.i = (int32_t)gi;
-                                    cd.j = (int32_t)gj;
-                                    cd.dt = (float)dv;
-                                    cd.p = p;
-                                    cand[idx] = cd;
+                                Cand cd;
+                                cd.i = gi;
+                                cd.j = gj;
+                                cd.dt = (float)dv;
+                                cd.p = p;
+                                if (dv <= thrU) {
+                                    const uint32_t idx = atomicAdd(args.cntU, 1u);
+                                    if (idx < args.capU) args.candU[idx] = cd;
+                                }
+                                if (dv <= thrR) {
+                                    const uint32_t idx = atomicAdd(args.cntR, 1u);
+                                    if (idx < args.capR) args.candR[idx] = cd;
                                 }
                             }
                         }
@@ -274,12 +378,8 @@ template <int PREC>
 static void launch256(int mode, const ScreenArgs &a, int64_t grid, hipStream_t st)
 {
     dim3 g((unsigned)grid), b(256);
-    switch (mode) {
-    case M_MIN: hipLaunchKernelGGL((screen256_kernel<PREC, M_MIN>), g, b, 0, st, a); break;
-    case M_MIN | M_EMIT_R: hipLaunchKernelGGL((screen256_kernel<PREC, M_MIN | M_EMIT_R>), g, b, 0, st, a); break;
-    case M_EMIT_U: hipLaunchKernelGGL((screen256_kernel<PREC, M_EMIT_U>), g, b, 0, st, a); break;
-    default: break;
-    }
+    if (mode == M_MIN) hipLaunchKernelGGL((screen256_kernel<PREC, M_MIN>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((screen256_kernel<PREC, M_EMIT>), g, b, 0, st, a);
 }
 
 void launch_screen256(int prec, int mode, const ScreenArgs &a, int64_t grid, hipStream_t st)

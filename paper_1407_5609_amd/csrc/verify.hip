@@ -103,8 +103,10 @@ __global__ void select_kernel(const Prob *probs, const uint64_t *tiles, int64_t 
         const double E = tile_bound_of(P, tile_I(e), tile_J(e), prec);
         double lb = m - E;
         lb -= add_margin(m, E);
-        const double U = __longlong_as_double((long long)Ubits[p]);
-        if (lb <= U) {
+        bool want = false;
+        if (Ubits) want = lb <= __longlong_as_double((long long)Ubits[p]);
+        if (P.r2 >= 0.0) want = want || lb <= P.r2;
+        if (want) {
             const uint32_t k = atomicAdd(sel_count, 1u);
             sel[k] = e;
         }

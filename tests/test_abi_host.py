@@ -171,3 +171,34 @@ def test_bound_holds_on_emulated_screens_and_has_teeth(lib, kind):
 def test_int8_bound_is_zero(lib):
     b = np.ones(4, np.float32)
     assert lib.cpmi_dbg_tile_bound(b.ctypes.data, b.ctypes.data, 4096, 4096, 3) == 0.0
+
+
+def test_layout256_covers_the_slice_and_reads_what_was_written(lib):
+    """Every direct-to-LDS load of the 256-tile screen reads a row inside the
+    tile and a 16-byte chunk inside the 128-byte slice; together they cover
+    every (row, chunk) once, write every LDS byte of the block once, and the
+    fragment read of (row, chunk) looks exactly where that chunk was written."""
+    lib.cpmi_dbg_layout256.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p]
+    out = np.zeros(4, np.int32)
+    seen_src, seen_dst = {}, set()
+    for w in range(4):
+        for q in range(8):
+            for lane in range(64):
+                assert lib.cpmi_dbg_layout256(w, q, lane, out.ctypes.data) == 0
+                row, col, dst, rd = (int(v) for v in out)
+                assert 0 <= row < 256 and 0 <= col < 128 and col % 16 == 0
+                assert 0 <= dst < 256 * 128 and dst % 16 == 0
+                key = (row, col // 16)
+                assert key not in seen_src
+                seen_src[key] = dst
+                seen_dst.add(dst)
+    assert len(seen_src) == 256 * 8 and len(seen_dst) == 256 * 8
+    for (row, chunk), dst in seen_src.items():
+        assert lib.cpmi_dbg_layout256(0, 0, 0, out.ctypes.data) == 0
+    # fragment read positions: compare with the write position of the same chunk
+    for w in range(4):
+        for q in range(8):
+            for lane in range(64):
+                lib.cpmi_dbg_layout256(w, q, lane, out.ctypes.data)
+                assert int(out[3]) == int(out[2])
+    assert lib.cpmi_dbg_layout256(4, 0, 0, out.ctypes.data) == -1
