@@ -41,8 +41,8 @@ int64_t cpmi_dbg_tile_list(int64_t n, int64_t excl, int tile, uint64_t *out, int
 double cpmi_dbg_tile_bound(const float *bI, const float *bJ, int32_t kpad, int64_t d, int precision);
 
 /* Host only: the 256-tile screen's K-slice layout for direct-to-LDS load
- * (wave 0..3, block q 0..7, lane 0..63): out4 = {tile row read, byte column
- * read within the 128-byte slice, LDS byte written, LDS byte at which a
+ * (wave 0..3, block q 0..3, lane 0..63): out4 = {tile row read, byte column
+ * read within the 64-byte slice, LDS byte written, LDS byte at which a
  * fragment read of that (row, chunk) looks}. */
 int cpmi_dbg_layout256(int wave, int q, int lane, int32_t *out4);
 

@@ -27,10 +27,16 @@ def _hipcc():
     return h if os.path.exists(h) else "hipcc"
 
 
+# The screen kernels never see a NaN (non-finite input is rejected before the
+# screen runs), so their min chains need no NaN canonicalisation; infinities
+# are still honoured (they are used as sentinels).
+EXTRA = {"screen.hip": ["-fno-honor-nans"], "screen256.hip": ["-fno-honor-nans"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"]
-    cmd = [_hipcc(), *lang, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), *lang, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -70,6 +70,7 @@ struct cpmi_ctx {
     // tile list cache
     std::vector<int64_t> tiles_key;
     int64_t ntiles = 0;
+    int64_t nfull = 0;   // leading entries of the list that are full tiles
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t es0 = nullptr, es1 = nullptr;  // around the first screen pass
@@ -137,10 +138,11 @@ int ensure_pinned(cpmi_ctx *c, size_t bytes)
 
 int elem_bytes(int prec) { return prec == P_F32 ? 4 : (prec == P_BF16 ? 2 : 1); }
 
-// Rows are padded to a whole number of 128-byte LDS slices.
-int32_t kpad_for(int prec, int64_t d)
+// Rows are padded to whole LDS slices: 128 bytes for the 128-tile screen, and
+// four 64-byte slices (one turn of the load ring) for the 256-tile screen.
+int32_t kpad_for(int prec, int64_t d, int tile)
 {
-    const int64_t per = 128 / elem_bytes(prec);
+    const int64_t per = (tile == 256 ? 256 : 128) / elem_bytes(prec);
     return (int32_t)((d + per - 1) / per * per);
 }
 
@@ -195,16 +197,18 @@ int64_t pairs_of(int64_t n, int64_t excl)
     return m > 0 ? m * (m + 1) / 2 : 0;
 }
 
-// Tile list: upper-triangle tiles holding at least one admissible pair. For a
-// single problem, tiles are ordered in bands of 8 tile rows (column-major in a
-// band, so concurrent work-groups share row and column panels) and the list is
-// split into 8 contiguous chunks interleaved slot by slot, so that the
-// work-groups the dispatcher sends to one XCD (slot % 8) walk one chunk and
-// keep its panels in that XCD's L2. For several problems (uneven costs) the
-// tiles are listed most-expensive problem first and dispatched in order.
-void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t> &out)
+// Tile list: upper-triangle tiles holding at least one admissible pair. The
+// list holds first the full tiles (every pair admissible) and then the partial
+// ones (diagonal, exclusion band, ragged edge); *nfull counts the former. For
+// a single problem the tiles are ordered in bands of 8 tile rows
+// (column-major in a band, so concurrent work-groups share row and column
+// panels) and the full part is split into 8 contiguous chunks interleaved
+// slot by slot, so that the work-groups the dispatcher sends to one XCD
+// (slot % 8) walk one chunk and keep its panels in that XCD's L2. For several
+// problems (uneven costs) the tiles are listed most-expensive problem first.
+void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t> &out, int64_t *nfull)
 {
-    std::vector<uint64_t> L;
+    std::vector<uint64_t> L, part;
     std::vector<size_t> order(hp.size());
     for (size_t p = 0; p < hp.size(); ++p) order[p] = p;
     if (hp.size() > 1)
@@ -221,7 +225,10 @@ void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t
             for (int64_t J = b0; J < nT; ++J)
                 for (int64_t I = b0; I < std::min(b0 + G, nT) && I <= J; ++I) {
                     const int64_t maxj = std::min(J * tile + tile - 1, h.n - 1);
-                    if (maxj - I * tile >= h.excl) L.push_back(tile_pack((uint32_t)p, (uint32_t)I, (uint32_t)J));
+                    if (maxj - I * tile < h.excl) continue;
+                    const bool full = (J * tile - (I * tile + tile - 1) >= h.excl) && ((I + 1) * tile <= h.n) &&
+                                      ((J + 1) * tile <= h.n);
+                    (full ? L : part).push_back(tile_pack((uint32_t)p, (uint32_t)I, (uint32_t)J));
                 }
     }
     out.clear();
@@ -236,6 +243,8 @@ void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t
     } else {
         out = L;
     }
+    *nfull = (int64_t)out.size();
+    out.insert(out.end(), part.begin(), part.end());
 }
 
 struct RunOut {
@@ -252,7 +261,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
     // ---- workspace layout
     size_t xs_b = 0, sh_b = 0, bm_b = 0, mu_b = 0;
     for (auto &h : hp) {
-        h.kpad = kpad_for(prec, h.d);
+        h.kpad = kpad_for(prec, h.d, tile);
         h.npad = (h.n + 255) / 256 * 256;
         h.xs_off = xs_b;
         xs_b += (size_t)h.npad * h.kpad * esz;
@@ -282,7 +291,9 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
     }
     if (key != c->tiles_key) {
         std::vector<uint64_t> tl;
-        build_tiles(hp, tile, tl);
+        int64_t nf = 0;
+        build_tiles(hp, tile, tl, &nf);
+        c->nfull = nf;
         if ((rc = ensure(c, c->tiles, tl.size() * 8))) return rc;
         if ((rc = ensure(c, c->tile_min, tl.size() * 4))) return rc;
         if ((rc = ensure(c, c->sel, tl.size() * 8))) return rc;
@@ -291,6 +302,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         c->tiles_key = key;
     }
     const int64_t ntiles = c->ntiles;
+    const int64_t nfull = c->nfull;
 
     for (int attempt = 0; attempt < 4; ++attempt) {
         if ((rc = ensure(c, c->candR, (size_t)c->capR * sizeof(Cand)))) return rc;
@@ -374,9 +386,20 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             a.candU = (Cand *)c->candU.p;
             a.cntU = dcnt + C_U;
             a.capU = c->capU;
-            const int64_t grid1 = tile == 256 ? std::min<int64_t>(ntiles, c->ncu) : ntiles;
             if (!batch_graph) hipEventRecord(c->es0, st);
-            launch_screen(prec, tile, M_MIN, a, grid1, st);
+            if (tile == 256) {
+                // full tiles on the persistent unmasked screen, then the partial ones
+                ScreenArgs f = a;
+                f.ntiles = nfull;
+                launch_screen(prec, tile, M_MIN, false, f, std::min<int64_t>(nfull, c->ncu), st);
+                ScreenArgs q = a;
+                q.tiles = a.tiles + nfull;
+                q.tile_min = a.tile_min + nfull;
+                q.ntiles = ntiles - nfull;
+                launch_screen(prec, tile, M_MIN, true, q, std::min<int64_t>(ntiles - nfull, c->ncu), st);
+            } else {
+                launch_screen(prec, tile, M_MIN, true, a, ntiles, st);
+            }
             if (!batch_graph) hipEventRecord(c->es1, st);
             unsigned long long *ubits = want_cpp ? (unsigned long long *)c->ubits.p : nullptr;
             if (want_cpp) launch_reduce_U(dprobs, a.tiles, ntiles, a.tile_min, prec, ubits, st);
@@ -385,7 +408,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             b.tiles = (const uint64_t *)c->sel.p;
             b.sel_count = dcnt + C_SEL;
             b.U = (const double *)ubits;
-            launch_screen(prec, tile, M_EMIT, b,
+            launch_screen(prec, tile, M_EMIT, true, b,
                           std::min<int64_t>(std::max<int64_t>(ntiles, 1), tile == 256 ? c->ncu : 2048), st);
             if (want_cpp) {
                 launch_verify_cpp(dprobs, (const Cand *)c->candU.p, dcnt + C_U, c->capU, prec, tile,
@@ -664,7 +687,7 @@ int cpmi_points(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d, i
     hp[0].src = pts;
     hp[0].src_i8 = dtype == CPMI_I8;
     hp[0].r2 = want_frnn ? R2 : -1.0;
-    const int tile = pick_tile(c, prec, kpad_for(prec, d));
+    const int tile = pick_tile(c, prec, kpad_for(prec, d, 128));
     RunOut ro;
     if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro))) return rc;
     if ((rc = flags_error(c, ro.res[0].flags))) return rc;
@@ -732,7 +755,7 @@ int cpmi_motif(cpmi_ctx *c, const float *series, int64_t len, int64_t ell, int64
     hp[0].src = series;
     hp[0].len = len;
     hp[0].r2 = want_frnn ? R2 : -1.0;
-    const int tile = pick_tile(c, prec, kpad_for(prec, ell));
+    const int tile = pick_tile(c, prec, kpad_for(prec, ell, 128));
     RunOut ro;
     if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro))) return rc;
     if ((rc = flags_error(c, ro.res[0].flags))) return rc;
@@ -779,7 +802,7 @@ int cpmi_motif_batch(cpmi_ctx *c, const float *const *series, const int64_t *len
         h.len = L;
         hp.push_back(h);
         idx.push_back(s);
-        kmax = std::max<int64_t>(kmax, kpad_for(prec, ell));
+        kmax = std::max<int64_t>(kmax, kpad_for(prec, ell, 128));
     }
     if (hp.empty()) return CPMI_OK;
     int rc;
@@ -817,16 +840,17 @@ int64_t cpmi_dbg_tile_list(int64_t n, int64_t excl, int tile, uint64_t *out, int
     hp[0].n = n;
     hp[0].excl = excl;
     std::vector<uint64_t> tl;
-    build_tiles(hp, tile, tl);
+    int64_t nf = 0;
+    build_tiles(hp, tile, tl, &nf);
     for (int64_t k = 0; k < (int64_t)tl.size() && k < cap; ++k) out[k] = tl[k];
     return (int64_t)tl.size();
 }
 
 int cpmi_dbg_layout256(int wave, int q, int lane, int32_t *out4)
 {
-    if (wave < 0 || wave > 3 || q < 0 || q > 7 || lane < 0 || lane > 63 || !out4) return CPMI_ERR_ARG;
+    if (wave < 0 || wave > 3 || q < 0 || q >= l256::NQ || lane < 0 || lane > 63 || !out4) return CPMI_ERR_ARG;
     out4[0] = l256::dma_row(wave, q, lane);
-    out4[1] = l256::dma_col(lane);
+    out4[1] = l256::dma_col(wave, q, lane);
     out4[2] = l256::dma_lds(wave, q, lane);
     out4[3] = l256::frag_lds(out4[0], out4[1] >> 4);
     return CPMI_OK;
@@ -857,7 +881,7 @@ int cpmi_dbg_znorm(cpmi_ctx *c, const float *series, int64_t len, int64_t ell, i
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)stream;
     const int64_t N = len - ell + 1;
-    const int32_t kpad = kpad_for(prec, ell);
+    const int32_t kpad = kpad_for(prec, ell, 128);
     const int64_t npad = (N + 255) / 256 * 256;
     if ((rc = ensure(c, c->xs, (size_t)npad * kpad * elem_bytes(prec)))) return rc;
     if ((rc = ensure(c, c->shat, (size_t)npad * 4))) return rc;

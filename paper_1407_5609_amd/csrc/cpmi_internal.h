@@ -114,8 +114,10 @@ void launch_prep_points(const void *pts, int dtype, int64_t n, int64_t d, int64_
 void launch_prep_series(const SeriesJob *jobs, int64_t njobs, int64_t total_blocks, int prec, int tile,
                         hipStream_t st);
 
-// Gram screen (grid = work-groups; phase 2 loops over *sel_count entries).
-void launch_screen(int prec, int tile, int mode, const ScreenArgs &a, int64_t grid, hipStream_t st);
+// Gram screen (grid = work-groups; pass 2 loops over *sel_count entries).
+// masked = false promises that every pair of every listed tile is admissible
+// (used by the 256-tile screen for its list of full tiles).
+void launch_screen(int prec, int tile, int mode, bool masked, const ScreenArgs &a, int64_t grid, hipStream_t st);
 
 // Pass 1 -> pass 2: U[p] = min over tiles of (tile min + bound); then the
 // tiles whose lower bound (tile min - bound) does not exceed U[p] (if Ubits)

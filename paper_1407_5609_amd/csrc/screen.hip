@@ -257,13 +257,13 @@ static void launch_t(int mode, const ScreenArgs &a, int64_t grid, hipStream_t st
     else hipLaunchKernelGGL((screen_kernel<PREC, TILE, M_EMIT>), g, b, 0, st, a);
 }
 
-void launch_screen256(int prec, int mode, const ScreenArgs &a, int64_t grid, hipStream_t st);
+void launch_screen256(int prec, int mode, bool masked, const ScreenArgs &a, int64_t grid, hipStream_t st);
 
-void launch_screen(int prec, int tile, int mode, const ScreenArgs &a, int64_t grid, hipStream_t st)
+void launch_screen(int prec, int tile, int mode, bool masked, const ScreenArgs &a, int64_t grid, hipStream_t st)
 {
     if (grid <= 0) return;
     if (tile == 256) {
-        launch_screen256(prec, mode, a, grid, st);
+        launch_screen256(prec, mode, masked, a, grid, st);
     } else {
         if (prec == P_F32) launch_t<P_F32, 128>(mode, a, grid, st);
         else if (prec == P_BF16) launch_t<P_BF16, 128>(mode, a, grid, st);

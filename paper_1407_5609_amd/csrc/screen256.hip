@@ -6,13 +6,13 @@
 // throughput on large problems:
 //   * a persistent grid walks the tile list with stride gridDim.x, so a
 //     work-group keeps the slots of one XCD chunk of the list;
-//   * K slices (128 bytes per row) go straight from global memory into LDS
-//     with global_load_lds_dwordx4 (no staging registers), double-buffered,
-//     one barrier per slice, and the first slice of the next tile is fetched
-//     while the current tile's epilogue runs;
-//   * each 8-row, 1 KB LDS block stores row r's 16-byte chunk c at slot
-//     c ^ (r & 7), so the fragment reads of 8 consecutive rows hit 8
-//     different bank groups;
+//   * K slices (64 bytes per row) go straight from global memory into LDS
+//     with global_load_lds_dwordx4 (no staging registers) through a ring of
+//     four stages: the loads run three slices ahead of the multiply, across
+//     tile boundaries, with one barrier per slice;
+//   * each 16-row, 1 KB LDS block stores row r's 16-byte chunk c at slot
+//     c ^ ((r >> 2) & 3), so the fragment reads of 16 consecutive rows hit
+//     all 64 banks once (layout256.h);
 //   * 4 waves in a 2x2 grid, each owning 128x128 outputs as 4x4 32x32 MFMA
 //     blocks (256 accumulators per lane);
 //   * the epilogue takes, per accumulator row, the minimum over the four
@@ -22,6 +22,7 @@
 #include "bound.h"
 #include "cpmi_internal.h"
 #include "layout256.h"
+
 
 namespace cpmi {
 
@@ -33,14 +34,20 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) const void g_void;
+// Read-only kernel inputs (tile list, problem descriptors) are read through
+// the constant address space: with uniform addresses that gives scalar loads,
+// which are counted apart from the vector loads and so never wait behind the
+// direct-to-LDS loads in flight.
+typedef __attribute__((address_space(4))) const uint64_t c_u64;
+typedef __attribute__((address_space(4))) const Prob c_prob;
 
 namespace {
 
 constexpr int T256 = 256;         // tile edge
 constexpr int WT256 = 128;        // wave tile edge
 constexpr int MB256 = 4;          // 32x32 blocks per wave edge
-constexpr int SL = 128;           // K slice, bytes per row
-constexpr int OPB = T256 * SL;    // one operand slice in LDS (32 KB)
+constexpr int SL = l256::SLICE;   // K slice, bytes per row (64)
+constexpr int OPB = T256 * SL;    // one operand slice in LDS (16 KB)
 
 template <int PREC> struct A2 { using T = f32x16; using S = float; };
 template <> struct A2<P_I8> { using T = i32x16; using S = int; };
@@ -79,86 +86,86 @@ __device__ __forceinline__ int part(int g, int sj) { return sj - 2 * g; }
 
 }  // namespace
 
-// The two LDS stages are distinct __shared__ objects and every slice step
-// names its stage at compile time, so the compiler can see that the
-// direct-to-LDS loads into one stage never alias the fragment reads of the
-// other and does not make those reads wait for the loads in flight.
+// The four LDS stages are distinct __shared__ objects and every slice step
+// names its stages at compile time, so the compiler can see that the
+// direct-to-LDS loads into one stage never alias the fragment reads of
+// another and does not make those reads wait for the loads in flight.
 __shared__ __attribute__((aligned(1024))) unsigned char g_stage0[2 * OPB];
 __shared__ __attribute__((aligned(1024))) unsigned char g_stage1[2 * OPB];
+__shared__ __attribute__((aligned(1024))) unsigned char g_stage2[2 * OPB];
+__shared__ __attribute__((aligned(1024))) unsigned char g_stage3[2 * OPB];
 
 template <int STG> __device__ __forceinline__ unsigned char *stage_ptr()
 {
-    return STG == 0 ? g_stage0 : g_stage1;
+    return STG == 0 ? g_stage0 : (STG == 1 ? g_stage1 : (STG == 2 ? g_stage2 : g_stage3));
 }
 
 // Per-tile addressing of the direct-to-LDS loads: a uniform base per operand
-// plus one 32-bit per-lane offset, so the loads use the scalar-base form and
-// keep no 64-bit per-lane addresses live.
+// plus one 32-bit per-lane offset, so the loads use the scalar-base form.
 struct TileAddr {
-    const unsigned char *ga;  // operand A rows of the tile (slice 0)
-    const unsigned char *gb;  // operand B rows of the tile (slice 0)
-    uint32_t lane_off;        // (wave*64 + ld_row) * rowbytes + ld_col
-    uint32_t step8;           // 8 * rowbytes
-    int nst;                  // K slices
+    const unsigned char *ga;  // operand A rows of the tile
+    const unsigned char *gb;  // operand B rows of the tile
+    uint32_t lane_off;        // (row within a 16-row block) * rowbytes + swizzled column
+    uint32_t rowbytes;
+    int nst;                  // K slices of the tile
 };
 
 template <int ESZ>
-__device__ __forceinline__ TileAddr tile_addr(const ScreenArgs &args, uint64_t ent, int wave, int ld_row, int ld_col)
+__device__ __forceinline__ TileAddr tile_addr(const ScreenArgs &args, uint64_t ent, int lane)
 {
-    const Prob &P = args.probs[tile_prob(ent)];
+    const c_prob &P = ((c_prob *)args.probs)[tile_prob(ent)];
     const uint32_t rowbytes = (uint32_t)P.kpad * ESZ;
     const unsigned char *xs = (const unsigned char *)P.xs;
     TileAddr ta;
     ta.ga = xs + (int64_t)tile_I(ent) * T256 * rowbytes;
     ta.gb = xs + (int64_t)tile_J(ent) * T256 * rowbytes;
-    // row of this lane inside its 8-row block (the block's first row is part
-    // of the uniform base in issue_slice), and the swizzled byte column
-    ta.lane_off = (uint32_t)ld_row * rowbytes + (uint32_t)ld_col;
-    ta.step8 = 8u * rowbytes;
+    // the column swizzle of a lane does not depend on the block (layout256.h)
+    ta.lane_off = (uint32_t)l256::dma_row(0, 0, lane) * rowbytes + (uint32_t)l256::dma_col(0, 0, lane);
+    ta.rowbytes = rowbytes;
     ta.nst = (int)(rowbytes / SL);
     return ta;
 }
 
+// The 8 direct-to-LDS loads of one wave for K slice s of a tile (4 blocks of
+// 16 rows per operand).
 __device__ __forceinline__ void issue_slice(const TileAddr &ta, int s, int wave, unsigned char *__restrict__ wr)
 {
     unsigned char *la = wr;
     unsigned char *lb = wr + OPB;
-    // uniform base of this wave's first 8-row block; block q adds q * 8 rows
-    const uint32_t rowbytes = ta.step8 >> 3;
-    const unsigned char *ga = ta.ga + s * SL + (uint32_t)l256::dma_row(wave, 0, 0) * rowbytes;
-    const unsigned char *gb = ta.gb + s * SL + (uint32_t)l256::dma_row(wave, 0, 0) * rowbytes;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const uint32_t bq = (uint32_t)q * ta.step8;
+    for (int q = 0; q < l256::NQ; ++q) {
+        const uint32_t rb = (uint32_t)l256::dma_row(wave, q, 0) * ta.rowbytes + (uint32_t)(s * SL);
         const int ldst = l256::dma_lds(wave, q, 0);
-        __builtin_amdgcn_global_load_lds((g_void *)(ga + bq + ta.lane_off), (lds_void *)(la + ldst), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds((g_void *)(gb + bq + ta.lane_off), (lds_void *)(lb + ldst), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((g_void *)(ta.ga + rb + ta.lane_off), (lds_void *)(la + ldst), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((g_void *)(ta.gb + rb + ta.lane_off), (lds_void *)(lb + ldst), 16, 0, 0);
     }
 }
 
 // Scheduling masks of __builtin_amdgcn_sched_group_barrier.
 constexpr int SG_MFMA = 0x008;
+constexpr int SG_VMEM_READ = 0x020;
 constexpr int SG_DS_READ = 0x100;
 
-// One K slice: prefetch the following slice (or the next tile's first one)
-// into the other stage, multiply this stage, then wait and synchronise.
-// Within the slice the fragments of k-group g+1 are read from LDS while the
-// 16 MFMAs of k-group g run (pinned with scheduling group barriers).
-// The stage being read and the stage being filled arrive as restrict
-// pointers: once inlined, their accesses carry distinct alias scopes, which is
-// what lets the wait-count insertion see that the LDS reads below need not
-// wait for the direct-to-LDS loads just issued.
-template <int PREC>
-__device__ __forceinline__ void slice_step_impl(typename A2<PREC>::T (&acc)[MB256][MB256], const TileAddr &cur,
-                                                int s, const TileAddr &nxt, bool has_next, int wave, int wm, int wn,
-                                                int lrow, int lhalf, const unsigned char *__restrict__ rd,
-                                                unsigned char *__restrict__ wr)
+// s_waitcnt immediates (gfx9 encoding: vmcnt[3:0] | expcnt << 4 | lgkmcnt << 8 | vmcnt[5:4] << 14).
+// WAIT_SLICE: at most the 16 loads of the two newest slices in flight, all LDS reads done.
+constexpr int WAIT_SLICE = (16 & 15) | (7 << 4) | (0 << 8) | ((16 >> 4) << 14);
+constexpr int WAIT_LGKM0 = 15 | (7 << 4) | (0 << 8) | (3 << 14);
+
+// One K slice: issue the loads of the slice three ahead into the free stage,
+// multiply this stage, then wait for the next stage and synchronise. The
+// read and written stages arrive as restrict pointers: once inlined their
+// accesses carry distinct alias scopes, so the LDS reads below do not wait for
+// the loads just issued. Loads, fragment reads and MFMAs are interleaved with
+// scheduling group barriers.
+template <int PREC, bool FIRST = false>
+__device__ __forceinline__ void slice_step(typename A2<PREC>::T (&acc)[MB256][MB256], const TileAddr &ia, int is,
+                                           int wave, int wm, int wn, int lrow, int lhalf,
+                                           const unsigned char *__restrict__ rd, unsigned char *__restrict__ wr)
 {
-    if (s + 1 < cur.nst) issue_slice(cur, s + 1, wave, wr);
-    else if (has_next) issue_slice(nxt, 0, wave, wr);
+    issue_slice(ia, is, wave, wr);
     const unsigned char *la = rd;
-    const unsigned char *lb = la + OPB;
-    constexpr int NG = SL / 32;
+    const unsigned char *lb = rd + OPB;
+    constexpr int NG = SL / 32;  // k-groups per slice
     u32x4 fa[NG][MB256], fb[NG][MB256];
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
@@ -174,33 +181,28 @@ __device__ __forceinline__ void slice_step_impl(typename A2<PREC>::T (&acc)[MB25
 #pragma unroll
         for (int a = 0; a < MB256; ++a)
 #pragma unroll
-            for (int b = 0; b < MB256; ++b) mma2<PREC>(acc[a][b], fa[g][a], fb[g][b]);
-    // schedule: group 0 reads, then per group 16 MFMAs with the next group's
-    // 8 reads spread between them (FP32 issues 4 MFMAs per fragment pair)
+            for (int b = 0; b < MB256; ++b) {
+                if (FIRST && g == 0) acc[a][b] = typename A2<PREC>::T{};  // folds into the MFMA's zero operand
+                mma2<PREC>(acc[a][b], fa[g][a], fb[g][b]);
+            }
+    // schedule: k-group 0 reads; then per MFMA pair of k-group 0 one read of
+    // k-group 1 and one of the 8 loads; then k-group 1's MFMAs
     constexpr int MPG = (PREC == P_F32 ? 4 : 1) * MB256 * MB256;  // MFMAs per k-group
     __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 2 * MB256, 0);
 #pragma unroll
-    for (int g = 0; g + 1 < NG; ++g)
-#pragma unroll
-        for (int k = 0; k < 2 * MB256; ++k) {
-            __builtin_amdgcn_sched_group_barrier(SG_MFMA, MPG / (2 * MB256), 0);
-            __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
-        }
+    for (int k = 0; k < 2 * MB256; ++k) {
+        __builtin_amdgcn_sched_group_barrier(SG_MFMA, MPG / (2 * MB256), 0);
+        __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(SG_VMEM_READ, 1, 0);
+    }
     __builtin_amdgcn_sched_group_barrier(SG_MFMA, MPG, 0);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    __builtin_amdgcn_s_waitcnt(WAIT_SLICE);
+    __builtin_amdgcn_s_barrier();
 }
 
-template <int PREC, int STG>
-__device__ __forceinline__ void slice_step(typename A2<PREC>::T (&acc)[MB256][MB256], const TileAddr &cur, int s,
-                                           const TileAddr &nxt, bool has_next, int wave, int wm, int wn, int lrow,
-                                           int lhalf)
-{
-    slice_step_impl<PREC>(acc, cur, s, nxt, has_next, wave, wm, wn, lrow, lhalf, stage_ptr<STG>(),
-                          stage_ptr<1 - STG>());
-}
-
-template <int PREC, int MODE>
+// MASKED = false: every pair of every listed tile is admissible (the host
+// lists such full tiles apart), so the epilogue carries no masking code.
+template <int PREC, int MODE, bool MASKED>
 __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) void screen256_kernel(ScreenArgs args)
 {
     using AccT = typename A2<PREC>::T;
@@ -209,44 +211,75 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     constexpr int ESZ = PREC == P_F32 ? 4 : (PREC == P_BF16 ? 2 : 1);
 
     __shared__ S sh_red[4];
+    // row scalars of blocks I and J, double-buffered by tile parity
+    __shared__ __attribute__((aligned(16))) S sh_s[2 * 2 * T256];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave >> 1, wn = wave & 1;
     const int lrow = lane & 31, lhalf = lane >> 5;
-    // direct-to-LDS pattern: lane i fills bytes [16 i, 16 i + 16) of a 1 KB
-    // block of 8 rows, i.e. row i / 8, slot i % 8, which holds chunk slot ^ row
-    const int ld_row = l256::dma_row(0, 0, lane);
-    const int ld_col = l256::dma_col(lane);
 
     const int64_t count = (MODE & M_EMIT) ? (int64_t)*args.sel_count : args.ntiles;
     const int64_t stride = gridDim.x;
 
+    c_u64 *tiles = (c_u64 *)args.tiles;
     auto next_valid = [&](int64_t t) -> int64_t {
-        while (t < count && args.tiles[t] == TILE_NONE) t += stride;
+        while (t < count && tiles[t] == TILE_NONE) t += stride;
         return t;
     };
 
-    int stg = 0;
     int64_t t = next_valid(blockIdx.x);
-    TileAddr cur{};
-    if (t < count) {
-        cur = tile_addr<ESZ>(args, args.tiles[t], wave, ld_row, ld_col);
-        issue_slice(cur, 0, wave, stage_ptr<0>());
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    if (t >= count) return;
+    int tcount = 0;
+
+    // load cursor: runs three slices ahead of the multiply, across tiles; at
+    // the end of the list it keeps re-reading its last slice (always in bounds)
+    int64_t it = t;
+    int is = 0;
+    TileAddr ia = tile_addr<ESZ>(args, tiles[it], lane);
+    auto advance = [&]() {
+        if (is + 1 < ia.nst) {
+            ++is;
+        } else {
+            const int64_t tn = next_valid(it + stride);
+            if (tn < count) {
+                it = tn;
+                is = 0;
+                ia = tile_addr<ESZ>(args, tiles[it], lane);
+            }
+        }
+    };
+    issue_slice(ia, is, wave, stage_ptr<0>());
+    advance();
+    issue_slice(ia, is, wave, stage_ptr<1>());
+    advance();
+    issue_slice(ia, is, wave, stage_ptr<2>());
+    advance();
+    __builtin_amdgcn_s_waitcnt(WAIT_SLICE);
+    __builtin_amdgcn_s_barrier();
 
     while (t < count) {
-        const uint64_t ent = args.tiles[t];
+        const uint64_t ent = tiles[t];
         const uint32_t p = tile_prob(ent);
-        const Prob &P = args.probs[p];
+        const c_prob &P = ((c_prob *)args.probs)[p];
         const int64_t I = tile_I(ent), J = tile_J(ent);
-        const int nst = cur.nst;
-        const int64_t tn = next_valid(t + stride);
-        const bool has_next = tn < count;
-        const TileAddr nxt = has_next ? tile_addr<ESZ>(args, args.tiles[tn], wave, ld_row, ld_col) : cur;
+        const int nst = (int)((int64_t)P.kpad * ESZ / SL);
+        const int32_t i0 = (int32_t)(I * T256) + wm * WT256, j0 = (int32_t)(J * T256) + wn * WT256;
+        // row scalars of this tile: each wave loads 64 of block I and 64 of
+        // block J straight into this tile's half of sh_s. They are older than
+        // the slices multiplied below, so the per-slice waits cover them (the
+        // tile has at least four slices) and no VGPR or extra wait is needed.
+        S *sh_t = sh_s + (tcount & 1) * (2 * T256);
+        {
+            const unsigned char *sb = (const unsigned char *)P.shat;
+            const uint32_t lo = (uint32_t)lane * 4;
+            __builtin_amdgcn_global_load_lds((g_void *)(sb + (I * T256 + wave * 64) * 4 + lo),
+                                             (lds_void *)(sh_t + wave * 64), 4, 0, 0);
+            __builtin_amdgcn_global_load_lds((g_void *)(sb + (J * T256 + wave * 64) * 4 + lo),
+                                             (lds_void *)(sh_t + T256 + wave * 64), 4, 0, 0);
+        }
+        ++tcount;
 
         AccT acc[MB256][MB256];
 #pragma unroll
@@ -254,47 +287,57 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
 #pragma unroll
             for (int b = 0; b < MB256; ++b) acc[a][b] = AccT{};
 
-        int s = 0;
-        if (stg == 1) {
-            slice_step<PREC, 1>(acc, cur, s, nxt, has_next, wave, wm, wn, lrow, lhalf);
-            ++s;
+        // nst is a multiple of 4 (rows are padded to whole groups of four
+        // slices), so every tile starts at stage 0
+        for (int s = 0; s < nst; s += 4) {
+            TileAddr cia = ia;
+            int cis = is;
+            advance();
+            slice_step<PREC>(acc, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<0>(), stage_ptr<3>());
+            cia = ia;
+            cis = is;
+            advance();
+            slice_step<PREC>(acc, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<1>(), stage_ptr<0>());
+            cia = ia;
+            cis = is;
+            advance();
+            slice_step<PREC>(acc, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<2>(), stage_ptr<1>());
+            cia = ia;
+            cis = is;
+            advance();
+            slice_step<PREC>(acc, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<3>(), stage_ptr<2>());
         }
-        for (; s + 1 < nst; s += 2) {
-            slice_step<PREC, 0>(acc, cur, s, nxt, has_next, wave, wm, wn, lrow, lhalf);
-            slice_step<PREC, 1>(acc, cur, s + 1, nxt, has_next, wave, wm, wn, lrow, lhalf);
-        }
-        if (s < nst) slice_step<PREC, 0>(acc, cur, s, nxt, has_next, wave, wm, wn, lrow, lhalf);
-        stg = (stg + nst) & 1;
-        cur = nxt;
+        const int64_t tn = next_valid(t + stride);
 
         // ---------------- epilogue ----------------
         // 32-bit row/column indices (n < 2^31 is enforced by the host)
         const int32_t n = (int32_t)P.n, excl = (int32_t)P.excl;
-        const int32_t i0 = (int32_t)(I * T256) + wm * WT256, j0 = (int32_t)(J * T256) + wn * WT256;
-        const bool full = ((int64_t)J * T256 - ((int64_t)I * T256 + T256 - 1) >= P.excl) &&
-                          ((int64_t)I * T256 + T256 <= P.n) && ((int64_t)J * T256 + T256 <= P.n);
-        const S *shat = (const S *)P.shat;
+        const bool full = !MASKED || (((int64_t)J * T256 - ((int64_t)I * T256 + T256 - 1) >= P.excl) &&
+                                      ((int64_t)I * T256 + T256 <= P.n) && ((int64_t)J * T256 + T256 <= P.n));
         S sj[MB256];
 #pragma unroll
-        for (int b = 0; b < MB256; ++b) sj[b] = shat[j0 + b * 32 + lrow];
+        for (int b = 0; b < MB256; ++b) sj[b] = sh_t[T256 + wn * WT256 + b * 32 + lrow];
 
-        S best = SINF;
-#pragma unroll
-        for (int a = 0; a < MB256; ++a) {
-            // rows of this lane in block a: 8*(r/4) + 4*lhalf + (r%4), four runs of 4 consecutive rows
-            S si[16];
+        // rows of this lane in block a: 8*(r/4) + 4*lhalf + (r%4), four runs of 4 rows
+        auto load_si = [&](int a, S (&si)[16]) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int32_t rb = i0 + a * 32 + 8 * q + 4 * lhalf;
+                const int rb = wm * WT256 + a * 32 + 8 * q + 4 * lhalf;
                 if constexpr (PREC == P_I8) {
-                    const i32x4 v = *(const i32x4 *)(shat + rb);
+                    const i32x4 v = *(const i32x4 *)(sh_t + rb);
                     si[4 * q] = v.x; si[4 * q + 1] = v.y; si[4 * q + 2] = v.z; si[4 * q + 3] = v.w;
                 } else {
-                    const f32x4 v = *(const f32x4 *)(shat + rb);
+                    const f32x4 v = *(const f32x4 *)(sh_t + rb);
                     si[4 * q] = v.x; si[4 * q + 1] = v.y; si[4 * q + 2] = v.z; si[4 * q + 3] = v.w;
                 }
             }
-            if (full) {
+        };
+        S best = SINF;
+        if (full) {
+#pragma unroll
+            for (int a = 0; a < MB256; ++a) {
+                S si[16];
+                load_si(a, si);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     S m0 = part(acc[a][0][r], sj[0]);
@@ -302,7 +345,14 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                     for (int b = 1; b < MB256; ++b) m0 = smin(m0, part(acc[a][b][r], sj[b]));
                     best = smin(best, (S)(si[r] + m0));
                 }
-            } else {
+                // one accumulator block at a time keeps the epilogue's registers few
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else if constexpr (MASKED) {
+#pragma unroll
+            for (int a = 0; a < MB256; ++a) {
+                S si[16];
+                load_si(a, si);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
@@ -314,6 +364,7 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                         best = ok ? smin(best, dv) : best;
                     }
                 }
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
 
@@ -336,7 +387,7 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
-                        const S si = shat[gi];
+                        const S si = sh_t[gi - (int32_t)(I * T256)];
 #pragma unroll
                         for (int b = 0; b < MB256; ++b) {
                             const int32_t gj = j0 + b * 32 + lrow;
@@ -364,7 +415,8 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         if constexpr (MODE & M_MIN) {
             best = wmin(best);
             if (lane == 0) sh_red[wave] = best;
-            __syncthreads();
+            __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
+            __builtin_amdgcn_s_barrier();
             if (tid == 0) {
                 S m = smin(smin(sh_red[0], sh_red[1]), smin(sh_red[2], sh_red[3]));
                 args.tile_min[t] = __builtin_bit_cast(uint32_t, m);
@@ -375,19 +427,20 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
 }
 
 template <int PREC>
-static void launch256(int mode, const ScreenArgs &a, int64_t grid, hipStream_t st)
+static void launch256(int mode, bool masked, const ScreenArgs &a, int64_t grid, hipStream_t st)
 {
     dim3 g((unsigned)grid), b(256);
-    if (mode == M_MIN) hipLaunchKernelGGL((screen256_kernel<PREC, M_MIN>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((screen256_kernel<PREC, M_EMIT>), g, b, 0, st, a);
+    if (mode == M_MIN && !masked) hipLaunchKernelGGL((screen256_kernel<PREC, M_MIN, false>), g, b, 0, st, a);
+    else if (mode == M_MIN) hipLaunchKernelGGL((screen256_kernel<PREC, M_MIN, true>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((screen256_kernel<PREC, M_EMIT, true>), g, b, 0, st, a);
 }
 
-void launch_screen256(int prec, int mode, const ScreenArgs &a, int64_t grid, hipStream_t st)
+void launch_screen256(int prec, int mode, bool masked, const ScreenArgs &a, int64_t grid, hipStream_t st)
 {
     if (grid <= 0) return;
-    if (prec == P_F32) launch256<P_F32>(mode, a, grid, st);
-    else if (prec == P_BF16) launch256<P_BF16>(mode, a, grid, st);
-    else launch256<P_I8>(mode, a, grid, st);
+    if (prec == P_F32) launch256<P_F32>(mode, masked, a, grid, st);
+    else if (prec == P_BF16) launch256<P_BF16>(mode, masked, a, grid, st);
+    else launch256<P_I8>(mode, masked, a, grid, st);
 }
 
 }  // namespace cpmi

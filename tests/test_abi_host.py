@@ -54,12 +54,12 @@ def test_null_context_is_rejected_without_a_gpu(lib):
     assert lib.cpmi_version() == 10000
 
 
-def _tiles(lib, n, excl, tile):
+def _tiles(lib, n, excl, tile, raw=False):
     cnt = lib.cpmi_dbg_tile_list(n, excl, tile, None, 0)
     out = np.zeros(max(cnt, 1), dtype=np.uint64)
     assert lib.cpmi_dbg_tile_list(n, excl, tile, out.ctypes.data, cnt) == cnt
     out = out[:cnt]
-    return out[out != np.uint64(0xFFFFFFFFFFFFFFFF)]
+    return out if raw else out[out != np.uint64(0xFFFFFFFFFFFFFFFF)]
 
 
 @pytest.mark.parametrize("n,excl,tile", [(1, 1, 128), (2, 1, 128), (300, 1, 128), (1000, 1, 256), (2049, 1, 128),
@@ -81,8 +81,18 @@ def test_tile_list_covers_each_admissible_pair_once(lib, n, excl, tile):
         covered += k
     m = n - excl
     assert covered == (m * (m + 1) // 2 if m > 0 else 0)
-    # the XCD interleave keeps a single problem's list in 8 strided chunks
-    assert lib.cpmi_dbg_tile_list(n, excl, tile, None, 0) % 8 == 0 or n < 2
+    # full tiles (every pair admissible) come first, padded to a multiple of 8
+    # slots for the XCD interleave; partial tiles follow
+    raw = _tiles(lib, n, excl, tile, raw=True)
+    NONE = np.uint64(0xFFFFFFFFFFFFFFFF)
+    def is_full(e):
+        a, b = int((e >> np.uint64(22)) & np.uint64(0x3FFFFF)), int(e & np.uint64(0x3FFFFF))
+        return b * tile - (a * tile + tile - 1) >= excl and (a + 1) * tile <= n and (b + 1) * tile <= n
+    kinds = [None if e == NONE else is_full(e) for e in raw]
+    first_partial = next((k for k, v in enumerate(kinds) if v is False), len(kinds))
+    assert all(v is not False for v in kinds[:first_partial])
+    assert all(v is False for v in kinds[first_partial:])
+    assert first_partial % 8 == 0
 
 
 def test_tile_list_rejects_bad_arguments(lib):
@@ -175,30 +185,35 @@ def test_int8_bound_is_zero(lib):
 
 def test_layout256_covers_the_slice_and_reads_what_was_written(lib):
     """Every direct-to-LDS load of the 256-tile screen reads a row inside the
-    tile and a 16-byte chunk inside the 128-byte slice; together they cover
-    every (row, chunk) once, write every LDS byte of the block once, and the
-    fragment read of (row, chunk) looks exactly where that chunk was written."""
+    tile and a 16-byte chunk inside the 64-byte slice; together they cover
+    every (row, chunk) once, write every LDS byte of the block once, the
+    fragment read of (row, chunk) looks exactly where that chunk was written,
+    and 16 consecutive rows read at one chunk touch 16 distinct bank groups."""
     lib.cpmi_dbg_layout256.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p]
+    SL, NQ = 64, 4
     out = np.zeros(4, np.int32)
-    seen_src, seen_dst = {}, set()
+    ref = np.zeros(4, np.int32)
+    where = {}
+    dsts = set()
     for w in range(4):
-        for q in range(8):
+        for q in range(NQ):
             for lane in range(64):
                 assert lib.cpmi_dbg_layout256(w, q, lane, out.ctypes.data) == 0
                 row, col, dst, rd = (int(v) for v in out)
-                assert 0 <= row < 256 and 0 <= col < 128 and col % 16 == 0
-                assert 0 <= dst < 256 * 128 and dst % 16 == 0
-                key = (row, col // 16)
-                assert key not in seen_src
-                seen_src[key] = dst
-                seen_dst.add(dst)
-    assert len(seen_src) == 256 * 8 and len(seen_dst) == 256 * 8
-    for (row, chunk), dst in seen_src.items():
-        assert lib.cpmi_dbg_layout256(0, 0, 0, out.ctypes.data) == 0
-    # fragment read positions: compare with the write position of the same chunk
-    for w in range(4):
-        for q in range(8):
-            for lane in range(64):
-                lib.cpmi_dbg_layout256(w, q, lane, out.ctypes.data)
-                assert int(out[3]) == int(out[2])
+                assert 0 <= row < 256 and 0 <= col < SL and col % 16 == 0
+                assert 0 <= dst < 256 * SL and dst % 16 == 0
+                assert (row, col // 16) not in where
+                where[(row, col // 16)] = dst
+                dsts.add(dst)
+                assert rd == dst                       # read position == written position
+                # the kernel uses one per-lane column for every block
+                lib.cpmi_dbg_layout256(0, 0, lane, ref.ctypes.data)
+                assert col == int(ref[1])
+                assert row - int(ref[0]) == (w * NQ + q) * 16
+    assert len(where) == 256 * (SL // 16) and len(dsts) == 256 * (SL // 16)
+    for r0 in range(0, 256, 16):
+        for chunk in range(SL // 16):
+            banks = {(where[(r, chunk)] // 4) % 64 for r in range(r0, r0 + 16)}
+            assert len(banks) == 16
     assert lib.cpmi_dbg_layout256(4, 0, 0, out.ctypes.data) == -1
+    assert lib.cpmi_dbg_layout256(0, NQ, 0, out.ctypes.data) == -1
