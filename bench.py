@@ -1,0 +1,160 @@
+"""Benchmark: exact closest pair + fixed-radius pairs on the precision-form workload.
+
+Workload: n = 262,144 points, d = 512, float32, 64-cluster Gaussian mixture with
+one planted pair (workloads.cfg_mixture); radius R = half the lower-median
+nearest-neighbour distance (an oracle-computed input read from
+tests/golden/mixture_n262144_d512.json). One step = one call of the whole hot
+path: row prep -> BF16 matrix-core screen (tile minima) -> bound reduction and
+tile selection -> second screen of the selected tiles -> FP64 verification ->
+closest pair + sorted radius pairs, result exact (checked against the oracle's
+stored answer). The plain FP32 screen is timed on the same workload for the
+BF16-vs-FP32 speedup.
+
+Prints one JSON line. `roofline` refers to the dominant kernel (the full-tile
+pass-1 screen), timed with HIP events on the call's stream; `cpu_baseline` is
+the CPU oracle on a bounded sample (rank 0, N = 1 only).
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "exact pair-evals/s + % MFMA roofline; BF16-screened vs plain FP32 speedup"
+PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak (published)
+PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 matrix peak (published)
+GOLDEN = os.path.join(ROOT, "tests", "golden", "mixture_n262144_d512.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "screen256_bf16_mixture_n262144_d512.traffic.json")
+SCREEN_SRC = os.path.join(ROOT, "paper_1407_5609_amd", "csrc", "screen256.hip")
+
+
+def _traffic_per_launch():
+    """HBM bytes per launch of the dominant kernel from the committed rocprof
+    counter summary, or None if absent or taken on a different kernel source."""
+    try:
+        t = json.load(open(TRAFFIC))
+        src = hashlib.sha256(open(SCREEN_SRC, "rb").read()).hexdigest()
+        if t.get("kernel_source_sha256") != src:
+            return None
+        return float(t["hbm_bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(X, target_s=15.0):
+    """Time the CPU oracle's closest-pair search on the first m rows."""
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    oracle.set_threads(threads)
+    m = 2048
+    t = time.perf_counter()
+    oracle.closest_pair(X[:m])
+    dt = time.perf_counter() - t
+    rate = m * (m - 1) / 2 / max(dt, 1e-6)
+    m = int(min(X.shape[0], max(2048, (2 * rate * target_s) ** 0.5)))
+    t = time.perf_counter()
+    oracle.closest_pair(X[:m])
+    dt = time.perf_counter() - t
+    pairs = m * (m - 1) // 2
+    return {"value": pairs / dt, "unit": "pair-evals/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"closest pair over the first {m} rows of the workload ({pairs} pairs, d=512), "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp32-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU split of the tile "
+              "list is a design note, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1407_5609_amd as cp
+    import workloads as W
+
+    g = json.load(open(GOLDEN))
+    R2 = float.fromhex(g["R2"])
+    want_pair = (g["closest_pair"]["i"], g["closest_pair"]["j"], float.fromhex(g["closest_pair"]["d2"]))
+    want_pairs = np.array(g["frnn"]["pairs"], dtype=np.int64).reshape(-1, 2)
+    want_d2 = np.array([float.fromhex(v) for v in g["frnn"]["d2"]])
+
+    c = W.cfg_mixture()
+    Xh = c["X"]
+    n, d = Xh.shape
+    torch.cuda.set_device(0)
+    X = torch.from_numpy(Xh).to("cuda:0")
+    ctx = cp.Context(0)
+
+    def run(prec, steps, warmup):
+        exact = True
+        for _ in range(warmup):
+            ctx.points(X, R2=R2, precision=prec)
+        torch.cuda.synchronize()
+        screen_ms, t0 = [], time.perf_counter()
+        for _ in range(steps):
+            best, (p, dd) = ctx.points(X, R2=R2, precision=prec)
+            st = ctx.stats()
+            screen_ms.append(st.screen_ms)
+            exact &= (best.i, best.j, best.d2) == want_pair
+            exact &= bool(np.array_equal(p.cpu().numpy(), want_pairs)) and bool(np.array_equal(dd.cpu().numpy(),
+                                                                                          want_d2))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall / steps, float(np.mean(screen_ms)), st, exact
+
+    ms_step, screen_ms, st, exact_bf16 = run("bf16", args.steps, args.warmup)
+    fp32_ms, fp32_screen_ms, st32, exact_fp32 = run("f32", max(1, args.fp32_steps), 1)
+
+    pairs = st.valid_pairs
+    value = pairs / ms_step
+    achieved = 2.0 * d * st.screen_pairs / (screen_ms * 1e-3) / 1e12
+    traffic = _traffic_per_launch()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"mixture_n{n}_d{d}: exact closest pair + all pairs within R "
+                               "(BF16 matrix-core screen, FP64 verification)",
+                   "n": n, "d": d, "R": float.fromhex(g["R"]), "valid_pairs": pairs, "tile": st.tile},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic,
+                     "kernel": "screen256_kernel<bf16, min, full tiles>", "avg_launch_ms": screen_ms,
+                     "flops_per_launch": 2.0 * d * st.screen_pairs},
+        "fp32_plain": {"value": pairs / fp32_ms, "ms_per_step": fp32_ms * 1e3,
+                       "screen_tflops": 2.0 * d * st32.screen_pairs / (fp32_screen_ms * 1e-3) / 1e12,
+                       "screen_frac_of_fp32_peak": 2.0 * d * st32.screen_pairs / (fp32_screen_ms * 1e-3) / 1e12
+                       / PEAK_FP32_TFLOPS,
+                       "speedup_bf16_vs_fp32": fp32_ms / ms_step},
+        "exact_match": bool(exact_bf16 and exact_fp32),
+        "screen_err_over_bound": st.max_err_over_bound,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(Xh)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -99,7 +99,9 @@ typedef struct {
     int64_t reruns;              /* internal buffer growths that forced a re-run              */
     double max_err_over_bound;   /* max over verified candidates of |screen - d2| / bound      */
     double kernel_ms;            /* device time of the enqueued work, HIP events              */
-    double screen_ms;            /* device time of the first screen pass alone (0 if graphed) */
+    double screen_ms;            /* device time of the main first-pass screen launch (HIP
+                                    events on the call's stream; 0 when replayed from a graph) */
+    int64_t screen_pairs;        /* admissible pairs covered by that launch                    */
     int32_t precision;           /* precision actually used (CPMI_PREC_*)                     */
     int32_t tile;                /* screen tile edge used                                     */
 } cpmi_stats;

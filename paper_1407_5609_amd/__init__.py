@@ -38,7 +38,8 @@ class _CStats(C.Structure):
     _fields_ = [("valid_pairs", C.c_int64), ("tiles_total", C.c_int64), ("tiles_rescreened", C.c_int64),
                 ("cpp_candidates", C.c_int64), ("frnn_candidates", C.c_int64), ("frnn_pairs", C.c_int64),
                 ("reruns", C.c_int64), ("max_err_over_bound", C.c_double), ("kernel_ms", C.c_double),
-                ("screen_ms", C.c_double), ("precision", C.c_int32), ("tile", C.c_int32)]
+                ("screen_ms", C.c_double), ("screen_pairs", C.c_int64), ("precision", C.c_int32),
+                ("tile", C.c_int32)]
 
 
 def library_path() -> str:
@@ -101,6 +102,7 @@ class Stats:
     max_err_over_bound: float
     kernel_ms: float
     screen_ms: float
+    screen_pairs: int
     precision: int
     tile: int
 

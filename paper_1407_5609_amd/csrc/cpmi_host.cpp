@@ -71,6 +71,7 @@ struct cpmi_ctx {
     std::vector<int64_t> tiles_key;
     int64_t ntiles = 0;
     int64_t nfull = 0;   // leading entries of the list that are full tiles
+    int64_t nfull_pairs = 0;  // pairs covered by the full tiles
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t es0 = nullptr, es1 = nullptr;  // around the first screen pass
@@ -294,6 +295,9 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         int64_t nf = 0;
         build_tiles(hp, tile, tl, &nf);
         c->nfull = nf;
+        int64_t nreal = 0;
+        for (int64_t k = 0; k < nf; ++k) nreal += tl[k] != TILE_NONE;
+        c->nfull_pairs = nreal * (int64_t)tile * tile;
         if ((rc = ensure(c, c->tiles, tl.size() * 8))) return rc;
         if ((rc = ensure(c, c->tile_min, tl.size() * 4))) return rc;
         if ((rc = ensure(c, c->sel, tl.size() * 8))) return rc;
@@ -386,21 +390,24 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             a.candU = (Cand *)c->candU.p;
             a.cntU = dcnt + C_U;
             a.capU = c->capU;
-            if (!batch_graph) hipEventRecord(c->es0, st);
+            // the events bracket the dominant launch: the full-tile screen
+            // (or the single masked screen of the 128 tile)
             if (tile == 256) {
-                // full tiles on the persistent unmasked screen, then the partial ones
-                ScreenArgs f = a;
-                f.ntiles = nfull;
-                launch_screen(prec, tile, M_MIN, false, f, std::min<int64_t>(nfull, c->ncu), st);
                 ScreenArgs q = a;
                 q.tiles = a.tiles + nfull;
                 q.tile_min = a.tile_min + nfull;
                 q.ntiles = ntiles - nfull;
                 launch_screen(prec, tile, M_MIN, true, q, std::min<int64_t>(ntiles - nfull, c->ncu), st);
+                ScreenArgs f = a;
+                f.ntiles = nfull;
+                if (!batch_graph) hipEventRecord(c->es0, st);
+                launch_screen(prec, tile, M_MIN, false, f, std::min<int64_t>(nfull, c->ncu), st);
+                if (!batch_graph) hipEventRecord(c->es1, st);
             } else {
+                if (!batch_graph) hipEventRecord(c->es0, st);
                 launch_screen(prec, tile, M_MIN, true, a, ntiles, st);
+                if (!batch_graph) hipEventRecord(c->es1, st);
             }
-            if (!batch_graph) hipEventRecord(c->es1, st);
             unsigned long long *ubits = want_cpp ? (unsigned long long *)c->ubits.p : nullptr;
             if (want_cpp) launch_reduce_U(dprobs, a.tiles, ntiles, a.tile_min, prec, ubits, st);
             launch_select(dprobs, a.tiles, ntiles, a.tile_min, prec, ubits, (uint64_t *)c->sel.p, dcnt + C_SEL, st);
@@ -496,6 +503,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         int64_t vp = 0;
         for (auto &h : hp) vp += pairs_of(h.n, h.excl);
         c->stats.valid_pairs = vp;
+        c->stats.screen_pairs = tile == 256 ? c->nfull_pairs : vp;
         float mr = 0.f;
         for (auto &r : ro.res) mr = std::max(mr, __builtin_bit_cast(float, r.ratio_bits));
         c->stats.max_err_over_bound = mr;

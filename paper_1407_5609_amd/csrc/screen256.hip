@@ -151,53 +151,66 @@ constexpr int SG_DS_READ = 0x100;
 constexpr int WAIT_SLICE = (16 & 15) | (7 << 4) | (0 << 8) | ((16 >> 4) << 14);
 constexpr int WAIT_LGKM0 = 15 | (7 << 4) | (0 << 8) | (3 << 14);
 
-// One K slice: issue the loads of the slice three ahead into the free stage,
-// multiply this stage, then wait for the next stage and synchronise. The
-// read and written stages arrive as restrict pointers: once inlined their
-// accesses carry distinct alias scopes, so the LDS reads below do not wait for
-// the loads just issued. Loads, fragment reads and MFMAs are interleaved with
-// scheduling group barriers.
-template <int PREC, bool FIRST = false>
-__device__ __forceinline__ void slice_step(typename A2<PREC>::T (&acc)[MB256][MB256], const TileAddr &ia, int is,
-                                           int wave, int wm, int wn, int lrow, int lhalf,
-                                           const unsigned char *__restrict__ rd, unsigned char *__restrict__ wr)
+template <int PREC> using Frags = u32x4[MB256];
+
+template <int PREC>
+__device__ __forceinline__ void read_group(Frags<PREC> &fa, Frags<PREC> &fb, const unsigned char *__restrict__ st,
+                                           int g, int wm, int wn, int lrow, int lhalf)
 {
-    issue_slice(ia, is, wave, wr);
-    const unsigned char *la = rd;
-    const unsigned char *lb = rd + OPB;
-    constexpr int NG = SL / 32;  // k-groups per slice
-    u32x4 fa[NG][MB256], fb[NG][MB256];
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
+    for (int m = 0; m < MB256; ++m)
+        fa[m] = *(const u32x4 *)(st + l256::frag_lds(wm * WT256 + m * 32 + lrow, 2 * g + lhalf));
 #pragma unroll
-        for (int m = 0; m < MB256; ++m)
-            fa[g][m] = *(const u32x4 *)(la + l256::frag_lds(wm * WT256 + m * 32 + lrow, 2 * g + lhalf));
+    for (int m = 0; m < MB256; ++m)
+        fb[m] = *(const u32x4 *)(st + OPB + l256::frag_lds(wn * WT256 + m * 32 + lrow, 2 * g + lhalf));
+}
+
+template <int PREC>
+__device__ __forceinline__ void mma_group(typename A2<PREC>::T (&acc)[MB256][MB256], const Frags<PREC> &fa,
+                                          const Frags<PREC> &fb)
+{
 #pragma unroll
-        for (int m = 0; m < MB256; ++m)
-            fb[g][m] = *(const u32x4 *)(lb + l256::frag_lds(wn * WT256 + m * 32 + lrow, 2 * g + lhalf));
-    }
+    for (int a = 0; a < MB256; ++a)
 #pragma unroll
-    for (int g = 0; g < NG; ++g)
-#pragma unroll
-        for (int a = 0; a < MB256; ++a)
-#pragma unroll
-            for (int b = 0; b < MB256; ++b) {
-                if (FIRST && g == 0) acc[a][b] = typename A2<PREC>::T{};  // folds into the MFMA's zero operand
-                mma2<PREC>(acc[a][b], fa[g][a], fb[g][b]);
-            }
-    // schedule: k-group 0 reads; then per MFMA pair of k-group 0 one read of
-    // k-group 1 and one of the 8 loads; then k-group 1's MFMAs
+        for (int b = 0; b < MB256; ++b) mma2<PREC>(acc[a][b], fa[a], fb[b]);
+}
+
+// One K slice, software-pipelined across slices. On entry f0a/f0b hold k-group
+// 0 of this slice (stage `cur`). The step
+//   1. multiplies k-group 0 while it reads k-group 1 from `cur` and issues the
+//      loads of the slice three ahead into `wr` (the stage freed last step);
+//   2. waits until the next stage has landed and every wave is done reading
+//      `cur`, and synchronises;
+//   3. multiplies k-group 1 while it reads k-group 0 of the next stage `nxt`
+//      into f0a/f0b for the following step.
+// The three stages arrive as restrict pointers: once inlined their accesses
+// carry distinct alias scopes, so LDS reads never wait for the loads in flight.
+template <int PREC>
+__device__ __forceinline__ void slice_step(typename A2<PREC>::T (&acc)[MB256][MB256], Frags<PREC> &f0a,
+                                           Frags<PREC> &f0b, const TileAddr &ia, int is, int wave, int wm, int wn,
+                                           int lrow, int lhalf, const unsigned char *__restrict__ cur,
+                                           const unsigned char *__restrict__ nxt, unsigned char *__restrict__ wr)
+{
     constexpr int MPG = (PREC == P_F32 ? 4 : 1) * MB256 * MB256;  // MFMAs per k-group
-    __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 2 * MB256, 0);
+    Frags<PREC> f1a, f1b;
+    issue_slice(ia, is, wave, wr);
+    read_group<PREC>(f1a, f1b, cur, 1, wm, wn, lrow, lhalf);
+    mma_group<PREC>(acc, f0a, f0b);
 #pragma unroll
     for (int k = 0; k < 2 * MB256; ++k) {
         __builtin_amdgcn_sched_group_barrier(SG_MFMA, MPG / (2 * MB256), 0);
         __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
         __builtin_amdgcn_sched_group_barrier(SG_VMEM_READ, 1, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(SG_MFMA, MPG, 0);
     __builtin_amdgcn_s_waitcnt(WAIT_SLICE);
     __builtin_amdgcn_s_barrier();
+    read_group<PREC>(f0a, f0b, nxt, 0, wm, wn, lrow, lhalf);
+    mma_group<PREC>(acc, f1a, f1b);
+#pragma unroll
+    for (int k = 0; k < 2 * MB256; ++k) {
+        __builtin_amdgcn_sched_group_barrier(SG_DS_READ, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(SG_MFMA, MPG / (2 * MB256), 0);
+    }
 }
 
 // MASKED = false: every pair of every listed tile is admissible (the host
@@ -258,6 +271,8 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     advance();
     __builtin_amdgcn_s_waitcnt(WAIT_SLICE);
     __builtin_amdgcn_s_barrier();
+    Frags<PREC> f0a, f0b;  // k-group 0 of the next slice to multiply
+    read_group<PREC>(f0a, f0b, stage_ptr<0>(), 0, wm, wn, lrow, lhalf);
 
     while (t < count) {
         const uint64_t ent = tiles[t];
@@ -293,19 +308,23 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
             TileAddr cia = ia;
             int cis = is;
             advance();
-            slice_step<PREC>(acc, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<0>(), stage_ptr<3>());
+            slice_step<PREC>(acc, f0a, f0b, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<0>(), stage_ptr<1>(),
+                             stage_ptr<3>());
             cia = ia;
             cis = is;
             advance();
-            slice_step<PREC>(acc, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<1>(), stage_ptr<0>());
+            slice_step<PREC>(acc, f0a, f0b, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<1>(), stage_ptr<2>(),
+                             stage_ptr<0>());
             cia = ia;
             cis = is;
             advance();
-            slice_step<PREC>(acc, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<2>(), stage_ptr<1>());
+            slice_step<PREC>(acc, f0a, f0b, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<2>(), stage_ptr<3>(),
+                             stage_ptr<1>());
             cia = ia;
             cis = is;
             advance();
-            slice_step<PREC>(acc, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<3>(), stage_ptr<2>());
+            slice_step<PREC>(acc, f0a, f0b, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<3>(), stage_ptr<0>(),
+                             stage_ptr<2>());
         }
         const int64_t tn = next_valid(t + stride);
 
