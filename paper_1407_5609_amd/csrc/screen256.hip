@@ -275,6 +275,13 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     read_group<PREC>(f0a, f0b, stage_ptr<0>(), 0, wm, wn, lrow, lhalf);
 
     while (t < count) {
+        // per-lane values are rebuilt from an opaque copy of the lane index at
+        // every tile, so the compiler keeps only the lane index alive across
+        // the register-hungry epilogue instead of spilling derived offsets
+        // (whose reloads would wait behind the loads in flight)
+        int lane_t = lane;
+        asm volatile("" : "+v"(lane_t));
+        const int lrow = lane_t & 31, lhalf = lane_t >> 5;
         const uint64_t ent = tiles[t];
         const uint32_t p = tile_prob(ent);
         const c_prob &P = ((c_prob *)args.probs)[p];
@@ -288,7 +295,7 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         S *sh_t = sh_s + (tcount & 1) * (2 * T256);
         {
             const unsigned char *sb = (const unsigned char *)P.shat;
-            const uint32_t lo = (uint32_t)lane * 4;
+            const uint32_t lo = (uint32_t)lane_t * 4;
             __builtin_amdgcn_global_load_lds((g_void *)(sb + (I * T256 + wave * 64) * 4 + lo),
                                              (lds_void *)(sh_t + wave * 64), 4, 0, 0);
             __builtin_amdgcn_global_load_lds((g_void *)(sb + (J * T256 + wave * 64) * 4 + lo),
