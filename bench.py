@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp32-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (a reference launch for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU split of the tile "
@@ -116,8 +118,13 @@ def main():
         wall = time.perf_counter() - t0
         return wall / steps, float(np.mean(screen_ms)), st, exact
 
+    if args.calib_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        cp.dbg_copy(dst, src)
+        del src, dst
     ms_step, screen_ms, st, exact_bf16 = run("bf16", args.steps, args.warmup)
-    fp32_ms, fp32_screen_ms, st32, exact_fp32 = run("f32", max(1, args.fp32_steps), 1)
+    fp32 = run("f32", args.fp32_steps, 1) if args.fp32_steps > 0 else None
 
     pairs = st.valid_pairs
     value = pairs / ms_step
@@ -143,14 +150,15 @@ def main():
                      "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic,
                      "kernel": "screen256_kernel<bf16, min, full tiles>", "avg_launch_ms": screen_ms,
                      "flops_per_launch": 2.0 * d * st.screen_pairs},
-        "fp32_plain": {"value": pairs / fp32_ms, "ms_per_step": fp32_ms * 1e3,
-                       "screen_tflops": 2.0 * d * st32.screen_pairs / (fp32_screen_ms * 1e-3) / 1e12,
-                       "screen_frac_of_fp32_peak": 2.0 * d * st32.screen_pairs / (fp32_screen_ms * 1e-3) / 1e12
-                       / PEAK_FP32_TFLOPS,
-                       "speedup_bf16_vs_fp32": fp32_ms / ms_step},
-        "exact_match": bool(exact_bf16 and exact_fp32),
+        "exact_match": bool(exact_bf16 and (fp32 is None or fp32[3])),
         "screen_err_over_bound": st.max_err_over_bound,
     }
+    if fp32 is not None:
+        fp32_ms, fp32_screen_ms, st32, _ = fp32
+        tf = 2.0 * d * st32.screen_pairs / (fp32_screen_ms * 1e-3) / 1e12
+        out["fp32_plain"] = {"value": pairs / fp32_ms, "ms_per_step": fp32_ms * 1e3, "screen_tflops": tf,
+                             "screen_frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS, "tile": st32.tile,
+                             "speedup_bf16_vs_fp32": fp32_ms / ms_step}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Xh)
     print(json.dumps(out), flush=True)

@@ -107,7 +107,7 @@ typedef struct {
 } cpmi_stats;
 
 /* Create a context on HIP device `device`. tune_cache_path (nullable) names a
- * JSON file of tuned screen configurations written by the Python autotuner; if
+ * JSON file of tuned screen configurations written by cpmi_save_tune_cache; if
  * NULL or unreadable the built-in defaults are used. */
 int cpmi_create(cpmi_ctx **out, int device, const char *tune_cache_path);
 
@@ -168,6 +168,44 @@ int cpmi_last_stats(cpmi_ctx *ctx, cpmi_stats *out);
  * 128 or 256 for the matrix-core screen); 0 restores the default. Used by the
  * autotuner. Returns ERR_ARG for an unsupported value. */
 int cpmi_set_tile(cpmi_ctx *ctx, int precision, int tile);
+
+/* Autotuner result: the fastest precision tried and its fastest tile edge,
+ * and the best device time (ms, HIP events around the whole call) of every
+ * configuration tried, indexed [precision][tile 128, tile 256]; 0 where not
+ * tried. */
+typedef struct {
+    int32_t precision;
+    int32_t tile;
+    double ms[4][2];
+} cpmi_tune_result;
+
+/* Autotuner: time a closest-pair search (the screen configurations the
+ * library has: tile edge 128 or 256; with CPMI_PREC_AUTO on float32 input
+ * also FP32 against BF16 screening) on the caller's points, `reps` timed calls
+ * after one warm-up each, and record in the context the fastest tile for each
+ * precision tried and, for AUTO, the fastest precision, keyed by precision,
+ * dimension bucket (next power of two >= max(d, 64)) and size bucket
+ * (ceil(log2) of the row count of a point set with as many pairs). Later
+ * calls on problems in the same buckets use these choices; batched motifs use
+ * the bucket of their largest l and of their total pair count. Arguments as
+ * for cpmi_closest_pair; out: host. Errors: as cpmi_closest_pair, ERR_ARG for
+ * reps outside 1..1000. */
+int cpmi_autotune(cpmi_ctx *ctx, const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, int precision,
+                  void *stream, int reps, cpmi_tune_result *out);
+
+/* Write every tuned choice of the context as the JSON object that
+ * cpmi_create reads ({"bf16:k512:r18": 256, "auto:k512:r18": 2, ...}; the
+ * "auto" value is a CPMI_PREC_* code). The file is replaced atomically.
+ * Errors: ERR_ARG if the file cannot be written. */
+int cpmi_save_tune_cache(cpmi_ctx *ctx, const char *path);
+
+/* The precision and tile a call would use for float32 (CPMI_F32) or int8
+ * input of dimension d with `pairs` admissible pairs under `precision`
+ * (after tuning, the cache, or the built-in rule: tile 256 when the problem
+ * has at least four 256x256 tiles per compute unit, else 128). prec_out,
+ * tile_out: host. Does not touch the GPU. */
+int cpmi_tune_lookup(cpmi_ctx *ctx, int dtype, int precision, int64_t d, double pairs, int32_t *prec_out,
+                     int32_t *tile_out);
 
 /* Library version (major * 10000 + minor * 100 + patch). */
 int cpmi_version(void);

@@ -46,6 +46,19 @@ double cpmi_dbg_tile_bound(const float *bI, const float *bJ, int32_t kpad, int64
  * fragment read of that (row, chunk) looks}. */
 int cpmi_dbg_layout256(int wave, int q, int lane, int32_t *out4);
 
+/* Copy `bytes` (a multiple of 16) from src to dst (device, non-overlapping)
+ * with a plain vector copy kernel: a launch of known traffic (bytes read,
+ * bytes written) against which the hardware byte counters are scaled. */
+int cpmi_dbg_copy(void *dst, const void *src, int64_t bytes, void *stream);
+
+/* Host only: the tuning decisions of a context with `ncu` compute units
+ * after reading the cache file cache_in (nullable): the precision and tile a
+ * call with (dtype, precision, d, pairs) would use, as cpmi_tune_lookup. If
+ * cache_out is not NULL the loaded cache is written there as
+ * cpmi_save_tune_cache would. */
+int cpmi_dbg_tune(const char *cache_in, const char *cache_out, int ncu, int dtype, int precision, int64_t d,
+                  double pairs, int32_t *prec_out, int32_t *tile_out);
+
 #ifdef __cplusplus
 }
 #endif

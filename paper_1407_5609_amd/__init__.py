@@ -42,6 +42,15 @@ class _CStats(C.Structure):
                 ("tile", C.c_int32)]
 
 
+class _CTune(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("tile", C.c_int32), ("ms", (C.c_double * 2) * 4)]
+
+
+# Tuned choices measured on MI355X (written by `python -m paper_1407_5609_amd.autotune`);
+# a Context reads it unless another cache is named.
+DEFAULT_TUNE_CACHE = os.path.join(_HERE, "tune_gfx950.json")
+
+
 def library_path() -> str:
     return _LIB_PATH
 
@@ -66,7 +75,11 @@ def _load():
     L.cpmi_motif.argtypes = [vp, vp, i64, i64, i64, i32, dbl, vp, C.POINTER(_CPair), vp, vp, i64, C.POINTER(i64)]
     L.cpmi_motif_batch.argtypes = [vp, C.POINTER(vp), C.POINTER(i64), C.POINTER(i64), i64, i32, vp,
                                    C.POINTER(_CPair)]
+    L.cpmi_autotune.argtypes = [vp, vp, i32, i64, i64, i64, i32, vp, i32, C.POINTER(_CTune)]
+    L.cpmi_save_tune_cache.argtypes = [vp, C.c_char_p]
+    L.cpmi_tune_lookup.argtypes = [vp, i32, i32, i64, dbl, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.cpmi_dbg_mfma_probe.argtypes = [i32, vp, vp, vp, vp]
+    L.cpmi_dbg_copy.argtypes = [vp, vp, i64, vp]
     L.cpmi_dbg_znorm.argtypes = [vp, vp, i64, i64, i32, vp, vp, vp]
     return L
 
@@ -126,13 +139,15 @@ def _pair(cp: _CPair) -> Pair:
 class Context:
     """One cpmi context (device workspace, tuned tiles). Not thread-safe."""
 
-    def __init__(self, device: int | None = None, tune_cache: str | None = None):
+    def __init__(self, device: int | None = None, tune_cache: str | None = DEFAULT_TUNE_CACHE):
+        """tune_cache: JSON file of tuned choices (default: the packaged
+        MI355X cache if present); None uses the built-in rule only."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("cpmi needs a ROCm GPU; none is visible")
         self.device = torch.cuda.current_device() if device is None else int(device)
         h = C.c_void_p()
-        path = tune_cache.encode() if tune_cache else None
+        path = tune_cache.encode() if tune_cache and os.path.exists(tune_cache) else None
         rc = _lib.cpmi_create(C.byref(h), self.device, path)
         if rc != OK:
             raise CpmiError(rc, "cpmi_create failed")
@@ -164,6 +179,27 @@ class Context:
 
     def set_tile(self, precision, tile: int):
         self._check(_lib.cpmi_set_tile(self._h, _prec(precision), int(tile)))
+
+    def autotune(self, pts, precision="auto", reps: int = 3, stream=None) -> dict:
+        """Time the screen configurations on `pts` and record the fastest in
+        this context (cpmi_autotune). Returns the choice and the timings."""
+        dt, n, d, ld = self._points_args(pts)
+        out = _CTune()
+        self._check(_lib.cpmi_autotune(self._h, C.c_void_p(pts.data_ptr()), dt, n, d, ld, _prec(precision),
+                                       _stream_ptr(stream), int(reps), C.byref(out)))
+        names = {PREC_F32: "f32", PREC_BF16: "bf16", PREC_I8: "i8"}
+        ms = {f"{names[p]}/{t}": out.ms[p][k] for p in names for k, t in enumerate((128, 256)) if out.ms[p][k] > 0}
+        return {"precision": names[out.precision], "tile": out.tile, "ms": ms}
+
+    def save_tune_cache(self, path: str):
+        self._check(_lib.cpmi_save_tune_cache(self._h, path.encode()))
+
+    def tune_lookup(self, dtype: str, precision, d: int, pairs: float):
+        """(precision code, tile) a call of this shape would use."""
+        p, t = C.c_int32(), C.c_int32()
+        self._check(_lib.cpmi_tune_lookup(self._h, I8 if dtype in ("i8", "int8") else F32, _prec(precision),
+                                          int(d), float(pairs), C.byref(p), C.byref(t)))
+        return int(p.value), int(t.value)
 
     @staticmethod
     def _points_args(pts):
@@ -292,6 +328,17 @@ def dbg_mfma_probe(precision, A, B, C_out, stream=None):
                                   C.c_void_p(C_out.data_ptr()), _stream_ptr(stream))
     if rc != OK:
         raise CpmiError(rc, "mfma probe failed")
+
+
+def dbg_copy(dst, src, stream=None):
+    """Plain device copy of src into dst (same byte size, a multiple of 16):
+    a launch of known traffic for scaling hardware byte counters."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("dbg_copy needs contiguous tensors of equal byte size")
+    rc = _lib.cpmi_dbg_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nb, _stream_ptr(stream))
+    if rc != OK:
+        raise CpmiError(rc, "copy failed")
 
 
 _default = None

@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/cpmi.h"
@@ -48,6 +49,16 @@ struct HostProb {
     size_t xs_off = 0, sh_off = 0, bm_off = 0, mu_off = 0;
 };
 
+// One autotuner decision: for screens of precision `prec` (P_F32, P_BF16,
+// P_I8; 0 = the precision chosen for CPMI_PREC_AUTO on float input) whose
+// dimension falls in K bucket `kb` (next power of two >= max(d, 64)) and whose
+// size falls in row bucket `rb` (ceil(log2) of the row count, or of the row
+// count of a single problem with as many pairs for a batch), `value` is the
+// tile edge (128 or 256), or the precision for prec = 0.
+struct TuneEntry {
+    int prec, kb, rb, value;
+};
+
 constexpr int NCNT = 4;  // counters: radius candidates, pair candidates, selected tiles, radius pairs
 enum { C_R = 0, C_U = 1, C_SEL = 2, C_OUT = 3 };
 
@@ -58,7 +69,7 @@ struct cpmi_ctx {
     std::string err;
     cpmi_stats stats{};
     int tile_override[4] = {0, 0, 0, 0};
-    std::vector<std::pair<std::string, int>> tuned;  // ("bf16:k512", tile)
+    std::vector<TuneEntry> tuned;  // autotuner results (cache file and cpmi_autotune)
 
     DevBuf xs, shat, bmax, musg, probs, jobs, tiles, tile_min, sel, candR, candU, cand_d2, keys, vals, cnt, ubits, res;
     uint32_t capR = 1u << 20, capU = 1u << 18, capOut = 1u << 20;
@@ -149,24 +160,74 @@ int32_t kpad_for(int prec, int64_t d, int tile)
 
 const char *prec_name(int prec) { return prec == P_F32 ? "f32" : (prec == P_BF16 ? "bf16" : "i8"); }
 
-int kbucket(int64_t kpad)
+int kbucket(int64_t d)
 {
     int b = 64;
-    while (b < kpad && b < 8192) b <<= 1;
+    while (b < d && b < (1 << 20)) b <<= 1;
     return b;
 }
 
-int pick_tile(cpmi_ctx *c, int prec, int64_t kpad)
+// Row bucket of a problem with `pairs` admissible pairs: ceil(log2) of the row
+// count of a single point set with as many pairs.
+int rbucket(double pairs)
 {
-    if (c->tile_override[prec]) return c->tile_override[prec];
-    char key[64];
-    snprintf(key, sizeof key, "%s:k%d", prec_name(prec), kbucket(kpad));
-    for (auto &kv : c->tuned)
-        if (kv.first == key) return kv.second;
-    return 256;
+    // n(n-1)/2 = pairs  <=>  n = 1/2 + sqrt(1/4 + 2 pairs)
+    const double rows = 0.5 + std::sqrt(0.25 + 2.0 * std::max(pairs, 1.0));
+    int r = 0;
+    while ((double)(1ll << r) < rows * (1.0 - 1e-12) && r < 40) ++r;
+    return std::max(r, 8);
 }
 
-// Minimal reader of the tuner's JSON object {"bf16:k512": 256, ...}.
+int64_t pairs_of(int64_t n, int64_t excl)
+{
+    const int64_t m = n - excl;
+    return m > 0 ? m * (m + 1) / 2 : 0;
+}
+
+// Tuned value for (prec, kb, rb): the exact entry, else the entry of the
+// nearest row bucket with the same precision and K bucket (ties: the larger
+// bucket), else -1.
+int tuned_value(const cpmi_ctx *c, int prec, int kb, int rb)
+{
+    int best = -1, dist = 1 << 30, brb = -1;
+    for (const TuneEntry &e : c->tuned) {
+        if (e.prec != prec || e.kb != kb) continue;
+        const int dd = std::abs(e.rb - rb);
+        if (dd < dist || (dd == dist && e.rb > brb)) {
+            best = e.value;
+            dist = dd;
+            brb = e.rb;
+        }
+    }
+    return best;
+}
+
+void set_tuned(cpmi_ctx *c, int prec, int kb, int rb, int value)
+{
+    for (TuneEntry &e : c->tuned)
+        if (e.prec == prec && e.kb == kb && e.rb == rb) {
+            e.value = value;
+            return;
+        }
+    c->tuned.push_back(TuneEntry{prec, kb, rb, value});
+}
+
+// Screen tile for a problem of dimension d (the largest, for a batch) and
+// `pairs` admissible pairs: the override, else the tuned choice, else 256 when
+// the 256-tiles are enough to keep every CU busy several times over and 128
+// otherwise.
+int pick_tile(cpmi_ctx *c, int prec, int64_t d, double pairs)
+{
+    if (c->tile_override[prec]) return c->tile_override[prec];
+    const int v = tuned_value(c, prec, kbucket(d), rbucket(pairs));
+    if (v == 128 || v == 256) return v;
+    return pairs / (256.0 * 256.0) >= 4.0 * c->ncu ? 256 : 128;
+}
+
+const char *tune_name(int prec) { return prec == 0 ? "auto" : prec_name(prec); }
+
+// Reader of the tuner's JSON object {"bf16:k512:r18": 256, "auto:k512:r18": 2, ...}.
+// Unknown or malformed entries are ignored.
 void load_tune_cache(cpmi_ctx *c, const char *path)
 {
     if (!path) return;
@@ -181,21 +242,23 @@ void load_tune_cache(cpmi_ctx *c, const char *path)
     while ((pos = s.find('"', pos)) != std::string::npos) {
         size_t e = s.find('"', pos + 1);
         if (e == std::string::npos) break;
-        std::string key = s.substr(pos + 1, e - pos - 1);
-        size_t colon = s.find(':', e);
-        if (colon == std::string::npos) break;
-        char *end = nullptr;
-        long v = strtol(s.c_str() + colon + 1, &end, 10);
-        if (end != s.c_str() + colon + 1 && (v == 128 || v == 256) && key.find(":k") != std::string::npos)
-            c->tuned.emplace_back(key, (int)v);
+        const std::string key = s.substr(pos + 1, e - pos - 1);
         pos = e + 1;
+        size_t colon = s.find_first_not_of(" \t\r\n", e + 1);
+        if (colon == std::string::npos || s[colon] != ':') continue;
+        char *end = nullptr;
+        const long v = strtol(s.c_str() + colon + 1, &end, 10);
+        if (end == s.c_str() + colon + 1) continue;
+        char name[16] = {0};
+        int kb = 0, rb = 0;
+        if (sscanf(key.c_str(), "%15[a-z0-9]:k%d:r%d", name, &kb, &rb) != 3) continue;
+        int prec = -1;
+        for (int p = 0; p <= 3; ++p)
+            if (!strcmp(name, tune_name(p))) prec = p;
+        if (prec < 0 || kb < 64 || rb < 0 || rb > 40) continue;
+        if (prec == 0 ? (v != P_F32 && v != P_BF16) : (v != 128 && v != 256)) continue;
+        set_tuned(c, prec, kb, rb, (int)v);
     }
-}
-
-int64_t pairs_of(int64_t n, int64_t excl)
-{
-    const int64_t m = n - excl;
-    return m > 0 ? m * (m + 1) / 2 : 0;
 }
 
 // Tile list: upper-triangle tiles holding at least one admissible pair. The
@@ -573,13 +636,19 @@ int finish_frnn(cpmi_ctx *c, uint32_t count, hipStream_t st, int64_t *pairs, dou
     return CPMI_OK;
 }
 
-int resolve_prec(cpmi_ctx *c, int dtype, int precision)
+// Screen precision of a call; AUTO on float input takes the tuned choice for
+// the shape (dimension d, `pairs` admissible pairs), else BF16.
+int resolve_prec(cpmi_ctx *c, int dtype, int precision, int64_t d, double pairs)
 {
     if (dtype == CPMI_I8) {
         if (precision == CPMI_PREC_AUTO || precision == CPMI_PREC_I8) return P_I8;
         return fail(c, CPMI_ERR_ARG, "int8 points take CPMI_PREC_I8 (or AUTO)");
     }
-    if (precision == CPMI_PREC_AUTO || precision == CPMI_PREC_BF16) return P_BF16;
+    if (precision == CPMI_PREC_AUTO) {
+        const int v = tuned_value(c, 0, kbucket(d), rbucket(pairs));
+        return v == P_F32 ? P_F32 : P_BF16;
+    }
+    if (precision == CPMI_PREC_BF16) return P_BF16;
     if (precision == CPMI_PREC_F32) return P_F32;
     return fail(c, CPMI_ERR_ARG, "unknown precision %d for float32 input", precision);
 }
@@ -682,7 +751,8 @@ int cpmi_points(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d, i
         if (best) best->status = CPMI_ERR_NOPAIR, best->i = best->j = -1;
         return fail(c, CPMI_ERR_NOPAIR, "fewer than two points");
     }
-    const int prec = resolve_prec(c, dtype, precision);
+    const double npairs = (double)pairs_of(n, 1);
+    const int prec = resolve_prec(c, dtype, precision, d, npairs);
     if (prec < 0) return prec;
     int rc;
     if ((rc = set_device(c))) return rc;
@@ -695,7 +765,7 @@ int cpmi_points(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d, i
     hp[0].src = pts;
     hp[0].src_i8 = dtype == CPMI_I8;
     hp[0].r2 = want_frnn ? R2 : -1.0;
-    const int tile = pick_tile(c, prec, kpad_for(prec, d, 128));
+    const int tile = pick_tile(c, prec, d, npairs);
     RunOut ro;
     if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro))) return rc;
     if ((rc = flags_error(c, ro.res[0].flags))) return rc;
@@ -750,7 +820,8 @@ int cpmi_motif(cpmi_ctx *c, const float *series, int64_t len, int64_t ell, int64
         if (best) best->status = CPMI_ERR_NOPAIR, best->i = best->j = -1;
         return fail(c, CPMI_ERR_NOPAIR, "no admissible window pair (windows=%lld, exclusion=%lld)", (long long)N, (long long)excl);
     }
-    const int prec = resolve_prec(c, CPMI_F32, precision);
+    const double npairs = (double)pairs_of(N, excl);
+    const int prec = resolve_prec(c, CPMI_F32, precision, ell, npairs);
     int rc;
     if ((rc = set_device(c))) return rc;
     hipStream_t st = (hipStream_t)stream;
@@ -763,7 +834,7 @@ int cpmi_motif(cpmi_ctx *c, const float *series, int64_t len, int64_t ell, int64
     hp[0].src = series;
     hp[0].len = len;
     hp[0].r2 = want_frnn ? R2 : -1.0;
-    const int tile = pick_tile(c, prec, kpad_for(prec, ell, 128));
+    const int tile = pick_tile(c, prec, ell, npairs);
     RunOut ro;
     if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro))) return rc;
     if ((rc = flags_error(c, ro.res[0].flags))) return rc;
@@ -785,10 +856,10 @@ int cpmi_motif_batch(cpmi_ctx *c, const float *const *series, const int64_t *len
     if (nseries > (1 << 20)) return fail(c, CPMI_ERR_ARG, "at most 2^20 series per batch");
     if (precision != CPMI_PREC_AUTO && precision != CPMI_PREC_F32 && precision != CPMI_PREC_BF16)
         return fail(c, CPMI_ERR_ARG, "motif precision must be AUTO, F32 or BF16");
-    const int prec = resolve_prec(c, CPMI_F32, precision);
     std::vector<HostProb> hp;
     std::vector<int64_t> idx;  // batch position of each problem
-    int64_t kmax = 0;
+    int64_t ellmax = 0;
+    double npairs = 0.0;
     for (int64_t s = 0; s < nseries; ++s) {
         memset(&best[s], 0, sizeof best[s]);
         best[s].i = best[s].j = -1;
@@ -810,7 +881,8 @@ int cpmi_motif_batch(cpmi_ctx *c, const float *const *series, const int64_t *len
         h.len = L;
         hp.push_back(h);
         idx.push_back(s);
-        kmax = std::max<int64_t>(kmax, kpad_for(prec, ell, 128));
+        ellmax = std::max<int64_t>(ellmax, ell);
+        npairs += (double)pairs_of(N, ell);
     }
     if (hp.empty()) return CPMI_OK;
     int rc;
@@ -823,7 +895,8 @@ int cpmi_motif_batch(cpmi_ctx *c, const float *const *series, const int64_t *len
         HIPCHK(c, hipStreamWaitEvent(c->own, c->ev0, 0));
         st = c->own;
     }
-    const int tile = pick_tile(c, prec, kmax);
+    const int prec = resolve_prec(c, CPMI_F32, precision, ellmax, npairs);
+    const int tile = pick_tile(c, prec, ellmax, npairs);
     RunOut ro;
     if ((rc = run_search(c, hp, prec, tile, true, false, st, true, ro))) return rc;
     for (size_t p = 0; p < hp.size(); ++p) {
@@ -836,6 +909,92 @@ int cpmi_motif_batch(cpmi_ctx *c, const float *const *series, const int64_t *len
         fill_pair(ro.res[p], &b);
     }
     c->err.clear();
+    return CPMI_OK;
+}
+
+int cpmi_autotune(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, int precision,
+                  void *stream, int reps, cpmi_tune_result *out)
+{
+    if (!c) return CPMI_ERR_ARG;
+    if (!out || reps < 1 || reps > 1000) return fail(c, CPMI_ERR_ARG, "autotune needs out and 1 <= reps <= 1000");
+    memset(out, 0, sizeof *out);
+    if (n < 2 || d < 1 || ld < d || !pts) return fail(c, CPMI_ERR_ARG, "autotune needs n >= 2 points");
+    std::vector<int> precs;
+    if (dtype == CPMI_I8) {
+        if (precision != CPMI_PREC_AUTO && precision != CPMI_PREC_I8)
+            return fail(c, CPMI_ERR_ARG, "int8 points take CPMI_PREC_I8 (or AUTO)");
+        precs.push_back(P_I8);
+    } else if (dtype == CPMI_F32) {
+        if (precision == CPMI_PREC_AUTO) precs = {P_F32, P_BF16};
+        else if (precision == CPMI_PREC_F32 || precision == CPMI_PREC_BF16) precs.push_back(precision);
+        else return fail(c, CPMI_ERR_ARG, "unknown precision %d for float32 input", precision);
+    } else {
+        return fail(c, CPMI_ERR_ARG, "unknown dtype %d", dtype);
+    }
+    const int kb = kbucket(d), rb = rbucket((double)pairs_of(n, 1));
+    const int tiles[2] = {128, 256};
+    double best_all = 0.0;
+    for (int p : precs) {
+        const int saved = c->tile_override[p];
+        double best = 0.0;
+        int best_tile = 0;
+        for (int ti = 0; ti < 2; ++ti) {
+            c->tile_override[p] = tiles[ti];
+            double tmin = 0.0;
+            for (int r = 0; r <= reps; ++r) {  // the first call warms up
+                cpmi_pair bp;
+                const int rc = cpmi_points(c, pts, dtype, n, d, ld, p, -1.0, stream, &bp, nullptr, nullptr, 0,
+                                           nullptr);
+                if (rc) {
+                    c->tile_override[p] = saved;
+                    return rc;
+                }
+                if (r > 0 && (tmin == 0.0 || c->stats.kernel_ms < tmin)) tmin = c->stats.kernel_ms;
+            }
+            out->ms[p][ti] = tmin;
+            if (best_tile == 0 || tmin < best) best = tmin, best_tile = tiles[ti];
+        }
+        c->tile_override[p] = saved;
+        set_tuned(c, p, kb, rb, best_tile);
+        if (out->precision == 0 || best < best_all) {
+            best_all = best;
+            out->precision = p;
+            out->tile = best_tile;
+        }
+    }
+    if (precs.size() > 1) set_tuned(c, 0, kb, rb, out->precision);
+    c->err.clear();
+    return CPMI_OK;
+}
+
+int cpmi_save_tune_cache(cpmi_ctx *c, const char *path)
+{
+    if (!c) return CPMI_ERR_ARG;
+    if (!path) return fail(c, CPMI_ERR_ARG, "path is NULL");
+    std::vector<TuneEntry> t = c->tuned;
+    std::sort(t.begin(), t.end(), [](const TuneEntry &a, const TuneEntry &b) {
+        return std::make_tuple(a.prec, a.kb, a.rb) < std::make_tuple(b.prec, b.kb, b.rb);
+    });
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return fail(c, CPMI_ERR_ARG, "cannot write %s", tmp.c_str());
+    fprintf(f, "{");
+    for (size_t k = 0; k < t.size(); ++k)
+        fprintf(f, "%s\n \"%s:k%d:r%d\": %d", k ? "," : "", tune_name(t[k].prec), t[k].kb, t[k].rb, t[k].value);
+    fprintf(f, "\n}\n");
+    const bool ok = fclose(f) == 0;
+    if (!ok || rename(tmp.c_str(), path) != 0) return fail(c, CPMI_ERR_ARG, "cannot write %s", path);
+    return CPMI_OK;
+}
+
+int cpmi_tune_lookup(cpmi_ctx *c, int dtype, int precision, int64_t d, double pairs, int32_t *prec_out,
+                     int32_t *tile_out)
+{
+    if (!c || !prec_out || !tile_out) return CPMI_ERR_ARG;
+    const int p = resolve_prec(c, dtype, precision, d, pairs);
+    if (p < 0) return p;
+    *prec_out = p;
+    *tile_out = pick_tile(c, p, d, pairs);
     return CPMI_OK;
 }
 
@@ -852,6 +1011,30 @@ int64_t cpmi_dbg_tile_list(int64_t n, int64_t excl, int tile, uint64_t *out, int
     build_tiles(hp, tile, tl, &nf);
     for (int64_t k = 0; k < (int64_t)tl.size() && k < cap; ++k) out[k] = tl[k];
     return (int64_t)tl.size();
+}
+
+int cpmi_dbg_copy(void *dst, const void *src, int64_t bytes, void *stream)
+{
+    if (!dst || !src || bytes < 0 || bytes % 16) return CPMI_ERR_ARG;
+    const char *a = (const char *)src, *b = (const char *)dst;
+    if (a < b + bytes && b < a + bytes) return CPMI_ERR_ARG;
+    launch_calib_copy(src, dst, bytes / 16, (hipStream_t)stream);
+    if (hipGetLastError() != hipSuccess) return CPMI_ERR_HIP;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return CPMI_ERR_HIP;
+    return CPMI_OK;
+}
+
+int cpmi_dbg_tune(const char *cache_in, const char *cache_out, int ncu, int dtype, int precision, int64_t d,
+                  double pairs, int32_t *prec_out, int32_t *tile_out)
+{
+    if (ncu < 1) return CPMI_ERR_ARG;
+    cpmi_ctx c;  // host state only: no stream, event or buffer is created
+    c.ncu = ncu;
+    load_tune_cache(&c, cache_in);
+    int rc = CPMI_OK;
+    if (cache_out) rc = cpmi_save_tune_cache(&c, cache_out);
+    if (rc == CPMI_OK) rc = cpmi_tune_lookup(&c, dtype, precision, d, pairs, prec_out, tile_out);
+    return rc;
 }
 
 int cpmi_dbg_layout256(int wave, int q, int lane, int32_t *out4)
@@ -883,7 +1066,7 @@ int cpmi_dbg_znorm(cpmi_ctx *c, const float *series, int64_t len, int64_t ell, i
                    double *sigma, void *stream)
 {
     if (!c || !series || !mu || !sigma || ell < 2 || len < ell) return CPMI_ERR_ARG;
-    const int prec = resolve_prec(c, CPMI_F32, precision);
+    const int prec = resolve_prec(c, CPMI_F32, precision, ell, (double)pairs_of(len - ell + 1, ell));
     if (prec < 0) return prec;
     int rc;
     if ((rc = set_device(c))) return rc;

@@ -102,6 +102,7 @@ struct SeriesJob {
 void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st);
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st);
 void launch_reset_res(ResDev *r, int64_t n, hipStream_t st);
+void launch_calib_copy(const void *src, void *dst, int64_t n16, hipStream_t st);
 
 // Row preparation of points (float32 or int8): screen operand, row scalars,
 // per-block maxima (bmax must be zero on entry), flags.

@@ -70,6 +70,16 @@ __global__ void reset_res_kernel(ResDev *r, int64_t n)
     }
 }
 
+// Plain copy of n16 16-byte words; a reference of known traffic for the
+// hardware byte counters (each word is read once and written once).
+typedef unsigned int cu32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void calib_copy_kernel(const cu32x4 *__restrict__ src, cu32x4 *__restrict__ dst,
+                                                         int64_t n16)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 static unsigned grid_for(int64_t n, int per)
 {
     int64_t g = (n + per - 1) / per;
@@ -85,6 +95,12 @@ void launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t st)
 void launch_fill_u64(uint64_t *p, uint64_t v, int64_t n, hipStream_t st)
 {
     if (n > 0) hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, p, v, n);
+}
+void launch_calib_copy(const void *src, void *dst, int64_t n16, hipStream_t st)
+{
+    if (n16 > 0)
+        hipLaunchKernelGGL(calib_copy_kernel, dim3(grid_for(n16, 256 * 8)), dim3(256), 0, st, (const cu32x4 *)src,
+                           (cu32x4 *)dst, n16);
 }
 void launch_reset_res(ResDev *r, int64_t n, hipStream_t st)
 {

@@ -217,3 +217,74 @@ def test_layout256_covers_the_slice_and_reads_what_was_written(lib):
             assert len(banks) == 16
     assert lib.cpmi_dbg_layout256(4, 0, 0, out.ctypes.data) == -1
     assert lib.cpmi_dbg_layout256(0, NQ, 0, out.ctypes.data) == -1
+
+
+# --------------------------------------------------------------------------
+# tune cache: parsing, lookup, defaults (host only)
+# --------------------------------------------------------------------------
+
+def _tune(lib, cache_in, dtype, prec, d, pairs, ncu=256, cache_out=None):
+    lib.cpmi_dbg_tune.argtypes = [C.c_char_p, C.c_char_p, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_double,
+                                  C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    p, t = C.c_int32(-9), C.c_int32(-9)
+    rc = lib.cpmi_dbg_tune(cache_in.encode() if cache_in else None, cache_out.encode() if cache_out else None,
+                           ncu, dtype, prec, d, pairs, C.byref(p), C.byref(t))
+    return rc, p.value, t.value
+
+
+def _pairs(n):
+    return n * (n - 1) / 2
+
+
+def test_tune_defaults_without_a_cache(lib):
+    F32, I8 = 0, 1
+    # AUTO on float input screens in BF16; int8 in INT8
+    assert _tune(lib, None, F32, 0, 512, _pairs(262144)) == (0, 2, 256)
+    assert _tune(lib, None, I8, 0, 4096, _pairs(100000)) == (0, 3, 256)
+    assert _tune(lib, None, F32, 1, 64, _pairs(262144)) == (0, 1, 256)
+    # small problems (fewer than four 256-tiles per compute unit) take 128
+    assert _tune(lib, None, F32, 0, 64, _pairs(4096)) == (0, 2, 128)
+    # threshold: 4 * ncu tiles of 256 x 256 pairs
+    n = int((2 * 4 * 256 * 65536) ** 0.5) + 2
+    assert _tune(lib, None, F32, 2, 64, _pairs(n))[2] == 256
+    assert _tune(lib, None, F32, 2, 64, _pairs(n), ncu=1024)[2] == 128
+    # int8 points take only INT8 (or AUTO)
+    assert _tune(lib, None, I8, 2, 64, 100.0)[0] == -1
+
+
+def test_tune_cache_lookup_and_round_trip(lib, tmp_path):
+    F32 = 0
+    cache = tmp_path / "tune.json"
+    cache.write_text('{"bf16:k512:r18": 128, "bf16:k512:r12": 256, "auto:k512:r18": 1,\n'
+                     ' "f32:k64:r12": 128, "bogus:k64:r12": 256, "bf16:k512:r16": 77, "i8:k4096:r17": 128,\n'
+                     ' "bf16:k512": 256, "auto:k64:r12": 5}\n')
+    c = str(cache)
+    # exact bucket
+    assert _tune(lib, c, F32, 2, 512, _pairs(262144)) == (0, 2, 128)
+    # AUTO takes the tuned precision (FP32 here) and that precision's tile (none tuned: default rule)
+    assert _tune(lib, c, F32, 0, 300, _pairs(262144)) == (0, 1, 256)
+    # nearest row bucket (the r16 entry has an invalid tile and is ignored)
+    assert _tune(lib, c, F32, 2, 512, _pairs(1 << 14)) == (0, 2, 256)      # r14: r12 nearer
+    assert _tune(lib, c, F32, 2, 512, _pairs(1 << 20)) == (0, 2, 128)      # r20: r18 nearer
+    # equal distance goes to the larger bucket: r15 is 3 from r12 and from r18
+    assert _tune(lib, c, F32, 2, 512, _pairs(1 << 15)) == (0, 2, 128)
+    # the size bucket of n points is ceil(log2(n))
+    assert _tune(lib, c, F32, 2, 512, _pairs((1 << 12) + 1)) == (0, 2, 256)  # r13: r12 nearer
+    assert _tune(lib, c, F32, 2, 512, _pairs((1 << 12))) == (0, 2, 256)
+    # other K bucket: default rule
+    assert _tune(lib, c, F32, 2, 1024, _pairs(1 << 20)) == (0, 2, 256)
+    # invalid AUTO value ignored: BF16
+    assert _tune(lib, c, F32, 0, 64, _pairs(4096))[1] == 2
+    assert _tune(lib, c, 1, 3, 4096, _pairs(100000)) == (0, 3, 128)
+    # round trip keeps exactly the valid entries
+    out = tmp_path / "out.json"
+    assert _tune(lib, c, F32, 2, 512, 10.0, cache_out=str(out))[0] == 0
+    import json
+    got = json.loads(out.read_text())
+    assert got == {"auto:k512:r18": 1, "f32:k64:r12": 128, "bf16:k512:r12": 256, "bf16:k512:r18": 128,
+                   "i8:k4096:r17": 128}
+    out2 = tmp_path / "out2.json"
+    assert _tune(lib, str(out), F32, 2, 512, 10.0, cache_out=str(out2))[0] == 0
+    assert out2.read_text() == out.read_text()
+    # unwritable destination is an argument error
+    assert _tune(lib, c, F32, 2, 512, 10.0, cache_out=str(tmp_path / "no" / "dir.json"))[0] == -1

@@ -311,3 +311,53 @@ def test_repeat_calls_are_deterministic(ctx, torch_dev):
         best, (p, d) = ctx.points(t, R2=c["R2"], precision="bf16")
         outs.append((best.i, best.j, best.d2, p.cpu().numpy().tobytes(), d.cpu().numpy().tobytes()))
     assert outs[0] == outs[1] == outs[2]
+
+
+# ---------------------------------------------------------------------------
+# autotuner and the traffic-calibration copy
+# ---------------------------------------------------------------------------
+
+def test_autotune_records_choices_and_answers_stay_exact(torch_dev, tmp_path):
+    import paper_1407_5609_amd as cp
+    c = cp.Context(0, tune_cache=None)
+    try:
+        rng = np.random.default_rng(77)
+        X, plant = W.planted_gaussian_points(rng, 3000, 96, 1e-3)
+        t = _dev(X, torch_dev)
+        r = c.autotune(t, "auto", reps=1)
+        assert set(r["ms"]) == {"f32/128", "f32/256", "bf16/128", "bf16/256"}
+        assert all(v > 0 for v in r["ms"].values())
+        best_key = f'{r["precision"]}/{r["tile"]}'
+        assert r["ms"][best_key] == min(r["ms"].values())
+        # later AUTO calls of this shape use the recorded choice, and stay exact
+        pairs = 3000 * 2999 / 2
+        p, tile = c.tune_lookup("f32", "auto", 96, pairs)
+        assert ({1: "f32", 2: "bf16"}[p], tile) == (r["precision"], r["tile"])
+        best = c.closest_pair(t, precision="auto")
+        st = c.stats()
+        assert (st.precision, st.tile) == (p, tile)
+        _check_pair(best, oracle.closest_pair(X))
+        # the saved cache reproduces the choice in a new context
+        path = str(tmp_path / "tune.json")
+        c.save_tune_cache(path)
+        c2 = cp.Context(0, tune_cache=path)
+        assert c2.tune_lookup("f32", "auto", 96, pairs) == (p, tile)
+        c2.close()
+        # int8 tunes the INT8 screen only
+        Xi = rng.integers(0, 3, (1200, 200)).astype(np.int8)
+        ri = c.autotune(_dev(Xi, torch_dev), "auto", reps=1)
+        assert ri["precision"] == "i8" and set(ri["ms"]) == {"i8/128", "i8/256"}
+    finally:
+        c.close()
+
+
+def test_calibration_copy_moves_every_byte(torch_dev):
+    import torch
+
+    import paper_1407_5609_amd as cp
+    src = torch.arange((1 << 20) + 4, dtype=torch.int32, device=torch_dev)
+    dst = torch.full_like(src, -1)
+    cp.dbg_copy(dst, src)
+    assert torch.equal(dst, src)
+    with pytest.raises(ValueError):
+        cp.dbg_copy(dst[:-1], src)

@@ -193,6 +193,27 @@ def test_against_scipy_pdist():
     np.testing.assert_allclose(d2, flat[sel], rtol=1e-12)
 
 
+def test_nearest_neighbour_against_scipy_and_duplicates():
+    """Per-point nearest-neighbour squared distance (used to derive the
+    mixture workload's radius): scipy's FP64 distances give the same minimum
+    per row, duplicated rows give exactly 0, and a point's own distance is
+    never taken."""
+    rng = np.random.default_rng(5)
+    X, _ = W.mixture_points(rng, 700, 48)
+    X[10] = X[300]                                        # an exact duplicate
+    nn = oracle.nearest_neighbour_d2(X)
+    ref = ssd.squareform(ssd.pdist(X.astype(np.float64), "sqeuclidean"))
+    np.fill_diagonal(ref, np.inf)
+    np.testing.assert_allclose(nn, ref.min(axis=1), rtol=1e-12, atol=0)
+    assert nn[10] == 0.0 and nn[300] == 0.0
+    assert np.all(nn[np.arange(700) != 10][:299] > 0)
+    # a single point apart from the rest has its own nearest neighbour, not itself
+    Y = np.zeros((3, 4), np.float32)
+    Y[1, 0] = 1.0
+    Y[2, 0] = 3.0
+    assert oracle.nearest_neighbour_d2(Y).tolist() == [1.0, 1.0, 4.0]
+
+
 # --------------------------------------------------------------------------
 # planted answers (known by construction)
 # --------------------------------------------------------------------------
