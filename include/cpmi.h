@@ -108,7 +108,9 @@ typedef struct {
 
 /* Create a context on HIP device `device`. tune_cache_path (nullable) names a
  * JSON file of tuned screen configurations written by cpmi_save_tune_cache; if
- * NULL or unreadable the built-in defaults are used. */
+ * NULL or unreadable the built-in defaults are used. *out: host. Errors:
+ * ERR_ARG (out NULL, no such device), ERR_HIP (the HIP runtime could not
+ * enumerate devices or create the context's stream and events). */
 int cpmi_create(cpmi_ctx **out, int device, const char *tune_cache_path);
 
 /* Release the context and its device workspace. NULL is accepted. */

@@ -59,6 +59,10 @@ def _load():
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"{_LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
                           " (hipcc, gfx950); there is no CPU fallback")
+    # torch's HIP runtime must be the process's runtime (the library resolves
+    # libamdhip64.so.7 to whichever copy is loaded first), and torch must be the
+    # first to initialise the device (see Context)
+    import torch  # noqa: F401
     L = C.CDLL(_LIB_PATH)
     vp, i64, dbl, i32 = C.c_void_p, C.c_int64, C.c_double, C.c_int
     L.cpmi_create.argtypes = [C.POINTER(vp), i32, C.c_char_p]
@@ -146,11 +150,14 @@ class Context:
         if not torch.cuda.is_available():
             raise RuntimeError("cpmi needs a ROCm GPU; none is visible")
         self.device = torch.cuda.current_device() if device is None else int(device)
+        # the library shares torch's HIP runtime; let torch initialise the device first
+        torch.cuda.set_device(self.device)
         h = C.c_void_p()
         path = tune_cache.encode() if tune_cache and os.path.exists(tune_cache) else None
         rc = _lib.cpmi_create(C.byref(h), self.device, path)
         if rc != OK:
-            raise CpmiError(rc, "cpmi_create failed")
+            raise CpmiError(rc, f"cpmi_create failed on device {self.device} "
+                                f"(torch sees {torch.cuda.device_count()} devices)")
         self._h = h
 
     def close(self):

@@ -673,7 +673,8 @@ int cpmi_create(cpmi_ctx **out, int device, const char *tune_cache_path)
     if (!out) return CPMI_ERR_ARG;
     *out = nullptr;
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return CPMI_ERR_ARG;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) return CPMI_ERR_HIP;
+    if (device < 0 || device >= ndev) return CPMI_ERR_ARG;
     cpmi_ctx *c = new cpmi_ctx();
     c->device = device;
     if (hipSetDevice(device) != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
