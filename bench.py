@@ -94,6 +94,10 @@ def main():
     want_pairs = np.array(g["frnn"]["pairs"], dtype=np.int64).reshape(-1, 2)
     want_d2 = np.array([float.fromhex(v) for v in g["frnn"]["d2"]])
 
+    def note(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    note("generating the mixture workload")
     c = W.cfg_mixture()
     Xh = c["X"]
     n, d = Xh.shape
@@ -123,7 +127,9 @@ def main():
         dst = torch.empty_like(src)
         cp.dbg_copy(dst, src)
         del src, dst
+    note("timing the BF16-screened path")
     ms_step, screen_ms, st, exact_bf16 = run("bf16", args.steps, args.warmup)
+    note(f"BF16: {ms_step * 1e3:.2f} ms/step; timing the plain FP32 path")
     fp32 = run("f32", args.fp32_steps, 1) if args.fp32_steps > 0 else None
 
     pairs = st.valid_pairs
@@ -160,6 +166,7 @@ def main():
                              "screen_frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS, "tile": st32.tile,
                              "speedup_bf16_vs_fp32": fp32_ms / ms_step}
     if not args.no_cpu_baseline:
+        note("timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(Xh)
     print(json.dumps(out), flush=True)
 

@@ -1,0 +1,109 @@
+"""GPU parity at the workloads' full sizes, in the configuration the benchmark
+times (a context with the tuned tile choices).
+
+The closest pair and radius pairs must equal the oracle's stored answers
+bit for bit (tests/golden/, written by make_golden.py from the oracle only).
+Where the oracle cannot afford the whole workload (the 512-series batch), it
+checks a seeded sample of series whole and every other series one output at a
+time: the reported pair is admissible, its squared distance is the oracle's
+canonical value for that pair, and it is no larger than the oracle's value for
+the planted pair (an admissible pair, so an upper bound of the minimum).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch  # noqa: F401
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests need an MI355X")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    import paper_1407_5609_amd as cp
+    c = cp.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _golden(name):
+    return json.load(open(os.path.join(GOLDEN, name)))
+
+
+def _want(g):
+    pair = (g["closest_pair"]["i"], g["closest_pair"]["j"], float.fromhex(g["closest_pair"]["d2"]))
+    pairs = np.array(g["frnn"]["pairs"], dtype=np.int64).reshape(-1, 2)
+    d2 = np.array([float.fromhex(v) for v in g["frnn"]["d2"]])
+    return pair, pairs, d2
+
+
+def test_mixture_full_size_golden(ctx, torch_dev):
+    g = _golden("mixture_n262144_d512.json")
+    want_pair, want_pairs, want_d2 = _want(g)
+    c = W.cfg_mixture()
+    X = c["X"]
+    t = _dev(X, torch_dev)
+    R2 = float.fromhex(g["R2"])
+    for prec in ("bf16", "f32"):
+        best, (p, d) = ctx.points(t, R2=R2, precision=prec)
+        assert (best.i, best.j, best.d2) == want_pair, (prec, best)
+        assert np.array_equal(p.cpu().numpy(), want_pairs)
+        assert np.array_equal(d.cpu().numpy(), want_d2)
+        st = ctx.stats()
+        assert st.valid_pairs == W.valid_pairs_points(X.shape[0])
+        assert st.max_err_over_bound <= 1.0
+        assert 0.0 <= best.screen_err <= best.screen_bound
+    # sampled pairs, one at a time: none beats the reported minimum
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        i, j = sorted(rng.choice(X.shape[0], 2, replace=False).tolist())
+        assert oracle.d2(X, i, j) >= want_pair[2]
+
+
+def _window_d2(T, ell, i, j):
+    """Canonical squared distance of windows i and j, each z-normalised on its own."""
+    a, _, _ = oracle.znorm(T[i:i + ell], ell)
+    b, _, _ = oracle.znorm(T[j:j + ell], ell)
+    return oracle.d2(np.concatenate([a, b]), 0, 1)
+
+
+@pytest.mark.parametrize("prec", ["auto", "f32"])
+def test_batch_full_size(ctx, torch_dev, prec):
+    g = _golden("batch_512.json")
+    c = W.cfg_batch()
+    series, ells, plants = c["series"], c["ells"], c["plants"]
+    ts = [_dev(T, torch_dev) for T in series]
+    first = ctx.motif_batch(ts, ells, precision=prec)
+    st = ctx.stats()
+    assert st.valid_pairs == sum(W.valid_pairs_motif(len(T), e, e) for T, e in zip(series, ells))
+    again = ctx.motif_batch(ts, ells, precision=prec)          # replayed from the captured graph
+    assert [(r.i, r.j, r.d2) for r in first] == [(r.i, r.j, r.d2) for r in again]
+    for e in g["sample"]:
+        r = first[e["series"]]
+        assert (r.i, r.j, r.d2) == (e["closest_pair"]["i"], e["closest_pair"]["j"],
+                                    float.fromhex(e["closest_pair"]["d2"])), e["series"]
+    for s, (T, ell, (a, b)) in enumerate(zip(series, ells, plants)):
+        r = first[s]
+        assert 0 <= r.i and r.j - r.i >= ell and r.j <= len(T) - ell, (s, r)
+        assert r.d2 == _window_d2(T, ell, r.i, r.j), s
+        assert r.d2 <= _window_d2(T, ell, a, b), s
+        assert 0.0 <= r.screen_err <= r.screen_bound or r.screen_bound == 0.0
