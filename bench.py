@@ -31,7 +31,9 @@ PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak (published)
 PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 matrix peak (published)
 GOLDEN = os.path.join(ROOT, "tests", "golden", "mixture_n262144_d512.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "screen256_bf16_mixture_n262144_d512.traffic.json")
-SCREEN_SRC = os.path.join(ROOT, "paper_1407_5609_amd", "csrc", "screen256.hip")
+# sources of the dominant kernel: the counters are only valid for this exact code
+SCREEN_SRCS = [os.path.join(ROOT, "paper_1407_5609_amd", "csrc", f)
+               for f in ("screen256.hip", "layout256.h", "bound.h", "cpmi_internal.h")]
 
 
 def _traffic_per_launch():
@@ -39,8 +41,10 @@ def _traffic_per_launch():
     counter summary, or None if absent or taken on a different kernel source."""
     try:
         t = json.load(open(TRAFFIC))
-        src = hashlib.sha256(open(SCREEN_SRC, "rb").read()).hexdigest()
-        if t.get("kernel_source_sha256") != src:
+        h = hashlib.sha256()
+        for f in SCREEN_SRCS:
+            h.update(open(f, "rb").read())
+        if t.get("kernel_source_sha256") != h.hexdigest():
             return None
         return float(t["hbm_bytes_per_launch"])
     except Exception:
