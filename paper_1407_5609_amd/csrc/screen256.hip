@@ -32,6 +32,7 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) const void g_void;
 // Read-only kernel inputs (tile list, problem descriptors) are read through
@@ -73,16 +74,73 @@ template <typename S> __device__ __forceinline__ S smin(S a, S b);
 template <> __device__ __forceinline__ float smin(float a, float b) { return fminf(a, b); }
 template <> __device__ __forceinline__ int smin(int a, int b) { return min(a, b); }
 
+// This lane's index, recomputed by the hardware at each use: values derived
+// from a lane index computed once would otherwise stay live (and be spilled)
+// across the register-hungry epilogue, and their reloads would wait behind the
+// loads in flight.
+__device__ __forceinline__ int fresh_lane()
+{
+    int l;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+    return l;
+}
+
+// Minimum over the wave, returned in every lane: xor butterflies within each
+// half-wave (ds_swizzle bit-mask mode, offset = xor_mask << 10 | 0x1f), then
+// the two halves through lanes 0 and 32. No lane index is needed.
+#define CPMI_SWZ_STEP(PAT)                                                                           \
+    v = smin(v, __builtin_bit_cast(S, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), PAT)))
 template <typename S> __device__ __forceinline__ S wmin(S v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = smin(v, __shfl_xor(v, o, 64));
-    return v;
+    CPMI_SWZ_STEP(0x041f);
+    CPMI_SWZ_STEP(0x081f);
+    CPMI_SWZ_STEP(0x101f);
+    CPMI_SWZ_STEP(0x201f);
+    CPMI_SWZ_STEP(0x401f);
+    const S a = __builtin_bit_cast(S, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
+    const S b = __builtin_bit_cast(S, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+    return smin(a, b);
 }
+#undef CPMI_SWZ_STEP
 
 // s^_j - 2 g  (float: one fma; int8: exact int32)
 __device__ __forceinline__ float part(float g, float sj) { return fmaf(-2.0f, g, sj); }
 __device__ __forceinline__ int part(int g, int sj) { return sj - 2 * g; }
+
+// Bits of one 32-bit lane value as S. (Taken through a scalar argument: the
+// compiler lowers a bit cast of a vector element such as v.y as a read of the
+// vector's first element.)
+template <typename S> __device__ __forceinline__ S bits_as(uint32_t u) { return __builtin_bit_cast(S, u); }
+
+// Reads of the per-tile row scalars, which direct-to-LDS loads wrote. Those
+// loads are older than every K slice of the tile, so the per-slice load waits
+// and barriers have already made them visible; the compiler cannot see that
+// and would drain every load in flight (including the next tile's slices)
+// before a plain read. These reads wait for themselves, in the same asm block.
+// Four 16-byte values at p, p + 32 B, p + 64 B, p + 96 B.
+__device__ __forceinline__ void lds_landed_4x128(const void *p, u32x4 &a, u32x4 &b, u32x4 &c, u32x4 &d)
+{
+    const uint32_t ad = (uint32_t)(uintptr_t)p;
+    asm volatile("ds_read_b128 %0, %4\n\t"
+                 "ds_read_b128 %1, %4 offset:32\n\t"
+                 "ds_read_b128 %2, %4 offset:64\n\t"
+                 "ds_read_b128 %3, %4 offset:96\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(a), "=&v"(b), "=&v"(c), "=&v"(d)
+                 : "v"(ad));
+}
+// Four 4-byte values at p, p + 128 B, p + 256 B, p + 384 B.
+__device__ __forceinline__ u32x4 lds_landed_4x32(const void *p)
+{
+    u32x2 lo, hi;
+    const uint32_t a = (uint32_t)(uintptr_t)p;
+    asm volatile("ds_read2_b32 %0, %2 offset1:32\n\t"
+                 "ds_read2_b32 %1, %2 offset0:64 offset1:96\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(lo), "=&v"(hi)
+                 : "v"(a));
+    return u32x4{lo.x, lo.y, hi.x, hi.y};
+}
 
 }  // namespace
 
@@ -111,8 +169,9 @@ struct TileAddr {
 };
 
 template <int ESZ>
-__device__ __forceinline__ TileAddr tile_addr(const ScreenArgs &args, uint64_t ent, int lane)
+__device__ __forceinline__ TileAddr tile_addr(const ScreenArgs &args, uint64_t ent)
 {
+    const int lane = fresh_lane();
     const c_prob &P = ((c_prob *)args.probs)[tile_prob(ent)];
     const uint32_t rowbytes = (uint32_t)P.kpad * ESZ;
     const unsigned char *xs = (const unsigned char *)P.xs;
@@ -182,7 +241,10 @@ __device__ __forceinline__ void mma_group(typename A2<PREC>::T (&acc)[MB256][MB2
 //   2. waits until the next stage has landed and every wave is done reading
 //      `cur`, and synchronises;
 //   3. multiplies k-group 1 while it reads k-group 0 of the next stage `nxt`
-//      into f0a/f0b for the following step.
+//      into f0a/f0b for the following step. (The tile loop reads k-group 0
+//      of a tile again at its start, so the read-ahead of a tile's last step
+//      is dead once the tile ends and the fragments are not held in
+//      registers through the epilogue.)
 // The three stages arrive as restrict pointers: once inlined their accesses
 // carry distinct alias scopes, so LDS reads never wait for the loads in flight.
 template <int PREC>
@@ -227,11 +289,8 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     // row scalars of blocks I and J, double-buffered by tile parity
     __shared__ __attribute__((aligned(16))) S sh_s[2 * 2 * T256];
 
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int wm = wave >> 1, wn = wave & 1;
-    const int lrow = lane & 31, lhalf = lane >> 5;
 
     const int64_t count = (MODE & M_EMIT) ? (int64_t)*args.sel_count : args.ntiles;
     const int64_t stride = gridDim.x;
@@ -250,7 +309,7 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     // the end of the list it keeps re-reading its last slice (always in bounds)
     int64_t it = t;
     int is = 0;
-    TileAddr ia = tile_addr<ESZ>(args, tiles[it], lane);
+    TileAddr ia = tile_addr<ESZ>(args, tiles[it]);
     auto advance = [&]() {
         if (is + 1 < ia.nst) {
             ++is;
@@ -259,7 +318,7 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
             if (tn < count) {
                 it = tn;
                 is = 0;
-                ia = tile_addr<ESZ>(args, tiles[it], lane);
+                ia = tile_addr<ESZ>(args, tiles[it]);
             }
         }
     };
@@ -271,17 +330,20 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     advance();
     __builtin_amdgcn_s_waitcnt(WAIT_SLICE);
     __builtin_amdgcn_s_barrier();
-    Frags<PREC> f0a, f0b;  // k-group 0 of the next slice to multiply
-    read_group<PREC>(f0a, f0b, stage_ptr<0>(), 0, wm, wn, lrow, lhalf);
-
     while (t < count) {
         // per-lane values are rebuilt from an opaque copy of the lane index at
         // every tile, so the compiler keeps only the lane index alive across
         // the register-hungry epilogue instead of spilling derived offsets
         // (whose reloads would wait behind the loads in flight)
-        int lane_t = lane;
-        asm volatile("" : "+v"(lane_t));
+        const int lane_t = fresh_lane();
         const int lrow = lane_t & 31, lhalf = lane_t >> 5;
+        // k-group 0 of the tile's first slice (every tile starts at stage 0,
+        // which landed before the previous slice step's barrier). Read here,
+        // not carried over from the previous tile, so that the fragments are
+        // not held in registers through the epilogue; the set-up below
+        // (row-scalar loads, accumulator reset) hides the read's latency.
+        Frags<PREC> f0a, f0b;
+        read_group<PREC>(f0a, f0b, stage_ptr<0>(), 0, wm, wn, lrow, lhalf);
         const uint64_t ent = tiles[t];
         const uint32_t p = tile_prob(ent);
         const c_prob &P = ((c_prob *)args.probs)[p];
@@ -309,8 +371,8 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
 #pragma unroll
             for (int b = 0; b < MB256; ++b) acc[a][b] = AccT{};
 
-        // nst is a multiple of 4 (rows are padded to whole groups of four
-        // slices), so every tile starts at stage 0
+        // nst is a positive multiple of 4 (rows are padded to whole groups of
+        // four slices)
         for (int s = 0; s < nst; s += 4) {
             TileAddr cia = ia;
             int cis = is;
@@ -333,29 +395,30 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
             slice_step<PREC>(acc, f0a, f0b, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<3>(), stage_ptr<0>(),
                              stage_ptr<2>());
         }
-        const int64_t tn = next_valid(t + stride);
-
         // ---------------- epilogue ----------------
         // 32-bit row/column indices (n < 2^31 is enforced by the host)
         const int32_t n = (int32_t)P.n, excl = (int32_t)P.excl;
         const bool full = !MASKED || (((int64_t)J * T256 - ((int64_t)I * T256 + T256 - 1) >= P.excl) &&
                                       ((int64_t)I * T256 + T256 <= P.n) && ((int64_t)J * T256 + T256 <= P.n));
         S sj[MB256];
-#pragma unroll
-        for (int b = 0; b < MB256; ++b) sj[b] = sh_t[T256 + wn * WT256 + b * 32 + lrow];
+        {
+            const u32x4 v = lds_landed_4x32(sh_t + T256 + wn * WT256 + lrow);
+            sj[0] = bits_as<S>(v.x);
+            sj[1] = bits_as<S>(v.y);
+            sj[2] = bits_as<S>(v.z);
+            sj[3] = bits_as<S>(v.w);
+        }
 
         // rows of this lane in block a: 8*(r/4) + 4*lhalf + (r%4), four runs of 4 rows
         auto load_si = [&](int a, S (&si)[16]) {
+            u32x4 v[4];
+            lds_landed_4x128(sh_t + wm * WT256 + a * 32 + 4 * lhalf, v[0], v[1], v[2], v[3]);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int rb = wm * WT256 + a * 32 + 8 * q + 4 * lhalf;
-                if constexpr (PREC == P_I8) {
-                    const i32x4 v = *(const i32x4 *)(sh_t + rb);
-                    si[4 * q] = v.x; si[4 * q + 1] = v.y; si[4 * q + 2] = v.z; si[4 * q + 3] = v.w;
-                } else {
-                    const f32x4 v = *(const f32x4 *)(sh_t + rb);
-                    si[4 * q] = v.x; si[4 * q + 1] = v.y; si[4 * q + 2] = v.z; si[4 * q + 3] = v.w;
-                }
+                si[4 * q] = bits_as<S>(v[q].x);
+                si[4 * q + 1] = bits_as<S>(v[q].y);
+                si[4 * q + 2] = bits_as<S>(v[q].z);
+                si[4 * q + 3] = bits_as<S>(v[q].w);
             }
         };
         S best = SINF;
@@ -440,16 +503,19 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         }
         if constexpr (MODE & M_MIN) {
             best = wmin(best);
-            if (lane == 0) sh_red[wave] = best;
+            if (fresh_lane() == 0) sh_red[wave] = best;
             __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
             __builtin_amdgcn_s_barrier();
-            if (tid == 0) {
+            if (wave == 0 && fresh_lane() == 0) {
                 S m = smin(smin(sh_red[0], sh_red[1]), smin(sh_red[2], sh_red[3]));
                 args.tile_min[t] = __builtin_bit_cast(uint32_t, m);
             }
         }
-        t = tn;
+        t = next_valid(t + stride);
     }
+    // the load cursor keeps loads in flight past the last tile: let them land
+    // before the work-group (and its LDS) is released
+    __builtin_amdgcn_s_waitcnt(0);
 }
 
 template <int PREC>
