@@ -37,8 +37,10 @@ int64_t cpmi_dbg_tile_list(int64_t n, int64_t excl, int tile, uint64_t *out, int
 
 /* Host only: the screening-error bound applied to every pair of a tile whose
  * row blocks have maxima bI, bJ = (s^, ||x||, ||x~||, ||x - x~||) (4 floats
- * each), padded dimension kpad, true dimension d, screen precision. */
-double cpmi_dbg_tile_bound(const float *bI, const float *bJ, int32_t kpad, int64_t d, int precision);
+ * each), padded dimension kpad, true dimension d, screen precision, and
+ * screen value form: 0 = row scalars added after the product (128-row
+ * screen), 1 = row scalars folded into the product (256-row screen). */
+double cpmi_dbg_tile_bound(const float *bI, const float *bJ, int32_t kpad, int64_t d, int precision, int form);
 
 /* Host only: the 256-tile screen's K-slice layout for direct-to-LDS load
  * (wave 0..3, block q 0..3, lane 0..63): out4 = {tile row read, byte column

@@ -354,6 +354,14 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         key.push_back(h.kpad);
     }
     if (key != c->tiles_key) {
+        // the screen kernels index the tile list with 32-bit integers
+        double est = 0.0;
+        for (auto &h : hp) {
+            const double nT = std::ceil((double)h.n / tile);
+            est += nT * (nT + 1.0) / 2.0;
+        }
+        if (est > 2147483647.0 - 1048576.0)
+            return fail(c, CPMI_ERR_ARG, "problem too large for one screen (%.3g tiles; at most 2^31)", est);
         std::vector<uint64_t> tl;
         int64_t nf = 0;
         build_tiles(hp, tile, tl, &nf);
@@ -398,6 +406,8 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             q.motif = h.motif;
             q.src_i8 = h.src_i8;
             q.r2 = h.r2;
+            // the 256-row screen folds the row scalars into the matrix product
+            q.form = (tile == 256 && prec != P_I8) ? SCREEN_FOLDED : SCREEN_EPILOGUE;
             if (h.motif) {
                 q.mu = (const double *)((char *)c->musg.p + h.mu_off);
                 q.sigma = (const double *)((char *)c->musg.p + mu_b + h.mu_off);
@@ -1048,10 +1058,10 @@ int cpmi_dbg_layout256(int wave, int q, int lane, int32_t *out4)
     return CPMI_OK;
 }
 
-double cpmi_dbg_tile_bound(const float *bI, const float *bJ, int32_t kpad, int64_t d, int precision)
+double cpmi_dbg_tile_bound(const float *bI, const float *bJ, int32_t kpad, int64_t d, int precision, int form)
 {
     return tile_bound(make_float4(bI[0], bI[1], bI[2], bI[3]), make_float4(bJ[0], bJ[1], bJ[2], bJ[3]), kpad, d,
-                      precision);
+                      precision, form);
 }
 
 int cpmi_dbg_mfma_probe(int precision, const void *A, const void *B, float *C, void *stream)

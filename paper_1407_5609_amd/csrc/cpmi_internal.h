@@ -41,6 +41,8 @@ struct Prob {
     int32_t motif;         // 1 if the rows are z-normalised windows of src
     int32_t src_i8;        // 1 if src holds int8 points
     double r2;             // squared radius (negative: no radius search)
+    int32_t form;          // screen value form of the screen used (SCREEN_EPILOGUE / SCREEN_FOLDED)
+    int32_t pad_;
 };
 
 // Tile-list entry: problem (20 bits) | block row I (22 bits) | block col J (22 bits).

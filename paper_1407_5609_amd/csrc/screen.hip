@@ -178,7 +178,7 @@ __global__ __launch_bounds__(NTHREADS) void screen_kernel(ScreenArgs args)
         const int64_t i0 = I * TILE, j0 = J * TILE;
         // every pair of the tile admissible? (min j - max i >= excl, all rows real)
         const bool full = (j0 - (i0 + TILE - 1) >= excl) && (i0 + TILE <= n) && (j0 + TILE <= n);
-        const double E = tile_bound(P.bmax[I], P.bmax[J], P.kpad, P.d, PREC);
+        const double E = tile_bound(P.bmax[I], P.bmax[J], P.kpad, P.d, PREC, SCREEN_EPILOGUE);
         S thrU = -SINF, thrR = -SINF;
         if constexpr (MODE & M_EMIT) {
             if (args.U) {

@@ -104,7 +104,7 @@ template <typename S> __device__ __forceinline__ S wmin(S v)
 #undef CPMI_SWZ_STEP
 
 // s^_j - 2 g  (float: one fma; int8: exact int32)
-__device__ __forceinline__ float part(float g, float sj) { return fmaf(-2.0f, g, sj); }
+[[maybe_unused]] __device__ __forceinline__ float part(float g, float sj) { return fmaf(-2.0f, g, sj); }
 __device__ __forceinline__ int part(int g, int sj) { return sj - 2 * g; }
 
 // Bits of one 32-bit lane value as S. (Taken through a scalar argument: the
@@ -158,12 +158,12 @@ template <int STG> __device__ __forceinline__ unsigned char *stage_ptr()
     return STG == 0 ? g_stage0 : (STG == 1 ? g_stage1 : (STG == 2 ? g_stage2 : g_stage3));
 }
 
-// Per-tile addressing of the direct-to-LDS loads: a uniform base per operand
-// plus one 32-bit per-lane offset, so the loads use the scalar-base form.
+// Per-tile addressing of the direct-to-LDS loads: uniform values only (a
+// base per operand), so the load cursor lives in scalar registers; the
+// per-lane offset is recomputed at each issue from a fresh lane index.
 struct TileAddr {
     const unsigned char *ga;  // operand A rows of the tile
     const unsigned char *gb;  // operand B rows of the tile
-    uint32_t lane_off;        // (row within a 16-row block) * rowbytes + swizzled column
     uint32_t rowbytes;
     int nst;                  // K slices of the tile
 };
@@ -171,15 +171,12 @@ struct TileAddr {
 template <int ESZ>
 __device__ __forceinline__ TileAddr tile_addr(const ScreenArgs &args, uint64_t ent)
 {
-    const int lane = fresh_lane();
     const c_prob &P = ((c_prob *)args.probs)[tile_prob(ent)];
     const uint32_t rowbytes = (uint32_t)P.kpad * ESZ;
     const unsigned char *xs = (const unsigned char *)P.xs;
     TileAddr ta;
     ta.ga = xs + (int64_t)tile_I(ent) * T256 * rowbytes;
     ta.gb = xs + (int64_t)tile_J(ent) * T256 * rowbytes;
-    // the column swizzle of a lane does not depend on the block (layout256.h)
-    ta.lane_off = (uint32_t)l256::dma_row(0, 0, lane) * rowbytes + (uint32_t)l256::dma_col(0, 0, lane);
     ta.rowbytes = rowbytes;
     ta.nst = (int)(rowbytes / SL);
     return ta;
@@ -191,12 +188,17 @@ __device__ __forceinline__ void issue_slice(const TileAddr &ta, int s, int wave,
 {
     unsigned char *la = wr;
     unsigned char *lb = wr + OPB;
+    // (row within a 16-row block) * rowbytes + swizzled column; the column
+    // swizzle of a lane does not depend on the block (layout256.h)
+    const int lane = fresh_lane();
+    const uint32_t lane_off =
+        (uint32_t)l256::dma_row(0, 0, lane) * ta.rowbytes + (uint32_t)l256::dma_col(0, 0, lane);
 #pragma unroll
     for (int q = 0; q < l256::NQ; ++q) {
         const uint32_t rb = (uint32_t)l256::dma_row(wave, q, 0) * ta.rowbytes + (uint32_t)(s * SL);
         const int ldst = l256::dma_lds(wave, q, 0);
-        __builtin_amdgcn_global_load_lds((g_void *)(ta.ga + rb + ta.lane_off), (lds_void *)(la + ldst), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds((g_void *)(ta.gb + rb + ta.lane_off), (lds_void *)(lb + ldst), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((g_void *)(ta.ga + rb + lane_off), (lds_void *)(la + ldst), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((g_void *)(ta.gb + rb + lane_off), (lds_void *)(lb + ldst), 16, 0, 0);
     }
 }
 
@@ -275,6 +277,43 @@ __device__ __forceinline__ void slice_step(typename A2<PREC>::T (&acc)[MB256][MB
     }
 }
 
+// Folded row scalars (BF16 and FP32 screens): operands of one extra
+// matrix-core step per accumulator block whose product is -(s^_i + s^_j)/2,
+// so that the accumulator ends at fl(-(s^_i + s^_j)/2 + <x~_i, x~_j>) and
+// D~ = -2 acc (bound.h, folded form).
+//   BF16 (K = 16 per step; lane half h holds k = 8h .. 8h+7): with c = -s^/4
+//   split into three BF16 parts (c1, c2, c3), the A row of a lane in half 0
+//   holds [c1 c2 c3 1 1 1 0 0] and in half 1 [1 1 1 c1 c2 c3 0 0]; the B row
+//   the other pattern. Both halves then contribute c_i + c_j.
+//   FP32 (K = 2; lane half h holds k = h): A = (c_i, 1), B = (1, c_j) with
+//   c = -s^/2.
+__device__ __forceinline__ uint32_t bf16_rne_bits(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// BF16 fragment [c1 c2 c3 1 1 1 0 0] (first) or [1 1 1 c1 c2 c3 0 0] of
+// c = -s/4, the parts taken by round-to-nearest-even with exact remainders.
+__device__ __forceinline__ u32x4 fold_frag_bf16(float s, bool first)
+{
+    const float c = -0.25f * s;
+    const uint32_t h1 = bf16_rne_bits(c);
+    const float r1 = c - __uint_as_float(h1 << 16);
+    const uint32_t h2 = bf16_rne_bits(r1);
+    const float r2 = r1 - __uint_as_float(h2 << 16);
+    const uint32_t h3 = bf16_rne_bits(r2);
+    constexpr uint32_t ONE = 0x3f80u;
+    // per-dword selects (the lane half is divergent: no branches)
+    const uint32_t p0 = h1 | (h2 << 16), p1 = h3 | (ONE << 16), p2 = ONE | (ONE << 16);
+    const uint32_t q0 = ONE | (ONE << 16), q1 = ONE | (h1 << 16), q2 = h2 | (h3 << 16);
+    // the zero dword is materialised here rather than shared with a
+    // loop-wide zero register (which the allocator would spill with it)
+    uint32_t z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    return u32x4{first ? p0 : q0, first ? p1 : q1, first ? p2 : q2, z};
+}
+
 // MASKED = false: every pair of every listed tile is admissible (the host
 // lists such full tiles apart), so the epilogue carries no masking code.
 template <int PREC, int MODE, bool MASKED>
@@ -284,37 +323,55 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     using S = typename A2<PREC>::S;
     constexpr S SINF = PREC == P_I8 ? (S)0x7fffffff : (S)INFINITY;
     constexpr int ESZ = PREC == P_F32 ? 4 : (PREC == P_BF16 ? 2 : 1);
+    constexpr bool FOLD = PREC != P_I8;  // row scalars folded into the product
 
     __shared__ S sh_red[4];
-    // row scalars of blocks I and J, double-buffered by tile parity
+    // row scalars of blocks I and J, double-buffered by tile parity: the
+    // scalars of the next tile are loaded while the current one is screened
     __shared__ __attribute__((aligned(16))) S sh_s[2 * 2 * T256];
 
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int wm = wave >> 1, wn = wave & 1;
 
-    const int64_t count = (MODE & M_EMIT) ? (int64_t)*args.sel_count : args.ntiles;
-    const int64_t stride = gridDim.x;
+    // 32-bit tile indices (the host keeps lists below 2^31 entries), so that
+    // the loop bookkeeping stays in scalar registers and scalar compares
+    const int32_t count = (MODE & M_EMIT) ? (int32_t)*args.sel_count : (int32_t)args.ntiles;
+    const int32_t stride = (int32_t)gridDim.x;
 
     c_u64 *tiles = (c_u64 *)args.tiles;
-    auto next_valid = [&](int64_t t) -> int64_t {
+    auto next_valid = [&](int32_t t) -> int32_t {
         while (t < count && tiles[t] == TILE_NONE) t += stride;
         return t;
     };
+    // direct-to-LDS load of the row scalars of tile `tt` (blocks I and J) into
+    // sh_s half `half`: each wave loads 64 of block I and 64 of block J
+    auto load_scalars = [&](int32_t tt, int half) {
+        const uint64_t e = tiles[tt];
+        const c_prob &Q = ((c_prob *)args.probs)[tile_prob(e)];
+        const unsigned char *sb = (const unsigned char *)Q.shat;
+        const uint32_t lo = (uint32_t)fresh_lane() * 4;
+        S *dst = sh_s + half * (2 * T256);
+        __builtin_amdgcn_global_load_lds((g_void *)(sb + ((int64_t)tile_I(e) * T256 + wave * 64) * 4 + lo),
+                                         (lds_void *)(dst + wave * 64), 4, 0, 0);
+        __builtin_amdgcn_global_load_lds((g_void *)(sb + ((int64_t)tile_J(e) * T256 + wave * 64) * 4 + lo),
+                                         (lds_void *)(dst + T256 + wave * 64), 4, 0, 0);
+    };
 
-    int64_t t = next_valid(blockIdx.x);
+    int32_t t = next_valid((int32_t)blockIdx.x);
     if (t >= count) return;
     int tcount = 0;
+    load_scalars(t, 0);
 
     // load cursor: runs three slices ahead of the multiply, across tiles; at
     // the end of the list it keeps re-reading its last slice (always in bounds)
-    int64_t it = t;
+    int32_t it = t;
     int is = 0;
     TileAddr ia = tile_addr<ESZ>(args, tiles[it]);
     auto advance = [&]() {
         if (is + 1 < ia.nst) {
             ++is;
         } else {
-            const int64_t tn = next_valid(it + stride);
+            const int32_t tn = next_valid(it + stride);
             if (tn < count) {
                 it = tn;
                 is = 0;
@@ -328,48 +385,78 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     advance();
     issue_slice(ia, is, wave, stage_ptr<2>());
     advance();
+    // the first tile's scalars are older than the last 16 loads: landed
     __builtin_amdgcn_s_waitcnt(WAIT_SLICE);
     __builtin_amdgcn_s_barrier();
     while (t < count) {
-        // per-lane values are rebuilt from an opaque copy of the lane index at
-        // every tile, so the compiler keeps only the lane index alive across
-        // the register-hungry epilogue instead of spilling derived offsets
-        // (whose reloads would wait behind the loads in flight)
+        // per-lane values are rebuilt from a fresh lane index at every tile,
+        // so that nothing lane-derived is held through the epilogue
         const int lane_t = fresh_lane();
         const int lrow = lane_t & 31, lhalf = lane_t >> 5;
-        // k-group 0 of the tile's first slice (every tile starts at stage 0,
-        // which landed before the previous slice step's barrier). Read here,
-        // not carried over from the previous tile, so that the fragments are
-        // not held in registers through the epilogue; the set-up below
-        // (row-scalar loads, accumulator reset) hides the read's latency.
-        Frags<PREC> f0a, f0b;
-        read_group<PREC>(f0a, f0b, stage_ptr<0>(), 0, wm, wn, lrow, lhalf);
         const uint64_t ent = tiles[t];
         const uint32_t p = tile_prob(ent);
         const c_prob &P = ((c_prob *)args.probs)[p];
         const int64_t I = tile_I(ent), J = tile_J(ent);
         const int nst = (int)((int64_t)P.kpad * ESZ / SL);
         const int32_t i0 = (int32_t)(I * T256) + wm * WT256, j0 = (int32_t)(J * T256) + wn * WT256;
-        // row scalars of this tile: each wave loads 64 of block I and 64 of
-        // block J straight into this tile's half of sh_s. They are older than
-        // the slices multiplied below, so the per-slice waits cover them (the
-        // tile has at least four slices) and no VGPR or extra wait is needed.
-        S *sh_t = sh_s + (tcount & 1) * (2 * T256);
-        {
-            const unsigned char *sb = (const unsigned char *)P.shat;
-            const uint32_t lo = (uint32_t)lane_t * 4;
-            __builtin_amdgcn_global_load_lds((g_void *)(sb + (I * T256 + wave * 64) * 4 + lo),
-                                             (lds_void *)(sh_t + wave * 64), 4, 0, 0);
-            __builtin_amdgcn_global_load_lds((g_void *)(sb + (J * T256 + wave * 64) * 4 + lo),
-                                             (lds_void *)(sh_t + T256 + wave * 64), 4, 0, 0);
-        }
+        // this tile's row scalars were loaded one tile ago (or before the
+        // loop) and are older than every slice waited for since
+        const S *sh_t = sh_s + (tcount & 1) * (2 * T256);
+        const int32_t tn = next_valid(t + stride);
+        if (tn < count) load_scalars(tn, (tcount + 1) & 1);
         ++tcount;
 
         AccT acc[MB256][MB256];
+        if constexpr (FOLD) {
+            // s^ of this lane's rows: A block m row wm*128 + 32 m + lrow,
+            // B block m row wn*128 + 32 m + lrow
+            const u32x4 sa = lds_landed_4x32(sh_t + wm * WT256 + lrow);
+            const u32x4 sb = lds_landed_4x32(sh_t + T256 + wn * WT256 + lrow);
+            const uint32_t sav[4] = {sa.x, sa.y, sa.z, sa.w};
+            const uint32_t sbv[4] = {sb.x, sb.y, sb.z, sb.w};
+            if constexpr (PREC == P_BF16) {
+                u32x4 fa[MB256], fb[MB256];
 #pragma unroll
-        for (int a = 0; a < MB256; ++a)
+                for (int m = 0; m < MB256; ++m) {
+                    fa[m] = fold_frag_bf16(__uint_as_float(sav[m]), lhalf == 0);
+                    fb[m] = fold_frag_bf16(__uint_as_float(sbv[m]), lhalf != 0);
+                }
 #pragma unroll
-            for (int b = 0; b < MB256; ++b) acc[a][b] = AccT{};
+                for (int a = 0; a < MB256; ++a)
+#pragma unroll
+                    for (int b = 0; b < MB256; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[a]),
+                                                                            __builtin_bit_cast(bf16x8, fb[b]),
+                                                                            AccT{}, 0, 0, 0);
+            } else {
+                float fa[MB256], fb[MB256];
+#pragma unroll
+                for (int m = 0; m < MB256; ++m) {
+                    const float ca = -0.5f * __uint_as_float(sav[m]), cb = -0.5f * __uint_as_float(sbv[m]);
+                    fa[m] = lhalf == 0 ? ca : 1.0f;
+                    fb[m] = lhalf == 0 ? 1.0f : cb;
+                }
+#pragma unroll
+                for (int a = 0; a < MB256; ++a)
+#pragma unroll
+                    for (int b = 0; b < MB256; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[a], fb[b], AccT{}, 0, 0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int a = 0; a < MB256; ++a)
+#pragma unroll
+                for (int b = 0; b < MB256; ++b) acc[a][b] = AccT{};
+        }
+        // the folded operands are dead from here on
+        __builtin_amdgcn_sched_barrier(0);
+        // k-group 0 of the tile's first slice (every tile starts at stage 0,
+        // which landed before the previous slice step's barrier). Read here,
+        // not carried over from the previous tile, so that the fragments are
+        // not held in registers through the epilogue; the folded steps above
+        // run meanwhile.
+        Frags<PREC> f0a, f0b;
+        read_group<PREC>(f0a, f0b, stage_ptr<0>(), 0, wm, wn, lrow, lhalf);
 
         // nst is a positive multiple of 4 (rows are padded to whole groups of
         // four slices)
@@ -400,15 +487,15 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         const int32_t n = (int32_t)P.n, excl = (int32_t)P.excl;
         const bool full = !MASKED || (((int64_t)J * T256 - ((int64_t)I * T256 + T256 - 1) >= P.excl) &&
                                       ((int64_t)I * T256 + T256 <= P.n) && ((int64_t)J * T256 + T256 <= P.n));
+        // screen value of accumulator element r of block (a, b)
         S sj[MB256];
-        {
+        if constexpr (!FOLD) {
             const u32x4 v = lds_landed_4x32(sh_t + T256 + wn * WT256 + lrow);
             sj[0] = bits_as<S>(v.x);
             sj[1] = bits_as<S>(v.y);
             sj[2] = bits_as<S>(v.z);
             sj[3] = bits_as<S>(v.w);
         }
-
         // rows of this lane in block a: 8*(r/4) + 4*lhalf + (r%4), four runs of 4 rows
         auto load_si = [&](int a, S (&si)[16]) {
             u32x4 v[4];
@@ -423,25 +510,45 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         };
         S best = SINF;
         if (full) {
+            if constexpr (FOLD) {
+                // min of -2 acc = -2 max acc, one accumulator block at a
+                // time: the opaque step closes each block's maximum, so the
+                // compiler does not build one tree over (and copy out of the
+                // accumulator registers) all 256 values at once
+                S mx = -SINF;
 #pragma unroll
-            for (int a = 0; a < MB256; ++a) {
-                S si[16];
-                load_si(a, si);
+                for (int a = 0; a < MB256; ++a) {
+                    S ma = -SINF;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    S m0 = part(acc[a][0][r], sj[0]);
+                    for (int r = 0; r < 16; ++r)
 #pragma unroll
-                    for (int b = 1; b < MB256; ++b) m0 = smin(m0, part(acc[a][b][r], sj[b]));
-                    best = smin(best, (S)(si[r] + m0));
+                        for (int b = 0; b < MB256; ++b) ma = fmaxf(ma, acc[a][b][r]);
+                    asm volatile("" : "+v"(ma));
+                    mx = fmaxf(mx, ma);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-                // one accumulator block at a time keeps the epilogue's registers few
-                __builtin_amdgcn_sched_barrier(0);
+                best = -2.0f * mx;
+            } else {
+#pragma unroll
+                for (int a = 0; a < MB256; ++a) {
+                    S si[16];
+                    load_si(a, si);
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        S m0 = part(acc[a][0][r], sj[0]);
+#pragma unroll
+                        for (int b = 1; b < MB256; ++b) m0 = smin(m0, part(acc[a][b][r], sj[b]));
+                        best = smin(best, (S)(si[r] + m0));
+                    }
+                    // one accumulator block at a time keeps the epilogue's registers few
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
         } else if constexpr (MASKED) {
 #pragma unroll
             for (int a = 0; a < MB256; ++a) {
                 S si[16];
-                load_si(a, si);
+                if constexpr (!FOLD) load_si(a, si);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
@@ -449,7 +556,9 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                     for (int b = 0; b < MB256; ++b) {
                         const int32_t gj = j0 + b * 32 + lrow;
                         const bool ok = (gj - gi >= excl) && (gi < n) && (gj < n);
-                        const S dv = (S)(si[r] + part(acc[a][b][r], sj[b]));
+                        S dv;
+                        if constexpr (FOLD) dv = -2.0f * acc[a][b][r];
+                        else dv = (S)(si[r] + part(acc[a][b][r], sj[b]));
                         best = ok ? smin(best, dv) : best;
                     }
                 }
@@ -458,7 +567,8 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         }
 
         if constexpr (MODE & M_EMIT) {
-            const double E = tile_bound(P.bmax[I], P.bmax[J], P.kpad, P.d, PREC);
+            const double E = tile_bound(P.bmax[I], P.bmax[J], P.kpad, P.d, PREC,
+                                        FOLD ? SCREEN_FOLDED : SCREEN_EPILOGUE);
             S thrU = -SINF, thrR = -SINF;
             if (args.U) {
                 const double u = args.U[p];
@@ -476,11 +586,14 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
-                        const S si = sh_t[gi - (int32_t)(I * T256)];
+                        S si = 0;
+                        if constexpr (!FOLD) si = sh_t[gi - (int32_t)(I * T256)];
 #pragma unroll
                         for (int b = 0; b < MB256; ++b) {
                             const int32_t gj = j0 + b * 32 + lrow;
-                            const S dv = (S)(si + part(acc[a][b][r], sj[b]));
+                            S dv;
+                            if constexpr (FOLD) dv = -2.0f * acc[a][b][r];
+                            else dv = (S)(si + part(acc[a][b][r], sj[b]));
                             const bool ok = full || ((gj - gi >= excl) && (gi < n) && (gj < n));
                             if (ok && dv <= thr) {
                                 Cand cd;
@@ -511,7 +624,7 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                 args.tile_min[t] = __builtin_bit_cast(uint32_t, m);
             }
         }
-        t = next_valid(t + stride);
+        t = tn;
     }
     // the load cursor keeps loads in flight past the last tile: let them land
     // before the work-group (and its LDS) is released

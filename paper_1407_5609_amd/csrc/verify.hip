@@ -27,7 +27,7 @@ __device__ __forceinline__ double tile_min_value(uint32_t bits, int prec)
 __device__ __forceinline__ double tile_bound_of(const Prob &P, int64_t I, int64_t J, int prec)
 {
     if (prec == P_I8) return 0.0;
-    return tile_bound(P.bmax[I], P.bmax[J], P.kpad, P.d, prec);
+    return tile_bound(P.bmax[I], P.bmax[J], P.kpad, P.d, prec, P.form);
 }
 
 // Each wave takes 64 consecutive list entries per step; when they all belong

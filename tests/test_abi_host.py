@@ -25,7 +25,7 @@ def lib():
     L.cpmi_dbg_tile_list.restype = C.c_int64
     L.cpmi_dbg_tile_list.argtypes = [C.c_int64, C.c_int64, C.c_int, C.c_void_p, C.c_int64]
     L.cpmi_dbg_tile_bound.restype = C.c_double
-    L.cpmi_dbg_tile_bound.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_int]
+    L.cpmi_dbg_tile_bound.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_int, C.c_int]
     return L
 
 
@@ -121,9 +121,41 @@ def _row_stats(Xc, Xt):
 
 
 def _emulated_screen(Xt, shat):
+    """Row scalars added after the product (128-row screen)."""
     G = Xt @ Xt.T                                         # float32 accumulation (any order is covered)
     v = (shat[None, :] - np.float32(2) * G).astype(np.float32)
     return (shat[:, None] + v).astype(np.float32)
+
+
+def _split3_bf16(c):
+    """c (float32) as three round-to-nearest-even BF16 parts with exact remainders."""
+    h = _bf16(c)
+    r1 = (c - h).astype(np.float32)
+    m = _bf16(r1)
+    r2 = (r1 - m).astype(np.float32)
+    return h, m, _bf16(r2)
+
+
+def _emulated_folded_screen(Xt, shat, prec):
+    """Row scalars folded into the product (256-row screen): the accumulator
+    starts from the folded terms, adds every product in ascending k with one
+    float32 rounding per step, and D~ = -2 acc."""
+    n = Xt.shape[0]
+    acc = np.zeros((n, n), np.float32)
+    if prec == 2:
+        parts = _split3_bf16((np.float32(-0.25) * shat).astype(np.float32))
+        for _half in range(2):                           # both lane halves carry c_i + c_j
+            for q in parts:
+                acc = (acc + q[:, None]).astype(np.float32)
+            for q in parts:
+                acc = (acc + q[None, :]).astype(np.float32)
+    else:
+        c = (np.float32(-0.5) * shat).astype(np.float32)
+        acc = (acc + c[:, None]).astype(np.float32)
+        acc = (acc + c[None, :]).astype(np.float32)
+    for k in range(Xt.shape[1]):
+        acc = (acc + (Xt[:, k][:, None] * Xt[:, k][None, :]).astype(np.float32)).astype(np.float32)
+    return (np.float32(-2) * acc).astype(np.float32)
 
 
 def _canon(Xc):
@@ -134,8 +166,9 @@ def _canon(Xc):
     return D
 
 
+@pytest.mark.parametrize("form", [0, 1])
 @pytest.mark.parametrize("kind", ["points_f32", "points_bf16", "mixture_bf16", "windows_f32", "windows_bf16"])
-def test_bound_holds_on_emulated_screens_and_has_teeth(lib, kind):
+def test_bound_holds_on_emulated_screens_and_has_teeth(lib, kind, form):
     rng = np.random.default_rng(abs(hash(kind)) % 1000)
     if kind.startswith("points"):
         X = rng.normal(0, 1, (160, 96)).astype(np.float32)
@@ -156,7 +189,7 @@ def test_bound_holds_on_emulated_screens_and_has_teeth(lib, kind):
     X32 = Xc.astype(np.float32)
     Xt = X32 if prec == 1 else _bf16(X32)
     shat, a, at, r = _row_stats(Xc, Xt)
-    D = _emulated_screen(Xt, shat)
+    D = _emulated_screen(Xt, shat) if form == 0 else _emulated_folded_screen(Xt, shat, prec)
     d = Xc.shape[1]
     kpad = -(-d // (32 if prec == 1 else 64)) * (32 if prec == 1 else 64)
     n = Xc.shape[0]
@@ -168,11 +201,11 @@ def test_bound_holds_on_emulated_screens_and_has_teeth(lib, kind):
     for k, (i, j) in enumerate(zip(*iu)):
         bI = np.array([shat[i], a[i], at[i], r[i]], np.float32)
         bJ = np.array([shat[j], a[j], at[j], r[j]], np.float32)
-        E[k] = lib.cpmi_dbg_tile_bound(bI.ctypes.data, bJ.ctypes.data, kpad, d, prec)
+        E[k] = lib.cpmi_dbg_tile_bound(bI.ctypes.data, bJ.ctypes.data, kpad, d, prec, form)
     assert np.all(err <= E), float(np.max(err / E))
     # tile form (block maxima) is at least as large
     bI = np.array([shat.max(), a.max(), at.max(), r.max()], np.float32)
-    Et = lib.cpmi_dbg_tile_bound(bI.ctypes.data, bI.ctypes.data, kpad, d, prec)
+    Et = lib.cpmi_dbg_tile_bound(bI.ctypes.data, bI.ctypes.data, kpad, d, prec, form)
     assert Et >= E.max()
     # teeth: the emulated error reaches more than a thousandth of the bound
     assert np.max(err / E) > 1e-3
@@ -180,7 +213,8 @@ def test_bound_holds_on_emulated_screens_and_has_teeth(lib, kind):
 
 def test_int8_bound_is_zero(lib):
     b = np.ones(4, np.float32)
-    assert lib.cpmi_dbg_tile_bound(b.ctypes.data, b.ctypes.data, 4096, 4096, 3) == 0.0
+    for form in (0, 1):
+        assert lib.cpmi_dbg_tile_bound(b.ctypes.data, b.ctypes.data, 4096, 4096, 3, form) == 0.0
 
 
 def test_layout256_covers_the_slice_and_reads_what_was_written(lib):
