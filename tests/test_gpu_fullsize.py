@@ -107,3 +107,24 @@ def test_batch_full_size(ctx, torch_dev, prec):
         assert r.d2 == _window_d2(T, ell, r.i, r.j), s
         assert r.d2 <= _window_d2(T, ell, a, b), s
         assert 0.0 <= r.screen_err <= r.screen_bound or r.screen_bound == 0.0
+
+
+def test_int8_genotypes_full_size_golden(ctx, torch_dev):
+    """100,000 x 4096 int8 rows: the INT8 screen is exact, so the closest pair
+    and the pairs within R2 = 800 must equal the oracle's bit for bit."""
+    g = _golden("snp_n100000_d4096.json")
+    c = W.cfg_snp()
+    X = c["X"]
+    t = _dev(X, torch_dev)
+    best, (p, d) = ctx.points(t, R2=float(g["R2"]), precision="i8")
+    assert (best.i, best.j, best.d2) == (g["closest_pair"]["i"], g["closest_pair"]["j"],
+                                         float(g["closest_pair"]["d2"]))
+    assert best.screen_err == 0.0 and best.screen_bound == 0.0
+    assert np.array_equal(p.cpu().numpy(), np.array(g["frnn"]["pairs"], dtype=np.int64).reshape(-1, 2))
+    assert np.array_equal(d.cpu().numpy(), np.array(g["frnn"]["d2"], dtype=np.float64))
+    st = ctx.stats()
+    assert st.valid_pairs == W.valid_pairs_points(X.shape[0])
+    # the plants are the radius set (reading of the workload) and every reported d2 is exact
+    assert sorted(map(tuple, p.cpu().numpy().tolist())) == sorted((a, b) for a, b, _ in c["plants"])
+    for (i, j), v in zip(p.cpu().numpy().tolist(), d.cpu().numpy().tolist()):
+        assert oracle.d2(X, i, j) == v
