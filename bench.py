@@ -1,8 +1,8 @@
 """Benchmark: exact closest pair + fixed-radius pairs on the precision-form workload.
 
-Workload: n = 262,144 points, d = 512, float32, 64-cluster Gaussian mixture with
-one planted pair (workloads.cfg_mixture); radius R = half the lower-median
-nearest-neighbour distance (an oracle-computed input read from
+Default workload (the headline): n = 262,144 points, d = 512, float32, 64-cluster
+Gaussian mixture with one planted pair (workloads.cfg_mixture); radius R = half
+the lower-median nearest-neighbour distance (an oracle-computed input read from
 tests/golden/mixture_n262144_d512.json). One step = one call of the whole hot
 path: row prep -> BF16 matrix-core screen (tile minima) -> bound reduction and
 tile selection -> second screen of the selected tiles -> FP64 verification ->
@@ -15,6 +15,7 @@ pass-1 screen), timed with HIP events on the call's stream; `cpu_baseline` is
 the CPU oracle on a bounded sample (rank 0, N = 1 only).
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+    python bench.py --workload {mixture,points,motif,batch,snp}   (the other workloads, same JSON form)
 """
 import argparse
 import hashlib
@@ -27,13 +28,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "exact pair-evals/s + % MFMA roofline; BF16-screened vs plain FP32 speedup"
-PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak (published)
-PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 matrix peak (published)
-GOLDEN = os.path.join(ROOT, "tests", "golden", "mixture_n262144_d512.json")
+# published dense matrix-core peaks of MI355X
+PEAK = {"bf16": (2500.0, "TFLOP/s"), "f32": (157.3, "TFLOP/s"), "i8": (5000.0, "TOP/s")}
+PREC_NAME = {1: "f32", 2: "bf16", 3: "i8"}
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
 TRAFFIC = os.path.join(ROOT, "profiles", "screen256_bf16_mixture_n262144_d512.traffic.json")
 # sources of the dominant kernel: the counters are only valid for this exact code
 SCREEN_SRCS = [os.path.join(ROOT, "paper_1407_5609_amd", "csrc", f)
                for f in ("screen256.hip", "layout256.h", "bound.h", "cpmi_internal.h")]
+
+
+def note(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def _traffic_per_launch():
@@ -51,24 +57,173 @@ def _traffic_per_launch():
         return None
 
 
-def cpu_baseline(X, target_s=15.0):
-    """Time the CPU oracle's closest-pair search on the first m rows."""
-    import oracle
-    threads = min(16, os.cpu_count() or 1)
-    oracle.set_threads(threads)
-    m = 2048
+def _golden(name):
+    return json.load(open(os.path.join(GOLDEN_DIR, name)))
+
+
+def _want(g, as_int=False):
+    import numpy as np
+    conv = float if as_int else float.fromhex
+    pair = (g["closest_pair"]["i"], g["closest_pair"]["j"], conv(g["closest_pair"]["d2"]))
+    pairs = np.array(g["frnn"]["pairs"], dtype=np.int64).reshape(-1, 2)
+    d2 = np.array([conv(v) for v in g["frnn"]["d2"]], dtype=np.float64)
+    return pair, pairs, d2
+
+
+def _timed_oracle(fn, grow, target_s):
+    """Run fn(size) on a small size, then on the size expected to take ~target_s."""
+    size = grow(None, None)
     t = time.perf_counter()
-    oracle.closest_pair(X[:m])
+    fn(size)
     dt = time.perf_counter() - t
-    rate = m * (m - 1) / 2 / max(dt, 1e-6)
-    m = int(min(X.shape[0], max(2048, (2 * rate * target_s) ** 0.5)))
+    size = grow(size, max(dt, 1e-6) / target_s)
     t = time.perf_counter()
-    oracle.closest_pair(X[:m])
-    dt = time.perf_counter() - t
-    pairs = m * (m - 1) // 2
-    return {"value": pairs / dt, "unit": "pair-evals/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"closest pair over the first {m} rows of the workload ({pairs} pairs, d=512), "
-                      f"{dt:.1f} s"}
+    fn(size)
+    return size, time.perf_counter() - t
+
+
+# ---------------------------------------------------------------------------
+# workloads: step(ctx, prec) runs one call of the hot path and returns whether
+# the result equals the oracle's stored answer
+# ---------------------------------------------------------------------------
+
+class Workload:
+    precs = ("bf16", "f32")        # primary precision first; the second is the comparison leg
+    flops_per_pair = None          # algorithmic flops (int ops) per admissible pair
+    graph = False                  # launches replayed from a captured graph (no per-launch events)
+
+
+class Points(Workload):
+    """Common part of the point workloads (closest pair + radius pairs of one set)."""
+
+    def _setup(self, torch, X, golden, as_int=False):
+        g = _golden(golden)
+        self.R2 = float(g["R2"]) if as_int else float.fromhex(g["R2"])
+        self.want = _want(g, as_int)
+        self.Xh = X
+        self.n, self.d = X.shape
+        self.X = torch.from_numpy(X).to("cuda:0")
+        self.flops_per_pair = 2.0 * self.d
+        return g
+
+    def step(self, ctx, prec):
+        import numpy as np
+        best, (p, dd) = ctx.points(self.X, R2=self.R2, precision=prec)
+        wp, wpairs, wd = self.want
+        return ((best.i, best.j, best.d2) == wp and np.array_equal(p.cpu().numpy(), wpairs)
+                and np.array_equal(dd.cpu().numpy(), wd))
+
+    def cpu_baseline(self, target_s):
+        import oracle
+        X, m0 = self.Xh, min(self.Xh.shape[0], 2048)
+
+        def grow(m, ratio):
+            return m0 if m is None else int(min(X.shape[0], max(m0, m / ratio ** 0.5)))
+        m, dt = _timed_oracle(lambda m: oracle.closest_pair(X[:m]), grow, target_s)
+        pairs = m * (m - 1) // 2
+        return pairs / dt, (f"closest pair over the first {m} of {X.shape[0]} rows ({pairs} pairs, "
+                            f"d={X.shape[1]} {X.dtype}), {dt:.1f} s")
+
+
+class Mixture(Points):
+    name = "mixture"
+
+    def __init__(self, W, torch):
+        g = self._setup(torch, W.cfg_mixture()["X"], "mixture_n262144_d512.json")
+        self.config = {"workload": f"mixture_n{self.n}_d{self.d}: exact closest pair + all pairs within R "
+                                   "(BF16 matrix-core screen, FP64 verification)",
+                       "n": self.n, "d": self.d, "R": float.fromhex(g["R"])}
+
+
+class SmallPoints(Points):
+    name = "points"
+    precs = ("f32", "bf16")
+
+    def __init__(self, W, torch):
+        self._setup(torch, W.cfg_points_small()["X"], "points_n4096_d64.json")
+        self.config = {"workload": f"points_n{self.n}_d{self.d}: exact closest pair + all pairs within R=8",
+                       "n": self.n, "d": self.d}
+
+
+class Snp(Points):
+    name = "snp"
+    precs = ("i8",)
+
+    def __init__(self, W, torch):
+        self._setup(torch, W.cfg_snp()["X"], "snp_n100000_d4096.json", as_int=True)
+        self.config = {"workload": f"snp_n{self.n}_d{self.d}: exact int8 closest pair + all pairs with d2 <= 800 "
+                                   "(INT8 matrix-core screen, exact)", "n": self.n, "d": self.d}
+
+
+class Motif(Workload):
+    name = "motif"
+
+    def __init__(self, W, torch):
+        g = _golden("motif_L65536_l256.json")
+        self.R2 = float.fromhex(g["R2"])
+        self.want = _want(g)
+        c = W.cfg_motif()
+        self.Th, self.ell, self.excl = c["T"], c["ell"], c["excl"]
+        self.T = torch.from_numpy(self.Th).to("cuda:0")
+        self.flops_per_pair = 2.0 * self.ell
+        self.config = {"workload": f"motif_L{len(self.Th)}_l{self.ell}: exact z-normalised motif + all window pairs "
+                                   "within R=2 (exclusion l)", "length": len(self.Th), "ell": self.ell}
+
+    def step(self, ctx, prec):
+        import numpy as np
+        best, (p, dd) = ctx.motif(self.T, self.ell, excl=self.excl, R2=self.R2, precision=prec)
+        wp, wpairs, wd = self.want
+        return ((best.i, best.j, best.d2) == wp and np.array_equal(p.cpu().numpy(), wpairs)
+                and np.array_equal(dd.cpu().numpy(), wd))
+
+    def cpu_baseline(self, target_s):
+        import oracle
+        import workloads as W
+        T, ell, L0 = self.Th, self.ell, 4 * self.ell + 2048
+
+        def grow(L, ratio):
+            return L0 if L is None else int(min(len(T), max(L0, L / ratio ** 0.5)))
+        L, dt = _timed_oracle(lambda L: oracle.motif(T[:L], ell), grow, target_s)
+        pairs = W.valid_pairs_motif(L, ell, ell)
+        return pairs / dt, f"motif of the first {L} samples of the series ({pairs} window pairs, l={ell}), {dt:.1f} s"
+
+
+class Batch(Workload):
+    name = "batch"
+    precs = ("auto", "f32")
+    graph = True
+
+    def __init__(self, W, torch):
+        g = _golden("batch_512.json")
+        c = W.cfg_batch()
+        self.series, self.ells = c["series"], c["ells"]
+        self.ts = [torch.from_numpy(T).to("cuda:0") for T in self.series]
+        self.sample = g["sample"]
+        pairs = [W.valid_pairs_motif(len(T), e, e) for T, e in zip(self.series, self.ells)]
+        self.flops = sum(2.0 * e * p for e, p in zip(self.ells, pairs))
+        self.config = {"workload": f"batch_{len(self.series)}: exact z-normalised motif of each of 512 series "
+                                   "(lengths 4096-65536, l in {64,128,256,512}) in one graph-replayed batch",
+                       "series": len(self.series), "algorithmic_flops": self.flops}
+
+    def step(self, ctx, prec):
+        res = ctx.motif_batch(self.ts, self.ells, precision=prec)
+        return all((res[e["series"]].i, res[e["series"]].j, res[e["series"]].d2) ==
+                   (e["closest_pair"]["i"], e["closest_pair"]["j"], float.fromhex(e["closest_pair"]["d2"]))
+                   for e in self.sample)
+
+    def cpu_baseline(self, target_s):
+        import oracle
+        import workloads as W
+        t0, k, pairs = time.perf_counter(), 0, 0
+        while k < len(self.series) and time.perf_counter() - t0 < target_s:
+            oracle.motif(self.series[k], self.ells[k])
+            pairs += W.valid_pairs_motif(len(self.series[k]), self.ells[k], self.ells[k])
+            k += 1
+        dt = time.perf_counter() - t0
+        return pairs / dt, f"motifs of the first {k} series of the batch ({pairs} window pairs), {dt:.1f} s"
+
+
+WORKLOADS = {w.name: w for w in (Mixture, SmallPoints, Motif, Batch, Snp)}
 
 
 def main():
@@ -76,8 +231,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--fp32-steps", type=int, default=2)
+    ap.add_argument("--workload", default="mixture", choices=sorted(WORKLOADS))
+    ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the comparison precision (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (a reference launch for hardware byte counters)")
     args = ap.parse_args()
@@ -86,63 +243,54 @@ def main():
               "list is a design note, not built", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1407_5609_amd as cp
     import workloads as W
 
-    g = json.load(open(GOLDEN))
-    R2 = float.fromhex(g["R2"])
-    want_pair = (g["closest_pair"]["i"], g["closest_pair"]["j"], float.fromhex(g["closest_pair"]["d2"]))
-    want_pairs = np.array(g["frnn"]["pairs"], dtype=np.int64).reshape(-1, 2)
-    want_d2 = np.array([float.fromhex(v) for v in g["frnn"]["d2"]])
-
-    def note(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-    note("generating the mixture workload")
-    c = W.cfg_mixture()
-    Xh = c["X"]
-    n, d = Xh.shape
     torch.cuda.set_device(0)
-    X = torch.from_numpy(Xh).to("cuda:0")
+    note(f"generating the {args.workload} workload")
+    wl = WORKLOADS[args.workload](W, torch)
     ctx = cp.Context(0)
-
-    def run(prec, steps, warmup):
-        exact = True
-        for _ in range(warmup):
-            ctx.points(X, R2=R2, precision=prec)
-        torch.cuda.synchronize()
-        screen_ms, t0 = [], time.perf_counter()
-        for _ in range(steps):
-            best, (p, dd) = ctx.points(X, R2=R2, precision=prec)
-            st = ctx.stats()
-            screen_ms.append(st.screen_ms)
-            exact &= (best.i, best.j, best.d2) == want_pair
-            exact &= bool(np.array_equal(p.cpu().numpy(), want_pairs)) and bool(np.array_equal(dd.cpu().numpy(),
-                                                                                          want_d2))
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        return wall / steps, float(np.mean(screen_ms)), st, exact
 
     if args.calib_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
         dst = torch.empty_like(src)
         cp.dbg_copy(dst, src)
         del src, dst
-    note("timing the BF16-screened path")
-    ms_step, screen_ms, st, exact_bf16 = run("bf16", args.steps, args.warmup)
-    note(f"BF16: {ms_step * 1e3:.2f} ms/step; timing the plain FP32 path")
-    fp32 = run("f32", args.fp32_steps, 1) if args.fp32_steps > 0 else None
 
+    def run(prec, steps, warmup):
+        exact = True
+        for _ in range(warmup):
+            wl.step(ctx, prec)
+        torch.cuda.synchronize()
+        screen_ms, t0 = [], time.perf_counter()
+        for _ in range(steps):
+            exact &= bool(wl.step(ctx, prec))
+            st = ctx.stats()
+            screen_ms.append(st.screen_ms)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall / steps, sum(screen_ms) / len(screen_ms), st, exact
+
+    prec = wl.precs[0]
+    note(f"timing the {prec} path")
+    ms_step, screen_ms, st, exact = run(prec, args.steps, args.warmup)
+    note(f"{prec}: {ms_step * 1e3:.2f} ms/step")
+    pprec = PREC_NAME[st.precision]
+    peak, punit = PEAK[pprec]
     pairs = st.valid_pairs
-    value = pairs / ms_step
-    achieved = 2.0 * d * st.screen_pairs / (screen_ms * 1e-3) / 1e12
-    traffic = _traffic_per_launch()
+    if wl.graph:
+        # a graph replay records no per-launch events: the whole step's device work is the unit
+        work, dur_ms, kernel = wl.flops, ms_step * 1e3, "whole batched step (graph replay)"
+    else:
+        work, dur_ms = wl.flops_per_pair * st.screen_pairs, screen_ms
+        kernel = (f"screen256_kernel<{pprec}, min, full tiles>" if st.tile == 256
+                  else f"screen_kernel<{pprec}, min> (128-row tiles, all tiles)")
+    achieved = work / (dur_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": pairs / ms_step,
         "unit": "pair-evals/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -151,27 +299,33 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": pprec,
         "data": "synthetic",
-        "config": {"workload": f"mixture_n{n}_d{d}: exact closest pair + all pairs within R "
-                               "(BF16 matrix-core screen, FP64 verification)",
-                   "n": n, "d": d, "R": float.fromhex(g["R"]), "valid_pairs": pairs, "tile": st.tile},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_BF16_TFLOPS, "traffic": traffic,
-                     "kernel": "screen256_kernel<bf16, min, full tiles>", "avg_launch_ms": screen_ms,
-                     "flops_per_launch": 2.0 * d * st.screen_pairs},
-        "exact_match": bool(exact_bf16 and (fp32 is None or fp32[3])),
+        "config": dict(wl.config, valid_pairs=pairs, tile=st.tile),
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": punit, "frac": achieved / peak,
+                     "traffic": _traffic_per_launch() if args.workload == "mixture" else None,
+                     "kernel": kernel, "avg_launch_ms": dur_ms, "work_per_launch": work},
+        "exact_match": bool(exact),
         "screen_err_over_bound": st.max_err_over_bound,
     }
-    if fp32 is not None:
-        fp32_ms, fp32_screen_ms, st32, _ = fp32
-        tf = 2.0 * d * st32.screen_pairs / (fp32_screen_ms * 1e-3) / 1e12
-        out["fp32_plain"] = {"value": pairs / fp32_ms, "ms_per_step": fp32_ms * 1e3, "screen_tflops": tf,
-                             "screen_frac_of_fp32_peak": tf / PEAK_FP32_TFLOPS, "tile": st32.tile,
-                             "speedup_bf16_vs_fp32": fp32_ms / ms_step}
+    if len(wl.precs) > 1 and args.fp32_steps > 0:
+        cprec = wl.precs[1]
+        note(f"timing the {cprec} comparison path")
+        c_ms, c_screen_ms, st2, c_exact = run(cprec, args.fp32_steps, 1)
+        out["exact_match"] = bool(exact and c_exact)
+        leg = {"value": pairs / c_ms, "ms_per_step": c_ms * 1e3, "tile": st2.tile,
+               f"speedup_{prec}_vs_{cprec}": c_ms / ms_step}
+        if not wl.graph:
+            tf = wl.flops_per_pair * st2.screen_pairs / (c_screen_ms * 1e-3) / 1e12
+            leg.update(screen_tflops=tf, screen_frac_of_peak=tf / PEAK[PREC_NAME[st2.precision]][0])
+        out["fp32_plain" if cprec == "f32" else f"{cprec}_screen"] = leg
     if not args.no_cpu_baseline:
         note("timing the CPU oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(Xh)
+        import oracle
+        oracle.set_threads(min(16, os.cpu_count() or 1))
+        v, sample = wl.cpu_baseline(args.cpu_seconds)
+        out["cpu_baseline"] = {"value": v, "unit": "pair-evals/s", "cores": oracle.max_threads(), "kind": "oracle",
+                               "sample": sample}
     print(json.dumps(out), flush=True)
 
 

@@ -48,6 +48,11 @@ double cpmi_dbg_tile_bound(const float *bI, const float *bJ, int32_t kpad, int64
  * fragment read of that (row, chunk) looks}. */
 int cpmi_dbg_layout256(int wave, int q, int lane, int32_t *out4);
 
+/* Host only: byte offset of byte `byte` of row `row` in the screen operand
+ * of the 256-row screen (rows of `rowbytes` bytes, a multiple of 256),
+ * which is stored slice-major per block of 256 rows; -1 for bad arguments. */
+int64_t cpmi_dbg_xs_offset256(int64_t row, int64_t byte, int64_t rowbytes);
+
 /* Copy `bytes` (a multiple of 16) from src to dst (device, non-overlapping)
  * with a plain vector copy kernel: a launch of known traffic (bytes read,
  * bytes written) against which the hardware byte counters are scaled. */

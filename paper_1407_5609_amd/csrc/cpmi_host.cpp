@@ -1048,6 +1048,12 @@ int cpmi_dbg_tune(const char *cache_in, const char *cache_out, int ncu, int dtyp
     return rc;
 }
 
+int64_t cpmi_dbg_xs_offset256(int64_t row, int64_t byte, int64_t rowbytes)
+{
+    if (row < 0 || byte < 0 || rowbytes <= 0 || rowbytes % (4 * l256::SLICE) || byte >= rowbytes) return -1;
+    return l256::xs_offset(row, byte, rowbytes);
+}
+
 int cpmi_dbg_layout256(int wave, int q, int lane, int32_t *out4)
 {
     if (wave < 0 || wave > 3 || q < 0 || q >= l256::NQ || lane < 0 || lane > 63 || !out4) return CPMI_ERR_ARG;

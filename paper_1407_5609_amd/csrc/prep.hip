@@ -16,6 +16,7 @@
 // or two separately rounded operations, as the canonical definition requires.
 #include "bound.h"
 #include "cpmi_internal.h"
+#include "layout256.h"
 
 namespace cpmi {
 
@@ -107,6 +108,15 @@ void launch_reset_res(ResDev *r, int64_t n, hipStream_t st)
     if (n > 0) hipLaunchKernelGGL(reset_res_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, r, n);
 }
 
+// Element index of element k of row r in the screen operand (rows of kpad
+// elements of esz bytes): row-major for the 128-row screen, slice-major per
+// 256-row block for the 256-row screen (layout256.h).
+__device__ __forceinline__ int64_t xs_index(int64_t r, int64_t k, int32_t kpad, int esz, int tile)
+{
+    if (tile != 256) return r * (int64_t)kpad + k;
+    return l256::xs_offset(r, k * esz, (int64_t)kpad * esz) / esz;
+}
+
 // ---------------------------------------------------------------------------
 // points: one wave per row
 // ---------------------------------------------------------------------------
@@ -121,11 +131,10 @@ __global__ __launch_bounds__(256) void prep_points_kernel(const void *pts, int64
     const bool real = row < n;
     if constexpr (INT8_IN) {
         const signed char *x = (const signed char *)pts + row * ld;
-        signed char *o = (signed char *)xs + row * (int64_t)kpad;
         int s = 0;
         for (int64_t k = lane; k < kpad; k += 64) {
             const signed char v = (real && k < d) ? x[k] : (signed char)0;
-            o[k] = v;
+            ((signed char *)xs)[xs_index(row, k, kpad, 1, tile)] = v;
             s += (int)v * (int)v;
         }
 #pragma unroll
@@ -142,10 +151,10 @@ __global__ __launch_bounds__(256) void prep_points_kernel(const void *pts, int64
             float vt;
             if constexpr (PREC == P_BF16) {
                 const unsigned short h = f32_to_bf16_rne(v);
-                ((unsigned short *)xs)[row * (int64_t)kpad + k] = h;
+                ((unsigned short *)xs)[xs_index(row, k, kpad, 2, tile)] = h;
                 vt = bf16_to_f32(h);
             } else {
-                ((float *)xs)[row * (int64_t)kpad + k] = v;
+                ((float *)xs)[xs_index(row, k, kpad, 4, tile)] = v;
                 vt = v;
             }
             const double vd = (double)v, vtd = (double)vt;
@@ -260,11 +269,11 @@ __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs,
             float vt;
             if constexpr (PREC == P_BF16) {
                 const unsigned short h = f32_to_bf16_rne((float)xh);
-                ((unsigned short *)J.xs)[w * (int64_t)J.kpad + k] = h;
+                ((unsigned short *)J.xs)[xs_index(w, k, J.kpad, 2, tile)] = h;
                 vt = bf16_to_f32(h);
             } else {
                 vt = (float)xh;
-                ((float *)J.xs)[w * (int64_t)J.kpad + k] = vt;
+                ((float *)J.xs)[xs_index(w, k, J.kpad, 4, tile)] = vt;
             }
             const double vtd = (double)vt;
             s = fma(xh, xh, s);

@@ -175,6 +175,7 @@ __device__ __forceinline__ TileAddr tile_addr(const ScreenArgs &args, uint64_t e
     const uint32_t rowbytes = (uint32_t)P.kpad * ESZ;
     const unsigned char *xs = (const unsigned char *)P.xs;
     TileAddr ta;
+    // start of the 256-row blocks I and J (the same in either layout)
     ta.ga = xs + (int64_t)tile_I(ent) * T256 * rowbytes;
     ta.gb = xs + (int64_t)tile_J(ent) * T256 * rowbytes;
     ta.rowbytes = rowbytes;
@@ -183,19 +184,20 @@ __device__ __forceinline__ TileAddr tile_addr(const ScreenArgs &args, uint64_t e
 }
 
 // The 8 direct-to-LDS loads of one wave for K slice s of a tile (4 blocks of
-// 16 rows per operand).
+// 16 rows per operand). The operand is slice-major per 256-row block
+// (layout256.h: xs_offset), so slice s of the tile's rows is 16 KB of
+// consecutive memory and each load reads 1 KB of it.
 __device__ __forceinline__ void issue_slice(const TileAddr &ta, int s, int wave, unsigned char *__restrict__ wr)
 {
     unsigned char *la = wr;
     unsigned char *lb = wr + OPB;
-    // (row within a 16-row block) * rowbytes + swizzled column; the column
-    // swizzle of a lane does not depend on the block (layout256.h)
+    // (row within a 16-row block) * SL + swizzled column; the column swizzle
+    // of a lane does not depend on the block (layout256.h)
     const int lane = fresh_lane();
-    const uint32_t lane_off =
-        (uint32_t)l256::dma_row(0, 0, lane) * ta.rowbytes + (uint32_t)l256::dma_col(0, 0, lane);
+    const uint32_t lane_off = (uint32_t)l256::dma_row(0, 0, lane) * SL + (uint32_t)l256::dma_col(0, 0, lane);
 #pragma unroll
     for (int q = 0; q < l256::NQ; ++q) {
-        const uint32_t rb = (uint32_t)l256::dma_row(wave, q, 0) * ta.rowbytes + (uint32_t)(s * SL);
+        const uint32_t rb = (uint32_t)s * (T256 * SL) + (uint32_t)l256::dma_row(wave, q, 0) * SL;
         const int ldst = l256::dma_lds(wave, q, 0);
         __builtin_amdgcn_global_load_lds((g_void *)(ta.ga + rb + lane_off), (lds_void *)(la + ldst), 16, 0, 0);
         __builtin_amdgcn_global_load_lds((g_void *)(ta.gb + rb + lane_off), (lds_void *)(lb + ldst), 16, 0, 0);

@@ -322,3 +322,22 @@ def test_tune_cache_lookup_and_round_trip(lib, tmp_path):
     assert out2.read_text() == out.read_text()
     # unwritable destination is an argument error
     assert _tune(lib, c, F32, 2, 512, 10.0, cache_out=str(tmp_path / "no" / "dir.json"))[0] == -1
+
+
+@pytest.mark.parametrize("rowbytes", [256, 512, 1024])
+def test_blocked_operand_layout_is_a_bijection_and_slices_are_contiguous(lib, rowbytes):
+    """The 256-row screen's operand layout maps every (row, byte) of a padded
+    operand to a distinct offset inside it, and the 16 rows x 64 bytes that
+    one direct-to-LDS load reads are one contiguous 1 KB run."""
+    f = lib.cpmi_dbg_xs_offset256
+    f.restype = C.c_int64
+    f.argtypes = [C.c_int64, C.c_int64, C.c_int64]
+    npad = 512
+    offs = np.array([[f(r, b, rowbytes) for b in range(rowbytes)] for r in range(npad)], dtype=np.int64)
+    assert offs.min() == 0 and offs.max() == npad * rowbytes - 1
+    assert len(np.unique(offs)) == npad * rowbytes
+    for r0 in range(0, npad, 16):
+        for s in range(rowbytes // 64):
+            run = np.sort(offs[r0:r0 + 16, 64 * s:64 * s + 64].ravel())
+            assert run[-1] - run[0] == 1023 and np.all(np.diff(run) == 1)
+    assert f(0, rowbytes, rowbytes) == -1 and f(0, 0, 200) == -1
