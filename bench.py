@@ -106,10 +106,15 @@ class Points(Workload):
         self.flops_per_pair = 2.0 * self.d
         return g
 
+    query = "points"   # "cpp": the closest pair alone
+
     def step(self, ctx, prec):
         import numpy as np
-        best, (p, dd) = ctx.points(self.X, R2=self.R2, precision=prec)
         wp, wpairs, wd = self.want
+        if self.query == "cpp":
+            best = ctx.closest_pair(self.X, precision=prec)
+            return (best.i, best.j, best.d2) == wp
+        best, (p, dd) = ctx.points(self.X, R2=self.R2, precision=prec)
         return ((best.i, best.j, best.d2) == wp and np.array_equal(p.cpu().numpy(), wpairs)
                 and np.array_equal(dd.cpu().numpy(), wd))
 
@@ -235,6 +240,11 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the comparison precision (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--query", default="points", choices=["points", "cpp"],
+                    help="point workloads: closest pair + radius pairs (default) or the closest pair alone")
+    ap.add_argument("--prune", type=int, default=0,
+                    help="reference-point tile pruning with this many references (point workloads; 0: off)")
+    ap.add_argument("--prune-f", type=float, default=10.0, help="projection factor of the references")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (a reference launch for hardware byte counters)")
     args = ap.parse_args()
@@ -251,7 +261,14 @@ def main():
     torch.cuda.set_device(0)
     note(f"generating the {args.workload} workload")
     wl = WORKLOADS[args.workload](W, torch)
+    if args.query != "points":
+        if not isinstance(wl, Points):
+            sys.exit(f"--query {args.query} applies to the point workloads only")
+        wl.query = args.query
+        wl.config = dict(wl.config, query="closest pair only")
     ctx = cp.Context(0)
+    if args.prune:
+        ctx.set_pruning(args.prune, args.prune_f, seed=1)
 
     if args.calib_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
@@ -308,6 +325,9 @@ def main():
         "exact_match": bool(exact),
         "screen_err_over_bound": st.max_err_over_bound,
     }
+    if args.prune:
+        out["config"]["pruning"] = {"references": args.prune, "f": args.prune_f, "tiles_pruned": st.tiles_pruned,
+                                    "tiles_screened": st.tiles_total}
     if len(wl.precs) > 1 and args.fp32_steps > 0:
         cprec = wl.precs[1]
         note(f"timing the {cprec} comparison path")

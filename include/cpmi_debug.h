@@ -58,6 +58,13 @@ int64_t cpmi_dbg_xs_offset256(int64_t row, int64_t byte, int64_t rowbytes);
  * bytes written) against which the hardware byte counters are scaled. */
 int cpmi_dbg_copy(void *dst, const void *src, int64_t bytes, void *stream);
 
+/* Host only: the lower bound that reference-point pruning applies to every
+ * pair of a tile whose row blocks have, for each of q references, distance
+ * intervals [loI[k], hiI[k]] and [loJ[k], hiJ[k]] (host arrays of q
+ * doubles): max over k of the gap between the intervals, less a margin for
+ * the rounding of the distances (Section 3, triangle inequality). */
+double cpmi_dbg_tile_lb(const double *loI, const double *hiI, const double *loJ, const double *hiJ, int q);
+
 /* Host only: the tuning decisions of a context with `ncu` compute units
  * after reading the cache file cache_in (nullable): the precision and tile a
  * call with (dtype, precision, d, pairs) would use, as cpmi_tune_lookup. If

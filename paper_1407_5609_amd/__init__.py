@@ -39,7 +39,7 @@ class _CStats(C.Structure):
                 ("cpp_candidates", C.c_int64), ("frnn_candidates", C.c_int64), ("frnn_pairs", C.c_int64),
                 ("reruns", C.c_int64), ("max_err_over_bound", C.c_double), ("kernel_ms", C.c_double),
                 ("screen_ms", C.c_double), ("screen_pairs", C.c_int64), ("precision", C.c_int32),
-                ("tile", C.c_int32)]
+                ("tile", C.c_int32), ("tiles_pruned", C.c_int64)]
 
 
 class _CTune(C.Structure):
@@ -71,6 +71,7 @@ def _load():
     L.cpmi_last_error.restype = C.c_char_p
     L.cpmi_last_stats.argtypes = [vp, C.POINTER(_CStats)]
     L.cpmi_set_tile.argtypes = [vp, i32, i32]
+    L.cpmi_set_pruning.argtypes = [vp, i32, dbl, C.c_uint64]
     L.cpmi_version.restype = i32
     L.cpmi_closest_pair.argtypes = [vp, vp, i32, i64, i64, i64, i32, vp, C.POINTER(_CPair)]
     L.cpmi_frnn.argtypes = [vp, vp, i32, i64, i64, i64, dbl, i32, vp, vp, vp, i64, C.POINTER(i64)]
@@ -122,6 +123,7 @@ class Stats:
     screen_pairs: int
     precision: int
     tile: int
+    tiles_pruned: int
 
 
 def _prec(p) -> int:
@@ -186,6 +188,11 @@ class Context:
 
     def set_tile(self, precision, tile: int):
         self._check(_lib.cpmi_set_tile(self._h, _prec(precision), int(tile)))
+
+    def set_pruning(self, q: int, f: float = 10.0, seed: int = 0):
+        """Reference-point tile pruning for point sets (cpmi_set_pruning): q
+        references projected by f; q = 0 turns it off. Answers are unchanged."""
+        self._check(_lib.cpmi_set_pruning(self._h, int(q), float(f), int(seed)))
 
     def autotune(self, pts, precision="auto", reps: int = 3, stream=None) -> dict:
         """Time the screen configurations on `pts` and record the fastest in

@@ -17,6 +17,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <limits>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -45,6 +47,7 @@ struct HostProb {
     int64_t len = 0;                // series length (motif)
     int32_t kpad = 0;
     int64_t npad = 0;
+    const int32_t *perm = nullptr;  // screen row r holds source row perm[r] (reference-point order), or null
     // workspace offsets
     size_t xs_off = 0, sh_off = 0, bm_off = 0, mu_off = 0;
 };
@@ -92,6 +95,12 @@ struct cpmi_ctx {
     // captured batch graph
     hipGraphExec_t gexec = nullptr;
     std::vector<int64_t> graph_key;
+
+    // reference-point tile pruning of point sets (cpmi_set_pruning)
+    int prune_q = 0;
+    double prune_f = 10.0;
+    uint64_t prune_seed = 0;
+    DevBuf mD, mperm, mlo, mhi, mrefs;
 };
 
 namespace {
@@ -270,7 +279,11 @@ void load_tune_cache(cpmi_ctx *c, const char *path)
 // slot by slot, so that the work-groups the dispatcher sends to one XCD
 // (slot % 8) walk one chunk and keep its panels in that XCD's L2. For several
 // problems (uneven costs) the tiles are listed most-expensive problem first.
-void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t> &out, int64_t *nfull)
+// keep(I, J) (optional, single problem) drops tiles proved empty of answers;
+// jend[I] (optional) is a block column from which on every tile of row I is
+// dropped, so that the scan of a band can stop there.
+void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t> &out, int64_t *nfull,
+                 const std::function<bool(int64_t, int64_t)> &keep = {}, const std::vector<int64_t> *jend = nullptr)
 {
     std::vector<uint64_t> L, part;
     std::vector<size_t> order(hp.size());
@@ -285,15 +298,22 @@ void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t
         const HostProb &h = hp[p];
         if (pairs_of(h.n, h.excl) == 0) continue;
         const int64_t nT = (h.n + tile - 1) / tile;
-        for (int64_t b0 = 0; b0 < nT; b0 += G)
-            for (int64_t J = b0; J < nT; ++J)
+        for (int64_t b0 = 0; b0 < nT; b0 += G) {
+            int64_t jstop = nT;
+            if (jend) {
+                jstop = 0;
+                for (int64_t I = b0; I < std::min(b0 + G, nT); ++I) jstop = std::max(jstop, (*jend)[I]);
+            }
+            for (int64_t J = b0; J < jstop; ++J)
                 for (int64_t I = b0; I < std::min(b0 + G, nT) && I <= J; ++I) {
                     const int64_t maxj = std::min(J * tile + tile - 1, h.n - 1);
                     if (maxj - I * tile < h.excl) continue;
+                    if (keep && !keep(I, J)) continue;
                     const bool full = (J * tile - (I * tile + tile - 1) >= h.excl) && ((I + 1) * tile <= h.n) &&
                                       ((J + 1) * tile <= h.n);
                     (full ? L : part).push_back(tile_pack((uint32_t)p, (uint32_t)I, (uint32_t)J));
                 }
+        }
     }
     out.clear();
     if (hp.size() == 1) {
@@ -317,8 +337,12 @@ struct RunOut {
 };
 
 // Launch the whole exact search for the problems in hp; synchronises once.
+// `forced` (optional) is a tile list built by the caller (reference-point
+// pruning) with its first `forced_nfull` entries full tiles; it bypasses the
+// list cache.
 int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool want_cpp, bool want_frnn,
-               hipStream_t st, bool batch_graph, RunOut &ro)
+               hipStream_t st, bool batch_graph, RunOut &ro, const std::vector<uint64_t> *forced = nullptr,
+               int64_t forced_nfull = 0)
 {
     const int64_t np = (int64_t)hp.size();
     const int esz = elem_bytes(prec);
@@ -353,7 +377,19 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         key.push_back(h.excl);
         key.push_back(h.kpad);
     }
-    if (key != c->tiles_key) {
+    if (forced) {
+        const std::vector<uint64_t> &tl = *forced;
+        c->nfull = forced_nfull;
+        int64_t nreal = 0;
+        for (int64_t k = 0; k < forced_nfull; ++k) nreal += tl[k] != TILE_NONE;
+        c->nfull_pairs = nreal * (int64_t)tile * tile;
+        if ((rc = ensure(c, c->tiles, std::max<size_t>(tl.size(), 1) * 8))) return rc;
+        if ((rc = ensure(c, c->tile_min, std::max<size_t>(tl.size(), 1) * 4))) return rc;
+        if ((rc = ensure(c, c->sel, std::max<size_t>(tl.size(), 1) * 8))) return rc;
+        if (!tl.empty()) HIPCHK(c, hipMemcpyAsync(c->tiles.p, tl.data(), tl.size() * 8, hipMemcpyHostToDevice, st));
+        c->ntiles = (int64_t)tl.size();
+        c->tiles_key.clear();  // the cached list is gone
+    } else if (key != c->tiles_key) {
         // the screen kernels index the tile list with 32-bit integers
         double est = 0.0;
         for (auto &h : hp) {
@@ -408,6 +444,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             q.r2 = h.r2;
             // the 256-row screen folds the row scalars into the matrix product
             q.form = (tile == 256 && prec != P_I8) ? SCREEN_FOLDED : SCREEN_EPILOGUE;
+            q.perm = h.perm;
             if (h.motif) {
                 q.mu = (const double *)((char *)c->musg.p + h.mu_off);
                 q.sigma = (const double *)((char *)c->musg.p + mu_b + h.mu_off);
@@ -449,7 +486,8 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             } else {
                 const HostProb &h = hp[0];
                 launch_prep_points(h.src, h.src_i8 ? CPMI_I8 : CPMI_F32, h.n, h.d, h.ld, prec, P[0].xs ? (void *)P[0].xs : nullptr,
-                                   h.kpad, h.npad, (void *)P[0].shat, (float4 *)P[0].bmax, tile, &dres[0].flags, st);
+                                   h.kpad, h.npad, (void *)P[0].shat, (float4 *)P[0].bmax, tile, &dres[0].flags,
+                                   h.perm, st);
             }
             ScreenArgs a;
             memset(&a, 0, sizeof a);
@@ -493,8 +531,8 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             if (want_cpp) {
                 launch_verify_cpp(dprobs, (const Cand *)c->candU.p, dcnt + C_U, c->capU, prec, tile,
                                   (double *)c->cand_d2.p, dres, st);
-                launch_pick_cpp((const Cand *)c->candU.p, dcnt + C_U, c->capU, (const double *)c->cand_d2.p, dres,
-                                st);
+                launch_pick_cpp(dprobs, (const Cand *)c->candU.p, dcnt + C_U, c->capU, (const double *)c->cand_d2.p,
+                                dres, st);
             }
             if (want_frnn)
                 launch_verify_frnn(dprobs, (const Cand *)c->candR.p, dcnt + C_R, c->capR, prec, tile,
@@ -669,6 +707,104 @@ int set_device(cpmi_ctx *c)
     return CPMI_OK;
 }
 
+// Lower bound on the distance of every pair of a tile whose blocks have the
+// reference-distance intervals [loI, hiI] and [loJ, hiJ] (q references): by
+// the triangle inequality |d(r,x) - d(r,y)| <= d(x,y), so the gap between the
+// intervals of any one reference bounds every pair. The distances carry a
+// relative rounding error far below 2^-40 (FP64 sums of at most 2^20
+// squares); 2^-34 of the larger endpoint is subtracted for it.
+double tile_lower_bound(const double *loI, const double *hiI, const double *loJ, const double *hiJ, int q)
+{
+    double lb = 0.0;
+    for (int k = 0; k < q; ++k) {
+        double g = std::max(loJ[k] - hiI[k], loI[k] - hiJ[k]);
+        g -= 0x1p-34 * std::max(std::fabs(hiI[k]), std::fabs(hiJ[k]));
+        lb = std::max(lb, g);
+    }
+    return lb;
+}
+
+uint64_t splitmix64(uint64_t x)
+{
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+
+// Reference-point pruning of one point set (Section 3, MPR steps 1-3): order
+// the rows by their distance to the first projected reference (h.perm) and
+// bring back to the host, per block of `tile` rows in that order and per
+// reference, the interval of distances (lo, hi: nT x q). Synchronises once.
+int prune_prepare(cpmi_ctx *c, HostProb &h, int tile, hipStream_t st, std::vector<double> &lo,
+                  std::vector<double> &hi)
+{
+    const int q = c->prune_q;
+    const int64_t n = h.n;
+    const int dtype = h.src_i8 ? CPMI_I8 : CPMI_F32;
+    const int64_t nT = (n + tile - 1) / tile;
+    int64_t mpad = 1;
+    while (mpad < n) mpad <<= 1;
+    int rc;
+    if ((rc = ensure(c, c->mD, (size_t)q * n * 8))) return rc;
+    if ((rc = ensure(c, c->mperm, (size_t)n * 4))) return rc;
+    if ((rc = ensure(c, c->mlo, (size_t)nT * q * 8))) return rc;
+    if ((rc = ensure(c, c->mhi, (size_t)nT * q * 8))) return rc;
+    if ((rc = ensure(c, c->mrefs, (size_t)q * 4))) return rc;
+    if ((rc = ensure(c, c->keys, (size_t)mpad * 8))) return rc;
+    if ((rc = ensure(c, c->vals, (size_t)mpad * 8))) return rc;
+    std::vector<int32_t> refs(q);
+    for (int k = 0; k < q; ++k) refs[k] = (int32_t)(splitmix64(c->prune_seed * 64 + (uint64_t)k) % (uint64_t)n);
+    HIPCHK(c, hipMemcpyAsync(c->mrefs.p, refs.data(), q * 4, hipMemcpyHostToDevice, st));
+    double *D = (double *)c->mD.p;
+    int32_t *perm = (int32_t *)c->mperm.p;
+    launch_ref_dist(h.src, dtype, n, h.d, h.ld, (const int32_t *)c->mrefs.p, q, c->prune_f, D, st);
+    launch_ref_keys(D, n, (uint64_t *)c->keys.p, (double *)c->vals.p, st);
+    launch_sort_pairs((uint64_t *)c->keys.p, (double *)c->vals.p, n, mpad, st);
+    launch_perm_from_sorted((const double *)c->vals.p, n, perm, st);
+    launch_block_range(D, n, q, perm, tile, nT, (double *)c->mlo.p, (double *)c->mhi.p, st);
+    HIPCHK(c, hipGetLastError());
+    lo.assign((size_t)nT * q, 0.0);
+    hi.assign((size_t)nT * q, 0.0);
+    HIPCHK(c, hipMemcpyAsync(lo.data(), c->mlo.p, lo.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync(hi.data(), c->mhi.p, hi.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    h.perm = perm;
+    return CPMI_OK;
+}
+
+// Tile list of the rows in reference order without the tiles whose lower
+// bound exceeds T (MPR's test of step 5, per tile). *npruned counts the
+// dropped tiles. band >= 0 keeps only the tiles with J - I <= band.
+void pruned_tiles(const HostProb &h, int tile, int q, const std::vector<double> &lo, const std::vector<double> &hi,
+                  double T, int64_t band, std::vector<uint64_t> &tl, int64_t &nfull, int64_t &npruned)
+{
+    const int64_t nT = (h.n + tile - 1) / tile;
+    auto lb = [&](int64_t I, int64_t J) {
+        return tile_lower_bound(&lo[I * q], &hi[I * q], &lo[J * q], &hi[J * q], q);
+    };
+    // the rows are ordered by reference 0, so its gap only grows with J: jend[I]
+    // is the first block column whose reference-0 gap alone exceeds T
+    std::vector<int64_t> jend(nT);
+    for (int64_t I = 0; I < nT; ++I) {
+        int64_t a = I, b = nT;
+        while (a < b) {
+            const int64_t m = (a + b) / 2;
+            const double g = lo[m * q] - hi[I * q] - 0x1p-34 * std::max(std::fabs(hi[I * q]), std::fabs(hi[m * q]));
+            if (g > T) b = m;
+            else a = m + 1;
+        }
+        jend[I] = band >= 0 ? std::min(a, I + band + 1) : a;
+    }
+    std::vector<HostProb> one(1, h);
+    build_tiles(
+        one, tile, tl, &nfull,
+        [&](int64_t I, int64_t J) { return (band < 0 || J - I <= band) && !(lb(I, J) > T); }, &jend);
+    int64_t kept = 0;
+    for (uint64_t e : tl) kept += e != TILE_NONE;
+    npruned = nT * (nT + 1) / 2 - kept;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -708,8 +844,9 @@ int cpmi_destroy(cpmi_ctx *c)
     hipSetDevice(c->device);
     hipDeviceSynchronize();
     if (c->gexec) hipGraphExecDestroy(c->gexec);
-    DevBuf *bufs[] = {&c->xs, &c->shat, &c->bmax, &c->musg, &c->probs, &c->jobs, &c->tiles, &c->tile_min, &c->sel,
-                      &c->candR, &c->candU, &c->cand_d2, &c->keys, &c->vals, &c->cnt, &c->ubits, &c->res};
+    DevBuf *bufs[] = {&c->xs,      &c->shat,  &c->bmax, &c->musg, &c->probs, &c->jobs, &c->tiles, &c->tile_min,
+                      &c->sel,     &c->candR, &c->candU, &c->cand_d2, &c->keys, &c->vals, &c->cnt, &c->ubits,
+                      &c->res,     &c->mD,    &c->mperm, &c->mlo, &c->mhi,   &c->mrefs};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
     if (c->pinned) hipHostFree(c->pinned);
@@ -728,6 +865,17 @@ int cpmi_last_stats(cpmi_ctx *c, cpmi_stats *out)
 {
     if (!c || !out) return CPMI_ERR_ARG;
     *out = c->stats;
+    return CPMI_OK;
+}
+
+int cpmi_set_pruning(cpmi_ctx *c, int q, double f, uint64_t seed)
+{
+    if (!c) return CPMI_ERR_ARG;
+    if (q < 0 || q > 32) return fail(c, CPMI_ERR_ARG, "q must be in 0..32");
+    if (!(f > 0.0) || !std::isfinite(f)) return fail(c, CPMI_ERR_ARG, "f must be finite and > 0");
+    c->prune_q = q;
+    c->prune_f = f;
+    c->prune_seed = seed;
     return CPMI_OK;
 }
 
@@ -778,7 +926,31 @@ int cpmi_points(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d, i
     hp[0].r2 = want_frnn ? R2 : -1.0;
     const int tile = pick_tile(c, prec, d, npairs);
     RunOut ro;
-    if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro))) return rc;
+    if (c->prune_q > 0 && n > tile) {
+        // MPR keeps a running upper bound of the least distance; here it comes
+        // from a first search over the diagonal band of the reference order
+        // (neighbouring blocks, where close pairs land), and the full search
+        // then skips every tile whose reference bound exceeds it and the radius
+        std::vector<double> lo, hi;
+        if ((rc = prune_prepare(c, hp[0], tile, st, lo, hi))) return rc;
+        std::vector<uint64_t> tl;
+        int64_t nfull = 0, npruned = 0;
+        const double inf = std::numeric_limits<double>::infinity();
+        double thr2 = want_frnn ? R2 : 0.0;
+        if (want_cpp) {
+            pruned_tiles(hp[0], tile, c->prune_q, lo, hi, inf, 1, tl, nfull, npruned);
+            RunOut band;
+            if ((rc = run_search(c, hp, prec, tile, true, false, st, false, band, &tl, nfull))) return rc;
+            if ((rc = flags_error(c, band.res[0].flags))) return rc;
+            const double u = __builtin_bit_cast(double, (uint64_t)band.res[0].best_d2);
+            thr2 = std::max(thr2, std::isfinite(u) ? u : inf);
+        }
+        pruned_tiles(hp[0], tile, c->prune_q, lo, hi, std::sqrt(thr2) * (1.0 + 0x1p-30), -1, tl, nfull, npruned);
+        if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro, &tl, nfull))) return rc;
+        c->stats.tiles_pruned = npruned;
+    } else {
+        if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro))) return rc;
+    }
     if ((rc = flags_error(c, ro.res[0].flags))) return rc;
     if (want_cpp) {
         fill_pair(ro.res[0], best);
@@ -1033,6 +1205,12 @@ int cpmi_dbg_copy(void *dst, const void *src, int64_t bytes, void *stream)
     if (hipGetLastError() != hipSuccess) return CPMI_ERR_HIP;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return CPMI_ERR_HIP;
     return CPMI_OK;
+}
+
+double cpmi_dbg_tile_lb(const double *loI, const double *hiI, const double *loJ, const double *hiJ, int q)
+{
+    if (!loI || !hiI || !loJ || !hiJ || q < 1) return -1.0;
+    return tile_lower_bound(loI, hiI, loJ, hiJ, q);
 }
 
 int cpmi_dbg_tune(const char *cache_in, const char *cache_out, int ncu, int dtype, int precision, int64_t d,

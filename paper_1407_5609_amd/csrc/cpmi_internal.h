@@ -43,7 +43,11 @@ struct Prob {
     double r2;             // squared radius (negative: no radius search)
     int32_t form;          // screen value form of the screen used (SCREEN_EPILOGUE / SCREEN_FOLDED)
     int32_t pad_;
+    const int32_t *perm;   // screen row r holds source row perm[r] (reference-point order), or null
 };
+
+// Source row of screen row r.
+__host__ __device__ inline int64_t src_row(const Prob &P, int64_t r) { return P.perm ? (int64_t)P.perm[r] : r; }
 
 // Tile-list entry: problem (20 bits) | block row I (22 bits) | block col J (22 bits).
 __host__ __device__ inline uint64_t tile_pack(uint32_t p, uint32_t I, uint32_t J)
@@ -110,7 +114,7 @@ void launch_calib_copy(const void *src, void *dst, int64_t n16, hipStream_t st);
 // per-block maxima (bmax must be zero on entry), flags.
 void launch_prep_points(const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, int prec, void *xs,
                         int32_t kpad, int64_t npad, void *shat, float4 *bmax, int tile, unsigned int *flags,
-                        hipStream_t st);
+                        const int32_t *perm, hipStream_t st);
 
 // Window builder of many series: canonical mean/sigma, z-normalised screen
 // operand, row scalars, block maxima (zero on entry), flags.
@@ -133,14 +137,21 @@ void launch_select(const Prob *probs, const uint64_t *tiles, int64_t ntiles, con
 // Candidate verification in canonical FP64 (exact int64 for int8).
 void launch_verify_cpp(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec, int tile,
                        double *cand_d2, ResDev *res, hipStream_t st);
-void launch_pick_cpp(const Cand *cand, const uint32_t *cnt, uint32_t cap, const double *cand_d2, ResDev *res,
-                     hipStream_t st);
+void launch_pick_cpp(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, const double *cand_d2,
+                     ResDev *res, hipStream_t st);
 void launch_verify_frnn(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec, int tile,
                         uint64_t *keys, double *vals, uint32_t *out_cnt, uint32_t out_cap, ResDev *res,
                         hipStream_t st);
 // Sort m (key, value) pairs by key; arrays hold mpad >= m entries (mpad a power
 // of two), the tail is overwritten with sentinels.
 void launch_sort_pairs(uint64_t *keys, double *vals, int64_t m, int64_t mpad, hipStream_t st);
+// reference-point pruning (mpr.hip)
+void launch_ref_dist(const void *X, int dtype, int64_t n, int64_t d, int64_t ld, const int32_t *refs, int q,
+                     double f, double *D, hipStream_t st);
+void launch_ref_keys(const double *D0, int64_t n, uint64_t *keys, double *vals, hipStream_t st);
+void launch_perm_from_sorted(const double *vals, int64_t n, int32_t *perm, hipStream_t st);
+void launch_block_range(const double *D, int64_t n, int q, const int32_t *perm, int tile, int64_t nblk, double *lo,
+                        double *hi, hipStream_t st);
 // Unpack sorted keys (i << 32 | j) into int64 pairs [m][2] and copy values.
 void launch_emit_pairs(const uint64_t *keys, const double *vals, int64_t m, int64_t *pairs, double *d2,
                        hipStream_t st);

@@ -123,14 +123,17 @@ __device__ __forceinline__ int64_t xs_index(int64_t r, int64_t k, int32_t kpad, 
 template <int PREC, bool INT8_IN>
 __global__ __launch_bounds__(256) void prep_points_kernel(const void *pts, int64_t n, int64_t d, int64_t ld,
                                                           void *xs, int32_t kpad, int64_t npad, void *shat,
-                                                          float4 *bmax, int tile, unsigned int *flags)
+                                                          float4 *bmax, int tile, unsigned int *flags,
+                                                          const int32_t *perm)
 {
     const int lane = threadIdx.x & 63;
     const int64_t row = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= npad) return;
     const bool real = row < n;
+    // screen row `row` holds source row srow (a permutation of 0..n-1, or the identity)
+    const int64_t srow = (real && perm) ? (int64_t)perm[row] : row;
     if constexpr (INT8_IN) {
-        const signed char *x = (const signed char *)pts + row * ld;
+        const signed char *x = (const signed char *)pts + srow * ld;
         int s = 0;
         for (int64_t k = lane; k < kpad; k += 64) {
             const signed char v = (real && k < d) ? x[k] : (signed char)0;
@@ -142,7 +145,7 @@ __global__ __launch_bounds__(256) void prep_points_kernel(const void *pts, int64
         if (lane == 0) ((int *)shat)[row] = s;
         return;
     } else {
-        const float *x = (const float *)pts + row * ld;
+        const float *x = (const float *)pts + srow * ld;
         double s = 0.0, t2 = 0.0, r2 = 0.0;
         bool bad = false;
         for (int64_t k = lane; k < kpad; k += 64) {
@@ -185,18 +188,18 @@ __global__ __launch_bounds__(256) void prep_points_kernel(const void *pts, int64
 
 void launch_prep_points(const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, int prec, void *xs,
                         int32_t kpad, int64_t npad, void *shat, float4 *bmax, int tile, unsigned int *flags,
-                        hipStream_t st)
+                        const int32_t *perm, hipStream_t st)
 {
     dim3 g((unsigned)((npad + 3) / 4)), b(256);
     if (dtype == 1)
         hipLaunchKernelGGL((prep_points_kernel<P_I8, true>), g, b, 0, st, pts, n, d, ld, xs, kpad, npad, shat, bmax,
-                           tile, flags);
+                           tile, flags, perm);
     else if (prec == P_BF16)
         hipLaunchKernelGGL((prep_points_kernel<P_BF16, false>), g, b, 0, st, pts, n, d, ld, xs, kpad, npad, shat,
-                           bmax, tile, flags);
+                           bmax, tile, flags, perm);
     else
         hipLaunchKernelGGL((prep_points_kernel<P_F32, false>), g, b, 0, st, pts, n, d, ld, xs, kpad, npad, shat,
-                           bmax, tile, flags);
+                           bmax, tile, flags, perm);
 }
 
 // ---------------------------------------------------------------------------

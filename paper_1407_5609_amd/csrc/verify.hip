@@ -185,6 +185,14 @@ __device__ __forceinline__ void record_error(ResDev *r, double dt, double d2, do
     }
 }
 
+// Source rows (a < b) of a candidate, whose screen rows may be permuted.
+__device__ __forceinline__ void cand_rows(const Prob &P, const Cand &cd, int64_t &a, int64_t &b)
+{
+    const int64_t x = src_row(P, cd.i), y = src_row(P, cd.j);
+    a = x < y ? x : y;
+    b = x < y ? y : x;
+}
+
 __global__ void verify_cpp_kernel(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec,
                                   int tile, double *cand_d2, ResDev *res)
 {
@@ -192,21 +200,26 @@ __global__ void verify_cpp_kernel(const Prob *probs, const Cand *cand, const uin
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < m; c += (int64_t)gridDim.x * blockDim.x) {
         const Cand cd = cand[c];
         const Prob &P = probs[cd.p];
-        const double d2 = canonical_d2(P, cd.i, cd.j);
+        int64_t a, b;
+        cand_rows(P, cd, a, b);
+        const double d2 = canonical_d2(P, a, b);
         cand_d2[c] = d2;
         atomicMin(&res[cd.p].best_d2, (unsigned long long)__double_as_longlong(d2));
         record_error(&res[cd.p], (double)cd.dt, d2, tile_bound_of(P, cd.i / tile, cd.j / tile, prec));
     }
 }
 
-__global__ void pick_cpp_kernel(const Cand *cand, const uint32_t *cnt, uint32_t cap, const double *cand_d2,
-                                ResDev *res)
+__global__ void pick_cpp_kernel(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap,
+                                const double *cand_d2, ResDev *res)
 {
     const int64_t m = min((int64_t)*cnt, (int64_t)cap);
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < m; c += (int64_t)gridDim.x * blockDim.x) {
         const Cand cd = cand[c];
-        if ((unsigned long long)__double_as_longlong(cand_d2[c]) == res[cd.p].best_d2)
-            atomicMin(&res[cd.p].best_ij, ((unsigned long long)(unsigned)cd.i << 32) | (unsigned)cd.j);
+        if ((unsigned long long)__double_as_longlong(cand_d2[c]) == res[cd.p].best_d2) {
+            int64_t a, b;
+            cand_rows(probs[cd.p], cd, a, b);
+            atomicMin(&res[cd.p].best_ij, ((unsigned long long)(unsigned)a << 32) | (unsigned)b);
+        }
     }
 }
 
@@ -218,12 +231,15 @@ __global__ void verify_frnn_kernel(const Prob *probs, const Cand *cand, const ui
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < m; c += (int64_t)gridDim.x * blockDim.x) {
         const Cand cd = cand[c];
         const Prob &P = probs[cd.p];
-        const double d2 = canonical_d2(P, cd.i, cd.j);
+        int64_t a, b;
+        cand_rows(P, cd, a, b);
+        const double d2 = canonical_d2(P, a, b);
+        // the bound is indexed by screen-row blocks
         record_error(&res[cd.p], (double)cd.dt, d2, tile_bound_of(P, cd.i / tile, cd.j / tile, prec));
         if (d2 <= P.r2) {
             const uint32_t k = atomicAdd(out_cnt, 1u);
             if (k < out_cap) {
-                keys[k] = ((uint64_t)(uint32_t)cd.i << 32) | (uint32_t)cd.j;
+                keys[k] = ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
                 vals[k] = d2;
             }
         }
@@ -239,10 +255,10 @@ void launch_verify_cpp(const Prob *probs, const Cand *cand, const uint32_t *cnt,
                        cand_d2, res);
 }
 
-void launch_pick_cpp(const Cand *cand, const uint32_t *cnt, uint32_t cap, const double *cand_d2, ResDev *res,
-                     hipStream_t st)
+void launch_pick_cpp(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, const double *cand_d2,
+                     ResDev *res, hipStream_t st)
 {
-    hipLaunchKernelGGL(pick_cpp_kernel, dim3(256), dim3(256), 0, st, cand, cnt, cap, cand_d2, res);
+    hipLaunchKernelGGL(pick_cpp_kernel, dim3(256), dim3(256), 0, st, probs, cand, cnt, cap, cand_d2, res);
 }
 
 void launch_verify_frnn(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec, int tile,

@@ -341,3 +341,67 @@ def test_blocked_operand_layout_is_a_bijection_and_slices_are_contiguous(lib, ro
             run = np.sort(offs[r0:r0 + 16, 64 * s:64 * s + 64].ravel())
             assert run[-1] - run[0] == 1023 and np.all(np.diff(run) == 1)
     assert f(0, rowbytes, rowbytes) == -1 and f(0, 0, 200) == -1
+
+
+# --------------------------------------------------------------------------
+# reference-point lower bound (Section 3)
+# --------------------------------------------------------------------------
+
+def _lb(lib, loI, hiI, loJ, hiJ):
+    f = lib.cpmi_dbg_tile_lb
+    f.restype = C.c_double
+    f.argtypes = [C.c_void_p] * 4 + [C.c_int]
+    arr = [np.ascontiguousarray(a, dtype=np.float64) for a in (loI, hiI, loJ, hiJ)]
+    return f(*(a.ctypes.data for a in arr), len(arr[0]))
+
+
+def test_reference_bound_reproduces_the_papers_worked_example(lib):
+    """Section 3.2: x = (0,0), y = (1,0); a reference at distance sqrt(2) from
+    x at 45 degrees bounds d(x,y) by 0.414, at 30 degrees by 0.6722; at
+    distance 10 the same angles give 0.6803 and 0.8526; at 45 degrees the bound
+    tends to 1/sqrt(2) as the reference moves away (the projection idea)."""
+    x, y = np.array([0.0, 0.0]), np.array([1.0, 0.0])
+
+    def bound(r):
+        dx, dy = np.linalg.norm(r - x), np.linalg.norm(r - y)
+        return _lb(lib, [dx], [dx], [dy], [dy])           # single points: degenerate intervals
+    pol = lambda rad, deg: rad * np.array([np.cos(np.radians(deg)), np.sin(np.radians(deg))])
+    # printed to 3-4 decimals; two printed values are off in the fourth decimal
+    # (0.6803 for the exact 0.680243, 0.8526 for the exact 0.852350), so the
+    # printed values are matched to 3e-4 and the exact ones to 1e-6
+    assert abs(bound(pol(np.sqrt(2), 45)) - 0.414) < 5e-4
+    assert abs(bound(pol(np.sqrt(2), 30)) - 0.6722) < 3e-4
+    assert abs(bound(pol(10.0, 45)) - 0.6803) < 3e-4
+    assert abs(bound(pol(10.0, 30)) - 0.8526) < 3e-4
+    assert abs(bound(pol(10.0, 45)) - 0.680243) < 1e-6
+    assert abs(bound(pol(10.0, 30)) - 0.852350) < 1e-6
+    # Section 3.4, case 1 (reference beyond the bisector on y's side): the bound
+    # tends to c cos(theta) as the reference is projected out (s = d(A,R)/c
+    # grows), within the paper's c/(2s) term, and grows with s
+    for s_ in (1e2, 1e3, 1e4):
+        assert abs(bound(pol(s_, 45)) - np.cos(np.radians(45))) <= 1 / (2 * s_)
+    vals = [bound(pol(s_, 45)) for s_ in (np.sqrt(2), 10.0, 1e2, 1e4)]
+    assert all(a < b for a, b in zip(vals, vals[1:]))
+    # the reference on the perpendicular bisector bounds nothing
+    assert bound(np.array([0.5, 3.0])) == 0.0
+    # several references: the best one counts
+    assert abs(_lb(lib, [1.0, np.sqrt(2)], [1.0, np.sqrt(2)], [1.0, 1.0], [1.0, 1.0]) - (np.sqrt(2) - 1)) < 1e-9
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tile_bound_holds_for_every_pair_of_random_blocks(lib, seed):
+    """Blocks of points, intervals of their distances to projected references:
+    the bound never exceeds the least distance between the two blocks, and it
+    is positive for well separated blocks (it has teeth)."""
+    rng = np.random.default_rng(seed)
+    d, q = 16, 4
+    A = rng.normal(0, 1, (40, d))
+    B = rng.normal(0, 1, (40, d)) + (0.0 if seed == 0 else 6.0)
+    R = 10.0 * rng.normal(0, 1, (q, d))                    # projected references (f = 10)
+    DA = np.linalg.norm(A[:, None, :] - R[None], axis=2)
+    DB = np.linalg.norm(B[:, None, :] - R[None], axis=2)
+    lb = _lb(lib, DA.min(0), DA.max(0), DB.min(0), DB.max(0))
+    dmin = np.min(np.linalg.norm(A[:, None, :] - B[None], axis=2))
+    assert 0.0 <= lb <= dmin
+    if seed != 0:
+        assert lb > 1.0

@@ -79,6 +79,26 @@ def test_mixture_full_size_golden(ctx, torch_dev):
         assert oracle.d2(X, i, j) >= want_pair[2]
 
 
+def test_mixture_full_size_golden_with_pruning(ctx, torch_dev):
+    """The same answer with reference-point tile pruning on; most tiles are
+    dropped (the rows cluster around 64 centres)."""
+    g = _golden("mixture_n262144_d512.json")
+    want_pair, want_pairs, want_d2 = _want(g)
+    X = W.cfg_mixture()["X"]
+    t = _dev(X, torch_dev)
+    ctx.set_pruning(8, 10.0, seed=1)
+    try:
+        best, (p, d) = ctx.points(t, R2=float.fromhex(g["R2"]), precision="bf16")
+        st = ctx.stats()
+    finally:
+        ctx.set_pruning(0)
+    assert (best.i, best.j, best.d2) == want_pair
+    assert np.array_equal(p.cpu().numpy(), want_pairs)
+    assert np.array_equal(d.cpu().numpy(), want_d2)
+    assert st.tiles_pruned > 0 and st.valid_pairs == W.valid_pairs_points(X.shape[0])
+    print("pruned", st.tiles_pruned, "of", st.tiles_pruned + st.tiles_total, "tiles")
+
+
 def _window_d2(T, ell, i, j):
     """Canonical squared distance of windows i and j, each z-normalised on its own."""
     a, _, _ = oracle.znorm(T[i:i + ell], ell)

@@ -361,3 +361,65 @@ def test_calibration_copy_moves_every_byte(torch_dev):
     assert torch.equal(dst, src)
     with pytest.raises(ValueError):
         cp.dbg_copy(dst[:-1], src)
+
+
+# ---------------------------------------------------------------------------
+# reference-point tile pruning (Section 3, MPR): same answers, fewer tiles
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("q", [1, 4])
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_pruned_points_match_oracle(ctx, torch_dev, tile, prec, q):
+    rng = np.random.default_rng(100 + q)
+    X, _ = W.mixture_points(rng, 3000, 48)
+    R2 = 30.0
+    ctx.set_pruning(q, 10.0, seed=q)
+    try:
+        best, fr = ctx.points(_dev(X, torch_dev), R2=R2, precision=prec)
+        st = ctx.stats()
+    finally:
+        ctx.set_pruning(0)
+    _check_pair(best, oracle.closest_pair(X))
+    _check_frnn(fr, oracle.frnn(X, R2))
+    assert st.tiles_pruned > 0
+    assert st.max_err_over_bound <= 1.0
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_pruned_ties_go_to_lexicographic_minimum_in_input_order(ctx, torch_dev, tile, prec):
+    """Exact duplicates land anywhere in the reference order; the reported pair
+    is still the lexicographically least in the caller's indices."""
+    rng = np.random.default_rng(8)
+    X, _ = W.mixture_points(rng, 2500, 32)
+    for a, b in ((1700, 90), (2400, 90), (90, 600)):
+        X[a] = X[b]
+    ctx.set_pruning(3, 10.0, seed=5)
+    try:
+        best, fr = ctx.points(_dev(X, torch_dev), R2=0.0, precision=prec)
+    finally:
+        ctx.set_pruning(0)
+    assert (best.i, best.j, best.d2) == oracle.closest_pair(X) == (90, 600, 0.0)
+    _check_frnn(fr, oracle.frnn(X, 0.0))
+
+
+def test_pruned_int8_and_frnn_only(ctx, torch_dev, tile):
+    rng = np.random.default_rng(21)
+    X = W.snp_matrix(rng, 1500, 512)
+    W.plant_snp_pairs(rng, X, m=(2, 9, 30))
+    ctx.set_pruning(4, 10.0)
+    try:
+        best = ctx.closest_pair(_dev(X, torch_dev), precision="i8")
+        p, d = ctx.frnn(_dev(X, torch_dev), 40, precision="i8")
+    finally:
+        ctx.set_pruning(0)
+    oi, oj, od = oracle.closest_pair(X)
+    assert (best.i, best.j, best.d2) == (oi, oj, float(od))
+    _check_frnn((p, d), oracle.frnn(X, 40))
+
+
+def test_pruning_arguments(ctx):
+    import paper_1407_5609_amd as cp
+    for q, f in ((-1, 10.0), (33, 10.0), (2, 0.0), (2, float("nan"))):
+        with pytest.raises(cp.CpmiError):
+            ctx.set_pruning(q, f)
+    ctx.set_pruning(0)
