@@ -15,7 +15,8 @@ pass-1 screen), timed with HIP events on the call's stream; `cpu_baseline` is
 the CPU oracle on a bounded sample (rank 0, N = 1 only).
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
-    python bench.py --workload {mixture,points,motif,batch,snp}   (the other workloads, same JSON form)
+    python bench.py --workload {mixture,points,motif,walk,batch,snp}   (the other workloads, same JSON form)
+    python bench.py --workload walk --prune 10                   (reference-point tile pruning)
 """
 import argparse
 import hashlib
@@ -162,22 +163,28 @@ class Snp(Points):
 
 class Motif(Workload):
     name = "motif"
+    query = "points"   # "cpp": the motif alone, no radius pairs
 
     def __init__(self, W, torch):
-        g = _golden("motif_L65536_l256.json")
+        self._setup(torch, W.cfg_motif(), "motif_L65536_l256.json")
+
+    def _setup(self, torch, c, golden):
+        g = _golden(golden)
         self.R2 = float.fromhex(g["R2"])
         self.want = _want(g)
-        c = W.cfg_motif()
         self.Th, self.ell, self.excl = c["T"], c["ell"], c["excl"]
         self.T = torch.from_numpy(self.Th).to("cuda:0")
         self.flops_per_pair = 2.0 * self.ell
-        self.config = {"workload": f"motif_L{len(self.Th)}_l{self.ell}: exact z-normalised motif + all window pairs "
-                                   "within R=2 (exclusion l)", "length": len(self.Th), "ell": self.ell}
+        self.config = {"workload": f"{c['name']}: exact z-normalised motif + all window pairs within "
+                                   f"R={c['R']:g} (exclusion l)", "length": len(self.Th), "ell": self.ell}
 
     def step(self, ctx, prec):
         import numpy as np
-        best, (p, dd) = ctx.motif(self.T, self.ell, excl=self.excl, R2=self.R2, precision=prec)
         wp, wpairs, wd = self.want
+        if self.query == "cpp":
+            best, _ = ctx.motif(self.T, self.ell, excl=self.excl, precision=prec)
+            return (best.i, best.j, best.d2) == wp
+        best, (p, dd) = ctx.motif(self.T, self.ell, excl=self.excl, R2=self.R2, precision=prec)
         return ((best.i, best.j, best.d2) == wp and np.array_equal(p.cpu().numpy(), wpairs)
                 and np.array_equal(dd.cpu().numpy(), wd))
 
@@ -191,6 +198,15 @@ class Motif(Workload):
         L, dt = _timed_oracle(lambda L: oracle.motif(T[:L], ell), grow, target_s)
         pairs = W.valid_pairs_motif(L, ell, ell)
         return pairs / dt, f"motif of the first {L} samples of the series ({pairs} window pairs, l={ell}), {dt:.1f} s"
+
+
+class Walk(Motif):
+    """The random-walk shape the paper measures reference-point pruning on
+    (100,000 samples, windows of 1,024); run it with --prune 10."""
+    name = "walk"
+
+    def __init__(self, W, torch):
+        self._setup(torch, W.cfg_walk(), "walk_L100000_l1024.json")
 
 
 class Batch(Workload):
@@ -228,7 +244,7 @@ class Batch(Workload):
         return pairs / dt, f"motifs of the first {k} series of the batch ({pairs} window pairs), {dt:.1f} s"
 
 
-WORKLOADS = {w.name: w for w in (Mixture, SmallPoints, Motif, Batch, Snp)}
+WORKLOADS = {w.name: w for w in (Mixture, SmallPoints, Motif, Walk, Batch, Snp)}
 
 
 def main():
@@ -241,9 +257,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--query", default="points", choices=["points", "cpp"],
-                    help="point workloads: closest pair + radius pairs (default) or the closest pair alone")
+                    help="point and single-series motif workloads: closest pair + radius pairs (default) "
+                         "or the closest pair alone")
     ap.add_argument("--prune", type=int, default=0,
-                    help="reference-point tile pruning with this many references (point workloads; 0: off)")
+                    help="reference-point tile pruning with this many references (point and single-series motif workloads; 0: off)")
     ap.add_argument("--prune-f", type=float, default=10.0, help="projection factor of the references")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (a reference launch for hardware byte counters)")
@@ -262,8 +279,8 @@ def main():
     note(f"generating the {args.workload} workload")
     wl = WORKLOADS[args.workload](W, torch)
     if args.query != "points":
-        if not isinstance(wl, Points):
-            sys.exit(f"--query {args.query} applies to the point workloads only")
+        if not isinstance(wl, (Points, Motif)):
+            sys.exit(f"--query {args.query} applies to the point and single-series motif workloads only")
         wl.query = args.query
         wl.config = dict(wl.config, query="closest pair only")
     ctx = cp.Context(0)

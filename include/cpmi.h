@@ -210,19 +210,21 @@ int cpmi_save_tune_cache(cpmi_ctx *ctx, const char *path);
 int cpmi_tune_lookup(cpmi_ctx *ctx, int dtype, int precision, int64_t d, double pairs, int32_t *prec_out,
                      int32_t *tile_out);
 
-/* Reference-point tile pruning for point sets (MPR, Section 3: reference
- * points projected by a factor f, points ordered by their distance to the
- * first reference, pairs dropped when the triangle-inequality lower bound
- * exceeds the current upper bound). With q >= 1 the point calls
- * (cpmi_closest_pair, cpmi_frnn, cpmi_points) pick q reference rows from
- * `seed`, project them by f (every coordinate times f), order the rows by
- * their distance to the first projected reference, and skip every screen
- * tile whose rows are provably farther apart than both the least distance
- * between neighbours in that order and the radius. Answers are unchanged
- * (exact); stats.tiles_pruned counts the skipped tiles. q = 0 turns it off
- * (the default). Motifs are never pruned (the exclusion zone is defined on
- * window positions). Errors: ERR_ARG for q outside 0..32 or f not finite
- * and > 0. */
+/* Reference-point tile pruning (MPR, Section 3: reference points projected
+ * by a factor f, points ordered by their distance to the first reference,
+ * pairs dropped when the triangle-inequality lower bound exceeds the current
+ * upper bound). With q >= 1 the point calls (cpmi_closest_pair, cpmi_frnn,
+ * cpmi_points) and the single-series motif call (cpmi_motif, on the
+ * z-normalised windows) pick q reference rows (windows) from `seed`, project
+ * them by f (every coordinate times f), order the rows by their distance to
+ * the first projected reference, and skip every screen tile whose rows are
+ * provably farther apart than both the least distance found between
+ * neighbouring blocks in that order and the radius. A pruned motif always
+ * uses the 256-row screen, which applies the exclusion zone to the window
+ * positions of the reordered rows. Answers are unchanged (exact);
+ * stats.tiles_pruned counts the skipped tiles. q = 0 turns it off (the
+ * default). cpmi_motif_batch is never pruned. Errors: ERR_ARG for q outside
+ * 0..32 or f not finite and > 0. */
 int cpmi_set_pruning(cpmi_ctx *ctx, int q, double f, uint64_t seed);
 
 /* Library version (major * 10000 + minor * 100 + patch). */

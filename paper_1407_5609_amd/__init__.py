@@ -190,8 +190,9 @@ class Context:
         self._check(_lib.cpmi_set_tile(self._h, _prec(precision), int(tile)))
 
     def set_pruning(self, q: int, f: float = 10.0, seed: int = 0):
-        """Reference-point tile pruning for point sets (cpmi_set_pruning): q
-        references projected by f; q = 0 turns it off. Answers are unchanged."""
+        """Reference-point tile pruning for point sets and single-series
+        motifs (cpmi_set_pruning): q references projected by f; q = 0 turns it
+        off. Answers are unchanged."""
         self._check(_lib.cpmi_set_pruning(self._h, int(q), float(f), int(seed)))
 
     def autotune(self, pts, precision="auto", reps: int = 3, stream=None) -> dict:

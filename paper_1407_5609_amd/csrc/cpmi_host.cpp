@@ -48,6 +48,7 @@ struct HostProb {
     int32_t kpad = 0;
     int64_t npad = 0;
     const int32_t *perm = nullptr;  // screen row r holds source row perm[r] (reference-point order), or null
+    const int32_t *iperm = nullptr; // its inverse (windows of a series: the builder writes window w to row iperm[w])
     // workspace offsets
     size_t xs_off = 0, sh_off = 0, bm_off = 0, mu_off = 0;
 };
@@ -85,7 +86,7 @@ struct cpmi_ctx {
     std::vector<int64_t> tiles_key;
     int64_t ntiles = 0;
     int64_t nfull = 0;   // leading entries of the list that are full tiles
-    int64_t nfull_pairs = 0;  // pairs covered by the full tiles
+    int64_t nfull_pairs = 0;  // pairs covered by the timed screen launch (full tiles, or all when none is full)
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t es0 = nullptr, es1 = nullptr;  // around the first screen pass
@@ -100,7 +101,7 @@ struct cpmi_ctx {
     int prune_q = 0;
     double prune_f = 10.0;
     uint64_t prune_seed = 0;
-    DevBuf mD, mperm, mlo, mhi, mrefs;
+    DevBuf mD, mperm, miperm, mlo, mhi, mrefs, msort;
 };
 
 namespace {
@@ -281,7 +282,9 @@ void load_tune_cache(cpmi_ctx *c, const char *path)
 // problems (uneven costs) the tiles are listed most-expensive problem first.
 // keep(I, J) (optional, single problem) drops tiles proved empty of answers;
 // jend[I] (optional) is a block column from which on every tile of row I is
-// dropped, so that the scan of a band can stop there.
+// dropped, so that the scan of a band can stop there. For the windows of a
+// series in reference order (perm set) screen rows are not positions: every
+// tile may hold excluded pairs, so all are partial.
 void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t> &out, int64_t *nfull,
                  const std::function<bool(int64_t, int64_t)> &keep = {}, const std::vector<int64_t> *jend = nullptr)
 {
@@ -297,6 +300,7 @@ void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t
         const size_t p = order[oi];
         const HostProb &h = hp[p];
         if (pairs_of(h.n, h.excl) == 0) continue;
+        const bool permuted = h.motif && h.perm;
         const int64_t nT = (h.n + tile - 1) / tile;
         for (int64_t b0 = 0; b0 < nT; b0 += G) {
             int64_t jstop = nT;
@@ -307,10 +311,10 @@ void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t
             for (int64_t J = b0; J < jstop; ++J)
                 for (int64_t I = b0; I < std::min(b0 + G, nT) && I <= J; ++I) {
                     const int64_t maxj = std::min(J * tile + tile - 1, h.n - 1);
-                    if (maxj - I * tile < h.excl) continue;
+                    if (!permuted && maxj - I * tile < h.excl) continue;
                     if (keep && !keep(I, J)) continue;
-                    const bool full = (J * tile - (I * tile + tile - 1) >= h.excl) && ((I + 1) * tile <= h.n) &&
-                                      ((J + 1) * tile <= h.n);
+                    const bool full = !permuted && (J * tile - (I * tile + tile - 1) >= h.excl) &&
+                                      ((I + 1) * tile <= h.n) && ((J + 1) * tile <= h.n);
                     (full ? L : part).push_back(tile_pack((uint32_t)p, (uint32_t)I, (uint32_t)J));
                 }
         }
@@ -339,10 +343,12 @@ struct RunOut {
 // Launch the whole exact search for the problems in hp; synchronises once.
 // `forced` (optional) is a tile list built by the caller (reference-point
 // pruning) with its first `forced_nfull` entries full tiles; it bypasses the
-// list cache.
+// list cache. `reuse_operand` skips the row preparation: the screen operand
+// and row scalars of the previous call (same problems, precision and tile)
+// are still in the workspace.
 int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool want_cpp, bool want_frnn,
                hipStream_t st, bool batch_graph, RunOut &ro, const std::vector<uint64_t> *forced = nullptr,
-               int64_t forced_nfull = 0)
+               int64_t forced_nfull = 0, bool reuse_operand = false)
 {
     const int64_t np = (int64_t)hp.size();
     const int esz = elem_bytes(prec);
@@ -380,8 +386,10 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
     if (forced) {
         const std::vector<uint64_t> &tl = *forced;
         c->nfull = forced_nfull;
+        // pairs of the timed launch: the full tiles, or every tile when all are partial
+        const int64_t nt = forced_nfull > 0 ? forced_nfull : (int64_t)tl.size();
         int64_t nreal = 0;
-        for (int64_t k = 0; k < forced_nfull; ++k) nreal += tl[k] != TILE_NONE;
+        for (int64_t k = 0; k < nt; ++k) nreal += tl[k] != TILE_NONE;
         c->nfull_pairs = nreal * (int64_t)tile * tile;
         if ((rc = ensure(c, c->tiles, std::max<size_t>(tl.size(), 1) * 8))) return rc;
         if ((rc = ensure(c, c->tile_min, std::max<size_t>(tl.size(), 1) * 4))) return rc;
@@ -402,8 +410,9 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         int64_t nf = 0;
         build_tiles(hp, tile, tl, &nf);
         c->nfull = nf;
+        const int64_t nt = nf > 0 ? nf : (int64_t)tl.size();
         int64_t nreal = 0;
-        for (int64_t k = 0; k < nf; ++k) nreal += tl[k] != TILE_NONE;
+        for (int64_t k = 0; k < nt; ++k) nreal += tl[k] != TILE_NONE;
         c->nfull_pairs = nreal * (int64_t)tile * tile;
         if ((rc = ensure(c, c->tiles, tl.size() * 8))) return rc;
         if ((rc = ensure(c, c->tile_min, tl.size() * 4))) return rc;
@@ -455,7 +464,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
                 j.ell = h.d;
                 j.npad = h.npad;
                 j.blk_base = blk;
-                blk += h.npad / 256;
+                blk += h.npad / SERIES_WPB;
                 j.xs = (void *)q.xs;
                 j.shat = (void *)q.shat;
                 j.bmax = (float4 *)q.bmax;
@@ -463,6 +472,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
                 j.sigma = (double *)q.sigma;
                 j.flags = &((ResDev *)c->res.p)[p].flags;
                 j.kpad = h.kpad;
+                j.iperm = h.iperm;
                 jobs.push_back(j);
             }
         }
@@ -480,10 +490,13 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             launch_reset_res(dres, np, st);
             launch_fill_u32(dcnt, 0u, NCNT, st);
             launch_fill_u64((uint64_t *)c->ubits.p, 0x7ff0000000000000ull, np, st);
-            launch_fill_u32((uint32_t *)c->bmax.p, 0u, (int64_t)(bm_b / 4), st);
-            if (!jobs.empty()) {
+            if (reuse_operand) {
+                // the operand, row scalars and block maxima are in place
+            } else if (!jobs.empty()) {
+                launch_fill_u32((uint32_t *)c->bmax.p, 0u, (int64_t)(bm_b / 4), st);
                 launch_prep_series((const SeriesJob *)c->jobs.p, (int64_t)jobs.size(), blk, prec, tile, st);
             } else {
+                launch_fill_u32((uint32_t *)c->bmax.p, 0u, (int64_t)(bm_b / 4), st);
                 const HostProb &h = hp[0];
                 launch_prep_points(h.src, h.src_i8 ? CPMI_I8 : CPMI_F32, h.n, h.d, h.ld, prec, P[0].xs ? (void *)P[0].xs : nullptr,
                                    h.kpad, h.npad, (void *)P[0].shat, (float4 *)P[0].bmax, tile, &dres[0].flags,
@@ -502,16 +515,19 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             a.cntU = dcnt + C_U;
             a.capU = c->capU;
             // the events bracket the dominant launch: the full-tile screen
-            // (or the single masked screen of the 128 tile)
+            // (the masked one when every tile is partial, and the single
+            // masked screen of the 128 tile)
             if (tile == 256) {
+                const bool timed_masked = nfull == 0;
                 ScreenArgs q = a;
                 q.tiles = a.tiles + nfull;
                 q.tile_min = a.tile_min + nfull;
                 q.ntiles = ntiles - nfull;
+                if (!batch_graph && timed_masked) hipEventRecord(c->es0, st);
                 launch_screen(prec, tile, M_MIN, true, q, std::min<int64_t>(ntiles - nfull, c->ncu), st);
                 ScreenArgs f = a;
                 f.ntiles = nfull;
-                if (!batch_graph) hipEventRecord(c->es0, st);
+                if (!batch_graph && !timed_masked) hipEventRecord(c->es0, st);
                 launch_screen(prec, tile, M_MIN, false, f, std::min<int64_t>(nfull, c->ncu), st);
                 if (!batch_graph) hipEventRecord(c->es1, st);
             } else {
@@ -724,6 +740,18 @@ double tile_lower_bound(const double *loI, const double *hiI, const double *loJ,
     return lb;
 }
 
+// Whether tile_lower_bound(...) > T, stopping at the first reference that
+// shows it.
+bool tile_bound_exceeds(const double *loI, const double *hiI, const double *loJ, const double *hiJ, int q, double T)
+{
+    for (int k = 0; k < q; ++k) {
+        double g = std::max(loJ[k] - hiI[k], loI[k] - hiJ[k]);
+        g -= 0x1p-34 * std::max(std::fabs(hiI[k]), std::fabs(hiJ[k]));
+        if (g > T) return true;
+    }
+    return false;
+}
+
 uint64_t splitmix64(uint64_t x)
 {
     x += 0x9e3779b97f4a7c15ull;
@@ -732,36 +760,45 @@ uint64_t splitmix64(uint64_t x)
     return x ^ (x >> 31);
 }
 
-// Reference-point pruning of one point set (Section 3, MPR steps 1-3): order
-// the rows by their distance to the first projected reference (h.perm) and
-// bring back to the host, per block of `tile` rows in that order and per
-// reference, the interval of distances (lo, hi: nT x q). Synchronises once.
+// Reference-point pruning of one point set or of the windows of one series
+// (Section 3, MPR steps 1-3): order the rows by their distance to the first
+// projected reference (h.perm; for windows also its inverse, h.iperm, padded
+// to whole 256-row blocks) and bring back to the host, per block of `tile`
+// rows in that order and per reference, the interval of distances (lo, hi:
+// nT x q). Synchronises once.
 int prune_prepare(cpmi_ctx *c, HostProb &h, int tile, hipStream_t st, std::vector<double> &lo,
                   std::vector<double> &hi)
 {
     const int q = c->prune_q;
     const int64_t n = h.n;
+    const int64_t npad = (n + 255) / 256 * 256;
     const int dtype = h.src_i8 ? CPMI_I8 : CPMI_F32;
     const int64_t nT = (n + tile - 1) / tile;
-    int64_t mpad = 1;
-    while (mpad < n) mpad <<= 1;
     int rc;
-    if ((rc = ensure(c, c->mD, (size_t)q * n * 8))) return rc;
-    if ((rc = ensure(c, c->mperm, (size_t)n * 4))) return rc;
+    if ((rc = ensure(c, c->mD, ((size_t)q * n + (h.motif ? (size_t)q * h.d : 0)) * 8))) return rc;
+    if ((rc = ensure(c, c->mperm, (size_t)npad * 4))) return rc;
+    if (h.motif && (rc = ensure(c, c->miperm, (size_t)n * 4))) return rc;
     if ((rc = ensure(c, c->mlo, (size_t)nT * q * 8))) return rc;
     if ((rc = ensure(c, c->mhi, (size_t)nT * q * 8))) return rc;
     if ((rc = ensure(c, c->mrefs, (size_t)q * 4))) return rc;
-    if ((rc = ensure(c, c->keys, (size_t)mpad * 8))) return rc;
-    if ((rc = ensure(c, c->vals, (size_t)mpad * 8))) return rc;
+    if ((rc = ensure(c, c->keys, (size_t)n * 8))) return rc;  // sort scratch: indices
+    if ((rc = ensure(c, c->vals, (size_t)n * 8))) return rc;  // sorted keys
+    size_t tb = 0;
+    HIPCHK(c, sort_ref_order(nullptr, &tb, nullptr, nullptr, nullptr, nullptr, n, st));
+    if ((rc = ensure(c, c->msort, std::max<size_t>(tb, 1)))) return rc;
     std::vector<int32_t> refs(q);
     for (int k = 0; k < q; ++k) refs[k] = (int32_t)(splitmix64(c->prune_seed * 64 + (uint64_t)k) % (uint64_t)n);
     HIPCHK(c, hipMemcpyAsync(c->mrefs.p, refs.data(), q * 4, hipMemcpyHostToDevice, st));
     double *D = (double *)c->mD.p;
     int32_t *perm = (int32_t *)c->mperm.p;
-    launch_ref_dist(h.src, dtype, n, h.d, h.ld, (const int32_t *)c->mrefs.p, q, c->prune_f, D, st);
-    launch_ref_keys(D, n, (uint64_t *)c->keys.p, (double *)c->vals.p, st);
-    launch_sort_pairs((uint64_t *)c->keys.p, (double *)c->vals.p, n, mpad, st);
-    launch_perm_from_sorted((const double *)c->vals.p, n, perm, st);
+    if (h.motif) {
+        launch_ref_dist_windows((const float *)h.src, n, h.d, (const int32_t *)c->mrefs.p, q, c->prune_f,
+                                D + (size_t)q * n, D, st);
+    } else {
+        launch_ref_dist(h.src, dtype, n, h.d, h.ld, (const int32_t *)c->mrefs.p, q, c->prune_f, D, st);
+    }
+    HIPCHK(c, sort_ref_order(c->msort.p, &tb, D, (double *)c->vals.p, (int32_t *)c->keys.p, perm, n, st));
+    if (h.motif) launch_perm_finish(perm, (int32_t *)c->miperm.p, n, npad, st);
     launch_block_range(D, n, q, perm, tile, nT, (double *)c->mlo.p, (double *)c->mhi.p, st);
     HIPCHK(c, hipGetLastError());
     lo.assign((size_t)nT * q, 0.0);
@@ -770,6 +807,7 @@ int prune_prepare(cpmi_ctx *c, HostProb &h, int tile, hipStream_t st, std::vecto
     HIPCHK(c, hipMemcpyAsync(hi.data(), c->mhi.p, hi.size() * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
     h.perm = perm;
+    if (h.motif) h.iperm = (const int32_t *)c->miperm.p;
     return CPMI_OK;
 }
 
@@ -780,8 +818,8 @@ void pruned_tiles(const HostProb &h, int tile, int q, const std::vector<double> 
                   double T, int64_t band, std::vector<uint64_t> &tl, int64_t &nfull, int64_t &npruned)
 {
     const int64_t nT = (h.n + tile - 1) / tile;
-    auto lb = [&](int64_t I, int64_t J) {
-        return tile_lower_bound(&lo[I * q], &hi[I * q], &lo[J * q], &hi[J * q], q);
+    auto exceeds = [&](int64_t I, int64_t J) {
+        return T < 0.0 || tile_bound_exceeds(&lo[I * q], &hi[I * q], &lo[J * q], &hi[J * q], q, T);
     };
     // the rows are ordered by reference 0, so its gap only grows with J: jend[I]
     // is the first block column whose reference-0 gap alone exceeds T
@@ -799,10 +837,40 @@ void pruned_tiles(const HostProb &h, int tile, int q, const std::vector<double> 
     std::vector<HostProb> one(1, h);
     build_tiles(
         one, tile, tl, &nfull,
-        [&](int64_t I, int64_t J) { return (band < 0 || J - I <= band) && !(lb(I, J) > T); }, &jend);
+        [&](int64_t I, int64_t J) { return (band < 0 || J - I <= band) && !exceeds(I, J); }, &jend);
     int64_t kept = 0;
     for (uint64_t e : tl) kept += e != TILE_NONE;
     npruned = nT * (nT + 1) / 2 - kept;
+}
+
+// The exact search of one problem with reference-point tile pruning. MPR keeps
+// a running upper bound of the least distance; here it comes from a first
+// search over the diagonal band of the reference order (neighbouring blocks,
+// where close pairs land), and the full search then skips every tile whose
+// reference bound exceeds it and the radius.
+int pruned_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool want_cpp, bool want_frnn,
+                  hipStream_t st, RunOut &ro)
+{
+    std::vector<double> lo, hi;
+    int rc;
+    if ((rc = prune_prepare(c, hp[0], tile, st, lo, hi))) return rc;
+    std::vector<uint64_t> tl;
+    int64_t nfull = 0, npruned = 0;
+    const double inf = std::numeric_limits<double>::infinity();
+    double thr2 = want_frnn ? hp[0].r2 : 0.0;
+    if (want_cpp) {
+        pruned_tiles(hp[0], tile, c->prune_q, lo, hi, inf, 1, tl, nfull, npruned);
+        RunOut band;
+        if ((rc = run_search(c, hp, prec, tile, true, false, st, false, band, &tl, nfull))) return rc;
+        if ((rc = flags_error(c, band.res[0].flags))) return rc;
+        const double u = __builtin_bit_cast(double, (uint64_t)band.res[0].best_d2);
+        thr2 = std::max(thr2, std::isfinite(u) ? u : inf);
+    }
+    pruned_tiles(hp[0], tile, c->prune_q, lo, hi, std::sqrt(thr2) * (1.0 + 0x1p-30), -1, tl, nfull, npruned);
+    // the band search (if any) left the screen operand in place
+    if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro, &tl, nfull, want_cpp))) return rc;
+    c->stats.tiles_pruned = npruned;
+    return CPMI_OK;
 }
 
 }  // namespace
@@ -846,7 +914,7 @@ int cpmi_destroy(cpmi_ctx *c)
     if (c->gexec) hipGraphExecDestroy(c->gexec);
     DevBuf *bufs[] = {&c->xs,      &c->shat,  &c->bmax, &c->musg, &c->probs, &c->jobs, &c->tiles, &c->tile_min,
                       &c->sel,     &c->candR, &c->candU, &c->cand_d2, &c->keys, &c->vals, &c->cnt, &c->ubits,
-                      &c->res,     &c->mD,    &c->mperm, &c->mlo, &c->mhi,   &c->mrefs};
+                      &c->res,     &c->mD,    &c->mperm, &c->miperm, &c->mlo, &c->mhi, &c->mrefs, &c->msort};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
     if (c->pinned) hipHostFree(c->pinned);
@@ -927,27 +995,7 @@ int cpmi_points(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d, i
     const int tile = pick_tile(c, prec, d, npairs);
     RunOut ro;
     if (c->prune_q > 0 && n > tile) {
-        // MPR keeps a running upper bound of the least distance; here it comes
-        // from a first search over the diagonal band of the reference order
-        // (neighbouring blocks, where close pairs land), and the full search
-        // then skips every tile whose reference bound exceeds it and the radius
-        std::vector<double> lo, hi;
-        if ((rc = prune_prepare(c, hp[0], tile, st, lo, hi))) return rc;
-        std::vector<uint64_t> tl;
-        int64_t nfull = 0, npruned = 0;
-        const double inf = std::numeric_limits<double>::infinity();
-        double thr2 = want_frnn ? R2 : 0.0;
-        if (want_cpp) {
-            pruned_tiles(hp[0], tile, c->prune_q, lo, hi, inf, 1, tl, nfull, npruned);
-            RunOut band;
-            if ((rc = run_search(c, hp, prec, tile, true, false, st, false, band, &tl, nfull))) return rc;
-            if ((rc = flags_error(c, band.res[0].flags))) return rc;
-            const double u = __builtin_bit_cast(double, (uint64_t)band.res[0].best_d2);
-            thr2 = std::max(thr2, std::isfinite(u) ? u : inf);
-        }
-        pruned_tiles(hp[0], tile, c->prune_q, lo, hi, std::sqrt(thr2) * (1.0 + 0x1p-30), -1, tl, nfull, npruned);
-        if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro, &tl, nfull))) return rc;
-        c->stats.tiles_pruned = npruned;
+        if ((rc = pruned_search(c, hp, prec, tile, want_cpp, want_frnn, st, ro))) return rc;
     } else {
         if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro))) return rc;
     }
@@ -990,7 +1038,7 @@ int cpmi_motif(cpmi_ctx *c, const float *series, int64_t len, int64_t ell, int64
     if (count_out) *count_out = 0;
     if (!series) return fail(c, CPMI_ERR_ARG, "series pointer is NULL");
     if (ell < 2 || len < ell) return fail(c, CPMI_ERR_ARG, "need 2 <= ell <= len (ell=%lld len=%lld)", (long long)ell, (long long)len);
-    if (ell > 8192) return fail(c, CPMI_ERR_ARG, "ell must be <= 8192");
+    if (ell > SERIES_MAX_ELL) return fail(c, CPMI_ERR_ARG, "ell must be <= %d", SERIES_MAX_ELL);
     if (len >= (1ll << 31) - 256) return fail(c, CPMI_ERR_ARG, "len must be below 2^31");
     if (!want_cpp && !want_frnn) return fail(c, CPMI_ERR_ARG, "nothing requested (best == NULL and R2 < 0)");
     if (want_frnn && (!pairs || !count_out || cap < 0)) return fail(c, CPMI_ERR_ARG, "radius search needs pairs, cap and count_out");
@@ -1017,9 +1065,16 @@ int cpmi_motif(cpmi_ctx *c, const float *series, int64_t len, int64_t ell, int64
     hp[0].src = series;
     hp[0].len = len;
     hp[0].r2 = want_frnn ? R2 : -1.0;
-    const int tile = pick_tile(c, prec, ell, npairs);
     RunOut ro;
-    if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro))) return rc;
+    if (c->prune_q > 0 && N > 256 && excl <= (1 << 30)) {
+        // windows in reference order: only the 256-row screen applies the
+        // exclusion zone to permuted rows (in 32-bit unsigned arithmetic,
+        // hence the bound on excl)
+        if ((rc = pruned_search(c, hp, prec, 256, want_cpp, want_frnn, st, ro))) return rc;
+    } else {
+        const int tile = pick_tile(c, prec, ell, npairs);
+        if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro))) return rc;
+    }
     if ((rc = flags_error(c, ro.res[0].flags))) return rc;
     if (want_cpp) {
         fill_pair(ro.res[0], best);
@@ -1047,7 +1102,7 @@ int cpmi_motif_batch(cpmi_ctx *c, const float *const *series, const int64_t *len
         memset(&best[s], 0, sizeof best[s]);
         best[s].i = best[s].j = -1;
         const int64_t L = lens[s], ell = ells[s];
-        if (!series[s] || ell < 2 || ell > 8192 || L < ell || L >= (1ll << 31) - 256)
+        if (!series[s] || ell < 2 || ell > SERIES_MAX_ELL || L < ell || L >= (1ll << 31) - 256)
             return fail(c, CPMI_ERR_ARG, "series %lld: bad arguments (len=%lld ell=%lld)", (long long)s, (long long)L, (long long)ell);
         const int64_t N = L - ell + 1;
         if (N <= ell) {
@@ -1291,7 +1346,7 @@ int cpmi_dbg_znorm(cpmi_ctx *c, const float *series, int64_t len, int64_t ell, i
     HIPCHK(c, hipMemcpyAsync(c->jobs.p, &j, sizeof j, hipMemcpyHostToDevice, st));
     launch_reset_res((ResDev *)c->res.p, 1, st);
     launch_fill_u32((uint32_t *)c->bmax.p, 0u, (npad / 128) * 4, st);
-    launch_prep_series((const SeriesJob *)c->jobs.p, 1, npad / 256, prec, 128, st);
+    launch_prep_series((const SeriesJob *)c->jobs.p, 1, npad / SERIES_WPB, prec, 128, st);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));
     return CPMI_OK;

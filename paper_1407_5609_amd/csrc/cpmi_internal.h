@@ -85,13 +85,18 @@ struct ResDev {
     unsigned int flags;           // F_* input flags of the problem
 };
 
+// Longest window of a series, and windows per builder block (which stages
+// SERIES_WPB + ell - 1 values in LDS).
+constexpr int SERIES_MAX_ELL = 8192;
+constexpr int SERIES_WPB = 64;
+
 // Job of the window builder: one series.
 struct SeriesJob {
     const float *T;
     int64_t len;
     int64_t ell;
     int64_t npad;       // padded rows (windows) of xs
-    int64_t blk_base;   // first 256-row builder block of this job (prefix sum)
+    int64_t blk_base;   // first builder block (SERIES_WPB windows) of this job (prefix sum)
     void *xs;
     void *shat;
     float4 *bmax;
@@ -100,6 +105,7 @@ struct SeriesJob {
     unsigned int *flags;
     int32_t kpad;
     int32_t pad0;
+    const int32_t *iperm;  // screen row of window w (reference order), or null for w itself
 };
 
 // ---- launchers (defined in the .hip files) --------------------------------
@@ -148,8 +154,12 @@ void launch_sort_pairs(uint64_t *keys, double *vals, int64_t m, int64_t mpad, hi
 // reference-point pruning (mpr.hip)
 void launch_ref_dist(const void *X, int dtype, int64_t n, int64_t d, int64_t ld, const int32_t *refs, int q,
                      double f, double *D, hipStream_t st);
-void launch_ref_keys(const double *D0, int64_t n, uint64_t *keys, double *vals, hipStream_t st);
-void launch_perm_from_sorted(const double *vals, int64_t n, int32_t *perm, hipStream_t st);
+hipError_t sort_ref_order(void *temp, size_t *temp_bytes, const double *D0, double *keys_out, int32_t *idx,
+                          int32_t *perm, int64_t n, hipStream_t st);
+// rz: q * ell doubles of scratch (the projected, z-normalised references).
+void launch_ref_dist_windows(const float *T, int64_t N, int64_t ell, const int32_t *refs, int q, double f,
+                             double *rz, double *D, hipStream_t st);
+void launch_perm_finish(int32_t *perm, int32_t *iperm, int64_t n, int64_t npad, hipStream_t st);
 void launch_block_range(const double *D, int64_t n, int q, const int32_t *perm, int tile, int64_t nblk, double *lo,
                         double *hi, hipStream_t st);
 // Unpack sorted keys (i << 32 | j) into int64 pairs [m][2] and copy values.

@@ -18,6 +18,8 @@
 // far larger than it (the host side).
 #include <algorithm>
 
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "cpmi_internal.h"
 
 namespace cpmi {
@@ -34,7 +36,8 @@ __device__ __forceinline__ double wave_sum_d(double v)
 template <typename T> __device__ __forceinline__ double val(const T *p, int64_t k) { return (double)p[k]; }
 
 // D[k * n + i] = || f * x_ref_k - x_i || for every point i and reference k.
-// One wave per point; lanes across coordinates.
+// One wave per point, lanes across coordinates, all references (q <= 32) in
+// one sweep over the point.
 template <typename T>
 __global__ __launch_bounds__(256) void ref_dist_kernel(const T *X, int64_t n, int64_t d, int64_t ld,
                                                        const int32_t *refs, int q, double f, double *D)
@@ -43,52 +46,163 @@ __global__ __launch_bounds__(256) void ref_dist_kernel(const T *X, int64_t n, in
     const int64_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
     const T *x = X + i * ld;
-    for (int k = 0; k < q; ++k) {
-        const T *r = X + (int64_t)refs[k] * ld;
-        double s = 0.0;
-        for (int64_t c = lane; c < d; c += 64) {
-            const double t = f * val(r, c) - val(x, c);
-            s = fma(t, t, s);
+    double s[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) s[k] = 0.0;
+    for (int64_t c = lane; c < d; c += 64) {
+        const double xv = val(x, c);
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            if (k < q) {
+                const double t = f * val(X + (int64_t)refs[k] * ld, c) - xv;
+                s[k] = fma(t, t, s[k]);
+            }
         }
-        s = wave_sum_d(s);
-        if (lane == 0) D[(int64_t)k * n + i] = sqrt(s);
+    }
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        if (k < q) {
+            const double v = wave_sum_d(s[k]);
+            if (lane == 0) D[(int64_t)k * n + i] = sqrt(v);
+        }
     }
 }
 
-// Sort keys for the order by distance to reference 0: the bits of a
-// non-negative double order like the double; the value carries the index.
-__global__ void ref_keys_kernel(const double *D0, int64_t n, uint64_t *keys, double *vals)
+// The q projected references of a series, z-normalised: rz[k * ell + c] =
+// f * (T[r_k + c] - mu) / sigma (FP64; mean and sigma by a wave reduction;
+// a window of zero variance counts as the zero vector). One wave each.
+__global__ __launch_bounds__(64) void ref_windows_kernel(const float *T, int64_t ell, const int32_t *refs, double f,
+                                                         double *rz)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        keys[i] = (uint64_t)__double_as_longlong(D0[i]);
-        vals[i] = (double)i;
+    const int k = blockIdx.x, lane = threadIdx.x;
+    const float *x = T + refs[k];
+    double s = 0.0;
+    for (int64_t c = lane; c < ell; c += 64) s += (double)x[c];
+    const double m = wave_sum_d(s) / (double)ell;
+    double v2 = 0.0;
+    for (int64_t c = lane; c < ell; c += 64) {
+        const double e = (double)x[c] - m;
+        v2 = fma(e, e, v2);
+    }
+    const double sg = sqrt(wave_sum_d(v2) / (double)ell);
+    const double sc = sg > 0.0 ? f / sg : 0.0;
+    for (int64_t c = lane; c < ell; c += 64) rz[(int64_t)k * ell + c] = ((double)x[c] - m) * sc;
+}
+
+// D[k * N + w] = || rz_k - xhat_w || for every window w of the series, xhat_w
+// = (T[w + c] - mu_w) / sigma_w, c < ell (a window of zero variance counts as
+// the zero vector; the builder reports such a series as an error). A
+// work-group takes 64 consecutive windows, a lane each, with the stretch of
+// the series they cover staged in LDS; its four waves split the window
+// length and their partial sums meet in LDS. The reference values are the
+// same across a wave and come in through scalar loads. Mean and sigma here
+// are not the builder's canonical ones: the distances only feed the pruning
+// test, whose margin covers their rounding.
+template <int QM>
+__global__ __launch_bounds__(256) void ref_dist_windows_kernel(const float *T, int64_t N, int64_t ell,
+                                                               const double *rz_, int q, double *D)
+{
+    __shared__ float sh[64 + SERIES_MAX_ELL];
+    __shared__ double red[4][64];
+    const __attribute__((address_space(4))) double *rz = (const __attribute__((address_space(4))) double *)rz_;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);   // uniform: scalar reference loads
+    const int64_t w0 = (int64_t)blockIdx.x * 64;
+    const int64_t span = min<int64_t>(64 + ell - 1, N + ell - 1 - w0);   // values of the live windows
+    for (int64_t k = threadIdx.x; k < span; k += 256) sh[k] = T[w0 + k];
+    __syncthreads();
+    const int64_t wl = min<int64_t>(lane, N - 1 - w0);   // this lane's window (the last live one past N)
+    const float *x = sh + wl;
+    const int64_t part = (ell + 3) / 4;
+    const int64_t c0 = min<int64_t>(ell, wave * part), c1 = min<int64_t>(ell, c0 + part);
+    // sum of the four waves' partial values v, in every lane of every wave
+    auto total = [&](double v) {
+        red[wave][lane] = v;
+        __syncthreads();
+        const double t = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+        __syncthreads();
+        return t;
+    };
+    double s = 0.0;
+    for (int64_t c = c0; c < c1; ++c) s += (double)x[c];
+    const double m = total(s) / (double)ell;
+    double v2 = 0.0;
+    for (int64_t c = c0; c < c1; ++c) {
+        const double e = (double)x[c] - m;
+        v2 = fma(e, e, v2);
+    }
+    const double sg = sqrt(total(v2) / (double)ell);
+    const double inv = sg > 0.0 ? 1.0 / sg : 0.0;
+    double acc[QM];
+#pragma unroll
+    for (int k = 0; k < QM; ++k) acc[k] = 0.0;
+#pragma unroll 4
+    for (int64_t c = c0; c < c1; ++c) {
+        const double xv = ((double)x[c] - m) * inv;
+#pragma unroll
+        for (int k = 0; k < QM; ++k) {
+            if (k < q) {
+                const double t = rz[(int64_t)k * ell + c] - xv;
+                acc[k] = fma(t, t, acc[k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < QM; ++k) {
+        if (k < q) {
+            const double v = total(acc[k]);
+            if (wave == 0 && w0 + lane < N) D[(int64_t)k * N + w0 + lane] = sqrt(v);
+        }
     }
 }
 
-__global__ void perm_from_sorted_kernel(const double *vals, int64_t n, int32_t *perm)
+// Complete a permutation of 0..n-1 for the screen: its inverse, and the tail
+// n..npad-1 (padding rows, which the screen masks by row index) set to 0.
+__global__ void perm_finish_kernel(int32_t *perm, int32_t *iperm, int64_t n, int64_t npad)
 {
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
-        perm[r] = (int32_t)vals[r];
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < npad; r += (int64_t)gridDim.x * blockDim.x) {
+        if (r < n) iperm[perm[r]] = (int32_t)r;
+        else perm[r] = 0;
+    }
 }
 
-// Per block of `tile` screen rows and reference k: the interval of distances,
-// lo[b * q + k], hi[b * q + k]. One thread per (block, reference).
-__global__ void block_range_kernel(const double *D, int64_t n, int q, const int32_t *perm, int tile, int64_t nblk,
-                                   double *lo, double *hi)
+__global__ void iota_kernel(int32_t *v, int64_t n)
 {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= nblk * q) return;
-    const int64_t b = t / q;
-    const int k = (int)(t % q);
-    double mn = INFINITY, mx = -INFINITY;
-    const int64_t r1 = min(n, (b + 1) * tile);
-    for (int64_t r = b * tile; r < r1; ++r) {
-        const double v = D[(int64_t)k * n + perm[r]];
-        mn = fmin(mn, v);
-        mx = fmax(mx, v);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = (int32_t)i;
+}
+
+// Per block of `tile` (<= 256) screen rows and reference k: the interval of
+// distances, lo[b * q + k], hi[b * q + k]. One work-group of 256 threads per
+// block, a thread per row, reduced over the work-group.
+__global__ __launch_bounds__(256) void block_range_kernel(const double *D, int64_t n, int q, const int32_t *perm,
+                                                          int tile, double *lo, double *hi)
+{
+    __shared__ double red[2][4];
+    const int64_t b = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t r = b * tile + tid;
+    const bool live = tid < tile && r < n;
+    const int64_t src = live ? perm[r] : 0;
+    for (int k = 0; k < q; ++k) {
+        const double v = live ? D[(int64_t)k * n + src] : 0.0;
+        double mn = live ? v : INFINITY, mx = live ? v : -INFINITY;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            mn = fmin(mn, __shfl_xor(mn, o, 64));
+            mx = fmax(mx, __shfl_xor(mx, o, 64));
+        }
+        if (lane == 0) {
+            red[0][wave] = mn;
+            red[1][wave] = mx;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            lo[b * q + k] = fmin(fmin(red[0][0], red[0][1]), fmin(red[0][2], red[0][3]));
+            hi[b * q + k] = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+        }
+        __syncthreads();
     }
-    lo[t] = mn;
-    hi[t] = mx;
 }
 
 unsigned grid_of(int64_t n, int per) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, 65536)); }
@@ -105,22 +219,36 @@ void launch_ref_dist(const void *X, int dtype, int64_t n, int64_t d, int64_t ld,
         hipLaunchKernelGGL((ref_dist_kernel<float>), g, b, 0, st, (const float *)X, n, d, ld, refs, q, f, D);
 }
 
-void launch_ref_keys(const double *D0, int64_t n, uint64_t *keys, double *vals, hipStream_t st)
+void launch_ref_dist_windows(const float *T, int64_t N, int64_t ell, const int32_t *refs, int q, double f,
+                             double *rz, double *D, hipStream_t st)
 {
-    hipLaunchKernelGGL(ref_keys_kernel, dim3(grid_of(n, 256)), dim3(256), 0, st, D0, n, keys, vals);
+    hipLaunchKernelGGL(ref_windows_kernel, dim3((unsigned)q), dim3(64), 0, st, T, ell, refs, f, rz);
+    const dim3 g((unsigned)((N + 63) / 64)), b(256);
+    if (q <= 4) hipLaunchKernelGGL((ref_dist_windows_kernel<4>), g, b, 0, st, T, N, ell, rz, q, D);
+    else if (q <= 12) hipLaunchKernelGGL((ref_dist_windows_kernel<12>), g, b, 0, st, T, N, ell, rz, q, D);
+    else hipLaunchKernelGGL((ref_dist_windows_kernel<32>), g, b, 0, st, T, N, ell, rz, q, D);
 }
 
-void launch_perm_from_sorted(const double *vals, int64_t n, int32_t *perm, hipStream_t st)
+void launch_perm_finish(int32_t *perm, int32_t *iperm, int64_t n, int64_t npad, hipStream_t st)
 {
-    hipLaunchKernelGGL(perm_from_sorted_kernel, dim3(grid_of(n, 256)), dim3(256), 0, st, vals, n, perm);
+    hipLaunchKernelGGL(perm_finish_kernel, dim3(grid_of(npad, 256)), dim3(256), 0, st, perm, iperm, n, npad);
+}
+
+// The reference order: perm[0..n) = the indices 0..n-1 sorted (stably) by
+// D0 (rocPRIM's device radix sort). temp == nullptr only sets *temp_bytes.
+// keys_out (n doubles) and idx (n int32) are scratch.
+hipError_t sort_ref_order(void *temp, size_t *temp_bytes, const double *D0, double *keys_out, int32_t *idx,
+                          int32_t *perm, int64_t n, hipStream_t st)
+{
+    if (temp) hipLaunchKernelGGL(iota_kernel, dim3(grid_of(n, 256)), dim3(256), 0, st, idx, n);
+    return rocprim::radix_sort_pairs(temp, *temp_bytes, D0, keys_out, (const int32_t *)idx, perm, (unsigned int)n, 0,
+                                     64, st);
 }
 
 void launch_block_range(const double *D, int64_t n, int q, const int32_t *perm, int tile, int64_t nblk, double *lo,
                         double *hi, hipStream_t st)
 {
-    const int64_t t = nblk * q;
-    hipLaunchKernelGGL(block_range_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, D, n, q, perm, tile,
-                       nblk, lo, hi);
+    hipLaunchKernelGGL(block_range_kernel, dim3((unsigned)nblk), dim3(256), 0, st, D, n, q, perm, tile, lo, hi);
 }
 
 }  // namespace cpmi

@@ -203,16 +203,20 @@ void launch_prep_points(const void *pts, int dtype, int64_t n, int64_t d, int64_
 }
 
 // ---------------------------------------------------------------------------
-// series: a block of 256 threads builds 256 consecutive windows of one job.
-// Pass A (one thread per window): canonical mean and sigma, sequential in k.
-// Pass B (one wave per window, lanes across k): normalised values, screen
-// operand and row scalars.
+// series: a block of 256 threads builds SERIES_WPB (64) consecutive windows
+// of one job (small blocks: many waves in flight to cover the latency of the
+// sequential sums). The block's stretch of the series (64 + ell - 1 values,
+// ell <= 8192) is staged in LDS once. Pass A (one thread per window, the
+// first wave): canonical mean and sigma, sequential in k. Pass B (one wave
+// per window, lanes across k): normalised values, screen operand and row
+// scalars.
 // ---------------------------------------------------------------------------
 template <int PREC>
 __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs, int64_t njobs, int tile)
 {
-    __shared__ double sh_mu[256];
-    __shared__ double sh_sg[256];
+    __shared__ double sh_mu[SERIES_WPB];
+    __shared__ double sh_sg[SERIES_WPB];
+    __shared__ float sh_T[SERIES_WPB + SERIES_MAX_ELL];
     // job of this block: last job with blk_base <= blockIdx.x
     int64_t lo = 0, hi = njobs - 1;
     const int64_t bid = blockIdx.x;
@@ -223,26 +227,52 @@ __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs,
     }
     const SeriesJob J = jobs[lo];
     const int64_t N = J.len - J.ell + 1;          // windows
-    const int64_t w0 = (bid - J.blk_base) * 256;  // first window of the block
+    const int64_t w0 = (bid - J.blk_base) * SERIES_WPB;  // first window of the block
     const int tid = threadIdx.x;
-    const float *T = J.T;
     const int64_t ell = J.ell;
+    // values T[w0 .. w0 + span) : every window of the block that exists
+    const int64_t span = w0 < N ? min<int64_t>(SERIES_WPB + ell - 1, J.len - w0) : 0;
+    for (int64_t k = tid; k < span; k += 256) sh_T[k] = J.T[w0 + k];
+    __syncthreads();
 
-    {
+    if (tid < SERIES_WPB) {
         const int64_t w = w0 + tid;
         double mu = 0.0, sg = 0.0;
         if (w < N) {
+            // sequential in k; the LDS reads of eight terms are issued
+            // before their additions
+            const float *tw = sh_T + tid;   // T[w + k] = tw[k]
             double s = 0.0;
             bool bad = false;
-            for (int64_t k = 0; k < ell; ++k) {
-                const float v = T[w + k];
-                if (!isfinite(v)) bad = true;
-                s += (double)v;
+            int64_t k = 0;
+            for (; k + 8 <= ell; k += 8) {
+                float v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = tw[k + u];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    bad |= !isfinite(v[u]);
+                    s += (double)v[u];
+                }
+            }
+            for (; k < ell; ++k) {
+                bad |= !isfinite(tw[k]);
+                s += (double)tw[k];
             }
             mu = s / (double)ell;
             double v2 = 0.0;
-            for (int64_t k = 0; k < ell; ++k) {
-                const double e = (double)T[w + k] - mu;
+            for (k = 0; k + 8 <= ell; k += 8) {
+                float v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = tw[k + u];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const double e = (double)v[u] - mu;
+                    v2 = fma(e, e, v2);
+                }
+            }
+            for (; k < ell; ++k) {
+                const double e = (double)tw[k] - mu;
                 v2 = fma(e, e, v2);
             }
             v2 = v2 / (double)ell;
@@ -260,23 +290,25 @@ __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs,
     __syncthreads();
 
     const int lane = tid & 63, wave = tid >> 6;
-    for (int q = wave; q < 256; q += 4) {
+    for (int q = wave; q < SERIES_WPB; q += 4) {
         const int64_t w = w0 + q;
         if (w >= J.npad) break;
         const bool real = w < N && sh_sg[q] > 0.0;
+        // screen row of window w (a permutation of the windows, or w itself)
+        const int64_t row = (J.iperm && w < N) ? (int64_t)J.iperm[w] : w;
         const double mu = sh_mu[q], sg = sh_sg[q];
         double s = 0.0, t2 = 0.0, r2 = 0.0;
         for (int64_t k = lane; k < J.kpad; k += 64) {
             double xh = 0.0;
-            if (real && k < ell) xh = ((double)T[w + k] - mu) / sg;
+            if (real && k < ell) xh = ((double)sh_T[q + k] - mu) / sg;   // T[w + k]
             float vt;
             if constexpr (PREC == P_BF16) {
                 const unsigned short h = f32_to_bf16_rne((float)xh);
-                ((unsigned short *)J.xs)[xs_index(w, k, J.kpad, 2, tile)] = h;
+                ((unsigned short *)J.xs)[xs_index(row, k, J.kpad, 2, tile)] = h;
                 vt = bf16_to_f32(h);
             } else {
                 vt = (float)xh;
-                ((float *)J.xs)[xs_index(w, k, J.kpad, 4, tile)] = vt;
+                ((float *)J.xs)[xs_index(row, k, J.kpad, 4, tile)] = vt;
             }
             const double vtd = (double)vt;
             s = fma(xh, xh, s);
@@ -288,8 +320,8 @@ __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs,
         t2 = wave_sum(t2);
         r2 = wave_sum(r2);
         if (lane == 0) {
-            ((float *)J.shat)[w] = (float)s;
-            float *bm = (float *)(J.bmax + w / tile);
+            ((float *)J.shat)[row] = (float)s;
+            float *bm = (float *)(J.bmax + row / tile);
             atomic_max_f32(bm + 0, f32_up(s));
             atomic_max_f32(bm + 1, up_f32(sqrt(s)));
             atomic_max_f32(bm + 2, up_f32(sqrt(t2)));

@@ -331,6 +331,9 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     // row scalars of blocks I and J, double-buffered by tile parity: the
     // scalars of the next tile are loaded while the current one is screened
     __shared__ __attribute__((aligned(16))) S sh_s[2 * 2 * T256];
+    // source positions of the rows of blocks I and J (windows of a series in
+    // reference order; same double buffering), for the exclusion zone
+    __shared__ __attribute__((aligned(16))) int32_t sh_o[2 * 2 * T256];
 
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int wm = wave >> 1, wn = wave & 1;
@@ -357,6 +360,17 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                                          (lds_void *)(dst + wave * 64), 4, 0, 0);
         __builtin_amdgcn_global_load_lds((g_void *)(sb + ((int64_t)tile_J(e) * T256 + wave * 64) * 4 + lo),
                                          (lds_void *)(dst + T256 + wave * 64), 4, 0, 0);
+        if constexpr (MASKED) {
+            if (Q.perm && Q.motif) {
+                // the permutation is padded to whole blocks by the host
+                const unsigned char *pb = (const unsigned char *)Q.perm;
+                int32_t *od = sh_o + half * (2 * T256);
+                __builtin_amdgcn_global_load_lds((g_void *)(pb + ((int64_t)tile_I(e) * T256 + wave * 64) * 4 + lo),
+                                                 (lds_void *)(od + wave * 64), 4, 0, 0);
+                __builtin_amdgcn_global_load_lds((g_void *)(pb + ((int64_t)tile_J(e) * T256 + wave * 64) * 4 + lo),
+                                                 (lds_void *)(od + T256 + wave * 64), 4, 0, 0);
+            }
+        }
     };
 
     int32_t t = next_valid((int32_t)blockIdx.x);
@@ -404,6 +418,7 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         // this tile's row scalars were loaded one tile ago (or before the
         // loop) and are older than every slice waited for since
         const S *sh_t = sh_s + (tcount & 1) * (2 * T256);
+        const int32_t *sh_ot = sh_o + (tcount & 1) * (2 * T256);
         const int32_t tn = next_valid(t + stride);
         if (tn < count) load_scalars(tn, (tcount + 1) & 1);
         ++tcount;
@@ -487,8 +502,46 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         // ---------------- epilogue ----------------
         // 32-bit row/column indices (n < 2^31 is enforced by the host)
         const int32_t n = (int32_t)P.n, excl = (int32_t)P.excl;
-        const bool full = !MASKED || (((int64_t)J * T256 - ((int64_t)I * T256 + T256 - 1) >= P.excl) &&
+        // windows in reference order: admissibility compares source positions
+        // (only masked tiles carry such problems; motifs are never int8)
+        const bool pexcl = MASKED && FOLD && P.perm && P.motif;
+        const bool full = !MASKED || (!pexcl && ((int64_t)J * T256 - ((int64_t)I * T256 + T256 - 1) >= P.excl) &&
                                       ((int64_t)I * T256 + T256 <= P.n) && ((int64_t)J * T256 + T256 <= P.n));
+        // source positions of this lane's 4 columns and, per block a, 16 rows
+        int32_t oj[MB256] = {0, 0, 0, 0};
+        if (pexcl) {
+            const u32x4 v = lds_landed_4x32(sh_ot + T256 + wn * WT256 + lrow);
+            oj[0] = (int32_t)v.x;
+            oj[1] = (int32_t)v.y;
+            oj[2] = (int32_t)v.z;
+            oj[3] = (int32_t)v.w;
+        }
+        auto load_oi = [&](int a, int32_t (&oi)[16]) {
+            u32x4 v[4];
+            lds_landed_4x128(sh_ot + wm * WT256 + a * 32 + 4 * lhalf, v[0], v[1], v[2], v[3]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                oi[4 * q] = (int32_t)v[q].x;
+                oi[4 * q + 1] = (int32_t)v[q].y;
+                oi[4 * q + 2] = (int32_t)v[q].z;
+                oi[4 * q + 3] = (int32_t)v[q].w;
+            }
+        };
+        // Admissible pair of screen rows gi, gj (source positions oa, ob),
+        // evaluated without branches (bitwise, not short-circuit). Rows in
+        // position order: gj - gi >= excl and gj < n (which imply gi < gj <
+        // n). Rows in reference order: gi < gj < n and |ob - oa| >= excl,
+        // tested as (oa + excl - 1 - ob) >= 2 excl - 1 in unsigned 32-bit
+        // arithmetic (positions below 2^31, excl at most 2^30, checked by the
+        // host).
+        const uint32_t pspan = 2u * (uint32_t)excl - 1u;
+        auto far_apart = [&](int32_t oa, int32_t ob) {
+            return ((uint32_t)oa + (uint32_t)(excl - 1) - (uint32_t)ob) >= pspan;
+        };
+        auto adm_pos = [&](int32_t gi, int32_t gj) { return (gj - gi >= excl) & (gj < n); };
+        auto adm_ref = [&](int32_t gi, int32_t gj, int32_t oa, int32_t ob) {
+            return far_apart(oa, ob) & (gj > gi) & (gj < n);
+        };
         // screen value of accumulator element r of block (a, b)
         S sj[MB256];
         if constexpr (!FOLD) {
@@ -547,24 +600,74 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                 }
             }
         } else if constexpr (MASKED) {
+            if constexpr (FOLD) {
+                // max of acc over the admissible elements, one accumulator
+                // block at a time (as above), every test a select. Three
+                // forms, chosen per tile: rows in position order; rows in
+                // reference order off the diagonal and the ragged edge
+                // (positions alone decide); and the rest.
+                const int form = !pexcl ? 0 : ((I != J) && ((int64_t)J * T256 + T256 <= P.n)) ? 1 : 2;
+                S mx = -SINF;
 #pragma unroll
-            for (int a = 0; a < MB256; ++a) {
-                S si[16];
-                if constexpr (!FOLD) load_si(a, si);
+                for (int a = 0; a < MB256; ++a) {
+                    int32_t oi[16] = {};
+                    if (form != 0) load_oi(a, oi);
+                    S ma = -SINF;
+                    // (a scheduling fence per row, and a row position the
+                    // compiler cannot share between the forms, keep the tests
+                    // next to their use: hoisted, they outgrow the free
+                    // registers)
+                    if (form == 1) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
+                        for (int r = 0; r < 16; ++r) {
+                            int32_t o = oi[r];
+                            asm volatile("" : "+v"(o));
 #pragma unroll
-                    for (int b = 0; b < MB256; ++b) {
-                        const int32_t gj = j0 + b * 32 + lrow;
-                        const bool ok = (gj - gi >= excl) && (gi < n) && (gj < n);
-                        S dv;
-                        if constexpr (FOLD) dv = -2.0f * acc[a][b][r];
-                        else dv = (S)(si[r] + part(acc[a][b][r], sj[b]));
-                        best = ok ? smin(best, dv) : best;
+                            for (int b = 0; b < MB256; ++b)
+                                ma = fmaxf(ma, far_apart(o, oj[b]) ? acc[a][b][r] : -SINF);
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+                    } else if (form == 0) {
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
+#pragma unroll
+                            for (int b = 0; b < MB256; ++b)
+                                ma = fmaxf(ma, adm_pos(gi, j0 + b * 32 + lrow) ? acc[a][b][r] : -SINF);
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) {
+                            const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
+#pragma unroll
+                            for (int b = 0; b < MB256; ++b)
+                                ma = fmaxf(ma, adm_ref(gi, j0 + b * 32 + lrow, oi[r], oj[b]) ? acc[a][b][r] : -SINF);
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
                     }
+                    asm volatile("" : "+v"(ma));
+                    mx = fmaxf(mx, ma);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-                __builtin_amdgcn_sched_barrier(0);
+                best = -2.0f * mx;
+            } else {
+#pragma unroll
+                for (int a = 0; a < MB256; ++a) {
+                    S si[16];
+                    load_si(a, si);
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
+#pragma unroll
+                        for (int b = 0; b < MB256; ++b) {
+                            const int32_t gj = j0 + b * 32 + lrow;
+                            const S dv = (S)(si[r] + part(acc[a][b][r], sj[b]));
+                            best = adm_pos(gi, gj) ? smin(best, dv) : best;
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
             }
         }
 
@@ -583,8 +686,10 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
             }
             const S thr = thrU > thrR ? thrU : thrR;
             if (wmin(best) <= thr) {
-#pragma unroll
-                for (int a = 0; a < MB256; ++a)
+#pragma clang loop unroll(full)
+                for (int a = 0; a < MB256; ++a) {
+                    int32_t oi[16] = {};
+                    if (pexcl) load_oi(a, oi);
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
                         const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
@@ -596,8 +701,8 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                             S dv;
                             if constexpr (FOLD) dv = -2.0f * acc[a][b][r];
                             else dv = (S)(si + part(acc[a][b][r], sj[b]));
-                            const bool ok = full || ((gj - gi >= excl) && (gi < n) && (gj < n));
-                            if (ok && dv <= thr) {
+                            const bool ok = full | (pexcl ? adm_ref(gi, gj, oi[r], oj[b]) : adm_pos(gi, gj));
+                            if (ok & (dv <= thr)) {
                                 Cand cd;
                                 cd.i = gi;
                                 cd.j = gj;
@@ -614,6 +719,7 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                             }
                         }
                     }
+                }
             }
         }
         if constexpr (MODE & M_MIN) {

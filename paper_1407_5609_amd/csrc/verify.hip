@@ -138,39 +138,66 @@ void launch_select(const Prob *probs, const uint64_t *tiles, int64_t ntiles, con
 }
 
 // ---------------------------------------------------------------------------
-// canonical squared distance
+// canonical squared distance, one wave per pair: the lanes form 64
+// consecutive terms at a time (loads and normalisations in parallel), and
+// every lane then adds them in order, broadcast lane by lane, so the sum is
+// the sequential FP64 sum over k = 0 .. d-1. The next 64 terms are formed
+// before the current ones are added.
 // ---------------------------------------------------------------------------
-__device__ double canonical_d2(const Prob &P, int64_t i, int64_t j)
+__device__ __forceinline__ double lane_value(double v, int u)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), u);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ double canonical_d2(const Prob &P, int64_t i, int64_t j, int lane)
 {
     const int64_t d = P.d;
-    if (P.motif) {
-        const float *T = (const float *)P.src;
-        const double mi = P.mu[i], si = P.sigma[i], mj = P.mu[j], sj = P.sigma[j];
-        double acc = 0.0;
-        for (int64_t k = 0; k < d; ++k) {
-            const double xi = ((double)T[i + k] - mi) / si;
-            const double xj = ((double)T[j + k] - mj) / sj;
-            const double t = xi - xj;
-            acc = fma(t, t, acc);
-        }
-        return acc;
-    }
     if (P.src_i8) {
+        // exact integer sum: any order
         const signed char *x = (const signed char *)P.src + i * P.ld;
         const signed char *y = (const signed char *)P.src + j * P.ld;
         long long acc = 0;
-        for (int64_t k = 0; k < d; ++k) {
+        for (int64_t k = lane; k < d; k += 64) {
             const long long t = (long long)x[k] - (long long)y[k];
             acc += t * t;
         }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
         return (double)acc;
     }
-    const float *x = (const float *)P.src + i * P.ld;
-    const float *y = (const float *)P.src + j * P.ld;
+    const float *T = (const float *)P.src;
+    const float *x = T + i * P.ld, *y = T + j * P.ld;
+    double mi = 0.0, si = 1.0, mj = 0.0, sj = 1.0;
+    if (P.motif) {
+        mi = P.mu[i], si = P.sigma[i], mj = P.mu[j], sj = P.sigma[j];
+        x = T + i;
+        y = T + j;
+    }
+    auto term = [&](int64_t k) -> double {
+        if (k >= d) return 0.0;
+        if (P.motif) return ((double)x[k] - mi) / si - ((double)y[k] - mj) / sj;
+        return (double)x[k] - (double)y[k];
+    };
     double acc = 0.0;
-    for (int64_t k = 0; k < d; ++k) {
-        const double t = (double)x[k] - (double)y[k];
-        acc = fma(t, t, acc);
+    double t = term(lane);
+    for (int64_t c0 = 0; c0 < d; c0 += 64) {
+        const double tn = term(c0 + 64 + lane);
+        if (c0 + 64 <= d) {
+#pragma unroll
+            for (int u = 0; u < 64; ++u) {
+                const double tu = lane_value(t, u);
+                acc = fma(tu, tu, acc);
+            }
+        } else {
+            for (int u = 0; u < (int)(d - c0); ++u) {
+                const double tu = lane_value(t, u);
+                acc = fma(tu, tu, acc);
+            }
+        }
+        t = tn;
     }
     return acc;
 }
@@ -193,19 +220,24 @@ __device__ __forceinline__ void cand_rows(const Prob &P, const Cand &cd, int64_t
     b = x < y ? y : x;
 }
 
-__global__ void verify_cpp_kernel(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec,
-                                  int tile, double *cand_d2, ResDev *res)
+// One wave per candidate (4 per work-group).
+__global__ __launch_bounds__(256) void verify_cpp_kernel(const Prob *probs, const Cand *cand, const uint32_t *cnt,
+                                                         uint32_t cap, int prec, int tile, double *cand_d2,
+                                                         ResDev *res)
 {
     const int64_t m = min((int64_t)*cnt, (int64_t)cap);
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < m; c += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t c = blockIdx.x * 4 + (threadIdx.x >> 6); c < m; c += (int64_t)gridDim.x * 4) {
         const Cand cd = cand[c];
         const Prob &P = probs[cd.p];
         int64_t a, b;
         cand_rows(P, cd, a, b);
-        const double d2 = canonical_d2(P, a, b);
-        cand_d2[c] = d2;
-        atomicMin(&res[cd.p].best_d2, (unsigned long long)__double_as_longlong(d2));
-        record_error(&res[cd.p], (double)cd.dt, d2, tile_bound_of(P, cd.i / tile, cd.j / tile, prec));
+        const double d2 = canonical_d2(P, a, b, lane);
+        if (lane == 0) {
+            cand_d2[c] = d2;
+            atomicMin(&res[cd.p].best_d2, (unsigned long long)__double_as_longlong(d2));
+            record_error(&res[cd.p], (double)cd.dt, d2, tile_bound_of(P, cd.i / tile, cd.j / tile, prec));
+        }
     }
 }
 
@@ -223,35 +255,39 @@ __global__ void pick_cpp_kernel(const Prob *probs, const Cand *cand, const uint3
     }
 }
 
-__global__ void verify_frnn_kernel(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec,
-                                   int tile, uint64_t *keys, double *vals, uint32_t *out_cnt, uint32_t out_cap,
-                                   ResDev *res)
+__global__ __launch_bounds__(256) void verify_frnn_kernel(const Prob *probs, const Cand *cand, const uint32_t *cnt,
+                                                          uint32_t cap, int prec, int tile, uint64_t *keys,
+                                                          double *vals, uint32_t *out_cnt, uint32_t out_cap,
+                                                          ResDev *res)
 {
     const int64_t m = min((int64_t)*cnt, (int64_t)cap);
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < m; c += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t c = blockIdx.x * 4 + (threadIdx.x >> 6); c < m; c += (int64_t)gridDim.x * 4) {
         const Cand cd = cand[c];
         const Prob &P = probs[cd.p];
         int64_t a, b;
         cand_rows(P, cd, a, b);
-        const double d2 = canonical_d2(P, a, b);
-        // the bound is indexed by screen-row blocks
-        record_error(&res[cd.p], (double)cd.dt, d2, tile_bound_of(P, cd.i / tile, cd.j / tile, prec));
-        if (d2 <= P.r2) {
-            const uint32_t k = atomicAdd(out_cnt, 1u);
-            if (k < out_cap) {
-                keys[k] = ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
-                vals[k] = d2;
+        const double d2 = canonical_d2(P, a, b, lane);
+        if (lane == 0) {
+            // the bound is indexed by screen-row blocks
+            record_error(&res[cd.p], (double)cd.dt, d2, tile_bound_of(P, cd.i / tile, cd.j / tile, prec));
+            if (d2 <= P.r2) {
+                const uint32_t k = atomicAdd(out_cnt, 1u);
+                if (k < out_cap) {
+                    keys[k] = ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
+                    vals[k] = d2;
+                }
             }
         }
     }
 }
 
-static unsigned verify_grid() { return 1024; }
+static unsigned verify_grid() { return 2048; }   // work-groups of 4 waves, a candidate per wave
 
 void launch_verify_cpp(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec, int tile,
                        double *cand_d2, ResDev *res, hipStream_t st)
 {
-    hipLaunchKernelGGL(verify_cpp_kernel, dim3(verify_grid()), dim3(64), 0, st, probs, cand, cnt, cap, prec, tile,
+    hipLaunchKernelGGL(verify_cpp_kernel, dim3(verify_grid()), dim3(256), 0, st, probs, cand, cnt, cap, prec, tile,
                        cand_d2, res);
 }
 
@@ -265,7 +301,7 @@ void launch_verify_frnn(const Prob *probs, const Cand *cand, const uint32_t *cnt
                         uint64_t *keys, double *vals, uint32_t *out_cnt, uint32_t out_cap, ResDev *res,
                         hipStream_t st)
 {
-    hipLaunchKernelGGL(verify_frnn_kernel, dim3(verify_grid()), dim3(64), 0, st, probs, cand, cnt, cap, prec, tile,
+    hipLaunchKernelGGL(verify_frnn_kernel, dim3(verify_grid()), dim3(256), 0, st, probs, cand, cnt, cap, prec, tile,
                        keys, vals, out_cnt, out_cap, res);
 }
 

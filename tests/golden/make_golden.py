@@ -1,15 +1,15 @@
-"""Write the expected results of the five workloads, computed by the CPU oracle.
+"""Write the expected results of the workloads, computed by the CPU oracle.
 
 Every value stored under tests/golden/ by this script comes from ``oracle``
 (plain FP64 brute force) applied to the seeded inputs of ``workloads``; nothing
 here touches the GPU library. Floats are stored with ``float.hex`` so that the
 comparison in the tests is exact.
 
-Usage:  python tests/golden/make_golden.py [points|motif|snp|mixture|batch ...]
+Usage:  python tests/golden/make_golden.py [points|motif|walk|snp|mixture|batch ...]
         (no argument: all). Threads: ORACLE_THREADS (default: all cores).
 
 Run times on 8 cores (latency-bound scalar FP64): points < 1 s, motif ~4 min,
-snp ~20 min, mixture ~1 h (one nearest-neighbour pass), batch sample ~10 min.
+walk ~45 min, snp ~20 min, mixture ~1 h (one nearest-neighbour pass), batch sample ~10 min.
 """
 import json
 import math
@@ -64,6 +64,17 @@ def motif():
     best, (pairs, dd) = oracle.motif(c["T"], c["ell"], c["excl"], c["R2"])
     _write(c["name"], {
         "workload": c["name"], "source": "oracle.motif on workloads.cfg_motif",
+        "ell": c["ell"], "excl": c["excl"], "plant": list(c["plant"]), "R2": _hex(c["R2"]),
+        "closest_pair": {"i": best[0], "j": best[1], "d2": _hex(best[2])},
+        "frnn": _frnn_obj(pairs, dd), "oracle_seconds": time.time() - t})
+
+
+def walk():
+    c = W.cfg_walk()
+    t = time.time()
+    best, (pairs, dd) = oracle.motif(c["T"], c["ell"], c["excl"], c["R2"])
+    _write(c["name"], {
+        "workload": c["name"], "source": "oracle.motif on workloads.cfg_walk",
         "ell": c["ell"], "excl": c["excl"], "plant": list(c["plant"]), "R2": _hex(c["R2"]),
         "closest_pair": {"i": best[0], "j": best[1], "d2": _hex(best[2])},
         "frnn": _frnn_obj(pairs, dd), "oracle_seconds": time.time() - t})
@@ -146,7 +157,7 @@ def batch():
         "sample": out, "oracle_seconds": time.time() - t})
 
 
-JOBS = {"points": points, "motif": motif, "snp": snp, "mixture": mixture, "batch": batch}
+JOBS = {"points": points, "motif": motif, "walk": walk, "snp": snp, "mixture": mixture, "batch": batch}
 
 if __name__ == "__main__":
     if os.environ.get("ORACLE_THREADS"):

@@ -99,6 +99,29 @@ def test_mixture_full_size_golden_with_pruning(ctx, torch_dev):
     print("pruned", st.tiles_pruned, "of", st.tiles_pruned + st.tiles_total, "tiles")
 
 
+def test_motif_full_size_golden_with_pruning(ctx, torch_dev):
+    """The 65,536-sample random walk (windows of 256) with reference-point
+    pruning: the windows are screened in reference order and the answers
+    equal the oracle's stored ones."""
+    g = _golden("motif_L65536_l256.json")
+    want_pair, want_pairs, want_d2 = _want(g)
+    c = W.cfg_motif()
+    t = _dev(c["T"], torch_dev)
+    ctx.set_pruning(10, 10.0, seed=1)
+    try:
+        for prec in ("f32", "bf16"):
+            best, (p, d) = ctx.motif(t, c["ell"], excl=c["excl"], R2=c["R2"], precision=prec)
+            st = ctx.stats()
+            assert (best.i, best.j, best.d2) == want_pair, (prec, best)
+            assert np.array_equal(p.cpu().numpy(), want_pairs)
+            assert np.array_equal(d.cpu().numpy(), want_d2)
+            assert st.valid_pairs == W.valid_pairs_motif(65536, 256, 256)
+            assert st.max_err_over_bound <= 1.0
+            print(prec, "pruned", st.tiles_pruned, "of", st.tiles_pruned + st.tiles_total, "tiles")
+    finally:
+        ctx.set_pruning(0)
+
+
 def _window_d2(T, ell, i, j):
     """Canonical squared distance of windows i and j, each z-normalised on its own."""
     a, _, _ = oracle.znorm(T[i:i + ell], ell)

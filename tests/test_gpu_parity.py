@@ -48,6 +48,13 @@ def _check_pair(best, want):
     assert abs(best.d2 - want[2]) <= 1e-9 * max(abs(want[2]), 1e-300)
 
 
+def _window_d2(T, ell, i, j):
+    """Canonical squared distance of windows i and j, each z-normalised on its own."""
+    a, _, _ = oracle.znorm(T[i:i + ell], ell)
+    b, _, _ = oracle.znorm(T[j:j + ell], ell)
+    return oracle.d2(np.concatenate([a, b]), 0, 1)
+
+
 def _check_frnn(got, want):
     gp, gd = got
     wp, wd = want
@@ -415,6 +422,75 @@ def test_pruned_int8_and_frnn_only(ctx, torch_dev, tile):
     oi, oj, od = oracle.closest_pair(X)
     assert (best.i, best.j, best.d2) == (oi, oj, float(od))
     _check_frnn((p, d), oracle.frnn(X, 40))
+
+
+@pytest.mark.parametrize("q", [1, 4])
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("length,ell,excl", [(3000, 64, 0), (5000, 100, 50), (2100, 128, 1), (1300, 16, 0)])
+def test_pruned_motif_matches_oracle(ctx, torch_dev, prec, q, length, ell, excl):
+    """Windows in reference order: the exclusion zone is applied to window
+    positions, not screen rows; answers equal the oracle's."""
+    rng = np.random.default_rng(length + ell + q)
+    T = W.random_walk(rng, length)
+    W.plant_motif(rng, T, ell)
+    R2 = 0.05 * ell
+    ctx.set_pruning(q, 10.0, seed=q)
+    try:
+        best, fr = ctx.motif(_dev(T, torch_dev), ell, excl=excl, R2=R2, precision=prec)
+        st = ctx.stats()
+        best_only, _ = ctx.motif(_dev(T, torch_dev), ell, excl=excl, precision=prec)
+    finally:
+        ctx.set_pruning(0)
+    ob, ofr = oracle.motif(T, ell, excl=excl if excl > 0 else ell, R2=R2)
+    _check_pair(best, ob)
+    _check_pair(best_only, ob)
+    _check_frnn(fr, ofr)
+    assert st.tile == 256 and st.max_err_over_bound <= 1.0
+    assert st.valid_pairs == W.valid_pairs_motif(length, ell, excl if excl > 0 else ell)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_pruned_motif_exclusion_boundary_and_ties(ctx, torch_dev, prec):
+    """A periodic series: windows one period apart are identical, so the
+    reference order puts whole runs of exact duplicates side by side; the
+    exclusion zone (on positions) decides which of them may pair, and ties go
+    to the lexicographic minimum in window positions."""
+    P, ell = 37, 16
+    rng = np.random.default_rng(15)
+    T = np.tile(rng.normal(0, 1, P).astype(np.float32), 40)
+    t = _dev(T, torch_dev)
+    ctx.set_pruning(3, 10.0, seed=2)
+    try:
+        best, _ = ctx.motif(t, ell, excl=P, precision=prec)
+        assert (best.i, best.j, best.d2) == (0, P, 0.0)
+        best, _ = ctx.motif(t, ell, excl=P + 1, precision=prec)
+        assert (best.i, best.j, best.d2) == (0, 2 * P, 0.0)
+        _, fr = ctx.motif(t, ell, excl=P + 1, R2=0.0, precision=prec, want_pair=False)
+    finally:
+        ctx.set_pruning(0)
+    _check_frnn(fr, oracle.motif(T, ell, excl=P + 1, R2=0.0)[1])
+
+
+def test_pruned_motif_drops_tiles_on_a_random_walk(ctx, torch_dev):
+    """Random walk of 20,000 samples, windows of 1,024 (the shapes the paper
+    measures MPR on), q = 10, f = 10: tiles are dropped and the reported pair
+    is admissible, its squared distance is the oracle's canonical value for
+    that pair and no larger than the oracle's value for the planted pair."""
+    rng = np.random.default_rng(5609)
+    ell = 1024
+    T = W.random_walk(rng, 20000)
+    a, b = W.plant_motif(rng, T, ell, 0.01)
+    ctx.set_pruning(10, 10.0, seed=1)
+    try:
+        best, _ = ctx.motif(_dev(T, torch_dev), ell, precision="bf16")
+        st = ctx.stats()
+    finally:
+        ctx.set_pruning(0)
+    assert best.j - best.i >= ell
+    assert best.d2 == _window_d2(T, ell, best.i, best.j)
+    assert best.d2 <= _window_d2(T, ell, a, b)
+    assert st.tiles_pruned > 0
+    print("pruned", st.tiles_pruned, "of", st.tiles_pruned + st.tiles_total, "tiles")
 
 
 def test_pruning_arguments(ctx):

@@ -19,6 +19,7 @@ from .synth import (  # noqa: F401
     batch_series,
     cfg_points_small,
     cfg_motif,
+    cfg_walk,
     cfg_mixture,
     cfg_batch,
     cfg_snp,

@@ -26,9 +26,10 @@ MASTER_SEED = 14075609  # the arXiv identifier 1407.5609
 
 
 def config_rng(index: int) -> np.random.Generator:
-    """Generator for workload ``index`` (0..4): PCG64 seeded from child
-    ``index`` of ``SeedSequence(MASTER_SEED).spawn(5)``."""
-    return np.random.default_rng(np.random.SeedSequence(MASTER_SEED).spawn(5)[index])
+    """Generator for workload ``index`` (0..15): PCG64 seeded from child
+    ``index`` of ``SeedSequence(MASTER_SEED).spawn(16)`` (children do not
+    depend on how many are spawned)."""
+    return np.random.default_rng(np.random.SeedSequence(MASTER_SEED).spawn(16)[index])
 
 
 # ----------------------------------------------------------------------------
@@ -161,6 +162,18 @@ def cfg_motif(length: int = 65536, ell: int = 256):
     T = random_walk(rng, length)
     plant = plant_motif(rng, T, ell, 0.01)
     return {"name": f"motif_L{length}_l{ell}", "T": T, "ell": ell, "excl": ell,
+            "plant": plant, "R": 2.0, "R2": 4.0}
+
+
+def cfg_walk(length: int = 100000, ell: int = 1024):
+    """Reference-point pruning shape (the paper's MPR runs: random walks of
+    10,000-100,000 samples, windows of 1,024): random walk of length 100,000,
+    l=1024, exclusion |i-j| < l, one planted motif (noise sd 0.01), FRNN
+    radius 2.0 in z-normalised units."""
+    rng = config_rng(5)
+    T = random_walk(rng, length)
+    plant = plant_motif(rng, T, ell, 0.01)
+    return {"name": f"walk_L{length}_l{ell}", "T": T, "ell": ell, "excl": ell,
             "plant": plant, "R": 2.0, "R2": 4.0}
 
 
