@@ -15,7 +15,7 @@ pass-1 screen), timed with HIP events on the call's stream; `cpu_baseline` is
 the CPU oracle on a bounded sample (rank 0, N = 1 only).
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
-    python bench.py --workload {mixture,points,motif,walk,batch,snp}   (the other workloads, same JSON form)
+    python bench.py --workload {mixture,points,motif,walk,batch,snp,strings,two_locus}   (same JSON form)
     python bench.py --workload walk --prune 10                   (reference-point tile pruning)
 """
 import argparse
@@ -209,6 +209,76 @@ class Walk(Motif):
         self._setup(torch, W.cfg_walk(), "walk_L100000_l1024.json")
 
 
+class Strings(Workload):
+    """Least correlated pair of 20,000 strings of length 64 over 4 letters
+    (Section 5: codes against complements on the INT8 matrix cores);
+    --query most runs the most correlated pair (Hamming closest pair)."""
+    name = "strings"
+    precs = ("i8",)
+    query = "least"
+
+    def __init__(self, W, torch):
+        c = W.cfg_strings()
+        self.g = _golden(f"{c['name']}.json")
+        self.Sh, self.sigma = c["S"], c["sigma"]
+        self.S = torch.from_numpy(self.Sh).to("cuda:0")
+        self.n, self.k = self.Sh.shape
+        self.flops_per_pair = 2.0 * self.sigma * self.k   # one multiply-add per code bit
+        self.config = {"workload": f"{c['name']}: exact least correlated pair of strings (one-hot codes vs "
+                                   "complements, INT8 matrix cores)", "n": self.n, "k": self.k,
+                       "sigma": self.sigma}
+
+    def step(self, ctx, prec):
+        r = ctx.strings_pair(self.S, self.sigma, self.query)
+        w = self.g[self.query]
+        return (r.i, r.j, r.matches) == (w["i"], w["j"], w["matches"])
+
+    def cpu_baseline(self, target_s):
+        import oracle
+        S, m0 = self.Sh, 1000
+
+        def grow(m, ratio):
+            return m0 if m is None else int(min(S.shape[0], max(m0, m / ratio ** 0.5)))
+        m, dt = _timed_oracle(lambda m: oracle.strings_pair(S[:m], self.sigma, self.query), grow, target_s)
+        pairs = m * (m - 1) // 2
+        return pairs / dt, f"{self.query} correlated pair of the first {m} strings ({pairs} pairs), {dt:.1f} s"
+
+
+class TwoLocus(Workload):
+    """Two-locus association on NOISE genotypes: 200 cases + 200 controls,
+    50,000 SNPs, one injected pair (Section 6, D = [A' A'; B' ~B'] on the
+    INT8 matrix cores)."""
+    name = "two_locus"
+    precs = ("i8",)
+
+    def __init__(self, W, torch):
+        c = W.cfg_two_locus()
+        self.g = _golden(f"{c['name']}.json")
+        self.Gh, self.m1, self.m2 = c["G"], c["m1"], c["m2"]
+        self.G = torch.from_numpy(self.Gh).to("cuda:0")
+        self.n = self.Gh.shape[1]
+        self.flops_per_pair = 2.0 * 3 * (self.m1 + self.m2)
+        self.config = {"workload": f"{c['name']}: exact two-locus SNP pair (columns of D = [A' A'; B' ~B'], INT8 "
+                                   "matrix cores)", "snps": self.n, "cases": self.m1, "controls": self.m2}
+
+    def step(self, ctx, prec):
+        r = ctx.two_locus(self.G, self.m1, self.m2, 0)
+        w = self.g["direction"]["0"]
+        return (r.i, r.j, r.matches) == (w["i"], w["j"], w["matches"])
+
+    def cpu_baseline(self, target_s):
+        import numpy as np
+        import oracle
+        G, m0 = self.Gh, 500
+
+        def grow(m, ratio):
+            return m0 if m is None else int(min(G.shape[1], max(m0, m / ratio ** 0.5)))
+        m, dt = _timed_oracle(lambda m: oracle.two_locus(np.ascontiguousarray(G[:, :m]), self.m1, self.m2, 0),
+                              grow, target_s)
+        pairs = m * (m - 1) // 2
+        return pairs / dt, f"two-locus pair among the first {m} SNPs ({pairs} pairs), {dt:.1f} s"
+
+
 class Batch(Workload):
     name = "batch"
     precs = ("auto", "f32")
@@ -244,7 +314,7 @@ class Batch(Workload):
         return pairs / dt, f"motifs of the first {k} series of the batch ({pairs} window pairs), {dt:.1f} s"
 
 
-WORKLOADS = {w.name: w for w in (Mixture, SmallPoints, Motif, Walk, Batch, Snp)}
+WORKLOADS = {w.name: w for w in (Mixture, SmallPoints, Motif, Walk, Batch, Snp, Strings, TwoLocus)}
 
 
 def main():
@@ -256,9 +326,9 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the comparison precision (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--query", default="points", choices=["points", "cpp"],
-                    help="point and single-series motif workloads: closest pair + radius pairs (default) "
-                         "or the closest pair alone")
+    ap.add_argument("--query", default=None, choices=["points", "cpp", "most", "least"],
+                    help="point and single-series motif workloads: closest pair + radius pairs (points, the "
+                         "default) or the closest pair alone (cpp); strings: least (default) or most correlated")
     ap.add_argument("--prune", type=int, default=0,
                     help="reference-point tile pruning with this many references (point and single-series motif workloads; 0: off)")
     ap.add_argument("--prune-f", type=float, default=10.0, help="projection factor of the references")
@@ -278,11 +348,16 @@ def main():
     torch.cuda.set_device(0)
     note(f"generating the {args.workload} workload")
     wl = WORKLOADS[args.workload](W, torch)
-    if args.query != "points":
+    if args.query == "cpp":
         if not isinstance(wl, (Points, Motif)):
-            sys.exit(f"--query {args.query} applies to the point and single-series motif workloads only")
+            sys.exit("--query cpp applies to the point and single-series motif workloads only")
         wl.query = args.query
         wl.config = dict(wl.config, query="closest pair only")
+    elif args.query in ("most", "least"):
+        if not isinstance(wl, Strings):
+            sys.exit(f"--query {args.query} applies to the strings workload only")
+        wl.query = args.query
+        wl.config = dict(wl.config, query=f"{args.query} correlated pair")
     ctx = cp.Context(0)
     if args.prune:
         ctx.set_pruning(args.prune, args.prune_f, seed=1)
@@ -321,6 +396,8 @@ def main():
         work, dur_ms = wl.flops_per_pair * st.screen_pairs, screen_ms
         kernel = (f"screen256_kernel<{pprec}, min, full tiles>" if st.tile == 256
                   else f"screen_kernel<{pprec}, min> (128-row tiles, all tiles)")
+        if args.prune and isinstance(wl, Motif):
+            kernel = f"screen256_kernel<{pprec}, min, masked tiles> (windows in reference order)"
     achieved = work / (dur_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,

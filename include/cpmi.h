@@ -227,6 +227,54 @@ int cpmi_tune_lookup(cpmi_ctx *ctx, int dtype, int precision, int64_t d, double 
  * 0..32 or f not finite and > 0. */
 int cpmi_set_pruning(cpmi_ctx *ctx, int q, double f, uint64_t seed);
 
+/* Result of a string-pair search. i < j are the two strings (SNPs for
+ * cpmi_two_locus); matches counts the positions where they agree
+ * (cpmi_strings_pair: u_ij of Section 5; cpmi_two_locus: the matching bits of
+ * columns i and n + j of D), out of `length` (k, or the column length
+ * 3 (m1 + m2)). status as in cpmi_pair. */
+typedef struct {
+    int64_t i, j;
+    int64_t matches;
+    int64_t length;
+    int32_t status;
+    int32_t reserved;
+} cpmi_match_pair;
+
+/* modes of cpmi_strings_pair */
+enum { CPMI_MOST_CORRELATED = 0, CPMI_LEAST_CORRELATED = 1 };
+
+/* Most or least correlated pair of n strings of length k over the alphabet
+ * {0, ..., sigma-1} (Section 5: the correlation of two strings is the fraction
+ * of positions where they agree, so the most correlated pair is the closest
+ * pair in Hamming distance). strings: device, int8, row i = string i, row
+ * stride ld >= k. Computed exactly and by brute force on the INT8 matrix
+ * cores through the one-hot encoding of Section 5 (each symbol -> sigma bits
+ * with one set): the squared distance of two code rows is their Hamming
+ * distance 2 (k - u_ij), and between a code row and a complemented one it is
+ * sigma k - 2 (k - u_ij) (the identity M(A'_i, ~A'_j) = 2 (k - u_ij)), so the
+ * least correlated pair is the closest (code, complement) pair with i != j.
+ * Ties go to the lexicographically smallest (i, j). out: host. Needs n >= 2,
+ * k >= 1, 2 <= sigma <= 64, sigma k <= 2^20. Errors: ERR_ARG (shapes, mode,
+ * or a symbol outside the alphabet), ERR_NOPAIR (n < 2). */
+int cpmi_strings_pair(cpmi_ctx *ctx, const int8_t *strings, int64_t n, int64_t k, int64_t ld, int sigma,
+                      int mode, void *stream, cpmi_match_pair *out);
+
+/* Two-locus association (Section 6): genotypes (device, int8 in {0, 1, 2},
+ * (m1 + m2) x n, row s = subject s, row stride ld >= n; the first m1 rows
+ * are cases, the rest controls). With A', B' the one-hot codes of the cases'
+ * and controls' columns, returns the SNP pair (i, j), i != j, whose columns i
+ * and n + j of D = [A' A'; B' ~B'] agree in the most bits (direction 0; that
+ * count is m1 + 2 u_A(i,j) + 2 (m2 - u_B(i,j)), so the pair maximises
+ * u_A - u_B, the number of subjects in which SNPs i and j agree among cases
+ * minus among controls: P_A(i,j) - P_B(i,j) when m1 = m2), or of
+ * D = [A' ~A'; B' B'] (direction 1: u_B - u_A). Exact, brute force on the
+ * INT8 matrix cores; ties to the lexicographically smallest (i, j), reported
+ * with i < j (the count is symmetric in i, j). out: host. Needs m1, m2 >= 1,
+ * n >= 2, 3 (m1 + m2) <= 2^20. Errors: ERR_ARG (shapes, direction, or a value
+ * outside {0, 1, 2}), ERR_NOPAIR (n < 2). */
+int cpmi_two_locus(cpmi_ctx *ctx, const int8_t *genotypes, int64_t m1, int64_t m2, int64_t n, int64_t ld,
+                   int direction, void *stream, cpmi_match_pair *out);
+
 /* Library version (major * 10000 + minor * 100 + patch). */
 int cpmi_version(void);
 

@@ -35,6 +35,16 @@ int cpmi_dbg_znorm(cpmi_ctx *ctx, const float *series, int64_t len, int64_t ell,
  * the count, or ERR_ARG. */
 int64_t cpmi_dbg_tile_list(int64_t n, int64_t excl, int tile, uint64_t *out, int64_t cap);
 
+/* Host only: the tile list of a two-set problem (the string searches of
+ * cpmi_strings_pair with CPMI_LEAST_CORRELATED and of cpmi_two_locus): na
+ * rows of the first set, nb of the second starting at row split (a multiple
+ * of 256, >= na); a pair (i, j) is admissible iff i < na, split <= j <
+ * split + nb and j - split != i. Writes min(count, cap) entries to out and
+ * the number of leading full-tile slots to *nfull (nullable); returns the
+ * count, or ERR_ARG. */
+int64_t cpmi_dbg_tile_list_two(int64_t na, int64_t nb, int64_t split, int tile, uint64_t *out, int64_t cap,
+                               int64_t *nfull);
+
 /* Host only: the screening-error bound applied to every pair of a tile whose
  * row blocks have maxima bI, bJ = (s^, ||x||, ||x~||, ||x - x~||) (4 floats
  * each), padded dimension kpad, true dimension d, screen precision, and

@@ -49,6 +49,16 @@ def lib():
             getattr(L, nm).argtypes = [_p, _i64, _i64, _i64, _i64, C.c_double, _p, _p, _i64]
         L.orc_nn_f32.restype = C.c_int
         L.orc_nn_f32.argtypes = [_p, _i64, _i64, _i64, _p]
+        L.orc_matches.restype = _i64
+        L.orc_matches.argtypes = [_p, _i64, _i64, _i64, _i64]
+        L.orc_encode.restype = None
+        L.orc_encode.argtypes = [_p, _i64, _i64, _i64, C.c_int, C.c_int, _p]
+        L.orc_bit_matches.restype = _i64
+        L.orc_bit_matches.argtypes = [_p, _p, _i64, _i64, _i64]
+        L.orc_strings_pair.restype = C.c_int
+        L.orc_strings_pair.argtypes = [_p, _i64, _i64, _i64, C.c_int, C.c_int, _p, _p, _p]
+        L.orc_two_locus.restype = C.c_int
+        L.orc_two_locus.argtypes = [_p, _i64, _i64, _i64, _i64, C.c_int, _p, _p, _p]
         L.orc_max_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -172,3 +182,69 @@ def motif(T: np.ndarray, ell: int, excl: int | None = None, R2: float | None = N
     best = closest_pair(Xhat, excl)
     fr = frnn(Xhat, R2, excl) if R2 is not None and R2 >= 0 else None
     return best, fr
+
+
+# ---------------------------------------------------------------------------
+# strings (Sections 5 and 6)
+# ---------------------------------------------------------------------------
+
+def _int8_rows(S: np.ndarray) -> np.ndarray:
+    S = np.ascontiguousarray(S)
+    if S.dtype != np.int8 or S.ndim != 2:
+        raise TypeError("expected a 2-D int8 array")
+    return S
+
+
+def matches(S: np.ndarray, i: int, j: int) -> int:
+    """m(S_i, S_j): positions where strings i and j agree (Section 5)."""
+    S = _int8_rows(S)
+    return int(lib().orc_matches(S.ctypes.data, S.shape[1], S.shape[1], i, j))
+
+
+def encode(S: np.ndarray, sigma: int, complement: bool = False) -> np.ndarray:
+    """Section 5's deterministic mapping (symbol v -> sigma bits, one set, the
+    paper's order 0 -> 0..001), optionally complemented: n x (sigma k) 0/1."""
+    S = _int8_rows(S)
+    n, k = S.shape
+    X = np.zeros((n, sigma * k), dtype=np.int8)
+    lib().orc_encode(S.ctypes.data, n, k, k, int(sigma), int(bool(complement)), X.ctypes.data)
+    return X
+
+
+def bit_matches(X: np.ndarray, Y: np.ndarray, i: int, j: int) -> int:
+    """M(X_i, Y_j): equal bits of two rows of 0/1 matrices of one width."""
+    X, Y = _int8_rows(X), _int8_rows(Y)
+    assert X.shape[1] == Y.shape[1]
+    return int(lib().orc_bit_matches(X.ctypes.data, Y.ctypes.data, X.shape[1], i, j))
+
+
+def strings_pair(S: np.ndarray, sigma: int, mode: str = "most"):
+    """(i, j, u): the most correlated pair (plain definition) or the least
+    correlated one (Section 5's code/complement reduction), u = m(S_i, S_j)."""
+    S = _int8_rows(S)
+    n, k = S.shape
+    oi, oj, om = C.c_int64(), C.c_int64(), C.c_int64()
+    rc = lib().orc_strings_pair(S.ctypes.data, n, k, k, int(sigma), {"most": 0, "least": 1}[mode],
+                                C.byref(oi), C.byref(oj), C.byref(om))
+    if rc == NOPAIR:
+        return None
+    if rc != 0:
+        raise MemoryError("oracle out of memory")
+    return int(oi.value), int(oj.value), int(om.value)
+
+
+def two_locus(G: np.ndarray, m1: int, m2: int, direction: int = 0):
+    """(i, j, matches): Section 6's pair of columns (i, n + j), i != j, of D =
+    [A' A'; B' ~B'] (direction 1: [A' ~A'; B' B']) with the most equal bits.
+    G: (m1 + m2) x n genotypes in {0, 1, 2}, cases first."""
+    G = _int8_rows(G)
+    assert G.shape[0] == m1 + m2
+    n = G.shape[1]
+    oi, oj, om = C.c_int64(), C.c_int64(), C.c_int64()
+    rc = lib().orc_two_locus(G.ctypes.data, int(m1), int(m2), n, n, int(direction), C.byref(oi), C.byref(oj),
+                             C.byref(om))
+    if rc == NOPAIR:
+        return None
+    if rc != 0:
+        raise MemoryError("oracle out of memory")
+    return int(oi.value), int(oj.value), int(om.value)

@@ -335,3 +335,163 @@ int orc_nn_f32(const float *X, int64_t n, int64_t d, int64_t ld, double *nn_out)
     free(buf);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Strings and correlation by matches (Sections 5 and 6).
+ *
+ *  - m(x, y) (Section 5 notation): the number of positions where two strings
+ *    of equal length agree. Strings are rows of symbols 0..sigma-1 (int8).
+ *    The correlation of strings i and j is m(S_i, S_j) / k. The most
+ *    correlated pair is the one of least Hamming distance (the light-bulb
+ *    problem statement of Section 4); by brute force over the definition.
+ *  - The deterministic mapping of Section 5: symbol v -> sigma bits with one
+ *    1, written as in the paper (0 -> 0..001, 1 -> 0..010, ...: the bit of
+ *    symbol v is the (v+1)-th from the right); the complement flips every bit.
+ *    M(X, Y) counts the equal bits of two bit strings.
+ *  - Least correlated pair (Section 5): with D1 the codes A' and D2 their
+ *    complements, the pair (a in D1, b in D2), a != b, whose bit strings agree
+ *    the most, reported as (min(a,b), max(a,b)).
+ *  - Two-locus association (Section 6): D = [A' A'; B' ~B'] (direction 0;
+ *    direction 1 swaps which half is complemented: [A' ~A'; B' B']), with A'
+ *    and B' the codes of the cases' and the controls' SNP columns; the pair
+ *    of columns (i, n + j), i != j, with the most equal bits, reported as
+ *    (min(i,j), max(i,j)).
+ * Ties go to the lexicographically smallest reported (i, j).
+ * ---------------------------------------------------------------------- */
+
+int64_t orc_matches(const int8_t *S, int64_t k, int64_t ld, int64_t i, int64_t j)
+{
+    int64_t u = 0;
+    for (int64_t c = 0; c < k; ++c) u += S[i * ld + c] == S[j * ld + c];
+    return u;
+}
+
+void orc_encode(const int8_t *S, int64_t n, int64_t k, int64_t ld, int sigma, int complement, int8_t *X)
+{
+    const int64_t L = (int64_t)sigma * k;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t c = 0; c < k; ++c)
+            for (int b = 0; b < sigma; ++b) {
+                const int bit = S[i * ld + c] == sigma - 1 - b;   /* b counts from the left */
+                X[i * L + c * sigma + b] = (int8_t)(complement ? 1 - bit : bit);
+            }
+}
+
+int64_t orc_bit_matches(const int8_t *X, const int8_t *Y, int64_t L, int64_t i, int64_t j)
+{
+    int64_t m = 0;
+    for (int64_t b = 0; b < L; ++b) m += X[i * L + b] == Y[j * L + b];
+    return m;
+}
+
+/* Best pair under "more is better" over the pairs a != b of rows of X
+ * (first set) and Y (second set) of L bits, reported unordered; or, with
+ * Y == NULL, over the pairs a < b of X. */
+static int best_bit_pair(const int8_t *X, const int8_t *Y, int64_t n, int64_t L, int64_t *oi, int64_t *oj,
+                         int64_t *om)
+{
+    int64_t bi = -1, bj = -1, bm = -1;
+#pragma omp parallel
+    {
+        int64_t ti = -1, tj = -1, tm = -1;
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t a = 0; a < n; ++a) {
+            for (int64_t b = Y ? 0 : a + 1; b < n; ++b) {
+                if (a == b) continue;
+                const int64_t m = orc_bit_matches(X, Y ? Y : X, L, a, b);
+                const int64_t i = a < b ? a : b, j = a < b ? b : a;
+                if (m > tm || (m == tm && (i < ti || (i == ti && j < tj)))) {
+                    tm = m;
+                    ti = i;
+                    tj = j;
+                }
+            }
+        }
+#pragma omp critical
+        {
+            if (tm > bm || (tm == bm && tm >= 0 && (ti < bi || (ti == bi && tj < bj)))) {
+                bm = tm;
+                bi = ti;
+                bj = tj;
+            }
+        }
+    }
+    if (bm < 0) return ORC_NOPAIR;
+    *oi = bi;
+    *oj = bj;
+    *om = bm;
+    return ORC_OK;
+}
+
+int orc_strings_pair(const int8_t *S, int64_t n, int64_t k, int64_t ld, int sigma, int mode, int64_t *oi,
+                     int64_t *oj, int64_t *omatches)
+{
+    if (n < 2) return ORC_NOPAIR;
+    if (mode == 0) {
+        int64_t bi = -1, bj = -1, bu = -1;
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = i + 1; j < n; ++j) {
+                const int64_t u = orc_matches(S, k, ld, i, j);
+                if (u > bu) {
+                    bu = u;
+                    bi = i;
+                    bj = j;
+                }
+            }
+        *oi = bi;
+        *oj = bj;
+        *omatches = bu;
+        return ORC_OK;
+    }
+    const int64_t L = (int64_t)sigma * k;
+    int8_t *A = (int8_t *)malloc((size_t)(n * L)), *Ac = (int8_t *)malloc((size_t)(n * L));
+    if (!A || !Ac) {
+        free(A);
+        free(Ac);
+        return ORC_NOMEM;
+    }
+    orc_encode(S, n, k, ld, sigma, 0, A);
+    orc_encode(S, n, k, ld, sigma, 1, Ac);
+    int64_t m = 0;
+    const int rc = best_bit_pair(A, Ac, n, L, oi, oj, &m);
+    free(A);
+    free(Ac);
+    if (rc == ORC_OK) *omatches = orc_matches(S, k, ld, *oi, *oj);
+    return rc;
+}
+
+int orc_two_locus(const int8_t *G, int64_t m1, int64_t m2, int64_t n, int64_t ld, int direction, int64_t *oi,
+                  int64_t *oj, int64_t *omatches)
+{
+    if (n < 2) return ORC_NOPAIR;
+    const int64_t m = m1 + m2, L = 3 * m;
+    /* rows of D1 and D2 are the columns of D: bits over subjects, cases first */
+    int8_t *D1 = (int8_t *)malloc((size_t)(n * L)), *D2 = (int8_t *)malloc((size_t)(n * L));
+    int8_t *col = (int8_t *)malloc((size_t)m);
+    int8_t *code = (int8_t *)malloc((size_t)L), *comp = (int8_t *)malloc((size_t)L);
+    if (!D1 || !D2 || !col || !code || !comp) {
+        free(D1);
+        free(D2);
+        free(col);
+        free(code);
+        free(comp);
+        return ORC_NOMEM;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t s = 0; s < m; ++s) col[s] = G[s * ld + i];
+        orc_encode(col, 1, m, m, 3, 0, code);
+        orc_encode(col, 1, m, m, 3, 1, comp);
+        for (int64_t b = 0; b < L; ++b) {
+            const int cases = b < 3 * m1;
+            D1[i * L + b] = code[b];
+            D2[i * L + b] = (direction == 0 ? !cases : cases) ? comp[b] : code[b];
+        }
+    }
+    const int rc = best_bit_pair(D1, D2, n, L, oi, oj, omatches);
+    free(D1);
+    free(D2);
+    free(col);
+    free(code);
+    free(comp);
+    return rc;
+}

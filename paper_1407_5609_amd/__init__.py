@@ -34,6 +34,11 @@ class _CPair(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class _CMatchPair(C.Structure):
+    _fields_ = [("i", C.c_int64), ("j", C.c_int64), ("matches", C.c_int64), ("length", C.c_int64),
+                ("status", C.c_int32), ("reserved", C.c_int32)]
+
+
 class _CStats(C.Structure):
     _fields_ = [("valid_pairs", C.c_int64), ("tiles_total", C.c_int64), ("tiles_rescreened", C.c_int64),
                 ("cpp_candidates", C.c_int64), ("frnn_candidates", C.c_int64), ("frnn_pairs", C.c_int64),
@@ -80,6 +85,8 @@ def _load():
     L.cpmi_motif.argtypes = [vp, vp, i64, i64, i64, i32, dbl, vp, C.POINTER(_CPair), vp, vp, i64, C.POINTER(i64)]
     L.cpmi_motif_batch.argtypes = [vp, C.POINTER(vp), C.POINTER(i64), C.POINTER(i64), i64, i32, vp,
                                    C.POINTER(_CPair)]
+    L.cpmi_strings_pair.argtypes = [vp, vp, i64, i64, i64, i32, i32, vp, C.POINTER(_CMatchPair)]
+    L.cpmi_two_locus.argtypes = [vp, vp, i64, i64, i64, i64, i32, vp, C.POINTER(_CMatchPair)]
     L.cpmi_autotune.argtypes = [vp, vp, i32, i64, i64, i64, i32, vp, i32, C.POINTER(_CTune)]
     L.cpmi_save_tune_cache.argtypes = [vp, C.c_char_p]
     L.cpmi_tune_lookup.argtypes = [vp, i32, i32, i64, dbl, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
@@ -106,6 +113,16 @@ class Pair:
     d: float
     screen_err: float
     screen_bound: float
+
+
+@dataclass
+class MatchPair:
+    """A string pair (cpmi_strings_pair) or SNP pair (cpmi_two_locus): i < j,
+    `matches` positions (bits of the D columns) in agreement out of `length`."""
+    i: int
+    j: int
+    matches: int
+    length: int
 
 
 @dataclass
@@ -246,6 +263,34 @@ class Context:
             return rc, pairs[:cnt.value], d2[:cnt.value]
 
     # ---- the calls of cpmi.h
+    @staticmethod
+    def _int8_matrix(x, what):
+        import torch
+        if x.device.type != "cuda" or x.dtype != torch.int8 or x.dim() != 2 or x.stride(1) != 1:
+            raise ValueError(f"{what} must be a 2-D int8 GPU tensor with unit column stride")
+        return x.shape[0], x.shape[1], max(x.stride(0), x.shape[1])
+
+    def strings_pair(self, strings, sigma: int, mode: str = "most", stream=None) -> MatchPair:
+        """Most or least correlated pair of the rows of `strings` (int8 symbols
+        in 0..sigma-1; cpmi_strings_pair)."""
+        n, k, ld = self._int8_matrix(strings, "strings")
+        m = {"most": 0, "least": 1}[mode]
+        out = _CMatchPair()
+        self._check(_lib.cpmi_strings_pair(self._h, C.c_void_p(strings.data_ptr()), n, k, ld, int(sigma), m,
+                                           _stream_ptr(stream), C.byref(out)))
+        return MatchPair(out.i, out.j, out.matches, out.length)
+
+    def two_locus(self, genotypes, m1: int, m2: int, direction: int = 0, stream=None) -> MatchPair:
+        """Two-locus association pair of the SNP columns of `genotypes`
+        ((m1 + m2) x n int8 in {0, 1, 2}, cases first; cpmi_two_locus)."""
+        rows, n, ld = self._int8_matrix(genotypes, "genotypes")
+        if rows != m1 + m2:
+            raise ValueError("genotypes must have m1 + m2 rows")
+        out = _CMatchPair()
+        self._check(_lib.cpmi_two_locus(self._h, C.c_void_p(genotypes.data_ptr()), int(m1), int(m2), n, ld,
+                                        int(direction), _stream_ptr(stream), C.byref(out)))
+        return MatchPair(out.i, out.j, out.matches, out.length)
+
     def closest_pair(self, pts, precision="auto", stream=None) -> Pair:
         dt, n, d, ld = self._points_args(pts)
         out = _CPair()

@@ -49,6 +49,8 @@ struct HostProb {
     int64_t npad = 0;
     const int32_t *perm = nullptr;  // screen row r holds source row perm[r] (reference-point order), or null
     const int32_t *iperm = nullptr; // its inverse (windows of a series: the builder writes window w to row iperm[w])
+    int64_t split = 0;              // two-set problem: first row of the second set (multiple of 256), else 0
+    int64_t na = 0;                 // two-set problem: rows of the first set (the second has n - split)
     // workspace offsets
     size_t xs_off = 0, sh_off = 0, bm_off = 0, mu_off = 0;
 };
@@ -102,6 +104,8 @@ struct cpmi_ctx {
     double prune_f = 10.0;
     uint64_t prune_seed = 0;
     DevBuf mD, mperm, miperm, mlo, mhi, mrefs, msort;
+    // string problems: encoded int8 rows and the encoder's flag word
+    DevBuf mZ, mflag;
 };
 
 namespace {
@@ -192,6 +196,17 @@ int64_t pairs_of(int64_t n, int64_t excl)
 {
     const int64_t m = n - excl;
     return m > 0 ? m * (m + 1) / 2 : 0;
+}
+
+// Admissible pairs of a problem: i < j with j - i >= excl, or for two sets
+// every (first-set row, second-set row) pair but the rows of equal index.
+int64_t pairs_of(const HostProb &h)
+{
+    if (h.split > 0) {
+        const int64_t nb = h.n - h.split;
+        return h.na * nb - std::min(h.na, nb);
+    }
+    return pairs_of(h.n, h.excl);
 }
 
 // Tuned value for (prec, kb, rb): the exact entry, else the entry of the
@@ -299,9 +314,30 @@ void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t
     for (size_t oi = 0; oi < hp.size(); ++oi) {
         const size_t p = order[oi];
         const HostProb &h = hp[p];
-        if (pairs_of(h.n, h.excl) == 0) continue;
+        if (pairs_of(h) == 0) continue;
         const bool permuted = h.motif && h.perm;
         const int64_t nT = (h.n + tile - 1) / tile;
+        if (h.split > 0) {
+            // two sets: block rows of the first set against block columns of
+            // the second, in bands of G rows (column-major in a band); a tile
+            // is partial on the ragged edges and where row i meets column
+            // split + i
+            const int64_t nA = (h.na + tile - 1) / tile, J0 = h.split / tile;
+            for (int64_t b0 = 0; b0 < nA; b0 += G)
+                for (int64_t J = J0; J < nT; ++J)
+                    for (int64_t I = b0; I < std::min(b0 + G, nA); ++I) {
+                        // rows i in [r0, r1), second-set indices j - split in [c0, c1):
+                        // no admissible pair if every pair is an equal-index one
+                        const int64_t r0 = I * tile, r1 = std::min((I + 1) * tile, h.na);
+                        const int64_t c0 = J * tile - h.split, c1 = std::min((J + 1) * tile, h.n) - h.split;
+                        const int64_t same = std::max<int64_t>(0, std::min(r1, c1) - std::max(r0, c0));
+                        if ((r1 - r0) * (c1 - c0) == same) continue;
+                        if (keep && !keep(I, J)) continue;
+                        const bool full = ((I + 1) * tile <= h.na) && ((J + 1) * tile <= h.n) && (J - J0 != I);
+                        (full ? L : part).push_back(tile_pack((uint32_t)p, (uint32_t)I, (uint32_t)J));
+                    }
+            continue;
+        }
         for (int64_t b0 = 0; b0 < nT; b0 += G) {
             int64_t jstop = nT;
             if (jend) {
@@ -382,6 +418,8 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         key.push_back(h.n);
         key.push_back(h.excl);
         key.push_back(h.kpad);
+        key.push_back(h.split);
+        key.push_back(h.na);
     }
     if (forced) {
         const std::vector<uint64_t> &tl = *forced;
@@ -454,6 +492,8 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             // the 256-row screen folds the row scalars into the matrix product
             q.form = (tile == 256 && prec != P_I8) ? SCREEN_FOLDED : SCREEN_EPILOGUE;
             q.perm = h.perm;
+            q.split = (int32_t)h.split;
+            q.na = h.na;
             if (h.motif) {
                 q.mu = (const double *)((char *)c->musg.p + h.mu_off);
                 q.sigma = (const double *)((char *)c->musg.p + mu_b + h.mu_off);
@@ -628,7 +668,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         c->stats.precision = prec;
         c->stats.tile = tile;
         int64_t vp = 0;
-        for (auto &h : hp) vp += pairs_of(h.n, h.excl);
+        for (auto &h : hp) vp += pairs_of(h);
         c->stats.valid_pairs = vp;
         c->stats.screen_pairs = tile == 256 ? c->nfull_pairs : vp;
         float mr = 0.f;
@@ -873,6 +913,42 @@ int pruned_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bo
     return CPMI_OK;
 }
 
+// String problems (Sections 5 and 6): zeroed workspace for `rows` encoded
+// rows of Lz int8 values, filled by `encode` (which may raise F_SYMBOL in the
+// flag word), then one exact int8 closest-pair search over them. On success
+// *r holds the search result (screen rows a < b and the exact squared
+// distance). Synchronises.
+int encoded_search(cpmi_ctx *c, HostProb &h, int64_t rows, int64_t Lz, int tile, hipStream_t st,
+                   const std::function<void(signed char *, unsigned int *)> &encode, ResDev *r)
+{
+    int rc;
+    const size_t zb = ((size_t)rows * Lz + 3) / 4 * 4;
+    if ((rc = ensure(c, c->mZ, zb))) return rc;
+    if ((rc = ensure(c, c->mflag, 4))) return rc;
+    launch_fill_u32((uint32_t *)c->mZ.p, 0u, (int64_t)(zb / 4), st);
+    launch_fill_u32((uint32_t *)c->mflag.p, 0u, 1, st);
+    encode((signed char *)c->mZ.p, (unsigned int *)c->mflag.p);
+    HIPCHK(c, hipGetLastError());
+    unsigned int flag = 0;
+    HIPCHK(c, hipMemcpyAsync(&flag, c->mflag.p, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (flag & F_SYMBOL) return fail(c, CPMI_ERR_ARG, "a symbol lies outside the alphabet");
+    h.n = rows;
+    h.d = Lz;
+    h.ld = Lz;
+    h.excl = 1;
+    h.src = c->mZ.p;
+    h.src_i8 = 1;
+    h.r2 = -1.0;
+    std::vector<HostProb> hp(1, h);
+    RunOut ro;
+    if ((rc = run_search(c, hp, P_I8, tile, true, false, st, false, ro))) return rc;
+    if ((rc = flags_error(c, ro.res[0].flags))) return rc;
+    if (ro.res[0].best_d2 == ~0ull || ro.res[0].best_ij == ~0ull) return fail(c, CPMI_ERR_NOPAIR, "no admissible pair");
+    *r = ro.res[0];
+    return CPMI_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -914,7 +990,8 @@ int cpmi_destroy(cpmi_ctx *c)
     if (c->gexec) hipGraphExecDestroy(c->gexec);
     DevBuf *bufs[] = {&c->xs,      &c->shat,  &c->bmax, &c->musg, &c->probs, &c->jobs, &c->tiles, &c->tile_min,
                       &c->sel,     &c->candR, &c->candU, &c->cand_d2, &c->keys, &c->vals, &c->cnt, &c->ubits,
-                      &c->res,     &c->mD,    &c->mperm, &c->miperm, &c->mlo, &c->mhi, &c->mrefs, &c->msort};
+                      &c->res,     &c->mD,    &c->mperm, &c->miperm, &c->mlo, &c->mhi, &c->mrefs, &c->msort,
+                      &c->mZ,      &c->mflag};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
     if (c->pinned) hipHostFree(c->pinned);
@@ -1150,6 +1227,106 @@ int cpmi_motif_batch(cpmi_ctx *c, const float *const *series, const int64_t *len
     return CPMI_OK;
 }
 
+int cpmi_strings_pair(cpmi_ctx *c, const int8_t *strings, int64_t n, int64_t k, int64_t ld, int sigma, int mode,
+                      void *stream, cpmi_match_pair *out)
+{
+    if (!c) return CPMI_ERR_ARG;
+    c->err.clear();
+    c->stats = cpmi_stats{};
+    if (!out) return fail(c, CPMI_ERR_ARG, "out is NULL");
+    memset(out, 0, sizeof *out);
+    out->i = out->j = -1;
+    if (!strings) return fail(c, CPMI_ERR_ARG, "strings pointer is NULL");
+    if (mode != CPMI_MOST_CORRELATED && mode != CPMI_LEAST_CORRELATED) return fail(c, CPMI_ERR_ARG, "unknown mode %d", mode);
+    if (sigma < 2 || sigma > 64) return fail(c, CPMI_ERR_ARG, "sigma must be in 2..64");
+    if (k < 1 || ld < k || n < 0) return fail(c, CPMI_ERR_ARG, "bad shape n=%lld k=%lld ld=%lld", (long long)n, (long long)k, (long long)ld);
+    if ((int64_t)sigma * k > (1 << 20)) return fail(c, CPMI_ERR_ARG, "sigma * k must be <= 2^20");
+    if (n >= (1ll << 30)) return fail(c, CPMI_ERR_ARG, "n must be below 2^30");
+    if (n < 2) {
+        out->status = CPMI_ERR_NOPAIR;
+        return fail(c, CPMI_ERR_NOPAIR, "fewer than two strings");
+    }
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t Lz = (int64_t)sigma * k;
+    const bool least = mode == CPMI_LEAST_CORRELATED;
+    HostProb h;
+    int64_t rows = n;
+    int tile;
+    if (least) {
+        // codes in rows [0, n), complements from the next multiple of 256
+        h.split = (n + 255) / 256 * 256;
+        h.na = n;
+        rows = h.split + n;
+        tile = 256;
+    } else {
+        tile = pick_tile(c, P_I8, Lz, (double)pairs_of(n, 1));
+    }
+    ResDev r;
+    if ((rc = encoded_search(c, h, rows, Lz, tile, st,
+                             [&](signed char *Z, unsigned int *flag) {
+                                 launch_encode_strings((const signed char *)strings, n, k, ld, sigma, least ? 1 : 0, Z,
+                                                       Lz, h.split, flag, st);
+                             },
+                             &r)))
+        return rc;
+    const int64_t a = (int64_t)(r.best_ij >> 32), b = (int64_t)(r.best_ij & 0xffffffffu);
+    const int64_t d2 = (int64_t)__builtin_bit_cast(double, (uint64_t)r.best_d2);
+    out->i = a;
+    out->j = least ? b - h.split : b;
+    // code vs code: d2 = 2 (k - u); code vs complement: d2 = sigma k - 2 (k - u)
+    out->matches = least ? k - (Lz - d2) / 2 : k - d2 / 2;
+    out->length = k;
+    out->status = CPMI_OK;
+    c->stats.valid_pairs = pairs_of(n, 1);
+    return CPMI_OK;
+}
+
+int cpmi_two_locus(cpmi_ctx *c, const int8_t *genotypes, int64_t m1, int64_t m2, int64_t n, int64_t ld,
+                   int direction, void *stream, cpmi_match_pair *out)
+{
+    if (!c) return CPMI_ERR_ARG;
+    c->err.clear();
+    c->stats = cpmi_stats{};
+    if (!out) return fail(c, CPMI_ERR_ARG, "out is NULL");
+    memset(out, 0, sizeof *out);
+    out->i = out->j = -1;
+    if (!genotypes) return fail(c, CPMI_ERR_ARG, "genotypes pointer is NULL");
+    if (direction != 0 && direction != 1) return fail(c, CPMI_ERR_ARG, "direction must be 0 or 1");
+    if (m1 < 1 || m2 < 1 || n < 0 || ld < n) return fail(c, CPMI_ERR_ARG, "bad shape m1=%lld m2=%lld n=%lld ld=%lld", (long long)m1, (long long)m2, (long long)n, (long long)ld);
+    if (3 * (m1 + m2) > (1 << 20)) return fail(c, CPMI_ERR_ARG, "3 (m1 + m2) must be <= 2^20");
+    if (n >= (1ll << 30)) return fail(c, CPMI_ERR_ARG, "n must be below 2^30");
+    if (n < 2) {
+        out->status = CPMI_ERR_NOPAIR;
+        return fail(c, CPMI_ERR_NOPAIR, "fewer than two SNPs");
+    }
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t Lz = 3 * (m1 + m2);
+    HostProb h;
+    h.split = (n + 255) / 256 * 256;
+    h.na = n;
+    ResDev r;
+    if ((rc = encoded_search(c, h, h.split + n, Lz, 256, st,
+                             [&](signed char *Z, unsigned int *flag) {
+                                 launch_encode_two_locus((const signed char *)genotypes, m1, m2, n, ld, direction, Z,
+                                                         Lz, h.split, flag, st);
+                             },
+                             &r)))
+        return rc;
+    const int64_t a = (int64_t)(r.best_ij >> 32), b = (int64_t)(r.best_ij & 0xffffffffu);
+    const int64_t d2 = (int64_t)__builtin_bit_cast(double, (uint64_t)r.best_d2);
+    out->i = a;
+    out->j = b - h.split;
+    out->matches = Lz - d2;   // 0/1 rows: squared distance = mismatching bits
+    out->length = Lz;
+    out->status = CPMI_OK;
+    c->stats.valid_pairs = pairs_of(n, 1);
+    return CPMI_OK;
+}
+
 int cpmi_autotune(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, int precision,
                   void *stream, int reps, cpmi_tune_result *out)
 {
@@ -1248,6 +1425,22 @@ int64_t cpmi_dbg_tile_list(int64_t n, int64_t excl, int tile, uint64_t *out, int
     int64_t nf = 0;
     build_tiles(hp, tile, tl, &nf);
     for (int64_t k = 0; k < (int64_t)tl.size() && k < cap; ++k) out[k] = tl[k];
+    return (int64_t)tl.size();
+}
+
+int64_t cpmi_dbg_tile_list_two(int64_t na, int64_t nb, int64_t split, int tile, uint64_t *out, int64_t cap,
+                               int64_t *nfull)
+{
+    if (na < 0 || nb < 0 || split < na || split % 256 || (tile != 128 && tile != 256)) return CPMI_ERR_ARG;
+    std::vector<HostProb> hp(1);
+    hp[0].n = split + nb;
+    hp[0].split = split;
+    hp[0].na = na;
+    std::vector<uint64_t> tl;
+    int64_t nf = 0;
+    build_tiles(hp, tile, tl, &nf);
+    for (int64_t k = 0; k < (int64_t)tl.size() && k < cap; ++k) out[k] = tl[k];
+    if (nfull) *nfull = nf;
     return (int64_t)tl.size();
 }
 

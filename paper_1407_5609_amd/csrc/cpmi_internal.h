@@ -16,7 +16,7 @@ enum Mode : int {
 };
 
 // One flag word per problem; set by the builders, read back by the host.
-enum Flag : uint32_t { F_NONFINITE = 1u, F_DEGENERATE = 2u, F_RANGE = 4u };
+enum Flag : uint32_t { F_NONFINITE = 1u, F_DEGENERATE = 2u, F_RANGE = 4u, F_SYMBOL = 8u };
 
 // A pair emitted by the screen: rows (i, j) of problem p and its screen value.
 struct Cand {
@@ -42,8 +42,11 @@ struct Prob {
     int32_t src_i8;        // 1 if src holds int8 points
     double r2;             // squared radius (negative: no radius search)
     int32_t form;          // screen value form of the screen used (SCREEN_EPILOGUE / SCREEN_FOLDED)
-    int32_t pad_;
+    int32_t split;         // two-set problem (int8, 256-row screen): first row of the second set, a
+                           // multiple of 256; a pair (i < j) is admissible iff i < na, j >= split,
+                           // j < n and j - split != i. 0 for a single set.
     const int32_t *perm;   // screen row r holds source row perm[r] (reference-point order), or null
+    int64_t na;            // two-set problem: rows of the first set
 };
 
 // Source row of screen row r.
@@ -159,6 +162,12 @@ hipError_t sort_ref_order(void *temp, size_t *temp_bytes, const double *D0, doub
 // rz: q * ell doubles of scratch (the projected, z-normalised references).
 void launch_ref_dist_windows(const float *T, int64_t N, int64_t ell, const int32_t *refs, int q, double f,
                              double *rz, double *D, hipStream_t st);
+// Encoders of the string problems (encode.hip). Z: rows of Lz int8 values,
+// zeroed by the caller; flags: F_SYMBOL for a symbol outside the alphabet.
+void launch_encode_strings(const signed char *S, int64_t n, int64_t k, int64_t ld, int sigma, int complement,
+                           signed char *Z, int64_t Lz, int64_t split, unsigned int *flags, hipStream_t st);
+void launch_encode_two_locus(const signed char *G, int64_t m1, int64_t m2, int64_t n, int64_t ld, int direction,
+                             signed char *Z, int64_t Lz, int64_t split, unsigned int *flags, hipStream_t st);
 void launch_perm_finish(int32_t *perm, int32_t *iperm, int64_t n, int64_t npad, hipStream_t st);
 void launch_block_range(const double *D, int64_t n, int q, const int32_t *perm, int tile, int64_t nblk, double *lo,
                         double *hi, hipStream_t st);

@@ -505,7 +505,10 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         // windows in reference order: admissibility compares source positions
         // (only masked tiles carry such problems; motifs are never int8)
         const bool pexcl = MASKED && FOLD && P.perm && P.motif;
-        const bool full = !MASKED || (!pexcl && ((int64_t)J * T256 - ((int64_t)I * T256 + T256 - 1) >= P.excl) &&
+        // two sets of int8 rows: pairs across the sets (masked tiles test every pair)
+        const bool twoset = MASKED && !FOLD && P.split > 0;
+        const bool full = !MASKED || (!pexcl && !twoset &&
+                                      ((int64_t)J * T256 - ((int64_t)I * T256 + T256 - 1) >= P.excl) &&
                                       ((int64_t)I * T256 + T256 <= P.n) && ((int64_t)J * T256 + T256 <= P.n));
         // source positions of this lane's 4 columns and, per block a, 16 rows
         int32_t oj[MB256] = {0, 0, 0, 0};
@@ -539,6 +542,9 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
             return ((uint32_t)oa + (uint32_t)(excl - 1) - (uint32_t)ob) >= pspan;
         };
         auto adm_pos = [&](int32_t gi, int32_t gj) { return (gj - gi >= excl) & (gj < n); };
+        // two sets (the host lists only tiles with J >= split / 256, so gj >= split)
+        const int32_t na = (int32_t)P.na, split = P.split;
+        auto adm_two = [&](int32_t gi, int32_t gj) { return (gi < na) & (gj < n) & (gj - split != gi); };
         auto adm_ref = [&](int32_t gi, int32_t gj, int32_t oa, int32_t ob) {
             return far_apart(oa, ob) & (gj > gi) & (gj < n);
         };
@@ -652,22 +658,27 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                 }
                 best = -2.0f * mx;
             } else {
+                // (one loop per admissibility rule: the rule is uniform per tile)
+                auto masked_min = [&](auto adm) {
 #pragma unroll
-                for (int a = 0; a < MB256; ++a) {
-                    S si[16];
-                    load_si(a, si);
+                    for (int a = 0; a < MB256; ++a) {
+                        S si[16];
+                        load_si(a, si);
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
+                        for (int r = 0; r < 16; ++r) {
+                            const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
 #pragma unroll
-                        for (int b = 0; b < MB256; ++b) {
-                            const int32_t gj = j0 + b * 32 + lrow;
-                            const S dv = (S)(si[r] + part(acc[a][b][r], sj[b]));
-                            best = adm_pos(gi, gj) ? smin(best, dv) : best;
+                            for (int b = 0; b < MB256; ++b) {
+                                const int32_t gj = j0 + b * 32 + lrow;
+                                const S dv = (S)(si[r] + part(acc[a][b][r], sj[b]));
+                                best = adm(gi, gj) ? smin(best, dv) : best;
+                            }
                         }
+                        __builtin_amdgcn_sched_barrier(0);
                     }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
+                };
+                if (twoset) masked_min(adm_two);
+                else masked_min(adm_pos);
             }
         }
 
@@ -701,7 +712,9 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                             S dv;
                             if constexpr (FOLD) dv = -2.0f * acc[a][b][r];
                             else dv = (S)(si + part(acc[a][b][r], sj[b]));
-                            const bool ok = full | (pexcl ? adm_ref(gi, gj, oi[r], oj[b]) : adm_pos(gi, gj));
+                            const bool ok = full | (pexcl    ? adm_ref(gi, gj, oi[r], oj[b])
+                                                    : twoset ? adm_two(gi, gj)
+                                                             : adm_pos(gi, gj));
                             if (ok & (dv <= thr)) {
                                 Cand cd;
                                 cd.i = gi;
@@ -731,6 +744,12 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                 S m = smin(smin(sh_red[0], sh_red[1]), smin(sh_red[2], sh_red[3]));
                 args.tile_min[t] = __builtin_bit_cast(uint32_t, m);
             }
+        } else {
+            // The emission reads this tile's row scalars and positions from
+            // LDS at uneven times across the waves; the next tile's top
+            // prefetches the tile after it into this same half. No wave may
+            // start it before every wave is done here.
+            __builtin_amdgcn_s_barrier();
         }
         t = tn;
     }

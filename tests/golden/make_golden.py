@@ -5,7 +5,7 @@ Every value stored under tests/golden/ by this script comes from ``oracle``
 here touches the GPU library. Floats are stored with ``float.hex`` so that the
 comparison in the tests is exact.
 
-Usage:  python tests/golden/make_golden.py [points|motif|walk|snp|mixture|batch ...]
+Usage:  python tests/golden/make_golden.py [points|motif|walk|strings|two_locus|snp|mixture|batch ...]
         (no argument: all). Threads: ORACLE_THREADS (default: all cores).
 
 Run times on 8 cores (latency-bound scalar FP64): points < 1 s, motif ~4 min,
@@ -78,6 +78,32 @@ def walk():
         "ell": c["ell"], "excl": c["excl"], "plant": list(c["plant"]), "R2": _hex(c["R2"]),
         "closest_pair": {"i": best[0], "j": best[1], "d2": _hex(best[2])},
         "frnn": _frnn_obj(pairs, dd), "oracle_seconds": time.time() - t})
+
+
+def strings():
+    c = W.cfg_strings()
+    t = time.time()
+    most = oracle.strings_pair(c["S"], c["sigma"], "most")
+    least = oracle.strings_pair(c["S"], c["sigma"], "least")
+    _write(c["name"], {
+        "workload": c["name"], "source": "oracle.strings_pair on workloads.cfg_strings",
+        "sigma": c["sigma"], "near": list(c["near"]), "far": list(c["far"]),
+        "most": {"i": most[0], "j": most[1], "matches": most[2]},
+        "least": {"i": least[0], "j": least[1], "matches": least[2]},
+        "oracle_seconds": time.time() - t})
+
+
+def two_locus():
+    c = W.cfg_two_locus()
+    t = time.time()
+    out = {}
+    for direction in (0, 1):
+        i, j, m = oracle.two_locus(c["G"], c["m1"], c["m2"], direction)
+        out[str(direction)] = {"i": i, "j": j, "matches": m}
+    _write(c["name"], {
+        "workload": c["name"], "source": "oracle.two_locus on workloads.cfg_two_locus",
+        "m1": c["m1"], "m2": c["m2"], "pair": list(c["pair"]), "direction": out,
+        "oracle_seconds": time.time() - t})
 
 
 def snp():
@@ -157,7 +183,8 @@ def batch():
         "sample": out, "oracle_seconds": time.time() - t})
 
 
-JOBS = {"points": points, "motif": motif, "walk": walk, "snp": snp, "mixture": mixture, "batch": batch}
+JOBS = {"points": points, "motif": motif, "walk": walk, "strings": strings, "two_locus": two_locus, "snp": snp,
+        "mixture": mixture, "batch": batch}
 
 if __name__ == "__main__":
     if os.environ.get("ORACLE_THREADS"):

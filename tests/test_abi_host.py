@@ -95,6 +95,42 @@ def test_tile_list_covers_each_admissible_pair_once(lib, n, excl, tile):
     assert first_partial % 8 == 0
 
 
+@pytest.mark.parametrize("na,nb,tile", [(2, 2, 256), (300, 300, 256), (1000, 1000, 256), (513, 513, 128),
+                                        (700, 400, 256), (256, 256, 256)])
+def test_two_set_tile_list_covers_each_cross_pair_once(lib, na, nb, tile):
+    """The string searches pair every first-set row with every second-set row
+    except the one of equal index; each such pair lies in exactly one listed
+    tile, and the leading (full) tiles hold no inadmissible pair."""
+    split = (na + 255) // 256 * 256
+    nf = C.c_int64(0)
+    lib.cpmi_dbg_tile_list_two.restype = C.c_int64
+    lib.cpmi_dbg_tile_list_two.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int, C.c_void_p, C.c_int64,
+                                           C.POINTER(C.c_int64)]
+    cnt = lib.cpmi_dbg_tile_list_two(na, nb, split, tile, None, 0, None)
+    raw = np.zeros(max(cnt, 1), dtype=np.uint64)
+    assert lib.cpmi_dbg_tile_list_two(na, nb, split, tile, raw.ctypes.data, cnt, C.byref(nf)) == cnt
+    raw = raw[:cnt]
+    NONE = np.uint64(0xFFFFFFFFFFFFFFFF)
+    n = split + nb
+    seen = np.zeros((na, nb), dtype=np.int64)
+    for k, e in enumerate(raw):
+        if e == NONE:
+            continue
+        a, b = int((e >> np.uint64(22)) & np.uint64(0x3FFFFF)), int(e & np.uint64(0x3FFFFF))
+        i = np.arange(a * tile, a * tile + tile)
+        j = np.arange(b * tile, b * tile + tile)
+        ok = (i[:, None] < na) & (j[None, :] >= split) & (j[None, :] < n) & (j[None, :] - split != i[:, None])
+        assert ok.any()                                     # no empty tile
+        if k < nf.value:
+            assert ok.all()                                 # full tiles hold only admissible pairs
+        ii, jj = np.nonzero(ok)
+        np.add.at(seen, (i[ii], j[jj] - split), 1)
+    want = np.ones((na, nb), dtype=np.int64)
+    want[np.arange(min(na, nb)), np.arange(min(na, nb))] = 0
+    assert np.array_equal(seen, want)
+    assert lib.cpmi_dbg_tile_list_two(10, 10, 100, tile, None, 0, None) == -1   # split not a multiple of 256
+
+
 def test_tile_list_rejects_bad_arguments(lib):
     assert lib.cpmi_dbg_tile_list(10, 0, 128, None, 0) == -1
     assert lib.cpmi_dbg_tile_list(10, 1, 64, None, 0) == -1

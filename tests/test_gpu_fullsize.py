@@ -122,6 +122,50 @@ def test_motif_full_size_golden_with_pruning(ctx, torch_dev):
         ctx.set_pruning(0)
 
 
+@pytest.mark.parametrize("q", [0, 10])
+def test_walk_full_size_golden(ctx, torch_dev, q):
+    """Random walk of 100,000 samples, windows of 1,024 (the shape the paper
+    measures reference-point pruning on), unpruned and with q = 10 references
+    projected by f = 10: motif and radius pairs equal the oracle's."""
+    g = _golden("walk_L100000_l1024.json")
+    want_pair, want_pairs, want_d2 = _want(g)
+    c = W.cfg_walk()
+    t = _dev(c["T"], torch_dev)
+    ctx.set_pruning(q, 10.0, seed=1)
+    try:
+        best, (p, d) = ctx.motif(t, c["ell"], excl=c["excl"], R2=float.fromhex(g["R2"]), precision="bf16")
+        st = ctx.stats()
+        only, _ = ctx.motif(t, c["ell"], excl=c["excl"], precision="bf16")
+    finally:
+        ctx.set_pruning(0)
+    assert (best.i, best.j, best.d2) == want_pair
+    assert (only.i, only.j, only.d2) == want_pair
+    assert np.array_equal(p.cpu().numpy(), want_pairs)
+    assert np.array_equal(d.cpu().numpy(), want_d2)
+    assert st.max_err_over_bound <= 1.0
+    assert (st.tiles_pruned > 0) == (q > 0)
+
+
+def test_strings_full_size_golden(ctx, torch_dev):
+    g = _golden("strings_n20000_k64_s4.json")
+    c = W.cfg_strings()
+    t = _dev(c["S"], torch_dev)
+    for mode in ("most", "least"):
+        r = ctx.strings_pair(t, c["sigma"], mode)
+        assert (r.i, r.j, r.matches) == (g[mode]["i"], g[mode]["j"], g[mode]["matches"]), mode
+
+
+def test_two_locus_full_size_golden(ctx, torch_dev):
+    g = _golden("two_locus_n50000_m200+200.json")
+    c = W.cfg_two_locus()
+    t = _dev(c["G"], torch_dev)
+    for direction in (0, 1):
+        r = ctx.two_locus(t, c["m1"], c["m2"], direction)
+        w = g["direction"][str(direction)]
+        assert (r.i, r.j, r.matches) == (w["i"], w["j"], w["matches"]), direction
+    assert tuple(c["pair"]) == (g["direction"]["0"]["i"], g["direction"]["0"]["j"])
+
+
 def _window_d2(T, ell, i, j):
     """Canonical squared distance of windows i and j, each z-normalised on its own."""
     a, _, _ = oracle.znorm(T[i:i + ell], ell)

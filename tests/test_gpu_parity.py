@@ -449,6 +449,29 @@ def test_pruned_motif_matches_oracle(ctx, torch_dev, prec, q, length, ell, excl)
     assert st.valid_pairs == W.valid_pairs_motif(length, ell, excl if excl > 0 else ell)
 
 
+@pytest.mark.parametrize("prec", ["bf16", "f32"])
+def test_pruned_motif_many_selected_tiles(ctx, torch_dev, prec):
+    """Short windows and a wide radius: the second screen pass gets several
+    selected tiles per work-group, so a work-group emits one tile while its
+    waves have already prefetched the positions of the next ones; the
+    radius pairs must still respect the exclusion zone and equal the
+    oracle's."""
+    rng = np.random.default_rng(32)
+    T = W.random_walk(rng, 20000)
+    ell, R2 = 32, 3.0
+    ctx.set_pruning(4, 10.0, seed=3)
+    try:
+        best, fr = ctx.motif(_dev(T, torch_dev), ell, R2=R2, precision=prec)
+        st = ctx.stats()
+    finally:
+        ctx.set_pruning(0)
+    ob, ofr = oracle.motif(T, ell, R2=R2)
+    _check_pair(best, ob)
+    _check_frnn(fr, ofr)
+    print("selected tiles", st.tiles_rescreened, "radius pairs", len(ofr[0]))
+    assert st.tiles_rescreened > 300   # more than the 256 work-groups of the pass
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_pruned_motif_exclusion_boundary_and_ties(ctx, torch_dev, prec):
     """A periodic series: windows one period apart are identical, so the

@@ -374,3 +374,139 @@ def test_no_admissible_pair():
     assert best[:2] == (0, 20)
     best, _ = oracle.motif(T, 21)       # 20 windows, exclusion 21: none
     assert best is None
+
+
+# ---------------------------------------------------------------------------
+# strings and correlation by matches (Sections 5 and 6)
+# ---------------------------------------------------------------------------
+
+def test_matches_worked_example():
+    """Section 5's example: x = 10010 and y = 00111 agree in 2 positions."""
+    S = np.array([[1, 0, 0, 1, 0], [0, 0, 1, 1, 1]], dtype=np.int8)
+    assert oracle.matches(S, 0, 1) == 2
+
+
+def test_mapping_codes_and_their_matches():
+    """Section 5's alphabet {001, 010, 100}: 0 -> 001, 1 -> 010, 2 -> 100; two
+    codes agree in 3 bits if equal and 1 otherwise; a code and a complement
+    agree in 0 bits if the symbols are equal and 2 otherwise."""
+    S = np.array([[0], [1], [2]], dtype=np.int8)
+    A = oracle.encode(S, 3)
+    assert A.tolist() == [[0, 0, 1], [0, 1, 0], [1, 0, 0]]
+    Ac = oracle.encode(S, 3, complement=True)
+    assert np.array_equal(Ac, 1 - A)
+    for x in range(3):
+        for y in range(3):
+            assert oracle.bit_matches(A, A, x, y) == (3 if x == y else 1)
+            assert oracle.bit_matches(A, Ac, x, y) == (0 if x == y else 2)
+
+
+@pytest.mark.parametrize("sigma", [2, 3, 4, 7])
+def test_mapping_identities(sigma):
+    """M(A'_i, A'_j) = k + 2 u_ij and M(A'_i, ~A'_j) = 2 (k - u_ij) for the
+    three-letter mapping (Section 5); for sigma letters the first becomes
+    (sigma - 2) k + 2 u_ij (equal symbols agree in sigma bits, different ones
+    in sigma - 2) and the second is unchanged."""
+    rng = np.random.default_rng(sigma)
+    S = W.random_strings(rng, 30, 25, sigma)
+    k = S.shape[1]
+    A, Ac = oracle.encode(S, sigma), oracle.encode(S, sigma, complement=True)
+    for i in range(30):
+        for j in range(30):
+            u = int((S[i] == S[j]).sum())
+            assert oracle.matches(S, i, j) == u
+            assert oracle.bit_matches(A, A, i, j) == (sigma - 2) * k + 2 * u
+            assert oracle.bit_matches(A, Ac, i, j) == 2 * (k - u)
+
+
+def test_transformed_correlations():
+    """Section 5's run-time analysis: with p = u / k, the mapped correlation of
+    two codes is 1/3 + 2p/3 and of a code and a complement (2/3)(1 - p)."""
+    from fractions import Fraction as F
+    rng = np.random.default_rng(3)
+    S = W.random_strings(rng, 20, 33, 3)
+    k = S.shape[1]
+    A, Ac = oracle.encode(S, 3), oracle.encode(S, 3, complement=True)
+    for i in range(20):
+        for j in range(20):
+            p = F(oracle.matches(S, i, j), k)
+            assert F(oracle.bit_matches(A, A, i, j), 3 * k) == F(1, 3) + F(2, 3) * p
+            assert F(oracle.bit_matches(A, Ac, i, j), 3 * k) == F(2, 3) * (1 - p)
+
+
+def _brute_pair(S, better):
+    """Lexicographically first pair i < j whose u = m(S_i, S_j) is best."""
+    n = S.shape[0]
+    best = None
+    for i in range(n):
+        for j in range(i + 1, n):
+            u = int((S[i] == S[j]).sum())
+            if best is None or better(u, best[2]):
+                best = (i, j, u)
+    return best
+
+
+@pytest.mark.parametrize("sigma,n,k", [(2, 40, 16), (3, 50, 12), (4, 35, 9), (3, 2, 5)])
+def test_strings_pair_against_brute_force(sigma, n, k):
+    """The most correlated pair equals the plain argmax of u (and the closest
+    pair of the one-hot rows, whose squared distance is 2 (k - u)); the least
+    correlated pair found through codes and complements equals the plain
+    argmin of u, ties to the first pair."""
+    rng = np.random.default_rng(n + k)
+    S = W.random_strings(rng, n, k, sigma)
+    if n > 3:
+        S[n // 2] = S[1]                 # a duplicate: a tie candidate for the most
+        W.plant_string_pair(rng, S, sigma, 0)
+    most = oracle.strings_pair(S, sigma, "most")
+    assert most == _brute_pair(S, lambda u, b: u > b)
+    ci, cj, cd2 = oracle.closest_pair(oracle.encode(S, sigma))
+    assert (ci, cj) == most[:2] and cd2 == 2 * (k - most[2])
+    assert oracle.strings_pair(S, sigma, "least") == _brute_pair(S, lambda u, b: u < b)
+
+
+def _brute_two_locus(G, m1, direction):
+    """Lexicographically first SNP pair i < j maximising u_A - u_B (direction
+    0) or u_B - u_A, with u the subjects in which the two SNPs agree."""
+    n = G.shape[1]
+    best = None
+    for i in range(n):
+        for j in range(i + 1, n):
+            same = G[:, i] == G[:, j]
+            uA, uB = int(same[:m1].sum()), int(same[m1:].sum())
+            v = uA - uB if direction == 0 else uB - uA
+            if best is None or v > best[2]:
+                best = (i, j, v)
+    return best
+
+
+@pytest.mark.parametrize("m1,m2,n,direction", [(20, 20, 40, 0), (20, 20, 40, 1), (13, 25, 30, 0), (9, 4, 2, 1)])
+def test_two_locus_against_brute_force(m1, m2, n, direction):
+    """Section 6: the columns (i, n + j) of D agree in m1 + 2 u_A + 2 (m2 - u_B)
+    bits (direction 0), so the pair with the most agreeing bits is the pair
+    maximising u_A - u_B."""
+    rng = np.random.default_rng(m1 * 100 + n + direction)
+    G = rng.integers(0, 3, (m1 + m2, n), dtype=np.int8)
+    i, j, m = oracle.two_locus(G, m1, m2, direction)
+    bi, bj, v = _brute_two_locus(G, m1, direction)
+    assert (i, j) == (bi, bj)
+    assert m == m1 + 2 * m2 + 2 * v if direction == 0 else m == m2 + 2 * m1 + 2 * v
+
+
+def test_two_locus_correlation_identity():
+    """Section 6: with as many cases as controls, the correlation of columns i
+    and n + j of D is 1/2 + (p - q)/3, p and q the fractions of cases and of
+    controls in which SNPs i and j agree."""
+    from fractions import Fraction as F
+    rng = np.random.default_rng(504)
+    m = 30
+    G = rng.integers(0, 3, (2 * m, 12), dtype=np.int8)
+    A = oracle.encode(np.ascontiguousarray(G[:m].T), 3)
+    B = oracle.encode(np.ascontiguousarray(G[m:].T), 3)
+    Bc = oracle.encode(np.ascontiguousarray(G[m:].T), 3, complement=True)
+    D1 = np.concatenate([A, B], axis=1)
+    D2 = np.concatenate([A, Bc], axis=1)
+    for i in range(12):
+        for j in range(12):
+            same = G[:, i] == G[:, j]
+            p, q = F(int(same[:m].sum()), m), F(int(same[m:].sum()), m)
+            assert F(oracle.bit_matches(D1, D2, i, j), 6 * m) == F(1, 2) + (p - q) / 3

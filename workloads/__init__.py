@@ -20,6 +20,12 @@ from .synth import (  # noqa: F401
     cfg_points_small,
     cfg_motif,
     cfg_walk,
+    cfg_strings,
+    cfg_two_locus,
+    random_strings,
+    plant_string_pair,
+    noise_genotypes,
+    inject_two_locus_pair,
     cfg_mixture,
     cfg_batch,
     cfg_snp,

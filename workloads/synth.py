@@ -148,6 +148,68 @@ def batch_series(rng: np.random.Generator, count: int, lmin: int, lmax: int,
 # the five workloads
 # ----------------------------------------------------------------------------
 
+def random_strings(rng: np.random.Generator, n: int, k: int, sigma: int) -> np.ndarray:
+    """n strings of length k, symbols uniform in 0..sigma-1 (int8 rows)."""
+    return rng.integers(0, sigma, (n, k), dtype=np.int8)
+
+
+def plant_string_pair(rng: np.random.Generator, S: np.ndarray, sigma: int, agree: int):
+    """Overwrite string b with string a changed so that they agree in exactly
+    `agree` positions (the others get a different symbol). Returns (a, b),
+    a < b."""
+    n, k = S.shape
+    a, b = sorted(rng.choice(n, 2, replace=False).tolist())
+    keep = np.zeros(k, dtype=bool)
+    keep[rng.choice(k, agree, replace=False)] = True
+    shift = rng.integers(1, sigma, k)   # a non-zero shift changes the symbol
+    S[b] = np.where(keep, S[a], (S[a].astype(np.int64) + shift) % sigma).astype(np.int8)
+    return a, b
+
+
+def noise_genotypes(rng: np.random.Generator, m1: int, m2: int, n: int) -> np.ndarray:
+    """The NOISE data of the two-locus experiments (Section 6): (m1 + m2)
+    subjects x n SNPs, each value 0 or 1 with equal probability (int8)."""
+    return rng.integers(0, 2, (m1 + m2, n), dtype=np.int8)
+
+
+def inject_two_locus_pair(rng: np.random.Generator, G: np.ndarray, m1: int, agree_cases: int,
+                          agree_controls: int, levels: int = 2):
+    """Inject a SNP pair (a, b): SNP b copies SNP a in `agree_cases` random
+    cases and `agree_controls` random controls and differs in the other
+    subjects (value x -> (x + 1) mod levels: 0 <-> 1 for the binary NOISE
+    data). Returns (a, b), a < b."""
+    m, n = G.shape
+    a, b = sorted(rng.choice(n, 2, replace=False).tolist())
+    same = np.zeros(m, dtype=bool)
+    same[rng.choice(m1, agree_cases, replace=False)] = True
+    same[m1 + rng.choice(m - m1, agree_controls, replace=False)] = True
+    G[:, b] = np.where(same, G[:, a], (G[:, a].astype(np.int64) + 1) % levels).astype(np.int8)
+    return a, b
+
+
+def cfg_strings(n: int = 20000, k: int = 64, sigma: int = 4):
+    """Strings over a 4-letter alphabet (the discretised series of Section 4
+    use {1, 2, 3, 4}; here 0..3): n = 20,000 uniform random strings of length
+    64, one planted near-duplicate pair (agreeing in 60 of 64 positions) and
+    one planted opposite pair (agreeing in none)."""
+    rng = config_rng(6)
+    S = random_strings(rng, n, k, sigma)
+    near = plant_string_pair(rng, S, sigma, k - 4)
+    far = plant_string_pair(rng, S, sigma, 0)
+    return {"name": f"strings_n{n}_k{k}_s{sigma}", "S": S, "sigma": sigma, "near": near, "far": far}
+
+
+def cfg_two_locus(n: int = 50000, m1: int = 200, m2: int = 200):
+    """Two-locus NOISE data (Section 6): 200 cases and 200 controls, n =
+    50,000 SNPs, one injected pair whose columns (a, n + b) of D have
+    correlation 0.6 (1/2 + (p - q)/3 with p = 0.8 among cases, q = 0.5 among
+    controls), as in the paper's injection runs."""
+    rng = config_rng(7)
+    G = noise_genotypes(rng, m1, m2, n)
+    pair = inject_two_locus_pair(rng, G, m1, int(0.8 * m1), int(0.5 * m2))
+    return {"name": f"two_locus_n{n}_m{m1}+{m2}", "G": G, "m1": m1, "m2": m2, "pair": pair}
+
+
 def cfg_points_small():
     """Plain CPP + FRNN: n=4096, d=64, one planted pair (noise sd 1e-3), R=8."""
     rng = config_rng(0)
