@@ -372,10 +372,49 @@ __global__ __launch_bounds__(1024) void bitonic_local_kernel(uint64_t *keys, dou
     }
 }
 
+// The whole network in one work-group's LDS, for mpad <= LOCAL (one launch
+// instead of one per stage).
+__global__ __launch_bounds__(1024) void bitonic_small_kernel(uint64_t *keys, double *vals, int mpad)
+{
+    __shared__ uint64_t sk[LOCAL];
+    __shared__ double sv[LOCAL];
+    for (int q = threadIdx.x; q < mpad; q += 1024) {
+        sk[q] = keys[q];
+        sv[q] = vals[q];
+    }
+    __syncthreads();
+    for (int k = 2; k <= mpad; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int q = threadIdx.x; q < mpad; q += 1024) {
+                const int l = q ^ j;
+                if (l > q) {
+                    const bool up = (q & k) == 0;
+                    const uint64_t a = sk[q], b = sk[l];
+                    if ((a > b) == up) {
+                        sk[q] = b;
+                        sk[l] = a;
+                        const double t = sv[q];
+                        sv[q] = sv[l];
+                        sv[l] = t;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int q = threadIdx.x; q < mpad; q += 1024) {
+        keys[q] = sk[q];
+        vals[q] = sv[q];
+    }
+}
+
 void launch_sort_pairs(uint64_t *keys, double *vals, int64_t m, int64_t mpad, hipStream_t st)
 {
     if (m <= 1) return;
     if (mpad > m) hipLaunchKernelGGL(pad_sentinel_kernel, dim3(grid_of(mpad - m)), dim3(256), 0, st, keys, vals, m, mpad);
+    if (mpad <= LOCAL) {
+        hipLaunchKernelGGL(bitonic_small_kernel, dim3(1), dim3(1024), 0, st, keys, vals, (int)mpad);
+        return;
+    }
     for (int64_t k = 2; k <= mpad; k <<= 1) {
         int64_t j = k >> 1;
         for (; j >= LOCAL; j >>= 1)
