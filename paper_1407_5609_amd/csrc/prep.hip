@@ -118,69 +118,141 @@ __device__ __forceinline__ int64_t xs_index(int64_t r, int64_t k, int32_t kpad, 
 }
 
 // ---------------------------------------------------------------------------
-// points: one wave per row
+// points: a work-group of 256 threads prepares PREP_ROWS consecutive rows, one
+// wave per row at a time; the block maxima of its rows are reduced in LDS and
+// merged with one set of atomics per work-group (the rows of a work-group lie
+// in one tile block), not one per row: per-row atomics on the few addresses
+// of the blocks in flight serialise.
 // ---------------------------------------------------------------------------
+constexpr int PREP_ROWS = 32;   // divides every tile edge and every npad
+
 template <int PREC, bool INT8_IN>
 __global__ __launch_bounds__(256) void prep_points_kernel(const void *pts, int64_t n, int64_t d, int64_t ld,
                                                           void *xs, int32_t kpad, int64_t npad, void *shat,
                                                           float4 *bmax, int tile, unsigned int *flags,
                                                           const int32_t *perm)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= npad) return;
-    const bool real = row < n;
-    // screen row `row` holds source row srow (a permutation of 0..n-1, or the identity)
-    const int64_t srow = (real && perm) ? (int64_t)perm[row] : row;
-    if constexpr (INT8_IN) {
-        const signed char *x = (const signed char *)pts + srow * ld;
-        int s = 0;
-        for (int64_t k = lane; k < kpad; k += 64) {
-            const signed char v = (real && k < d) ? x[k] : (signed char)0;
-            ((signed char *)xs)[xs_index(row, k, kpad, 1, tile)] = v;
-            s += (int)v * (int)v;
-        }
+    __shared__ float4 sh_bm[4];
+    __shared__ unsigned int sh_f[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * PREP_ROWS;
+    // four consecutive coordinates per lane, 256 per step (kpad is a multiple
+    // of 32; four elements never straddle a 64-byte slice of the operand);
+    // vector loads when the rows are 16-byte aligned
+    const bool vec = ((ld & 3) == 0) && (((uintptr_t)pts & 15) == 0);
+    float4 bm = make_float4(0.f, 0.f, 0.f, 0.f);
+    unsigned int fl = 0;
+    for (int q = wave; q < PREP_ROWS; q += 4) {
+        const int64_t row = r0 + q;
+        const bool real = row < n;
+        // screen row `row` holds source row srow (a permutation of 0..n-1, or the identity)
+        const int64_t srow = (real && perm) ? (int64_t)perm[row] : row;
+        if constexpr (INT8_IN) {
+            const signed char *x = (const signed char *)pts + srow * ld;
+            const bool vec8 = ((ld & 3) == 0) && (((uintptr_t)pts & 3) == 0);
+            int s = 0;
+#pragma unroll 2
+            for (int64_t k0 = 4 * lane; k0 < kpad; k0 += 256) {
+                signed char v[4];
+                if (real && vec8 && k0 + 4 <= d) {
+                    const int qv = *(const int *)(x + k0);
 #pragma unroll
-        for (int of = 32; of > 0; of >>= 1) s += __shfl_xor(s, of, 64);
-        if (lane == 0) ((int *)shat)[row] = s;
-        return;
-    } else {
-        const float *x = (const float *)pts + srow * ld;
-        double s = 0.0, t2 = 0.0, r2 = 0.0;
-        bool bad = false;
-        for (int64_t k = lane; k < kpad; k += 64) {
-            const float v = (real && k < d) ? x[k] : 0.0f;
-            if (!isfinite(v)) bad = true;
-            float vt;
-            if constexpr (PREC == P_BF16) {
-                const unsigned short h = f32_to_bf16_rne(v);
-                ((unsigned short *)xs)[xs_index(row, k, kpad, 2, tile)] = h;
-                vt = bf16_to_f32(h);
-            } else {
-                ((float *)xs)[xs_index(row, k, kpad, 4, tile)] = v;
-                vt = v;
+                    for (int u = 0; u < 4; ++u) v[u] = (signed char)(qv >> (8 * u));
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v[u] = (real && k0 + u < d) ? x[k0 + u] : (signed char)0;
+                }
+                int packed = 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    packed |= (int)(unsigned char)v[u] << (8 * u);
+                    s += (int)v[u] * (int)v[u];
+                }
+                *(int *)((signed char *)xs + xs_index(row, k0, kpad, 1, tile)) = packed;
             }
-            const double vd = (double)v, vtd = (double)vt;
-            s = fma(vd, vd, s);
-            t2 = fma(vtd, vtd, t2);
-            const double df = vd - vtd;  // exact: both are float values
-            r2 = fma(df, df, r2);
+#pragma unroll
+            for (int of = 32; of > 0; of >>= 1) s += __shfl_xor(s, of, 64);
+            if (lane == 0) ((int *)shat)[row] = s;
+        } else {
+            const float *x = (const float *)pts + srow * ld;
+            double s = 0.0, t2 = 0.0, r2 = 0.0;
+            bool bad = false;
+#pragma unroll 2
+            for (int64_t k0 = 4 * lane; k0 < kpad; k0 += 256) {
+                float v[4];
+                if (real && vec && k0 + 4 <= d) {
+                    const float4 qv = *(const float4 *)(x + k0);
+                    v[0] = qv.x;
+                    v[1] = qv.y;
+                    v[2] = qv.z;
+                    v[3] = qv.w;
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) v[u] = (real && k0 + u < d) ? x[k0 + u] : 0.0f;
+                }
+                float vt[4];
+                if constexpr (PREC == P_BF16) {
+                    unsigned short h[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        h[u] = f32_to_bf16_rne(v[u]);
+                        vt[u] = bf16_to_f32(h[u]);
+                    }
+                    const uint2 pk = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                                                (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+                    *(uint2 *)((unsigned short *)xs + xs_index(row, k0, kpad, 2, tile)) = pk;
+                } else {
+                    *(float4 *)((float *)xs + xs_index(row, k0, kpad, 4, tile)) =
+                        make_float4(v[0], v[1], v[2], v[3]);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) vt[u] = v[u];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    bad |= !isfinite(v[u]);
+                    const double vd = (double)v[u], vtd = (double)vt[u];
+                    s = fma(vd, vd, s);
+                    t2 = fma(vtd, vtd, t2);
+                    const double df = vd - vtd;  // exact: both are float values
+                    r2 = fma(df, df, r2);
+                }
+            }
+            s = wave_sum(s);
+            t2 = wave_sum(t2);
+            r2 = wave_sum(r2);
+            const unsigned long long anybad = __ballot(bad);
+            if (lane == 0) {
+                ((float *)shat)[row] = (float)s;
+                bm.x = fmaxf(bm.x, f32_up(s));
+                bm.y = fmaxf(bm.y, up_f32(sqrt(s)));
+                bm.z = fmaxf(bm.z, up_f32(sqrt(t2)));
+                bm.w = fmaxf(bm.w, up_f32(sqrt(r2)));
+                if (anybad) fl |= F_NONFINITE;
+                if (!(s < 0x1p100)) fl |= F_RANGE;
+            }
         }
-        s = wave_sum(s);
-        t2 = wave_sum(t2);
-        r2 = wave_sum(r2);
-        const unsigned long long anybad = __ballot(bad);
+    }
+    if constexpr (!INT8_IN) {
         if (lane == 0) {
-            ((float *)shat)[row] = (float)s;
-            const float4 st = make_float4((float)s, up_f32(sqrt(s)), up_f32(sqrt(t2)), up_f32(sqrt(r2)));
-            float *bm = (float *)(bmax + row / tile);
-            atomic_max_f32(bm + 0, f32_up(s));
-            atomic_max_f32(bm + 1, st.y);
-            atomic_max_f32(bm + 2, st.z);
-            atomic_max_f32(bm + 3, st.w);
-            unsigned int f = 0;
-            if (anybad) f |= F_NONFINITE;
-            if (!(s < 0x1p100)) f |= F_RANGE;
+            sh_bm[wave] = bm;
+            sh_f[wave] = fl;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float4 m = sh_bm[0];
+            unsigned int f = sh_f[0];
+            for (int w = 1; w < 4; ++w) {
+                m.x = fmaxf(m.x, sh_bm[w].x);
+                m.y = fmaxf(m.y, sh_bm[w].y);
+                m.z = fmaxf(m.z, sh_bm[w].z);
+                m.w = fmaxf(m.w, sh_bm[w].w);
+                f |= sh_f[w];
+            }
+            float *b = (float *)(bmax + r0 / tile);
+            atomic_max_f32(b + 0, m.x);
+            atomic_max_f32(b + 1, m.y);
+            atomic_max_f32(b + 2, m.z);
+            atomic_max_f32(b + 3, m.w);
             if (f) atomicOr(flags, f);
         }
     }
@@ -190,7 +262,7 @@ void launch_prep_points(const void *pts, int dtype, int64_t n, int64_t d, int64_
                         int32_t kpad, int64_t npad, void *shat, float4 *bmax, int tile, unsigned int *flags,
                         const int32_t *perm, hipStream_t st)
 {
-    dim3 g((unsigned)((npad + 3) / 4)), b(256);
+    dim3 g((unsigned)(npad / PREP_ROWS)), b(256);
     if (dtype == 1)
         hipLaunchKernelGGL((prep_points_kernel<P_I8, true>), g, b, 0, st, pts, n, d, ld, xs, kpad, npad, shat, bmax,
                            tile, flags, perm);
@@ -290,6 +362,8 @@ __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs,
     __syncthreads();
 
     const int lane = tid & 63, wave = tid >> 6;
+    __shared__ float4 sh_bm[4];
+    float4 bmw = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int q = wave; q < SERIES_WPB; q += 4) {
         const int64_t w = w0 + q;
         if (w >= J.npad) break;
@@ -321,11 +395,41 @@ __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs,
         r2 = wave_sum(r2);
         if (lane == 0) {
             ((float *)J.shat)[row] = (float)s;
-            float *bm = (float *)(J.bmax + row / tile);
-            atomic_max_f32(bm + 0, f32_up(s));
-            atomic_max_f32(bm + 1, up_f32(sqrt(s)));
-            atomic_max_f32(bm + 2, up_f32(sqrt(t2)));
-            atomic_max_f32(bm + 3, up_f32(sqrt(r2)));
+            const float4 v = make_float4(f32_up(s), up_f32(sqrt(s)), up_f32(sqrt(t2)), up_f32(sqrt(r2)));
+            if (J.iperm) {
+                // windows in reference order land in any tile block
+                float *bm = (float *)(J.bmax + row / tile);
+                atomic_max_f32(bm + 0, v.x);
+                atomic_max_f32(bm + 1, v.y);
+                atomic_max_f32(bm + 2, v.z);
+                atomic_max_f32(bm + 3, v.w);
+            } else {
+                bmw.x = fmaxf(bmw.x, v.x);
+                bmw.y = fmaxf(bmw.y, v.y);
+                bmw.z = fmaxf(bmw.z, v.z);
+                bmw.w = fmaxf(bmw.w, v.w);
+            }
+        }
+    }
+    // windows in position order: the block's SERIES_WPB rows lie in one tile
+    // block; one set of atomics per work-group (per-window atomics on the few
+    // block addresses in flight serialise)
+    if (!J.iperm) {
+        if (lane == 0) sh_bm[wave] = bmw;
+        __syncthreads();
+        if (tid == 0) {
+            float4 m = sh_bm[0];
+            for (int w = 1; w < 4; ++w) {
+                m.x = fmaxf(m.x, sh_bm[w].x);
+                m.y = fmaxf(m.y, sh_bm[w].y);
+                m.z = fmaxf(m.z, sh_bm[w].z);
+                m.w = fmaxf(m.w, sh_bm[w].w);
+            }
+            float *bm = (float *)(J.bmax + w0 / tile);
+            atomic_max_f32(bm + 0, m.x);
+            atomic_max_f32(bm + 1, m.y);
+            atomic_max_f32(bm + 2, m.z);
+            atomic_max_f32(bm + 3, m.w);
         }
     }
 }
