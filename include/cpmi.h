@@ -259,6 +259,31 @@ enum { CPMI_MOST_CORRELATED = 0, CPMI_LEAST_CORRELATED = 1 };
 int cpmi_strings_pair(cpmi_ctx *ctx, const int8_t *strings, int64_t n, int64_t k, int64_t ld, int sigma,
                       int mode, void *stream, cpmi_match_pair *out);
 
+/* Randomised light-bulb bucketing (Section 4, MLBA; Section 5 for the least
+ * correlated pair), a candidate generator for the problem of
+ * cpmi_strings_pair. Each of `iterations` iterations picks `columns` random
+ * columns (distinct; drawn from `seed`), sorts the rows by their values in
+ * those columns, and adds every pair of rows with equal values there (one
+ * bucket) to the candidates; each candidate's exact match count is computed
+ * and the best pair kept (ties to the lexicographically smallest (i, j)).
+ * CPMI_MOST_CORRELATED buckets the strings themselves (columns are
+ * positions, at most 64 / ceil(log2 sigma) of them); CPMI_LEAST_CORRELATED
+ * buckets the one-hot codes against their complements (columns are bit
+ * positions of the codes, at most 64) and keeps (code, complement) pairs of
+ * different strings. The answer is the exact best pair with high probability
+ * only (enough iterations; the paper's analysis); the reported count is
+ * always the pair's exact one. *pairs_out (host, nullable) receives the
+ * number of candidate pairs collected over all iterations (the paper's
+ * measure of work). cap: candidate pairs one iteration may hold. strings:
+ * device, as for cpmi_strings_pair; out: host. Needs n < 2^21 - 1. Errors:
+ * ERR_ARG (shapes, mode, columns, iterations, cap, a symbol outside the
+ * alphabet), ERR_NOPAIR (n < 2, or no two rows ever shared a bucket),
+ * ERR_CAPACITY (an iteration produced more than cap candidates; *pairs_out
+ * still counts them). */
+int cpmi_strings_lightbulb(cpmi_ctx *ctx, const int8_t *strings, int64_t n, int64_t k, int64_t ld, int sigma,
+                           int mode, int iterations, int columns, uint64_t seed, int64_t cap, void *stream,
+                           cpmi_match_pair *out, int64_t *pairs_out);
+
 /* Two-locus association (Section 6): genotypes (device, int8 in {0, 1, 2},
  * (m1 + m2) x n, row s = subject s, row stride ld >= n; the first m1 rows
  * are cases, the rest controls). With A', B' the one-hot codes of the cases'

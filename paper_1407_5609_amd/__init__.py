@@ -87,6 +87,8 @@ def _load():
                                    C.POINTER(_CPair)]
     L.cpmi_strings_pair.argtypes = [vp, vp, i64, i64, i64, i32, i32, vp, C.POINTER(_CMatchPair)]
     L.cpmi_two_locus.argtypes = [vp, vp, i64, i64, i64, i64, i32, vp, C.POINTER(_CMatchPair)]
+    L.cpmi_strings_lightbulb.argtypes = [vp, vp, i64, i64, i64, i32, i32, i32, i32, C.c_uint64, i64, vp,
+                                         C.POINTER(_CMatchPair), C.POINTER(i64)]
     L.cpmi_autotune.argtypes = [vp, vp, i32, i64, i64, i64, i32, vp, i32, C.POINTER(_CTune)]
     L.cpmi_save_tune_cache.argtypes = [vp, C.c_char_p]
     L.cpmi_tune_lookup.argtypes = [vp, i32, i32, i64, dbl, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
@@ -279,6 +281,18 @@ class Context:
         self._check(_lib.cpmi_strings_pair(self._h, C.c_void_p(strings.data_ptr()), n, k, ld, int(sigma), m,
                                            _stream_ptr(stream), C.byref(out)))
         return MatchPair(out.i, out.j, out.matches, out.length)
+
+    def strings_lightbulb(self, strings, sigma: int, mode: str = "most", iterations: int = 16, columns: int = 8,
+                          seed: int = 0, cap: int = 1 << 22, stream=None):
+        """Randomised light-bulb bucketing (cpmi_strings_lightbulb): returns
+        (MatchPair, pairs collected)."""
+        n, k, ld = self._int8_matrix(strings, "strings")
+        m = {"most": 0, "least": 1}[mode]
+        out, pairs = _CMatchPair(), C.c_int64(0)
+        self._check(_lib.cpmi_strings_lightbulb(self._h, C.c_void_p(strings.data_ptr()), n, k, ld, int(sigma), m,
+                                                int(iterations), int(columns), int(seed), int(cap),
+                                                _stream_ptr(stream), C.byref(out), C.byref(pairs)))
+        return MatchPair(out.i, out.j, out.matches, out.length), int(pairs.value)
 
     def two_locus(self, genotypes, m1: int, m2: int, direction: int = 0, stream=None) -> MatchPair:
         """Two-locus association pair of the SNP columns of `genotypes`

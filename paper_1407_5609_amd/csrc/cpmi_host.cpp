@@ -106,6 +106,9 @@ struct cpmi_ctx {
     DevBuf mD, mperm, miperm, mlo, mhi, mrefs, msort;
     // string problems: encoded int8 rows and the encoder's flag word
     DevBuf mZ, mflag;
+    // light-bulb bucketing: keys and rows (in, out), sort scratch, columns,
+    // candidates, counters
+    DevBuf lbA, lbT, lbC, lbP, lbK;
 };
 
 namespace {
@@ -991,7 +994,7 @@ int cpmi_destroy(cpmi_ctx *c)
     DevBuf *bufs[] = {&c->xs,      &c->shat,  &c->bmax, &c->musg, &c->probs, &c->jobs, &c->tiles, &c->tile_min,
                       &c->sel,     &c->candR, &c->candU, &c->cand_d2, &c->keys, &c->vals, &c->cnt, &c->ubits,
                       &c->res,     &c->mD,    &c->mperm, &c->miperm, &c->mlo, &c->mhi, &c->mrefs, &c->msort,
-                      &c->mZ,      &c->mflag};
+                      &c->mZ,      &c->mflag, &c->lbA, &c->lbT, &c->lbC, &c->lbP, &c->lbK};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
     if (c->pinned) hipHostFree(c->pinned);
@@ -1277,6 +1280,103 @@ int cpmi_strings_pair(cpmi_ctx *c, const int8_t *strings, int64_t n, int64_t k, 
     out->j = least ? b - h.split : b;
     // code vs code: d2 = 2 (k - u); code vs complement: d2 = sigma k - 2 (k - u)
     out->matches = least ? k - (Lz - d2) / 2 : k - d2 / 2;
+    out->length = k;
+    out->status = CPMI_OK;
+    c->stats.valid_pairs = pairs_of(n, 1);
+    return CPMI_OK;
+}
+
+int cpmi_strings_lightbulb(cpmi_ctx *c, const int8_t *strings, int64_t n, int64_t k, int64_t ld, int sigma,
+                           int mode, int iterations, int columns, uint64_t seed, int64_t cap, void *stream,
+                           cpmi_match_pair *out, int64_t *pairs_out)
+{
+    if (!c) return CPMI_ERR_ARG;
+    c->err.clear();
+    c->stats = cpmi_stats{};
+    if (!out) return fail(c, CPMI_ERR_ARG, "out is NULL");
+    memset(out, 0, sizeof *out);
+    out->i = out->j = -1;
+    if (pairs_out) *pairs_out = 0;
+    if (!strings) return fail(c, CPMI_ERR_ARG, "strings pointer is NULL");
+    if (mode != CPMI_MOST_CORRELATED && mode != CPMI_LEAST_CORRELATED) return fail(c, CPMI_ERR_ARG, "unknown mode %d", mode);
+    if (sigma < 2 || sigma > 64) return fail(c, CPMI_ERR_ARG, "sigma must be in 2..64");
+    if (k < 1 || ld < k || n < 0) return fail(c, CPMI_ERR_ARG, "bad shape n=%lld k=%lld ld=%lld", (long long)n, (long long)k, (long long)ld);
+    if (n >= (1ll << 21) - 1) return fail(c, CPMI_ERR_ARG, "n must be below 2^21 - 1");
+    if (iterations < 1) return fail(c, CPMI_ERR_ARG, "iterations must be >= 1");
+    if (cap < 1 || cap > (1ll << 30)) return fail(c, CPMI_ERR_ARG, "cap must be in 1..2^30");
+    int bits_per = 1;
+    while ((1 << bits_per) < sigma) ++bits_per;
+    if (mode == CPMI_LEAST_CORRELATED) bits_per = 1;
+    const int64_t ncol_all = mode == CPMI_MOST_CORRELATED ? k : (int64_t)sigma * k;
+    if (columns < 1 || columns > ncol_all || (int64_t)columns * bits_per > 64)
+        return fail(c, CPMI_ERR_ARG, "columns must be in 1..min(%lld, %d)", (long long)ncol_all, 64 / bits_per);
+    if (n < 2) {
+        out->status = CPMI_ERR_NOPAIR;
+        return fail(c, CPMI_ERR_NOPAIR, "fewer than two strings");
+    }
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const int m = mode == CPMI_MOST_CORRELATED ? 0 : 1;
+    const int64_t total = m == 0 ? n : 2 * n;
+    // columns of every iteration, distinct within an iteration (seeded
+    // partial Fisher-Yates draws)
+    std::vector<int32_t> cols((size_t)iterations * columns);
+    {
+        std::vector<int32_t> pool((size_t)ncol_all);
+        uint64_t ctr = seed * 0x9e3779b97f4a7c15ull;
+        for (int it = 0; it < iterations; ++it) {
+            for (int64_t q = 0; q < ncol_all; ++q) pool[q] = (int32_t)q;
+            for (int q = 0; q < columns; ++q) {
+                const int64_t r = q + (int64_t)(splitmix64(ctr++) % (uint64_t)(ncol_all - q));
+                std::swap(pool[q], pool[r]);
+                cols[(size_t)it * columns + q] = pool[q];
+            }
+        }
+    }
+    size_t tb = 0;
+    HIPCHK(c, lb_sort(nullptr, &tb, nullptr, nullptr, nullptr, nullptr, total, columns * bits_per, st));
+    if ((rc = ensure(c, c->lbA, (size_t)total * 24))) return rc;   // keys in, keys out, rows in, rows out
+    if ((rc = ensure(c, c->lbT, std::max<size_t>(tb, 1)))) return rc;
+    if ((rc = ensure(c, c->lbC, cols.size() * 4))) return rc;
+    if ((rc = ensure(c, c->lbP, (size_t)cap * 8))) return rc;
+    if ((rc = ensure(c, c->lbK, 64))) return rc;
+    uint64_t *kin = (uint64_t *)c->lbA.p, *kout = kin + total;
+    int32_t *rin = (int32_t *)(kout + total), *rout = rin + total;
+    unsigned long long *cnt = (unsigned long long *)c->lbK.p, *tot = cnt + 1, *best = cnt + 2;
+    unsigned int *ovf = (unsigned int *)(cnt + 3), *flag = ovf + 1;
+    HIPCHK(c, hipMemcpyAsync(c->lbC.p, cols.data(), cols.size() * 4, hipMemcpyHostToDevice, st));
+    launch_fill_u64((uint64_t *)c->lbK.p, 0ull, 2, st);
+    launch_fill_u64((uint64_t *)best, m == 0 ? 0ull : ~0ull, 1, st);
+    launch_fill_u32(ovf, 0u, 2, st);
+    launch_check_symbols((const signed char *)strings, n, k, ld, sigma, flag, st);
+    for (int it = 0; it < iterations; ++it) {
+        launch_fill_u64((uint64_t *)cnt, 0ull, 1, st);
+        launch_lb_keys((const signed char *)strings, n, ld, sigma, m, bits_per, (const int32_t *)c->lbC.p + (size_t)it * columns,
+                       columns, kin, rin, st);
+        HIPCHK(c, lb_sort(c->lbT.p, &tb, kin, kout, rin, rout, total, columns * bits_per, st));
+        launch_lb_pairs(kout, rout, total, n, m, (int2 *)c->lbP.p, (uint32_t)cap, cnt, st);
+        launch_lb_verify((const signed char *)strings, k, ld, m, (const int2 *)c->lbP.p, cnt, (uint32_t)cap, best, tot,
+                         ovf, st);
+    }
+    HIPCHK(c, hipGetLastError());
+    uint64_t res[4];
+    HIPCHK(c, hipMemcpyAsync(res, c->lbK.p, 32, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    const uint32_t ovf_h = (uint32_t)res[3], flag_h = (uint32_t)(res[3] >> 32);
+    if (flag_h & F_SYMBOL) return fail(c, CPMI_ERR_ARG, "a symbol lies outside the alphabet");
+    if (pairs_out) *pairs_out = (int64_t)res[1];
+    if (ovf_h) return fail(c, CPMI_ERR_CAPACITY, "a bucketing pass produced more than %lld candidate pairs; "
+                                                 "choose more columns or a larger cap", (long long)cap);
+    const uint64_t b = res[2];
+    if ((m == 0 && b == 0) || (m == 1 && b == ~0ull)) {
+        out->status = CPMI_ERR_NOPAIR;
+        return fail(c, CPMI_ERR_NOPAIR, "no pair shared a bucket");
+    }
+    const uint64_t mask = (1ull << 42) - 1, ij = m == 0 ? (~b & mask) : (b & mask);
+    out->i = (int64_t)(ij >> 21);
+    out->j = (int64_t)(ij & ((1ull << 21) - 1));
+    out->matches = (int64_t)(b >> 42);
     out->length = k;
     out->status = CPMI_OK;
     c->stats.valid_pairs = pairs_of(n, 1);

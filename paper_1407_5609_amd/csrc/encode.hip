@@ -81,6 +81,18 @@ __global__ __launch_bounds__(256) void encode_two_locus_kernel(const signed char
     }
 }
 
+// Flag F_SYMBOL if some symbol of the strings lies outside 0..sigma-1.
+__global__ void check_symbols_kernel(const signed char *S, int64_t n, int64_t k, int64_t ld, int sigma,
+                                     unsigned int *flags)
+{
+    const int64_t total = n * k;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int s = S[(t / k) * ld + t % k];
+        if (s < 0 || s >= sigma) atomicOr(flags, (unsigned int)F_SYMBOL);
+    }
+}
+
 unsigned grid_for(int64_t total)
 {
     const int64_t g = (total + 255) / 256;
@@ -94,6 +106,12 @@ void launch_encode_strings(const signed char *S, int64_t n, int64_t k, int64_t l
 {
     hipLaunchKernelGGL(encode_strings_kernel, dim3(grid_for(n * k)), dim3(256), 0, st, S, n, k, ld, sigma, complement,
                        Z, Lz, split, flags);
+}
+
+void launch_check_symbols(const signed char *S, int64_t n, int64_t k, int64_t ld, int sigma, unsigned int *flags,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(check_symbols_kernel, dim3(grid_for(n * k)), dim3(256), 0, st, S, n, k, ld, sigma, flags);
 }
 
 void launch_encode_two_locus(const signed char *G, int64_t m1, int64_t m2, int64_t n, int64_t ld, int direction,

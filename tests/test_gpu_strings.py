@@ -117,3 +117,65 @@ def test_string_errors(ctx, torch_dev):
     # the context still works after the errors
     r = ctx.strings_pair(_dev(np.array([[0, 1], [0, 1], [1, 0]], np.int8), torch_dev), 2, "most")
     assert (r.i, r.j, r.matches) == (0, 1, 2)
+
+
+# ---------------------------------------------------------------------------
+# randomised light-bulb bucketing (Section 4, MLBA)
+# ---------------------------------------------------------------------------
+
+def test_lightbulb_finds_the_planted_most_correlated_pair(ctx, torch_dev):
+    """A pair agreeing in 58 of 64 positions among 5,000 random strings over 4
+    letters: with 8 random columns it shares a bucket in an iteration with
+    probability (58/64)^8 = 0.45, so 24 iterations find it (the exact best
+    pair) and collect far fewer pairs than the n(n-1)/2 of brute force."""
+    rng = np.random.default_rng(41)
+    S = W.random_strings(rng, 5000, 64, 4)
+    a, b = W.plant_string_pair(rng, S, 4, 58)
+    want = oracle.strings_pair(S, 4, "most")
+    assert want[:2] == (a, b)
+    r, pairs = ctx.strings_lightbulb(_dev(S, torch_dev), 4, "most", iterations=24, columns=8, seed=7)
+    assert (r.i, r.j, r.matches) == want
+    assert 0 < pairs < 5000 * 4999 // 2 // 100
+    # the same seed gives the same run
+    r2, pairs2 = ctx.strings_lightbulb(_dev(S, torch_dev), 4, "most", iterations=24, columns=8, seed=7)
+    assert (r2.i, r2.j, r2.matches, pairs2) == (r.i, r.j, r.matches, pairs)
+
+
+def test_lightbulb_finds_the_least_correlated_binary_pair(ctx, torch_dev):
+    """Binary strings (Section 5's light bulbs): a pair disagreeing everywhere
+    makes a code and the other's complement identical, so it shares a bucket
+    in every iteration."""
+    rng = np.random.default_rng(42)
+    S = W.random_strings(rng, 3000, 64, 2)
+    W.plant_string_pair(rng, S, 2, 0)
+    want = oracle.strings_pair(S, 2, "least")
+    r, pairs = ctx.strings_lightbulb(_dev(S, torch_dev), 2, "least", iterations=4, columns=20, seed=1)
+    assert (r.i, r.j, r.matches) == want
+    assert pairs > 0
+
+
+@pytest.mark.parametrize("mode,sigma,columns", [("most", 3, 4), ("least", 3, 12), ("most", 5, 3)])
+def test_lightbulb_reports_exact_counts(ctx, torch_dev, mode, sigma, columns):
+    """Whatever pairs the random buckets yield, the reported pair's count is
+    its exact one and never beats the exact optimum."""
+    rng = np.random.default_rng(sigma + columns)
+    S = W.random_strings(rng, 800, 24, sigma)
+    r, pairs = ctx.strings_lightbulb(_dev(S, torch_dev), sigma, mode, iterations=6, columns=columns, seed=3)
+    assert 0 <= r.i < r.j < 800
+    assert r.matches == oracle.matches(S, r.i, r.j)
+    best = oracle.strings_pair(S, sigma, mode)[2]
+    assert r.matches <= best if mode == "most" else r.matches >= best
+
+
+def test_lightbulb_errors(ctx, torch_dev):
+    import paper_1407_5609_amd as cp
+    S = _dev(np.zeros((100, 8), np.int8), torch_dev)
+    with pytest.raises(cp.CpmiError):
+        ctx.strings_lightbulb(S, 4, "most", columns=33)          # 33 x 2 bits > 64
+    with pytest.raises(cp.CpmiError):
+        ctx.strings_lightbulb(S, 4, "most", iterations=0)
+    with pytest.raises(cp.CpmiError) as e:
+        ctx.strings_lightbulb(S, 4, "most", columns=2, cap=10)   # identical strings: one bucket of 100
+    assert e.value.code == cp.ERR_CAPACITY
+    r, pairs = ctx.strings_lightbulb(S, 4, "most", columns=2, cap=10000)
+    assert (r.i, r.j, r.matches) == (0, 1, 8) and pairs == 100 * 99 // 2 * 16
