@@ -103,7 +103,7 @@ struct cpmi_ctx {
     int prune_q = 0;
     double prune_f = 10.0;
     uint64_t prune_seed = 0;
-    DevBuf mD, mperm, miperm, mlo, mhi, mrefs, msort;
+    DevBuf mD, mperm, miperm, mlo, mhi, mrefs, msort, mrowstat;
     // string problems: encoded int8 rows and the encoder's flag word
     DevBuf mZ, mflag;
     // light-bulb bucketing: keys and rows (in, out), sort scratch, columns,
@@ -516,6 +516,10 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
                 j.flags = &((ResDev *)c->res.p)[p].flags;
                 j.kpad = h.kpad;
                 j.iperm = h.iperm;
+                if (h.iperm) {
+                    if ((rc = ensure(c, c->mrowstat, (size_t)h.npad * sizeof(float4)))) return rc;
+                    j.rowstat = (float4 *)c->mrowstat.p;
+                }
                 jobs.push_back(j);
             }
         }
@@ -538,6 +542,9 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             } else if (!jobs.empty()) {
                 launch_fill_u32((uint32_t *)c->bmax.p, 0u, (int64_t)(bm_b / 4), st);
                 launch_prep_series((const SeriesJob *)c->jobs.p, (int64_t)jobs.size(), blk, prec, tile, st);
+                // windows in reference order (one series): block maxima from the per-row terms
+                if (jobs.size() == 1 && jobs[0].rowstat)
+                    launch_block_max(jobs[0].rowstat, hp[0].npad, tile, (float4 *)P[0].bmax, st);
             } else {
                 launch_fill_u32((uint32_t *)c->bmax.p, 0u, (int64_t)(bm_b / 4), st);
                 const HostProb &h = hp[0];
@@ -993,7 +1000,7 @@ int cpmi_destroy(cpmi_ctx *c)
     if (c->gexec) hipGraphExecDestroy(c->gexec);
     DevBuf *bufs[] = {&c->xs,      &c->shat,  &c->bmax, &c->musg, &c->probs, &c->jobs, &c->tiles, &c->tile_min,
                       &c->sel,     &c->candR, &c->candU, &c->cand_d2, &c->keys, &c->vals, &c->cnt, &c->ubits,
-                      &c->res,     &c->mD,    &c->mperm, &c->miperm, &c->mlo, &c->mhi, &c->mrefs, &c->msort,
+                      &c->res,     &c->mD,    &c->mperm, &c->miperm, &c->mlo, &c->mhi, &c->mrefs, &c->msort, &c->mrowstat,
                       &c->mZ,      &c->mflag, &c->lbA, &c->lbT, &c->lbC, &c->lbP, &c->lbK};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);

@@ -109,6 +109,7 @@ struct SeriesJob {
     int32_t kpad;
     int32_t pad0;
     const int32_t *iperm;  // screen row of window w (reference order), or null for w itself
+    float4 *rowstat;       // with iperm: per-row maxima terms, reduced per block by launch_block_max
 };
 
 // ---- launchers (defined in the .hip files) --------------------------------
@@ -127,6 +128,8 @@ void launch_prep_points(const void *pts, int dtype, int64_t n, int64_t d, int64_
 
 // Window builder of many series: canonical mean/sigma, z-normalised screen
 // operand, row scalars, block maxima (zero on entry), flags.
+// bmax[b] = componentwise max of rowstat over the rows of block b (tile <= 256 rows).
+void launch_block_max(const float4 *rowstat, int64_t npad, int tile, float4 *bmax, hipStream_t st);
 void launch_prep_series(const SeriesJob *jobs, int64_t njobs, int64_t total_blocks, int prec, int tile,
                         hipStream_t st);
 

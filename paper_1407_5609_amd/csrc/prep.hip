@@ -372,6 +372,8 @@ __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs,
         const int64_t row = (J.iperm && w < N) ? (int64_t)J.iperm[w] : w;
         const double mu = sh_mu[q], sg = sh_sg[q];
         double s = 0.0, t2 = 0.0, r2 = 0.0;
+        // (two iterations in flight: the divisions are long dependent chains)
+#pragma unroll 2
         for (int64_t k = lane; k < J.kpad; k += 64) {
             double xh = 0.0;
             if (real && k < ell) xh = ((double)sh_T[q + k] - mu) / sg;   // T[w + k]
@@ -397,12 +399,9 @@ __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs,
             ((float *)J.shat)[row] = (float)s;
             const float4 v = make_float4(f32_up(s), up_f32(sqrt(s)), up_f32(sqrt(t2)), up_f32(sqrt(r2)));
             if (J.iperm) {
-                // windows in reference order land in any tile block
-                float *bm = (float *)(J.bmax + row / tile);
-                atomic_max_f32(bm + 0, v.x);
-                atomic_max_f32(bm + 1, v.y);
-                atomic_max_f32(bm + 2, v.z);
-                atomic_max_f32(bm + 3, v.w);
+                // windows in reference order land in any tile block: per-row
+                // terms, reduced per block afterwards (launch_block_max)
+                J.rowstat[row] = v;
             } else {
                 bmw.x = fmaxf(bmw.x, v.x);
                 bmw.y = fmaxf(bmw.y, v.y);
@@ -432,6 +431,38 @@ __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs,
             atomic_max_f32(bm + 3, m.w);
         }
     }
+}
+
+__global__ __launch_bounds__(256) void block_max_kernel(const float4 *rowstat, int tile, float4 *bmax)
+{
+    __shared__ float4 red[4];
+    const int64_t b = blockIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    float4 v = t < tile ? rowstat[b * tile + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        v.x = fmaxf(v.x, __shfl_xor(v.x, o, 64));
+        v.y = fmaxf(v.y, __shfl_xor(v.y, o, 64));
+        v.z = fmaxf(v.z, __shfl_xor(v.z, o, 64));
+        v.w = fmaxf(v.w, __shfl_xor(v.w, o, 64));
+    }
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (t == 0) {
+        float4 m = red[0];
+        for (int w = 1; w < 4; ++w) {
+            m.x = fmaxf(m.x, red[w].x);
+            m.y = fmaxf(m.y, red[w].y);
+            m.z = fmaxf(m.z, red[w].z);
+            m.w = fmaxf(m.w, red[w].w);
+        }
+        bmax[b] = m;
+    }
+}
+
+void launch_block_max(const float4 *rowstat, int64_t npad, int tile, float4 *bmax, hipStream_t st)
+{
+    hipLaunchKernelGGL(block_max_kernel, dim3((unsigned)(npad / tile)), dim3(256), 0, st, rowstat, tile, bmax);
 }
 
 void launch_prep_series(const SeriesJob *jobs, int64_t njobs, int64_t total_blocks, int prec, int tile,
