@@ -12,7 +12,15 @@
  *   - time-series motif (Section 2 l-mers, Section 3 problem statement): the two
  *     closest l-mers of a series T. Windows are z-normalised and a pair of
  *     windows (i, j) is admissible only if j - i >= excl (overlapping windows
- *     are trivial matches).
+ *     are trivial matches);
+ *   - the most and the least correlated pair of strings over a small alphabet
+ *     (Sections 4-5; correlation = fraction of agreeing positions), exactly
+ *     through the one-hot encoding on the INT8 matrix cores, or by the
+ *     randomised light-bulb bucketing (MLBA);
+ *   - the two-locus association pair of SNPs (Section 6).
+ *
+ * Reference-point pruning (MPR, Section 3) can be switched on for the point
+ * and single-series motif searches (cpmi_set_pruning).
  *
  * Every answer is exact with respect to the canonical FP64 arithmetic below,
  * whatever the screening precision: a Gram-form screen on the matrix cores
