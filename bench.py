@@ -359,6 +359,8 @@ def main():
     ap.add_argument("--workload", default="mixture", choices=sorted(WORKLOADS))
     ap.add_argument("--fp32-steps", type=int, default=2, help="steps of the comparison precision (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-peak-probe", action="store_true",
+                    help="skip the sustained matrix-core rate probe reported beside the published peak")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--query", default=None, choices=["points", "cpp", "most", "least"],
                     help="point and single-series motif workloads: closest pair + radius pairs (points, the "
@@ -453,6 +455,13 @@ def main():
         "exact_match": bool(exact),
         "screen_err_over_bound": st.max_err_over_bound,
     }
+    if wl.roofline and not args.no_peak_probe:
+        # context: what a pure multiply-accumulate kernel in the same instructions sustains on this
+        # GPU under load (clock-limited), beside the published peak the fraction is taken against
+        note("probing the sustained matrix-core rate")
+        mp, _ = cp.dbg_mfma_peak(pprec)
+        out["roofline"]["measured_peak"] = mp
+        out["roofline"]["frac_of_measured_peak"] = achieved / mp
     if not wl.roofline:
         out["roofline"] = None
         out["config"]["pairs_collected"] = wl.pairs_collected

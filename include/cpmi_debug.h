@@ -21,6 +21,15 @@ extern "C" {
  * Checks the operand/accumulator lane layouts the screen assumes. */
 int cpmi_dbg_mfma_probe(int precision, const void *A, const void *B, float *C, void *stream);
 
+/* The sustained matrix-core rate of device `device` in TFLOP/s (TOP/s for
+ * int8): one work-group per compute unit, each wave issuing 16 independent
+ * 32x32 accumulations (CPMI_PREC_F32, _BF16 or _I8 operands, the screen's
+ * instructions) for `iters` rounds from registers, timed with HIP events.
+ * *ms_out (host, nullable): the timed launch. Allocates and frees its own
+ * output buffer; synchronises the device's null stream. Returns the rate, or
+ * a negative CPMI_ERR_* code. */
+double cpmi_dbg_mfma_peak(int device, int precision, int iters, double *ms_out);
+
 /* Run only the l-mer builder on a series and return the canonical window
  * means and sigmas (device double [len - ell + 1] each), so that they can be
  * compared bit for bit with the definition (Section 2 windows, two-pass

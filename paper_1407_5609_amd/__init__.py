@@ -94,6 +94,8 @@ def _load():
     L.cpmi_tune_lookup.argtypes = [vp, i32, i32, i64, dbl, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.cpmi_dbg_mfma_probe.argtypes = [i32, vp, vp, vp, vp]
     L.cpmi_dbg_copy.argtypes = [vp, vp, i64, vp]
+    L.cpmi_dbg_mfma_peak.restype = dbl
+    L.cpmi_dbg_mfma_peak.argtypes = [i32, i32, i32, C.POINTER(dbl)]
     L.cpmi_dbg_znorm.argtypes = [vp, vp, i64, i64, i32, vp, vp, vp]
     return L
 
@@ -413,6 +415,17 @@ def dbg_copy(dst, src, stream=None):
     rc = _lib.cpmi_dbg_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nb, _stream_ptr(stream))
     if rc != OK:
         raise CpmiError(rc, "copy failed")
+
+
+def dbg_mfma_peak(precision="bf16", iters: int = 100000, device: int = 0):
+    """Sustained matrix-core rate (TFLOP/s, TOP/s for int8) of a pure
+    multiply-accumulate kernel in the screen's instructions
+    (cpmi_dbg_mfma_peak); returns (rate, milliseconds)."""
+    ms = C.c_double(0.0)
+    r = _lib.cpmi_dbg_mfma_peak(int(device), _prec(precision), int(iters), C.byref(ms))
+    if r < 0:
+        raise CpmiError(int(r), "matrix-core rate probe failed")
+    return float(r), float(ms.value)
 
 
 _default = None

@@ -1603,6 +1603,37 @@ double cpmi_dbg_tile_bound(const float *bI, const float *bJ, int32_t kpad, int64
                       precision, form);
 }
 
+double cpmi_dbg_mfma_peak(int device, int precision, int iters, double *ms_out)
+{
+    if (precision < 1 || precision > 3 || iters < 1) return CPMI_ERR_ARG;
+    if (hipSetDevice(device) != hipSuccess) return CPMI_ERR_HIP;
+    int ncu = 256;
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device);
+    const int prec = precision == CPMI_PREC_F32 ? P_F32 : (precision == CPMI_PREC_BF16 ? P_BF16 : P_I8);
+    float *out = nullptr;
+    hipEvent_t e0, e1;
+    if (hipMalloc(&out, (size_t)ncu * 256 * sizeof(float)) != hipSuccess) return CPMI_ERR_HIP;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    launch_mfma_peak(prec, 2, ncu, out, nullptr);   // warm-up
+    hipEventRecord(e0, nullptr);
+    launch_mfma_peak(prec, iters, ncu, out, nullptr);
+    hipEventRecord(e1, nullptr);
+    const hipError_t e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(out);
+    if (e != hipSuccess || !(ms > 0.f)) return CPMI_ERR_HIP;
+    if (ms_out) *ms_out = ms;
+    // operations of one accumulation step: 32 x 32 outputs times K (8 = four FP32 instructions, 16, 32),
+    // two per multiply-add
+    const double per = prec == P_F32 ? 32.0 * 32 * 8 * 2 : (prec == P_BF16 ? 32.0 * 32 * 16 * 2 : 32.0 * 32 * 32 * 2);
+    const double ops = (double)ncu * 4 * 16 * (double)iters * per;
+    return ops / (ms * 1e-3) / 1e12;
+}
+
 int cpmi_dbg_mfma_probe(int precision, const void *A, const void *B, float *C, void *stream)
 {
     if (precision < 1 || precision > 3 || !A || !B || !C) return CPMI_ERR_ARG;

@@ -194,6 +194,7 @@ void launch_emit_pairs(const uint64_t *keys, const double *vals, int64_t m, int6
                        hipStream_t st);
 
 // Debug: one 32x32 MFMA block through the screen's fragment path.
+void launch_mfma_peak(int prec, int iters, int grid, float *out, hipStream_t st);
 void launch_mfma_probe(int prec, const void *A, const void *B, float *C, hipStream_t st);
 
 }  // namespace cpmi

@@ -292,6 +292,44 @@ __global__ void mfma_probe_kernel(const unsigned char *A, const unsigned char *B
     }
 }
 
+// Sustained matrix-core rate: every wave keeps 16 independent accumulations
+// (the screen's instruction and register budget: 256 accumulator registers)
+// busy for `iters` rounds with operands held in registers, so no memory
+// traffic limits it; one store per lane at the end keeps the work alive.
+template <int PREC>
+__global__ __launch_bounds__(256, 1) void mfma_peak_kernel(int iters, float *out)
+{
+    using AccT = typename Acc<PREC>::T;
+    const int lane = threadIdx.x & 63;
+    // small non-zero operands (varying by lane) that keep the sums finite
+    const uint32_t pat = PREC == P_I8 ? 0x01020301u * (uint32_t)(1 + (lane & 3))
+                                      : (PREC == P_BF16 ? 0x3a003a00u + (uint32_t)lane * 0x00010001u
+                                                        : 0x3a000000u + (uint32_t)lane);
+    const u32x4 a = {pat, pat ^ 0x00100010u, pat, pat ^ 0x00200020u};
+    const u32x4 b0 = {pat ^ 0x00300030u, pat, pat ^ 0x00100010u, pat};
+    const u32x4 b1 = {pat, pat ^ 0x00200020u, pat, pat ^ 0x00300030u};
+    AccT acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = AccT{};
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) mma<PREC>(acc[q], a, (q & 1) ? b1 : b0);
+    }
+    float sum = 0.f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) sum += (float)acc[q][r];
+    out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = sum;
+}
+
+void launch_mfma_peak(int prec, int iters, int grid, float *out, hipStream_t st)
+{
+    if (prec == P_F32) hipLaunchKernelGGL(mfma_peak_kernel<P_F32>, dim3(grid), dim3(256), 0, st, iters, out);
+    else if (prec == P_BF16) hipLaunchKernelGGL(mfma_peak_kernel<P_BF16>, dim3(grid), dim3(256), 0, st, iters, out);
+    else hipLaunchKernelGGL(mfma_peak_kernel<P_I8>, dim3(grid), dim3(256), 0, st, iters, out);
+}
+
 void launch_mfma_probe(int prec, const void *A, const void *B, float *C, hipStream_t st)
 {
     const unsigned char *a = (const unsigned char *)A, *b = (const unsigned char *)B;

@@ -441,3 +441,18 @@ def test_tile_bound_holds_for_every_pair_of_random_blocks(lib, seed):
     assert 0.0 <= lb <= dmin
     if seed != 0:
         assert lb > 1.0
+
+
+def test_headers_compile_and_link_as_c99(tmp_path):
+    """The boundary is plain C: the public headers compile with a C99 compiler
+    (warnings as errors) and a C program links against libcpmi.so and gets
+    the argument errors back without a GPU."""
+    import subprocess
+    import paper_1407_5609_amd as cp
+    lib = cp.library_path()
+    exe = str(tmp_path / "c_consumer")
+    cmd = ["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic", "-I", os.path.join(ROOT, "include"),
+           os.path.join(ROOT, "tests", "c_consumer.c"), lib, f"-Wl,-rpath,{os.path.dirname(lib)}", "-o", exe]
+    subprocess.run(cmd, check=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", (r.stdout, r.stderr)

@@ -522,3 +522,13 @@ def test_pruning_arguments(ctx):
         with pytest.raises(cp.CpmiError):
             ctx.set_pruning(q, f)
     ctx.set_pruning(0)
+
+
+@pytest.mark.parametrize("prec,published", [("bf16", 2500.0), ("f32", 157.3), ("i8", 5000.0)])
+def test_sustained_matrix_core_rate_is_below_the_published_peak(torch_dev, prec, published):
+    """The rate probe reported beside the published peak: positive, a sizeable
+    share of the datasheet figure, never above it."""
+    import paper_1407_5609_amd as cp
+    rate, ms = cp.dbg_mfma_peak(prec, iters=2000)
+    print(prec, "sustained", round(rate, 1), "of", published, "in", round(ms, 3), "ms")
+    assert ms > 0 and 0.2 * published < rate <= 1.02 * published
