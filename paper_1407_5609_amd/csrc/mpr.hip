@@ -98,7 +98,7 @@ __global__ __launch_bounds__(64) void ref_windows_kernel(const float *T, int64_t
 // same across a wave and come in through scalar loads. Mean and sigma here
 // are not the builder's canonical ones: the distances only feed the pruning
 // test, whose margin covers their rounding.
-template <int QM>
+template <int QM, bool EXACT>
 __global__ __launch_bounds__(256) void ref_dist_windows_kernel(const float *T, int64_t N, int64_t ell,
                                                                const double *rz_, int q, double *D)
 {
@@ -133,23 +133,40 @@ __global__ __launch_bounds__(256) void ref_dist_windows_kernel(const float *T, i
     }
     const double sg = sqrt(total(v2) / (double)ell);
     const double inv = sg > 0.0 ? 1.0 / sg : 0.0;
+    // reference row of accumulator k: k itself when QM == q, else clamped (the
+    // surplus accumulators repeat the last reference and are not stored), so
+    // that no branch on q separates the scalar loads of a group of columns
+    const __attribute__((address_space(4))) double *rk[QM];
+#pragma unroll
+    for (int k = 0; k < QM; ++k) rk[k] = rz + (int64_t)(EXACT ? k : min(k, q - 1)) * ell;
     double acc[QM];
 #pragma unroll
     for (int k = 0; k < QM; ++k) acc[k] = 0.0;
-#pragma unroll 4
-    for (int64_t c = c0; c < c1; ++c) {
-        const double xv = ((double)x[c] - m) * inv;
+    int64_t c = c0;
+    for (; c + 4 <= c1; c += 4) {
+        double xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = ((double)x[c + u] - m) * inv;
 #pragma unroll
         for (int k = 0; k < QM; ++k) {
-            if (k < q) {
-                const double t = rz[(int64_t)k * ell + c] - xv;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double t = rk[k][c + u] - xv[u];
                 acc[k] = fma(t, t, acc[k]);
             }
         }
     }
+    for (; c < c1; ++c) {
+        const double xv = ((double)x[c] - m) * inv;
+#pragma unroll
+        for (int k = 0; k < QM; ++k) {
+            const double t = rk[k][c] - xv;
+            acc[k] = fma(t, t, acc[k]);
+        }
+    }
 #pragma unroll
     for (int k = 0; k < QM; ++k) {
-        if (k < q) {
+        if (EXACT || k < q) {
             const double v = total(acc[k]);
             if (wave == 0 && w0 + lane < N) D[(int64_t)k * N + w0 + lane] = sqrt(v);
         }
@@ -224,9 +241,16 @@ void launch_ref_dist_windows(const float *T, int64_t N, int64_t ell, const int32
 {
     hipLaunchKernelGGL(ref_windows_kernel, dim3((unsigned)q), dim3(64), 0, st, T, ell, refs, f, rz);
     const dim3 g((unsigned)((N + 63) / 64)), b(256);
-    if (q <= 4) hipLaunchKernelGGL((ref_dist_windows_kernel<4>), g, b, 0, st, T, N, ell, rz, q, D);
-    else if (q <= 12) hipLaunchKernelGGL((ref_dist_windows_kernel<12>), g, b, 0, st, T, N, ell, rz, q, D);
-    else hipLaunchKernelGGL((ref_dist_windows_kernel<32>), g, b, 0, st, T, N, ell, rz, q, D);
+    switch (q) {
+#define CPMI_RDW(Q) \
+    case Q: hipLaunchKernelGGL((ref_dist_windows_kernel<Q, true>), g, b, 0, st, T, N, ell, rz, q, D); break;
+        CPMI_RDW(1) CPMI_RDW(2) CPMI_RDW(3) CPMI_RDW(4) CPMI_RDW(5) CPMI_RDW(6) CPMI_RDW(7) CPMI_RDW(8)
+        CPMI_RDW(9) CPMI_RDW(10) CPMI_RDW(11) CPMI_RDW(12)
+#undef CPMI_RDW
+    default:
+        if (q <= 16) hipLaunchKernelGGL((ref_dist_windows_kernel<16, false>), g, b, 0, st, T, N, ell, rz, q, D);
+        else hipLaunchKernelGGL((ref_dist_windows_kernel<32, false>), g, b, 0, st, T, N, ell, rz, q, D);
+    }
 }
 
 void launch_perm_finish(int32_t *perm, int32_t *iperm, int64_t n, int64_t npad, hipStream_t st)

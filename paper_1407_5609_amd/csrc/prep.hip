@@ -280,8 +280,8 @@ void launch_prep_points(const void *pts, int dtype, int64_t n, int64_t d, int64_
 // sequential sums). The block's stretch of the series (64 + ell - 1 values,
 // ell <= 8192) is staged in LDS once. Pass A (one thread per window, the
 // first wave): canonical mean and sigma, sequential in k. Pass B (one wave
-// per window, lanes across k): normalised values, screen operand and row
-// scalars.
+// per window, four consecutive k per lane): normalised values, screen
+// operand and row scalars.
 // ---------------------------------------------------------------------------
 template <int PREC>
 __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs, int64_t njobs, int tile)
@@ -370,34 +370,53 @@ __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs,
         const bool real = w < N && sh_sg[q] > 0.0;
         // screen row of window w (a permutation of the windows, or w itself)
         const int64_t row = (J.iperm && w < N) ? (int64_t)J.iperm[w] : w;
-        const double mu = sh_mu[q], sg = sh_sg[q];
+        const double mu = sh_mu[q];
+        // one correctly rounded reciprocal per window: the operand's FP64
+        // values (T - mu) * inv are within 2^-51 (relative) of the canonical
+        // quotients (T - mu) / sigma, which the row terms below absorb
+        const double inv = real ? 1.0 / sh_sg[q] : 0.0;
         double s = 0.0, t2 = 0.0, r2 = 0.0;
-        // (two iterations in flight: the divisions are long dependent chains)
+        // four consecutive elements per lane (never across a 64-byte slice)
 #pragma unroll 2
-        for (int64_t k = lane; k < J.kpad; k += 64) {
-            double xh = 0.0;
-            if (real && k < ell) xh = ((double)sh_T[q + k] - mu) / sg;   // T[w + k]
-            float vt;
+        for (int64_t k0 = 4 * lane; k0 < J.kpad; k0 += 256) {
+            double xh[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                xh[u] = (real && k0 + u < ell) ? ((double)sh_T[q + k0 + u] - mu) * inv : 0.0;   // T[w + k]
+            float vt[4];
             if constexpr (PREC == P_BF16) {
-                const unsigned short h = f32_to_bf16_rne((float)xh);
-                ((unsigned short *)J.xs)[xs_index(row, k, J.kpad, 2, tile)] = h;
-                vt = bf16_to_f32(h);
+                unsigned short h[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    h[u] = f32_to_bf16_rne((float)xh[u]);
+                    vt[u] = bf16_to_f32(h[u]);
+                }
+                *(uint2 *)((unsigned short *)J.xs + xs_index(row, k0, J.kpad, 2, tile)) =
+                    make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
             } else {
-                vt = (float)xh;
-                ((float *)J.xs)[xs_index(row, k, J.kpad, 4, tile)] = vt;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) vt[u] = (float)xh[u];
+                *(float4 *)((float *)J.xs + xs_index(row, k0, J.kpad, 4, tile)) = make_float4(vt[0], vt[1], vt[2], vt[3]);
             }
-            const double vtd = (double)vt;
-            s = fma(xh, xh, s);
-            t2 = fma(vtd, vtd, t2);
-            const double df = xh - vtd;
-            r2 = fma(df, df, r2);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double vtd = (double)vt[u];
+                s = fma(xh[u], xh[u], s);
+                t2 = fma(vtd, vtd, t2);
+                const double df = xh[u] - vtd;
+                r2 = fma(df, df, r2);
+            }
         }
         s = wave_sum(s);
         t2 = wave_sum(t2);
         r2 = wave_sum(r2);
         if (lane == 0) {
             ((float *)J.shat)[row] = (float)s;
-            const float4 v = make_float4(f32_up(s), up_f32(sqrt(s)), up_f32(sqrt(t2)), up_f32(sqrt(r2)));
+            // r: distance of the operand from the canonical window, widened by
+            // 2^-50 ||x|| for the reciprocal's rounding above (the norms
+            // carry the 2^-40 widening of up_f32, which covers it)
+            const float4 v = make_float4(f32_up(s), up_f32(sqrt(s)), up_f32(sqrt(t2)),
+                                         up_f32(sqrt(r2) + 0x1p-50 * sqrt(s)));
             if (J.iperm) {
                 // windows in reference order land in any tile block: per-row
                 // terms, reduced per block afterwards (launch_block_max)
