@@ -22,10 +22,12 @@ namespace cpmi {
 
 __device__ __forceinline__ unsigned short f32_to_bf16_rne(float x)
 {
-    unsigned int u = __float_as_uint(x);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
+    // branch-free: round to nearest even, except NaN (kept a NaN, quiet if
+    // its payload lies in the dropped bits); infinities round to themselves
+    const unsigned int u = __float_as_uint(x);
+    const unsigned int r = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    const unsigned int nan = (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
+    return (unsigned short)(((u & 0x7fffffffu) > 0x7f800000u) ? nan : r);
 }
 
 __device__ __forceinline__ float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
@@ -275,89 +277,109 @@ void launch_prep_points(const void *pts, int dtype, int64_t n, int64_t d, int64_
 }
 
 // ---------------------------------------------------------------------------
-// series: a block of 256 threads builds SERIES_WPB (64) consecutive windows
-// of one job (small blocks: many waves in flight to cover the latency of the
-// sequential sums). The block's stretch of the series (64 + ell - 1 values,
-// ell <= 8192) is staged in LDS once. Pass A (one thread per window, the
-// first wave): canonical mean and sigma, sequential in k. Pass B (one wave
-// per window, four consecutive k per lane): normalised values, screen
-// operand and row scalars.
+// series, in two kernels. Statistics: a block of 256 threads takes 256
+// consecutive windows of one job (four builder blocks; a job holds a whole
+// number of them), a thread per window, with the stretch of the series they
+// cover (256 + ell - 1 values, ell <= 8192) staged in LDS: canonical mean and
+// sigma, each a sequential sum in k. Every window's chain of dependent
+// additions runs at once, in all four waves. Operand: a block of 256 threads
+// builds SERIES_WPB (64) consecutive windows, one wave per window and four
+// consecutive k per lane: normalised values, screen operand and row scalars.
 // ---------------------------------------------------------------------------
+constexpr int STATS_W = 4 * SERIES_WPB;
+
+// Job of builder block bid: the last job with blk_base <= bid.
+__device__ __forceinline__ int64_t job_of(const SeriesJob *jobs, int64_t njobs, int64_t bid)
+{
+    int64_t lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].blk_base <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void series_stats_kernel(const SeriesJob *jobs, int64_t njobs)
+{
+    __shared__ float sh_T[STATS_W + SERIES_MAX_ELL];
+    const int64_t bid = (int64_t)blockIdx.x * (STATS_W / SERIES_WPB);
+    const SeriesJob J = jobs[job_of(jobs, njobs, bid)];
+    const int64_t N = J.len - J.ell + 1;
+    const int64_t w0 = (bid - J.blk_base) * SERIES_WPB;
+    const int tid = threadIdx.x;
+    const int64_t ell = J.ell;
+    const int64_t span = w0 < N ? min<int64_t>(STATS_W + ell - 1, J.len - w0) : 0;
+    for (int64_t k = tid; k < span; k += 256) sh_T[k] = J.T[w0 + k];
+    __syncthreads();
+    const int64_t w = w0 + tid;
+    if (w >= N) return;
+    // sequential in k; the LDS reads of eight terms are issued before their
+    // additions
+    const float *tw = sh_T + tid;   // T[w + k] = tw[k]
+    double s = 0.0;
+    bool bad = false;
+    int64_t k = 0;
+    for (; k + 8 <= ell; k += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = tw[k + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            bad |= !isfinite(v[u]);
+            s += (double)v[u];
+        }
+    }
+    for (; k < ell; ++k) {
+        bad |= !isfinite(tw[k]);
+        s += (double)tw[k];
+    }
+    const double mu = s / (double)ell;
+    double v2 = 0.0;
+    for (k = 0; k + 8 <= ell; k += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = tw[k + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double e = (double)v[u] - mu;
+            v2 = fma(e, e, v2);
+        }
+    }
+    for (; k < ell; ++k) {
+        const double e = (double)tw[k] - mu;
+        v2 = fma(e, e, v2);
+    }
+    const double sg = sqrt(v2 / (double)ell);
+    J.mu[w] = mu;
+    J.sigma[w] = sg;
+    unsigned int f = 0;
+    if (bad) f |= F_NONFINITE;
+    if (!(sg > 0.0)) f |= F_DEGENERATE;
+    if (f) atomicOr(J.flags, f);
+}
+
 template <int PREC>
 __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs, int64_t njobs, int tile)
 {
     __shared__ double sh_mu[SERIES_WPB];
     __shared__ double sh_sg[SERIES_WPB];
     __shared__ float sh_T[SERIES_WPB + SERIES_MAX_ELL];
-    // job of this block: last job with blk_base <= blockIdx.x
-    int64_t lo = 0, hi = njobs - 1;
     const int64_t bid = blockIdx.x;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].blk_base <= bid) lo = mid;
-        else hi = mid - 1;
-    }
-    const SeriesJob J = jobs[lo];
+    const SeriesJob J = jobs[job_of(jobs, njobs, bid)];
     const int64_t N = J.len - J.ell + 1;          // windows
     const int64_t w0 = (bid - J.blk_base) * SERIES_WPB;  // first window of the block
     const int tid = threadIdx.x;
     const int64_t ell = J.ell;
-    // values T[w0 .. w0 + span) : every window of the block that exists
+    // values T[w0 .. w0 + span) : every window of the block that exists; zeros
+    // after them up to the last element a lane reads (SERIES_WPB + kpad - 1 <=
+    // SERIES_WPB + SERIES_MAX_ELL), so that no value read below is left unset
     const int64_t span = w0 < N ? min<int64_t>(SERIES_WPB + ell - 1, J.len - w0) : 0;
-    for (int64_t k = tid; k < span; k += 256) sh_T[k] = J.T[w0 + k];
-    __syncthreads();
-
+    for (int64_t k = tid; k < SERIES_WPB + J.kpad - 1; k += 256) sh_T[k] = k < span ? J.T[w0 + k] : 0.0f;
     if (tid < SERIES_WPB) {
         const int64_t w = w0 + tid;
-        double mu = 0.0, sg = 0.0;
-        if (w < N) {
-            // sequential in k; the LDS reads of eight terms are issued
-            // before their additions
-            const float *tw = sh_T + tid;   // T[w + k] = tw[k]
-            double s = 0.0;
-            bool bad = false;
-            int64_t k = 0;
-            for (; k + 8 <= ell; k += 8) {
-                float v[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = tw[k + u];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    bad |= !isfinite(v[u]);
-                    s += (double)v[u];
-                }
-            }
-            for (; k < ell; ++k) {
-                bad |= !isfinite(tw[k]);
-                s += (double)tw[k];
-            }
-            mu = s / (double)ell;
-            double v2 = 0.0;
-            for (k = 0; k + 8 <= ell; k += 8) {
-                float v[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = tw[k + u];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const double e = (double)v[u] - mu;
-                    v2 = fma(e, e, v2);
-                }
-            }
-            for (; k < ell; ++k) {
-                const double e = (double)tw[k] - mu;
-                v2 = fma(e, e, v2);
-            }
-            v2 = v2 / (double)ell;
-            sg = sqrt(v2);
-            J.mu[w] = mu;
-            J.sigma[w] = sg;
-            unsigned int f = 0;
-            if (bad) f |= F_NONFINITE;
-            if (!(sg > 0.0)) f |= F_DEGENERATE;
-            if (f) atomicOr(J.flags, f);
-        }
-        sh_mu[tid] = mu;
-        sh_sg[tid] = sg;
+        sh_mu[tid] = w < N ? J.mu[w] : 0.0;
+        sh_sg[tid] = w < N ? J.sigma[w] : 0.0;
     }
     __syncthreads();
 
@@ -377,12 +399,19 @@ __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs,
         const double inv = real ? 1.0 / sh_sg[q] : 0.0;
         double s = 0.0, t2 = 0.0, r2 = 0.0;
         // four consecutive elements per lane (never across a 64-byte slice)
+        const int ell32 = (int)ell;   // <= SERIES_MAX_ELL: 32-bit element indices
 #pragma unroll 2
-        for (int64_t k0 = 4 * lane; k0 < J.kpad; k0 += 256) {
+        for (int k0 = 4 * lane; k0 < J.kpad; k0 += 256) {
             double xh[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                xh[u] = (real && k0 + u < ell) ? ((double)sh_T[q + k0 + u] - mu) * inv : 0.0;   // T[w + k]
+            for (int u = 0; u < 4; ++u) {
+                // T[w + k], read for every lane and k (past the window the
+                // value is dropped), so that the four reads go out together; a
+                // window that is not real has inv = 0, hence xh = 0
+                const float t = sh_T[q + k0 + u];
+                const double v = ((double)t - mu) * inv;
+                xh[u] = (k0 + u < ell32) ? v : 0.0;
+            }
             float vt[4];
             if constexpr (PREC == P_BF16) {
                 unsigned short h[4];
@@ -488,6 +517,10 @@ void launch_prep_series(const SeriesJob *jobs, int64_t njobs, int64_t total_bloc
                         hipStream_t st)
 {
     if (total_blocks <= 0) return;
+    // jobs hold whole 256-window blocks; a statistics block past the last
+    // window has nothing to do
+    const int64_t sb = (total_blocks + STATS_W / SERIES_WPB - 1) / (STATS_W / SERIES_WPB);
+    hipLaunchKernelGGL(series_stats_kernel, dim3((unsigned)sb), dim3(256), 0, st, jobs, njobs);
     if (prec == P_BF16)
         hipLaunchKernelGGL(prep_series_kernel<P_BF16>, dim3((unsigned)total_blocks), dim3(256), 0, st, jobs, njobs,
                            tile);
