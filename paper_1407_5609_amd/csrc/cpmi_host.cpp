@@ -790,18 +790,6 @@ double tile_lower_bound(const double *loI, const double *hiI, const double *loJ,
     return lb;
 }
 
-// Whether tile_lower_bound(...) > T, stopping at the first reference that
-// shows it.
-bool tile_bound_exceeds(const double *loI, const double *hiI, const double *loJ, const double *hiJ, int q, double T)
-{
-    for (int k = 0; k < q; ++k) {
-        double g = std::max(loJ[k] - hiI[k], loI[k] - hiJ[k]);
-        g -= 0x1p-34 * std::max(std::fabs(hiI[k]), std::fabs(hiJ[k]));
-        if (g > T) return true;
-    }
-    return false;
-}
-
 uint64_t splitmix64(uint64_t x)
 {
     x += 0x9e3779b97f4a7c15ull;
@@ -868,8 +856,23 @@ void pruned_tiles(const HostProb &h, int tile, int q, const std::vector<double> 
                   double T, int64_t band, std::vector<uint64_t> &tl, int64_t &nfull, int64_t &npruned)
 {
     const int64_t nT = (h.n + tile - 1) / tile;
+    // intervals widened by the rounding margin of tile_lower_bound, once per
+    // block: [lo - m, hi + m], m = 2^-34 |hi|. A gap between widened intervals
+    // subtracts mI + mJ >= 2^-34 max(|hiI|, |hiJ|), so a tile dropped here has
+    // tile_lower_bound > T (the test stops at the first reference that shows
+    // it)
+    std::vector<double> lw((size_t)nT * q), hw((size_t)nT * q);
+    for (size_t k = 0; k < lw.size(); ++k) {
+        const double m = 0x1p-34 * std::fabs(hi[k]);
+        lw[k] = lo[k] - m;
+        hw[k] = hi[k] + m;
+    }
     auto exceeds = [&](int64_t I, int64_t J) {
-        return T < 0.0 || tile_bound_exceeds(&lo[I * q], &hi[I * q], &lo[J * q], &hi[J * q], q, T);
+        if (T < 0.0) return true;
+        const double *lI = &lw[I * q], *hI = &hw[I * q], *lJ = &lw[J * q], *hJ = &hw[J * q];
+        for (int k = 0; k < q; ++k)
+            if ((lJ[k] - hI[k] > T) | (lI[k] - hJ[k] > T)) return true;
+        return false;
     };
     // the rows are ordered by reference 0, so its gap only grows with J: jend[I]
     // is the first block column whose reference-0 gap alone exceeds T
@@ -878,8 +881,7 @@ void pruned_tiles(const HostProb &h, int tile, int q, const std::vector<double> 
         int64_t a = I, b = nT;
         while (a < b) {
             const int64_t m = (a + b) / 2;
-            const double g = lo[m * q] - hi[I * q] - 0x1p-34 * std::max(std::fabs(hi[I * q]), std::fabs(hi[m * q]));
-            if (g > T) b = m;
+            if (lw[m * q] - hw[I * q] > T) b = m;
             else a = m + 1;
         }
         jend[I] = band >= 0 ? std::min(a, I + band + 1) : a;
