@@ -147,11 +147,12 @@ def _bf16(x32):
     return u.astype(np.uint32).view(np.float32)
 
 
-def _row_stats(Xc, Xt):
-    """(s^, a, at, r) per row as the library defines them (upper bounds)."""
+def _row_stats(Xc, Xt, widen=0.0):
+    """(s^, a, at, r) per row as the library defines them (upper bounds); r
+    widened by widen * ||Xc|| (the window builder's reciprocal form)."""
     s = np.sum(Xc * Xc, axis=1)
     at = np.sqrt(np.sum(Xt.astype(np.float64) ** 2, axis=1))
-    r = np.sqrt(np.sum((Xc - Xt.astype(np.float64)) ** 2, axis=1))
+    r = np.sqrt(np.sum((Xc - Xt.astype(np.float64)) ** 2, axis=1)) + widen * np.sqrt(s)
     up = lambda v: np.nextafter((v * (1 + 2.0 ** -40)).astype(np.float32), np.float32(np.inf))
     return s.astype(np.float32), up(np.sqrt(s)), up(at), up(r)
 
@@ -203,7 +204,8 @@ def _canon(Xc):
 
 
 @pytest.mark.parametrize("form", [0, 1])
-@pytest.mark.parametrize("kind", ["points_f32", "points_bf16", "mixture_bf16", "windows_f32", "windows_bf16"])
+@pytest.mark.parametrize("kind", ["points_f32", "points_bf16", "mixture_bf16", "windows_f32", "windows_bf16",
+                                  "windows_recip_f32", "windows_recip_bf16"])
 def test_bound_holds_on_emulated_screens_and_has_teeth(lib, kind, form):
     rng = np.random.default_rng(abs(hash(kind)) % 1000)
     if kind.startswith("points"):
@@ -218,13 +220,23 @@ def test_bound_holds_on_emulated_screens_and_has_teeth(lib, kind, form):
     else:
         T = W.random_walk(rng, 600)
         W.plant_motif(rng, T, 128)
-        Xc, _, _ = oracle.znorm(T, 128)
+        Xc, mu, sg = oracle.znorm(T, 128)
         Xc = Xc[:160]
         canon_src = Xc
+    widen = 0.0
+    Xop = Xc
+    if "recip" in kind:
+        # the builder's operand values: (T - mu) * (1 / sigma), one rounded
+        # reciprocal per window, r widened by 2^-50 ||x'||; the bound must hold
+        # against the canonical quotients all the same
+        Wv = np.lib.stride_tricks.sliding_window_view(T.astype(np.float64), 128)[:160]
+        Xop = (Wv - mu[:160, None]) * (1.0 / sg[:160])[:, None]
+        assert not np.array_equal(Xop, Xc)          # the two forms do differ in the last bits
+        widen = 2.0 ** -50
     prec = 1 if kind.endswith("f32") else 2
-    X32 = Xc.astype(np.float32)
+    X32 = Xop.astype(np.float32)
     Xt = X32 if prec == 1 else _bf16(X32)
-    shat, a, at, r = _row_stats(Xc, Xt)
+    shat, a, at, r = _row_stats(Xop, Xt, widen)
     D = _emulated_screen(Xt, shat) if form == 0 else _emulated_folded_screen(Xt, shat, prec)
     d = Xc.shape[1]
     kpad = -(-d // (32 if prec == 1 else 64)) * (32 if prec == 1 else 64)
