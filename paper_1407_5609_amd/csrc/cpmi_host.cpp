@@ -104,6 +104,10 @@ struct cpmi_ctx {
     double prune_f = 10.0;
     uint64_t prune_seed = 0;
     DevBuf mD, mperm, miperm, mlo, mhi, mrefs, msort, mrowstat;
+    // the block intervals read back (pinned; valid once evlohi has completed)
+    double *plohi = nullptr;
+    size_t plohi_cap = 0;
+    hipEvent_t evlohi = nullptr;
     // string problems: encoded int8 rows and the encoder's flag word
     DevBuf mZ, mflag;
     // light-bulb bucketing: keys and rows (in, out), sort scratch, columns,
@@ -387,8 +391,9 @@ struct RunOut {
 // are still in the workspace.
 int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool want_cpp, bool want_frnn,
                hipStream_t st, bool batch_graph, RunOut &ro, const std::vector<uint64_t> *forced = nullptr,
-               int64_t forced_nfull = 0, bool reuse_operand = false)
+               int64_t forced_nfull = 0, bool reuse_operand = false, const std::function<void()> &while_busy = {})
 {
+    bool busy_done = false;
     const int64_t np = (int64_t)hp.size();
     const int esz = elem_bytes(prec);
     // ---- workspace layout
@@ -640,6 +645,11 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         HIPCHK(c, hipMemcpyAsync((char *)c->pinned + np * sizeof(ResDev), c->cnt.p, NCNT * 4, hipMemcpyDeviceToHost,
                                  st));
         HIPCHK(c, hipEventRecord(c->ev1, st));
+        // host work that overlaps the search (once, not on reruns)
+        if (while_busy && !busy_done) {
+            busy_done = true;
+            while_busy();
+        }
         HIPCHK(c, hipStreamSynchronize(st));
         float ms = 0.f;
         hipEventElapsedTime(&ms, c->ev0, c->ev1);
@@ -803,9 +813,9 @@ uint64_t splitmix64(uint64_t x)
 // projected reference (h.perm; for windows also its inverse, h.iperm, padded
 // to whole 256-row blocks) and bring back to the host, per block of `tile`
 // rows in that order and per reference, the interval of distances (lo, hi:
-// nT x q). Synchronises once.
-int prune_prepare(cpmi_ctx *c, HostProb &h, int tile, hipStream_t st, std::vector<double> &lo,
-                  std::vector<double> &hi)
+// nT x q each, one after the other in c->plohi). Does not synchronise: the
+// intervals are there once c->evlohi has completed (prune_fetch).
+int prune_prepare(cpmi_ctx *c, HostProb &h, int tile, hipStream_t st)
 {
     const int q = c->prune_q;
     const int64_t n = h.n;
@@ -839,13 +849,29 @@ int prune_prepare(cpmi_ctx *c, HostProb &h, int tile, hipStream_t st, std::vecto
     if (h.motif) launch_perm_finish(perm, (int32_t *)c->miperm.p, n, npad, st);
     launch_block_range(D, n, q, perm, tile, nT, (double *)c->mlo.p, (double *)c->mhi.p, st);
     HIPCHK(c, hipGetLastError());
-    lo.assign((size_t)nT * q, 0.0);
-    hi.assign((size_t)nT * q, 0.0);
-    HIPCHK(c, hipMemcpyAsync(lo.data(), c->mlo.p, lo.size() * 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipMemcpyAsync(hi.data(), c->mhi.p, hi.size() * 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipStreamSynchronize(st));
+    const size_t nb = (size_t)nT * q * 8;
+    if (c->plohi_cap < 2 * nb) {
+        if (c->plohi) hipHostFree(c->plohi);
+        c->plohi = nullptr;
+        c->plohi_cap = 0;
+        HIPCHK(c, hipHostMalloc((void **)&c->plohi, 2 * nb, hipHostMallocDefault));
+        c->plohi_cap = 2 * nb;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->plohi, c->mlo.p, nb, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipMemcpyAsync((char *)c->plohi + nb, c->mhi.p, nb, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipEventRecord(c->evlohi, st));
     h.perm = perm;
     if (h.motif) h.iperm = (const int32_t *)c->miperm.p;
+    return CPMI_OK;
+}
+
+// The block intervals of the last prune_prepare, once they have landed.
+int prune_fetch(cpmi_ctx *c, int64_t nT, int q, std::vector<double> &lo, std::vector<double> &hi)
+{
+    HIPCHK(c, hipEventSynchronize(c->evlohi));
+    const size_t m = (size_t)nT * q;
+    lo.assign(c->plohi, c->plohi + m);
+    hi.assign(c->plohi + m, c->plohi + 2 * m);
     return CPMI_OK;
 }
 
@@ -903,22 +929,48 @@ void pruned_tiles(const HostProb &h, int tile, int q, const std::vector<double> 
 int pruned_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool want_cpp, bool want_frnn,
                   hipStream_t st, RunOut &ro)
 {
+    const int q = c->prune_q;
+    const int64_t nT = (hp[0].n + tile - 1) / tile;
     std::vector<double> lo, hi;
     int rc;
-    if ((rc = prune_prepare(c, hp[0], tile, st, lo, hi))) return rc;
-    std::vector<uint64_t> tl;
-    int64_t nfull = 0, npruned = 0;
+    if ((rc = prune_prepare(c, hp[0], tile, st))) return rc;
+    std::vector<uint64_t> tl, tlr;
+    int64_t nfull = 0, npruned = 0, nfull_r = 0, npruned_r = 0;
     const double inf = std::numeric_limits<double>::infinity();
-    double thr2 = want_frnn ? hp[0].r2 : 0.0;
+    const double r2 = want_frnn ? hp[0].r2 : 0.0;
+    double thr2 = r2;
+    bool have_r = false;
     if (want_cpp) {
-        pruned_tiles(hp[0], tile, c->prune_q, lo, hi, inf, 1, tl, nfull, npruned);
+        // the band list needs no intervals (with T = inf no tile is dropped)
+        const std::vector<double> none((size_t)nT * q, 0.0);
+        pruned_tiles(hp[0], tile, q, none, none, inf, 1, tl, nfull, npruned);
+        // while the band search runs: fetch the intervals and, with a radius,
+        // build the list for T = R, the final one unless the band's least
+        // squared distance exceeds R^2
+        int frc = CPMI_OK;
+        auto busy = [&]() {
+            frc = prune_fetch(c, nT, q, lo, hi);
+            if (frc == CPMI_OK && want_frnn) {
+                pruned_tiles(hp[0], tile, q, lo, hi, std::sqrt(r2) * (1.0 + 0x1p-30), -1, tlr, nfull_r, npruned_r);
+                have_r = true;
+            }
+        };
         RunOut band;
-        if ((rc = run_search(c, hp, prec, tile, true, false, st, false, band, &tl, nfull))) return rc;
+        if ((rc = run_search(c, hp, prec, tile, true, false, st, false, band, &tl, nfull, false, busy))) return rc;
+        if (frc) return frc;
         if ((rc = flags_error(c, band.res[0].flags))) return rc;
         const double u = __builtin_bit_cast(double, (uint64_t)band.res[0].best_d2);
         thr2 = std::max(thr2, std::isfinite(u) ? u : inf);
+    } else if ((rc = prune_fetch(c, nT, q, lo, hi))) {
+        return rc;
     }
-    pruned_tiles(hp[0], tile, c->prune_q, lo, hi, std::sqrt(thr2) * (1.0 + 0x1p-30), -1, tl, nfull, npruned);
+    if (have_r && thr2 == r2) {
+        tl.swap(tlr);
+        nfull = nfull_r;
+        npruned = npruned_r;
+    } else {
+        pruned_tiles(hp[0], tile, q, lo, hi, std::sqrt(thr2) * (1.0 + 0x1p-30), -1, tl, nfull, npruned);
+    }
     // the band search (if any) left the screen operand in place
     if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro, &tl, nfull, want_cpp))) return rc;
     c->stats.tiles_pruned = npruned;
@@ -982,6 +1034,7 @@ int cpmi_create(cpmi_ctx **out, int device, const char *tune_cache_path)
     if (hipSetDevice(device) != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
         hipEventCreate(&c->ev1) != hipSuccess || hipEventCreate(&c->es0) != hipSuccess ||
         hipEventCreate(&c->es1) != hipSuccess ||
+        hipEventCreateWithFlags(&c->evlohi, hipEventDisableTiming) != hipSuccess ||
         hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return CPMI_ERR_HIP;
@@ -1007,6 +1060,8 @@ int cpmi_destroy(cpmi_ctx *c)
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
     if (c->pinned) hipHostFree(c->pinned);
+    if (c->plohi) hipHostFree(c->plohi);
+    if (c->evlohi) hipEventDestroy(c->evlohi);
     if (c->ev0) hipEventDestroy(c->ev0);
     if (c->ev1) hipEventDestroy(c->ev1);
     if (c->es0) hipEventDestroy(c->es0);
