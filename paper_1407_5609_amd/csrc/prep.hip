@@ -306,8 +306,10 @@ void launch_prep_points(const void *pts, int dtype, int64_t n, int64_t d, int64_
 // cover (256 + ell - 1 values, ell <= 8192) staged in LDS: canonical mean and
 // sigma, each a sequential sum in k. Every window's chain of dependent
 // additions runs at once, in all four waves. Operand: a block of 256 threads
-// builds SERIES_WPB (64) consecutive windows, one wave per window and four
-// consecutive k per lane: normalised values, screen operand and row scalars.
+// builds SERIES_WPB (64) consecutive windows, a lane per window and a quarter
+// of the elements per wave, in 16-byte chunks: normalised values, screen
+// operand and row scalars (the quarters' sums meet in LDS, no wave
+// reductions).
 // ---------------------------------------------------------------------------
 constexpr int STATS_W = 4 * SERIES_WPB;
 
@@ -385,9 +387,12 @@ __global__ __launch_bounds__(256) void series_stats_kernel(const SeriesJob *jobs
 template <int PREC>
 __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs, int64_t njobs, int tile)
 {
+    constexpr int ESZ = PREC == P_BF16 ? 2 : 4;
+    constexpr int CH = 16 / ESZ;   // elements per 16-byte store
     __shared__ double sh_mu[SERIES_WPB];
-    __shared__ double sh_sg[SERIES_WPB];
+    __shared__ double sh_inv[SERIES_WPB];
     __shared__ float sh_T[SERIES_WPB + SERIES_MAX_ELL];
+    __shared__ double sh_part[3][4][SERIES_WPB];
     const int64_t bid = blockIdx.x;
     const SeriesJob J = jobs[job_of(jobs, njobs, bid)];
     const int64_t N = J.len - J.ell + 1;          // windows
@@ -401,106 +406,94 @@ __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs,
     for (int64_t k = tid; k < SERIES_WPB + J.kpad - 1; k += 256) sh_T[k] = k < span ? J.T[w0 + k] : 0.0f;
     if (tid < SERIES_WPB) {
         const int64_t w = w0 + tid;
+        const double sg = w < N ? J.sigma[w] : 0.0;
         sh_mu[tid] = w < N ? J.mu[w] : 0.0;
-        sh_sg[tid] = w < N ? J.sigma[w] : 0.0;
+        // one correctly rounded reciprocal per window: the operand's FP64
+        // values (T - mu) * inv are within 2^-51 (relative) of the canonical
+        // quotients (T - mu) / sigma, which the row terms below absorb; a
+        // window that is not real has inv = 0, hence an operand row of zeros
+        sh_inv[tid] = sg > 0.0 ? 1.0 / sg : 0.0;
     }
     __syncthreads();
 
+    // lane l: window w0 + l (every block lies inside its job's npad rows);
+    // wave v: the quarter [v kpad/4, (v+1) kpad/4) of its elements (a whole
+    // number of 16-byte chunks, which never straddle a 64-byte slice)
     const int lane = tid & 63, wave = tid >> 6;
-    __shared__ float4 sh_bm[4];
-    float4 bmw = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int q = wave; q < SERIES_WPB; q += 4) {
-        const int64_t w = w0 + q;
-        if (w >= J.npad) break;
-        const bool real = w < N && sh_sg[q] > 0.0;
-        // screen row of window w (a permutation of the windows, or w itself)
-        const int64_t row = (J.iperm && w < N) ? (int64_t)J.iperm[w] : w;
-        const double mu = sh_mu[q];
-        // one correctly rounded reciprocal per window: the operand's FP64
-        // values (T - mu) * inv are within 2^-51 (relative) of the canonical
-        // quotients (T - mu) / sigma, which the row terms below absorb
-        const double inv = real ? 1.0 / sh_sg[q] : 0.0;
-        double s = 0.0, t2 = 0.0, r2 = 0.0;
-        // four consecutive elements per lane (never across a 64-byte slice)
-        const int ell32 = (int)ell;   // <= SERIES_MAX_ELL: 32-bit element indices
-#pragma unroll 2
-        for (int k0 = 4 * lane; k0 < J.kpad; k0 += 256) {
-            double xh[4];
+    const int64_t w = w0 + lane;
+    const int64_t row = (J.iperm && w < N) ? (int64_t)J.iperm[w] : w;
+    const double mu = sh_mu[lane], inv = sh_inv[lane];
+    const int ell32 = (int)ell;   // <= SERIES_MAX_ELL: 32-bit element indices
+    const int kq = J.kpad / 4;
+    const float *tw = sh_T + lane;   // T[w + k] = tw[k]
+    double s = 0.0, t2 = 0.0, r2 = 0.0;
+    for (int k0 = wave * kq; k0 < (wave + 1) * kq; k0 += CH) {
+        double xh[CH];
+        float vt[CH];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                // T[w + k], read for every lane and k (past the window the
-                // value is dropped), so that the four reads go out together; a
-                // window that is not real has inv = 0, hence xh = 0
-                const float t = sh_T[q + k0 + u];
-                const double v = ((double)t - mu) * inv;
-                xh[u] = (k0 + u < ell32) ? v : 0.0;
-            }
-            float vt[4];
-            if constexpr (PREC == P_BF16) {
-                unsigned short h[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    h[u] = f32_to_bf16_rne((float)xh[u]);
-                    vt[u] = bf16_to_f32(h[u]);
-                }
-                *(uint2 *)((unsigned short *)J.xs + xs_index(row, k0, J.kpad, 2, tile)) =
-                    make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16));
-            } else {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) vt[u] = (float)xh[u];
-                *(float4 *)((float *)J.xs + xs_index(row, k0, J.kpad, 4, tile)) = make_float4(vt[0], vt[1], vt[2], vt[3]);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const double vtd = (double)vt[u];
-                s = fma(xh[u], xh[u], s);
-                t2 = fma(vtd, vtd, t2);
-                const double df = xh[u] - vtd;
-                r2 = fma(df, df, r2);
-            }
+        for (int u = 0; u < CH; ++u) {
+            // read for every k (past the window the value is dropped)
+            const double v = ((double)tw[k0 + u] - mu) * inv;
+            xh[u] = (k0 + u < ell32) ? v : 0.0;
         }
-        s = wave_sum(s);
-        t2 = wave_sum(t2);
-        r2 = wave_sum(r2);
-        if (lane == 0) {
-            ((float *)J.shat)[row] = (float)s;
-            // r: distance of the operand from the canonical window, widened by
-            // 2^-50 ||x|| for the reciprocal's rounding above (the norms
-            // carry the 2^-40 widening of up_f32, which covers it)
-            const float4 v = make_float4(f32_up(s), up_f32(sqrt(s)), up_f32(sqrt(t2)),
-                                         up_f32(sqrt(r2) + 0x1p-50 * sqrt(s)));
-            if (J.iperm) {
-                // windows in reference order land in any tile block: per-row
-                // terms, reduced per block afterwards (launch_block_max)
-                J.rowstat[row] = v;
-            } else {
-                bmw.x = fmaxf(bmw.x, v.x);
-                bmw.y = fmaxf(bmw.y, v.y);
-                bmw.z = fmaxf(bmw.z, v.z);
-                bmw.w = fmaxf(bmw.w, v.w);
+        if constexpr (PREC == P_BF16) {
+            uint32_t h[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                h[u] = f32_to_bf16_rne((float)xh[u]);
+                vt[u] = bf16_to_f32((unsigned short)h[u]);
             }
+            *(uint4 *)((unsigned short *)J.xs + xs_index(row, k0, J.kpad, 2, tile)) =
+                make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+        } else {
+#pragma unroll
+            for (int u = 0; u < CH; ++u) vt[u] = (float)xh[u];
+            *(float4 *)((float *)J.xs + xs_index(row, k0, J.kpad, 4, tile)) = make_float4(vt[0], vt[1], vt[2], vt[3]);
         }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const double vtd = (double)vt[u];
+            s = fma(xh[u], xh[u], s);
+            t2 = fma(vtd, vtd, t2);
+            const double df = xh[u] - vtd;
+            r2 = fma(df, df, r2);
+        }
+    }
+    sh_part[0][wave][lane] = s;
+    sh_part[1][wave][lane] = t2;
+    sh_part[2][wave][lane] = r2;
+    __syncthreads();
+    if (wave != 0) return;
+    s = (sh_part[0][0][lane] + sh_part[0][1][lane]) + (sh_part[0][2][lane] + sh_part[0][3][lane]);
+    t2 = (sh_part[1][0][lane] + sh_part[1][1][lane]) + (sh_part[1][2][lane] + sh_part[1][3][lane]);
+    r2 = (sh_part[2][0][lane] + sh_part[2][1][lane]) + (sh_part[2][2][lane] + sh_part[2][3][lane]);
+    ((float *)J.shat)[row] = (float)s;
+    // r: distance of the operand from the canonical window, widened by
+    // 2^-50 ||x|| for the reciprocal's rounding (the norms carry the 2^-40
+    // widening of up_f32, which covers it)
+    float4 v = make_float4(f32_up(s), up_f32(sqrt(s)), up_f32(sqrt(t2)), up_f32(sqrt(r2) + 0x1p-50 * sqrt(s)));
+    if (J.iperm) {
+        // windows in reference order land in any tile block: per-row terms,
+        // reduced per block afterwards (launch_block_max)
+        J.rowstat[row] = v;
+        return;
     }
     // windows in position order: the block's SERIES_WPB rows lie in one tile
     // block; one set of atomics per work-group (per-window atomics on the few
     // block addresses in flight serialise)
-    if (!J.iperm) {
-        if (lane == 0) sh_bm[wave] = bmw;
-        __syncthreads();
-        if (tid == 0) {
-            float4 m = sh_bm[0];
-            for (int w = 1; w < 4; ++w) {
-                m.x = fmaxf(m.x, sh_bm[w].x);
-                m.y = fmaxf(m.y, sh_bm[w].y);
-                m.z = fmaxf(m.z, sh_bm[w].z);
-                m.w = fmaxf(m.w, sh_bm[w].w);
-            }
-            float *bm = (float *)(J.bmax + w0 / tile);
-            atomic_max_f32(bm + 0, m.x);
-            atomic_max_f32(bm + 1, m.y);
-            atomic_max_f32(bm + 2, m.z);
-            atomic_max_f32(bm + 3, m.w);
-        }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        v.x = fmaxf(v.x, __shfl_xor(v.x, o, 64));
+        v.y = fmaxf(v.y, __shfl_xor(v.y, o, 64));
+        v.z = fmaxf(v.z, __shfl_xor(v.z, o, 64));
+        v.w = fmaxf(v.w, __shfl_xor(v.w, o, 64));
+    }
+    if (lane == 0) {
+        float *bm = (float *)(J.bmax + w0 / tile);
+        atomic_max_f32(bm + 0, v.x);
+        atomic_max_f32(bm + 1, v.y);
+        atomic_max_f32(bm + 2, v.z);
+        atomic_max_f32(bm + 3, v.w);
     }
 }
 
