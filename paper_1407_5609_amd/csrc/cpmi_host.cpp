@@ -1398,41 +1398,103 @@ int cpmi_strings_lightbulb(cpmi_ctx *c, const int8_t *strings, int64_t n, int64_
             }
         }
     }
+    // iterations in batches of B <= 256 (keys, rows, their sorted copies and
+    // the pair counts and offsets of a batch within 160 MiB)
+    const int B = (int)std::min<int64_t>(std::min(iterations, 256),
+                                         std::max<int64_t>(1, ((int64_t)160 << 20) / (total * 40)));
+    const int key_bits = columns * bits_per;
+    std::vector<int32_t> seg((size_t)B + 1);
+    for (int b = 0; b <= B; ++b) seg[b] = (int32_t)(b * total);
     size_t tb = 0;
-    HIPCHK(c, lb_sort(nullptr, &tb, nullptr, nullptr, nullptr, nullptr, total, columns * bits_per, st));
-    if ((rc = ensure(c, c->lbA, (size_t)total * 24))) return rc;   // keys in, keys out, rows in, rows out
+    {
+        // scratch of the sort: the largest of the full and the last batch
+        const int Bl = iterations % B ? iterations % B : B;
+        size_t t1 = 0, t2 = 0;
+        HIPCHK(c, lb_sort(nullptr, &t1, nullptr, nullptr, nullptr, nullptr, total, B, nullptr, key_bits, st));
+        HIPCHK(c, lb_sort(nullptr, &t2, nullptr, nullptr, nullptr, nullptr, total, Bl, nullptr, key_bits, st));
+        tb = std::max(std::max(t1, t2), lb_scan_bytes((int64_t)B * total));
+    }
+    // keys in, keys out, rows in, rows out, pairs per position, their prefix sums
+    if ((rc = ensure(c, c->lbA, (size_t)B * total * 40))) return rc;
     if ((rc = ensure(c, c->lbT, std::max<size_t>(tb, 1)))) return rc;
-    if ((rc = ensure(c, c->lbC, cols.size() * 4))) return rc;
-    if ((rc = ensure(c, c->lbP, (size_t)cap * 8))) return rc;
-    if ((rc = ensure(c, c->lbK, 64))) return rc;
-    uint64_t *kin = (uint64_t *)c->lbA.p, *kout = kin + total;
-    int32_t *rin = (int32_t *)(kout + total), *rout = rin + total;
-    unsigned long long *cnt = (unsigned long long *)c->lbK.p, *tot = cnt + 1, *best = cnt + 2;
-    unsigned int *ovf = (unsigned int *)(cnt + 3), *flag = ovf + 1;
-    HIPCHK(c, hipMemcpyAsync(c->lbC.p, cols.data(), cols.size() * 4, hipMemcpyHostToDevice, st));
-    launch_fill_u64((uint64_t *)c->lbK.p, 0ull, 2, st);
+    if ((rc = ensure(c, c->lbC, (cols.size() + seg.size()) * 4))) return rc;
+    if ((rc = ensure(c, c->lbK, 16 + (size_t)B * 16))) return rc;
+    uint64_t *kin = (uint64_t *)c->lbA.p, *kout = kin + (size_t)B * total;
+    int32_t *rin = (int32_t *)(kout + (size_t)B * total), *rout = rin + (size_t)B * total;
+    uint64_t *num = (uint64_t *)(rout + (size_t)B * total), *poff = num + (size_t)B * total;
+    const int32_t *dcols = (const int32_t *)c->lbC.p, *dseg = dcols + cols.size();
+    // lbK: best pair, symbol flag, then the pairs of each iteration of a batch
+    unsigned long long *best = (unsigned long long *)c->lbK.p;
+    unsigned int *flag = (unsigned int *)(best + 1);
+    uint64_t *segcnt = (uint64_t *)(best + 2);
+    {
+        std::vector<int32_t> up(cols);
+        up.insert(up.end(), seg.begin(), seg.end());
+        HIPCHK(c, hipMemcpyAsync(c->lbC.p, up.data(), up.size() * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipStreamSynchronize(st));   // `up` is released below
+    }
     launch_fill_u64((uint64_t *)best, m == 0 ? 0ull : ~0ull, 1, st);
-    launch_fill_u32(ovf, 0u, 2, st);
+    launch_fill_u32(flag, 0u, 2, st);
     launch_check_symbols((const signed char *)strings, n, k, ld, sigma, flag, st);
-    for (int it = 0; it < iterations; ++it) {
-        launch_fill_u64((uint64_t *)cnt, 0ull, 1, st);
-        launch_lb_keys((const signed char *)strings, n, ld, sigma, m, bits_per, (const int32_t *)c->lbC.p + (size_t)it * columns,
-                       columns, kin, rin, st);
-        HIPCHK(c, lb_sort(c->lbT.p, &tb, kin, kout, rin, rout, total, columns * bits_per, st));
-        launch_lb_pairs(kout, rout, total, n, m, (int2 *)c->lbP.p, (uint32_t)cap, cnt, st);
-        launch_lb_verify((const signed char *)strings, k, ld, m, (const int2 *)c->lbP.p, cnt, (uint32_t)cap, best, tot,
-                         ovf, st);
+    uint64_t collected = 0;
+    std::vector<uint64_t> hc((size_t)B + 2), ho((size_t)B);
+    // candidates of one fill within max(cap, 2^26) pairs (each iteration's are
+    // at most cap once counted)
+    const uint64_t fill_max = std::max<uint64_t>((uint64_t)cap, (uint64_t)1 << 26);
+    for (int it0 = 0; it0 < iterations; it0 += B) {
+        const int nb = std::min(B, iterations - it0);
+        launch_lb_keys((const signed char *)strings, n, ld, sigma, m, bits_per, dcols + (size_t)it0 * columns, columns,
+                       nb, kin, rin, st);
+        HIPCHK(c, lb_sort(c->lbT.p, &tb, kin, kout, rin, rout, total, nb, dseg, key_bits, st));
+        // pairs per sorted position, their offsets, the pairs of each iteration
+        launch_lb_count(kout, rout, total, nb, n, m, num, poff, c->lbT.p, c->lbT.cap, segcnt, st);
+        // (best and the symbol flag come along: a bad symbol is reported first)
+        HIPCHK(c, hipMemcpyAsync(hc.data(), best, 16 + (size_t)nb * 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        if ((uint32_t)hc[1] & F_SYMBOL) return fail(c, CPMI_ERR_ARG, "a symbol lies outside the alphabet");
+        bool over = false;
+        for (int b = 0; b < nb; ++b) {
+            const uint64_t v = hc[2 + b];
+            collected += v;
+            over |= v > (uint64_t)cap;
+            ho[b] = b ? ho[b - 1] + hc[2 + b - 1] : 0;   // first pair of iteration b in the batch
+        }
+        if (over) {
+            if (pairs_out) *pairs_out = (int64_t)collected;
+            return fail(c, CPMI_ERR_CAPACITY, "a bucketing pass produced more than %lld candidate pairs; "
+                                              "choose more columns or a larger cap", (long long)cap);
+        }
+        // write and verify the candidates of consecutive iterations, as many
+        // as one fill holds (groups [b0, b1) found first, so that the buffer
+        // is sized before any fill is queued)
+        std::vector<std::pair<int, int>> groups;
+        uint64_t most = 0;
+        for (int b0 = 0; b0 < nb;) {
+            uint64_t msum = hc[2 + b0];
+            int b1 = b0 + 1;
+            while (b1 < nb && msum + hc[2 + b1] <= fill_max) msum += hc[2 + b1++];
+            groups.emplace_back(b0, b1);
+            most = std::max(most, msum);
+            b0 = b1;
+        }
+        if (most == 0) continue;
+        if ((rc = ensure(c, c->lbP, (size_t)most * 8))) return rc;
+        for (auto [b0, b1] : groups) {
+            const uint64_t msum = (b1 < nb ? ho[b1] : ho[nb - 1] + hc[2 + nb - 1]) - ho[b0];
+            if (msum == 0) continue;
+            launch_lb_fill(kout, rout, total, (int64_t)b0 * total, (int64_t)b1 * total, n, m, poff, ho[b0],
+                           (int2 *)c->lbP.p, st);
+            launch_lb_verify((const signed char *)strings, k, ld, m, (const int2 *)c->lbP.p, msum, best, st);
+        }
     }
     HIPCHK(c, hipGetLastError());
-    uint64_t res[4];
-    HIPCHK(c, hipMemcpyAsync(res, c->lbK.p, 32, hipMemcpyDeviceToHost, st));
+    uint64_t res[2];
+    HIPCHK(c, hipMemcpyAsync(res, c->lbK.p, 16, hipMemcpyDeviceToHost, st));
     HIPCHK(c, hipStreamSynchronize(st));
-    const uint32_t ovf_h = (uint32_t)res[3], flag_h = (uint32_t)(res[3] >> 32);
+    const uint32_t flag_h = (uint32_t)res[1];
     if (flag_h & F_SYMBOL) return fail(c, CPMI_ERR_ARG, "a symbol lies outside the alphabet");
-    if (pairs_out) *pairs_out = (int64_t)res[1];
-    if (ovf_h) return fail(c, CPMI_ERR_CAPACITY, "a bucketing pass produced more than %lld candidate pairs; "
-                                                 "choose more columns or a larger cap", (long long)cap);
-    const uint64_t b = res[2];
+    if (pairs_out) *pairs_out = (int64_t)collected;
+    const uint64_t b = res[0];
     if ((m == 0 && b == 0) || (m == 1 && b == ~0ull)) {
         out->status = CPMI_ERR_NOPAIR;
         return fail(c, CPMI_ERR_NOPAIR, "no pair shared a bucket");

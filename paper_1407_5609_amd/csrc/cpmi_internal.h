@@ -173,19 +173,28 @@ void launch_check_symbols(const signed char *S, int64_t n, int64_t k, int64_t ld
                           hipStream_t st);
 void launch_encode_two_locus(const signed char *G, int64_t m1, int64_t m2, int64_t n, int64_t ld, int direction,
                              signed char *Z, int64_t Lz, int64_t split, unsigned int *flags, hipStream_t st);
-// Light-bulb bucketing (lightbulb.hip). Rows: the n strings (mode 0) or
-// their one-hot codes and complements (mode 1, 2n rows); keys of ncols
-// chosen columns (bits_per bits each); count: candidates of the iteration
-// (cleared by the caller); best: packed best pair (see the kernels).
+// Light-bulb bucketing (lightbulb.hip), B iterations at once. Rows: the n
+// strings (mode 0) or their one-hot codes and complements (mode 1, 2n rows:
+// `total`); iteration b's keys (ncols chosen columns, bits_per bits each) and
+// rows fill [b total, (b+1) total) of keys/rows. The sort orders each
+// iteration's part: keys tagged with b above their bits, else a segmented
+// sort (seg: B + 1 offsets b total). lb_count: pairs per
+// sorted position (num), their exclusive prefix sum over the batch (off;
+// rocPRIM scan with temp_bytes >= lb_scan_bytes) and the pairs of each
+// iteration (segcnt[B]); lb_fill writes the pairs of positions [p0, p1) to
+// cand[off[p] - base ...]; lb_verify merges the exact match counts of
+// cand[0, m) into the packed best pair (see the kernels).
 void launch_lb_keys(const signed char *S, int64_t n, int64_t ld, int sigma, int mode, int bits_per,
-                    const int32_t *cols, int ncols, uint64_t *keys, int32_t *rows, hipStream_t st);
+                    const int32_t *cols, int ncols, int B, uint64_t *keys, int32_t *rows, hipStream_t st);
 hipError_t lb_sort(void *temp, size_t *temp_bytes, const uint64_t *keys_in, uint64_t *keys_out, const int32_t *rows_in,
-                   int32_t *rows_out, int64_t total, int key_bits, hipStream_t st);
-void launch_lb_pairs(const uint64_t *keys, const int32_t *rows, int64_t total, int64_t n, int mode, int2 *cand,
-                     uint32_t cap, unsigned long long *count, hipStream_t st);
-void launch_lb_verify(const signed char *S, int64_t k, int64_t ld, int mode, const int2 *cand,
-                      const unsigned long long *count, uint32_t cap, unsigned long long *best,
-                      unsigned long long *total, unsigned int *overflow, hipStream_t st);
+                   int32_t *rows_out, int64_t total, int B, const int32_t *seg, int key_bits, hipStream_t st);
+size_t lb_scan_bytes(int64_t all);
+void launch_lb_count(const uint64_t *keys, const int32_t *rows, int64_t total, int B, int64_t n, int mode,
+                     uint64_t *num, uint64_t *off, void *temp, size_t temp_bytes, uint64_t *segcnt, hipStream_t st);
+void launch_lb_fill(const uint64_t *keys, const int32_t *rows, int64_t total, int64_t p0, int64_t p1, int64_t n,
+                    int mode, const uint64_t *off, uint64_t base, int2 *cand, hipStream_t st);
+void launch_lb_verify(const signed char *S, int64_t k, int64_t ld, int mode, const int2 *cand, uint64_t m,
+                      unsigned long long *best, hipStream_t st);
 void launch_perm_finish(int32_t *perm, int32_t *iperm, int64_t n, int64_t npad, hipStream_t st);
 void launch_block_range(const double *D, int64_t n, int q, const int32_t *perm, int tile, int64_t nblk, double *lo,
                         double *hi, hipStream_t st);

@@ -4,10 +4,18 @@
 // One iteration: a key per row from the symbols (bits) of c randomly chosen
 // columns, a radix sort of the rows by key, every pair of rows that share a
 // bucket (equal keys) added to the candidates, and the candidates' exact
-// match counts merged into the best pair so far. After enough iterations the
-// best pair is the most (least) correlated one with high probability; the
-// reported count is always the pair's exact one.
+// match counts merged into the best pair so far. The iterations run in
+// batches: one key kernel, one sort (keys tagged with their iteration, or a
+// segment per iteration where the tag does not fit in 64 bits), a counting
+// pass over the buckets and a prefix sum of its counts, then a pass that
+// writes the candidates at their offsets and one verification of them all.
+// After enough iterations the best pair is the most (least) correlated one
+// with high probability; the reported count is always the pair's exact one.
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_segmented_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
+#include <algorithm>
 
 #include "cpmi_internal.h"
 
@@ -15,15 +23,22 @@ namespace cpmi {
 
 namespace {
 
-// Key of row r: the chosen columns' values, bits_per packed bits each, first
-// column in the most significant place. Rows are strings (mode 0: symbols,
-// bits_per = ceil(log2 sigma)) or the one-hot bit strings of Section 5 (mode
-// 1: the codes of the n strings, then their complements; a column is a bit
-// position c * sigma + b, bit b of the code of symbol S[c] being S[c] == b).
+// Key of row r in iteration b of the batch (blockIdx.y): the chosen
+// columns' values, bits_per packed bits each, first column in the most
+// significant place. Rows are strings (mode 0: symbols, bits_per =
+// ceil(log2 sigma)) or the one-hot bit strings of Section 5 (mode 1: the
+// codes of the n strings, then their complements; a column is a bit position
+// c * sigma + b, bit b of the code of symbol S[c] being S[c] == b). With
+// tag set, b itself sits above the ncols * bits_per key bits, so that one
+// sort of the whole batch keeps the iterations apart.
 __global__ void lb_keys_kernel(const signed char *S, int64_t n, int64_t ld, int sigma, int mode, int bits_per,
-                               const int32_t *cols, int ncols, uint64_t *keys, int32_t *rows)
+                               const int32_t *cols_all, int ncols, bool tag, uint64_t *keys_all, int32_t *rows_all)
 {
     const int64_t total = mode == 0 ? n : 2 * n;
+    const int b = blockIdx.y;
+    const int32_t *cols = cols_all + (int64_t)b * ncols;
+    uint64_t *keys = keys_all + (int64_t)b * total;
+    int32_t *rows = rows_all + (int64_t)b * total;
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < total; r += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = r < n ? r : r - n;
         const bool comp = r >= n;
@@ -39,46 +54,63 @@ __global__ void lb_keys_kernel(const signed char *S, int64_t n, int64_t ld, int 
             }
             key = (key << bits_per) | v;
         }
-        keys[r] = key;
+        keys[r] = tag ? key | ((uint64_t)b << (ncols * bits_per)) : key;
         rows[r] = (int32_t)r;
     }
 }
 
-// Every pair of a bucket (a run of equal keys in sorted order): the thread of
-// sorted position p pairs it with the positions after it in the run. Mode 1
-// keeps only (code, complement) pairs of different strings. Candidates
-// beyond `cap` are counted but not stored.
-__global__ void lb_pairs_kernel(const uint64_t *keys, const int32_t *rows, int64_t total, int64_t n, int mode,
-                                int2 *cand, uint32_t cap, unsigned long long *count)
+// Every pair of a bucket (a run of equal keys in the sorted segment of its
+// iteration): the thread of sorted position p pairs it with the positions
+// after it in the run. Mode 1 keeps only (code, complement) pairs of
+// different strings. Without cand, num[p] = the number of such pairs of p;
+// with it, they are written to cand[off[p] - base ...] (off: the exclusive
+// prefix sum of num over the batch), for the positions [p0, p1). Both passes
+// take the same pairs in the same order; no atomics.
+__global__ void lb_pairs_kernel(const uint64_t *keys, const int32_t *rows, int64_t total, int64_t p0, int64_t p1,
+                                int64_t n, int mode, uint64_t *num, int2 *cand, const uint64_t *off, uint64_t base)
 {
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t p = p0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < p1;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t end = (p / total + 1) * total;
         const uint64_t kp = keys[p];
-        for (int64_t q = p + 1; q < total && keys[q] == kp; ++q) {
-            int32_t a = rows[p], b = rows[q];
+        uint64_t at = cand ? off[p] - base : 0, mine = 0;
+        for (int64_t q = p + 1; q < end && keys[q] == kp; ++q) {
+            int32_t a = rows[p], c = rows[q];
             if (mode == 1) {
-                if ((a < n) == (b < n)) continue;                 // both codes or both complements
+                if ((a < n) == (c < n)) continue;                 // both codes or both complements
                 if (a >= n) {
                     const int32_t t = a;
-                    a = b;
-                    b = t;
+                    a = c;
+                    c = t;
                 }
-                b -= (int32_t)n;                                   // complement of string b
-                if (a == b) continue;
+                c -= (int32_t)n;                                   // complement of string c
+                if (a == c) continue;
             }
-            const int32_t i = a < b ? a : b, j = a < b ? b : a;
-            const unsigned long long idx = atomicAdd(count, 1ull);
-            if (idx < cap) cand[idx] = make_int2(i, j);
+            if (cand) cand[at++] = make_int2(a < c ? a : c, a < c ? c : a);
+            else ++mine;
         }
+        if (!cand) num[p] = mine;
     }
+}
+
+// Pairs of each iteration b < nb of the batch from the prefix sums:
+// seg[b] = off[(b+1) total] - off[b total] (the last one ending at
+// off[all - 1] + num[all - 1]).
+__global__ void lb_segments_kernel(const uint64_t *num, const uint64_t *off, int64_t total, int nb, uint64_t *seg)
+{
+    const int b = threadIdx.x;
+    if (b >= nb) return;
+    const int64_t all = total * nb;
+    const uint64_t hi = b + 1 < nb ? off[(b + 1) * total] : off[all - 1] + num[all - 1];
+    seg[b] = hi - off[(int64_t)b * total];
 }
 
 // Exact match count of each candidate, merged into the best pair:
 // most correlated: max of (u << 42 | ~(i << 21 | j) & (2^42 - 1));
 // least correlated: min of (u << 42 | i << 21 | j) (ties to the smallest (i, j)).
-__global__ void lb_verify_kernel(const signed char *S, int64_t k, int64_t ld, int mode, const int2 *cand,
-                                 const unsigned long long *count, uint32_t cap, unsigned long long *best)
+__global__ void lb_verify_kernel(const signed char *S, int64_t k, int64_t ld, int mode, const int2 *cand, uint64_t m,
+                                 unsigned long long *best)
 {
-    const uint64_t m = min<uint64_t>(*count, (uint64_t)cap);
     for (uint64_t c = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; c < m; c += (uint64_t)gridDim.x * blockDim.x) {
         const int2 pr = cand[c];
         const signed char *x = S + (int64_t)pr.x * ld, *y = S + (int64_t)pr.y * ld;
@@ -90,15 +122,6 @@ __global__ void lb_verify_kernel(const signed char *S, int64_t k, int64_t ld, in
     }
 }
 
-// After an iteration: add its candidate count to the running total and flag
-// an overflow of the candidate buffer.
-__global__ void lb_account_kernel(const unsigned long long *count, uint32_t cap, unsigned long long *total,
-                                  unsigned int *overflow)
-{
-    total[0] += count[0];
-    if (count[0] > cap) overflow[0] = 1u;
-}
-
 unsigned lb_grid(int64_t total)
 {
     const int64_t g = (total + 255) / 256;
@@ -107,34 +130,70 @@ unsigned lb_grid(int64_t total)
 
 }  // namespace
 
+// Bits of the iteration tag of a batch of B (0 for B = 1), or -1 when the
+// tag does not fit above the key bits (the sort then takes a segment per
+// iteration).
+int lb_tag_bits(int B, int key_bits)
+{
+    int t = 0;
+    while ((1 << t) < B) ++t;
+    return key_bits + t <= 64 ? t : -1;
+}
+
 void launch_lb_keys(const signed char *S, int64_t n, int64_t ld, int sigma, int mode, int bits_per,
-                    const int32_t *cols, int ncols, uint64_t *keys, int32_t *rows, hipStream_t st)
+                    const int32_t *cols, int ncols, int B, uint64_t *keys, int32_t *rows, hipStream_t st)
 {
     const int64_t total = mode == 0 ? n : 2 * n;
-    hipLaunchKernelGGL(lb_keys_kernel, dim3(lb_grid(total)), dim3(256), 0, st, S, n, ld, sigma, mode, bits_per, cols,
-                       ncols, keys, rows);
+    const bool tag = lb_tag_bits(B, ncols * bits_per) > 0;
+    hipLaunchKernelGGL(lb_keys_kernel, dim3(lb_grid(total), (unsigned)B), dim3(256), 0, st, S, n, ld, sigma, mode,
+                       bits_per, cols, ncols, tag, keys, rows);
 }
 
 hipError_t lb_sort(void *temp, size_t *temp_bytes, const uint64_t *keys_in, uint64_t *keys_out, const int32_t *rows_in,
-                   int32_t *rows_out, int64_t total, int key_bits, hipStream_t st)
+                   int32_t *rows_out, int64_t total, int B, const int32_t *seg, int key_bits, hipStream_t st)
 {
-    return rocprim::radix_sort_pairs(temp, *temp_bytes, keys_in, keys_out, rows_in, rows_out, (unsigned int)total, 0,
-                                     key_bits, st);
+    const int t = lb_tag_bits(B, key_bits);
+    if (t >= 0)
+        return rocprim::radix_sort_pairs(temp, *temp_bytes, keys_in, keys_out, rows_in, rows_out,
+                                         (unsigned int)(total * B), 0, key_bits + t, st);
+    return rocprim::segmented_radix_sort_pairs(temp, *temp_bytes, keys_in, keys_out, rows_in, rows_out,
+                                               (unsigned int)(total * B), (unsigned int)B, seg, seg + 1, 0, key_bits,
+                                               st);
 }
 
-void launch_lb_pairs(const uint64_t *keys, const int32_t *rows, int64_t total, int64_t n, int mode, int2 *cand,
-                     uint32_t cap, unsigned long long *count, hipStream_t st)
+void launch_lb_count(const uint64_t *keys, const int32_t *rows, int64_t total, int B, int64_t n, int mode,
+                     uint64_t *num, uint64_t *off, void *temp, size_t temp_bytes, uint64_t *seg, hipStream_t st)
 {
-    hipLaunchKernelGGL(lb_pairs_kernel, dim3(lb_grid(total)), dim3(256), 0, st, keys, rows, total, n, mode, cand, cap,
-                       count);
+    const int64_t all = total * B;
+    hipLaunchKernelGGL(lb_pairs_kernel, dim3(lb_grid(all)), dim3(256), 0, st, keys, rows, total, (int64_t)0, all, n,
+                       mode, num, (int2 *)nullptr, (const uint64_t *)nullptr, (uint64_t)0);
+    size_t tb = temp_bytes;
+    rocprim::exclusive_scan(temp, tb, num, off, (uint64_t)0, (size_t)all, rocprim::plus<uint64_t>(), st);
+    hipLaunchKernelGGL(lb_segments_kernel, dim3(1), dim3(256), 0, st, num, off, total, B, seg);
 }
 
-void launch_lb_verify(const signed char *S, int64_t k, int64_t ld, int mode, const int2 *cand,
-                      const unsigned long long *count, uint32_t cap, unsigned long long *best,
-                      unsigned long long *total, unsigned int *overflow, hipStream_t st)
+size_t lb_scan_bytes(int64_t all)
 {
-    hipLaunchKernelGGL(lb_verify_kernel, dim3(4096), dim3(256), 0, st, S, k, ld, mode, cand, count, cap, best);
-    hipLaunchKernelGGL(lb_account_kernel, dim3(1), dim3(1), 0, st, count, cap, total, overflow);
+    size_t tb = 0;
+    rocprim::exclusive_scan(nullptr, tb, (const uint64_t *)nullptr, (uint64_t *)nullptr, (uint64_t)0, (size_t)all,
+                            rocprim::plus<uint64_t>(), (hipStream_t)0);
+    return tb;
+}
+
+void launch_lb_fill(const uint64_t *keys, const int32_t *rows, int64_t total, int64_t p0, int64_t p1, int64_t n,
+                    int mode, const uint64_t *off, uint64_t base, int2 *cand, hipStream_t st)
+{
+    if (p1 <= p0) return;
+    hipLaunchKernelGGL(lb_pairs_kernel, dim3(lb_grid(p1 - p0)), dim3(256), 0, st, keys, rows, total, p0, p1, n, mode,
+                       (uint64_t *)nullptr, cand, off, base);
+}
+
+void launch_lb_verify(const signed char *S, int64_t k, int64_t ld, int mode, const int2 *cand, uint64_t m,
+                      unsigned long long *best, hipStream_t st)
+{
+    if (m == 0) return;
+    hipLaunchKernelGGL(lb_verify_kernel, dim3(lb_grid((int64_t)std::min<uint64_t>(m, 1u << 22))), dim3(256), 0, st, S,
+                       k, ld, mode, cand, m, best);
 }
 
 }  // namespace cpmi
