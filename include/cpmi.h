@@ -277,7 +277,8 @@ int cpmi_strings_pair(cpmi_ctx *ctx, const int8_t *strings, int64_t n, int64_t k
  * CPMI_MOST_CORRELATED buckets the strings themselves (columns are
  * positions, at most 64 / ceil(log2 sigma) of them); CPMI_LEAST_CORRELATED
  * buckets the one-hot codes against their complements (columns are bit
- * positions of the codes, at most 64) and keeps (code, complement) pairs of
+ * positions of the codes, at most 64; bit c sigma + b is set where symbol c
+ * is sigma - 1 - b, Section 5's order) and keeps (code, complement) pairs of
  * different strings. The answer is the exact best pair with high probability
  * only (enough iterations; the paper's analysis); the reported count is
  * always the pair's exact one. *pairs_out (host, nullable) receives the
@@ -287,7 +288,14 @@ int cpmi_strings_pair(cpmi_ctx *ctx, const int8_t *strings, int64_t n, int64_t k
  * ERR_ARG (shapes, mode, columns, iterations, cap, a symbol outside the
  * alphabet), ERR_NOPAIR (n < 2, or no two rows ever shared a bucket),
  * ERR_CAPACITY (an iteration produced more than cap candidates; *pairs_out
- * still counts them). */
+ * counts the pairs of the iterations run until then, that one included).
+ * The columns of an iteration are the first `columns` entries of a partial
+ * Fisher-Yates shuffle of 0..C-1 (C = k, or sigma k for the least correlated
+ * pair), restarted from the identity for every iteration: step q swaps
+ * entries q and q + (splitmix64(c) mod (C - q)), where c counts up from
+ * seed * 0x9e3779b97f4a7c15 (mod 2^64) over the steps of all iterations and
+ * splitmix64(c) is SplitMix64's output for state c (the state advanced by
+ * 0x9e3779b97f4a7c15, then mixed). */
 int cpmi_strings_lightbulb(cpmi_ctx *ctx, const int8_t *strings, int64_t n, int64_t k, int64_t ld, int sigma,
                            int mode, int iterations, int columns, uint64_t seed, int64_t cap, void *stream,
                            cpmi_match_pair *out, int64_t *pairs_out);

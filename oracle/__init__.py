@@ -248,3 +248,85 @@ def two_locus(G: np.ndarray, m1: int, m2: int, direction: int = 0):
     if rc != 0:
         raise MemoryError("oracle out of memory")
     return int(oi.value), int(oj.value), int(om.value)
+
+
+# ---------------------------------------------------------------------------
+# randomised light-bulb bucketing (Section 4, MLBA; Section 5's codes and
+# complements for the least correlated pair)
+# ---------------------------------------------------------------------------
+
+_M64 = (1 << 64) - 1
+_GOLDEN = 0x9E3779B97F4A7C15
+
+
+def splitmix64(state: int) -> int:
+    """SplitMix64 (Steele, Lea and Flood, 2014): the output for `state`, i.e.
+    the state advanced by the golden-ratio increment, then mixed."""
+    z = (state + _GOLDEN) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def lightbulb_columns(seed: int, iterations: int, columns: int, ncols: int):
+    """The columns each iteration draws: the first `columns` entries of a
+    partial Fisher-Yates shuffle of 0..ncols-1, restarted per iteration; step
+    q swaps entries q and q + splitmix64(c) mod (ncols - q), c counting up
+    from seed * golden (mod 2^64) over all steps."""
+    c = (seed * _GOLDEN) & _M64
+    out = []
+    for _ in range(iterations):
+        pool = list(range(ncols))
+        for q in range(columns):
+            r = q + splitmix64(c) % (ncols - q)
+            c = (c + 1) & _M64
+            pool[q], pool[r] = pool[r], pool[q]
+        out.append(pool[:columns])
+    return out
+
+
+def lightbulb(S: np.ndarray, sigma: int, mode: str, iterations: int, columns: int, seed: int):
+    """MLBA as a candidate generator: per iteration, the rows whose values in
+    the drawn columns agree form a bucket and every pair in a bucket is a
+    candidate. Most correlated: rows are the strings, columns positions.
+    Least correlated: rows are the one-hot codes of the strings and their
+    complements, columns bit positions of the codes, and the candidates are
+    the (code i, complement j) pairs with i != j. Returns (candidate pairs
+    over all iterations, best) with best = (i, j, m(S_i, S_j)) over the
+    candidates, the most (least) matches first, then the smallest (i, j); or
+    None without candidates. Plain loops over buckets: small inputs."""
+    S = _int8_rows(S)
+    n, k = S.shape
+    if mode == "most":
+        R = S.astype(np.int64)
+        ncol = k
+    else:
+        X = encode(S, sigma).astype(np.int64)
+        R = np.concatenate([X, 1 - X])                  # rows n..2n-1: complements
+        ncol = sigma * k
+    total = 0
+    cands = set()
+    for cols in lightbulb_columns(seed, iterations, columns, ncol):
+        buckets = {}
+        for r in range(R.shape[0]):
+            buckets.setdefault(tuple(R[r, cols].tolist()), []).append(r)
+        for rows in buckets.values():
+            for x in range(len(rows)):
+                for y in range(x + 1, len(rows)):
+                    a, b = rows[x], rows[y]
+                    if mode == "least":
+                        if (a < n) == (b < n):
+                            continue
+                        a, b = (a, b - n) if a < n else (b, a - n)
+                        if a == b:
+                            continue
+                    total += 1
+                    cands.add((min(a, b), max(a, b)))
+    if not cands:
+        return total, None
+    scored = [(matches(S, i, j), i, j) for i, j in cands]
+    if mode == "most":
+        u, i, j = min(scored, key=lambda t: (-t[0], t[1], t[2]))
+    else:
+        u, i, j = min(scored, key=lambda t: (t[0], t[1], t[2]))
+    return total, (i, j, u)

@@ -28,9 +28,9 @@ namespace {
 // significant place. Rows are strings (mode 0: symbols, bits_per =
 // ceil(log2 sigma)) or the one-hot bit strings of Section 5 (mode 1: the
 // codes of the n strings, then their complements; a column is a bit position
-// c * sigma + b, bit b of the code of symbol S[c] being S[c] == b). With
-// tag set, b itself sits above the ncols * bits_per key bits, so that one
-// sort of the whole batch keeps the iterations apart.
+// c * sigma + b of the codes, set where S[c] == sigma - 1 - b). With tag
+// set, the iteration's index sits above the ncols * bits_per key bits, so
+// that one sort of the whole batch keeps the iterations apart.
 __global__ void lb_keys_kernel(const signed char *S, int64_t n, int64_t ld, int sigma, int mode, int bits_per,
                                const int32_t *cols_all, int ncols, bool tag, uint64_t *keys_all, int32_t *rows_all)
 {
@@ -48,8 +48,10 @@ __global__ void lb_keys_kernel(const signed char *S, int64_t n, int64_t ld, int 
             if (mode == 0) {
                 v = (uint64_t)(unsigned char)S[i * ld + cols[c]];
             } else {
+                // bit b of symbol c's group is set for symbol sigma - 1 - b
+                // (Section 5's order, 0 -> 0..01)
                 const int32_t pos = cols[c];
-                const int bit = S[i * ld + pos / sigma] == pos % sigma;
+                const int bit = S[i * ld + pos / sigma] == sigma - 1 - pos % sigma;
                 v = (uint64_t)(comp ? !bit : bit);
             }
             key = (key << bits_per) | v;

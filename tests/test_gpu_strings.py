@@ -179,3 +179,27 @@ def test_lightbulb_errors(ctx, torch_dev):
     assert e.value.code == cp.ERR_CAPACITY
     r, pairs = ctx.strings_lightbulb(S, 4, "most", columns=2, cap=10000)
     assert (r.i, r.j, r.matches) == (0, 1, 8) and pairs == 100 * 99 // 2 * 16
+
+
+@pytest.mark.parametrize("mode,n,k,sigma,iterations,columns,seed", [
+    ("most", 900, 24, 4, 16, 6, 7),       # one batch, keys tagged with the iteration
+    ("most", 300, 12, 4, 300, 5, 3),      # two batches (at most 256 iterations each)
+    ("most", 400, 40, 4, 6, 32, 5),       # 64 key bits: no room for the tag, segmented sort
+    ("least", 300, 16, 2, 40, 12, 11),    # codes against complements (600 rows)
+    ("least", 250, 10, 3, 5, 8, 2),       # 8 of the 30 bits of the codes of three-letter strings
+])
+def test_lightbulb_candidates_match_oracle(ctx, torch_dev, mode, n, k, sigma, iterations, columns, seed):
+    """The candidates collected over all iterations (the paper's work measure)
+    and the best candidate equal the oracle's MLBA with the same column draw
+    (SplitMix64 on both sides, each written from its published definition)."""
+    rng = np.random.default_rng(500 + n + k)
+    S = W.random_strings(rng, n, k, sigma)
+    W.plant_string_pair(rng, S, sigma, k - 1 if mode == "most" else 0)
+    for r in range(5):                                    # a few near-duplicates: real buckets
+        S[10 + r] = S[200 + r]
+        S[10 + r, r % k] = (S[10 + r, r % k] + 1) % sigma
+    want_total, want_best = oracle.lightbulb(S, sigma, mode, iterations, columns, seed)
+    got, pairs = ctx.strings_lightbulb(_dev(S, torch_dev), sigma, mode, iterations=iterations, columns=columns,
+                                       seed=seed)
+    assert pairs == want_total
+    assert want_best is not None and (got.i, got.j, got.matches) == want_best

@@ -510,3 +510,92 @@ def test_two_locus_correlation_identity():
             same = G[:, i] == G[:, j]
             p, q = F(int(same[:m].sum()), m), F(int(same[m:].sum()), m)
             assert F(oracle.bit_matches(D1, D2, i, j), 6 * m) == F(1, 2) + (p - q) / 3
+
+
+# --------------------------------------------------------------------------
+# light-bulb bucketing (Section 4, MLBA): the draw and the candidates
+# --------------------------------------------------------------------------
+
+def test_splitmix64_published_test_vector():
+    """SplitMix64's reference stream from state 1234567 (the test vector of
+    its published reference implementation): output k is the output for
+    state 1234567 + k golden."""
+    want = [6457827717110365317, 3203168211198807973, 9817491932198370423, 4593380528125082431,
+            16408922859458223821]
+    state = 1234567
+    got = []
+    for _ in want:
+        got.append(oracle.splitmix64(state))
+        state = (state + 0x9E3779B97F4A7C15) % (1 << 64)
+    assert got == want
+
+
+def test_lightbulb_columns_are_distinct_draws():
+    cols = oracle.lightbulb_columns(5, 40, 9, 30)
+    assert len(cols) == 40
+    for c in cols:
+        assert len(set(c)) == 9 and all(0 <= v < 30 for v in c)
+    assert cols != oracle.lightbulb_columns(6, 40, 9, 30)
+    # every column turns up: the draw covers the range
+    assert set(itertools.chain.from_iterable(cols)) == set(range(30))
+    # drawing all columns gives a permutation
+    assert sorted(oracle.lightbulb_columns(3, 1, 30, 30)[0]) == list(range(30))
+
+
+def _pairs_in(counts):
+    return sum(c * (c - 1) // 2 for c in counts)
+
+
+def test_lightbulb_all_columns_buckets_identical_strings():
+    """With every position drawn the buckets are the classes of identical
+    strings: candidates = sum of C(multiplicity, 2) per iteration, and the
+    best pair agrees everywhere."""
+    rng = np.random.default_rng(41)
+    S = W.random_strings(rng, 60, 6, 3)
+    S[7] = S[3]
+    S[40] = S[3]
+    S[21] = S[50]
+    mult = {}
+    for r in S:
+        mult[r.tobytes()] = mult.get(r.tobytes(), 0) + 1
+    total, best = oracle.lightbulb(S, 3, "most", 3, 6, seed=2)
+    assert total == 3 * _pairs_in(mult.values())
+    assert best == (3, 7, 6)
+
+
+def test_lightbulb_one_column_is_a_histogram():
+    """One drawn column: the buckets are that column's symbol classes."""
+    rng = np.random.default_rng(42)
+    S = W.random_strings(rng, 50, 9, 4)
+    for seed in range(3):
+        (col,), = oracle.lightbulb_columns(seed, 1, 1, 9)
+        total, best = oracle.lightbulb(S, 4, "most", 1, 1, seed)
+        assert total == _pairs_in(np.bincount(S[:, col], minlength=4))
+        # the best candidate by brute force over the pairs sharing that symbol
+        pool = [(oracle.matches(S, i, j), i, j) for i in range(50) for j in range(i + 1, 50) if S[i, col] == S[j, col]]
+        u, i, j = max(pool, key=lambda t: (t[0], -t[1], -t[2]))
+        assert best == (i, j, u)
+
+
+def test_lightbulb_least_against_brute_force():
+    """Least correlated: a candidate is a string i whose code agrees on the
+    drawn bits with the complement of a string j != i. Brute force over all
+    ordered (i, j) per iteration, from the codes written out directly."""
+    rng = np.random.default_rng(43)
+    n, k, sigma, c, its = 14, 5, 3, 4, 5
+    S = W.random_strings(rng, n, k, sigma)
+    X = np.zeros((n, sigma * k), dtype=np.int64)     # Section 5's order: symbol 0 -> 0..01
+    for i in range(n):
+        for p in range(k):
+            X[i, p * sigma + sigma - 1 - S[i, p]] = 1
+    total, cands = 0, set()
+    for cols in oracle.lightbulb_columns(9, its, c, sigma * k):
+        for i in range(n):
+            for j in range(n):
+                if i != j and all(X[i, b] == 1 - X[j, b] for b in cols):
+                    total += 1
+                    cands.add((min(i, j), max(i, j)))
+    got_total, got_best = oracle.lightbulb(S, sigma, "least", its, c, 9)
+    assert got_total == total
+    u, i, j = min(((sum(S[a] == S[b]), a, b) for a, b in cands), key=lambda t: (t[0], t[1], t[2]))
+    assert got_best == (i, j, int(u))
