@@ -348,10 +348,10 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         while (t < count && tiles[t] == TILE_NONE) t += stride;
         return t;
     };
-    // direct-to-LDS load of the row scalars of the tile with list entry `e`
-    // (blocks I and J) into sh_s half `half`: each wave loads 64 of block I
-    // and 64 of block J
-    auto load_scalars = [&](uint64_t e, int half) {
+    // direct-to-LDS load of the row scalars of tile `tt` (blocks I and J) into
+    // sh_s half `half`: each wave loads 64 of block I and 64 of block J
+    auto load_scalars = [&](int32_t tt, int half) {
+        const uint64_t e = tiles[tt];
         const c_prob &Q = ((c_prob *)args.probs)[tile_prob(e)];
         const unsigned char *sb = (const unsigned char *)Q.shat;
         const uint32_t lo = (uint32_t)fresh_lane() * 4;
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     int32_t t = next_valid((int32_t)blockIdx.x);
     if (t >= count) return;
     int tcount = 0;
-    load_scalars(tiles[t], 0);
+    load_scalars(t, 0);
 
     // load cursor: runs three slices ahead of the multiply, across tiles; at
     // the end of the list it keeps re-reading its last slice (always in bounds)
@@ -404,11 +404,6 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     // the first tile's scalars are older than the last 16 loads: landed
     __builtin_amdgcn_s_waitcnt(WAIT_SLICE);
     __builtin_amdgcn_s_barrier();
-    // entry of slot t + stride, the first probe of the search for the tile
-    // after t; inside the loop it is read one tile ahead, before the
-    // epilogue, so that its scalar load does not stall the top of the next
-    // tile
-    uint64_t pre = t + stride < count ? tiles[t + stride] : TILE_NONE;
     while (t < count) {
         // per-lane values are rebuilt from a fresh lane index at every tile,
         // so that nothing lane-derived is held through the epilogue
@@ -424,15 +419,8 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         // loop) and are older than every slice waited for since
         const S *sh_t = sh_s + (tcount & 1) * (2 * T256);
         const int32_t *sh_ot = sh_o + (tcount & 1) * (2 * T256);
-        // next tile of this work-group: slot t + stride unless that slot is
-        // empty (t + 2 stride < 2^31: the host bounds the list length)
-        int32_t tn = t + stride;
-        uint64_t en = pre;
-        if (pre == TILE_NONE) {
-            tn = next_valid(t + 2 * stride);
-            en = tn < count ? tiles[tn] : TILE_NONE;
-        }
-        if (tn < count) load_scalars(en, (tcount + 1) & 1);
+        const int32_t tn = next_valid(t + stride);
+        if (tn < count) load_scalars(tn, (tcount + 1) & 1);
         ++tcount;
 
         AccT acc[MB256][MB256];
@@ -511,11 +499,6 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
             slice_step<PREC>(acc, f0a, f0b, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<3>(), stage_ptr<0>(),
                              stage_ptr<2>());
         }
-        // the probe for the tile after tn (see pre above): issued before the
-        // epilogue, whose work covers its latency
-        __builtin_amdgcn_sched_barrier(0);
-        pre = tn + stride < count ? tiles[tn + stride] : TILE_NONE;
-        __builtin_amdgcn_sched_barrier(0);
         // ---------------- epilogue ----------------
         // 32-bit row/column indices (n < 2^31 is enforced by the host)
         const int32_t n = (int32_t)P.n, excl = (int32_t)P.excl;
