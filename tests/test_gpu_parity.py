@@ -202,7 +202,7 @@ def test_int8_points_bit_exact(ctx, torch_dev, tile, n, d):
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 @pytest.mark.parametrize("length,ell,excl", [(700, 16, 0), (3000, 64, 0), (5000, 100, 50), (6000, 256, 0),
-                                              (4500, 512, 0), (2100, 128, 1)])
+                                              (4500, 512, 0), (2100, 128, 1), (3001, 37, 0), (2500, 301, 0)])
 def test_motif_matches_oracle(ctx, torch_dev, tile, prec, length, ell, excl):
     rng = np.random.default_rng(length + ell)
     T = W.random_walk(rng, length)
@@ -248,7 +248,7 @@ def test_motif_full_size_golden(ctx, torch_dev, tile):
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_motif_batch_matches_oracle(ctx, torch_dev, tile, prec):
     rng = np.random.default_rng(77)
-    series, ells, plants = W.batch_series(rng, 20, 600, 4000, ells=(16, 64, 128, 256))
+    series, ells, plants = W.batch_series(rng, 20, 600, 4000, ells=(16, 37, 64, 128, 201, 256))
     ts = [_dev(T, torch_dev) for T in series]
     for rep in range(2):                    # second call replays the captured graph
         res = ctx.motif_batch(ts, ells, precision=prec)
