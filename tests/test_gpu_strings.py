@@ -183,6 +183,7 @@ def test_lightbulb_errors(ctx, torch_dev):
 
 @pytest.mark.parametrize("mode,n,k,sigma,iterations,columns,seed", [
     ("most", 900, 24, 4, 16, 6, 7),       # one batch, keys tagged with the iteration
+    ("most", 500, 20, 4, 1, 4, 9),        # a single iteration: plain sort, no tag
     ("most", 300, 12, 4, 300, 5, 3),      # two batches (at most 256 iterations each)
     ("most", 400, 40, 4, 6, 32, 5),       # 64 key bits: no room for the tag, segmented sort
     ("least", 300, 16, 2, 40, 12, 11),    # codes against complements (600 rows)
