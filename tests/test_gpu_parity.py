@@ -261,6 +261,50 @@ def test_motif_batch_matches_oracle(ctx, torch_dev, tile, prec):
     assert ctx.stats().valid_pairs == sum(W.valid_pairs_motif(len(T), e, e) for T, e in zip(series, ells))
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16", "i8"])
+def test_radius_boundary_is_inclusive_to_the_last_bit(ctx, torch_dev, tile, prec):
+    """R^2 equal to a pair's canonical d^2 keeps that pair; the next double
+    below drops it (the screen's thresholds carry the bound and a margin, the
+    FP64 verifier decides)."""
+    rng = np.random.default_rng(21)
+    if prec == "i8":
+        X = rng.integers(-3, 4, (900, 40), dtype=np.int8)
+    else:
+        X = rng.normal(0, 1, (900, 40)).astype(np.float32)
+    P, D = oracle.frnn(X, float(np.inf))
+    r2 = float(np.sort(D)[40])                     # the 41st smallest d^2 (ties at it included)
+    at = {tuple(p) for p in P[D == r2].tolist()}
+    for R2, inside in ((r2, True), (float(np.nextafter(r2, -np.inf)), False)):
+        _, fr = ctx.points(_dev(X, torch_dev), R2=R2, precision=prec, want_pair=False)
+        got = {tuple(p) for p in fr[0].cpu().numpy().tolist()}
+        assert (at <= got) if inside else not (at & got), (R2, inside)
+        _check_frnn(fr, oracle.frnn(X, R2))
+
+
+def test_candidate_buffers_grow_and_the_answers_stay_exact(torch_dev):
+    """More candidates than the internal buffers hold (closest-pair
+    candidates 2^18, radius candidates 2^20 by default): the call grows them,
+    runs again, and returns the exact answers (a fresh context, so the
+    buffers start at their defaults)."""
+    import paper_1407_5609_amd as cp
+    c = cp.Context(0)
+    try:
+        # 1200 identical rows: all 719,400 pairs tie at d^2 = 0
+        X = np.tile(np.random.default_rng(3).normal(0, 1, (1, 16)).astype(np.float32), (1200, 1))
+        best, _ = c.points(_dev(X, torch_dev), precision="bf16")
+        assert (best.i, best.j, best.d2) == (0, 1, 0.0)
+        assert c.stats().reruns >= 1
+        # every one of 1,279,200 pairs within the radius
+        Y = np.random.default_rng(4).normal(0, 1, (1600, 8)).astype(np.float32)
+        best, fr = c.points(_dev(Y, torch_dev), R2=1e9, precision="bf16", cap=1 << 21)
+        assert c.stats().reruns >= 1
+        _check_pair(best, oracle.closest_pair(Y))
+        _check_frnn(fr, oracle.frnn(Y, 1e9))
+        assert len(fr[0]) == 1600 * 1599 // 2
+    finally:
+        c.close()
+
+
 # ---------------------------------------------------------------------------
 # error paths (forced from the host; every kernel still exits normally)
 # ---------------------------------------------------------------------------
