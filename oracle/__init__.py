@@ -44,6 +44,8 @@ def lib():
         for nm in ("orc_cpp_f32", "orc_cpp_f64", "orc_cpp_i8"):
             getattr(L, nm).restype = C.c_int
             getattr(L, nm).argtypes = [_p, _i64, _i64, _i64, _i64, _p, _p, _p]
+        L.orc_cpp_f64_lanes.restype = C.c_int
+        L.orc_cpp_f64_lanes.argtypes = [_p, _i64, _i64, _i64, _i64, _p, _p, _p]
         for nm in ("orc_frnn_f32", "orc_frnn_f64", "orc_frnn_i8"):
             getattr(L, nm).restype = _i64
             getattr(L, nm).argtypes = [_p, _i64, _i64, _i64, _i64, C.c_double, _p, _p, _i64]
@@ -122,6 +124,22 @@ def closest_pair(X: np.ndarray, excl: int = 1):
     return oi.value, oj.value, od.value
 
 
+def closest_pair_lanes(X: np.ndarray, excl: int = 1):
+    """closest_pair for float64 rows with SIMD lanes across pairs j: each
+    pair's arithmetic and the tie rule are those of closest_pair, so the
+    result is the same bit for bit; only faster on large inputs."""
+    X, n, d, ld = _rows(X)
+    if X.dtype != np.float64:
+        raise TypeError("closest_pair_lanes takes float64 rows")
+    oi, oj, od = _i64(), _i64(), C.c_double()
+    rc = lib().orc_cpp_f64_lanes(X.ctypes.data, n, d, ld, int(excl), C.byref(oi), C.byref(oj), C.byref(od))
+    if rc == NOPAIR:
+        return None
+    if rc != 0:
+        raise RuntimeError(f"oracle closest pair failed: {rc}")
+    return oi.value, oj.value, od.value
+
+
 def frnn(X: np.ndarray, R2: float, excl: int = 1):
     """All pairs i<j (j-i>=excl) with canonical d2 <= R2, sorted by (i, j).
     Returns (pairs int64 [m,2], d2 [m])."""
@@ -172,14 +190,15 @@ def znorm(T: np.ndarray, ell: int):
     return Xhat, mu, sg
 
 
-def motif(T: np.ndarray, ell: int, excl: int | None = None, R2: float | None = None):
+def motif(T: np.ndarray, ell: int, excl: int | None = None, R2: float | None = None, lanes: bool = False):
     """Motif of a series: closest pair of z-normalised windows with j-i >= excl
     (default excl = ell), plus all admissible pairs with d2 <= R2 if R2 given.
+    lanes=True takes the closest pair from closest_pair_lanes (same result).
     Returns (best (i, j, d2) or None, frnn (pairs, d2) or None)."""
     if excl is None or excl <= 0:
         excl = ell
     Xhat, _, _ = znorm(T, ell)
-    best = closest_pair(Xhat, excl)
+    best = closest_pair_lanes(Xhat, excl) if lanes else closest_pair(Xhat, excl)
     fr = frnn(Xhat, R2, excl) if R2 is not None and R2 >= 0 else None
     return best, fr
 

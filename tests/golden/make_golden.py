@@ -9,7 +9,8 @@ Usage:  python tests/golden/make_golden.py [points|motif|walk|strings|two_locus|
         (no argument: all). Threads: ORACLE_THREADS (default: all cores).
 
 Run times on 8 cores (latency-bound scalar FP64): points < 1 s, motif ~4 min,
-walk ~45 min, snp ~20 min, mixture ~1 h (one nearest-neighbour pass), batch sample ~10 min.
+walk ~45 min, snp ~20 min, mixture ~1 h (one nearest-neighbour pass), batch (all 512 series,
+lane-parallel closest pair) ~30 min.
 """
 import json
 import math
@@ -159,28 +160,23 @@ def mixture():
         "frnn": _frnn_obj(pairs, dd), "oracle_seconds": time.time() - t})
 
 
-BATCH_SAMPLE = 12
-
-
-def batch_sample_indices(count=512):
-    rng = np.random.default_rng(W.MASTER_SEED + 4)
-    return sorted(int(v) for v in rng.choice(count, BATCH_SAMPLE, replace=False))
-
-
 def batch():
+    """Every series of the batch: z-normalised windows and their closest pair
+    by the oracle's lane-parallel brute force (closest_pair_lanes, equal bit
+    for bit to the plain loop; tests/test_oracle_pins.py checks that)."""
     c = W.cfg_batch()
     t = time.time()
     out = []
-    for s in batch_sample_indices(len(c["series"])):
-        T, ell = c["series"][s], c["ells"][s]
-        best, _ = oracle.motif(T, ell)
+    for s, (T, ell) in enumerate(zip(c["series"], c["ells"])):
+        best, _ = oracle.motif(T, ell, lanes=True)
         out.append({"series": s, "len": int(T.shape[0]), "ell": int(ell),
                     "plant": list(c["plants"][s]),
                     "closest_pair": {"i": best[0], "j": best[1], "d2": _hex(best[2])}})
-        print("batch series", s, "done", time.time() - t, flush=True)
+        print("batch series", s, "len", int(T.shape[0]), "ell", int(ell), "done", round(time.time() - t, 1),
+              flush=True)
     _write(c["name"], {
-        "workload": c["name"], "source": "oracle.motif on a seeded sample of workloads.cfg_batch series",
-        "sample": out, "oracle_seconds": time.time() - t})
+        "workload": c["name"], "source": "oracle.motif(lanes=True) on every workloads.cfg_batch series",
+        "series": out, "oracle_seconds": time.time() - t})
 
 
 JOBS = {"points": points, "motif": motif, "walk": walk, "strings": strings, "two_locus": two_locus, "snp": snp,

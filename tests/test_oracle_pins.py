@@ -599,3 +599,43 @@ def test_lightbulb_least_against_brute_force():
     assert got_total == total
     u, i, j = min(((sum(S[a] == S[b]), a, b) for a, b in cands), key=lambda t: (t[0], t[1], t[2]))
     assert got_best == (i, j, int(u))
+
+
+# --------------------------------------------------------------------------
+# the lane-parallel closest pair (used for the large batch's expected values)
+# --------------------------------------------------------------------------
+
+def _lane_cases():
+    rng = np.random.default_rng(7)
+    out = []
+    for n, d, excl in [(2, 1, 1), (3, 5, 1), (9, 2, 1), (37, 7, 3), (64, 16, 64), (65, 16, 64), (130, 33, 1),
+                       (257, 65, 40), (300, 128, 128), (1001, 12, 500)]:
+        X = rng.normal(0, 1, (n, d))
+        if n > 10:
+            X[n // 3] = X[n // 2]                            # an exact duplicate
+            X[n - 1] = X[1]                                  # a second one, later in the order
+        out.append((X, excl))
+    # integer coordinates: exact ties at d2 = 1, first of them must win
+    X = np.array([[5, 5], [9, 9], [0, 0], [6, 5], [1, 0], [20, 20], [21, 20]], dtype=np.float64)
+    out.append((X, 1))
+    out.append((np.ascontiguousarray(X[::-1]), 1))
+    return out
+
+
+@pytest.mark.parametrize("case", range(len(_lane_cases())))
+def test_lanes_closest_pair_equals_the_plain_loop(case):
+    X, excl = _lane_cases()[case]
+    assert oracle.closest_pair_lanes(X, excl) == oracle.closest_pair(X, excl)
+
+
+def test_lanes_closest_pair_on_windows_and_strides():
+    rng = np.random.default_rng(8)
+    T = W.random_walk(rng, 3000)
+    for ell in (16, 64, 100):
+        Xhat, _, _ = oracle.znorm(T, ell)
+        assert oracle.closest_pair_lanes(Xhat, ell) == oracle.closest_pair(Xhat, ell)
+        assert oracle.motif(T, ell, lanes=True) == oracle.motif(T, ell)
+    big = rng.normal(0, 1, (200, 40))
+    view = big[:, :33]                                        # rows with a stride larger than d
+    assert oracle.closest_pair_lanes(view, 2) == oracle.closest_pair(np.ascontiguousarray(view), 2)
+    assert oracle.closest_pair_lanes(rng.normal(0, 1, (5, 3)), 5) is None
