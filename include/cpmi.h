@@ -135,9 +135,14 @@ int cpmi_closest_pair(cpmi_ctx *ctx, const void *pts, int dtype, int64_t n, int6
 /* Fixed-radius pairs (Section 3.5, MPR-FRNNS emits j into N(i) and i into N(j)
  * when d <= R): every pair i<j with canonical d2 <= R2, sorted by (i, j).
  * R2 is the squared radius (callers pass fl(R*R); for int8 data an integer).
- * pairs: device int64 [cap][2]; d2: device double [cap] or NULL; count_out:
- * host. If the count exceeds cap, nothing is written to pairs/d2, *count_out
- * holds the count and ERR_CAPACITY is returned (call again with cap >= count). */
+ * pairs: device int64 [cap][2] (may be NULL when cap == 0); d2: device
+ * double [cap] or NULL; count_out: host. If the count exceeds cap, nothing is
+ * written to pairs/d2, *count_out holds the count and ERR_CAPACITY is
+ * returned (call again with cap >= count). The count is exact at any size
+ * (64-bit, also beyond 2^32 pairs); one call returns at most 2^28 pairs: above
+ * that, or when more than 2^28 pairs lie within the screening bound of R2
+ * (the pairs are then counted, not stored), ERR_CAPACITY is returned with the
+ * exact count whatever cap is. */
 int cpmi_frnn(cpmi_ctx *ctx, const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, double R2,
               int precision, void *stream, int64_t *pairs, double *d2, int64_t cap, int64_t *count_out);
 

@@ -49,6 +49,8 @@ def lib():
         for nm in ("orc_frnn_f32", "orc_frnn_f64", "orc_frnn_i8"):
             getattr(L, nm).restype = _i64
             getattr(L, nm).argtypes = [_p, _i64, _i64, _i64, _i64, C.c_double, _p, _p, _i64]
+        L.orc_frnn_count_f32.restype = _i64
+        L.orc_frnn_count_f32.argtypes = [_p, _i64, _i64, _i64, _i64, C.c_double]
         L.orc_nn_f32.restype = C.c_int
         L.orc_nn_f32.argtypes = [_p, _i64, _i64, _i64, _p]
         L.orc_matches.restype = _i64
@@ -158,6 +160,14 @@ def frnn(X: np.ndarray, R2: float, excl: int = 1):
                 dd = dd.astype(np.int64)
             return pairs, dd
         cap = int(cnt)
+
+
+def frnn_count(X: np.ndarray, R2: float, excl: int = 1) -> int:
+    """Number of pairs i<j (j-i>=excl) with canonical d2 <= R2 (float32 rows)."""
+    X, n, d, ld = _rows(X)
+    if X.dtype != np.float32:
+        raise TypeError("frnn_count takes float32 points")
+    return int(lib().orc_frnn_count_f32(X.ctypes.data, n, d, ld, int(excl), float(R2)))
 
 
 def nearest_neighbour_d2(X: np.ndarray) -> np.ndarray:

@@ -410,6 +410,18 @@ int64_t orc_frnn_i8(const int8_t *X, int64_t n, int64_t d, int64_t ld, int64_t e
     ORC_FRNN_BODY((double)orc_d2_i8(X, d, ld, i, j))
 }
 
+/* Number of pairs i<j (j-i >= excl) with d^2 <= R2, without listing them
+ * (Section 3.5's output size; |N(i)| summed over i is twice this). */
+int64_t orc_frnn_count_f32(const float *X, int64_t n, int64_t d, int64_t ld, int64_t excl, double R2)
+{
+    if (excl < 1) excl = 1;
+    int64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : total)
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + excl; j < n; ++j) total += orc_d2_f32(X, d, ld, i, j) <= R2;
+    return total;
+}
+
 /* ------------------------------------------------------------------------ */
 /* nearest-neighbour squared distance of every point (over all j != i).      */
 /* Used only to derive a workload's radius from the data; each unordered     */

@@ -261,7 +261,7 @@ class Context:
             d2 = torch.empty(cap, dtype=torch.float64, device=f"cuda:{self.device}")
             cnt = C.c_int64(0)
             rc = fn(pairs, d2, cap, cnt)
-            if rc == ERR_CAPACITY:
+            if rc == ERR_CAPACITY and cnt.value > cap:
                 cap = int(cnt.value)
                 continue
             return rc, pairs[:cnt.value], d2[:cnt.value]
@@ -322,6 +322,17 @@ class Context:
                                                 C.c_void_p(D.data_ptr()), k, C.byref(cnt)), cap)
         self._check(rc)
         return pairs, d2
+
+    def frnn_count(self, pts, R2: float, precision="auto", stream=None) -> int:
+        """Number of pairs within the radius, from cpmi_frnn with no room for
+        pairs (the first call of the two-call protocol; exact beyond 2^32)."""
+        dt, n, d, ld = self._points_args(pts)
+        cnt = C.c_int64(0)
+        rc = _lib.cpmi_frnn(self._h, C.c_void_p(pts.data_ptr()), dt, n, d, ld, float(R2), _prec(precision),
+                            _stream_ptr(stream), None, None, 0, C.byref(cnt))
+        if rc != ERR_CAPACITY:
+            self._check(rc)
+        return int(cnt.value)
 
     def points(self, pts, R2: float | None = None, precision="auto", stream=None, cap: int = 1 << 16,
                want_pair: bool = True):

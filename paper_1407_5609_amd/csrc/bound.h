@@ -82,6 +82,14 @@ __host__ __device__ inline float f32_up(double x)
     return f;
 }
 
+// Largest float <= x.
+__host__ __device__ inline float f32_down(double x)
+{
+    float f = (float)x;
+    if ((double)f > x) f = nextafterf(f, -INFINITY);
+    return f;
+}
+
 // Relative/absolute margin for one FP64 addition or subtraction of a and b.
 __host__ __device__ inline double add_margin(double a, double b)
 {

@@ -37,6 +37,20 @@ struct DevBuf {
     size_t cap = 0;
 };
 
+// Device memory of one exact search. The context owns one set, grown on
+// demand; the allocation-free entry point carves a set out of the static
+// scratch array instead (Arena).
+struct Work {
+    DevBuf xs, shat, bmax, musg, probs, jobs, tiles, tile_min, sel, candR, candU, cand_d2, keys, vals, cnt, ubits, res,
+        mrowstat;
+};
+
+// Bump allocation over a fixed device range.
+struct Arena {
+    char *base = nullptr;
+    size_t size = 0, used = 0;
+};
+
 struct HostProb {
     int64_t n = 0, d = 0, ld = 0;   // rows, dimension, source stride
     int64_t excl = 1;
@@ -65,8 +79,14 @@ struct TuneEntry {
     int prec, kb, rb, value;
 };
 
-constexpr int NCNT = 4;  // counters: radius candidates, pair candidates, selected tiles, radius pairs
-enum { C_R = 0, C_U = 1, C_SEL = 2, C_OUT = 3 };
+// 64-bit device counters: radius candidates, pair candidates, selected tiles,
+// verified radius pairs, radius pairs counted by the screen alone
+constexpr int NCNT = 5;
+enum { C_R = 0, C_U = 1, C_SEL = 2, C_OUT = 3, C_IN = 4 };
+// Largest candidate or output buffer a search grows to (entries). A radius
+// search whose candidates exceed it is re-run in the counting form, which
+// gives the exact number of pairs without storing them.
+constexpr uint64_t CAND_MAX = 1ull << 28;
 
 }  // namespace
 
@@ -77,8 +97,8 @@ struct cpmi_ctx {
     int tile_override[4] = {0, 0, 0, 0};
     std::vector<TuneEntry> tuned;  // autotuner results (cache file and cpmi_autotune)
 
-    DevBuf xs, shat, bmax, musg, probs, jobs, tiles, tile_min, sel, candR, candU, cand_d2, keys, vals, cnt, ubits, res;
-    uint32_t capR = 1u << 20, capU = 1u << 18, capOut = 1u << 20;
+    Work w;  // device memory of the searches (grown on demand)
+    uint64_t capR = 1u << 20, capU = 1u << 18, capOut = 1u << 20;
 
     // host mirrors
     void *pinned = nullptr;  // counters + results read back
@@ -103,7 +123,7 @@ struct cpmi_ctx {
     int prune_q = 0;
     double prune_f = 10.0;
     uint64_t prune_seed = 0;
-    DevBuf mD, mperm, miperm, mlo, mhi, mrefs, msort, mrowstat;
+    DevBuf mD, mperm, miperm, mlo, mhi, mrefs, msort;
     // the block intervals read back (pinned; valid once evlohi has completed)
     double *plohi = nullptr;
     size_t plohi_cap = 0;
@@ -380,20 +400,42 @@ void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t
 
 struct RunOut {
     std::vector<ResDev> res;
-    uint32_t cnt[NCNT];
+    uint64_t cnt[NCNT];
+    bool counted = false;   // radius search ran in the counting form: pairs not stored
+    // pairs within the radius (exact)
+    uint64_t radius_pairs() const { return cnt[C_OUT] + (counted ? cnt[C_IN] : 0); }
 };
+
+// Slice of `bytes` of the arena for b (no allocation).
+int take(cpmi_ctx *c, Arena &ar, DevBuf &b, size_t bytes)
+{
+    if (b.p && b.cap >= bytes) return CPMI_OK;
+    const size_t want = (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+    if (ar.used + want > ar.size)
+        return fail(c, CPMI_ERR_CAPACITY, "the search needs more than the %zu bytes of static scratch", ar.size);
+    b.p = ar.base + ar.used;
+    b.cap = want;
+    ar.used += want;
+    return CPMI_OK;
+}
 
 // Launch the whole exact search for the problems in hp; synchronises once.
 // `forced` (optional) is a tile list built by the caller (reference-point
 // pruning) with its first `forced_nfull` entries full tiles; it bypasses the
 // list cache. `reuse_operand` skips the row preparation: the screen operand
 // and row scalars of the previous call (same problems, precision and tile)
-// are still in the workspace.
+// are still in the workspace. With an arena, every device buffer is a slice
+// of it (nothing is allocated; a search that does not fit fails with
+// CPMI_ERR_CAPACITY) and the context's workspace and list cache are untouched.
 int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool want_cpp, bool want_frnn,
                hipStream_t st, bool batch_graph, RunOut &ro, const std::vector<uint64_t> *forced = nullptr,
-               int64_t forced_nfull = 0, bool reuse_operand = false, const std::function<void()> &while_busy = {})
+               int64_t forced_nfull = 0, bool reuse_operand = false, const std::function<void()> &while_busy = {},
+               Arena *ar = nullptr)
 {
     bool busy_done = false;
+    Work local;
+    Work &W = ar ? local : c->w;
+    auto get = [&](DevBuf &b, size_t bytes) { return ar ? take(c, *ar, b, bytes) : ensure(c, b, bytes); };
     const int64_t np = (int64_t)hp.size();
     const int esz = elem_bytes(prec);
     // ---- workspace layout
@@ -411,14 +453,14 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         if (h.motif) mu_b += (size_t)h.npad * 8;
     }
     int rc;
-    if ((rc = ensure(c, c->xs, xs_b))) return rc;
-    if ((rc = ensure(c, c->shat, sh_b))) return rc;
-    if ((rc = ensure(c, c->bmax, bm_b))) return rc;
-    if ((rc = ensure(c, c->musg, 2 * mu_b))) return rc;
-    if ((rc = ensure(c, c->probs, np * sizeof(Prob)))) return rc;
-    if ((rc = ensure(c, c->res, np * sizeof(ResDev)))) return rc;
-    if ((rc = ensure(c, c->ubits, np * 8))) return rc;
-    if ((rc = ensure(c, c->cnt, NCNT * 4))) return rc;
+    if ((rc = get(W.xs, xs_b))) return rc;
+    if ((rc = get(W.shat, sh_b))) return rc;
+    if ((rc = get(W.bmax, bm_b))) return rc;
+    if ((rc = get(W.musg, 2 * mu_b))) return rc;
+    if ((rc = get(W.probs, np * sizeof(Prob)))) return rc;
+    if ((rc = get(W.res, np * sizeof(ResDev)))) return rc;
+    if ((rc = get(W.ubits, np * 8))) return rc;
+    if ((rc = get(W.cnt, NCNT * 8))) return rc;
 
     // ---- tile list (cached by shape)
     std::vector<int64_t> key{(int64_t)tile, np};
@@ -429,22 +471,15 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         key.push_back(h.split);
         key.push_back(h.na);
     }
-    if (forced) {
-        const std::vector<uint64_t> &tl = *forced;
-        c->nfull = forced_nfull;
-        // pairs of the timed launch: the full tiles, or every tile when all are partial
-        const int64_t nt = forced_nfull > 0 ? forced_nfull : (int64_t)tl.size();
+    // pairs of the timed launch: the full tiles, or every tile when all are partial
+    auto timed_pairs = [&](const std::vector<uint64_t> &tl, int64_t nf) {
+        const int64_t nt = nf > 0 ? nf : (int64_t)tl.size();
         int64_t nreal = 0;
         for (int64_t k = 0; k < nt; ++k) nreal += tl[k] != TILE_NONE;
-        c->nfull_pairs = nreal * (int64_t)tile * tile;
-        if ((rc = ensure(c, c->tiles, std::max<size_t>(tl.size(), 1) * 8))) return rc;
-        if ((rc = ensure(c, c->tile_min, std::max<size_t>(tl.size(), 1) * 4))) return rc;
-        if ((rc = ensure(c, c->sel, std::max<size_t>(tl.size(), 1) * 8))) return rc;
-        if (!tl.empty()) HIPCHK(c, hipMemcpyAsync(c->tiles.p, tl.data(), tl.size() * 8, hipMemcpyHostToDevice, st));
-        c->ntiles = (int64_t)tl.size();
-        c->tiles_key.clear();  // the cached list is gone
-    } else if (key != c->tiles_key) {
-        // the screen kernels index the tile list with 32-bit integers
+        return nreal * (int64_t)tile * tile;
+    };
+    // the screen kernels index the tile list with 32-bit integers
+    auto list_fits = [&]() {
         double est = 0.0;
         for (auto &h : hp) {
             const double nT = std::ceil((double)h.n / tile);
@@ -452,30 +487,62 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         }
         if (est > 2147483647.0 - 1048576.0)
             return fail(c, CPMI_ERR_ARG, "problem too large for one screen (%.3g tiles; at most 2^31)", est);
-        std::vector<uint64_t> tl;
-        int64_t nf = 0;
-        build_tiles(hp, tile, tl, &nf);
-        c->nfull = nf;
-        const int64_t nt = nf > 0 ? nf : (int64_t)tl.size();
-        int64_t nreal = 0;
-        for (int64_t k = 0; k < nt; ++k) nreal += tl[k] != TILE_NONE;
-        c->nfull_pairs = nreal * (int64_t)tile * tile;
-        if ((rc = ensure(c, c->tiles, tl.size() * 8))) return rc;
-        if ((rc = ensure(c, c->tile_min, tl.size() * 4))) return rc;
-        if ((rc = ensure(c, c->sel, tl.size() * 8))) return rc;
-        if (!tl.empty()) HIPCHK(c, hipMemcpy(c->tiles.p, tl.data(), tl.size() * 8, hipMemcpyHostToDevice));
-        c->ntiles = (int64_t)tl.size();
-        c->tiles_key = key;
+        return (int)CPMI_OK;
+    };
+    int64_t ntiles, nfull, nfull_pairs;
+    if (forced || ar) {
+        std::vector<uint64_t> built;
+        if (!forced) {
+            if ((rc = list_fits())) return rc;
+            build_tiles(hp, tile, built, &forced_nfull);
+        }
+        const std::vector<uint64_t> &tl = forced ? *forced : built;
+        nfull = forced_nfull;
+        nfull_pairs = timed_pairs(tl, forced_nfull);
+        if ((rc = get(W.tiles, std::max<size_t>(tl.size(), 1) * 8))) return rc;
+        if ((rc = get(W.tile_min, std::max<size_t>(tl.size(), 1) * 4))) return rc;
+        if ((rc = get(W.sel, std::max<size_t>(tl.size(), 1) * 8))) return rc;
+        if (!tl.empty()) HIPCHK(c, hipMemcpyAsync(W.tiles.p, tl.data(), tl.size() * 8, hipMemcpyHostToDevice, st));
+        if (!tl.empty() && !forced) HIPCHK(c, hipStreamSynchronize(st));   // `built` is released on return
+        ntiles = (int64_t)tl.size();
+        if (!ar) c->tiles_key.clear();  // the cached list is gone
+    } else {
+        if (key != c->tiles_key) {
+            if ((rc = list_fits())) return rc;
+            std::vector<uint64_t> tl;
+            int64_t nf = 0;
+            build_tiles(hp, tile, tl, &nf);
+            c->nfull = nf;
+            c->nfull_pairs = timed_pairs(tl, nf);
+            if ((rc = get(W.tiles, tl.size() * 8))) return rc;
+            if ((rc = get(W.tile_min, tl.size() * 4))) return rc;
+            if ((rc = get(W.sel, tl.size() * 8))) return rc;
+            if (!tl.empty()) HIPCHK(c, hipMemcpy(W.tiles.p, tl.data(), tl.size() * 8, hipMemcpyHostToDevice));
+            c->ntiles = (int64_t)tl.size();
+            c->tiles_key = key;
+        }
+        ntiles = c->ntiles;
+        nfull = c->nfull;
+        nfull_pairs = c->nfull_pairs;
     }
-    const int64_t ntiles = c->ntiles;
-    const int64_t nfull = c->nfull;
+    // candidate and output capacities: the context's (grown on overflow), or
+    // what the arena has left (closest pair only: no radius buffers)
+    uint64_t capR = c->capR, capU = c->capU, capOut = c->capOut;
+    if (ar) {
+        if (want_frnn) return fail(c, CPMI_ERR_ARG, "the allocation-free search takes no radius");
+        capR = capOut = 0;
+        const size_t room = ar->size > ar->used + 6 * 256 ? ar->size - ar->used - 6 * 256 : 0;
+        capU = std::min<uint64_t>(1u << 20, room / (sizeof(Cand) + 8));
+        if (capU < 1024) return fail(c, CPMI_ERR_CAPACITY, "the static scratch has no room left for candidates");
+    }
+    bool count_mode = false;
 
     for (int attempt = 0; attempt < 4; ++attempt) {
-        if ((rc = ensure(c, c->candR, (size_t)c->capR * sizeof(Cand)))) return rc;
-        if ((rc = ensure(c, c->candU, (size_t)c->capU * sizeof(Cand)))) return rc;
-        if ((rc = ensure(c, c->cand_d2, (size_t)c->capU * 8))) return rc;
-        if ((rc = ensure(c, c->keys, (size_t)c->capOut * 8))) return rc;
-        if ((rc = ensure(c, c->vals, (size_t)c->capOut * 8))) return rc;
+        if ((rc = get(W.candR, (size_t)capR * sizeof(Cand)))) return rc;
+        if ((rc = get(W.candU, (size_t)capU * sizeof(Cand)))) return rc;
+        if ((rc = get(W.cand_d2, (size_t)capU * 8))) return rc;
+        if ((rc = get(W.keys, (size_t)capOut * 8))) return rc;
+        if ((rc = get(W.vals, (size_t)capOut * 8))) return rc;
 
         // ---- problem descriptors
         std::vector<Prob> P(np);
@@ -485,9 +552,9 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             const HostProb &h = hp[p];
             Prob &q = P[p];
             memset(&q, 0, sizeof q);
-            q.xs = (char *)c->xs.p + h.xs_off;
-            q.shat = (char *)c->shat.p + h.sh_off;
-            q.bmax = (const float4 *)((char *)c->bmax.p + h.bm_off);
+            q.xs = (char *)W.xs.p + h.xs_off;
+            q.shat = (char *)W.shat.p + h.sh_off;
+            q.bmax = (const float4 *)((char *)W.bmax.p + h.bm_off);
             q.src = h.src;
             q.n = h.n;
             q.d = h.d;
@@ -503,8 +570,8 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             q.split = (int32_t)h.split;
             q.na = h.na;
             if (h.motif) {
-                q.mu = (const double *)((char *)c->musg.p + h.mu_off);
-                q.sigma = (const double *)((char *)c->musg.p + mu_b + h.mu_off);
+                q.mu = (const double *)((char *)W.musg.p + h.mu_off);
+                q.sigma = (const double *)((char *)W.musg.p + mu_b + h.mu_off);
                 SeriesJob j;
                 memset(&j, 0, sizeof j);
                 j.T = (const float *)h.src;
@@ -518,40 +585,40 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
                 j.bmax = (float4 *)q.bmax;
                 j.mu = (double *)q.mu;
                 j.sigma = (double *)q.sigma;
-                j.flags = &((ResDev *)c->res.p)[p].flags;
+                j.flags = &((ResDev *)W.res.p)[p].flags;
                 j.kpad = h.kpad;
                 j.iperm = h.iperm;
                 if (h.iperm) {
-                    if ((rc = ensure(c, c->mrowstat, (size_t)h.npad * sizeof(float4)))) return rc;
-                    j.rowstat = (float4 *)c->mrowstat.p;
+                    if ((rc = get(W.mrowstat, (size_t)h.npad * sizeof(float4)))) return rc;
+                    j.rowstat = (float4 *)W.mrowstat.p;
                 }
                 jobs.push_back(j);
             }
         }
-        HIPCHK(c, hipMemcpyAsync(c->probs.p, P.data(), np * sizeof(Prob), hipMemcpyHostToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(W.probs.p, P.data(), np * sizeof(Prob), hipMemcpyHostToDevice, st));
         if (!jobs.empty()) {
-            if ((rc = ensure(c, c->jobs, jobs.size() * sizeof(SeriesJob)))) return rc;
-            HIPCHK(c, hipMemcpyAsync(c->jobs.p, jobs.data(), jobs.size() * sizeof(SeriesJob), hipMemcpyHostToDevice,
+            if ((rc = get(W.jobs, jobs.size() * sizeof(SeriesJob)))) return rc;
+            HIPCHK(c, hipMemcpyAsync(W.jobs.p, jobs.data(), jobs.size() * sizeof(SeriesJob), hipMemcpyHostToDevice,
                                      st));
         }
 
-        const Prob *dprobs = (const Prob *)c->probs.p;
-        ResDev *dres = (ResDev *)c->res.p;
-        uint32_t *dcnt = (uint32_t *)c->cnt.p;
+        const Prob *dprobs = (const Prob *)W.probs.p;
+        ResDev *dres = (ResDev *)W.res.p;
+        u64c *dcnt = (u64c *)W.cnt.p;
         auto enqueue = [&]() {
             launch_reset_res(dres, np, st);
-            launch_fill_u32(dcnt, 0u, NCNT, st);
-            launch_fill_u64((uint64_t *)c->ubits.p, 0x7ff0000000000000ull, np, st);
+            launch_fill_u64((uint64_t *)dcnt, 0ull, NCNT, st);
+            launch_fill_u64((uint64_t *)W.ubits.p, 0x7ff0000000000000ull, np, st);
             if (reuse_operand) {
                 // the operand, row scalars and block maxima are in place
             } else if (!jobs.empty()) {
-                launch_fill_u32((uint32_t *)c->bmax.p, 0u, (int64_t)(bm_b / 4), st);
-                launch_prep_series((const SeriesJob *)c->jobs.p, (int64_t)jobs.size(), blk, prec, tile, st);
+                launch_fill_u32((uint32_t *)W.bmax.p, 0u, (int64_t)(bm_b / 4), st);
+                launch_prep_series((const SeriesJob *)W.jobs.p, (int64_t)jobs.size(), blk, prec, tile, st);
                 // windows in reference order (one series): block maxima from the per-row terms
                 if (jobs.size() == 1 && jobs[0].rowstat)
                     launch_block_max(jobs[0].rowstat, hp[0].npad, tile, (float4 *)P[0].bmax, st);
             } else {
-                launch_fill_u32((uint32_t *)c->bmax.p, 0u, (int64_t)(bm_b / 4), st);
+                launch_fill_u32((uint32_t *)W.bmax.p, 0u, (int64_t)(bm_b / 4), st);
                 const HostProb &h = hp[0];
                 launch_prep_points(h.src, h.src_i8 ? CPMI_I8 : CPMI_F32, h.n, h.d, h.ld, prec, P[0].xs ? (void *)P[0].xs : nullptr,
                                    h.kpad, h.npad, (void *)P[0].shat, (float4 *)P[0].bmax, tile, &dres[0].flags,
@@ -560,15 +627,16 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             ScreenArgs a;
             memset(&a, 0, sizeof a);
             a.probs = dprobs;
-            a.tiles = (const uint64_t *)c->tiles.p;
+            a.tiles = (const uint64_t *)W.tiles.p;
             a.ntiles = ntiles;
-            a.tile_min = (uint32_t *)c->tile_min.p;
-            a.candR = (Cand *)c->candR.p;
+            a.tile_min = (uint32_t *)W.tile_min.p;
+            a.candR = (Cand *)W.candR.p;
             a.cntR = dcnt + C_R;
-            a.capR = c->capR;
-            a.candU = (Cand *)c->candU.p;
+            a.capR = capR;
+            a.candU = (Cand *)W.candU.p;
             a.cntU = dcnt + C_U;
-            a.capU = c->capU;
+            a.capU = capU;
+            a.cntIn = count_mode ? dcnt + C_IN : nullptr;
             // the events bracket the dominant launch: the full-tile screen
             // (the masked one when every tile is partial, and the single
             // masked screen of the 128 tile)
@@ -590,32 +658,35 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
                 launch_screen(prec, tile, M_MIN, true, a, ntiles, st);
                 if (!batch_graph) hipEventRecord(c->es1, st);
             }
-            unsigned long long *ubits = want_cpp ? (unsigned long long *)c->ubits.p : nullptr;
+            unsigned long long *ubits = want_cpp ? (unsigned long long *)W.ubits.p : nullptr;
             if (want_cpp) launch_reduce_U(dprobs, a.tiles, ntiles, a.tile_min, prec, ubits, st);
-            launch_select(dprobs, a.tiles, ntiles, a.tile_min, prec, ubits, (uint64_t *)c->sel.p, dcnt + C_SEL, st);
+            launch_select(dprobs, a.tiles, ntiles, a.tile_min, prec, ubits, (uint64_t *)W.sel.p, dcnt + C_SEL, st);
             ScreenArgs b = a;
-            b.tiles = (const uint64_t *)c->sel.p;
+            b.tiles = (const uint64_t *)W.sel.p;
             b.sel_count = dcnt + C_SEL;
             b.U = (const double *)ubits;
             launch_screen(prec, tile, M_EMIT, true, b,
                           std::min<int64_t>(std::max<int64_t>(ntiles, 1), tile == 256 ? c->ncu : 2048), st);
             if (want_cpp) {
-                launch_verify_cpp(dprobs, (const Cand *)c->candU.p, dcnt + C_U, c->capU, prec, tile,
-                                  (double *)c->cand_d2.p, dres, st);
-                launch_pick_cpp(dprobs, (const Cand *)c->candU.p, dcnt + C_U, c->capU, (const double *)c->cand_d2.p,
+                launch_verify_cpp(dprobs, (const Cand *)W.candU.p, dcnt + C_U, capU, prec, tile,
+                                  (double *)W.cand_d2.p, dres, st);
+                launch_pick_cpp(dprobs, (const Cand *)W.candU.p, dcnt + C_U, capU, (const double *)W.cand_d2.p,
                                 dres, st);
             }
             if (want_frnn)
-                launch_verify_frnn(dprobs, (const Cand *)c->candR.p, dcnt + C_R, c->capR, prec, tile,
-                                   (uint64_t *)c->keys.p, (double *)c->vals.p, dcnt + C_OUT, c->capOut, dres, st);
+                launch_verify_frnn(dprobs, (const Cand *)W.candR.p, dcnt + C_R, capR, prec, tile,
+                                   (uint64_t *)W.keys.p, (double *)W.vals.p, dcnt + C_OUT, count_mode ? 0 : capOut,
+                                   dres, st);
         };
 
         HIPCHK(c, hipEventRecord(c->ev0, st));
         if (batch_graph) {
             std::vector<int64_t> gkey = key;
             gkey.push_back(prec);
-            gkey.push_back((int64_t)c->capR);
-            gkey.push_back((int64_t)c->capU);
+            gkey.push_back((int64_t)capR);
+            gkey.push_back((int64_t)capU);
+            gkey.push_back((int64_t)capOut);
+            gkey.push_back((int64_t)count_mode);
             if (!c->gexec || gkey != c->graph_key) {
                 if (c->gexec) {
                     hipGraphExecDestroy(c->gexec);
@@ -639,11 +710,19 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             enqueue();
         }
         HIPCHK(c, hipGetLastError());
-        const size_t rb = np * sizeof(ResDev) + NCNT * 4;
-        if ((rc = ensure_pinned(c, rb))) return rc;
-        HIPCHK(c, hipMemcpyAsync(c->pinned, c->res.p, np * sizeof(ResDev), hipMemcpyDeviceToHost, st));
-        HIPCHK(c, hipMemcpyAsync((char *)c->pinned + np * sizeof(ResDev), c->cnt.p, NCNT * 4, hipMemcpyDeviceToHost,
-                                 st));
+        // results and counters: into pinned memory, or (arena) pageable memory
+        const size_t rb = np * sizeof(ResDev) + NCNT * 8;
+        std::vector<unsigned char> pageable;
+        unsigned char *hostbuf;
+        if (ar) {
+            pageable.resize(rb);
+            hostbuf = pageable.data();
+        } else {
+            if ((rc = ensure_pinned(c, rb))) return rc;
+            hostbuf = (unsigned char *)c->pinned;
+        }
+        HIPCHK(c, hipMemcpyAsync(hostbuf, W.res.p, np * sizeof(ResDev), hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipMemcpyAsync(hostbuf + np * sizeof(ResDev), W.cnt.p, NCNT * 8, hipMemcpyDeviceToHost, st));
         HIPCHK(c, hipEventRecord(c->ev1, st));
         // host work that overlaps the search (once, not on reruns)
         if (while_busy && !busy_done) {
@@ -657,26 +736,41 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         ms = 0.f;
         if (!batch_graph) hipEventElapsedTime(&ms, c->es0, c->es1);
         c->stats.screen_ms = ms;
-        ro.res.assign((ResDev *)c->pinned, (ResDev *)c->pinned + np);
-        memcpy(ro.cnt, (char *)c->pinned + np * sizeof(ResDev), sizeof ro.cnt);
+        ro.res.assign((ResDev *)hostbuf, (ResDev *)hostbuf + np);
+        memcpy(ro.cnt, hostbuf + np * sizeof(ResDev), sizeof ro.cnt);
+        ro.counted = count_mode;
 
-        bool again = false;
-        if (ro.cnt[C_R] > c->capR) {
-            c->capR = ro.cnt[C_R] + ro.cnt[C_R] / 2 + 1024;
-            again = true;
-        }
-        if (ro.cnt[C_U] > c->capU) {
-            c->capU = ro.cnt[C_U] + ro.cnt[C_U] / 2 + 1024;
-            again = true;
-        }
-        if (ro.cnt[C_OUT] > c->capOut) {
-            c->capOut = ro.cnt[C_OUT] + ro.cnt[C_OUT] / 2 + 1024;
-            again = true;
-        }
         // a flagged input makes the candidate counts meaningless; report, don't grow
         bool flagged = false;
         for (auto &r : ro.res) flagged |= r.flags != 0;
-        if (again && !flagged) {
+        auto grown = [](uint64_t need) { return std::min<uint64_t>(need + need / 2 + 1024, CAND_MAX); };
+        bool again = false;
+        if (!flagged && ro.cnt[C_U] > capU) {
+            if (ar || ro.cnt[C_U] > CAND_MAX)
+                return fail(c, CPMI_ERR_CAPACITY, "%llu closest-pair candidates (at most %llu)",
+                            (unsigned long long)ro.cnt[C_U], (unsigned long long)(ar ? capU : CAND_MAX));
+            capU = c->capU = grown(ro.cnt[C_U]);
+            again = true;
+        }
+        if (!flagged && ro.cnt[C_R] > capR) {
+            if (ro.cnt[C_R] > CAND_MAX && !count_mode) {
+                // too many to store: count the pairs instead (the band of
+                // uncertain ones is verified, the rest proved by the screen)
+                count_mode = true;
+            } else if (ro.cnt[C_R] > CAND_MAX) {
+                return fail(c, CPMI_ERR_CAPACITY,
+                            "%llu radius candidates within the screening bound of R2 (at most %llu)",
+                            (unsigned long long)ro.cnt[C_R], (unsigned long long)CAND_MAX);
+            } else {
+                capR = c->capR = grown(ro.cnt[C_R]);
+            }
+            again = true;
+        }
+        if (!flagged && !count_mode && ro.cnt[C_OUT] > capOut && ro.cnt[C_OUT] <= CAND_MAX) {
+            capOut = c->capOut = grown(ro.cnt[C_OUT]);
+            again = true;
+        }
+        if (again) {
             c->stats.reruns++;
             continue;
         }
@@ -684,13 +778,13 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         c->stats.tiles_rescreened = ro.cnt[C_SEL];
         c->stats.cpp_candidates = ro.cnt[C_U];
         c->stats.frnn_candidates = ro.cnt[C_R];
-        c->stats.frnn_pairs = ro.cnt[C_OUT];
+        c->stats.frnn_pairs = (int64_t)ro.radius_pairs();
         c->stats.precision = prec;
         c->stats.tile = tile;
         int64_t vp = 0;
         for (auto &h : hp) vp += pairs_of(h);
         c->stats.valid_pairs = vp;
-        c->stats.screen_pairs = tile == 256 ? c->nfull_pairs : vp;
+        c->stats.screen_pairs = tile == 256 ? nfull_pairs : vp;
         float mr = 0.f;
         for (auto &r : ro.res) mr = std::max(mr, __builtin_bit_cast(float, r.ratio_bits));
         c->stats.max_err_over_bound = mr;
@@ -725,36 +819,42 @@ void fill_pair(const ResDev &r, cpmi_pair *out)
 }
 
 // Sort the verified radius pairs and copy them to the caller.
-int finish_frnn(cpmi_ctx *c, uint32_t count, hipStream_t st, int64_t *pairs, double *d2, int64_t cap,
+int finish_frnn(cpmi_ctx *c, const RunOut &ro, hipStream_t st, int64_t *pairs, double *d2, int64_t cap,
                 int64_t *count_out)
 {
-    if (count_out) *count_out = count;
-    if ((int64_t)count > cap) return fail(c, CPMI_ERR_CAPACITY, "%u pairs within the radius, capacity %lld", count, (long long)cap);
+    const uint64_t count = ro.radius_pairs();
+    if (count_out) *count_out = (int64_t)count;
+    if ((int64_t)count > cap)
+        return fail(c, CPMI_ERR_CAPACITY, "%llu pairs within the radius, capacity %lld", (unsigned long long)count,
+                    (long long)cap);
+    if (ro.counted || count > CAND_MAX)
+        return fail(c, CPMI_ERR_CAPACITY, "%llu pairs within the radius: more than one call returns (%llu)",
+                    (unsigned long long)count, (unsigned long long)CAND_MAX);
     if (count == 0) return CPMI_OK;
     int64_t mpad = 1;
     while (mpad < (int64_t)count) mpad <<= 1;
-    if ((size_t)mpad * 8 > c->keys.cap || (size_t)mpad * 8 > c->vals.cap) {
+    if ((size_t)mpad * 8 > c->w.keys.cap || (size_t)mpad * 8 > c->w.vals.cap) {
         // grow while keeping the verified pairs
         DevBuf nk, nv;
         HIPCHK(c, hipMalloc(&nk.p, mpad * 8));
         HIPCHK(c, hipMalloc(&nv.p, mpad * 8));
-        HIPCHK(c, hipMemcpyAsync(nk.p, c->keys.p, (size_t)count * 8, hipMemcpyDeviceToDevice, st));
-        HIPCHK(c, hipMemcpyAsync(nv.p, c->vals.p, (size_t)count * 8, hipMemcpyDeviceToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(nk.p, c->w.keys.p, (size_t)count * 8, hipMemcpyDeviceToDevice, st));
+        HIPCHK(c, hipMemcpyAsync(nv.p, c->w.vals.p, (size_t)count * 8, hipMemcpyDeviceToDevice, st));
         HIPCHK(c, hipStreamSynchronize(st));
-        hipFree(c->keys.p);
-        hipFree(c->vals.p);
-        c->keys.p = nk.p;
-        c->keys.cap = mpad * 8;
-        c->vals.p = nv.p;
-        c->vals.cap = mpad * 8;
+        hipFree(c->w.keys.p);
+        hipFree(c->w.vals.p);
+        c->w.keys.p = nk.p;
+        c->w.keys.cap = mpad * 8;
+        c->w.vals.p = nv.p;
+        c->w.vals.cap = mpad * 8;
         if (c->gexec) {
             hipGraphExecDestroy(c->gexec);
             c->gexec = nullptr;
             c->graph_key.clear();
         }
     }
-    launch_sort_pairs((uint64_t *)c->keys.p, (double *)c->vals.p, count, mpad, st);
-    launch_emit_pairs((const uint64_t *)c->keys.p, (const double *)c->vals.p, count, pairs, d2, st);
+    launch_sort_pairs((uint64_t *)c->w.keys.p, (double *)c->w.vals.p, count, mpad, st);
+    launch_emit_pairs((const uint64_t *)c->w.keys.p, (const double *)c->w.vals.p, count, pairs, d2, st);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));
     return CPMI_OK;
@@ -829,8 +929,8 @@ int prune_prepare(cpmi_ctx *c, HostProb &h, int tile, hipStream_t st)
     if ((rc = ensure(c, c->mlo, (size_t)nT * q * 8))) return rc;
     if ((rc = ensure(c, c->mhi, (size_t)nT * q * 8))) return rc;
     if ((rc = ensure(c, c->mrefs, (size_t)q * 4))) return rc;
-    if ((rc = ensure(c, c->keys, (size_t)n * 8))) return rc;  // sort scratch: indices
-    if ((rc = ensure(c, c->vals, (size_t)n * 8))) return rc;  // sorted keys
+    if ((rc = ensure(c, c->w.keys, (size_t)n * 8))) return rc;  // sort scratch: indices
+    if ((rc = ensure(c, c->w.vals, (size_t)n * 8))) return rc;  // sorted keys
     size_t tb = 0;
     HIPCHK(c, sort_ref_order(nullptr, &tb, nullptr, nullptr, nullptr, nullptr, n, st));
     if ((rc = ensure(c, c->msort, std::max<size_t>(tb, 1)))) return rc;
@@ -845,7 +945,7 @@ int prune_prepare(cpmi_ctx *c, HostProb &h, int tile, hipStream_t st)
     } else {
         launch_ref_dist(h.src, dtype, n, h.d, h.ld, (const int32_t *)c->mrefs.p, q, c->prune_f, D, st);
     }
-    HIPCHK(c, sort_ref_order(c->msort.p, &tb, D, (double *)c->vals.p, (int32_t *)c->keys.p, perm, n, st));
+    HIPCHK(c, sort_ref_order(c->msort.p, &tb, D, (double *)c->w.vals.p, (int32_t *)c->w.keys.p, perm, n, st));
     if (h.motif) launch_perm_finish(perm, (int32_t *)c->miperm.p, n, npad, st);
     launch_block_range(D, n, q, perm, tile, nT, (double *)c->mlo.p, (double *)c->mhi.p, st);
     HIPCHK(c, hipGetLastError());
@@ -1053,9 +1153,9 @@ int cpmi_destroy(cpmi_ctx *c)
     hipSetDevice(c->device);
     hipDeviceSynchronize();
     if (c->gexec) hipGraphExecDestroy(c->gexec);
-    DevBuf *bufs[] = {&c->xs,      &c->shat,  &c->bmax, &c->musg, &c->probs, &c->jobs, &c->tiles, &c->tile_min,
-                      &c->sel,     &c->candR, &c->candU, &c->cand_d2, &c->keys, &c->vals, &c->cnt, &c->ubits,
-                      &c->res,     &c->mD,    &c->mperm, &c->miperm, &c->mlo, &c->mhi, &c->mrefs, &c->msort, &c->mrowstat,
+    DevBuf *bufs[] = {&c->w.xs,      &c->w.shat,  &c->w.bmax, &c->w.musg, &c->w.probs, &c->w.jobs, &c->w.tiles, &c->w.tile_min,
+                      &c->w.sel,     &c->w.candR, &c->w.candU, &c->w.cand_d2, &c->w.keys, &c->w.vals, &c->w.cnt, &c->w.ubits,
+                      &c->w.res,     &c->mD,    &c->mperm, &c->miperm, &c->mlo, &c->mhi, &c->mrefs, &c->msort, &c->w.mrowstat,
                       &c->mZ,      &c->mflag, &c->lbA, &c->lbT, &c->lbC, &c->lbP, &c->lbK};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
@@ -1116,7 +1216,8 @@ int cpmi_points(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d, i
     if (dtype == CPMI_I8 && d > 32768) return fail(c, CPMI_ERR_ARG, "int8 dimension must be <= 32768 (int32 Gram)");
     if (d > (1 << 20)) return fail(c, CPMI_ERR_ARG, "dimension must be <= 2^20");
     if (!want_cpp && !want_frnn) return fail(c, CPMI_ERR_ARG, "nothing requested (best == NULL and R2 < 0)");
-    if (want_frnn && (!pairs || !count_out || cap < 0)) return fail(c, CPMI_ERR_ARG, "radius search needs pairs, cap and count_out");
+    if (want_frnn && ((cap > 0 && !pairs) || !count_out || cap < 0))
+        return fail(c, CPMI_ERR_ARG, "radius search needs count_out, cap >= 0 and pairs (unless cap == 0)");
     if (std::isnan(R2)) return fail(c, CPMI_ERR_ARG, "R2 is NaN");
     if (n < 2) {
         if (best) best->status = CPMI_ERR_NOPAIR, best->i = best->j = -1;
@@ -1148,7 +1249,7 @@ int cpmi_points(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d, i
         fill_pair(ro.res[0], best);
         if (best->status) return fail(c, best->status, "no admissible pair");
     }
-    if (want_frnn) return finish_frnn(c, ro.cnt[C_OUT], st, pairs, d2, cap, count_out);
+    if (want_frnn) return finish_frnn(c, ro, st, pairs, d2, cap, count_out);
     return CPMI_OK;
 }
 
@@ -1185,7 +1286,8 @@ int cpmi_motif(cpmi_ctx *c, const float *series, int64_t len, int64_t ell, int64
     if (ell > SERIES_MAX_ELL) return fail(c, CPMI_ERR_ARG, "ell must be <= %d", SERIES_MAX_ELL);
     if (len >= (1ll << 31) - 256) return fail(c, CPMI_ERR_ARG, "len must be below 2^31");
     if (!want_cpp && !want_frnn) return fail(c, CPMI_ERR_ARG, "nothing requested (best == NULL and R2 < 0)");
-    if (want_frnn && (!pairs || !count_out || cap < 0)) return fail(c, CPMI_ERR_ARG, "radius search needs pairs, cap and count_out");
+    if (want_frnn && ((cap > 0 && !pairs) || !count_out || cap < 0))
+        return fail(c, CPMI_ERR_ARG, "radius search needs count_out, cap >= 0 and pairs (unless cap == 0)");
     if (std::isnan(R2)) return fail(c, CPMI_ERR_ARG, "R2 is NaN");
     if (precision != CPMI_PREC_AUTO && precision != CPMI_PREC_F32 && precision != CPMI_PREC_BF16)
         return fail(c, CPMI_ERR_ARG, "motif precision must be AUTO, F32 or BF16");
@@ -1224,7 +1326,7 @@ int cpmi_motif(cpmi_ctx *c, const float *series, int64_t len, int64_t ell, int64
         fill_pair(ro.res[0], best);
         if (best->status) return fail(c, best->status, "no admissible pair");
     }
-    if (want_frnn) return finish_frnn(c, ro.cnt[C_OUT], st, pairs, d2, cap, count_out);
+    if (want_frnn) return finish_frnn(c, ro, st, pairs, d2, cap, count_out);
     return CPMI_OK;
 }
 
@@ -1774,11 +1876,11 @@ int cpmi_dbg_znorm(cpmi_ctx *c, const float *series, int64_t len, int64_t ell, i
     const int64_t N = len - ell + 1;
     const int32_t kpad = kpad_for(prec, ell, 128);
     const int64_t npad = (N + 255) / 256 * 256;
-    if ((rc = ensure(c, c->xs, (size_t)npad * kpad * elem_bytes(prec)))) return rc;
-    if ((rc = ensure(c, c->shat, (size_t)npad * 4))) return rc;
-    if ((rc = ensure(c, c->bmax, (size_t)(npad / 128) * 16))) return rc;
-    if ((rc = ensure(c, c->res, sizeof(ResDev)))) return rc;
-    if ((rc = ensure(c, c->jobs, sizeof(SeriesJob)))) return rc;
+    if ((rc = ensure(c, c->w.xs, (size_t)npad * kpad * elem_bytes(prec)))) return rc;
+    if ((rc = ensure(c, c->w.shat, (size_t)npad * 4))) return rc;
+    if ((rc = ensure(c, c->w.bmax, (size_t)(npad / 128) * 16))) return rc;
+    if ((rc = ensure(c, c->w.res, sizeof(ResDev)))) return rc;
+    if ((rc = ensure(c, c->w.jobs, sizeof(SeriesJob)))) return rc;
     SeriesJob j;
     memset(&j, 0, sizeof j);
     j.T = series;
@@ -1786,17 +1888,17 @@ int cpmi_dbg_znorm(cpmi_ctx *c, const float *series, int64_t len, int64_t ell, i
     j.ell = ell;
     j.npad = npad;
     j.blk_base = 0;
-    j.xs = c->xs.p;
-    j.shat = c->shat.p;
-    j.bmax = (float4 *)c->bmax.p;
+    j.xs = c->w.xs.p;
+    j.shat = c->w.shat.p;
+    j.bmax = (float4 *)c->w.bmax.p;
     j.mu = mu;
     j.sigma = sigma;
-    j.flags = &((ResDev *)c->res.p)->flags;
+    j.flags = &((ResDev *)c->w.res.p)->flags;
     j.kpad = kpad;
-    HIPCHK(c, hipMemcpyAsync(c->jobs.p, &j, sizeof j, hipMemcpyHostToDevice, st));
-    launch_reset_res((ResDev *)c->res.p, 1, st);
-    launch_fill_u32((uint32_t *)c->bmax.p, 0u, (npad / 128) * 4, st);
-    launch_prep_series((const SeriesJob *)c->jobs.p, 1, npad / SERIES_WPB, prec, 128, st);
+    HIPCHK(c, hipMemcpyAsync(c->w.jobs.p, &j, sizeof j, hipMemcpyHostToDevice, st));
+    launch_reset_res((ResDev *)c->w.res.p, 1, st);
+    launch_fill_u32((uint32_t *)c->w.bmax.p, 0u, (npad / 128) * 4, st);
+    launch_prep_series((const SeriesJob *)c->w.jobs.p, 1, npad / SERIES_WPB, prec, 128, st);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));
     return CPMI_OK;

@@ -62,21 +62,59 @@ __host__ __device__ inline uint32_t tile_I(uint64_t t) { return (uint32_t)(t >> 
 __host__ __device__ inline uint32_t tile_J(uint64_t t) { return (uint32_t)t & 0x3fffffu; }
 constexpr uint64_t TILE_NONE = ~0ull;
 
+typedef unsigned long long u64c;   // 64-bit device counter (atomicAdd operand)
+
 // Arguments of the Gram screen kernel.
 struct ScreenArgs {
     const Prob *probs;
     const uint64_t *tiles;     // tile list
     int64_t ntiles;            // entries (pass 1); pass 2 reads *sel_count
-    const uint32_t *sel_count; // pass 2: number of valid entries of `tiles`
+    const u64c *sel_count;     // pass 2: number of valid entries of `tiles` (below 2^31)
     uint32_t *tile_min;        // pass 1: per entry, min screen value (float or int32 bits)
     const double *U;           // pass 2: per problem closest-pair upper bound, or null (no pair search)
     Cand *candR;               // radius candidates
-    uint32_t *cntR;            // their counter (may exceed capR: the required size)
-    uint32_t capR;
+    u64c *cntR;                // their counter (may exceed capR: the required size)
+    uint64_t capR;
     Cand *candU;               // closest-pair candidates
-    uint32_t *cntU;
-    uint32_t capU;
+    u64c *cntU;
+    uint64_t capU;
+    // Counting form of the radius search (null: off). Pairs whose screen
+    // value alone proves d^2 <= r2 (D~ <= r2 - bound) are only counted here;
+    // the rest of the radius candidates (the band r2 - bound < D~ <= r2 +
+    // bound) are emitted to candR as usual.
+    u64c *cntIn;
 };
+
+// Wave-aggregated reservation of n slots per lane (called by every lane of
+// the wave, in wave-uniform control flow): one atomic add per wave and
+// counter. Returns this lane's first slot; lanes with n = 0 get an unused value.
+__device__ inline uint64_t wave_reserve(u64c *cnt, uint32_t n)
+{
+    const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    uint32_t incl = n;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    const uint32_t total = (uint32_t)__shfl((int)incl, 63, 64);
+    u64c base = 0;
+    if (total != 0) {
+        if (lane == 0) base = atomicAdd(cnt, (u64c)total);
+        base = __shfl(base, 0, 64);
+    }
+    return (uint64_t)base + (incl - n);
+}
+
+// Sum of n over the wave added to *cnt with one atomic (same calling rules).
+__device__ inline void wave_count(u64c *cnt, uint32_t n)
+{
+    uint32_t v = n;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
+    const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    if (lane == 0 && v != 0) atomicAdd(cnt, (u64c)v);
+}
 
 // Per-problem result of the verifier (device), reset before each run.
 struct ResDev {
@@ -144,15 +182,17 @@ void launch_screen(int prec, int tile, int mode, bool masked, const ScreenArgs &
 void launch_reduce_U(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min, int prec,
                      unsigned long long *Ubits, hipStream_t st);
 void launch_select(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min, int prec,
-                   const unsigned long long *Ubits, uint64_t *sel, uint32_t *sel_count, hipStream_t st);
+                   const unsigned long long *Ubits, uint64_t *sel, u64c *sel_count, hipStream_t st);
 
 // Candidate verification in canonical FP64 (exact int64 for int8).
-void launch_verify_cpp(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec, int tile,
+void launch_verify_cpp(const Prob *probs, const Cand *cand, const u64c *cnt, uint64_t cap, int prec, int tile,
                        double *cand_d2, ResDev *res, hipStream_t st);
-void launch_pick_cpp(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, const double *cand_d2,
+void launch_pick_cpp(const Prob *probs, const Cand *cand, const u64c *cnt, uint64_t cap, const double *cand_d2,
                      ResDev *res, hipStream_t st);
-void launch_verify_frnn(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec, int tile,
-                        uint64_t *keys, double *vals, uint32_t *out_cnt, uint32_t out_cap, ResDev *res,
+// out_cnt counts every verified pair within the radius; the first out_cap are
+// written to keys/vals (out_cap = 0: count only).
+void launch_verify_frnn(const Prob *probs, const Cand *cand, const u64c *cnt, uint64_t cap, int prec, int tile,
+                        uint64_t *keys, double *vals, u64c *out_cnt, uint64_t out_cap, ResDev *res,
                         hipStream_t st);
 // Sort m (key, value) pairs by key; arrays hold mpad >= m entries (mpad a power
 // of two), the tail is overwritten with sentinels.

@@ -179,7 +179,7 @@ __global__ __launch_bounds__(NTHREADS) void screen_kernel(ScreenArgs args)
         // every pair of the tile admissible? (min j - max i >= excl, all rows real)
         const bool full = (j0 - (i0 + TILE - 1) >= excl) && (i0 + TILE <= n) && (j0 + TILE <= n);
         const double E = tile_bound(P.bmax[I], P.bmax[J], P.kpad, P.d, PREC, SCREEN_EPILOGUE);
-        S thrU = -SINF, thrR = -SINF;
+        S thrU = -SINF, thrR = -SINF, thrIn = -SINF;
         if constexpr (MODE & M_EMIT) {
             if (args.U) {
                 const double u = args.U[p];
@@ -189,50 +189,71 @@ __global__ __launch_bounds__(NTHREADS) void screen_kernel(ScreenArgs args)
             if (P.r2 >= 0.0) {
                 if constexpr (PREC == P_I8) thrR = (S)fmin(floor(P.r2), 2147483646.0);
                 else thrR = f32_up(P.r2 + E + add_margin(P.r2, E));
+                if (args.cntIn) {
+                    if constexpr (PREC == P_I8) thrIn = thrR;   // exact: no band
+                    else thrIn = f32_down(P.r2 - E - add_margin(P.r2, E));
+                }
             }
         }
-        const S thr = thrU > thrR ? thrU : thrR;
-        S mn = SINF;
+        // every element of this lane: (row, column, screen value, admissible)
+        auto each = [&](auto f) {
 #pragma unroll
-        for (int b = 0; b < MB; ++b) {
-            const int jl = wn * WT + b * 32 + lrow;
-            const S sj = sh_sj[jl];
-            const int64_t gj = j0 + jl;
+            for (int b = 0; b < MB; ++b) {
+                const int jl = wn * WT + b * 32 + lrow;
+                const S sj = sh_sj[jl];
+                const int64_t gj = j0 + jl;
 #pragma unroll
-            for (int a = 0; a < MB; ++a) {
+                for (int a = 0; a < MB; ++a) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int il = wm * WT + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
-                    const int64_t gi = i0 + il;
-                    S dv;
-                    if constexpr (PREC == P_I8)
-                        dv = sh_si[il] + (sj - 2 * acc[a][b][r]);
-                    else
-                        dv = sh_si[il] + fmaf(-2.0f, acc[a][b][r], sj);
-                    bool ok = true;
-                    if (!full) {
-                        ok = (gj - gi >= excl) && (gi < n) && (gj < n);
-                        dv = ok ? dv : SINF;
-                    }
-                    if constexpr (MODE & M_MIN) mn = PREC == P_I8 ? (S)min((int)mn, (int)dv) : (S)fminf(mn, dv);
-                    if constexpr (MODE & M_EMIT) {
-                        if (ok && dv <= thr) {
-                            Cand cd;
-                            cd.i = (int32_t)gi;
-                            cd.j = (int32_t)gj;
-                            cd.dt = (float)dv;
-                            cd.p = p;
-                            if (dv <= thrU) {
-                                const uint32_t idx = atomicAdd(args.cntU, 1u);
-                                if (idx < args.capU) args.candU[idx] = cd;
-                            }
-                            if (dv <= thrR) {
-                                const uint32_t idx = atomicAdd(args.cntR, 1u);
-                                if (idx < args.capR) args.candR[idx] = cd;
-                            }
-                        }
+                    for (int r = 0; r < 16; ++r) {
+                        const int il = wm * WT + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
+                        const int64_t gi = i0 + il;
+                        S dv;
+                        if constexpr (PREC == P_I8)
+                            dv = sh_si[il] + (sj - 2 * acc[a][b][r]);
+                        else
+                            dv = sh_si[il] + fmaf(-2.0f, acc[a][b][r], sj);
+                        const bool ok = full || ((gj - gi >= excl) && (gi < n) && (gj < n));
+                        f(gi, gj, dv, ok);
                     }
                 }
+            }
+        };
+        S mn = SINF;
+        if constexpr (MODE & M_MIN) {
+            each([&](int64_t, int64_t, S dv, bool ok) {
+                dv = ok ? dv : SINF;
+                mn = PREC == P_I8 ? (S)min((int)mn, (int)dv) : (S)fminf(mn, dv);
+            });
+        }
+        if constexpr (MODE & M_EMIT) {
+            // count this lane's pairs, reserve them with one atomic per wave
+            // and counter, then write them
+            uint32_t nU = 0, nR = 0, nIn = 0;
+            each([&](int64_t, int64_t, S dv, bool ok) {
+                nU += ok & (dv <= thrU);
+                const bool in = ok & (dv <= thrIn);
+                nIn += in;
+                nR += ok & !in & (dv <= thrR);
+            });
+            if (args.cntIn) wave_count(args.cntIn, nIn);
+            uint64_t kU = wave_reserve(args.cntU, nU), kR = wave_reserve(args.cntR, nR);
+            if (__any(nU + nR != 0)) {
+                each([&](int64_t gi, int64_t gj, S dv, bool ok) {
+                    Cand cd;
+                    cd.i = (int32_t)gi;
+                    cd.j = (int32_t)gj;
+                    cd.dt = (float)dv;
+                    cd.p = p;
+                    if (ok & (dv <= thrU)) {
+                        if (kU < args.capU) args.candU[kU] = cd;
+                        ++kU;
+                    }
+                    if (ok & !(dv <= thrIn) & (dv <= thrR)) {
+                        if (kR < args.capR) args.candR[kR] = cd;
+                        ++kR;
+                    }
+                });
             }
         }
         if constexpr (MODE & M_MIN) {

@@ -15,10 +15,14 @@
 //     all 64 banks once (layout256.h);
 //   * 4 waves in a 2x2 grid, each owning 128x128 outputs as 4x4 32x32 MFMA
 //     blocks (256 accumulators per lane);
-//   * the epilogue takes, per accumulator row, the minimum over the four
-//     column blocks of s^_j - 2 G (one fma and half a min3 per element), adds
-//     s^_i once per row, and only when the wave's minimum is within a
-//     threshold scans the elements again to emit pairs.
+//   * FP32 and BF16: the row scalars are folded into the product (one extra
+//     matrix-core step per block starts the accumulators at
+//     -(s^_i + s^_j)/2), so the screen value is -2 acc and the tile minimum
+//     is -2 times the largest accumulator (half a max3 per element, no
+//     per-element arithmetic). INT8: s^_i + (s^_j - 2 G) in exact int32;
+//   * emission (pass 2) runs only when the wave's minimum is within a
+//     threshold: each lane counts its pairs, one atomic add per wave and
+//     counter reserves their slots, and a second scan writes them.
 #include "bound.h"
 #include "cpmi_internal.h"
 #include "layout256.h"
@@ -685,7 +689,7 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         if constexpr (MODE & M_EMIT) {
             const double E = tile_bound(P.bmax[I], P.bmax[J], P.kpad, P.d, PREC,
                                         FOLD ? SCREEN_FOLDED : SCREEN_EPILOGUE);
-            S thrU = -SINF, thrR = -SINF;
+            S thrU = -SINF, thrR = -SINF, thrIn = -SINF;
             if (args.U) {
                 const double u = args.U[p];
                 if constexpr (PREC == P_I8) thrU = (S)fmin(u, 2147483646.0);
@@ -694,44 +698,65 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
             if (P.r2 >= 0.0) {
                 if constexpr (PREC == P_I8) thrR = (S)fmin(floor(P.r2), 2147483646.0);
                 else thrR = f32_up(P.r2 + E + add_margin(P.r2, E));
+                if (args.cntIn) {
+                    if constexpr (PREC == P_I8) thrIn = thrR;   // exact: no band
+                    else thrIn = f32_down(P.r2 - E - add_margin(P.r2, E));
+                }
             }
             const S thr = thrU > thrR ? thrU : thrR;
             if (wmin(best) <= thr) {
+                // every element of this lane: (row, column, screen value, admissible)
+                auto each = [&](auto f) {
 #pragma clang loop unroll(full)
-                for (int a = 0; a < MB256; ++a) {
-                    int32_t oi[16] = {};
-                    if (pexcl) load_oi(a, oi);
+                    for (int a = 0; a < MB256; ++a) {
+                        int32_t oi[16] = {};
+                        if (pexcl) load_oi(a, oi);
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
-                        S si = 0;
-                        if constexpr (!FOLD) si = sh_t[gi - (int32_t)(I * T256)];
+                        for (int r = 0; r < 16; ++r) {
+                            const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
+                            S si = 0;
+                            if constexpr (!FOLD) si = sh_t[gi - (int32_t)(I * T256)];
 #pragma unroll
-                        for (int b = 0; b < MB256; ++b) {
-                            const int32_t gj = j0 + b * 32 + lrow;
-                            S dv;
-                            if constexpr (FOLD) dv = -2.0f * acc[a][b][r];
-                            else dv = (S)(si + part(acc[a][b][r], sj[b]));
-                            const bool ok = full | (pexcl    ? adm_ref(gi, gj, oi[r], oj[b])
-                                                    : twoset ? adm_two(gi, gj)
-                                                             : adm_pos(gi, gj));
-                            if (ok & (dv <= thr)) {
-                                Cand cd;
-                                cd.i = gi;
-                                cd.j = gj;
-                                cd.dt = (float)dv;
-                                cd.p = p;
-                                if (dv <= thrU) {
-                                    const uint32_t idx = atomicAdd(args.cntU, 1u);
-                                    if (idx < args.capU) args.candU[idx] = cd;
-                                }
-                                if (dv <= thrR) {
-                                    const uint32_t idx = atomicAdd(args.cntR, 1u);
-                                    if (idx < args.capR) args.candR[idx] = cd;
-                                }
+                            for (int b = 0; b < MB256; ++b) {
+                                const int32_t gj = j0 + b * 32 + lrow;
+                                S dv;
+                                if constexpr (FOLD) dv = -2.0f * acc[a][b][r];
+                                else dv = (S)(si + part(acc[a][b][r], sj[b]));
+                                const bool ok = full | (pexcl    ? adm_ref(gi, gj, oi[r], oj[b])
+                                                        : twoset ? adm_two(gi, gj)
+                                                                 : adm_pos(gi, gj));
+                                f(gi, gj, dv, ok);
                             }
                         }
                     }
+                };
+                // count this lane's pairs, reserve them with one atomic per
+                // wave and counter, then write them
+                uint32_t nU = 0, nR = 0, nIn = 0;
+                each([&](int32_t, int32_t, S dv, bool ok) {
+                    nU += ok & (dv <= thrU);
+                    const bool in = ok & (dv <= thrIn);
+                    nIn += in;
+                    nR += ok & !in & (dv <= thrR);
+                });
+                if (args.cntIn) wave_count(args.cntIn, nIn);
+                uint64_t kU = wave_reserve(args.cntU, nU), kR = wave_reserve(args.cntR, nR);
+                if (__any(nU + nR != 0)) {
+                    each([&](int32_t gi, int32_t gj, S dv, bool ok) {
+                        Cand cd;
+                        cd.i = gi;
+                        cd.j = gj;
+                        cd.dt = (float)dv;
+                        cd.p = p;
+                        if (ok & (dv <= thrU)) {
+                            if (kU < args.capU) args.candU[kU] = cd;
+                            ++kU;
+                        }
+                        if (ok & !(dv <= thrIn) & (dv <= thrR)) {
+                            if (kR < args.capR) args.candR[kR] = cd;
+                            ++kR;
+                        }
+                    });
                 }
             }
         }

@@ -90,7 +90,7 @@ __global__ void reduce_U_kernel(const Prob *probs, const uint64_t *tiles, int64_
 }
 
 __global__ void select_kernel(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min,
-                              int prec, const unsigned long long *Ubits, uint64_t *sel, uint32_t *sel_count)
+                              int prec, const unsigned long long *Ubits, uint64_t *sel, u64c *sel_count)
 {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntiles;
          t += (int64_t)gridDim.x * blockDim.x) {
@@ -107,7 +107,7 @@ __global__ void select_kernel(const Prob *probs, const uint64_t *tiles, int64_t 
         if (Ubits) want = lb <= __longlong_as_double((long long)Ubits[p]);
         if (P.r2 >= 0.0) want = want || lb <= P.r2;
         if (want) {
-            const uint32_t k = atomicAdd(sel_count, 1u);
+            const u64c k = atomicAdd(sel_count, 1ull);
             sel[k] = e;
         }
     }
@@ -131,7 +131,7 @@ void launch_reduce_U(const Prob *probs, const uint64_t *tiles, int64_t ntiles, c
 }
 
 void launch_select(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min, int prec,
-                   const unsigned long long *Ubits, uint64_t *sel, uint32_t *sel_count, hipStream_t st)
+                   const unsigned long long *Ubits, uint64_t *sel, u64c *sel_count, hipStream_t st)
 {
     hipLaunchKernelGGL(select_kernel, dim3(grid_of(ntiles)), dim3(256), 0, st, probs, tiles, ntiles, tile_min, prec,
                        Ubits, sel, sel_count);
@@ -221,8 +221,8 @@ __device__ __forceinline__ void cand_rows(const Prob &P, const Cand &cd, int64_t
 }
 
 // One wave per candidate (4 per work-group).
-__global__ __launch_bounds__(256) void verify_cpp_kernel(const Prob *probs, const Cand *cand, const uint32_t *cnt,
-                                                         uint32_t cap, int prec, int tile, double *cand_d2,
+__global__ __launch_bounds__(256) void verify_cpp_kernel(const Prob *probs, const Cand *cand, const u64c *cnt,
+                                                         uint64_t cap, int prec, int tile, double *cand_d2,
                                                          ResDev *res)
 {
     const int64_t m = min((int64_t)*cnt, (int64_t)cap);
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(256) void verify_cpp_kernel(const Prob *probs, cons
     }
 }
 
-__global__ void pick_cpp_kernel(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap,
+__global__ void pick_cpp_kernel(const Prob *probs, const Cand *cand, const u64c *cnt, uint64_t cap,
                                 const double *cand_d2, ResDev *res)
 {
     const int64_t m = min((int64_t)*cnt, (int64_t)cap);
@@ -255,9 +255,9 @@ __global__ void pick_cpp_kernel(const Prob *probs, const Cand *cand, const uint3
     }
 }
 
-__global__ __launch_bounds__(256) void verify_frnn_kernel(const Prob *probs, const Cand *cand, const uint32_t *cnt,
-                                                          uint32_t cap, int prec, int tile, uint64_t *keys,
-                                                          double *vals, uint32_t *out_cnt, uint32_t out_cap,
+__global__ __launch_bounds__(256) void verify_frnn_kernel(const Prob *probs, const Cand *cand, const u64c *cnt,
+                                                          uint64_t cap, int prec, int tile, uint64_t *keys,
+                                                          double *vals, u64c *out_cnt, uint64_t out_cap,
                                                           ResDev *res)
 {
     const int64_t m = min((int64_t)*cnt, (int64_t)cap);
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void verify_frnn_kernel(const Prob *probs, con
             // the bound is indexed by screen-row blocks
             record_error(&res[cd.p], (double)cd.dt, d2, tile_bound_of(P, cd.i / tile, cd.j / tile, prec));
             if (d2 <= P.r2) {
-                const uint32_t k = atomicAdd(out_cnt, 1u);
+                const u64c k = atomicAdd(out_cnt, 1ull);
                 if (k < out_cap) {
                     keys[k] = ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
                     vals[k] = d2;
@@ -284,21 +284,21 @@ __global__ __launch_bounds__(256) void verify_frnn_kernel(const Prob *probs, con
 
 static unsigned verify_grid() { return 2048; }   // work-groups of 4 waves, a candidate per wave
 
-void launch_verify_cpp(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec, int tile,
+void launch_verify_cpp(const Prob *probs, const Cand *cand, const u64c *cnt, uint64_t cap, int prec, int tile,
                        double *cand_d2, ResDev *res, hipStream_t st)
 {
     hipLaunchKernelGGL(verify_cpp_kernel, dim3(verify_grid()), dim3(256), 0, st, probs, cand, cnt, cap, prec, tile,
                        cand_d2, res);
 }
 
-void launch_pick_cpp(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, const double *cand_d2,
+void launch_pick_cpp(const Prob *probs, const Cand *cand, const u64c *cnt, uint64_t cap, const double *cand_d2,
                      ResDev *res, hipStream_t st)
 {
     hipLaunchKernelGGL(pick_cpp_kernel, dim3(256), dim3(256), 0, st, probs, cand, cnt, cap, cand_d2, res);
 }
 
-void launch_verify_frnn(const Prob *probs, const Cand *cand, const uint32_t *cnt, uint32_t cap, int prec, int tile,
-                        uint64_t *keys, double *vals, uint32_t *out_cnt, uint32_t out_cap, ResDev *res,
+void launch_verify_frnn(const Prob *probs, const Cand *cand, const u64c *cnt, uint64_t cap, int prec, int tile,
+                        uint64_t *keys, double *vals, u64c *out_cnt, uint64_t out_cap, ResDev *res,
                         hipStream_t st)
 {
     hipLaunchKernelGGL(verify_frnn_kernel, dim3(verify_grid()), dim3(256), 0, st, probs, cand, cnt, cap, prec, tile,

@@ -639,3 +639,19 @@ def test_lanes_closest_pair_on_windows_and_strides():
     view = big[:, :33]                                        # rows with a stride larger than d
     assert oracle.closest_pair_lanes(view, 2) == oracle.closest_pair(np.ascontiguousarray(view), 2)
     assert oracle.closest_pair_lanes(rng.normal(0, 1, (5, 3)), 5) is None
+
+
+def test_frnn_count_against_scipy_and_closed_form():
+    """The pair count of a radius: scipy's pdist counted at the same squared
+    radius (away from ties), n(n-1)/2 above the largest distance, and the
+    exclusion zone removing exactly the pairs with j - i < excl."""
+    rng = np.random.default_rng(15)
+    X = rng.normal(0, 1, (700, 5)).astype(np.float32)
+    d2 = ssd.pdist(X.astype(np.float64), "sqeuclidean")
+    for R2 in (2.0, 6.5, 11.0):
+        assert oracle.frnn_count(X, R2) == int(np.count_nonzero(d2 <= R2))
+        assert oracle.frnn_count(X, R2) == len(oracle.frnn(X, R2)[0])
+    n = X.shape[0]
+    assert oracle.frnn_count(X, 1e30) == n * (n - 1) // 2
+    assert oracle.frnn_count(X, 1e30, excl=10) == (n - 10) * (n - 9) // 2
+    assert oracle.frnn_count(X, -1.0) == 0
