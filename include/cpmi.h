@@ -132,6 +132,25 @@ int cpmi_destroy(cpmi_ctx *ctx);
 int cpmi_closest_pair(cpmi_ctx *ctx, const void *pts, int dtype, int64_t n, int64_t d, int64_t ld,
                       int precision, void *stream, cpmi_pair *out);
 
+/* Closest pair as cpmi_closest_pair, without allocating: for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc). Every device buffer of the search is a
+ * slice of a static device array of CPMI_NOALLOC_SCRATCH_BYTES per GPU, which
+ * the library holds until the process ends; no hipMalloc, hipFree or pinned
+ * host allocation is made (results come back through pageable host memory).
+ * Same arguments, layout, result and errors as cpmi_closest_pair, plus
+ * ERR_CAPACITY when the search does not fit the array: the screen operand
+ * (n rounded up to 256 rows of d rounded up to the screen's K step, 2 bytes
+ * per element in BF16, 4 in FP32, 1 in int8), the row scalars, the tile lists
+ * and room for at least 1024 closest-pair candidates (e.g. up to about 40,000
+ * BF16 points of d = 512), or when more than 2^20 candidates tie within the
+ * screening bound. The reference-point pruning switch is ignored. All calls on
+ * one GPU share its array: calls that overlap in time on one GPU (several
+ * threads or streams) race and give undefined results; serialise them. */
+#define CPMI_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int cpmi_closest_pair_noalloc(cpmi_ctx *ctx, const void *pts, int dtype, int64_t n, int64_t d, int64_t ld,
+                              int precision, void *stream, cpmi_pair *out);
+
 /* Fixed-radius pairs (Section 3.5, MPR-FRNNS emits j into N(i) and i into N(j)
  * when d <= R): every pair i<j with canonical d2 <= R2, sorted by (i, j).
  * R2 is the squared radius (callers pass fl(R*R); for int8 data an integer).

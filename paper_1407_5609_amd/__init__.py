@@ -79,6 +79,7 @@ def _load():
     L.cpmi_set_pruning.argtypes = [vp, i32, dbl, C.c_uint64]
     L.cpmi_version.restype = i32
     L.cpmi_closest_pair.argtypes = [vp, vp, i32, i64, i64, i64, i32, vp, C.POINTER(_CPair)]
+    L.cpmi_closest_pair_noalloc.argtypes = [vp, vp, i32, i64, i64, i64, i32, vp, C.POINTER(_CPair)]
     L.cpmi_frnn.argtypes = [vp, vp, i32, i64, i64, i64, dbl, i32, vp, vp, vp, i64, C.POINTER(i64)]
     L.cpmi_points.argtypes = [vp, vp, i32, i64, i64, i64, i32, dbl, vp, C.POINTER(_CPair), vp, vp, i64,
                               C.POINTER(i64)]
@@ -312,6 +313,15 @@ class Context:
         out = _CPair()
         self._check(_lib.cpmi_closest_pair(self._h, C.c_void_p(pts.data_ptr()), dt, n, d, ld, _prec(precision),
                                            _stream_ptr(stream), C.byref(out)))
+        return _pair(out)
+
+    def closest_pair_noalloc(self, pts, precision="auto", stream=None) -> Pair:
+        """cpmi_closest_pair_noalloc: the closest pair with every device buffer
+        taken from the library's static scratch (no allocation)."""
+        dt, n, d, ld = self._points_args(pts)
+        out = _CPair()
+        self._check(_lib.cpmi_closest_pair_noalloc(self._h, C.c_void_p(pts.data_ptr()), dt, n, d, ld,
+                                                   _prec(precision), _stream_ptr(stream), C.byref(out)))
         return _pair(out)
 
     def frnn(self, pts, R2: float, precision="auto", stream=None, cap: int = 1 << 16):

@@ -19,6 +19,7 @@
 #include <cstring>
 #include <functional>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -29,6 +30,17 @@
 #include "layout256.h"
 
 using namespace cpmi;
+
+// Device memory of the allocation-free closest pair (cpmi_closest_pair_noalloc):
+// one static array per GPU, held until the process ends. Host code never
+// passes its name to a kernel or a copy: each device's address is taken once
+// with hipGetSymbolAddress (cpmi_create, with the device current) and used
+// from then on.
+static constexpr size_t kScratchBytes = CPMI_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static constexpr int kMaxDevices = 64;
+static void *g_scratch_addr[kMaxDevices];
+static std::mutex g_scratch_mu;
 
 namespace {
 
@@ -110,6 +122,7 @@ struct cpmi_ctx {
     int64_t nfull = 0;   // leading entries of the list that are full tiles
     int64_t nfull_pairs = 0;  // pairs covered by the timed screen launch (full tiles, or all when none is full)
 
+    void *scratch = nullptr;  // this device's static scratch (device address)
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t es0 = nullptr, es1 = nullptr;  // around the first screen pass
     hipStream_t own = nullptr;
@@ -1142,6 +1155,25 @@ int cpmi_create(cpmi_ctx **out, int device, const char *tune_cache_path)
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         c->ncu = ncu;
+    if (device < kMaxDevices) {
+        // the static scratch's address on this device, taken once per device
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_addr[device]) {
+            void *p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+                hipEventDestroy(c->ev0);
+                hipEventDestroy(c->ev1);
+                hipEventDestroy(c->es0);
+                hipEventDestroy(c->es1);
+                hipEventDestroy(c->evlohi);
+                hipStreamDestroy(c->own);
+                delete c;
+                return CPMI_ERR_HIP;
+            }
+            g_scratch_addr[device] = p;
+        }
+        c->scratch = g_scratch_addr[device];
+    }
     load_tune_cache(c, tune_cache_path);
     *out = c;
     return CPMI_OK;
@@ -1258,6 +1290,58 @@ int cpmi_closest_pair(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_
 {
     if (!out) return c ? fail(c, CPMI_ERR_ARG, "out is NULL") : CPMI_ERR_ARG;
     return cpmi_points(c, pts, dtype, n, d, ld, precision, -1.0, stream, out, nullptr, nullptr, 0, nullptr);
+}
+
+int cpmi_closest_pair_noalloc(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d, int64_t ld,
+                              int precision, void *stream, cpmi_pair *out)
+{
+    if (!c) return CPMI_ERR_ARG;
+    c->err.clear();
+    c->stats = cpmi_stats{};
+    if (!out) return fail(c, CPMI_ERR_ARG, "out is NULL");
+    memset(out, 0, sizeof *out);
+    out->i = out->j = -1;
+    if (!pts) return fail(c, CPMI_ERR_ARG, "points pointer is NULL");
+    if (dtype != CPMI_F32 && dtype != CPMI_I8) return fail(c, CPMI_ERR_ARG, "unknown dtype %d", dtype);
+    if (d < 1 || ld < d || n < 0)
+        return fail(c, CPMI_ERR_ARG, "bad shape n=%lld d=%lld ld=%lld", (long long)n, (long long)d, (long long)ld);
+    if (dtype == CPMI_I8 && d > 32768) return fail(c, CPMI_ERR_ARG, "int8 dimension must be <= 32768 (int32 Gram)");
+    if (!c->scratch) return fail(c, CPMI_ERR_ARG, "no static scratch on device %d", c->device);
+    if (n < 2) {
+        out->status = CPMI_ERR_NOPAIR;
+        return fail(c, CPMI_ERR_NOPAIR, "fewer than two points");
+    }
+    const double npairs = (double)pairs_of(n, 1);
+    const int prec = resolve_prec(c, dtype, precision, d, npairs);
+    if (prec < 0) return prec;
+    const int tile = pick_tile(c, prec, d, npairs);
+    // reject what cannot fit before any work is queued: the screen operand
+    // and row scalars alone
+    const int64_t npad = (n + 255) / 256 * 256;
+    const double need = (double)npad * kpad_for(prec, d, tile) * elem_bytes(prec) + (double)npad * 4.0;
+    if (need > (double)kScratchBytes)
+        return fail(c, CPMI_ERR_CAPACITY, "%lld x %lld points need %.0f bytes of screen operand; the static scratch "
+                    "holds %zu", (long long)n, (long long)d, need, kScratchBytes);
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    std::vector<HostProb> hp(1);
+    hp[0].n = n;
+    hp[0].d = d;
+    hp[0].ld = ld;
+    hp[0].excl = 1;
+    hp[0].src = pts;
+    hp[0].src_i8 = dtype == CPMI_I8;
+    hp[0].r2 = -1.0;
+    Arena ar;
+    ar.base = (char *)c->scratch;
+    ar.size = kScratchBytes;
+    RunOut ro;
+    if ((rc = run_search(c, hp, prec, tile, true, false, (hipStream_t)stream, false, ro, nullptr, 0, false, {}, &ar)))
+        return rc;
+    if ((rc = flags_error(c, ro.res[0].flags))) return rc;
+    fill_pair(ro.res[0], out);
+    if (out->status) return fail(c, out->status, "no admissible pair");
+    return CPMI_OK;
 }
 
 int cpmi_frnn(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, double R2, int precision,
