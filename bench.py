@@ -58,6 +58,16 @@ def _traffic_per_launch():
         return None
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def _golden(name):
     return json.load(open(os.path.join(GOLDEN_DIR, name)))
 
@@ -469,6 +479,18 @@ def main():
     if not wl.roofline:
         out["roofline"] = None
         out["config"]["pairs_collected"] = wl.pairs_collected
+    if isinstance(wl, (Points, Motif)) and not args.prune and st.precision != 3:
+        # the screen bound on this workload, on the hardware: every element of
+        # 16 seeded tiles, screen value against the verifier's canonical d2
+        import numpy as np
+        rows = wl.n if isinstance(wl, Points) else len(wl.Th) - wl.ell + 1
+        nT = (rows + st.tile - 1) // st.tile
+        rng = np.random.default_rng(20240607)
+        tl = sorted({(nT - 1, nT - 1)} | {tuple(sorted(int(v) for v in rng.integers(0, nT, 2))) for _ in range(15)})
+        src = wl.X if isinstance(wl, Points) else wl.T
+        _, _, _, ratio = ctx.dbg_screen_sample(src, tl, st.tile, precision=pprec,
+                                               ell=None if isinstance(wl, Points) else wl.ell)
+        out["screen_sample"] = {"tiles": len(tl), "pairs": len(tl) * st.tile ** 2, "max_err_over_bound": ratio}
     if args.prune:
         out["config"]["pruning"] = {"references": args.prune, "f": args.prune_f, "tiles_pruned": st.tiles_pruned,
                                     "tiles_screened": st.tiles_total}
@@ -486,10 +508,17 @@ def main():
     if not args.no_cpu_baseline:
         note("timing the CPU oracle on a sample")
         import oracle
-        oracle.set_threads(min(16, os.cpu_count() or 1))
+        # every host core this process may use, at most 16 (the host share of one GPU)
+        avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        threads = max(1, min(16, avail))
+        oracle.set_threads(threads)
         v, sample = wl.cpu_baseline(args.cpu_seconds)
-        out["cpu_baseline"] = {"value": v, "unit": "pair-evals/s", "cores": oracle.max_threads(), "kind": "oracle",
-                               "sample": sample}
+        oracle.set_threads(1)
+        v1, sample1 = wl.cpu_baseline(args.cpu_seconds / 3)
+        oracle.set_threads(threads)
+        out["cpu_baseline"] = {"value": v, "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
+                               "sample": sample, "host_cpus": avail, "cpu_model": _cpu_model(),
+                               "one_core": {"value": v1, "sample": sample1}}
     print(json.dumps(out), flush=True)
 
 

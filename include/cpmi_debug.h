@@ -30,6 +30,26 @@ int cpmi_dbg_mfma_probe(int precision, const void *A, const void *B, float *C, v
  * a negative CPMI_ERR_* code. */
 double cpmi_dbg_mfma_peak(int device, int precision, int iters, double *ms_out);
 
+/* The screen bound on the hardware. Runs the builder and the real screen
+ * kernel (tile edge `tile`, 128 or 256, at `precision`) over the m tiles
+ * tiles_ij (host int64 [m][2], block row I and block column J of edge tile),
+ * and writes every element's screen value D~ (row I*tile + il, column
+ * J*tile + jl) to dump_out (device, m*tile*tile, row-major per tile; float,
+ * or int32 for int8), its canonical d2 computed by the verifier to d2_out
+ * (device double, same indexing; elements whose row or column is past the
+ * last row are not written), each tile's bound E (the applied per-tile bound
+ * of the screen) to bound_out (host double [m]) and the largest
+ * |D~ - d2| / E over the tiles' elements to *max_ratio_out (host; for int8 0
+ * when every value is exact, else infinity). src: device points (series = 0:
+ * n x d rows of stride ld, float32 or int8) or a float32 series of length n
+ * whose z-normalised windows of length d are the rows (series = 1). The
+ * bound is what makes the screen exact; a ratio above 1 would break it.
+ * Errors: ERR_ARG (shapes, a tile out of range), ERR_NONFINITE,
+ * ERR_DEGENERATE, ERR_RANGE, ERR_HIP. */
+int cpmi_dbg_screen_sample(cpmi_ctx *ctx, const void *src, int dtype, int64_t n, int64_t d, int64_t ld, int series,
+                           int precision, int tile, const int64_t *tiles_ij, int64_t m, void *dump_out,
+                           double *d2_out, double *bound_out, double *max_ratio_out, void *stream);
+
 /* Run only the l-mer builder on a series and return the canonical window
  * means and sigmas (device double [len - ell + 1] each), so that they can be
  * compared bit for bit with the definition (Section 2 windows, two-pass

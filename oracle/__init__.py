@@ -49,6 +49,9 @@ def lib():
         for nm in ("orc_frnn_f32", "orc_frnn_f64", "orc_frnn_i8"):
             getattr(L, nm).restype = _i64
             getattr(L, nm).argtypes = [_p, _i64, _i64, _i64, _i64, C.c_double, _p, _p, _i64]
+        for nm in ("orc_block_d2_f32", "orc_block_d2_f64", "orc_block_d2_i8"):
+            getattr(L, nm).restype = None
+            getattr(L, nm).argtypes = [_p, _i64, _i64, _i64, _i64, _i64, _i64, _p]
         L.orc_frnn_count_f32.restype = _i64
         L.orc_frnn_count_f32.argtypes = [_p, _i64, _i64, _i64, _i64, C.c_double]
         L.orc_nn_f32.restype = C.c_int
@@ -160,6 +163,18 @@ def frnn(X: np.ndarray, R2: float, excl: int = 1):
                 dd = dd.astype(np.int64)
             return pairs, dd
         cap = int(cnt)
+
+
+def block_d2(X: np.ndarray, i0: int, ni: int, j0: int, nj: int) -> np.ndarray:
+    """Canonical d2 of rows i0..i0+ni-1 against rows j0..j0+nj-1: float64
+    [ni, nj] (int8 rows: exact integers as float64)."""
+    X, n, d, ld = _rows(X)
+    if not (0 <= i0 and i0 + ni <= n and 0 <= j0 and j0 + nj <= n):
+        raise IndexError("block out of range")
+    out = np.empty((ni, nj), dtype=np.float64)
+    getattr(lib(), "orc_block_d2_" + _kind(X))(X.ctypes.data, d, ld, int(i0), int(ni), int(j0), int(nj),
+                                               out.ctypes.data)
+    return out
 
 
 def frnn_count(X: np.ndarray, R2: float, excl: int = 1) -> int:

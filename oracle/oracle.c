@@ -410,6 +410,32 @@ int64_t orc_frnn_i8(const int8_t *X, int64_t n, int64_t d, int64_t ld, int64_t e
     ORC_FRNN_BODY((double)orc_d2_i8(X, d, ld, i, j))
 }
 
+/* d^2 of every pair (i0 + a, j0 + b), a < ni, b < nj, into out[a * nj + b]:
+ * a block of the distance matrix (used to check sampled screen values). */
+void orc_block_d2_f32(const float *X, int64_t d, int64_t ld, int64_t i0, int64_t ni, int64_t j0, int64_t nj,
+                      double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < ni; ++a)
+        for (int64_t b = 0; b < nj; ++b) out[a * nj + b] = orc_d2_f32(X, d, ld, i0 + a, j0 + b);
+}
+
+void orc_block_d2_f64(const double *X, int64_t d, int64_t ld, int64_t i0, int64_t ni, int64_t j0, int64_t nj,
+                      double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < ni; ++a)
+        for (int64_t b = 0; b < nj; ++b) out[a * nj + b] = orc_d2_f64(X, d, ld, i0 + a, j0 + b);
+}
+
+void orc_block_d2_i8(const int8_t *X, int64_t d, int64_t ld, int64_t i0, int64_t ni, int64_t j0, int64_t nj,
+                     double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < ni; ++a)
+        for (int64_t b = 0; b < nj; ++b) out[a * nj + b] = (double)orc_d2_i8(X, d, ld, i0 + a, j0 + b);
+}
+
 /* Number of pairs i<j (j-i >= excl) with d^2 <= R2, without listing them
  * (Section 3.5's output size; |N(i)| summed over i is twice this). */
 int64_t orc_frnn_count_f32(const float *X, int64_t n, int64_t d, int64_t ld, int64_t excl, double R2)

@@ -81,6 +81,8 @@ def _load():
     L.cpmi_closest_pair.argtypes = [vp, vp, i32, i64, i64, i64, i32, vp, C.POINTER(_CPair)]
     L.cpmi_closest_pair_noalloc.argtypes = [vp, vp, i32, i64, i64, i64, i32, vp, C.POINTER(_CPair)]
     L.cpmi_frnn.argtypes = [vp, vp, i32, i64, i64, i64, dbl, i32, vp, vp, vp, i64, C.POINTER(i64)]
+    L.cpmi_dbg_screen_sample.argtypes = [vp, vp, i32, i64, i64, i64, i32, i32, i32, vp, i64, vp, vp, vp,
+                                         C.POINTER(dbl), vp]
     L.cpmi_points.argtypes = [vp, vp, i32, i64, i64, i64, i32, dbl, vp, C.POINTER(_CPair), vp, vp, i64,
                               C.POINTER(i64)]
     L.cpmi_motif.argtypes = [vp, vp, i64, i64, i64, i32, dbl, vp, C.POINTER(_CPair), vp, vp, i64, C.POINTER(i64)]
@@ -409,6 +411,35 @@ class Context:
         return res
 
     # ---- diagnostics
+    def dbg_screen_sample(self, src, tiles, tile: int, precision="bf16", ell: int | None = None, stream=None):
+        """cpmi_dbg_screen_sample: screen values and canonical d2 of every
+        element of the listed tiles ((I, J) block pairs of edge `tile`) of a
+        point set, or (ell given) of the windows of a series. Returns
+        (dump [m, tile, tile], d2 [m, tile, tile] (NaN where no pair),
+        bounds [m], max ratio)."""
+        import numpy as np
+        import torch
+        tiles = np.ascontiguousarray(np.asarray(tiles, dtype=np.int64).reshape(-1, 2))
+        m = tiles.shape[0]
+        dev = f"cuda:{self.device}"
+        if ell is None:
+            dt, n, d, ld = self._points_args(src)
+            series = 0
+        else:
+            if src.device.type != "cuda" or src.dtype != torch.float32 or src.dim() != 1 or not src.is_contiguous():
+                raise ValueError("series must be a contiguous 1-D float32 GPU tensor")
+            dt, n, d, ld, series = F32, src.shape[0], int(ell), 1, 1
+        i8 = dt == I8
+        dump = torch.empty((m, tile, tile), dtype=torch.int32 if i8 else torch.float32, device=dev)
+        d2 = torch.full((m, tile, tile), float("nan"), dtype=torch.float64, device=dev)
+        bounds = np.zeros(m, dtype=np.float64)
+        ratio = C.c_double(0.0)
+        self._check(_lib.cpmi_dbg_screen_sample(
+            self._h, C.c_void_p(src.data_ptr()), dt, n, d, ld, series, _prec(precision), int(tile),
+            tiles.ctypes.data_as(C.c_void_p), m, C.c_void_p(dump.data_ptr()), C.c_void_p(d2.data_ptr()),
+            bounds.ctypes.data_as(C.c_void_p), C.byref(ratio), _stream_ptr(stream)))
+        return dump, d2, bounds, float(ratio.value)
+
     def dbg_znorm(self, series, ell: int, precision="f32", stream=None):
         import torch
         N = series.shape[0] - ell + 1

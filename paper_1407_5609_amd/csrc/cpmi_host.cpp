@@ -411,6 +411,15 @@ void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t
     out.insert(out.end(), part.begin(), part.end());
 }
 
+// Test of the screen bound (cpmi_dbg_screen_sample): device buffers of the
+// dumped screen values, canonical d2, per-tile bounds and the largest ratio.
+struct DumpReq {
+    void *out;
+    double *d2;
+    double *E;
+    unsigned int *ratio;
+};
+
 struct RunOut {
     std::vector<ResDev> res;
     uint64_t cnt[NCNT];
@@ -443,7 +452,7 @@ int take(cpmi_ctx *c, Arena &ar, DevBuf &b, size_t bytes)
 int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool want_cpp, bool want_frnn,
                hipStream_t st, bool batch_graph, RunOut &ro, const std::vector<uint64_t> *forced = nullptr,
                int64_t forced_nfull = 0, bool reuse_operand = false, const std::function<void()> &while_busy = {},
-               Arena *ar = nullptr)
+               Arena *ar = nullptr, const DumpReq *dump = nullptr)
 {
     bool busy_done = false;
     Work local;
@@ -642,6 +651,15 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             a.probs = dprobs;
             a.tiles = (const uint64_t *)W.tiles.p;
             a.ntiles = ntiles;
+            if (dump) {
+                // the listed tiles' screen values, checked against the canonical d2
+                ScreenArgs q = a;
+                q.dump = dump->out;
+                launch_fill_u32(dump->ratio, 0u, 1, st);
+                launch_screen(prec, tile, M_DUMP, true, q, std::min<int64_t>(ntiles, tile == 256 ? c->ncu : 2048), st);
+                launch_sample_check(dprobs, a.tiles, ntiles, tile, dump->out, prec, dump->d2, dump->E, dump->ratio, st);
+                return;
+            }
             a.tile_min = (uint32_t *)W.tile_min.p;
             a.candR = (Cand *)W.candR.p;
             a.cntR = dcnt + C_R;
@@ -747,7 +765,12 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         hipEventElapsedTime(&ms, c->ev0, c->ev1);
         c->stats.kernel_ms = ms;
         ms = 0.f;
-        if (!batch_graph) hipEventElapsedTime(&ms, c->es0, c->es1);
+        // (the screen events are not recorded in graph replays and test dumps;
+        // a failed query must not leave an error behind for the caller's next call)
+        if (!batch_graph && !dump && hipEventElapsedTime(&ms, c->es0, c->es1) != hipSuccess) {
+            ms = 0.f;
+            (void)hipGetLastError();
+        }
         c->stats.screen_ms = ms;
         ro.res.assign((ResDev *)hostbuf, (ResDev *)hostbuf + np);
         memcpy(ro.cnt, hostbuf + np * sizeof(ResDev), sizeof ro.cnt);
@@ -1945,6 +1968,62 @@ int cpmi_dbg_mfma_probe(int precision, const void *A, const void *B, float *C, v
     launch_mfma_probe(precision, A, B, C, (hipStream_t)stream);
     if (hipGetLastError() != hipSuccess) return CPMI_ERR_HIP;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return CPMI_ERR_HIP;
+    return CPMI_OK;
+}
+
+int cpmi_dbg_screen_sample(cpmi_ctx *c, const void *src, int dtype, int64_t n, int64_t d, int64_t ld, int series,
+                           int precision, int tile, const int64_t *tiles_ij, int64_t m, void *dump_out,
+                           double *d2_out, double *bound_out, double *max_ratio_out, void *stream)
+{
+    if (!c) return CPMI_ERR_ARG;
+    c->err.clear();
+    if (!src || !tiles_ij || !dump_out || !d2_out || !bound_out || !max_ratio_out || m < 1)
+        return fail(c, CPMI_ERR_ARG, "null argument or no tile");
+    if (tile != 128 && tile != 256) return fail(c, CPMI_ERR_ARG, "tile must be 128 or 256");
+    if (dtype != CPMI_F32 && dtype != CPMI_I8) return fail(c, CPMI_ERR_ARG, "unknown dtype");
+    if (series && (dtype != CPMI_F32 || d < 2 || n < d || d > SERIES_MAX_ELL))
+        return fail(c, CPMI_ERR_ARG, "series: float32, 2 <= ell <= len");
+    if (!series && (d < 1 || ld < d || n < 1)) return fail(c, CPMI_ERR_ARG, "bad shape");
+    if (dtype == CPMI_I8 && precision != CPMI_PREC_I8 && precision != CPMI_PREC_AUTO)
+        return fail(c, CPMI_ERR_ARG, "int8 points take CPMI_PREC_I8");
+    const int64_t rows = series ? n - d + 1 : n;
+    const int prec = resolve_prec(c, dtype, precision, d, (double)pairs_of(rows, 1));
+    if (prec < 0) return prec;
+    const int64_t nT = (rows + tile - 1) / tile;
+    std::vector<uint64_t> tl((size_t)m);
+    for (int64_t t = 0; t < m; ++t) {
+        const int64_t I = tiles_ij[2 * t], J = tiles_ij[2 * t + 1];
+        if (I < 0 || J < 0 || I >= nT || J >= nT) return fail(c, CPMI_ERR_ARG, "tile (%lld, %lld) out of range", (long long)I, (long long)J);
+        tl[(size_t)t] = tile_pack(0, (uint32_t)I, (uint32_t)J);
+    }
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<HostProb> hp(1);
+    hp[0].n = rows;
+    hp[0].d = d;
+    hp[0].ld = series ? 1 : ld;
+    hp[0].excl = series ? d : 1;
+    hp[0].motif = series ? 1 : 0;
+    hp[0].src = src;
+    hp[0].src_i8 = dtype == CPMI_I8;
+    hp[0].len = series ? n : 0;
+    // per-tile bounds and the ratio word: a small buffer of its own (test only)
+    DevBuf eb;
+    HIPCHK(c, hipMalloc(&eb.p, (size_t)m * 8 + 256));
+    DumpReq dr{dump_out, d2_out, (double *)eb.p, (unsigned int *)((char *)eb.p + (size_t)m * 8)};
+    RunOut ro;
+    rc = run_search(c, hp, prec, tile, false, false, st, false, ro, &tl, 0, false, {}, nullptr, &dr);
+    unsigned int rbits = 0;
+    if (rc == CPMI_OK) {
+        hipError_t e = hipMemcpy(bound_out, eb.p, (size_t)m * 8, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(&rbits, dr.ratio, 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) rc = fail(c, CPMI_ERR_HIP, "copy of the bounds failed: %s", hipGetErrorString(e));
+    }
+    hipFree(eb.p);
+    if (rc) return rc;
+    if ((rc = flags_error(c, ro.res[0].flags))) return rc;
+    *max_ratio_out = (double)__builtin_bit_cast(float, rbits);
     return CPMI_OK;
 }
 

@@ -12,7 +12,8 @@ enum Prec : int { P_F32 = 1, P_BF16 = 2, P_I8 = 3 };
 // Screen modes of the Gram kernel (bit set).
 enum Mode : int {
     M_MIN = 1,   // pass 1: record the tile minimum of the screen value
-    M_EMIT = 2   // pass 2: emit pairs within the closest-pair and/or radius thresholds
+    M_EMIT = 2,  // pass 2: emit pairs within the closest-pair and/or radius thresholds
+    M_DUMP = 4   // test: write the screen value of every element of every listed tile
 };
 
 // One flag word per problem; set by the builders, read back by the host.
@@ -83,6 +84,9 @@ struct ScreenArgs {
     // the rest of the radius candidates (the band r2 - bound < D~ <= r2 +
     // bound) are emitted to candR as usual.
     u64c *cntIn;
+    // M_DUMP: tile_edge^2 values per list entry, row-major within the tile
+    // (float, or int32 for int8)
+    void *dump;
 };
 
 // Wave-aggregated reservation of n slots per lane (called by every lane of
@@ -194,6 +198,14 @@ void launch_pick_cpp(const Prob *probs, const Cand *cand, const u64c *cnt, uint6
 void launch_verify_frnn(const Prob *probs, const Cand *cand, const u64c *cnt, uint64_t cap, int prec, int tile,
                         uint64_t *keys, double *vals, u64c *out_cnt, uint64_t out_cap, ResDev *res,
                         hipStream_t st);
+// Test of the screen bound on the hardware: for every element (row il,
+// column jl) of the m tiles of `tiles` dumped by the M_DUMP screen (rows and
+// columns past the problem's rows skipped), the canonical d2 (verifier
+// arithmetic) into d2_out, the tile's bound into E_out[t], and the largest
+// |screen - d2| / E into *ratio_bits (float bits, rounded up; for int8, 0 if
+// equal, else infinity).
+void launch_sample_check(const Prob *probs, const uint64_t *tiles, int64_t m, int tile, const void *dump, int prec,
+                         double *d2_out, double *E_out, unsigned int *ratio_bits, hipStream_t st);
 // Sort m (key, value) pairs by key; arrays hold mpad >= m entries (mpad a power
 // of two), the tail is overwritten with sentinels.
 void launch_sort_pairs(uint64_t *keys, double *vals, int64_t m, int64_t mpad, hipStream_t st);

@@ -219,6 +219,10 @@ __global__ __launch_bounds__(NTHREADS) void screen_kernel(ScreenArgs args)
                 }
             }
         };
+        if constexpr (MODE & M_DUMP) {
+            S *out = (S *)args.dump + (size_t)t * (TILE * TILE);
+            each([&](int64_t gi, int64_t gj, S dv, bool) { out[(gi - i0) * TILE + (gj - j0)] = dv; });
+        }
         S mn = SINF;
         if constexpr (MODE & M_MIN) {
             each([&](int64_t, int64_t, S dv, bool ok) {
@@ -275,6 +279,7 @@ static void launch_t(int mode, const ScreenArgs &a, int64_t grid, hipStream_t st
 {
     dim3 g((unsigned)grid), b(NTHREADS);
     if (mode == M_MIN) hipLaunchKernelGGL((screen_kernel<PREC, TILE, M_MIN>), g, b, 0, st, a);
+    else if (mode == M_DUMP) hipLaunchKernelGGL((screen_kernel<PREC, TILE, M_DUMP>), g, b, 0, st, a);
     else hipLaunchKernelGGL((screen_kernel<PREC, TILE, M_EMIT>), g, b, 0, st, a);
 }
 

@@ -686,6 +686,26 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
             }
         }
 
+        if constexpr (MODE & M_DUMP) {
+            // every element's screen value, as the other modes form it
+            S *out = (S *)args.dump + (size_t)t * (T256 * T256);
+#pragma unroll
+            for (int a = 0; a < MB256; ++a) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int32_t il = wm * WT256 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
+                    S si = 0;
+                    if constexpr (!FOLD) si = sh_t[il];
+#pragma unroll
+                    for (int b = 0; b < MB256; ++b) {
+                        S dv;
+                        if constexpr (FOLD) dv = -2.0f * acc[a][b][r];
+                        else dv = (S)(si + part(acc[a][b][r], sj[b]));
+                        out[il * T256 + wn * WT256 + b * 32 + lrow] = dv;
+                    }
+                }
+            }
+        }
         if constexpr (MODE & M_EMIT) {
             const double E = tile_bound(P.bmax[I], P.bmax[J], P.kpad, P.d, PREC,
                                         FOLD ? SCREEN_FOLDED : SCREEN_EPILOGUE);
@@ -789,6 +809,7 @@ static void launch256(int mode, bool masked, const ScreenArgs &a, int64_t grid, 
     dim3 g((unsigned)grid), b(256);
     if (mode == M_MIN && !masked) hipLaunchKernelGGL((screen256_kernel<PREC, M_MIN, false>), g, b, 0, st, a);
     else if (mode == M_MIN) hipLaunchKernelGGL((screen256_kernel<PREC, M_MIN, true>), g, b, 0, st, a);
+    else if (mode == M_DUMP) hipLaunchKernelGGL((screen256_kernel<PREC, M_DUMP, true>), g, b, 0, st, a);
     else hipLaunchKernelGGL((screen256_kernel<PREC, M_EMIT, true>), g, b, 0, st, a);
 }
 

@@ -282,6 +282,39 @@ __global__ __launch_bounds__(256) void verify_frnn_kernel(const Prob *probs, con
     }
 }
 
+// One wave per dumped element (grid-stride over m tiles x tile^2 elements).
+__global__ __launch_bounds__(256) void sample_check_kernel(const Prob *probs, const uint64_t *tiles, int64_t m,
+                                                           int tile, const void *dump, int prec, double *d2_out,
+                                                           double *E_out, unsigned int *ratio_bits)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t per = (int64_t)tile * tile;
+    for (int64_t e = blockIdx.x * 4 + (threadIdx.x >> 6); e < m * per; e += (int64_t)gridDim.x * 4) {
+        const int64_t t = e / per, il = (e % per) / tile, jl = e % tile;
+        const uint64_t ent = tiles[t];
+        const Prob &P = probs[tile_prob(ent)];
+        const int64_t gi = (int64_t)tile_I(ent) * tile + il, gj = (int64_t)tile_J(ent) * tile + jl;
+        const double E = tile_bound_of(P, tile_I(ent), tile_J(ent), prec);
+        if (lane == 0 && e % per == 0) E_out[t] = E;
+        if (gi >= P.n || gj >= P.n) continue;
+        const double d2 = canonical_d2(P, src_row(P, gi), src_row(P, gj), lane);
+        if (lane == 0) {
+            d2_out[e] = d2;
+            const double dt = prec == P_I8 ? (double)((const int *)dump)[e] : (double)((const float *)dump)[e];
+            const double err = fabs(dt - d2);
+            const float ratio = prec == P_I8 ? (err == 0.0 ? 0.0f : INFINITY) : f32_up(err / E);
+            atomicMax(ratio_bits, __float_as_uint(ratio));
+        }
+    }
+}
+
+void launch_sample_check(const Prob *probs, const uint64_t *tiles, int64_t m, int tile, const void *dump, int prec,
+                         double *d2_out, double *E_out, unsigned int *ratio_bits, hipStream_t st)
+{
+    hipLaunchKernelGGL(sample_check_kernel, dim3(2048), dim3(256), 0, st, probs, tiles, m, tile, dump, prec, d2_out,
+                       E_out, ratio_bits);
+}
+
 static unsigned verify_grid() { return 2048; }   // work-groups of 4 waves, a candidate per wave
 
 void launch_verify_cpp(const Prob *probs, const Cand *cand, const u64c *cnt, uint64_t cap, int prec, int tile,

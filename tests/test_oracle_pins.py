@@ -655,3 +655,16 @@ def test_frnn_count_against_scipy_and_closed_form():
     assert oracle.frnn_count(X, 1e30) == n * (n - 1) // 2
     assert oracle.frnn_count(X, 1e30, excl=10) == (n - 10) * (n - 9) // 2
     assert oracle.frnn_count(X, -1.0) == 0
+
+
+def test_block_d2_is_the_pairwise_distance():
+    rng = np.random.default_rng(16)
+    X = rng.normal(0, 1, (50, 9)).astype(np.float32)
+    B = oracle.block_d2(X, 3, 20, 30, 17)
+    ref = ssd.cdist(X[3:23].astype(np.float64), X[30:47].astype(np.float64), "sqeuclidean")
+    assert np.allclose(B, ref, rtol=1e-13, atol=0)
+    assert B[5, 7] == oracle.d2(X, 8, 37)
+    G = rng.integers(0, 3, (40, 33)).astype(np.int8)
+    Bi = oracle.block_d2(G, 0, 40, 0, 40)
+    Gi = G.astype(np.int64)
+    assert np.array_equal(Bi, ((Gi[:, None, :] - Gi[None, :, :]) ** 2).sum(-1).astype(np.float64))
