@@ -476,7 +476,9 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
     }
     int rc;
     if ((rc = get(W.xs, xs_b))) return rc;
-    if ((rc = get(W.shat, sh_b))) return rc;
+    // BF16: the folded row scalars (8 bytes a row) follow the row scalars
+    const size_t fold_b = prec == P_BF16 ? 2 * sh_b : 0;
+    if ((rc = get(W.shat, sh_b + fold_b))) return rc;
     if ((rc = get(W.bmax, bm_b))) return rc;
     if ((rc = get(W.musg, 2 * mu_b))) return rc;
     if ((rc = get(W.probs, np * sizeof(Prob)))) return rc;
@@ -522,7 +524,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         nfull = forced_nfull;
         nfull_pairs = timed_pairs(tl, forced_nfull);
         if ((rc = get(W.tiles, std::max<size_t>(tl.size(), 1) * 8))) return rc;
-        if ((rc = get(W.tile_min, std::max<size_t>(tl.size(), 1) * 4))) return rc;
+        if ((rc = get(W.tile_min, std::max<size_t>(tl.size(), 1) * 16))) return rc;
         if ((rc = get(W.sel, std::max<size_t>(tl.size(), 1) * 8))) return rc;
         if (!tl.empty()) HIPCHK(c, hipMemcpyAsync(W.tiles.p, tl.data(), tl.size() * 8, hipMemcpyHostToDevice, st));
         if (!tl.empty() && !forced) HIPCHK(c, hipStreamSynchronize(st));   // `built` is released on return
@@ -537,7 +539,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             c->nfull = nf;
             c->nfull_pairs = timed_pairs(tl, nf);
             if ((rc = get(W.tiles, tl.size() * 8))) return rc;
-            if ((rc = get(W.tile_min, tl.size() * 4))) return rc;
+            if ((rc = get(W.tile_min, tl.size() * 16))) return rc;
             if ((rc = get(W.sel, tl.size() * 8))) return rc;
             if (!tl.empty()) HIPCHK(c, hipMemcpy(W.tiles.p, tl.data(), tl.size() * 8, hipMemcpyHostToDevice));
             c->ntiles = (int64_t)tl.size();
@@ -576,6 +578,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             memset(&q, 0, sizeof q);
             q.xs = (char *)W.xs.p + h.xs_off;
             q.shat = (char *)W.shat.p + h.sh_off;
+            q.fold = fold_b ? (const uint2 *)((char *)W.shat.p + sh_b + 2 * h.sh_off) : nullptr;
             q.bmax = (const float4 *)((char *)W.bmax.p + h.bm_off);
             q.src = h.src;
             q.n = h.n;
@@ -604,6 +607,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
                 blk += h.npad / SERIES_WPB;
                 j.xs = (void *)q.xs;
                 j.shat = (void *)q.shat;
+                j.fold = (uint2 *)q.fold;
                 j.bmax = (float4 *)q.bmax;
                 j.mu = (double *)q.mu;
                 j.sigma = (double *)q.sigma;
@@ -644,7 +648,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
                 const HostProb &h = hp[0];
                 launch_prep_points(h.src, h.src_i8 ? CPMI_I8 : CPMI_F32, h.n, h.d, h.ld, prec, P[0].xs ? (void *)P[0].xs : nullptr,
                                    h.kpad, h.npad, (void *)P[0].shat, (float4 *)P[0].bmax, tile, &dres[0].flags,
-                                   h.perm, st);
+                                   h.perm, (uint2 *)P[0].fold, st);
             }
             ScreenArgs a;
             memset(&a, 0, sizeof a);
@@ -675,7 +679,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
                 const bool timed_masked = nfull == 0;
                 ScreenArgs q = a;
                 q.tiles = a.tiles + nfull;
-                q.tile_min = a.tile_min + nfull;
+                q.tile_min = a.tile_min + 4 * nfull;
                 q.ntiles = ntiles - nfull;
                 if (!batch_graph && timed_masked) hipEventRecord(c->es0, st);
                 launch_screen(prec, tile, M_MIN, true, q, std::min<int64_t>(ntiles - nfull, c->ncu), st);

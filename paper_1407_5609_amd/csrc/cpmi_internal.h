@@ -48,7 +48,29 @@ struct Prob {
                            // j < n and j - split != i. 0 for a single set.
     const int32_t *perm;   // screen row r holds source row perm[r] (reference-point order), or null
     int64_t na;            // two-set problem: rows of the first set
+    const uint2 *fold;     // BF16 screens: per row, fold_words(s^) (the folded row scalar), else null
 };
+
+// The folded row scalar of the BF16 256-row screen: c = -s^/4 split into three
+// BF16 parts c1 + c2 + c3 (each rounded to nearest even, the remainders exact),
+// packed as (c1 | c2 << 16, c3 | 1.0 << 16) so that the screen builds its
+// matrix-core operands [c1 c2 c3 1 1 1 0 0] / [1 1 1 c1 c2 c3 0 0] from two
+// words. |c1 + c2 + c3 - c| <= 2^-27 |c|.
+__host__ __device__ inline uint32_t bf16_rne_bits(float f)
+{
+    const uint32_t u = __builtin_bit_cast(uint32_t, f);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__host__ __device__ inline uint2 fold_words(float s)
+{
+    const float c = -0.25f * s;
+    const uint32_t h1 = bf16_rne_bits(c);
+    const float r1 = c - __builtin_bit_cast(float, h1 << 16);
+    const uint32_t h2 = bf16_rne_bits(r1);
+    const float r2 = r1 - __builtin_bit_cast(float, h2 << 16);
+    const uint32_t h3 = bf16_rne_bits(r2);
+    return make_uint2(h1 | (h2 << 16), h3 | (0x3f80u << 16));
+}
 
 // Source row of screen row r.
 __host__ __device__ inline int64_t src_row(const Prob &P, int64_t r) { return P.perm ? (int64_t)P.perm[r] : r; }
@@ -71,7 +93,7 @@ struct ScreenArgs {
     const uint64_t *tiles;     // tile list
     int64_t ntiles;            // entries (pass 1); pass 2 reads *sel_count
     const u64c *sel_count;     // pass 2: number of valid entries of `tiles` (below 2^31)
-    uint32_t *tile_min;        // pass 1: per entry, min screen value (float or int32 bits)
+    uint32_t *tile_min;        // pass 1: per entry, four words: each wave's min screen value (float or int32 bits)
     const double *U;           // pass 2: per problem closest-pair upper bound, or null (no pair search)
     Cand *candR;               // radius candidates
     u64c *cntR;                // their counter (may exceed capR: the required size)
@@ -151,6 +173,7 @@ struct SeriesJob {
     int32_t kpad;
     int32_t pad0;
     const int32_t *iperm;  // screen row of window w (reference order), or null for w itself
+    uint2 *fold;           // BF16: per row fold_words(s^), else null
     float4 *rowstat;       // with iperm: per-row maxima terms, reduced per block by launch_block_max
 };
 
@@ -166,7 +189,7 @@ void launch_calib_copy(const void *src, void *dst, int64_t n16, hipStream_t st);
 // per-block maxima (bmax must be zero on entry), flags.
 void launch_prep_points(const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, int prec, void *xs,
                         int32_t kpad, int64_t npad, void *shat, float4 *bmax, int tile, unsigned int *flags,
-                        const int32_t *perm, hipStream_t st);
+                        const int32_t *perm, uint2 *fold, hipStream_t st);
 
 // Window builder of many series: canonical mean/sigma, z-normalised screen
 // operand, row scalars, block maxima (zero on entry), flags.

@@ -155,7 +155,7 @@ template <int PREC, bool INT8_IN>
 __global__ __launch_bounds__(256) void prep_points_kernel(const void *pts, int64_t n, int64_t d, int64_t ld,
                                                           void *xs, int32_t kpad, int64_t npad, void *shat,
                                                           float4 *bmax, int tile, unsigned int *flags,
-                                                          const int32_t *perm)
+                                                          const int32_t *perm, uint2 *fold)
 {
     __shared__ float4 sh_bm[4];
     __shared__ unsigned int sh_f[4];
@@ -248,6 +248,7 @@ __global__ __launch_bounds__(256) void prep_points_kernel(const void *pts, int64
             const unsigned long long anybad = __ballot(bad);
             if (lane == 0) {
                 ((float *)shat)[row] = (float)s;
+                if (fold) fold[row] = fold_words((float)s);
                 bm.x = fmaxf(bm.x, f32_up(s));
                 bm.y = fmaxf(bm.y, up_f32(sqrt(s)));
                 bm.z = fmaxf(bm.z, up_f32(sqrt(t2)));
@@ -285,18 +286,18 @@ __global__ __launch_bounds__(256) void prep_points_kernel(const void *pts, int64
 
 void launch_prep_points(const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, int prec, void *xs,
                         int32_t kpad, int64_t npad, void *shat, float4 *bmax, int tile, unsigned int *flags,
-                        const int32_t *perm, hipStream_t st)
+                        const int32_t *perm, uint2 *fold, hipStream_t st)
 {
     dim3 g((unsigned)(npad / PREP_ROWS)), b(256);
     if (dtype == 1)
         hipLaunchKernelGGL((prep_points_kernel<P_I8, true>), g, b, 0, st, pts, n, d, ld, xs, kpad, npad, shat, bmax,
-                           tile, flags, perm);
+                           tile, flags, perm, nullptr);
     else if (prec == P_BF16)
         hipLaunchKernelGGL((prep_points_kernel<P_BF16, false>), g, b, 0, st, pts, n, d, ld, xs, kpad, npad, shat,
-                           bmax, tile, flags, perm);
+                           bmax, tile, flags, perm, fold);
     else
         hipLaunchKernelGGL((prep_points_kernel<P_F32, false>), g, b, 0, st, pts, n, d, ld, xs, kpad, npad, shat,
-                           bmax, tile, flags, perm);
+                           bmax, tile, flags, perm, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -468,6 +469,7 @@ __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs,
     t2 = (sh_part[1][0][lane] + sh_part[1][1][lane]) + (sh_part[1][2][lane] + sh_part[1][3][lane]);
     r2 = (sh_part[2][0][lane] + sh_part[2][1][lane]) + (sh_part[2][2][lane] + sh_part[2][3][lane]);
     ((float *)J.shat)[row] = (float)s;
+    if (J.fold) J.fold[row] = fold_words((float)s);
     // r: distance of the operand from the canonical window, widened by
     // 2^-50 ||x|| for the reciprocal's rounding (the norms carry the 2^-40
     // widening of up_f32, which covers it)

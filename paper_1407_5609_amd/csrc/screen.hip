@@ -87,7 +87,6 @@ __global__ __launch_bounds__(NTHREADS) void screen_kernel(ScreenArgs args)
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * TILE * LSTRIDE];
     __shared__ S sh_si[TILE];
     __shared__ S sh_sj[TILE];
-    __shared__ S sh_red[4];
 
     unsigned char *ldsA = lds;
     unsigned char *ldsB = lds + TILE * LSTRIDE;
@@ -261,16 +260,11 @@ __global__ __launch_bounds__(NTHREADS) void screen_kernel(ScreenArgs args)
             }
         }
         if constexpr (MODE & M_MIN) {
+            // each wave stores the minimum of its quarter of the tile
             mn = wave_min(mn);
-            if (lane == 0) sh_red[wave] = mn;
-            __syncthreads();
-            if (tid == 0) {
-                S m = sh_red[0];
-                for (int w = 1; w < 4; ++w) m = PREC == P_I8 ? (S)min((int)m, (int)sh_red[w]) : (S)fminf(m, sh_red[w]);
-                args.tile_min[t] = __builtin_bit_cast(uint32_t, m);
-            }
+            if (lane == 0) args.tile_min[4 * t + wave] = __builtin_bit_cast(uint32_t, mn);
         }
-        __syncthreads();  // LDS (sh_si/sh_sj/sh_red) is reused by the next tile
+        __syncthreads();  // LDS (sh_si/sh_sj) is reused by the next tile
     }
 }
 

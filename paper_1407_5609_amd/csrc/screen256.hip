@@ -89,23 +89,27 @@ __device__ __forceinline__ int fresh_lane()
     return l;
 }
 
-// Minimum over the wave, returned in every lane: xor butterflies within each
-// half-wave (ds_swizzle bit-mask mode, offset = xor_mask << 10 | 0x1f), then
-// the two halves through lanes 0 and 32. No lane index is needed.
-#define CPMI_SWZ_STEP(PAT)                                                                           \
-    v = smin(v, __builtin_bit_cast(S, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), PAT)))
+// Minimum over the wave, returned in every lane: within each row of 16 lanes
+// by DPP steps (lane pairs, then quad pairs, then row-half and row mirrors:
+// every lane ends with its row's minimum), then the four rows through
+// lanes 0, 16, 32 and 48. No LDS round trip, no lane index.
+template <int CTRL, typename S> __device__ __forceinline__ S dpp_min(S v)
+{
+    return smin(v, __builtin_bit_cast(S, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf,
+                                                                     false)));
+}
 template <typename S> __device__ __forceinline__ S wmin(S v)
 {
-    CPMI_SWZ_STEP(0x041f);
-    CPMI_SWZ_STEP(0x081f);
-    CPMI_SWZ_STEP(0x101f);
-    CPMI_SWZ_STEP(0x201f);
-    CPMI_SWZ_STEP(0x401f);
+    v = dpp_min<0xb1>(v);    // quad_perm [1,0,3,2]
+    v = dpp_min<0x4e>(v);    // quad_perm [2,3,0,1]
+    v = dpp_min<0x141>(v);   // row_half_mirror
+    v = dpp_min<0x140>(v);   // row_mirror
     const S a = __builtin_bit_cast(S, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
-    const S b = __builtin_bit_cast(S, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
-    return smin(a, b);
+    const S b = __builtin_bit_cast(S, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
+    const S c = __builtin_bit_cast(S, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+    const S d = __builtin_bit_cast(S, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
+    return smin(smin(a, b), smin(c, d));
 }
-#undef CPMI_SWZ_STEP
 
 // s^_j - 2 g  (float: one fma; int8: exact int32)
 [[maybe_unused]] __device__ __forceinline__ float part(float g, float sj) { return fmaf(-2.0f, g, sj); }
@@ -144,6 +148,18 @@ __device__ __forceinline__ u32x4 lds_landed_4x32(const void *p)
                  : "=&v"(lo), "=&v"(hi)
                  : "v"(a));
     return u32x4{lo.x, lo.y, hi.x, hi.y};
+}
+
+// Four 8-byte values at p, p + 256 B, p + 512 B, p + 768 B, as (first two,
+// last two).
+__device__ __forceinline__ void lds_landed_4x64(const void *p, u32x4 &lo, u32x4 &hi)
+{
+    const uint32_t a = (uint32_t)(uintptr_t)p;
+    asm volatile("ds_read2_b64 %0, %2 offset1:32\n\t"
+                 "ds_read2_b64 %1, %2 offset0:64 offset1:96\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(lo), "=&v"(hi)
+                 : "v"(a));
 }
 
 }  // namespace
@@ -216,7 +232,6 @@ constexpr int SG_DS_READ = 0x100;
 // s_waitcnt immediates (gfx9 encoding: vmcnt[3:0] | expcnt << 4 | lgkmcnt << 8 | vmcnt[5:4] << 14).
 // WAIT_SLICE: at most the 16 loads of the two newest slices in flight, all LDS reads done.
 constexpr int WAIT_SLICE = (16 & 15) | (7 << 4) | (0 << 8) | ((16 >> 4) << 14);
-constexpr int WAIT_LGKM0 = 15 | (7 << 4) | (0 << 8) | (3 << 14);
 
 template <int PREC> using Frags = u32x4[MB256];
 
@@ -293,31 +308,20 @@ __device__ __forceinline__ void slice_step(typename A2<PREC>::T (&acc)[MB256][MB
 //   the other pattern. Both halves then contribute c_i + c_j.
 //   FP32 (K = 2; lane half h holds k = h): A = (c_i, 1), B = (1, c_j) with
 //   c = -s^/2.
-__device__ __forceinline__ uint32_t bf16_rne_bits(float f)
+// BF16 fragment [c1 c2 c3 1 1 1 0 0] (first) or [1 1 1 c1 c2 c3 0 0] from the
+// row's folded scalar words w0 = c1 | c2 << 16, w1 = c3 | 1.0 << 16 (written
+// by the builder, fold_words).
+__device__ __forceinline__ u32x4 fold_frag_words(uint32_t w0, uint32_t w1, bool first)
 {
-    const uint32_t u = __float_as_uint(f);
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
-
-// BF16 fragment [c1 c2 c3 1 1 1 0 0] (first) or [1 1 1 c1 c2 c3 0 0] of
-// c = -s/4, the parts taken by round-to-nearest-even with exact remainders.
-__device__ __forceinline__ u32x4 fold_frag_bf16(float s, bool first)
-{
-    const float c = -0.25f * s;
-    const uint32_t h1 = bf16_rne_bits(c);
-    const float r1 = c - __uint_as_float(h1 << 16);
-    const uint32_t h2 = bf16_rne_bits(r1);
-    const float r2 = r1 - __uint_as_float(h2 << 16);
-    const uint32_t h3 = bf16_rne_bits(r2);
-    constexpr uint32_t ONE = 0x3f80u;
-    // per-dword selects (the lane half is divergent: no branches)
-    const uint32_t p0 = h1 | (h2 << 16), p1 = h3 | (ONE << 16), p2 = ONE | (ONE << 16);
-    const uint32_t q0 = ONE | (ONE << 16), q1 = ONE | (h1 << 16), q2 = h2 | (h3 << 16);
-    // the zero dword is materialised here rather than shared with a
-    // loop-wide zero register (which the allocator would spill with it)
+    constexpr uint32_t ONE2 = 0x3f803f80u;
+    const uint32_t q1 = 0x3f80u | (w0 << 16);
+    const uint32_t q2 = __builtin_amdgcn_alignbit(w1, w0, 16);
+    // per-dword selects (the lane half is divergent: no branches); the zero
+    // dword is materialised here rather than shared with a loop-wide zero
+    // register (which the allocator would spill with it)
     uint32_t z;
     asm volatile("v_mov_b32 %0, 0" : "=v"(z));
-    return u32x4{first ? p0 : q0, first ? p1 : q1, first ? p2 : q2, z};
+    return u32x4{first ? w0 : ONE2, first ? w1 : q1, first ? ONE2 : q2, z};
 }
 
 // MASKED = false: every pair of every listed tile is admissible (the host
@@ -331,10 +335,12 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     constexpr int ESZ = PREC == P_F32 ? 4 : (PREC == P_BF16 ? 2 : 1);
     constexpr bool FOLD = PREC != P_I8;  // row scalars folded into the product
 
-    __shared__ S sh_red[4];
     // row scalars of blocks I and J, double-buffered by tile parity: the
-    // scalars of the next tile are loaded while the current one is screened
-    __shared__ __attribute__((aligned(16))) S sh_s[2 * 2 * T256];
+    // scalars of the next tile are loaded while the current one is screened.
+    // BF16: the two folded-scalar words of each row; else s^ (one word)
+    constexpr int SW = PREC == P_BF16 ? 2 : 1;
+    __shared__ __attribute__((aligned(16))) uint32_t sh_w[2 * 2 * T256 * SW];
+    S *const sh_s = (S *)sh_w;
     // source positions of the rows of blocks I and J (windows of a series in
     // reference order; same double buffering), for the exclusion zone
     __shared__ __attribute__((aligned(16))) int32_t sh_o[2 * 2 * T256];
@@ -357,13 +363,28 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     auto load_scalars = [&](int32_t tt, int half) {
         const uint64_t e = tiles[tt];
         const c_prob &Q = ((c_prob *)args.probs)[tile_prob(e)];
-        const unsigned char *sb = (const unsigned char *)Q.shat;
         const uint32_t lo = (uint32_t)fresh_lane() * 4;
-        S *dst = sh_s + half * (2 * T256);
-        __builtin_amdgcn_global_load_lds((g_void *)(sb + ((int64_t)tile_I(e) * T256 + wave * 64) * 4 + lo),
-                                         (lds_void *)(dst + wave * 64), 4, 0, 0);
-        __builtin_amdgcn_global_load_lds((g_void *)(sb + ((int64_t)tile_J(e) * T256 + wave * 64) * 4 + lo),
-                                         (lds_void *)(dst + T256 + wave * 64), 4, 0, 0);
+        if constexpr (PREC == P_BF16) {
+            // 64 rows x 8 bytes of block I and of block J: two 256-byte loads each
+            const unsigned char *fb = (const unsigned char *)Q.fold;
+            uint32_t *dst = sh_w + half * (2 * T256 * 2);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                __builtin_amdgcn_global_load_lds(
+                    (g_void *)(fb + ((int64_t)tile_I(e) * T256 + wave * 64) * 8 + h * 256 + lo),
+                    (lds_void *)(dst + wave * 128 + h * 64), 4, 0, 0);
+                __builtin_amdgcn_global_load_lds(
+                    (g_void *)(fb + ((int64_t)tile_J(e) * T256 + wave * 64) * 8 + h * 256 + lo),
+                    (lds_void *)(dst + 2 * T256 + wave * 128 + h * 64), 4, 0, 0);
+            }
+        } else {
+            const unsigned char *sb = (const unsigned char *)Q.shat;
+            S *dst = sh_s + half * (2 * T256);
+            __builtin_amdgcn_global_load_lds((g_void *)(sb + ((int64_t)tile_I(e) * T256 + wave * 64) * 4 + lo),
+                                             (lds_void *)(dst + wave * 64), 4, 0, 0);
+            __builtin_amdgcn_global_load_lds((g_void *)(sb + ((int64_t)tile_J(e) * T256 + wave * 64) * 4 + lo),
+                                             (lds_void *)(dst + T256 + wave * 64), 4, 0, 0);
+        }
         if constexpr (MASKED) {
             if (Q.perm && Q.motif) {
                 // the permutation is padded to whole blocks by the host
@@ -422,6 +443,7 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         // this tile's row scalars were loaded one tile ago (or before the
         // loop) and are older than every slice waited for since
         const S *sh_t = sh_s + (tcount & 1) * (2 * T256);
+        const uint32_t *shw_t = sh_w + (tcount & 1) * (2 * T256 * 2);   // BF16 fold words
         const int32_t *sh_ot = sh_o + (tcount & 1) * (2 * T256);
         const int32_t tn = next_valid(t + stride);
         if (tn < count) load_scalars(tn, (tcount + 1) & 1);
@@ -429,19 +451,21 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
 
         AccT acc[MB256][MB256];
         if constexpr (FOLD) {
-            // s^ of this lane's rows: A block m row wm*128 + 32 m + lrow,
-            // B block m row wn*128 + 32 m + lrow
-            const u32x4 sa = lds_landed_4x32(sh_t + wm * WT256 + lrow);
-            const u32x4 sb = lds_landed_4x32(sh_t + T256 + wn * WT256 + lrow);
-            const uint32_t sav[4] = {sa.x, sa.y, sa.z, sa.w};
-            const uint32_t sbv[4] = {sb.x, sb.y, sb.z, sb.w};
+            // the row scalars of this lane's rows: A block m row
+            // wm*128 + 32 m + lrow, B block m row wn*128 + 32 m + lrow
             if constexpr (PREC == P_BF16) {
+                u32x4 a01, a23, b01, b23;
+                lds_landed_4x64(shw_t + 2 * (wm * WT256 + lrow), a01, a23);
+                lds_landed_4x64(shw_t + 2 * (T256 + wn * WT256 + lrow), b01, b23);
                 u32x4 fa[MB256], fb[MB256];
-#pragma unroll
-                for (int m = 0; m < MB256; ++m) {
-                    fa[m] = fold_frag_bf16(__uint_as_float(sav[m]), lhalf == 0);
-                    fb[m] = fold_frag_bf16(__uint_as_float(sbv[m]), lhalf != 0);
-                }
+                fa[0] = fold_frag_words(a01.x, a01.y, lhalf == 0);
+                fa[1] = fold_frag_words(a01.z, a01.w, lhalf == 0);
+                fa[2] = fold_frag_words(a23.x, a23.y, lhalf == 0);
+                fa[3] = fold_frag_words(a23.z, a23.w, lhalf == 0);
+                fb[0] = fold_frag_words(b01.x, b01.y, lhalf != 0);
+                fb[1] = fold_frag_words(b01.z, b01.w, lhalf != 0);
+                fb[2] = fold_frag_words(b23.x, b23.y, lhalf != 0);
+                fb[3] = fold_frag_words(b23.z, b23.w, lhalf != 0);
 #pragma unroll
                 for (int a = 0; a < MB256; ++a)
 #pragma unroll
@@ -450,6 +474,10 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                                                                             __builtin_bit_cast(bf16x8, fb[b]),
                                                                             AccT{}, 0, 0, 0);
             } else {
+                const u32x4 sa = lds_landed_4x32(sh_t + wm * WT256 + lrow);
+                const u32x4 sb = lds_landed_4x32(sh_t + T256 + wn * WT256 + lrow);
+                const uint32_t sav[4] = {sa.x, sa.y, sa.z, sa.w};
+                const uint32_t sbv[4] = {sb.x, sb.y, sb.z, sb.w};
                 float fa[MB256], fb[MB256];
 #pragma unroll
                 for (int m = 0; m < MB256; ++m) {
@@ -781,14 +809,12 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
             }
         }
         if constexpr (MODE & M_MIN) {
+            // each wave stores the minimum of its quarter of the tile
             best = wmin(best);
-            if (fresh_lane() == 0) sh_red[wave] = best;
-            __builtin_amdgcn_s_waitcnt(WAIT_LGKM0);
-            __builtin_amdgcn_s_barrier();
-            if (wave == 0 && fresh_lane() == 0) {
-                S m = smin(smin(sh_red[0], sh_red[1]), smin(sh_red[2], sh_red[3]));
-                args.tile_min[t] = __builtin_bit_cast(uint32_t, m);
-            }
+            if (fresh_lane() == 0) args.tile_min[4 * t + wave] = __builtin_bit_cast(uint32_t, best);
+            // window positions are read at uneven times across the waves and
+            // the next tile's top prefetches into the same half (masked tiles)
+            if constexpr (MASKED) __builtin_amdgcn_s_barrier();
         } else {
             // The emission reads this tile's row scalars and positions from
             // LDS at uneven times across the waves; the next tile's top

@@ -24,6 +24,14 @@ __device__ __forceinline__ double tile_min_value(uint32_t bits, int prec)
     return prec == P_I8 ? (double)(int)bits : (double)__uint_as_float(bits);
 }
 
+// Minimum screen value of list entry t: the least of its four waves' minima.
+__device__ __forceinline__ double tile_min_of(const uint32_t *tile_min, int64_t t, int prec)
+{
+    const uint4 w = *(const uint4 *)(tile_min + 4 * t);
+    return fmin(fmin(tile_min_value(w.x, prec), tile_min_value(w.y, prec)),
+                fmin(tile_min_value(w.z, prec), tile_min_value(w.w, prec)));
+}
+
 __device__ __forceinline__ double tile_bound_of(const Prob &P, int64_t I, int64_t J, int prec)
 {
     if (prec == P_I8) return 0.0;
@@ -50,7 +58,7 @@ __global__ void reduce_U_kernel(const Prob *probs, const uint64_t *tiles, int64_
             const uint64_t e = tiles[t];
             if (e != TILE_NONE) {
                 p = tile_prob(e);
-                const double m = tile_min_value(tile_min[t], prec);
+                const double m = tile_min_of(tile_min, t, prec);
                 if (m == m && !isinf(m)) {
                     const Prob &P = probs[p];
                     const double E = tile_bound_of(P, tile_I(e), tile_J(e), prec);
@@ -98,7 +106,7 @@ __global__ void select_kernel(const Prob *probs, const uint64_t *tiles, int64_t 
         if (e == TILE_NONE) continue;
         const uint32_t p = tile_prob(e);
         const Prob &P = probs[p];
-        const double m = tile_min_value(tile_min[t], prec);
+        const double m = tile_min_of(tile_min, t, prec);
         if (!(m == m) || isinf(m)) continue;
         const double E = tile_bound_of(P, tile_I(e), tile_J(e), prec);
         double lb = m - E;
