@@ -308,7 +308,8 @@ int cpmi_strings_pair(cpmi_ctx *ctx, const int8_t *strings, int64_t n, int64_t k
  * always the pair's exact one. *pairs_out (host, nullable) receives the
  * number of candidate pairs collected over all iterations (the paper's
  * measure of work). cap: candidate pairs one iteration may hold. strings:
- * device, as for cpmi_strings_pair; out: host. Needs n < 2^21 - 1. Errors:
+ * device, as for cpmi_strings_pair; out: host. Needs n < 2^21 - 1 and
+ * k < 2^22. Errors:
  * ERR_ARG (shapes, mode, columns, iterations, cap, a symbol outside the
  * alphabet), ERR_NOPAIR (n < 2, or no two rows ever shared a bucket),
  * ERR_CAPACITY (an iteration produced more than cap candidates; *pairs_out

@@ -104,6 +104,19 @@ int cpmi_dbg_copy(void *dst, const void *src, int64_t bytes, void *stream);
  * the rounding of the distances (Section 3, triangle inequality). */
 double cpmi_dbg_tile_lb(const double *loI, const double *hiI, const double *loJ, const double *hiJ, int q);
 
+/* Host only: the tile list of the reference-point pruned search of one point
+ * set of n rows (tile edge 128 or 256, q references): lo, hi (host, nT * q
+ * doubles, nT = ceil(n / tile)) are the per-block distance intervals, block
+ * I's interval for reference k at [I * q + k]; rows are in the order of
+ * reference 0, so lo[I * q] is non-decreasing in I. A tile (I, J), I <= J,
+ * is kept unless some reference's intervals, each widened by 2^-34 |hi|,
+ * are more than T apart (T < 0: every tile dropped); band >= 0 keeps only
+ * J - I <= band. Writes min(count, cap) entries (packed as
+ * cpmi_dbg_tile_list) to out, the leading full-tile slots to *nfull and the
+ * tiles dropped to *npruned (both nullable); returns the count, or ERR_ARG. */
+int64_t cpmi_dbg_pruned_tiles(int64_t n, int tile, int q, const double *lo, const double *hi, double T, int64_t band,
+                              uint64_t *out, int64_t cap, int64_t *nfull, int64_t *npruned);
+
 /* Host only: the tuning decisions of a context with `ncu` compute units
  * after reading the cache file cache_in (nullable): the precision and tile a
  * call with (dtype, precision, d, pairs) would use, as cpmi_tune_lookup. If

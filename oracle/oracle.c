@@ -410,6 +410,103 @@ int64_t orc_frnn_i8(const int8_t *X, int64_t n, int64_t d, int64_t ld, int64_t e
     ORC_FRNN_BODY((double)orc_d2_i8(X, d, ld, i, j))
 }
 
+/* The same radius list over FP64 rows with SIMD lanes across pairs j, as
+ * orc_cpp_f64_lanes does for the closest pair: each pair's d^2 is the
+ * ascending-k fma chain of orc_d2_f64, compared with R2 as in orc_frnn_f64,
+ * and the list is sorted the same way, so the output is the same bit for bit.
+ * Used to write expected radius lists of large inputs. */
+int64_t orc_frnn_f64_lanes(const double *X, int64_t n, int64_t d, int64_t ld, int64_t excl, double R2,
+                           int64_t *pairs, double *d2_out, int64_t cap)
+{
+    if (excl < 1) excl = 1;
+    if (n < 2 || d < 1) return 0;
+    const int64_t nb = (n + ORC_PJ - 1) / ORC_PJ;
+    const int64_t ni = (n + ORC_PI - 1) / ORC_PI * ORC_PI;
+    double *P = (double *)aligned_alloc(64, (size_t)(nb * d * ORC_PJ) * sizeof(double));
+    double *A = (double *)malloc((size_t)(ni * d) * sizeof(double));
+    if (!P || !A) { free(P); free(A); return ORC_NOMEM; }
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < nb; ++b)
+        for (int64_t k = 0; k < d; ++k)
+            for (int64_t l = 0; l < ORC_PJ; ++l) {
+                const int64_t j = b * ORC_PJ + l;
+                P[(b * d + k) * ORC_PJ + l] = j < n ? X[j * ld + k] : 0.0;
+            }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < ni; ++i)
+        for (int64_t k = 0; k < d; ++k) A[i * d + k] = i < n ? X[i * ld + k] : 0.0;
+
+    orc_vec all = {0, 0, 0, 0};
+    const int64_t nblk = (n + ORC_IB - 1) / ORC_IB;
+#pragma omp parallel
+    {
+        orc_vec loc = {0, 0, 0, 0};
+        double out[ORC_PI][ORC_PJ];
+#pragma omp for schedule(dynamic, 1) nowait
+        for (int64_t blk = 0; blk < nblk; ++blk) {
+            const int64_t i0 = blk * ORC_IB;
+            const int64_t i1 = i0 + ORC_IB < ni ? i0 + ORC_IB : ni;
+            if (i0 + excl >= n) continue;
+            for (int64_t b = (i0 + excl) / ORC_PJ; b < nb; ++b) {
+                const double *pb = P + b * d * ORC_PJ;
+                for (int64_t i = i0; i < i1; i += ORC_PI) {
+                    if (i >= n) break;
+                    if (b * ORC_PJ + ORC_PJ - 1 < i + excl) continue;
+                    const double *a0 = A + i * d, *a1 = a0 + d, *a2 = a1 + d, *a3 = a2 + d;
+                    __m256d c00 = _mm256_setzero_pd(), c01 = _mm256_setzero_pd();
+                    __m256d c10 = _mm256_setzero_pd(), c11 = _mm256_setzero_pd();
+                    __m256d c20 = _mm256_setzero_pd(), c21 = _mm256_setzero_pd();
+                    __m256d c30 = _mm256_setzero_pd(), c31 = _mm256_setzero_pd();
+                    for (int64_t k = 0; k < d; ++k) {
+                        const __m256d y0 = _mm256_load_pd(pb + k * ORC_PJ);
+                        const __m256d y1 = _mm256_load_pd(pb + k * ORC_PJ + 4);
+                        __m256d x, t;
+                        x = _mm256_broadcast_sd(a0 + k);
+                        t = _mm256_sub_pd(x, y0); c00 = _mm256_fmadd_pd(t, t, c00);
+                        t = _mm256_sub_pd(x, y1); c01 = _mm256_fmadd_pd(t, t, c01);
+                        x = _mm256_broadcast_sd(a1 + k);
+                        t = _mm256_sub_pd(x, y0); c10 = _mm256_fmadd_pd(t, t, c10);
+                        t = _mm256_sub_pd(x, y1); c11 = _mm256_fmadd_pd(t, t, c11);
+                        x = _mm256_broadcast_sd(a2 + k);
+                        t = _mm256_sub_pd(x, y0); c20 = _mm256_fmadd_pd(t, t, c20);
+                        t = _mm256_sub_pd(x, y1); c21 = _mm256_fmadd_pd(t, t, c21);
+                        x = _mm256_broadcast_sd(a3 + k);
+                        t = _mm256_sub_pd(x, y0); c30 = _mm256_fmadd_pd(t, t, c30);
+                        t = _mm256_sub_pd(x, y1); c31 = _mm256_fmadd_pd(t, t, c31);
+                    }
+                    _mm256_storeu_pd(out[0], c00); _mm256_storeu_pd(out[0] + 4, c01);
+                    _mm256_storeu_pd(out[1], c10); _mm256_storeu_pd(out[1] + 4, c11);
+                    _mm256_storeu_pd(out[2], c20); _mm256_storeu_pd(out[2] + 4, c21);
+                    _mm256_storeu_pd(out[3], c30); _mm256_storeu_pd(out[3] + 4, c31);
+                    for (int r = 0; r < ORC_PI; ++r)
+                        for (int l = 0; l < ORC_PJ; ++l) {
+                            const int64_t ii = i + r, jj = b * ORC_PJ + l;
+                            if (ii >= n || jj >= n || jj < ii + excl) continue;
+                            if (out[r][l] <= R2) vec_push(&loc, ii, jj, out[r][l]);
+                        }
+                }
+            }
+        }
+#pragma omp critical
+        {
+            if (loc.fail) all.fail = 1;
+            for (int64_t t = 0; t < loc.n; ++t) vec_push(&all, loc.v[t].i, loc.v[t].j, loc.v[t].d2);
+        }
+        free(loc.v);
+    }
+    free(P);
+    free(A);
+    if (all.fail) { free(all.v); return ORC_NOMEM; }
+    if (all.n > 1) qsort(all.v, (size_t)all.n, sizeof(orc_rec), rec_cmp);
+    for (int64_t t = 0; t < all.n && t < cap; ++t) {
+        pairs[2 * t] = all.v[t].i; pairs[2 * t + 1] = all.v[t].j;
+        if (d2_out) d2_out[t] = all.v[t].d2;
+    }
+    const int64_t cnt = all.n;
+    free(all.v);
+    return cnt;
+}
+
 /* d^2 of every pair (i0 + a, j0 + b), a < ni, b < nj, into out[a * nj + b]:
  * a block of the distance matrix (used to check sampled screen values). */
 void orc_block_d2_f32(const float *X, int64_t d, int64_t ld, int64_t i0, int64_t ni, int64_t j0, int64_t nj,

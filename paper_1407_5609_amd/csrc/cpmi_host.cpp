@@ -525,7 +525,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         nfull_pairs = timed_pairs(tl, forced_nfull);
         if ((rc = get(W.tiles, std::max<size_t>(tl.size(), 1) * 8))) return rc;
         if ((rc = get(W.tile_min, std::max<size_t>(tl.size(), 1) * 16))) return rc;
-        if ((rc = get(W.sel, std::max<size_t>(tl.size(), 1) * 8))) return rc;
+        if ((rc = get(W.sel, std::max<size_t>(tl.size(), 1) * 16))) return rc;
         if (!tl.empty()) HIPCHK(c, hipMemcpyAsync(W.tiles.p, tl.data(), tl.size() * 8, hipMemcpyHostToDevice, st));
         if (!tl.empty() && !forced) HIPCHK(c, hipStreamSynchronize(st));   // `built` is released on return
         ntiles = (int64_t)tl.size();
@@ -540,7 +540,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             c->nfull_pairs = timed_pairs(tl, nf);
             if ((rc = get(W.tiles, tl.size() * 8))) return rc;
             if ((rc = get(W.tile_min, tl.size() * 16))) return rc;
-            if ((rc = get(W.sel, tl.size() * 8))) return rc;
+            if ((rc = get(W.sel, tl.size() * 16))) return rc;
             if (!tl.empty()) HIPCHK(c, hipMemcpy(W.tiles.p, tl.data(), tl.size() * 8, hipMemcpyHostToDevice));
             c->ntiles = (int64_t)tl.size();
             c->tiles_key = key;
@@ -695,10 +695,13 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             }
             unsigned long long *ubits = want_cpp ? (unsigned long long *)W.ubits.p : nullptr;
             if (want_cpp) launch_reduce_U(dprobs, a.tiles, ntiles, a.tile_min, prec, ubits, st);
-            launch_select(dprobs, a.tiles, ntiles, a.tile_min, prec, ubits, (uint64_t *)W.sel.p, dcnt + C_SEL, st);
+            // selected tiles: appended at sel, and in list order at sel + ntiles
+            uint64_t *sel = (uint64_t *)W.sel.p;
+            launch_select(dprobs, a.tiles, ntiles, a.tile_min, prec, ubits, sel, dcnt + C_SEL, sel + ntiles, st);
             ScreenArgs b = a;
-            b.tiles = (const uint64_t *)W.sel.p;
+            b.tiles = sel;
             b.sel_count = dcnt + C_SEL;
+            b.sel_dense = sel + ntiles;
             b.U = (const double *)ubits;
             launch_screen(prec, tile, M_EMIT, true, b,
                           std::min<int64_t>(std::max<int64_t>(ntiles, 1), tile == 256 ? c->ncu : 2048), st);
@@ -1579,6 +1582,8 @@ int cpmi_strings_lightbulb(cpmi_ctx *c, const int8_t *strings, int64_t n, int64_
     if (sigma < 2 || sigma > 64) return fail(c, CPMI_ERR_ARG, "sigma must be in 2..64");
     if (k < 1 || ld < k || n < 0) return fail(c, CPMI_ERR_ARG, "bad shape n=%lld k=%lld ld=%lld", (long long)n, (long long)k, (long long)ld);
     if (n >= (1ll << 21) - 1) return fail(c, CPMI_ERR_ARG, "n must be below 2^21 - 1");
+    // the best pair is packed as count << 42 | pair, the count (at most k) in 22 bits
+    if (k >= (1ll << 22)) return fail(c, CPMI_ERR_ARG, "k must be below 2^22");
     if (iterations < 1) return fail(c, CPMI_ERR_ARG, "iterations must be >= 1");
     if (cap < 1 || cap > (1ll << 30)) return fail(c, CPMI_ERR_ARG, "cap must be in 1..2^30");
     int bits_per = 1;
@@ -1892,6 +1897,25 @@ int cpmi_dbg_copy(void *dst, const void *src, int64_t bytes, void *stream)
     if (hipGetLastError() != hipSuccess) return CPMI_ERR_HIP;
     if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return CPMI_ERR_HIP;
     return CPMI_OK;
+}
+
+int64_t cpmi_dbg_pruned_tiles(int64_t n, int tile, int q, const double *lo, const double *hi, double T, int64_t band,
+                              uint64_t *out, int64_t cap, int64_t *nfull, int64_t *npruned)
+{
+    if (n < 2 || (tile != 128 && tile != 256) || q < 1 || q > 32 || !lo || !hi || cap < 0 || (cap > 0 && !out))
+        return CPMI_ERR_ARG;
+    const int64_t nT = (n + tile - 1) / tile;
+    HostProb h;
+    h.n = n;
+    h.excl = 1;
+    std::vector<double> vlo(lo, lo + nT * q), vhi(hi, hi + nT * q);
+    std::vector<uint64_t> tl;
+    int64_t nf = 0, np = 0;
+    pruned_tiles(h, tile, q, vlo, vhi, T, band, tl, nf, np);
+    for (int64_t k = 0; k < (int64_t)tl.size() && k < cap; ++k) out[k] = tl[(size_t)k];
+    if (nfull) *nfull = nf;
+    if (npruned) *npruned = np;
+    return (int64_t)tl.size();
 }
 
 double cpmi_dbg_tile_lb(const double *loI, const double *hiI, const double *loJ, const double *hiJ, int q)

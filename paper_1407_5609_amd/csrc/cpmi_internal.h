@@ -91,8 +91,12 @@ typedef unsigned long long u64c;   // 64-bit device counter (atomicAdd operand)
 struct ScreenArgs {
     const Prob *probs;
     const uint64_t *tiles;     // tile list
-    int64_t ntiles;            // entries (pass 1); pass 2 reads *sel_count
+    int64_t ntiles;            // entries (pass 1); pass 2: entries of sel_dense
     const u64c *sel_count;     // pass 2: number of valid entries of `tiles` (below 2^31)
+    // pass 2: the selected tiles in list order (TILE_NONE elsewhere, ntiles
+    // entries), walked instead of `tiles` when more than a quarter of the
+    // list is selected (it keeps the list's panel locality); or null
+    const uint64_t *sel_dense;
     uint32_t *tile_min;        // pass 1: per entry, four words: each wave's min screen value (float or int32 bits)
     const double *U;           // pass 2: per problem closest-pair upper bound, or null (no pair search)
     Cand *candR;               // radius candidates
@@ -209,7 +213,7 @@ void launch_screen(int prec, int tile, int mode, bool masked, const ScreenArgs &
 void launch_reduce_U(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min, int prec,
                      unsigned long long *Ubits, hipStream_t st);
 void launch_select(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min, int prec,
-                   const unsigned long long *Ubits, uint64_t *sel, u64c *sel_count, hipStream_t st);
+                   const unsigned long long *Ubits, uint64_t *sel, u64c *sel_count, uint64_t *dense, hipStream_t st);
 
 // Candidate verification in canonical FP64 (exact int64 for int8).
 void launch_verify_cpp(const Prob *probs, const Cand *cand, const u64c *cnt, uint64_t cap, int prec, int tile,

@@ -97,10 +97,12 @@ __global__ __launch_bounds__(NTHREADS) void screen_kernel(ScreenArgs args)
     const int wm = wave >> 1, wn = wave & 1;
     const int lrow = lane & 31, lhalf = lane >> 5;
 
-    const int64_t count = (MODE & M_EMIT) ? (int64_t)*args.sel_count : args.ntiles;
+    const bool dense = (MODE & M_EMIT) && args.sel_dense && (int64_t)*args.sel_count * 4 > args.ntiles;
+    const int64_t count = (MODE & M_EMIT) && !dense ? (int64_t)*args.sel_count : args.ntiles;
+    const uint64_t *list = dense ? args.sel_dense : args.tiles;
 
     for (int64_t t = blockIdx.x; t < count; t += gridDim.x) {
-        const uint64_t ent = args.tiles[t];
+        const uint64_t ent = list[t];
         if (ent == TILE_NONE) continue;
         const uint32_t p = tile_prob(ent);
         const int64_t I = tile_I(ent), J = tile_J(ent);

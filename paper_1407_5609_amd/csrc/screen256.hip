@@ -350,10 +350,12 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
 
     // 32-bit tile indices (the host keeps lists below 2^31 entries), so that
     // the loop bookkeeping stays in scalar registers and scalar compares
-    const int32_t count = (MODE & M_EMIT) ? (int32_t)*args.sel_count : (int32_t)args.ntiles;
+    const bool dense = (MODE & M_EMIT) && args.sel_dense && (int64_t)*args.sel_count * 4 > args.ntiles;
+    const int32_t count =
+        (MODE & M_EMIT) && !dense ? (int32_t)*args.sel_count : (int32_t)args.ntiles;
     const int32_t stride = (int32_t)gridDim.x;
 
-    c_u64 *tiles = (c_u64 *)args.tiles;
+    c_u64 *tiles = (c_u64 *)(dense ? args.sel_dense : args.tiles);
     auto next_valid = [&](int32_t t) -> int32_t {
         while (t < count && tiles[t] == TILE_NONE) t += stride;
         return t;
@@ -396,6 +398,38 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                                                  (lds_void *)(od + T256 + wave * 64), 4, 0, 0);
             }
         }
+    };
+
+    // Pass 2's radius candidates: each wave takes output slots in slabs of
+    // SLAB (one atomic add per slab, not one per emission: at volume the
+    // candidates number millions and the counter is one word); the unused
+    // end of a slab is marked empty (problem index ~0) for the verifier.
+    constexpr uint32_t SLAB = 256;
+    uint64_t slab = 0;        // first slot of the wave's slab (wave-uniform)
+    uint32_t slab_used = SLAB;
+    uint32_t nIn = 0;         // pairs proved inside the radius by their screen value (counting form)
+    auto close_slab = [&]() {
+        // entries [slab_used, SLAB) of the current slab: empty
+        const uint32_t l = (uint32_t)fresh_lane();
+        for (uint32_t k = slab_used + l; k < SLAB; k += 64)
+            if (slab + k < args.capR) args.candR[slab + k] = Cand{0, 0, 0.0f, 0xffffffffu};
+    };
+    auto emit_r = [&](bool pred, const Cand &cd) {
+        const uint64_t m = __ballot(pred);
+        if (m == 0) return;
+        const uint32_t n = (uint32_t)__popcll(m);
+        if (slab_used + n > SLAB) {
+            if (slab_used < SLAB) close_slab();
+            u64c base = 0;
+            if (fresh_lane() == 0) base = atomicAdd(args.cntR, (u64c)SLAB);
+            slab = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32) |
+                   (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base);
+            slab_used = 0;
+        }
+        const uint32_t rank =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (pred && slab + slab_used + rank < args.capR) args.candR[slab + slab_used + rank] = cd;
+        slab_used += n;
     };
 
     int32_t t = next_valid((int32_t)blockIdx.x);
@@ -602,115 +636,118 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
             }
         };
         S best = SINF;
-        if (full) {
-            if constexpr (FOLD) {
-                // min of -2 acc = -2 max acc, one accumulator block at a
-                // time: the opaque step closes each block's maximum, so the
-                // compiler does not build one tree over (and copy out of the
-                // accumulator registers) all 256 values at once
-                S mx = -SINF;
-#pragma unroll
-                for (int a = 0; a < MB256; ++a) {
-                    S ma = -SINF;
-#pragma unroll
-                    for (int r = 0; r < 16; ++r)
-#pragma unroll
-                        for (int b = 0; b < MB256; ++b) ma = fmaxf(ma, acc[a][b][r]);
-                    asm volatile("" : "+v"(ma));
-                    mx = fmaxf(mx, ma);
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-                best = -2.0f * mx;
-            } else {
-#pragma unroll
-                for (int a = 0; a < MB256; ++a) {
-                    S si[16];
-                    load_si(a, si);
-#pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        S m0 = part(acc[a][0][r], sj[0]);
-#pragma unroll
-                        for (int b = 1; b < MB256; ++b) m0 = smin(m0, part(acc[a][b][r], sj[b]));
-                        best = smin(best, (S)(si[r] + m0));
+        // pass 1: the wave's minimum over its admissible elements
+        if constexpr (MODE & M_MIN) {
+            if (full) {
+                if constexpr (FOLD) {
+                    // min of -2 acc = -2 max acc, one accumulator block at a
+                    // time: the opaque step closes each block's maximum, so the
+                    // compiler does not build one tree over (and copy out of the
+                    // accumulator registers) all 256 values at once
+                    S mx = -SINF;
+    #pragma unroll
+                    for (int a = 0; a < MB256; ++a) {
+                        S ma = -SINF;
+    #pragma unroll
+                        for (int r = 0; r < 16; ++r)
+    #pragma unroll
+                            for (int b = 0; b < MB256; ++b) ma = fmaxf(ma, acc[a][b][r]);
+                        asm volatile("" : "+v"(ma));
+                        mx = fmaxf(mx, ma);
+                        __builtin_amdgcn_sched_barrier(0);
                     }
-                    // one accumulator block at a time keeps the epilogue's registers few
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-            }
-        } else if constexpr (MASKED) {
-            if constexpr (FOLD) {
-                // max of acc over the admissible elements, one accumulator
-                // block at a time (as above), every test a select. Three
-                // forms, chosen per tile: rows in position order; rows in
-                // reference order off the diagonal and the ragged edge
-                // (positions alone decide); and the rest.
-                const int form = !pexcl ? 0 : ((I != J) && ((int64_t)J * T256 + T256 <= P.n)) ? 1 : 2;
-                S mx = -SINF;
-#pragma unroll
-                for (int a = 0; a < MB256; ++a) {
-                    int32_t oi[16] = {};
-                    if (form != 0) load_oi(a, oi);
-                    S ma = -SINF;
-                    // (a scheduling fence per row, and a row position the
-                    // compiler cannot share between the forms, keep the tests
-                    // next to their use: hoisted, they outgrow the free
-                    // registers)
-                    if (form == 1) {
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            int32_t o = oi[r];
-                            asm volatile("" : "+v"(o));
-#pragma unroll
-                            for (int b = 0; b < MB256; ++b)
-                                ma = fmaxf(ma, far_apart(o, oj[b]) ? acc[a][b][r] : -SINF);
-                            __builtin_amdgcn_sched_barrier(0);
-                        }
-                    } else if (form == 0) {
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
-#pragma unroll
-                            for (int b = 0; b < MB256; ++b)
-                                ma = fmaxf(ma, adm_pos(gi, j0 + b * 32 + lrow) ? acc[a][b][r] : -SINF);
-                            __builtin_amdgcn_sched_barrier(0);
-                        }
-                    } else {
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
-#pragma unroll
-                            for (int b = 0; b < MB256; ++b)
-                                ma = fmaxf(ma, adm_ref(gi, j0 + b * 32 + lrow, oi[r], oj[b]) ? acc[a][b][r] : -SINF);
-                            __builtin_amdgcn_sched_barrier(0);
-                        }
-                    }
-                    asm volatile("" : "+v"(ma));
-                    mx = fmaxf(mx, ma);
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-                best = -2.0f * mx;
-            } else {
-                // (one loop per admissibility rule: the rule is uniform per tile)
-                auto masked_min = [&](auto adm) {
-#pragma unroll
+                    best = -2.0f * mx;
+                } else {
+    #pragma unroll
                     for (int a = 0; a < MB256; ++a) {
                         S si[16];
                         load_si(a, si);
-#pragma unroll
+    #pragma unroll
                         for (int r = 0; r < 16; ++r) {
-                            const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
-#pragma unroll
-                            for (int b = 0; b < MB256; ++b) {
-                                const int32_t gj = j0 + b * 32 + lrow;
-                                const S dv = (S)(si[r] + part(acc[a][b][r], sj[b]));
-                                best = adm(gi, gj) ? smin(best, dv) : best;
-                            }
+                            S m0 = part(acc[a][0][r], sj[0]);
+    #pragma unroll
+                            for (int b = 1; b < MB256; ++b) m0 = smin(m0, part(acc[a][b][r], sj[b]));
+                            best = smin(best, (S)(si[r] + m0));
                         }
+                        // one accumulator block at a time keeps the epilogue's registers few
                         __builtin_amdgcn_sched_barrier(0);
                     }
-                };
-                if (twoset) masked_min(adm_two);
-                else masked_min(adm_pos);
+                }
+            } else if constexpr (MASKED) {
+                if constexpr (FOLD) {
+                    // max of acc over the admissible elements, one accumulator
+                    // block at a time (as above), every test a select. Three
+                    // forms, chosen per tile: rows in position order; rows in
+                    // reference order off the diagonal and the ragged edge
+                    // (positions alone decide); and the rest.
+                    const int form = !pexcl ? 0 : ((I != J) && ((int64_t)J * T256 + T256 <= P.n)) ? 1 : 2;
+                    S mx = -SINF;
+    #pragma unroll
+                    for (int a = 0; a < MB256; ++a) {
+                        int32_t oi[16] = {};
+                        if (form != 0) load_oi(a, oi);
+                        S ma = -SINF;
+                        // (a scheduling fence per row, and a row position the
+                        // compiler cannot share between the forms, keep the tests
+                        // next to their use: hoisted, they outgrow the free
+                        // registers)
+                        if (form == 1) {
+    #pragma unroll
+                            for (int r = 0; r < 16; ++r) {
+                                int32_t o = oi[r];
+                                asm volatile("" : "+v"(o));
+    #pragma unroll
+                                for (int b = 0; b < MB256; ++b)
+                                    ma = fmaxf(ma, far_apart(o, oj[b]) ? acc[a][b][r] : -SINF);
+                                __builtin_amdgcn_sched_barrier(0);
+                            }
+                        } else if (form == 0) {
+    #pragma unroll
+                            for (int r = 0; r < 16; ++r) {
+                                const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
+    #pragma unroll
+                                for (int b = 0; b < MB256; ++b)
+                                    ma = fmaxf(ma, adm_pos(gi, j0 + b * 32 + lrow) ? acc[a][b][r] : -SINF);
+                                __builtin_amdgcn_sched_barrier(0);
+                            }
+                        } else {
+    #pragma unroll
+                            for (int r = 0; r < 16; ++r) {
+                                const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
+    #pragma unroll
+                                for (int b = 0; b < MB256; ++b)
+                                    ma = fmaxf(ma, adm_ref(gi, j0 + b * 32 + lrow, oi[r], oj[b]) ? acc[a][b][r] : -SINF);
+                                __builtin_amdgcn_sched_barrier(0);
+                            }
+                        }
+                        asm volatile("" : "+v"(ma));
+                        mx = fmaxf(mx, ma);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    best = -2.0f * mx;
+                } else {
+                    // (one loop per admissibility rule: the rule is uniform per tile)
+                    auto masked_min = [&](auto adm) {
+    #pragma unroll
+                        for (int a = 0; a < MB256; ++a) {
+                            S si[16];
+                            load_si(a, si);
+    #pragma unroll
+                            for (int r = 0; r < 16; ++r) {
+                                const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
+    #pragma unroll
+                                for (int b = 0; b < MB256; ++b) {
+                                    const int32_t gj = j0 + b * 32 + lrow;
+                                    const S dv = (S)(si[r] + part(acc[a][b][r], sj[b]));
+                                    best = adm(gi, gj) ? smin(best, dv) : best;
+                                }
+                            }
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+                    };
+                    if (twoset) masked_min(adm_two);
+                    else masked_min(adm_pos);
+                }
             }
         }
 
@@ -752,59 +789,76 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                 }
             }
             const S thr = thrU > thrR ? thrU : thrR;
-            if (wmin(best) <= thr) {
-                // every element of this lane: (row, column, screen value, admissible)
-                auto each = [&](auto f) {
-#pragma clang loop unroll(full)
-                    for (int a = 0; a < MB256; ++a) {
-                        int32_t oi[16] = {};
-                        if (pexcl) load_oi(a, oi);
+            // Each element within the threshold in some lane is classified
+            // and emitted with one atomic add per wave and counter (ballot,
+            // then slots by rank; radius candidates in slabs, above).
+            auto emit = [&](bool pred, Cand *cand, u64c *cnt, uint64_t cap, const Cand &cd) {
+                const uint64_t m = __ballot(pred);
+                if (m != 0) {
+                    u64c base = 0;
+                    if (fresh_lane() == 0) base = atomicAdd(cnt, (u64c)__popcll(m));
+                    base = ((u64c)(uint32_t)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32) |
+                           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base);
+                    const uint32_t rank =
+                        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    if (pred && base + rank < cap) cand[base + rank] = cd;
+                }
+            };
+            // The blocks one after another in a loop that is not unrolled
+            // (its accumulators picked by a switch): unrolled over all 256
+            // elements, the emission outgrows the instruction cache and the
+            // pass runs many times slower than the screen itself.
+#pragma unroll 1
+            for (int blk = 0; blk < MB256 * MB256; ++blk) {
+                const int a = blk / MB256, b = blk % MB256;
+                AccT v;
+                switch (blk) {
+#define CPMI_ACC_CASE(k) \
+    case k: v = acc[(k) / MB256][(k) % MB256]; break;
+                    CPMI_ACC_CASE(0) CPMI_ACC_CASE(1) CPMI_ACC_CASE(2) CPMI_ACC_CASE(3)
+                    CPMI_ACC_CASE(4) CPMI_ACC_CASE(5) CPMI_ACC_CASE(6) CPMI_ACC_CASE(7)
+                    CPMI_ACC_CASE(8) CPMI_ACC_CASE(9) CPMI_ACC_CASE(10) CPMI_ACC_CASE(11)
+                    CPMI_ACC_CASE(12) CPMI_ACC_CASE(13) CPMI_ACC_CASE(14) default: v = acc[3][3]; break;
+#undef CPMI_ACC_CASE
+                }
+                // this lane's rows of block a and column of block b
+                const int32_t ib = i0 + a * 32 + 4 * lhalf, gj = j0 + b * 32 + lrow;
+                S sjb = 0;
+                int32_t ojb = 0;
+                if constexpr (!FOLD) sjb = sh_t[T256 + gj - (int32_t)(J * T256)];
+                if (pexcl) ojb = sh_ot[T256 + gj - (int32_t)(J * T256)];
+                S dv[16];
+                bool near_any = false;
 #pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
-                            S si = 0;
-                            if constexpr (!FOLD) si = sh_t[gi - (int32_t)(I * T256)];
-#pragma unroll
-                            for (int b = 0; b < MB256; ++b) {
-                                const int32_t gj = j0 + b * 32 + lrow;
-                                S dv;
-                                if constexpr (FOLD) dv = -2.0f * acc[a][b][r];
-                                else dv = (S)(si + part(acc[a][b][r], sj[b]));
-                                const bool ok = full | (pexcl    ? adm_ref(gi, gj, oi[r], oj[b])
-                                                        : twoset ? adm_two(gi, gj)
-                                                                 : adm_pos(gi, gj));
-                                f(gi, gj, dv, ok);
-                            }
-                        }
+                for (int r = 0; r < 16; ++r) {
+                    if constexpr (FOLD) {
+                        dv[r] = -2.0f * v[r];
+                    } else {
+                        const int32_t gi = ib + 8 * (r >> 2) + (r & 3);
+                        dv[r] = (S)(sh_t[gi - (int32_t)(I * T256)] + part(v[r], sjb));
                     }
-                };
-                // count this lane's pairs, reserve them with one atomic per
-                // wave and counter, then write them
-                uint32_t nU = 0, nR = 0, nIn = 0;
-                each([&](int32_t, int32_t, S dv, bool ok) {
-                    nU += ok & (dv <= thrU);
-                    const bool in = ok & (dv <= thrIn);
-                    nIn += in;
-                    nR += ok & !in & (dv <= thrR);
-                });
-                if (args.cntIn) wave_count(args.cntIn, nIn);
-                uint64_t kU = wave_reserve(args.cntU, nU), kR = wave_reserve(args.cntR, nR);
-                if (__any(nU + nR != 0)) {
-                    each([&](int32_t gi, int32_t gj, S dv, bool ok) {
+                    near_any |= dv[r] <= thr;
+                }
+                if (!__any(near_any)) continue;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    if (__any(dv[r] <= thr)) {
+                        const int32_t gi = ib + 8 * (r >> 2) + (r & 3);
+                        int32_t oir = 0;
+                        if (pexcl) oir = sh_ot[gi - (int32_t)(I * T256)];
+                        const bool ok = full | (pexcl    ? adm_ref(gi, gj, oir, ojb)
+                                                : twoset ? adm_two(gi, gj)
+                                                         : adm_pos(gi, gj));
                         Cand cd;
                         cd.i = gi;
                         cd.j = gj;
-                        cd.dt = (float)dv;
+                        cd.dt = (float)dv[r];
                         cd.p = p;
-                        if (ok & (dv <= thrU)) {
-                            if (kU < args.capU) args.candU[kU] = cd;
-                            ++kU;
-                        }
-                        if (ok & !(dv <= thrIn) & (dv <= thrR)) {
-                            if (kR < args.capR) args.candR[kR] = cd;
-                            ++kR;
-                        }
-                    });
+                        const bool in = ok & (dv[r] <= thrIn);
+                        nIn += in;
+                        emit(ok & (dv[r] <= thrU), args.candU, args.cntU, args.capU, cd);
+                        emit_r(ok & !in & (dv[r] <= thrR), cd);
+                    }
                 }
             }
         }
@@ -823,6 +877,10 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
             __builtin_amdgcn_s_barrier();
         }
         t = tn;
+    }
+    if constexpr (MODE & M_EMIT) {
+        if (slab_used < SLAB) close_slab();
+        if (args.cntIn) wave_count(args.cntIn, nIn);
     }
     // the load cursor keeps loads in flight past the last tile: let them land
     // before the work-group (and its LDS) is released

@@ -97,12 +97,17 @@ __global__ void reduce_U_kernel(const Prob *probs, const uint64_t *tiles, int64_
     if (lane == 0 && cur_p != 0xffffffffu && cur != ~0ull) atomicMin(&Ubits[cur_p], cur);
 }
 
+// The selected tiles twice: appended to sel (any order), and in place of the
+// list in dense (list order, TILE_NONE elsewhere), which keeps the list's
+// locality when many tiles are selected.
 __global__ void select_kernel(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min,
-                              int prec, const unsigned long long *Ubits, uint64_t *sel, u64c *sel_count)
+                              int prec, const unsigned long long *Ubits, uint64_t *sel, u64c *sel_count,
+                              uint64_t *dense)
 {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntiles;
          t += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t e = tiles[t];
+        dense[t] = TILE_NONE;
         if (e == TILE_NONE) continue;
         const uint32_t p = tile_prob(e);
         const Prob &P = probs[p];
@@ -117,6 +122,7 @@ __global__ void select_kernel(const Prob *probs, const uint64_t *tiles, int64_t 
         if (want) {
             const u64c k = atomicAdd(sel_count, 1ull);
             sel[k] = e;
+            dense[t] = e;
         }
     }
 }
@@ -139,10 +145,10 @@ void launch_reduce_U(const Prob *probs, const uint64_t *tiles, int64_t ntiles, c
 }
 
 void launch_select(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min, int prec,
-                   const unsigned long long *Ubits, uint64_t *sel, u64c *sel_count, hipStream_t st)
+                   const unsigned long long *Ubits, uint64_t *sel, u64c *sel_count, uint64_t *dense, hipStream_t st)
 {
     hipLaunchKernelGGL(select_kernel, dim3(grid_of(ntiles)), dim3(256), 0, st, probs, tiles, ntiles, tile_min, prec,
-                       Ubits, sel, sel_count);
+                       Ubits, sel, sel_count, dense);
 }
 
 // ---------------------------------------------------------------------------
@@ -210,16 +216,6 @@ __device__ double canonical_d2(const Prob &P, int64_t i, int64_t j, int lane)
     return acc;
 }
 
-__device__ __forceinline__ void record_error(ResDev *r, double dt, double d2, double E)
-{
-    const double err = fabs(dt - d2);
-    atomicMax(&r->err_bits, __float_as_uint(f32_up(err)));
-    if (E > 0.0) {
-        atomicMax(&r->ratio_bits, __float_as_uint(f32_up(err / E)));
-        atomicMax(&r->bound_bits, __float_as_uint(f32_up(E)));
-    }
-}
-
 // Source rows (a < b) of a candidate, whose screen rows may be permuted.
 __device__ __forceinline__ void cand_rows(const Prob &P, const Cand &cd, int64_t &a, int64_t &b)
 {
@@ -228,13 +224,48 @@ __device__ __forceinline__ void cand_rows(const Prob &P, const Cand &cd, int64_t
     b = x < y ? y : x;
 }
 
-// One wave per candidate (4 per work-group).
+// Screening-error maxima of the candidates a wave verified, merged into the
+// problem's result with one set of atomics per run of one problem (lane 0).
+struct ErrAcc {
+    uint32_t p = 0xffffffffu;
+    float err = 0.f, ratio = 0.f, bound = 0.f;
+    __device__ void flush(ResDev *res)
+    {
+        if (p == 0xffffffffu) return;
+        atomicMax(&res[p].err_bits, __float_as_uint(err));
+        if (bound > 0.f) {
+            atomicMax(&res[p].ratio_bits, __float_as_uint(ratio));
+            atomicMax(&res[p].bound_bits, __float_as_uint(bound));
+        }
+    }
+    __device__ void add(ResDev *res, uint32_t q, double dt, double d2, double E)
+    {
+        if (q != p) {
+            flush(res);
+            p = q;
+            err = ratio = bound = 0.f;
+        }
+        const double e = fabs(dt - d2);
+        err = fmaxf(err, f32_up(e));
+        if (E > 0.0) {
+            ratio = fmaxf(ratio, f32_up(e / E));
+            bound = fmaxf(bound, f32_up(E));
+        }
+    }
+};
+
+// One wave per candidate (4 per work-group); each wave keeps the least d2
+// and the error maxima of the run of candidates of one problem it verified
+// and merges them with one set of atomics per run.
 __global__ __launch_bounds__(256) void verify_cpp_kernel(const Prob *probs, const Cand *cand, const u64c *cnt,
                                                          uint64_t cap, int prec, int tile, double *cand_d2,
                                                          ResDev *res)
 {
     const int64_t m = min((int64_t)*cnt, (int64_t)cap);
     const int lane = threadIdx.x & 63;
+    ErrAcc ea;
+    uint32_t bp = 0xffffffffu;
+    unsigned long long bbits = ~0ull;
     for (int64_t c = blockIdx.x * 4 + (threadIdx.x >> 6); c < m; c += (int64_t)gridDim.x * 4) {
         const Cand cd = cand[c];
         const Prob &P = probs[cd.p];
@@ -243,9 +274,19 @@ __global__ __launch_bounds__(256) void verify_cpp_kernel(const Prob *probs, cons
         const double d2 = canonical_d2(P, a, b, lane);
         if (lane == 0) {
             cand_d2[c] = d2;
-            atomicMin(&res[cd.p].best_d2, (unsigned long long)__double_as_longlong(d2));
-            record_error(&res[cd.p], (double)cd.dt, d2, tile_bound_of(P, cd.i / tile, cd.j / tile, prec));
+            if (cd.p != bp) {
+                if (bp != 0xffffffffu) atomicMin(&res[bp].best_d2, bbits);
+                bp = cd.p;
+                bbits = ~0ull;
+            }
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(d2);
+            bbits = bits < bbits ? bits : bbits;   // d2 >= 0: the bits order as the values
+            ea.add(res, cd.p, (double)cd.dt, d2, tile_bound_of(P, cd.i / tile, cd.j / tile, prec));
         }
+    }
+    if (lane == 0) {
+        if (bp != 0xffffffffu) atomicMin(&res[bp].best_d2, bbits);
+        ea.flush(res);
     }
 }
 
@@ -263,6 +304,61 @@ __global__ void pick_cpp_kernel(const Prob *probs, const Cand *cand, const u64c 
     }
 }
 
+// The canonical d2 of rows i and j computed by one lane alone: the same
+// terms in the same ascending order as canonical_d2, with no broadcasts
+// (each lane of a wave runs its own candidate).
+__device__ double canonical_d2_lane(const Prob &P, int64_t i, int64_t j)
+{
+    const int64_t d = P.d;
+    if (P.src_i8) {
+        const signed char *x = (const signed char *)P.src + i * P.ld;
+        const signed char *y = (const signed char *)P.src + j * P.ld;
+        long long acc = 0;
+        for (int64_t k = 0; k < d; ++k) {
+            const long long t = (long long)x[k] - (long long)y[k];
+            acc += t * t;
+        }
+        return (double)acc;
+    }
+    const float *T = (const float *)P.src;
+    double acc = 0.0;
+    if (P.motif) {
+        const float *x = T + i, *y = T + j;
+        const double mi = P.mu[i], si = P.sigma[i], mj = P.mu[j], sj = P.sigma[j];
+        for (int64_t k = 0; k < d; ++k) {
+            const double t = ((double)x[k] - mi) / si - ((double)y[k] - mj) / sj;
+            acc = fma(t, t, acc);
+        }
+        return acc;
+    }
+    const float *x = T + i * P.ld, *y = T + j * P.ld;
+    int64_t k = 0;
+    if ((((uintptr_t)x | (uintptr_t)y) & 15) == 0) {
+        // 16-byte loads, the terms still taken one at a time in order
+        for (; k + 4 <= d; k += 4) {
+            const float4 u = *(const float4 *)(x + k), w = *(const float4 *)(y + k);
+            double t = (double)u.x - (double)w.x;
+            acc = fma(t, t, acc);
+            t = (double)u.y - (double)w.y;
+            acc = fma(t, t, acc);
+            t = (double)u.z - (double)w.z;
+            acc = fma(t, t, acc);
+            t = (double)u.w - (double)w.w;
+            acc = fma(t, t, acc);
+        }
+    }
+    for (; k < d; ++k) {
+        const double t = (double)x[k] - (double)y[k];
+        acc = fma(t, t, acc);
+    }
+    return acc;
+}
+
+// One lane per candidate: at volume (millions of candidates) 64 chains in
+// flight per wave hide the FP64 latency that one chain per wave exposes. The
+// pairs within the radius get their output slots with one atomic add per
+// wave step, and the error maxima are merged with one set of atomics per
+// wave (all lanes of one problem) or per lane.
 __global__ __launch_bounds__(256) void verify_frnn_kernel(const Prob *probs, const Cand *cand, const u64c *cnt,
                                                           uint64_t cap, int prec, int tile, uint64_t *keys,
                                                           double *vals, u64c *out_cnt, uint64_t out_cap,
@@ -270,23 +366,51 @@ __global__ __launch_bounds__(256) void verify_frnn_kernel(const Prob *probs, con
 {
     const int64_t m = min((int64_t)*cnt, (int64_t)cap);
     const int lane = threadIdx.x & 63;
-    for (int64_t c = blockIdx.x * 4 + (threadIdx.x >> 6); c < m; c += (int64_t)gridDim.x * 4) {
-        const Cand cd = cand[c];
-        const Prob &P = probs[cd.p];
-        int64_t a, b;
-        cand_rows(P, cd, a, b);
-        const double d2 = canonical_d2(P, a, b, lane);
-        if (lane == 0) {
-            // the bound is indexed by screen-row blocks
-            record_error(&res[cd.p], (double)cd.dt, d2, tile_bound_of(P, cd.i / tile, cd.j / tile, prec));
-            if (d2 <= P.r2) {
-                const u64c k = atomicAdd(out_cnt, 1ull);
-                if (k < out_cap) {
-                    keys[k] = ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
-                    vals[k] = d2;
-                }
+    const int64_t wid = blockIdx.x * 4 + (threadIdx.x >> 6), nw = (int64_t)gridDim.x * 4;
+    ErrAcc ea;
+    for (int64_t base = wid * 64; base < m; base += nw * 64) {
+        const int64_t c = base + lane;
+        uint64_t key = 0;
+        double d2 = 0.0;
+        uint32_t in = 0;
+        if (c < m) {
+            const Cand cd = cand[c];
+            if (cd.p != 0xffffffffu) {   // not an unused slot of a screen wave's slab
+                const Prob &P = probs[cd.p];
+                int64_t a, b;
+                cand_rows(P, cd, a, b);
+                d2 = canonical_d2_lane(P, a, b);
+                // the bound is indexed by screen-row blocks
+                ea.add(res, cd.p, (double)cd.dt, d2, tile_bound_of(P, cd.i / tile, cd.j / tile, prec));
+                key = ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
+                in = d2 <= P.r2;
             }
         }
+        const uint64_t k = wave_reserve(out_cnt, in);
+        if (in && k < out_cap) {
+            keys[k] = key;
+            vals[k] = d2;
+        }
+    }
+    // one problem in every lane (or none): the wave's maxima, one lane merges them
+    const uint32_t p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)ea.p);
+    if (__all(ea.p == p0 || ea.p == 0xffffffffu)) {
+        float e = ea.err, r = ea.ratio, bd = ea.bound;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            e = fmaxf(e, __shfl_xor(e, o, 64));
+            r = fmaxf(r, __shfl_xor(r, o, 64));
+            bd = fmaxf(bd, __shfl_xor(bd, o, 64));
+        }
+        if (lane == 0 && p0 != 0xffffffffu) {
+            ea.p = p0;
+            ea.err = e;
+            ea.ratio = r;
+            ea.bound = bd;
+            ea.flush(res);
+        }
+    } else {
+        ea.flush(res);
     }
 }
 

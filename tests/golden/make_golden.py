@@ -5,12 +5,12 @@ Every value stored under tests/golden/ by this script comes from ``oracle``
 here touches the GPU library. Floats are stored with ``float.hex`` so that the
 comparison in the tests is exact.
 
-Usage:  python tests/golden/make_golden.py [points|motif|walk|strings|two_locus|snp|mixture|batch ...]
+Usage:  python tests/golden/make_golden.py [points|motif|walk|strings|two_locus|snp|mixture|batch|mixture_radius ...]
         (no argument: all). Threads: ORACLE_THREADS (default: all cores).
 
 Run times on 8 cores (latency-bound scalar FP64): points < 1 s, motif ~4 min,
 walk ~45 min, snp ~20 min, mixture ~1 h (one nearest-neighbour pass), batch (all 512 series,
-lane-parallel closest pair) ~30 min.
+lane-parallel closest pair) ~30 min, mixture_radius (lane-parallel radius list) ~6 min.
 """
 import json
 import math
@@ -179,8 +179,40 @@ def batch():
         "series": out, "oracle_seconds": time.time() - t})
 
 
+MIXTURE_RADIUS_R2 = 832.0
+
+
+def radius_digest(pairs, d2):
+    """SHA-256 of a radius list: the (i, j) pairs as little-endian int64, then
+    the squared distances as little-endian float64."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(pairs, dtype="<i8").tobytes())
+    h.update(np.ascontiguousarray(d2, dtype="<f8").tobytes())
+    return h.hexdigest()
+
+
+def mixture_radius():
+    """The mixture points with a radius that holds several hundred thousand
+    pairs (squared radius 832 against a typical squared distance of about
+    1,000 inside a cluster): the whole list by the oracle's lane-parallel
+    scan, stored as its length, digest and first and last pairs."""
+    c = W.cfg_mixture()
+    X = c["X"].astype(np.float64)          # exact: every float32 is a double
+    t = time.time()
+    pairs, dd = oracle.frnn(X, MIXTURE_RADIUS_R2, lanes=True)
+    head = [[int(a), int(b), _hex(v)] for (a, b), v in zip(pairs[:10], dd[:10])]
+    tail = [[int(a), int(b), _hex(v)] for (a, b), v in zip(pairs[-10:], dd[-10:])]
+    _write(c["name"] + "_radius", {
+        "workload": c["name"] + "_radius",
+        "source": "oracle.frnn(lanes=True) on workloads.cfg_mixture rows promoted to float64",
+        "R2": _hex(MIXTURE_RADIUS_R2), "count": int(len(pairs)), "sha256": radius_digest(pairs, dd),
+        "digest": "sha256 of the pairs as little-endian int64 (i, j), then the d2 as little-endian float64",
+        "head": head, "tail": tail, "oracle_seconds": time.time() - t})
+
+
 JOBS = {"points": points, "motif": motif, "walk": walk, "strings": strings, "two_locus": two_locus, "snp": snp,
-        "mixture": mixture, "batch": batch}
+        "mixture": mixture, "batch": batch, "mixture_radius": mixture_radius}
 
 if __name__ == "__main__":
     if os.environ.get("ORACLE_THREADS"):

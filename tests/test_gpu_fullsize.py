@@ -166,6 +166,38 @@ def test_two_locus_full_size_golden(ctx, torch_dev):
     assert tuple(c["pair"]) == (g["direction"]["0"]["i"], g["direction"]["0"]["j"])
 
 
+def _radius_digest(pairs, d2):
+    import hashlib
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(pairs, dtype="<i8").tobytes())
+    h.update(np.ascontiguousarray(d2, dtype="<f8").tobytes())
+    return h.hexdigest()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f32"])
+def test_mixture_radius_at_volume(ctx, torch_dev, prec):
+    """262,144 points of d = 512 with a radius that holds about 4*10^5 pairs:
+    the emitted candidates, their FP64 verification and the sorted list equal
+    the oracle's list bit for bit (length, digest, first and last pairs)."""
+    g = _golden("mixture_n262144_d512_radius.json")
+    gm = _golden("mixture_n262144_d512.json")
+    c = W.cfg_mixture()
+    t = _dev(c["X"], torch_dev)
+    R2 = float.fromhex(g["R2"])
+    best, (p, d) = ctx.points(t, R2=R2, precision=prec, cap=g["count"])
+    p, d = p.cpu().numpy(), d.cpu().numpy()
+    assert len(p) == g["count"] > 100_000
+    for (i, j, v), (a, b), x in zip(g["head"], p[:10], d[:10]):
+        assert (i, j, float.fromhex(v)) == (a, b, x)
+    for (i, j, v), (a, b), x in zip(g["tail"], p[-10:], d[-10:]):
+        assert (i, j, float.fromhex(v)) == (a, b, x)
+    assert _radius_digest(p, d) == g["sha256"]
+    assert (best.i, best.j, best.d2) == (gm["closest_pair"]["i"], gm["closest_pair"]["j"],
+                                         float.fromhex(gm["closest_pair"]["d2"]))
+    st = ctx.stats()
+    assert st.frnn_pairs == g["count"] and st.frnn_candidates >= g["count"]
+
+
 @pytest.mark.parametrize("prec", ["auto", "f32"])
 def test_batch_full_size(ctx, torch_dev, prec):
     """512 series of lengths 4,096-65,536 and windows of 64-512 in one batched

@@ -354,6 +354,50 @@ def test_error_codes(ctx, torch_dev):
     assert want > 1 and rc == cp.ERR_CAPACITY and cnt.value == want
 
 
+def test_range_nonfinite_series_and_strided_int8(ctx, torch_dev):
+    """Error paths the call contract names: a squared norm of 2^100 or more
+    (too large for the FP32 screen) gives ERR_RANGE on both float screens; a
+    NaN or an infinity inside a series gives ERR_NONFINITE from the motif
+    search (single and batched); int8 rows with a stride larger than d give
+    the oracle's exact answer."""
+    import paper_1407_5609_amd as cp
+    rng = np.random.default_rng(31)
+    X = rng.normal(size=(700, 16)).astype(np.float32)
+    X[333, 3] = np.float32(2.0 ** 51)                     # ||x||^2 = 2^102
+    for prec in ("f32", "bf16"):
+        with pytest.raises(cp.CpmiError) as e:
+            ctx.closest_pair(_dev(X, torch_dev), precision=prec)
+        assert e.value.code == cp.ERR_RANGE, prec
+    X[333, 3] = np.float32(2.0 ** 49)                     # ||x||^2 ~ 2^98: accepted
+    want = oracle.closest_pair(X)
+    best = ctx.closest_pair(_dev(X, torch_dev), precision="f32")
+    assert (best.i, best.j, best.d2) == want
+
+    T = W.random_walk(rng, 3000)
+    for bad in (np.nan, np.inf, -np.inf):
+        Tb = T.copy()
+        Tb[1717] = bad
+        with pytest.raises(cp.CpmiError) as e:
+            ctx.motif(_dev(Tb, torch_dev), 64)
+        assert e.value.code == cp.ERR_NONFINITE, bad
+        res = ctx.motif_batch([_dev(T, torch_dev), _dev(Tb, torch_dev)], [64, 64])
+        assert isinstance(res[1], cp.CpmiError) and res[1].code == cp.ERR_NONFINITE, bad
+        ob, _ = oracle.motif(T, 64)
+        assert (res[0].i, res[0].j, res[0].d2) == ob
+
+    G = rng.integers(0, 3, (1500, 200)).astype(np.int8)
+    G[1200, :150] = G[40, :150]
+    G[1200, 7] = (G[40, 7] + 1) % 3                        # d2 1 or 4 over the first 150 columns
+    view = _dev(G, torch_dev)[:, :150]                     # rows of stride 200, d = 150
+    assert view.stride(0) == 200
+    Gv = np.ascontiguousarray(G[:, :150])
+    best, (p, d) = ctx.points(view, R2=40.0, precision="i8")
+    oi, oj, od = oracle.closest_pair(Gv)
+    assert (best.i, best.j, best.d2) == (oi, oj, float(od))
+    wp, wd = oracle.frnn(Gv, 40.0)
+    assert np.array_equal(p.cpu().numpy(), wp) and np.array_equal(d.cpu().numpy(), wd.astype(np.float64))
+
+
 def test_repeat_calls_are_deterministic(ctx, torch_dev):
     c = W.cfg_points_small()
     t = _dev(c["X"], torch_dev)

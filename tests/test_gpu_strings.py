@@ -179,6 +179,12 @@ def test_lightbulb_errors(ctx, torch_dev):
     assert e.value.code == cp.ERR_CAPACITY
     r, pairs = ctx.strings_lightbulb(S, 4, "most", columns=2, cap=10000)
     assert (r.i, r.j, r.matches) == (0, 1, 8) and pairs == 100 * 99 // 2 * 16
+    # a match count of k or more than 22 bits would not fit the packed best pair
+    import torch
+    L = torch.zeros((2, 1 << 22), dtype=torch.int8, device=torch_dev)
+    with pytest.raises(cp.CpmiError) as e:
+        ctx.strings_lightbulb(L, 2, "most", columns=4)
+    assert e.value.code == cp.ERR_ARG and "2^22" in ctx.last_error()
 
 
 @pytest.mark.parametrize("mode,n,k,sigma,iterations,columns,seed", [

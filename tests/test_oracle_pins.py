@@ -668,3 +668,15 @@ def test_block_d2_is_the_pairwise_distance():
     Bi = oracle.block_d2(G, 0, 40, 0, 40)
     Gi = G.astype(np.int64)
     assert np.array_equal(Bi, ((Gi[:, None, :] - Gi[None, :, :]) ** 2).sum(-1).astype(np.float64))
+
+
+@pytest.mark.parametrize("case", range(len(_lane_cases())))
+def test_lanes_radius_list_equals_the_plain_loop(case):
+    X, excl = _lane_cases()[case]
+    if X.shape[0] < 3:
+        return
+    d2 = ssd.pdist(X, "sqeuclidean")
+    for R2 in (0.0, float(np.quantile(d2, 0.1)), float(np.quantile(d2, 0.5)), 1e300):
+        a = oracle.frnn(X, R2, excl)
+        b = oracle.frnn(X, R2, excl, lanes=True)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
