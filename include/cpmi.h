@@ -207,30 +207,39 @@ int cpmi_set_tile(cpmi_ctx *ctx, int precision, int tile);
 /* Autotuner result: the fastest precision tried and its fastest tile edge,
  * and the best device time (ms, HIP events around the whole call) of every
  * configuration tried, indexed [precision][tile 128, tile 256]; 0 where not
- * tried. */
+ * tried. For the 256 tile also the band height of the tile order chosen
+ * (block rows per band; 0 if the 128 tile won) and the times of bands 4, 8
+ * and 16, indexed [precision][band]. */
 typedef struct {
     int32_t precision;
     int32_t tile;
     double ms[4][2];
+    int32_t band;
+    int32_t reserved;
+    double band_ms[4][3];
 } cpmi_tune_result;
 
 /* Autotuner: time a closest-pair search (the screen configurations the
  * library has: tile edge 128 or 256; with CPMI_PREC_AUTO on float32 input
- * also FP32 against BF16 screening) on the caller's points, `reps` timed calls
- * after one warm-up each, and record in the context the fastest tile for each
- * precision tried and, for AUTO, the fastest precision, keyed by precision,
- * dimension bucket (next power of two >= max(d, 64)) and size bucket
- * (ceil(log2) of the row count of a point set with as many pairs). Later
- * calls on problems in the same buckets use these choices; batched motifs use
- * the bucket of their largest l and of their total pair count. Arguments as
+ * also FP32 against BF16 screening; for the 256 tile the band height of the
+ * tile order, 4, 8 or 16 block rows) on the caller's points, `reps` timed calls
+ * after one warm-up each, and record in the context the fastest tile and band
+ * for each precision tried and, for AUTO, the fastest precision, keyed by
+ * precision, dimension bucket (next power of two >= max(d, 64)) and size
+ * bucket (ceil(log2) of the row count of a point set with as many pairs).
+ * Later calls on problems in the same buckets use these choices; batched
+ * motifs use the precision and tile of the bucket of their largest l and of
+ * their total pair count, and each series the band of its own l and pair
+ * count. Arguments as
  * for cpmi_closest_pair; out: host. Errors: as cpmi_closest_pair, ERR_ARG for
  * reps outside 1..1000. */
 int cpmi_autotune(cpmi_ctx *ctx, const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, int precision,
                   void *stream, int reps, cpmi_tune_result *out);
 
 /* Write every tuned choice of the context as the JSON object that
- * cpmi_create reads ({"bf16:k512:r18": 256, "auto:k512:r18": 2, ...}; the
- * "auto" value is a CPMI_PREC_* code). The file is replaced atomically.
+ * cpmi_create reads ({"bf16:k512:r18": 256, "auto:k512:r18": 2,
+ * "band.bf16:k512:r18": 8, ...}; the "auto" value is a CPMI_PREC_* code, a
+ * "band." entry a band height). The file is replaced atomically.
  * Errors: ERR_ARG if the file cannot be written. */
 int cpmi_save_tune_cache(cpmi_ctx *ctx, const char *path);
 
@@ -241,6 +250,13 @@ int cpmi_save_tune_cache(cpmi_ctx *ctx, const char *path);
  * tile_out: host. Does not touch the GPU. */
 int cpmi_tune_lookup(cpmi_ctx *ctx, int dtype, int precision, int64_t d, double pairs, int32_t *prec_out,
                      int32_t *tile_out);
+
+/* The band height of the tile order (block rows per band of the 256-tile
+ * screen) a problem of dimension d with `pairs` admissible pairs uses at
+ * `precision` (CPMI_PREC_F32, _BF16 or _I8): tuned (or from the cache), else
+ * 8. In a batched motif call each series uses its own. band_out: host. Does
+ * not touch the GPU. */
+int cpmi_tune_lookup_band(cpmi_ctx *ctx, int precision, int64_t d, double pairs, int32_t *band_out);
 
 /* Reference-point tile pruning (MPR, Section 3: reference points projected
  * by a factor f, points ordered by their distance to the first reference,

@@ -48,7 +48,8 @@ class _CStats(C.Structure):
 
 
 class _CTune(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("tile", C.c_int32), ("ms", (C.c_double * 2) * 4)]
+    _fields_ = [("precision", C.c_int32), ("tile", C.c_int32), ("ms", (C.c_double * 2) * 4), ("band", C.c_int32),
+                ("reserved", C.c_int32), ("band_ms", (C.c_double * 3) * 4)]
 
 
 # Tuned choices measured on MI355X (written by `python -m paper_1407_5609_amd.autotune`);
@@ -81,6 +82,7 @@ def _load():
     L.cpmi_closest_pair.argtypes = [vp, vp, i32, i64, i64, i64, i32, vp, C.POINTER(_CPair)]
     L.cpmi_closest_pair_noalloc.argtypes = [vp, vp, i32, i64, i64, i64, i32, vp, C.POINTER(_CPair)]
     L.cpmi_frnn.argtypes = [vp, vp, i32, i64, i64, i64, dbl, i32, vp, vp, vp, i64, C.POINTER(i64)]
+    L.cpmi_tune_lookup_band.argtypes = [vp, i32, i64, dbl, C.POINTER(C.c_int32)]
     L.cpmi_dbg_screen_sample.argtypes = [vp, vp, i32, i64, i64, i64, i32, i32, i32, vp, i64, vp, vp, vp,
                                          C.POINTER(dbl), vp]
     L.cpmi_points.argtypes = [vp, vp, i32, i64, i64, i64, i32, dbl, vp, C.POINTER(_CPair), vp, vp, i64,
@@ -228,7 +230,15 @@ class Context:
                                        _stream_ptr(stream), int(reps), C.byref(out)))
         names = {PREC_F32: "f32", PREC_BF16: "bf16", PREC_I8: "i8"}
         ms = {f"{names[p]}/{t}": out.ms[p][k] for p in names for k, t in enumerate((128, 256)) if out.ms[p][k] > 0}
-        return {"precision": names[out.precision], "tile": out.tile, "ms": ms}
+        band_ms = {f"{names[p]}/band{b}": out.band_ms[p][k] for p in names for k, b in enumerate((4, 8, 16))
+                   if out.band_ms[p][k] > 0}
+        return {"precision": names[out.precision], "tile": out.tile, "band": out.band, "ms": ms, "band_ms": band_ms}
+
+    def tune_lookup_band(self, precision, d: int, pairs: float) -> int:
+        """Band height of the tile order a problem would use (cpmi_tune_lookup_band)."""
+        b = C.c_int32(0)
+        self._check(_lib.cpmi_tune_lookup_band(self._h, _prec(precision), int(d), float(pairs), C.byref(b)))
+        return int(b.value)
 
     def save_tune_cache(self, path: str):
         self._check(_lib.cpmi_save_tune_cache(self._h, path.encode()))

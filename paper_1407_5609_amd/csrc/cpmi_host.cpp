@@ -49,6 +49,8 @@ struct DevBuf {
     size_t cap = 0;
 };
 
+constexpr int BAND_DEFAULT = 8;   // block rows per band of the tile order, untuned
+
 // Device memory of one exact search. The context owns one set, grown on
 // demand; the allocation-free entry point carves a set out of the static
 // scratch array instead (Arena).
@@ -70,6 +72,7 @@ struct HostProb {
     int src_i8 = 0;
     double r2 = -1.0;
     const void *src = nullptr;      // points, or the series
+    int band = BAND_DEFAULT;        // block rows per band of the tile order
     int64_t len = 0;                // series length (motif)
     int32_t kpad = 0;
     int64_t npad = 0;
@@ -86,10 +89,14 @@ struct HostProb {
 // dimension falls in K bucket `kb` (next power of two >= max(d, 64)) and whose
 // size falls in row bucket `rb` (ceil(log2) of the row count, or of the row
 // count of a single problem with as many pairs for a batch), `value` is the
-// tile edge (128 or 256), or the precision for prec = 0.
+// tile edge (128 or 256), or the precision for prec = 0. Entries of kind
+// KIND_BAND hold the band height of the tile order (block rows per band) for
+// that precision and buckets.
 struct TuneEntry {
     int prec, kb, rb, value;
+    int kind = 0;
 };
+enum { KIND_TILE = 0, KIND_BAND = 1 };
 
 // 64-bit device counters: radius candidates, pair candidates, selected tiles,
 // verified radius pairs, radius pairs counted by the screen alone
@@ -107,6 +114,7 @@ struct cpmi_ctx {
     std::string err;
     cpmi_stats stats{};
     int tile_override[4] = {0, 0, 0, 0};
+    int band_override = 0;         // band height forced by the autotuner while it times one
     std::vector<TuneEntry> tuned;  // autotuner results (cache file and cpmi_autotune)
 
     Work w;  // device memory of the searches (grown on demand)
@@ -252,11 +260,11 @@ int64_t pairs_of(const HostProb &h)
 // Tuned value for (prec, kb, rb): the exact entry, else the entry of the
 // nearest row bucket with the same precision and K bucket (ties: the larger
 // bucket), else -1.
-int tuned_value(const cpmi_ctx *c, int prec, int kb, int rb)
+int tuned_value(const cpmi_ctx *c, int prec, int kb, int rb, int kind = KIND_TILE)
 {
     int best = -1, dist = 1 << 30, brb = -1;
     for (const TuneEntry &e : c->tuned) {
-        if (e.prec != prec || e.kb != kb) continue;
+        if (e.kind != kind || e.prec != prec || e.kb != kb) continue;
         const int dd = std::abs(e.rb - rb);
         if (dd < dist || (dd == dist && e.rb > brb)) {
             best = e.value;
@@ -267,14 +275,23 @@ int tuned_value(const cpmi_ctx *c, int prec, int kb, int rb)
     return best;
 }
 
-void set_tuned(cpmi_ctx *c, int prec, int kb, int rb, int value)
+void set_tuned(cpmi_ctx *c, int prec, int kb, int rb, int value, int kind = KIND_TILE)
 {
     for (TuneEntry &e : c->tuned)
-        if (e.prec == prec && e.kb == kb && e.rb == rb) {
+        if (e.kind == kind && e.prec == prec && e.kb == kb && e.rb == rb) {
             e.value = value;
             return;
         }
-    c->tuned.push_back(TuneEntry{prec, kb, rb, value});
+    c->tuned.push_back(TuneEntry{prec, kb, rb, value, kind});
+}
+
+// Band height of the tile order for one problem of dimension d with `pairs`
+// admissible pairs at precision prec: the override, the tuned choice, or 8.
+int pick_band(const cpmi_ctx *c, int prec, int64_t d, double pairs)
+{
+    if (c->band_override > 0) return c->band_override;
+    const int v = tuned_value(c, prec, kbucket(d), rbucket(pairs), KIND_BAND);
+    return v >= 1 && v <= 64 ? v : BAND_DEFAULT;
 }
 
 // Screen tile for a problem of dimension d (the largest, for a batch) and
@@ -314,15 +331,25 @@ void load_tune_cache(cpmi_ctx *c, const char *path)
         char *end = nullptr;
         const long v = strtol(s.c_str() + colon + 1, &end, 10);
         if (end == s.c_str() + colon + 1) continue;
-        char name[16] = {0};
+        char name[24] = {0};
         int kb = 0, rb = 0;
-        if (sscanf(key.c_str(), "%15[a-z0-9]:k%d:r%d", name, &kb, &rb) != 3) continue;
+        if (sscanf(key.c_str(), "%23[a-z0-9.]:k%d:r%d", name, &kb, &rb) != 3) continue;
+        int kind = KIND_TILE;
+        const char *pn = name;
+        if (!strncmp(name, "band.", 5)) {
+            kind = KIND_BAND;
+            pn = name + 5;
+        }
         int prec = -1;
         for (int p = 0; p <= 3; ++p)
-            if (!strcmp(name, tune_name(p))) prec = p;
-        if (prec < 0 || kb < 64 || rb < 0 || rb > 40) continue;
-        if (prec == 0 ? (v != P_F32 && v != P_BF16) : (v != 128 && v != 256)) continue;
-        set_tuned(c, prec, kb, rb, (int)v);
+            if (!strcmp(pn, tune_name(p))) prec = p;
+        if (prec < 0 || kb < 64 || kb > (1 << 20) || rb < 0 || rb > 40) continue;
+        if (kind == KIND_BAND) {
+            if (prec == 0 || v < 1 || v > 64) continue;
+        } else if (prec == 0 ? (v != P_F32 && v != P_BF16) : (v != 128 && v != 256)) {
+            continue;
+        }
+        set_tuned(c, prec, kb, rb, (int)v, kind);
     }
 }
 
@@ -350,10 +377,10 @@ void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t
         std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
             return hp[a].kpad > hp[b].kpad || (hp[a].kpad == hp[b].kpad && hp[a].n > hp[b].n);
         });
-    const int64_t G = 8;
     for (size_t oi = 0; oi < hp.size(); ++oi) {
         const size_t p = order[oi];
         const HostProb &h = hp[p];
+        const int64_t G = std::max(1, h.band);
         if (pairs_of(h) == 0) continue;
         const bool permuted = h.motif && h.perm;
         const int64_t nT = (h.n + tile - 1) / tile;
@@ -489,6 +516,8 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
     // ---- tile list (cached by shape)
     std::vector<int64_t> key{(int64_t)tile, np};
     for (auto &h : hp) {
+        h.band = pick_band(c, prec, h.d, (double)pairs_of(h));
+        key.push_back(h.band);
         key.push_back(h.n);
         key.push_back(h.excl);
         key.push_back(h.kpad);
@@ -1792,6 +1821,7 @@ int cpmi_autotune(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d,
     }
     const int kb = kbucket(d), rb = rbucket((double)pairs_of(n, 1));
     const int tiles[2] = {128, 256};
+    int band_of[4] = {0, 0, 0, 0};
     double best_all = 0.0;
     for (int p : precs) {
         const int saved = c->tile_override[p];
@@ -1815,6 +1845,35 @@ int cpmi_autotune(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d,
         }
         c->tile_override[p] = saved;
         set_tuned(c, p, kb, rb, best_tile);
+        if (best_tile == 256) {
+            // the band height of the tile order (block rows per band): panel
+            // reuse in L2 against the spread of the work-groups of one XCD
+            const int bands[3] = {4, 8, 16};
+            c->tile_override[p] = 256;
+            double bbest = 0.0;
+            int bb = BAND_DEFAULT;
+            for (int bi = 0; bi < 3; ++bi) {
+                c->band_override = bands[bi];
+                double tmin = 0.0;
+                for (int r = 0; r <= reps; ++r) {
+                    cpmi_pair bp;
+                    const int rc = cpmi_points(c, pts, dtype, n, d, ld, p, -1.0, stream, &bp, nullptr, nullptr, 0,
+                                               nullptr);
+                    if (rc) {
+                        c->tile_override[p] = saved;
+                        c->band_override = 0;
+                        return rc;
+                    }
+                    if (r > 0 && (tmin == 0.0 || c->stats.kernel_ms < tmin)) tmin = c->stats.kernel_ms;
+                }
+                out->band_ms[p][bi] = tmin;
+                if (bi == 0 || tmin < bbest) bbest = tmin, bb = bands[bi];
+            }
+            c->band_override = 0;
+            c->tile_override[p] = saved;
+            set_tuned(c, p, kb, rb, bb, KIND_BAND);
+            band_of[p] = bb;
+        }
         if (out->precision == 0 || best < best_all) {
             best_all = best;
             out->precision = p;
@@ -1822,6 +1881,7 @@ int cpmi_autotune(cpmi_ctx *c, const void *pts, int dtype, int64_t n, int64_t d,
         }
     }
     if (precs.size() > 1) set_tuned(c, 0, kb, rb, out->precision);
+    out->band = band_of[out->precision];
     c->err.clear();
     return CPMI_OK;
 }
@@ -1832,14 +1892,15 @@ int cpmi_save_tune_cache(cpmi_ctx *c, const char *path)
     if (!path) return fail(c, CPMI_ERR_ARG, "path is NULL");
     std::vector<TuneEntry> t = c->tuned;
     std::sort(t.begin(), t.end(), [](const TuneEntry &a, const TuneEntry &b) {
-        return std::make_tuple(a.prec, a.kb, a.rb) < std::make_tuple(b.prec, b.kb, b.rb);
+        return std::make_tuple(a.kind, a.prec, a.kb, a.rb) < std::make_tuple(b.kind, b.prec, b.kb, b.rb);
     });
     const std::string tmp = std::string(path) + ".tmp";
     FILE *f = fopen(tmp.c_str(), "w");
     if (!f) return fail(c, CPMI_ERR_ARG, "cannot write %s", tmp.c_str());
     fprintf(f, "{");
     for (size_t k = 0; k < t.size(); ++k)
-        fprintf(f, "%s\n \"%s:k%d:r%d\": %d", k ? "," : "", tune_name(t[k].prec), t[k].kb, t[k].rb, t[k].value);
+        fprintf(f, "%s\n \"%s%s:k%d:r%d\": %d", k ? "," : "", t[k].kind == KIND_BAND ? "band." : "",
+                tune_name(t[k].prec), t[k].kb, t[k].rb, t[k].value);
     fprintf(f, "\n}\n");
     const bool ok = fclose(f) == 0;
     if (!ok || rename(tmp.c_str(), path) != 0) return fail(c, CPMI_ERR_ARG, "cannot write %s", path);
@@ -1854,6 +1915,15 @@ int cpmi_tune_lookup(cpmi_ctx *c, int dtype, int precision, int64_t d, double pa
     if (p < 0) return p;
     *prec_out = p;
     *tile_out = pick_tile(c, p, d, pairs);
+    return CPMI_OK;
+}
+
+int cpmi_tune_lookup_band(cpmi_ctx *c, int precision, int64_t d, double pairs, int32_t *band_out)
+{
+    if (!c || !band_out) return CPMI_ERR_ARG;
+    if (precision != CPMI_PREC_F32 && precision != CPMI_PREC_BF16 && precision != CPMI_PREC_I8)
+        return fail(c, CPMI_ERR_ARG, "precision must be F32, BF16 or I8");
+    *band_out = pick_band(c, precision, d, pairs);
     return CPMI_OK;
 }
 

@@ -70,7 +70,7 @@ int main(int argc, char **argv)
     int32_t p = 0, tl = 0;
     snprintf(in, sizeof in, "%s/good.json", argv[1]);
     snprintf(out, sizeof out, "%s/saved.json", argv[1]);
-    CHECK(write_file(in, "{\n \"bf16:k512:r18\": 128,\n \"auto:k64:r12\": 1,\n \"i8:k4096:r17\": 256\n}\n"));
+    CHECK(write_file(in, "{\n \"bf16:k512:r18\": 128,\n \"auto:k64:r12\": 1,\n \"i8:k4096:r17\": 256,\n \"band.bf16:k512:r18\": 16,\n \"band.auto:k64:r3\": 4,\n \"band.i8:k4096:r17\": 99\n}\n"));
     CHECK(cpmi_dbg_tune(in, out, 256, CPMI_F32, CPMI_PREC_BF16, 512, 3.4e10, &p, &tl) == CPMI_OK);
     CHECK(cpmi_dbg_tune(out, NULL, 256, CPMI_F32, CPMI_PREC_AUTO, 40, 1e6, &p, &tl) == CPMI_OK);
     const char *bad[] = {"", "{", "{\"bf16:k512:r18\": }", "{\"x:y\": 3}", "{\"bf16:k99999999999999999999:r3\": 128}",

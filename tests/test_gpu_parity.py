@@ -432,11 +432,33 @@ def test_autotune_records_choices_and_answers_stay_exact(torch_dev, tmp_path):
         st = c.stats()
         assert (st.precision, st.tile) == (p, tile)
         _check_pair(best, oracle.closest_pair(X))
-        # the saved cache reproduces the choice in a new context
+        # the band height of the tile order is timed where the 256 tile wins
+        # (a larger problem), recorded per precision and saved with the rest
+        import torch
+        g = torch.Generator(device=torch_dev)
+        g.manual_seed(5)
+        Xb = torch.randn((65536, 32), generator=g, device=torch_dev)
+        rb = c.autotune(Xb, "auto", reps=1)
+        pb = 65536 * 65535 / 2
+        timed = set()
+        for pr in ("f32", "bf16"):
+            bms = {k: v for k, v in rb["band_ms"].items() if k.startswith(pr + "/")}
+            if not bms:
+                assert c.tune_lookup("f32", pr, 32, pb)[1] == 128
+                continue
+            timed.add(pr)
+            assert set(bms) == {f"{pr}/band4", f"{pr}/band8", f"{pr}/band16"} and all(v > 0 for v in bms.values())
+            fastest = int(min(bms, key=bms.get).split("band")[1])
+            assert c.tune_lookup_band(pr, 32, pb) == fastest
+        assert timed, rb
+        assert rb["band"] == (c.tune_lookup_band(rb["precision"], 32, pb) if rb["tile"] == 256 else 0)
+        # the saved cache reproduces the choices in a new context
         path = str(tmp_path / "tune.json")
         c.save_tune_cache(path)
         c2 = cp.Context(0, tune_cache=path)
         assert c2.tune_lookup("f32", "auto", 96, pairs) == (p, tile)
+        for pr in timed:
+            assert c2.tune_lookup_band(pr, 32, pb) == c.tune_lookup_band(pr, 32, pb)
         c2.close()
         # int8 tunes the INT8 screen only
         Xi = rng.integers(0, 3, (1200, 200)).astype(np.int8)
@@ -444,6 +466,41 @@ def test_autotune_records_choices_and_answers_stay_exact(torch_dev, tmp_path):
         assert ri["precision"] == "i8" and set(ri["ms"]) == {"i8/128", "i8/256"}
     finally:
         c.close()
+
+
+def test_batch_takes_each_series_band_from_the_tune_cache(torch_dev, tmp_path):
+    """Tuned band heights are per (precision, K bucket, size bucket): in one
+    batched call each series orders its tiles with the band of its own l and
+    pair count, and every answer stays the oracle's."""
+    import json
+    import paper_1407_5609_amd as cp
+    rng = np.random.default_rng(78)
+    lens, ells = [9000, 7000, 12000, 6000], [64, 512, 64, 512]
+    series = [W.random_walk(rng, L) for L in lens]
+    plants = [W.plant_motif(rng, T, e) for T, e in zip(series, ells)]
+    cache = {"auto:k64:r14": 2, "auto:k512:r14": 2, "bf16:k512:r16": 256, "bf16:k64:r16": 256}
+    for e, b in ((64, 4), (512, 16)):
+        for rb in range(8, 20):
+            cache[f"band.bf16:k{e}:r{rb}"] = b
+    path = str(tmp_path / "bands.json")
+    json.dump(cache, open(path, "w"))
+    c = cp.Context(0, tune_cache=path)
+    d = cp.Context(0, tune_cache=None)
+    try:
+        for L, e in zip(lens, ells):
+            pairs = W.valid_pairs_motif(L, e, e)
+            assert c.tune_lookup_band("bf16", e, pairs) == (4 if e == 64 else 16)
+            assert d.tune_lookup_band("bf16", e, pairs) == 8
+        ts = [_dev(T, torch_dev) for T in series]
+        got = c.motif_batch(ts, ells, precision="bf16")
+        ref = d.motif_batch(ts, ells, precision="bf16")
+        for T, e, plant, g, r in zip(series, ells, plants, got, ref):
+            ob, _ = oracle.motif(T, e)
+            assert (g.i, g.j, g.d2) == (r.i, r.j, r.d2) == ob
+            assert (g.i, g.j) == plant
+    finally:
+        c.close()
+        d.close()
 
 
 def test_calibration_copy_moves_every_byte(torch_dev):
