@@ -866,9 +866,11 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
             // each wave stores the minimum of its quarter of the tile
             best = wmin(best);
             if (fresh_lane() == 0) args.tile_min[4 * t + wave] = __builtin_bit_cast(uint32_t, best);
-            // window positions are read at uneven times across the waves and
-            // the next tile's top prefetches into the same half (masked tiles)
-            if constexpr (MASKED) __builtin_amdgcn_s_barrier();
+            // Masked tiles read window positions, and int8 tiles their row
+            // scalars, from LDS at uneven times across the waves; the next
+            // tile's top prefetches the tile after it into this same half.
+            // (Folded full tiles read nothing from LDS here.)
+            if constexpr (MASKED || !FOLD) __builtin_amdgcn_s_barrier();
         } else {
             // The emission reads this tile's row scalars and positions from
             // LDS at uneven times across the waves; the next tile's top
