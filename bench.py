@@ -411,6 +411,10 @@ def main():
     ap.add_argument("--prune", type=int, default=0,
                     help="reference-point tile pruning with this many references (point and single-series motif workloads; 0: off)")
     ap.add_argument("--prune-f", type=float, default=10.0, help="projection factor of the references")
+    ap.add_argument("--prune-order", type=int, default=0, choices=[0, 1],
+                    help="row order of pruned radius queries with two or more references: 0 = buckets of the first "
+                         "reference's distance sorted by the second's (the default), 1 = the first reference alone")
+    ap.add_argument("--prune-w", type=float, default=2.0, help="bucket width of order 0, in units of R")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (a reference launch for hardware byte counters)")
     args = ap.parse_args()
@@ -440,6 +444,7 @@ def main():
     ctx = cp.Context(0)
     if args.prune:
         ctx.set_pruning(args.prune, args.prune_f, seed=1)
+        ctx.dbg_set_prune_order(args.prune_order, args.prune_w)
 
     if args.calib_copy:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
@@ -526,7 +531,8 @@ def main():
         # the paper's measure of pruned work (Section 3.6, Tables 1-2) is the
         # pairs that reach an exact distance; here: the pairs in the tiles the
         # screen still evaluates, and the candidates verified in FP64
-        out["config"]["pruning"] = {"references": args.prune, "f": args.prune_f, "tiles_pruned": st.tiles_pruned,
+        out["config"]["pruning"] = {"references": args.prune, "f": args.prune_f, "order": args.prune_order,
+                                    "bucket_width_over_R": args.prune_w, "tiles_pruned": st.tiles_pruned,
                                     "tiles_screened": st.tiles_total,
                                     "pairs_in_screened_tiles_at_most": st.tiles_total * st.tile ** 2,
                                     "fp64_verified_pairs": st.cpp_candidates + st.frnn_candidates}

@@ -107,8 +107,8 @@ double cpmi_dbg_tile_lb(const double *loI, const double *hiI, const double *loJ,
 /* Host only: the tile list of the reference-point pruned search of one point
  * set of n rows (tile edge 128 or 256, q references): lo, hi (host, nT * q
  * doubles, nT = ceil(n / tile)) are the per-block distance intervals, block
- * I's interval for reference k at [I * q + k]; rows are in the order of
- * reference 0, so lo[I * q] is non-decreasing in I. A tile (I, J), I <= J,
+ * I's interval for reference k at [I * q + k] (any order of the blocks; the
+ * enumeration stops early where reference 0's intervals allow). A tile (I, J), I <= J,
  * is kept unless some reference's intervals, each widened by 2^-34 |hi|,
  * are more than T apart (T < 0: every tile dropped); band >= 0 keeps only
  * J - I <= band. Writes min(count, cap) entries (packed as
@@ -116,6 +116,23 @@ double cpmi_dbg_tile_lb(const double *loI, const double *hiI, const double *loJ,
  * tiles dropped to *npruned (both nullable); returns the count, or ERR_ARG. */
 int64_t cpmi_dbg_pruned_tiles(int64_t n, int tile, int q, const double *lo, const double *hi, double T, int64_t band,
                               uint64_t *out, int64_t cap, int64_t *nfull, int64_t *npruned);
+
+/* The same list built by the library's device kernels (the list the pruned
+ * searches screen): lo, hi host arrays as above, copied to the device; tiles
+ * in bands of 8 block rows; exclusion excl (1 for point sets); permuted != 0
+ * for windows in reference order (every tile partial). Entries and counts as
+ * cpmi_dbg_pruned_tiles with band = -1 (out: host). Synchronises `stream`.
+ * Returns the count, or ERR_ARG / ERR_HIP. */
+int64_t cpmi_dbg_pruned_tiles_gpu(cpmi_ctx *ctx, int64_t n, int tile, int q, const double *lo, const double *hi,
+                                  double T, int64_t excl, int permuted, uint64_t *out, int64_t cap, int64_t *nfull,
+                                  int64_t *npruned, void *stream);
+
+/* Row order of the pruned radius searches with two or more references:
+ * order 0 (default) sorts the rows by buckets of width w * R of their
+ * distance to the first reference and by their distance to the second within
+ * a bucket; order 1 by the first reference alone (as closest-pair queries
+ * always do). w > 0 (default 2). Returns CPMI_OK or ERR_ARG. */
+int cpmi_dbg_set_prune_order(cpmi_ctx *ctx, int order, double w);
 
 /* Host only: the tuning decisions of a context with `ncu` compute units
  * after reading the cache file cache_in (nullable): the precision and tile a

@@ -102,6 +102,10 @@ def _load():
     L.cpmi_dbg_mfma_peak.restype = dbl
     L.cpmi_dbg_mfma_peak.argtypes = [i32, i32, i32, C.POINTER(dbl)]
     L.cpmi_dbg_znorm.argtypes = [vp, vp, i64, i64, i32, vp, vp, vp]
+    L.cpmi_dbg_pruned_tiles_gpu.restype = i64
+    L.cpmi_dbg_pruned_tiles_gpu.argtypes = [vp, i64, i32, i32, vp, vp, dbl, i64, i32, vp, i64, C.POINTER(i64),
+                                            C.POINTER(i64), vp]
+    L.cpmi_dbg_set_prune_order.argtypes = [vp, i32, dbl]
     return L
 
 
@@ -449,6 +453,29 @@ class Context:
             tiles.ctypes.data_as(C.c_void_p), m, C.c_void_p(dump.data_ptr()), C.c_void_p(d2.data_ptr()),
             bounds.ctypes.data_as(C.c_void_p), C.byref(ratio), _stream_ptr(stream)))
         return dump, d2, bounds, float(ratio.value)
+
+    def dbg_pruned_tiles_gpu(self, n: int, tile: int, lo, hi, T: float, excl: int = 1, permuted: bool = False,
+                             stream=None):
+        """cpmi_dbg_pruned_tiles_gpu: the pruned tile list built on the device
+        from per-block intervals lo, hi (host arrays [nT, q]). Returns
+        (entries as uint64 array, full slots, tiles dropped)."""
+        import numpy as np
+        lo = np.ascontiguousarray(lo, dtype=np.float64)
+        hi = np.ascontiguousarray(hi, dtype=np.float64)
+        nT = -(-int(n) // int(tile))
+        out = np.zeros(nT * (nT + 1) // 2 + 8, dtype=np.uint64)
+        nf, npr = C.c_int64(0), C.c_int64(0)
+        cnt = _lib.cpmi_dbg_pruned_tiles_gpu(self._h, int(n), int(tile), lo.shape[1], lo.ctypes.data, hi.ctypes.data,
+                                             float(T), int(excl), int(bool(permuted)), out.ctypes.data, len(out),
+                                             C.byref(nf), C.byref(npr), _stream_ptr(stream))
+        if cnt < 0:
+            self._check(int(cnt))
+        return out[:cnt].copy(), nf.value, npr.value
+
+    def dbg_set_prune_order(self, order: int, w: float = 2.0):
+        """Row order of pruned radius searches (cpmi_dbg_set_prune_order): 0 =
+        two references (buckets of width w R), 1 = the first reference only."""
+        self._check(_lib.cpmi_dbg_set_prune_order(self._h, int(order), float(w)))
 
     def dbg_znorm(self, series, ell: int, precision="f32", stream=None):
         import torch

@@ -145,10 +145,15 @@ struct cpmi_ctx {
     double prune_f = 10.0;
     uint64_t prune_seed = 0;
     DevBuf mD, mperm, miperm, mlo, mhi, mrefs, msort;
-    // the block intervals read back (pinned; valid once evlohi has completed)
-    double *plohi = nullptr;
-    size_t plohi_cap = 0;
-    hipEvent_t evlohi = nullptr;
+    // the pruned tile list built on the device: entries, per-segment counts
+    // and their scan, scan scratch, and its four totals (device; pinned copy)
+    DevBuf mtl, mseg, mscan, mout4;
+    int64_t *plist = nullptr;
+    // row order for radius queries with q >= 2: 0 = two references (buckets of
+    // the first reference's distance, width prune_w times R, sorted by the
+    // second's), 1 = the first reference alone
+    int prune_order = 0;
+    double prune_w = 2.0;
     // string problems: encoded int8 rows and the encoder's flag word
     DevBuf mZ, mflag;
     // light-bulb bucketing: keys and rows (in, out), sort scratch, columns,
@@ -438,6 +443,13 @@ void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t
     out.insert(out.end(), part.begin(), part.end());
 }
 
+// A tile list built on the device: the entries (8 bytes each), how many, how
+// many leading slots hold full tiles, and the tiles of the timed launch.
+struct DevList {
+    const uint64_t *tiles;
+    int64_t ntiles, nfull, timed_tiles;
+};
+
 // Test of the screen bound (cpmi_dbg_screen_sample): device buffers of the
 // dumped screen values, canonical d2, per-tile bounds and the largest ratio.
 struct DumpReq {
@@ -479,7 +491,7 @@ int take(cpmi_ctx *c, Arena &ar, DevBuf &b, size_t bytes)
 int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool want_cpp, bool want_frnn,
                hipStream_t st, bool batch_graph, RunOut &ro, const std::vector<uint64_t> *forced = nullptr,
                int64_t forced_nfull = 0, bool reuse_operand = false, const std::function<void()> &while_busy = {},
-               Arena *ar = nullptr, const DumpReq *dump = nullptr)
+               Arena *ar = nullptr, const DumpReq *dump = nullptr, const DevList *dlist = nullptr)
 {
     bool busy_done = false;
     Work local;
@@ -543,7 +555,18 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
         return (int)CPMI_OK;
     };
     int64_t ntiles, nfull, nfull_pairs;
-    if (forced || ar) {
+    if (dlist) {
+        // a list the device built (reference-point pruning): copied into place
+        ntiles = dlist->ntiles;
+        nfull = dlist->nfull;
+        nfull_pairs = dlist->timed_tiles * (int64_t)tile * tile;
+        if ((rc = get(W.tiles, std::max<size_t>(ntiles, 1) * 8))) return rc;
+        if ((rc = get(W.tile_min, std::max<size_t>(ntiles, 1) * 16))) return rc;
+        if ((rc = get(W.sel, std::max<size_t>(ntiles, 1) * 16))) return rc;
+        if (ntiles > 0)
+            HIPCHK(c, hipMemcpyAsync(W.tiles.p, dlist->tiles, ntiles * 8, hipMemcpyDeviceToDevice, st));
+        if (!ar) c->tiles_key.clear();
+    } else if (forced || ar) {
         std::vector<uint64_t> built;
         if (!forced) {
             if ((rc = list_fits())) return rc;
@@ -983,11 +1006,11 @@ uint64_t splitmix64(uint64_t x)
 // Reference-point pruning of one point set or of the windows of one series
 // (Section 3, MPR steps 1-3): order the rows by their distance to the first
 // projected reference (h.perm; for windows also its inverse, h.iperm, padded
-// to whole 256-row blocks) and bring back to the host, per block of `tile`
-// rows in that order and per reference, the interval of distances (lo, hi:
-// nT x q each, one after the other in c->plohi). Does not synchronise: the
-// intervals are there once c->evlohi has completed (prune_fetch).
-int prune_prepare(cpmi_ctx *c, HostProb &h, int tile, hipStream_t st)
+// to whole 256-row blocks), or with w > 0 by buckets of width w of that
+// distance and by the distance to the second reference within a bucket, and
+// reduce, per block of `tile` rows in that order and per reference, the
+// interval of distances (c->mlo, c->mhi: nT x q each). Queued on st only.
+int prune_prepare(cpmi_ctx *c, HostProb &h, int tile, double w, hipStream_t st)
 {
     const int q = c->prune_q;
     const int64_t n = h.n;
@@ -1003,47 +1026,32 @@ int prune_prepare(cpmi_ctx *c, HostProb &h, int tile, hipStream_t st)
     if ((rc = ensure(c, c->mrefs, (size_t)q * 4))) return rc;
     if ((rc = ensure(c, c->w.keys, (size_t)n * 8))) return rc;  // sort scratch: indices
     if ((rc = ensure(c, c->w.vals, (size_t)n * 8))) return rc;  // sorted keys
+    double *D = (double *)c->mD.p;
+    int32_t *perm = (int32_t *)c->mperm.p;
+    const bool two = w > 0.0 && q >= 2;
     size_t tb = 0;
-    HIPCHK(c, sort_ref_order(nullptr, &tb, nullptr, nullptr, nullptr, nullptr, n, st));
+    if (two) HIPCHK(c, sort_ref_order2(nullptr, &tb, D, D + n, w, nullptr, nullptr, nullptr, n, st));
+    else HIPCHK(c, sort_ref_order(nullptr, &tb, nullptr, nullptr, nullptr, nullptr, n, st));
     if ((rc = ensure(c, c->msort, std::max<size_t>(tb, 1)))) return rc;
     std::vector<int32_t> refs(q);
     for (int k = 0; k < q; ++k) refs[k] = (int32_t)(splitmix64(c->prune_seed * 64 + (uint64_t)k) % (uint64_t)n);
     HIPCHK(c, hipMemcpyAsync(c->mrefs.p, refs.data(), q * 4, hipMemcpyHostToDevice, st));
-    double *D = (double *)c->mD.p;
-    int32_t *perm = (int32_t *)c->mperm.p;
     if (h.motif) {
         launch_ref_dist_windows((const float *)h.src, n, h.d, (const int32_t *)c->mrefs.p, q, c->prune_f,
                                 D + (size_t)q * n, D, st);
     } else {
         launch_ref_dist(h.src, dtype, n, h.d, h.ld, (const int32_t *)c->mrefs.p, q, c->prune_f, D, st);
     }
-    HIPCHK(c, sort_ref_order(c->msort.p, &tb, D, (double *)c->w.vals.p, (int32_t *)c->w.keys.p, perm, n, st));
+    if (two)
+        HIPCHK(c, sort_ref_order2(c->msort.p, &tb, D, D + n, w, (double *)c->w.vals.p, (int32_t *)c->w.keys.p, perm,
+                                  n, st));
+    else
+        HIPCHK(c, sort_ref_order(c->msort.p, &tb, D, (double *)c->w.vals.p, (int32_t *)c->w.keys.p, perm, n, st));
     if (h.motif) launch_perm_finish(perm, (int32_t *)c->miperm.p, n, npad, st);
     launch_block_range(D, n, q, perm, tile, nT, (double *)c->mlo.p, (double *)c->mhi.p, st);
     HIPCHK(c, hipGetLastError());
-    const size_t nb = (size_t)nT * q * 8;
-    if (c->plohi_cap < 2 * nb) {
-        if (c->plohi) hipHostFree(c->plohi);
-        c->plohi = nullptr;
-        c->plohi_cap = 0;
-        HIPCHK(c, hipHostMalloc((void **)&c->plohi, 2 * nb, hipHostMallocDefault));
-        c->plohi_cap = 2 * nb;
-    }
-    HIPCHK(c, hipMemcpyAsync(c->plohi, c->mlo.p, nb, hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipMemcpyAsync((char *)c->plohi + nb, c->mhi.p, nb, hipMemcpyDeviceToHost, st));
-    HIPCHK(c, hipEventRecord(c->evlohi, st));
     h.perm = perm;
     if (h.motif) h.iperm = (const int32_t *)c->miperm.p;
-    return CPMI_OK;
-}
-
-// The block intervals of the last prune_prepare, once they have landed.
-int prune_fetch(cpmi_ctx *c, int64_t nT, int q, std::vector<double> &lo, std::vector<double> &hi)
-{
-    HIPCHK(c, hipEventSynchronize(c->evlohi));
-    const size_t m = (size_t)nT * q;
-    lo.assign(c->plohi, c->plohi + m);
-    hi.assign(c->plohi + m, c->plohi + 2 * m);
     return CPMI_OK;
 }
 
@@ -1072,14 +1080,18 @@ void pruned_tiles(const HostProb &h, int tile, int q, const std::vector<double> 
             if ((lJ[k] - hI[k] > T) | (lI[k] - hJ[k] > T)) return true;
         return false;
     };
-    // the rows are ordered by reference 0, so its gap only grows with J: jend[I]
-    // is the first block column whose reference-0 gap alone exceeds T
+    // the rows are ordered by reference 0 (or by buckets of it), so the least
+    // widened reference-0 distance of blocks J and after, env[J], does not
+    // decrease with J: jend[I] is the first block column from which on the
+    // reference-0 gap alone exceeds T
+    std::vector<double> env(nT);
+    for (int64_t J = nT - 1; J >= 0; --J) env[J] = J + 1 < nT ? std::min(lw[J * q], env[J + 1]) : lw[J * q];
     std::vector<int64_t> jend(nT);
     for (int64_t I = 0; I < nT; ++I) {
         int64_t a = I, b = nT;
         while (a < b) {
             const int64_t m = (a + b) / 2;
-            if (lw[m * q] - hw[I * q] > T) b = m;
+            if (env[m] - hw[I * q] > T) b = m;
             else a = m + 1;
         }
         jend[I] = band >= 0 ? std::min(a, I + band + 1) : a;
@@ -1093,59 +1105,86 @@ void pruned_tiles(const HostProb &h, int tile, int q, const std::vector<double> 
     npruned = nT * (nT + 1) / 2 - kept;
 }
 
+// Queue the device build of the pruned tile list of problem h (MPR's test of
+// step 5, per tile; the intervals of the last prune_prepare) with threshold
+// T_host, or sqrt(max(r2, U)) (1 + 2^-30) with U read from u_bits on the
+// device, and the copy of its totals to c->plist. No synchronisation.
+int queue_prune_list(cpmi_ctx *c, const HostProb &h, int tile, int q, double T_host, const unsigned long long *u_bits,
+                     double r2, hipStream_t st)
+{
+    const int64_t nT = (h.n + tile - 1) / tile;
+    const int64_t G = std::max(1, h.band);
+    const int64_t S = prune_segments(nT, G);
+    const bool permuted = h.motif && h.perm;
+    int rc;
+    if ((rc = ensure(c, c->mtl, ((size_t)nT * (nT + 1) / 2 + 8) * 8))) return rc;
+    if ((rc = ensure(c, c->mseg, (size_t)S * 16))) return rc;
+    if ((rc = ensure(c, c->mout4, 32))) return rc;
+    size_t tb = 0;
+    HIPCHK(c, launch_prune_list(nullptr, &tb, nullptr, nullptr, q, h.n, h.excl, tile, permuted, G, T_host,
+                                u_bits, r2, nullptr, nullptr, nullptr, nullptr, st));
+    if ((rc = ensure(c, c->mscan, std::max<size_t>(tb, 1)))) return rc;
+    if (!c->plist) HIPCHK(c, hipHostMalloc((void **)&c->plist, 32, hipHostMallocDefault));
+    uint64_t *seg = (uint64_t *)c->mseg.p;
+    HIPCHK(c, launch_prune_list(c->mscan.p, &tb, (const double *)c->mlo.p, (const double *)c->mhi.p, q, h.n,
+                                h.excl, tile, permuted, G, T_host, u_bits, r2, seg, seg + S, (uint64_t *)c->mtl.p,
+                                (int64_t *)c->mout4.p, st));
+    HIPCHK(c, hipMemcpyAsync(c->plist, c->mout4.p, 32, hipMemcpyDeviceToHost, st));
+    return CPMI_OK;
+}
+
+// The list queued by queue_prune_list, once the stream has passed it.
+DevList prune_list_of(const cpmi_ctx *c)
+{
+    const int64_t *o = c->plist;
+    return DevList{(const uint64_t *)c->mtl.p, o[0], o[1], o[1] > 0 ? o[2] : o[3]};
+}
+
 // The exact search of one problem with reference-point tile pruning. MPR keeps
 // a running upper bound of the least distance; here it comes from a first
 // search over the diagonal band of the reference order (neighbouring blocks,
 // where close pairs land), and the full search then skips every tile whose
-// reference bound exceeds it and the radius.
+// reference bound exceeds it and the radius. The full list is built on the
+// device behind the band search, from the band's U as the device left it.
 int pruned_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool want_cpp, bool want_frnn,
                   hipStream_t st, RunOut &ro)
 {
     const int q = c->prune_q;
-    const int64_t nT = (hp[0].n + tile - 1) / tile;
-    std::vector<double> lo, hi;
+    HostProb &h = hp[0];
+    const int64_t nT = (h.n + tile - 1) / tile;
+    const double r2 = want_frnn ? h.r2 : 0.0;
+    // radius queries with two or more references: the two-reference order
+    const bool two = want_frnn && q >= 2 && c->prune_order == 0 && r2 > 0.0 && std::isfinite(r2);
+    if ((double)nT * (nT + 1.0) / 2.0 > 2147483647.0 - 1048576.0)
+        return fail(c, CPMI_ERR_ARG, "problem too large for one pruned screen (%lld blocks)", (long long)nT);
     int rc;
-    if ((rc = prune_prepare(c, hp[0], tile, st))) return rc;
-    std::vector<uint64_t> tl, tlr;
-    int64_t nfull = 0, npruned = 0, nfull_r = 0, npruned_r = 0;
-    const double inf = std::numeric_limits<double>::infinity();
-    const double r2 = want_frnn ? hp[0].r2 : 0.0;
-    double thr2 = r2;
-    bool have_r = false;
+    if ((rc = prune_prepare(c, h, tile, two ? c->prune_w * std::sqrt(r2) : 0.0, st))) return rc;
+    h.band = pick_band(c, prec, h.d, (double)pairs_of(h));
     if (want_cpp) {
         // the band list needs no intervals (with T = inf no tile is dropped)
         const std::vector<double> none((size_t)nT * q, 0.0);
-        pruned_tiles(hp[0], tile, q, none, none, inf, 1, tl, nfull, npruned);
-        // while the band search runs: fetch the intervals and, with a radius,
-        // build the list for T = R, the final one unless the band's least
-        // squared distance exceeds R^2
+        std::vector<uint64_t> tl;
+        int64_t nfull = 0, npruned = 0;
+        pruned_tiles(h, tile, q, none, none, std::numeric_limits<double>::infinity(), 1, tl, nfull, npruned);
+        // queued behind the band search: the full list from the band's U
         int frc = CPMI_OK;
         auto busy = [&]() {
-            frc = prune_fetch(c, nT, q, lo, hi);
-            if (frc == CPMI_OK && want_frnn) {
-                pruned_tiles(hp[0], tile, q, lo, hi, std::sqrt(r2) * (1.0 + 0x1p-30), -1, tlr, nfull_r, npruned_r);
-                have_r = true;
-            }
+            frc = queue_prune_list(c, h, tile, q, 0.0, (const unsigned long long *)c->w.res.p, r2, st);
         };
         RunOut band;
         if ((rc = run_search(c, hp, prec, tile, true, false, st, false, band, &tl, nfull, false, busy))) return rc;
         if (frc) return frc;
         if ((rc = flags_error(c, band.res[0].flags))) return rc;
-        const double u = __builtin_bit_cast(double, (uint64_t)band.res[0].best_d2);
-        thr2 = std::max(thr2, std::isfinite(u) ? u : inf);
-    } else if ((rc = prune_fetch(c, nT, q, lo, hi))) {
-        return rc;
-    }
-    if (have_r && thr2 == r2) {
-        tl.swap(tlr);
-        nfull = nfull_r;
-        npruned = npruned_r;
     } else {
-        pruned_tiles(hp[0], tile, q, lo, hi, std::sqrt(thr2) * (1.0 + 0x1p-30), -1, tl, nfull, npruned);
+        if ((rc = queue_prune_list(c, h, tile, q, std::sqrt(r2) * (1.0 + 0x1p-30), nullptr, 0.0, st))) return rc;
+        HIPCHK(c, hipStreamSynchronize(st));
     }
+    const DevList dl = prune_list_of(c);
     // the band search (if any) left the screen operand in place
-    if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro, &tl, nfull, want_cpp))) return rc;
-    c->stats.tiles_pruned = npruned;
+    if ((rc = run_search(c, hp, prec, tile, want_cpp, want_frnn, st, false, ro, nullptr, 0, want_cpp, {}, nullptr,
+                         nullptr, &dl)))
+        return rc;
+    c->stats.tiles_pruned = nT * (nT + 1) / 2 - (c->plist[2] + c->plist[3]);
     return CPMI_OK;
 }
 
@@ -1206,7 +1245,6 @@ int cpmi_create(cpmi_ctx **out, int device, const char *tune_cache_path)
     if (hipSetDevice(device) != hipSuccess || hipEventCreate(&c->ev0) != hipSuccess ||
         hipEventCreate(&c->ev1) != hipSuccess || hipEventCreate(&c->es0) != hipSuccess ||
         hipEventCreate(&c->es1) != hipSuccess ||
-        hipEventCreateWithFlags(&c->evlohi, hipEventDisableTiming) != hipSuccess ||
         hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return CPMI_ERR_HIP;
@@ -1224,7 +1262,6 @@ int cpmi_create(cpmi_ctx **out, int device, const char *tune_cache_path)
                 hipEventDestroy(c->ev1);
                 hipEventDestroy(c->es0);
                 hipEventDestroy(c->es1);
-                hipEventDestroy(c->evlohi);
                 hipStreamDestroy(c->own);
                 delete c;
                 return CPMI_ERR_HIP;
@@ -1247,12 +1284,12 @@ int cpmi_destroy(cpmi_ctx *c)
     DevBuf *bufs[] = {&c->w.xs,      &c->w.shat,  &c->w.bmax, &c->w.musg, &c->w.probs, &c->w.jobs, &c->w.tiles, &c->w.tile_min,
                       &c->w.sel,     &c->w.candR, &c->w.candU, &c->w.cand_d2, &c->w.keys, &c->w.vals, &c->w.cnt, &c->w.ubits,
                       &c->w.res,     &c->mD,    &c->mperm, &c->miperm, &c->mlo, &c->mhi, &c->mrefs, &c->msort, &c->w.mrowstat,
-                      &c->mZ,      &c->mflag, &c->lbA, &c->lbT, &c->lbC, &c->lbP, &c->lbK};
+                      &c->mZ,      &c->mflag, &c->lbA, &c->lbT, &c->lbC, &c->lbP, &c->lbK, &c->mtl, &c->mseg,
+                      &c->mscan,   &c->mout4};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
     if (c->pinned) hipHostFree(c->pinned);
-    if (c->plohi) hipHostFree(c->plohi);
-    if (c->evlohi) hipEventDestroy(c->evlohi);
+    if (c->plist) hipHostFree(c->plist);
     if (c->ev0) hipEventDestroy(c->ev0);
     if (c->ev1) hipEventDestroy(c->ev1);
     if (c->es0) hipEventDestroy(c->es0);
@@ -1986,6 +2023,46 @@ int64_t cpmi_dbg_pruned_tiles(int64_t n, int tile, int q, const double *lo, cons
     if (nfull) *nfull = nf;
     if (npruned) *npruned = np;
     return (int64_t)tl.size();
+}
+
+int64_t cpmi_dbg_pruned_tiles_gpu(cpmi_ctx *c, int64_t n, int tile, int q, const double *lo, const double *hi, double T,
+                                  int64_t excl, int permuted, uint64_t *out, int64_t cap, int64_t *nfull,
+                                  int64_t *npruned, void *stream)
+{
+    if (!c) return CPMI_ERR_ARG;
+    if (n < 2 || n > ((int64_t)1 << 31) - 1 || (tile != 128 && tile != 256) || q < 1 || q > 32 || !lo || !hi ||
+        cap < 0 || (cap > 0 && !out) || excl < 1 || excl > ((int64_t)1 << 30))
+        return fail(c, CPMI_ERR_ARG, "bad arguments");
+    hipSetDevice(c->device);
+    const hipStream_t st = (hipStream_t)stream;
+    const int64_t nT = (n + tile - 1) / tile;
+    int rc;
+    if ((rc = ensure(c, c->mlo, (size_t)nT * q * 8))) return rc;
+    if ((rc = ensure(c, c->mhi, (size_t)nT * q * 8))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->mlo.p, lo, (size_t)nT * q * 8, hipMemcpyHostToDevice, st));
+    HIPCHK(c, hipMemcpyAsync(c->mhi.p, hi, (size_t)nT * q * 8, hipMemcpyHostToDevice, st));
+    HostProb h;
+    h.n = n;
+    h.excl = excl;
+    h.motif = permuted != 0;
+    static const int32_t any_perm = 0;
+    h.perm = permuted ? &any_perm : nullptr;   // only its presence counts here
+    if ((rc = queue_prune_list(c, h, tile, q, T, nullptr, 0.0, st))) return rc;
+    HIPCHK(c, hipStreamSynchronize(st));
+    const DevList dl = prune_list_of(c);
+    const int64_t m = std::min(cap, dl.ntiles);
+    if (m > 0) HIPCHK(c, hipMemcpy(out, dl.tiles, (size_t)m * 8, hipMemcpyDeviceToHost));
+    if (nfull) *nfull = dl.nfull;
+    if (npruned) *npruned = nT * (nT + 1) / 2 - (c->plist[2] + c->plist[3]);
+    return dl.ntiles;
+}
+
+int cpmi_dbg_set_prune_order(cpmi_ctx *c, int order, double w)
+{
+    if (!c || order < 0 || order > 1 || !(w > 0.0) || !std::isfinite(w)) return CPMI_ERR_ARG;
+    c->prune_order = order;
+    c->prune_w = w;
+    return CPMI_OK;
 }
 
 double cpmi_dbg_tile_lb(const double *loI, const double *hiI, const double *loJ, const double *hiJ, int q)

@@ -275,6 +275,17 @@ void launch_lb_fill(const uint64_t *keys, const int32_t *rows, int64_t total, in
 void launch_lb_verify(const signed char *S, int64_t k, int64_t ld, int mode, const int2 *cand, uint64_t m,
                       unsigned long long *best, hipStream_t st);
 void launch_perm_finish(int32_t *perm, int32_t *iperm, int64_t n, int64_t npad, hipStream_t st);
+hipError_t sort_ref_order2(void *temp, size_t *temp_bytes, const double *D0, const double *D1, double w,
+                           double *keys_out, int32_t *idx, int32_t *perm, int64_t n, hipStream_t st);
+int64_t prune_segments(int64_t nT, int64_t G);
+// The pruned tile list of one problem on the device (temp == nullptr: only
+// sets *temp_bytes). cnt, off: prune_segments(nT, G) words each; out:
+// nT (nT + 1) / 2 + 8 entries; out4 (device): entries, full slots, full
+// tiles, partial tiles. Threshold T_host, or from u_bits and r2.
+hipError_t launch_prune_list(void *temp, size_t *temp_bytes, const double *lo, const double *hi, int q, int64_t n,
+                             int64_t excl, int tile, bool permuted, int64_t G, double T_host,
+                             const unsigned long long *u_bits, double r2, uint64_t *cnt, uint64_t *off, uint64_t *out,
+                             int64_t *out4, hipStream_t st);
 void launch_block_range(const double *D, int64_t n, int q, const int32_t *perm, int tile, int64_t nblk, double *lo,
                         double *hi, hipStream_t st);
 // Unpack sorted keys (i << 32 | j) into int64 pairs [m][2] and copy values.

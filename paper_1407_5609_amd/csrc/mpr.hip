@@ -19,6 +19,7 @@
 #include <algorithm>
 
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "cpmi_internal.h"
 
@@ -224,6 +225,147 @@ __global__ __launch_bounds__(256) void block_range_kernel(const double *D, int64
 
 unsigned grid_of(int64_t n, int per) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, 65536)); }
 
+// Second key of the two-reference order: the bucket floor(D0 / w) of the row
+// sorted k-th by D1 (idx1[k]); the row index rides along.
+__global__ void bucket_key_kernel(const double *D0, const int32_t *idx1, double w, int64_t n, uint32_t *key,
+                                  int32_t *idx)
+{
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = idx1[k];
+        const double b = floor(D0[r] / w);
+        key[k] = b >= 4294967295.0 ? 0xffffffffu : (uint32_t)fmax(b, 0.0);
+        idx[k] = r;
+    }
+}
+
+// ---- the pruned tile list on the device (MPR step 5 applied to tiles)
+//
+// Tiles (I, J), I <= J, are enumerated in bands of G block rows, column by
+// column within a band (rows ascending): the order the screen's list uses. A
+// segment is one column J of one band: at most G tiles. Segment s of band bi
+// is column b0 + (s - segoff(bi)), b0 = bi G, with
+// segoff(bi) = bi nT - G bi (bi - 1) / 2 segments before band bi.
+struct SegMap {
+    int64_t nT, G, nB;
+    __device__ int64_t segoff(int64_t bi) const { return bi * nT - G * bi * (bi - 1) / 2; }
+    __device__ void at(int64_t s, int64_t &b0, int64_t &J) const
+    {
+        int64_t a = 0, b = nB - 1;   // the last band whose offset is <= s
+        while (a < b) {
+            const int64_t m = (a + b + 1) / 2;
+            if (segoff(m) <= s) a = m;
+            else b = m - 1;
+        }
+        b0 = a * G;
+        J = b0 + (s - segoff(a));
+    }
+};
+
+struct PruneTest {
+    const double *lo, *hi;
+    int q;
+    double T;
+    int64_t n, excl;
+    int tile;
+    bool permuted;
+    // the widened intervals of blocks I and J come more than T apart for some
+    // reference (the host's rule, operation for operation: a widening by
+    // 2^-34 |hi| on both sides)
+    __device__ bool far(int64_t I, int64_t J) const
+    {
+        if (T < 0.0) return true;
+        for (int k = 0; k < q; ++k) {
+            const double hI = hi[I * q + k], hJ = hi[J * q + k];
+            const double mI = 0x1p-34 * fabs(hI), mJ = 0x1p-34 * fabs(hJ);
+            const double lwI = lo[I * q + k] - mI, hwI = hI + mI;
+            const double lwJ = lo[J * q + k] - mJ, hwJ = hJ + mJ;
+            if ((lwJ - hwI > T) | (lwI - hwJ > T)) return true;
+        }
+        return false;
+    }
+    // 0: no admissible pair or pruned; 1: kept, every pair admissible; 2: kept, partial
+    __device__ int kind(int64_t I, int64_t J) const
+    {
+        const int64_t maxj = min(J * tile + tile - 1, n - 1);
+        if (!permuted && maxj - I * tile < excl) return 0;
+        if (far(I, J)) return 0;
+        const bool full = !permuted && (J * tile - (I * tile + tile - 1) >= excl) && ((I + 1) * tile <= n) &&
+                          ((J + 1) * tile <= n);
+        return full ? 1 : 2;
+    }
+};
+
+// The threshold: T_host, or sqrt(max(r2, U)) (1 + 2^-30) with U the least
+// squared distance a previous search left in *u_bits (double bits; not a
+// finite number: none found, keep every tile).
+__device__ double prune_threshold(double T_host, const unsigned long long *u_bits, double r2)
+{
+    if (!u_bits) return T_host;
+    double u = __longlong_as_double((long long)*u_bits);
+    if (!isfinite(u)) u = INFINITY;
+    return sqrt(fmax(r2, u)) * (1.0 + 0x1p-30);
+}
+
+// Per segment: kept full tiles << 32 | kept partial tiles.
+__global__ __launch_bounds__(256) void prune_count_kernel(SegMap sm, PruneTest pt, double T_host,
+                                                          const unsigned long long *u_bits, double r2, int64_t S,
+                                                          uint64_t *cnt)
+{
+    pt.T = prune_threshold(T_host, u_bits, r2);
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x) {
+        int64_t b0, J;
+        sm.at(s, b0, J);
+        uint64_t cf = 0, cp = 0;
+        for (int64_t I = b0; I < min(b0 + sm.G, sm.nT) && I <= J; ++I) {
+            const int k = pt.kind(I, J);
+            cf += k == 1;
+            cp += k == 2;
+        }
+        cnt[s] = cf << 32 | cp;
+    }
+}
+
+// Writes the list: the Tf kept full tiles split into 8 contiguous chunks of
+// C = ceil(Tf / 8) interleaved slot by slot (the chunk of slot x is x % 8, so
+// the work-groups of one XCD walk one chunk), the empty slots of that part
+// TILE_NONE, then the Tp partial tiles in order. out4 = {entries, full
+// slots (8 C), Tf, Tp}.
+__global__ __launch_bounds__(256) void prune_write_kernel(SegMap sm, PruneTest pt, double T_host,
+                                                          const unsigned long long *u_bits, double r2, int64_t S,
+                                                          const uint64_t *cnt, const uint64_t *off, uint64_t *out,
+                                                          int64_t *out4)
+{
+    pt.T = prune_threshold(T_host, u_bits, r2);
+    const uint64_t tot = off[S - 1] + cnt[S - 1];
+    const int64_t Tf = (int64_t)(tot >> 32), Tp = (int64_t)(tot & 0xffffffffu);
+    const int64_t C = (Tf + 7) / 8;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < S; s += (int64_t)gridDim.x * blockDim.x) {
+        if (s == 0) {
+            for (int64_t ch = 0; ch < 8; ++ch)
+                for (int64_t pos = max<int64_t>(0, Tf - ch * C); pos < C; ++pos) out[pos * 8 + ch] = TILE_NONE;
+            out4[0] = 8 * C + Tp;
+            out4[1] = 8 * C;
+            out4[2] = Tf;
+            out4[3] = Tp;
+        }
+        int64_t b0, J;
+        sm.at(s, b0, J);
+        int64_t rf = (int64_t)(off[s] >> 32), rp = (int64_t)(off[s] & 0xffffffffu);
+        for (int64_t I = b0; I < min(b0 + sm.G, sm.nT) && I <= J; ++I) {
+            const int k = pt.kind(I, J);
+            if (k == 0) continue;
+            const uint64_t e = tile_pack(0u, (uint32_t)I, (uint32_t)J);
+            if (k == 1) {
+                out[(rf % C) * 8 + rf / C] = e;
+                ++rf;
+            } else {
+                out[8 * C + rp] = e;
+                ++rp;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 void launch_ref_dist(const void *X, int dtype, int64_t n, int64_t d, int64_t ld, const int32_t *refs, int q,
@@ -267,6 +409,63 @@ hipError_t sort_ref_order(void *temp, size_t *temp_bytes, const double *D0, doub
     if (temp) hipLaunchKernelGGL(iota_kernel, dim3(grid_of(n, 256)), dim3(256), 0, st, idx, n);
     return rocprim::radix_sort_pairs(temp, *temp_bytes, D0, keys_out, (const int32_t *)idx, perm, (unsigned int)n, 0,
                                      64, st);
+}
+
+// The two-reference order: rows sorted by bucket floor(D0 / w), and by D1
+// within a bucket (two stable radix sorts: by D1, then by the bucket).
+// keys_out (n doubles) and idx (n int64 = 2n int32) are scratch.
+hipError_t sort_ref_order2(void *temp, size_t *temp_bytes, const double *D0, const double *D1, double w,
+                           double *keys_out, int32_t *idx, int32_t *perm, int64_t n, hipStream_t st)
+{
+    int32_t *idx1 = idx + n;                       // rows by D1
+    uint32_t *bkey = (uint32_t *)keys_out, *bkey_out = bkey + n;
+    if (!temp) {
+        size_t a = 0, b = 0;
+        hipError_t e = rocprim::radix_sort_pairs(nullptr, a, D1, keys_out, (const int32_t *)idx, idx1,
+                                                 (unsigned int)n, 0, 64, st);
+        if (e != hipSuccess) return e;
+        e = rocprim::radix_sort_pairs(nullptr, b, (const uint32_t *)bkey, bkey_out, (const int32_t *)idx, perm,
+                                      (unsigned int)n, 0, 32, st);
+        *temp_bytes = std::max(a, b);
+        return e;
+    }
+    hipLaunchKernelGGL(iota_kernel, dim3(grid_of(n, 256)), dim3(256), 0, st, idx, n);
+    hipError_t e = rocprim::radix_sort_pairs(temp, *temp_bytes, D1, keys_out, (const int32_t *)idx, idx1,
+                                             (unsigned int)n, 0, 64, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bucket_key_kernel, dim3(grid_of(n, 256)), dim3(256), 0, st, D0, (const int32_t *)idx1, w, n,
+                       bkey, idx);
+    return rocprim::radix_sort_pairs(temp, *temp_bytes, (const uint32_t *)bkey, bkey_out, (const int32_t *)idx, perm,
+                                     (unsigned int)n, 0, 32, st);
+}
+
+// Segments of the pruned list's enumeration (nT block rows, bands of G).
+int64_t prune_segments(int64_t nT, int64_t G)
+{
+    const int64_t nB = (nT + G - 1) / G;
+    return nB * nT - G * nB * (nB - 1) / 2;
+}
+
+hipError_t launch_prune_list(void *temp, size_t *temp_bytes, const double *lo, const double *hi, int q, int64_t n,
+                             int64_t excl, int tile, bool permuted, int64_t G, double T_host,
+                             const unsigned long long *u_bits, double r2, uint64_t *cnt, uint64_t *off, uint64_t *out,
+                             int64_t *out4, hipStream_t st)
+{
+    const int64_t nT = (n + tile - 1) / tile;
+    const int64_t S = prune_segments(nT, G);
+    if (!temp)
+        return rocprim::exclusive_scan(nullptr, *temp_bytes, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                       (uint64_t)0, (size_t)S, rocprim::plus<uint64_t>(), st);
+    SegMap sm{nT, G, (nT + G - 1) / G};
+    PruneTest pt{lo, hi, q, 0.0, n, excl, tile, permuted};
+    const dim3 g(grid_of(S, 256)), b(256);
+    hipLaunchKernelGGL(prune_count_kernel, g, b, 0, st, sm, pt, T_host, u_bits, r2, S, cnt);
+    hipError_t e = rocprim::exclusive_scan(temp, *temp_bytes, (const uint64_t *)cnt, off, (uint64_t)0, (size_t)S,
+                                           rocprim::plus<uint64_t>(), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(prune_write_kernel, g, b, 0, st, sm, pt, T_host, u_bits, r2, S, (const uint64_t *)cnt,
+                       (const uint64_t *)off, out, out4);
+    return hipGetLastError();
 }
 
 void launch_block_range(const double *D, int64_t n, int q, const int32_t *perm, int tile, int64_t nblk, double *lo,

@@ -490,18 +490,35 @@ def _pruned(lib, n, tile, lo, hi, T, band):
     return tiles, nf.value, npr.value
 
 
+def _interval_fixture(order):
+    """Block intervals of 37 blocks and 3 references: blocks in the order of
+    reference 0 (order 0), or in buckets of reference 0 (width 8) sorted by
+    reference 1 within a bucket (order 1, so reference 0 is not monotone)."""
+    rng = np.random.default_rng(77)
+    nT, q = 37, 3
+    lo = np.empty((nT, q))
+    if order == 0:
+        lo[:, 0] = np.sort(rng.uniform(0, 60, nT))
+        lo[:, 1:] = rng.uniform(0, 30, (nT, q - 1))
+    else:
+        d0, d1 = rng.uniform(0, 60, nT), rng.uniform(0, 30, nT)
+        idx = np.lexsort((d1, np.floor(d0 / 8.0)))
+        lo[:, 0], lo[:, 1] = d0[idx], d1[idx]
+        lo[:, 2] = rng.uniform(0, 30, nT)
+    hi = lo + rng.uniform(0.1, 3.0, (nT, q))
+    return nT, q, lo, hi
+
+
 @pytest.mark.parametrize("T,band", [(0.5, -1), (2.0, -1), (6.0, -1), (1e9, -1), (3.0, 1), (-1.0, -1)])
-def test_pruned_tile_list_is_the_interval_gap_rule(lib, T, band):
+@pytest.mark.parametrize("order", [0, 1])
+def test_pruned_tile_list_is_the_interval_gap_rule(lib, T, band, order):
     """The pruned list keeps exactly the tiles (I <= J, within the band) whose
     widened distance intervals come within T of each other for every
-    reference: the triangle inequality applied to blocks (Section 3)."""
-    rng = np.random.default_rng(77)
-    nT, q, tile = 37, 3, 256
+    reference: the triangle inequality applied to blocks (Section 3), with
+    the blocks in either row order the pruned searches use."""
+    nT, q, lo, hi = _interval_fixture(order)
+    tile = 256
     n = nT * tile - 50
-    lo = np.empty((nT, q))
-    lo[:, 0] = np.sort(rng.uniform(0, 60, nT))              # rows in the order of reference 0
-    lo[:, 1:] = rng.uniform(0, 30, (nT, q - 1))
-    hi = lo + rng.uniform(0.1, 3.0, (nT, q))
     got, nfull, npruned = _pruned(lib, n, tile, lo, hi, T, band)
     m = 2.0 ** -34 * np.abs(hi)
     lw, hw = lo - m, hi + m

@@ -122,22 +122,26 @@ def test_motif_full_size_golden_with_pruning(ctx, torch_dev):
         ctx.set_pruning(0)
 
 
-@pytest.mark.parametrize("q", [0, 10])
-def test_walk_full_size_golden(ctx, torch_dev, q):
+@pytest.mark.parametrize("q,order", [(0, 0), (10, 0), (10, 1)])
+def test_walk_full_size_golden(ctx, torch_dev, q, order):
     """Random walk of 100,000 samples, windows of 1,024 (the shape the paper
     measures reference-point pruning on), unpruned and with q = 10 references
-    projected by f = 10: motif and radius pairs equal the oracle's."""
+    projected by f = 10, the radius query in the two-reference order (0) or
+    the first reference's (1): motif and radius pairs equal the oracle's."""
     g = _golden("walk_L100000_l1024.json")
     want_pair, want_pairs, want_d2 = _want(g)
     c = W.cfg_walk()
     t = _dev(c["T"], torch_dev)
     ctx.set_pruning(q, 10.0, seed=1)
+    ctx.dbg_set_prune_order(order)
     try:
         best, (p, d) = ctx.motif(t, c["ell"], excl=c["excl"], R2=float.fromhex(g["R2"]), precision="bf16")
         st = ctx.stats()
         only, _ = ctx.motif(t, c["ell"], excl=c["excl"], precision="bf16")
     finally:
         ctx.set_pruning(0)
+        ctx.dbg_set_prune_order(0)
+    print("order", order, "tiles screened", st.tiles_total, "pruned", st.tiles_pruned)
     assert (best.i, best.j, best.d2) == want_pair
     assert (only.i, only.j, only.d2) == want_pair
     assert np.array_equal(p.cpu().numpy(), want_pairs)

@@ -519,18 +519,20 @@ def test_calibration_copy_moves_every_byte(torch_dev):
 # reference-point tile pruning (Section 3, MPR): same answers, fewer tiles
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("q", [1, 4])
+@pytest.mark.parametrize("q,order", [(1, 0), (4, 0), (4, 1)])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_pruned_points_match_oracle(ctx, torch_dev, tile, prec, q):
+def test_pruned_points_match_oracle(ctx, torch_dev, tile, prec, q, order):
     rng = np.random.default_rng(100 + q)
     X, _ = W.mixture_points(rng, 3000, 48)
     R2 = 30.0
     ctx.set_pruning(q, 10.0, seed=q)
+    ctx.dbg_set_prune_order(order)
     try:
         best, fr = ctx.points(_dev(X, torch_dev), R2=R2, precision=prec)
         st = ctx.stats()
     finally:
         ctx.set_pruning(0)
+        ctx.dbg_set_prune_order(0)
     _check_pair(best, oracle.closest_pair(X))
     _check_frnn(fr, oracle.frnn(X, R2))
     assert st.tiles_pruned > 0
@@ -569,23 +571,26 @@ def test_pruned_int8_and_frnn_only(ctx, torch_dev, tile):
     _check_frnn((p, d), oracle.frnn(X, 40))
 
 
-@pytest.mark.parametrize("q", [1, 4])
+@pytest.mark.parametrize("q,order", [(1, 0), (4, 0), (4, 1)])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 @pytest.mark.parametrize("length,ell,excl", [(3000, 64, 0), (5000, 100, 50), (2100, 128, 1), (1300, 16, 0)])
-def test_pruned_motif_matches_oracle(ctx, torch_dev, prec, q, length, ell, excl):
-    """Windows in reference order: the exclusion zone is applied to window
-    positions, not screen rows; answers equal the oracle's."""
+def test_pruned_motif_matches_oracle(ctx, torch_dev, prec, q, order, length, ell, excl):
+    """Windows in reference order (one reference, or buckets of one and the
+    order of a second): the exclusion zone is applied to window positions,
+    not screen rows; answers equal the oracle's."""
     rng = np.random.default_rng(length + ell + q)
     T = W.random_walk(rng, length)
     W.plant_motif(rng, T, ell)
     R2 = 0.05 * ell
     ctx.set_pruning(q, 10.0, seed=q)
+    ctx.dbg_set_prune_order(order)
     try:
         best, fr = ctx.motif(_dev(T, torch_dev), ell, excl=excl, R2=R2, precision=prec)
         st = ctx.stats()
         best_only, _ = ctx.motif(_dev(T, torch_dev), ell, excl=excl, precision=prec)
     finally:
         ctx.set_pruning(0)
+        ctx.dbg_set_prune_order(0)
     ob, ofr = oracle.motif(T, ell, excl=excl if excl > 0 else ell, R2=R2)
     _check_pair(best, ob)
     _check_pair(best_only, ob)
@@ -661,12 +666,120 @@ def test_pruned_motif_drops_tiles_on_a_random_walk(ctx, torch_dev):
     print("pruned", st.tiles_pruned, "of", st.tiles_pruned + st.tiles_total, "tiles")
 
 
+def _intervals(rng, nT, q, order):
+    """Per-block distance intervals [nT, q] with the blocks in the order of
+    reference 0 (order 0) or in buckets of reference 0 sorted by reference 1
+    (order 1: reference 0 not monotone)."""
+    lo = rng.uniform(0, 60, (nT, q))
+    if order == 0:
+        lo[:, 0] = np.sort(lo[:, 0])
+    elif q >= 2:
+        idx = np.lexsort((lo[:, 1], np.floor(lo[:, 0] / 6.0)))
+        lo[:, :2] = lo[idx, :2]
+    return lo, lo + rng.uniform(0.05, 3.0, (nT, q))
+
+
+def _list_rule(n, tile, lo, hi, T, excl=1, permuted=False, G=8):
+    """The pruned list written out: tiles I <= J with an admissible pair whose
+    widened intervals (2^-34 |hi| on each side) come within T for every
+    reference, in bands of G block rows (columns ascending, rows ascending);
+    full tiles first, split into 8 chunks interleaved slot by slot (empty
+    slots all ones), then the partial tiles."""
+    nT = lo.shape[0]
+    m = 2.0 ** -34 * np.abs(hi)
+    lw, hw = lo - m, hi + m
+    full, part = [], []
+    for b0 in range(0, nT, G):
+        for J in range(b0, nT):
+            for I in range(b0, min(b0 + G, nT)):
+                if I > J:
+                    continue
+                if not permuted and min(J * tile + tile - 1, n - 1) - I * tile < excl:
+                    continue
+                if T < 0 or np.any((lw[J] - hw[I] > T) | (lw[I] - hw[J] > T)):
+                    continue
+                e = (I << 22) | J
+                isfull = (not permuted and J * tile - (I * tile + tile - 1) >= excl and (I + 1) * tile <= n
+                          and (J + 1) * tile <= n)
+                (full if isfull else part).append(e)
+    C8 = (len(full) + 7) // 8
+    slots = [2 ** 64 - 1] * (8 * C8)
+    for s in range(8 * C8):
+        src = (s % 8) * C8 + s // 8
+        if src < len(full):
+            slots[s] = full[src]
+    return np.array(slots + part, dtype=np.uint64), 8 * C8, nT * (nT + 1) // 2 - len(full) - len(part)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("edge", [128, 256])
+@pytest.mark.parametrize("nT,q", [(1, 1), (5, 1), (37, 3), (140, 2)])
+def test_pruned_list_on_the_device_is_the_interval_gap_rule(ctx, torch_dev, order, edge, nT, q):
+    """The device-built list of the pruned searches (MPR's test of step 5 per
+    tile, Section 3): the same entries in the same order as the rule written
+    out, and as the host's list, for every threshold, both row orders, both
+    tile edges, ragged last blocks, exclusion zones and windows in reference
+    order (every tile partial)."""
+    import ctypes as C
+    import paper_1407_5609_amd as cp
+    rng = np.random.default_rng(1000 * nT + 10 * q + order)
+    lo, hi = _intervals(rng, nT, q, order)
+    n = max(2, nT * edge - 17)
+    hf = cp._lib.cpmi_dbg_pruned_tiles
+    hf.restype = C.c_int64
+    hf.argtypes = [C.c_int64, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_int64, C.c_void_p,
+                   C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    for T in (-1.0, 0.0, 0.7, 2.5, 9.0, float("inf")):
+        got, gnf, gnp = ctx.dbg_pruned_tiles_gpu(n, edge, lo, hi, T)
+        want, wnf, wnp = _list_rule(n, edge, lo, hi, T)
+        assert np.array_equal(got, want), (T, len(got), len(want))
+        assert (gnf, gnp) == (wnf, wnp)
+        hout = np.zeros(len(want) + 8, dtype=np.uint64)
+        hnf, hnp = C.c_int64(0), C.c_int64(0)
+        cnt = hf(n, edge, q, lo.ctypes.data, hi.ctypes.data, T, -1, hout.ctypes.data, len(hout), C.byref(hnf),
+                 C.byref(hnp))
+        assert np.array_equal(hout[:cnt], want) and (hnf.value, hnp.value) == (wnf, wnp)
+        for excl, permuted in ((3 * edge // 2, False), (1, True)):
+            got, gnf, gnp = ctx.dbg_pruned_tiles_gpu(n, edge, lo, hi, T, excl=excl, permuted=permuted)
+            want, wnf, wnp = _list_rule(n, edge, lo, hi, T, excl=excl, permuted=permuted)
+            assert np.array_equal(got, want), (T, excl, permuted)
+            assert (gnf, gnp) == (wnf, wnp)
+
+
+def test_pruned_list_on_the_device_at_size(ctx, torch_dev):
+    """1,024 blocks (the 262,144-point mixture at edge 256): 524,800 tiles in
+    66,048 segments, several scan blocks; equal to the rule (vectorised)."""
+    rng = np.random.default_rng(5)
+    nT, q, edge = 1024, 2, 256
+    lo, hi = _intervals(rng, nT, q, 1)
+    n = nT * edge
+    T = 4.0
+    got, gnf, gnp = ctx.dbg_pruned_tiles_gpu(n, edge, lo, hi, T)
+    m = 2.0 ** -34 * np.abs(hi)
+    lw, hw = lo - m, hi + m
+    far = np.zeros((nT, nT), dtype=bool)
+    for k in range(q):
+        far |= (lw[None, :, k] - hw[:, None, k] > T) | (lw[:, None, k] - hw[None, :, k] > T)
+    I, J = np.nonzero(np.triu(~far))
+    kept = {(int(i), int(j)) for i, j in zip(I, J)}
+    real = got[got != np.uint64(2 ** 64 - 1)]
+    gotset = {(int(e >> np.uint64(22)) & 0x3FFFFF, int(e) & 0x3FFFFF) for e in real}
+    assert len(real) == len(gotset) == len(kept) and gotset == kept
+    assert gnp == nT * (nT + 1) // 2 - len(kept)
+    full = [(i, j) for i, j in kept if i != j]
+    assert gnf == 8 * ((len(full) + 7) // 8)
+
+
 def test_pruning_arguments(ctx):
     import paper_1407_5609_amd as cp
     for q, f in ((-1, 10.0), (33, 10.0), (2, 0.0), (2, float("nan"))):
         with pytest.raises(cp.CpmiError):
             ctx.set_pruning(q, f)
     ctx.set_pruning(0)
+    for order, w in ((2, 2.0), (-1, 2.0), (0, 0.0), (0, float("inf"))):
+        with pytest.raises(cp.CpmiError):
+            ctx.dbg_set_prune_order(order, w)
+    ctx.dbg_set_prune_order(0)
 
 
 @pytest.mark.parametrize("prec,published", [("bf16", 2500.0), ("f32", 157.3), ("i8", 5000.0)])
