@@ -414,7 +414,7 @@ def main():
     ap.add_argument("--prune-order", type=int, default=0, choices=[0, 1],
                     help="row order of pruned radius queries with two or more references: 0 = buckets of the first "
                          "reference's distance sorted by the second's (the default), 1 = the first reference alone")
-    ap.add_argument("--prune-w", type=float, default=2.0, help="bucket width of order 0, in units of R")
+    ap.add_argument("--prune-w", type=float, default=1.0, help="bucket width of order 0, in units of R")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (a reference launch for hardware byte counters)")
     args = ap.parse_args()

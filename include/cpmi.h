@@ -172,6 +172,19 @@ int cpmi_points(cpmi_ctx *ctx, const void *pts, int dtype, int64_t n, int64_t d,
                 int precision, double R2, void *stream, cpmi_pair *best,
                 int64_t *pairs, double *d2, int64_t cap, int64_t *count_out);
 
+/* Neighbour lists N(i) of a radius search (Section 3.5: MPR-FRNNS outputs,
+ * for every point i, the other points within R) as compressed rows. pairs:
+ * device int64 [m][2], distinct pairs (i, j) with 0 <= i < j < n, in any
+ * order (as cpmi_frnn, cpmi_points and cpmi_motif return them); row_ptr:
+ * device int64 [n + 1]; cols: device int64 [2m]. The neighbours of point v
+ * are cols[row_ptr[v] .. row_ptr[v + 1]), ascending; every pair appears under
+ * both of its points. Buffers are the caller's; the library's workspace grows
+ * by about 32 (m + n) bytes. Synchronises `stream`. Errors: ERR_ARG (n < 1,
+ * n >= 2^31, m < 0, m >= 2^31, a NULL buffer that is needed, or a pair outside
+ * 0 <= i < j < n: row_ptr and cols are then unspecified), ERR_HIP. */
+int cpmi_pairs_to_csr(cpmi_ctx *ctx, const int64_t *pairs, int64_t m, int64_t n, int64_t *row_ptr, int64_t *cols,
+                      void *stream);
+
 /* Motif of a series (Section 3: the two closest l-mers of T). series: device
  * float32 [len]; windows i = 0..len-ell are z-normalised; pairs with
  * j - i < excl are excluded (excl <= 0 means excl = ell). best: host (may be

@@ -131,7 +131,7 @@ int64_t cpmi_dbg_pruned_tiles_gpu(cpmi_ctx *ctx, int64_t n, int tile, int q, con
  * order 0 (default) sorts the rows by buckets of width w * R of their
  * distance to the first reference and by their distance to the second within
  * a bucket; order 1 by the first reference alone (as closest-pair queries
- * always do). w > 0 (default 2). Returns CPMI_OK or ERR_ARG. */
+ * always do). w > 0 (default 1). Returns CPMI_OK or ERR_ARG. */
 int cpmi_dbg_set_prune_order(cpmi_ctx *ctx, int order, double w);
 
 /* Host only: the tuning decisions of a context with `ncu` compute units

@@ -170,6 +170,27 @@ def frnn(X: np.ndarray, R2: float, excl: int = 1, lanes: bool = False):
         cap = int(cnt)
 
 
+def neighbour_lists(pairs: np.ndarray, n: int):
+    """Section 3.5's output form: N(i), the other points within the radius,
+    for every point i, from the pair list (i, j), i < j, of frnn: j is added
+    to N(i) and i to N(j), each list ascending. Returned as compressed rows
+    (row_ptr int64 [n + 1], cols int64 [2m]). Plain loops over the pairs."""
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    lists = [[] for _ in range(n)]
+    for i, j in pairs.tolist():
+        if not 0 <= i < j < n:
+            raise ValueError(f"pair ({i}, {j}) outside 0 <= i < j < {n}")
+        lists[i].append(j)
+        lists[j].append(i)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    cols = []
+    for v in range(n):
+        lists[v].sort()
+        cols.extend(lists[v])
+        row_ptr[v + 1] = row_ptr[v] + len(lists[v])
+    return row_ptr, np.array(cols, dtype=np.int64)
+
+
 def block_d2(X: np.ndarray, i0: int, ni: int, j0: int, nj: int) -> np.ndarray:
     """Canonical d2 of rows i0..i0+ni-1 against rows j0..j0+nj-1: float64
     [ni, nj] (int8 rows: exact integers as float64)."""

@@ -102,6 +102,7 @@ def _load():
     L.cpmi_dbg_mfma_peak.restype = dbl
     L.cpmi_dbg_mfma_peak.argtypes = [i32, i32, i32, C.POINTER(dbl)]
     L.cpmi_dbg_znorm.argtypes = [vp, vp, i64, i64, i32, vp, vp, vp]
+    L.cpmi_pairs_to_csr.argtypes = [vp, vp, i64, i64, vp, vp, vp]
     L.cpmi_dbg_pruned_tiles_gpu.restype = i64
     L.cpmi_dbg_pruned_tiles_gpu.argtypes = [vp, i64, i32, i32, vp, vp, dbl, i64, i32, vp, i64, C.POINTER(i64),
                                             C.POINTER(i64), vp]
@@ -454,6 +455,22 @@ class Context:
             bounds.ctypes.data_as(C.c_void_p), C.byref(ratio), _stream_ptr(stream)))
         return dump, d2, bounds, float(ratio.value)
 
+    def pairs_to_csr(self, pairs, n: int, stream=None):
+        """Neighbour lists N(i) (Section 3.5) of a radius search's pairs
+        (device int64 [m, 2], i < j) as compressed rows (cpmi_pairs_to_csr):
+        returns (row_ptr [n + 1], cols [2m]), device int64; the neighbours of v
+        are cols[row_ptr[v]:row_ptr[v + 1]], ascending."""
+        import torch
+        if pairs.dtype != torch.int64 or pairs.dim() != 2 or pairs.shape[1] != 2 or not pairs.is_contiguous():
+            raise ValueError("pairs must be a contiguous int64 [m, 2] tensor")
+        m = pairs.shape[0]
+        row_ptr = torch.empty(int(n) + 1, dtype=torch.int64, device=pairs.device)
+        cols = torch.empty(max(2 * m, 1), dtype=torch.int64, device=pairs.device)
+        self._check(_lib.cpmi_pairs_to_csr(self._h, C.c_void_p(pairs.data_ptr()) if m else None, m, int(n),
+                                           C.c_void_p(row_ptr.data_ptr()), C.c_void_p(cols.data_ptr()),
+                                           _stream_ptr(stream)))
+        return row_ptr, cols[:2 * m]
+
     def dbg_pruned_tiles_gpu(self, n: int, tile: int, lo, hi, T: float, excl: int = 1, permuted: bool = False,
                              stream=None):
         """cpmi_dbg_pruned_tiles_gpu: the pruned tile list built on the device
@@ -472,7 +489,7 @@ class Context:
             self._check(int(cnt))
         return out[:cnt].copy(), nf.value, npr.value
 
-    def dbg_set_prune_order(self, order: int, w: float = 2.0):
+    def dbg_set_prune_order(self, order: int, w: float = 1.0):
         """Row order of pruned radius searches (cpmi_dbg_set_prune_order): 0 =
         two references (buckets of width w R), 1 = the first reference only."""
         self._check(_lib.cpmi_dbg_set_prune_order(self._h, int(order), float(w)))

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcpmi.so")
-SOURCES = ["cpmi_host.cpp", "prep.hip", "screen.hip", "screen256.hip", "verify.hip", "mpr.hip", "encode.hip", "lightbulb.hip"]
+SOURCES = ["cpmi_host.cpp", "prep.hip", "screen.hip", "screen256.hip", "verify.hip", "mpr.hip", "encode.hip", "lightbulb.hip", "csr.hip"]
 ARCH = "gfx950"
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", "-Wall",

@@ -148,12 +148,14 @@ struct cpmi_ctx {
     // the pruned tile list built on the device: entries, per-segment counts
     // and their scan, scan scratch, and its four totals (device; pinned copy)
     DevBuf mtl, mseg, mscan, mout4;
+    // neighbour lists (cpmi_pairs_to_csr): keys, counts, offsets; sort scratch
+    DevBuf csrW, csrT;
     int64_t *plist = nullptr;
     // row order for radius queries with q >= 2: 0 = two references (buckets of
     // the first reference's distance, width prune_w times R, sorted by the
     // second's), 1 = the first reference alone
     int prune_order = 0;
-    double prune_w = 2.0;
+    double prune_w = 1.0;
     // string problems: encoded int8 rows and the encoder's flag word
     DevBuf mZ, mflag;
     // light-bulb bucketing: keys and rows (in, out), sort scratch, columns,
@@ -1285,7 +1287,7 @@ int cpmi_destroy(cpmi_ctx *c)
                       &c->w.sel,     &c->w.candR, &c->w.candU, &c->w.cand_d2, &c->w.keys, &c->w.vals, &c->w.cnt, &c->w.ubits,
                       &c->w.res,     &c->mD,    &c->mperm, &c->miperm, &c->mlo, &c->mhi, &c->mrefs, &c->msort, &c->w.mrowstat,
                       &c->mZ,      &c->mflag, &c->lbA, &c->lbT, &c->lbC, &c->lbP, &c->lbK, &c->mtl, &c->mseg,
-                      &c->mscan,   &c->mout4};
+                      &c->mscan,   &c->mout4, &c->csrW, &c->csrT};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
     if (c->pinned) hipHostFree(c->pinned);
@@ -1300,6 +1302,30 @@ int cpmi_destroy(cpmi_ctx *c)
 }
 
 const char *cpmi_last_error(cpmi_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int cpmi_pairs_to_csr(cpmi_ctx *c, const int64_t *pairs, int64_t m, int64_t n, int64_t *row_ptr, int64_t *cols,
+                      void *stream)
+{
+    if (!c) return CPMI_ERR_ARG;
+    if (n < 1 || n >= ((int64_t)1 << 31) || m < 0 || m >= ((int64_t)1 << 31) || !row_ptr ||
+        (m > 0 && (!pairs || !cols)))
+        return fail(c, CPMI_ERR_ARG, "pairs_to_csr: bad arguments (n %lld, m %lld)", (long long)n, (long long)m);
+    hipSetDevice(c->device);
+    const hipStream_t st = (hipStream_t)stream;
+    size_t sort_bytes = 0;
+    const size_t wb = csr_scratch_bytes(m, n, &sort_bytes);
+    int rc;
+    if ((rc = ensure(c, c->csrW, wb))) return rc;
+    if ((rc = ensure(c, c->csrT, sort_bytes))) return rc;
+    unsigned int *bad = (unsigned int *)((char *)c->csrW.p + (wb - 256));
+    HIPCHK(c, launch_pairs_to_csr(pairs, m, n, row_ptr, cols, c->csrW.p, c->csrT.p, sort_bytes, bad, st));
+    if ((rc = ensure_pinned(c, 4))) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->pinned, bad, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (*(unsigned int *)c->pinned)
+        return fail(c, CPMI_ERR_ARG, "pairs_to_csr: a pair outside 0 <= i < j < %lld", (long long)n);
+    return CPMI_OK;
+}
 
 int cpmi_last_stats(cpmi_ctx *c, cpmi_stats *out)
 {

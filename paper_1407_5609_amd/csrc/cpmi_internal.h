@@ -278,6 +278,11 @@ void launch_perm_finish(int32_t *perm, int32_t *iperm, int64_t n, int64_t npad, 
 hipError_t sort_ref_order2(void *temp, size_t *temp_bytes, const double *D0, const double *D1, double w,
                            double *keys_out, int32_t *idx, int32_t *perm, int64_t n, hipStream_t st);
 int64_t prune_segments(int64_t nT, int64_t G);
+// neighbour lists from a pair list (csr.hip): device scratch of the returned
+// size (8-byte aligned) plus sort_bytes for the library sorts and scans
+size_t csr_scratch_bytes(int64_t m, int64_t n, size_t *sort_bytes);
+hipError_t launch_pairs_to_csr(const int64_t *pairs, int64_t m, int64_t n, int64_t *row_ptr, int64_t *cols,
+                               void *scratch, void *sort_tmp, size_t sort_bytes, unsigned int *bad, hipStream_t st);
 // The pruned tile list of one problem on the device (temp == nullptr: only
 // sets *temp_bytes). cnt, off: prune_segments(nT, G) words each; out:
 // nT (nT + 1) / 2 + 8 entries; out4 (device): entries, full slots, full

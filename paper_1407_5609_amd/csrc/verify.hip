@@ -41,11 +41,18 @@ __device__ __forceinline__ double tile_bound_of(const Prob &P, int64_t I, int64_
 // Each wave takes 64 consecutive list entries per step; when they all belong
 // to one problem (always for a single problem, and inside each problem's run
 // of a batched list) the wave reduces in registers and one lane keeps a
-// running minimum, so the global atomic is hit once per wave and problem.
-__global__ void reduce_U_kernel(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min,
-                                int prec, unsigned long long *Ubits)
+// running minimum. At the end the work-group's waves merge their minima per
+// problem in LDS, so the global atomic is hit about once per work-group and
+// problem. Work-groups of 1024 threads, a few steps per wave: enough waves to
+// cover the list in a few steps without many atomics on one address.
+constexpr int RU_THREADS = 1024;
+__global__ __launch_bounds__(RU_THREADS) void reduce_U_kernel(const Prob *probs, const uint64_t *tiles,
+                                                              int64_t ntiles, const uint32_t *tile_min, int prec,
+                                                              unsigned long long *Ubits)
 {
-    const int lane = threadIdx.x & 63;
+    __shared__ uint32_t wp[RU_THREADS / 64];
+    __shared__ unsigned long long wv[RU_THREADS / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t wid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
     uint32_t cur_p = 0xffffffffu;
@@ -94,7 +101,27 @@ __global__ void reduce_U_kernel(const Prob *probs, const uint64_t *tiles, int64_
             atomicMin(&Ubits[p], ub_bits);
         }
     }
-    if (lane == 0 && cur_p != 0xffffffffu && cur != ~0ull) atomicMin(&Ubits[cur_p], cur);
+    if (lane == 0) {
+        wp[wave] = cur != ~0ull ? cur_p : 0xffffffffu;
+        wv[wave] = cur;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // the waves' last problems, merged where neighbours share one
+        uint32_t p = 0xffffffffu;
+        unsigned long long v = ~0ull;
+        for (int w = 0; w < RU_THREADS / 64; ++w) {
+            if (wp[w] == 0xffffffffu) continue;
+            if (wp[w] != p) {
+                if (p != 0xffffffffu) atomicMin(&Ubits[p], v);
+                p = wp[w];
+                v = wv[w];
+            } else if (wv[w] < v) {
+                v = wv[w];
+            }
+        }
+        if (p != 0xffffffffu) atomicMin(&Ubits[p], v);
+    }
 }
 
 // The selected tiles twice: appended to sel (any order), and in place of the
@@ -138,10 +165,10 @@ static unsigned grid_of(int64_t n)
 void launch_reduce_U(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min, int prec,
                      unsigned long long *Ubits, hipStream_t st)
 {
-    int64_t g = (ntiles + 256 * 16 - 1) / (256 * 16);   // ~16 steps per wave
-    g = g < 1 ? 1 : (g > 2048 ? 2048 : g);
-    hipLaunchKernelGGL(reduce_U_kernel, dim3((unsigned)g), dim3(256), 0, st, probs, tiles, ntiles, tile_min, prec,
-                       Ubits);
+    int64_t g = (ntiles + RU_THREADS * 2 - 1) / (RU_THREADS * 2);   // about 2 steps per wave
+    g = g < 1 ? 1 : (g > 1024 ? 1024 : g);
+    hipLaunchKernelGGL(reduce_U_kernel, dim3((unsigned)g), dim3(RU_THREADS), 0, st, probs, tiles, ntiles, tile_min,
+                       prec, Ubits);
 }
 
 void launch_select(const Prob *probs, const uint64_t *tiles, int64_t ntiles, const uint32_t *tile_min, int prec,

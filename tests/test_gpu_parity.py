@@ -153,6 +153,45 @@ def test_points_strided_rows(ctx, torch_dev, prec):
     _check_frnn(fr, oracle.frnn(Xc, 70.0))
 
 
+@pytest.mark.parametrize("n,d,R2", [(1, 3, 1.0), (2, 3, 0.0), (700, 6, 3.0), (5000, 8, 6.0)])
+def test_neighbour_lists_match_oracle(ctx, torch_dev, n, d, R2):
+    """Section 3.5's N(i) for every point: the radius pairs of the GPU search
+    turned into compressed rows on the device equal the oracle's lists built
+    from its own pairs (row pointers and columns bit for bit), also from the
+    pairs in a shuffled order; isolated points have empty rows."""
+    import torch
+    rng = np.random.default_rng(n + d)
+    X = rng.normal(0, 1, (max(n, 2), d)).astype(np.float32)
+    if n >= 2:
+        p, _ = ctx.frnn(_dev(X, torch_dev), R2, precision="bf16")
+        want_pairs, _ = oracle.frnn(X, R2)
+    else:
+        p = torch.zeros((0, 2), dtype=torch.int64, device=torch_dev)
+        want_pairs = np.zeros((0, 2), dtype=np.int64)
+    want_rp, want_cols = oracle.neighbour_lists(want_pairs, n)
+    rp, cols = ctx.pairs_to_csr(p, n)
+    assert np.array_equal(rp.cpu().numpy(), want_rp)
+    assert np.array_equal(cols.cpu().numpy(), want_cols)
+    if p.shape[0] > 1:
+        perm = torch.from_numpy(rng.permutation(p.shape[0])).to(torch_dev)
+        rp2, cols2 = ctx.pairs_to_csr(p[perm].contiguous(), n)
+        assert torch.equal(rp2, rp) and torch.equal(cols2, cols)
+
+
+def test_neighbour_lists_refuse_bad_pairs(ctx, torch_dev):
+    import torch
+    import paper_1407_5609_amd as cp
+    for bad in ([[0, 1], [2, 2]], [[0, 1], [3, 1]], [[-1, 2]], [[0, 5]]):
+        t = torch.tensor(bad, dtype=torch.int64, device=torch_dev)
+        with pytest.raises(cp.CpmiError) as e:
+            ctx.pairs_to_csr(t, 5)
+        assert e.value.code == cp.ERR_ARG
+    with pytest.raises(cp.CpmiError):
+        ctx.pairs_to_csr(torch.zeros((0, 2), dtype=torch.int64, device=torch_dev), 0)
+    rp, cols = ctx.pairs_to_csr(torch.tensor([[1, 3]], dtype=torch.int64, device=torch_dev), 5)
+    assert rp.tolist() == [0, 0, 1, 1, 2, 2] and cols.tolist() == [3, 1]
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_exact_ties_go_to_lexicographic_minimum(ctx, torch_dev, tile, prec):
     rng = np.random.default_rng(31)

@@ -680,3 +680,31 @@ def test_lanes_radius_list_equals_the_plain_loop(case):
         a = oracle.frnn(X, R2, excl)
         b = oracle.frnn(X, R2, excl, lanes=True)
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_neighbour_lists_are_the_other_points_within_the_radius():
+    """Section 3.5's output N(i): from the radius pairs, every point's list
+    equals the brute-force set {j != i : d2(i, j) <= R2} of scipy's full
+    distance matrix (margin checked), ascending; the lists are symmetric and
+    hold 2m entries; isolated points have empty rows; an empty pair list gives
+    empty rows; a pair outside 0 <= i < j < n is refused."""
+    rng = np.random.default_rng(17)
+    X = rng.normal(0, 1, (300, 4)).astype(np.float32)
+    D = ssd.squareform(ssd.pdist(X.astype(np.float64), "sqeuclidean"))
+    for R2 in (0.5, 2.0):
+        off = D[~np.eye(300, dtype=bool)]
+        assert np.min(np.abs(off - R2)) / R2 > 1e-10
+        pairs, _ = oracle.frnn(X, R2)
+        row_ptr, cols = oracle.neighbour_lists(pairs, 300)
+        assert row_ptr[0] == 0 and row_ptr[-1] == 2 * len(pairs) == len(cols)
+        for v in range(300):
+            want = [j for j in range(300) if j != v and D[v, j] <= R2]
+            got = cols[row_ptr[v]:row_ptr[v + 1]].tolist()
+            assert got == want, v
+        edges = {(v, int(u)) for v in range(300) for u in cols[row_ptr[v]:row_ptr[v + 1]]}
+        assert all((u, v) in edges for v, u in edges)
+    rp, c = oracle.neighbour_lists(np.zeros((0, 2), dtype=np.int64), 5)
+    assert rp.tolist() == [0] * 6 and len(c) == 0
+    for bad in ((2, 2), (3, 1), (-1, 2), (0, 5)):
+        with pytest.raises(ValueError):
+            oracle.neighbour_lists(np.array([bad]), 5)
