@@ -504,6 +504,10 @@ def main():
                      "kernel": kernel, "avg_launch_ms": dur_ms, "work_per_launch": work},
         "exact_match": bool(exact),
         "screen_err_over_bound": st.max_err_over_bound,
+        # the last step's second pass: tiles screened again, candidates it emitted (the radius verifier
+        # drops first those that the bound of their own two rows puts outside R)
+        "pass2": {"tiles": st.tiles_rescreened, "of_tiles": st.tiles_total,
+                  "candidates": st.cpp_candidates + st.frnn_candidates},
     }
     if wl.roofline and not args.no_peak_probe:
         # context: what a pure multiply-accumulate kernel in the same instructions sustains on this

@@ -648,6 +648,14 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             q.perm = h.perm;
             q.split = (int32_t)h.split;
             q.na = h.na;
+            // each row's own bound terms: for the radius verifier's per-pair
+            // bound (one problem with a radius, FP32 / BF16), and for windows
+            // in reference order (reduced per block)
+            q.rowstat = nullptr;
+            if (np == 1 && ((h.r2 >= 0.0 && prec != P_I8) || h.iperm)) {
+                if ((rc = get(W.mrowstat, (size_t)h.npad * sizeof(float4)))) return rc;
+                q.rowstat = (const float4 *)W.mrowstat.p;
+            }
             if (h.motif) {
                 q.mu = (const double *)((char *)W.musg.p + h.mu_off);
                 q.sigma = (const double *)((char *)W.musg.p + mu_b + h.mu_off);
@@ -668,10 +676,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
                 j.flags = &((ResDev *)W.res.p)[p].flags;
                 j.kpad = h.kpad;
                 j.iperm = h.iperm;
-                if (h.iperm) {
-                    if ((rc = get(W.mrowstat, (size_t)h.npad * sizeof(float4)))) return rc;
-                    j.rowstat = (float4 *)W.mrowstat.p;
-                }
+                j.rowstat = (float4 *)q.rowstat;
                 jobs.push_back(j);
             }
         }
@@ -695,14 +700,14 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
                 launch_fill_u32((uint32_t *)W.bmax.p, 0u, (int64_t)(bm_b / 4), st);
                 launch_prep_series((const SeriesJob *)W.jobs.p, (int64_t)jobs.size(), blk, prec, tile, st);
                 // windows in reference order (one series): block maxima from the per-row terms
-                if (jobs.size() == 1 && jobs[0].rowstat)
+                if (jobs.size() == 1 && jobs[0].iperm)
                     launch_block_max(jobs[0].rowstat, hp[0].npad, tile, (float4 *)P[0].bmax, st);
             } else {
                 launch_fill_u32((uint32_t *)W.bmax.p, 0u, (int64_t)(bm_b / 4), st);
                 const HostProb &h = hp[0];
                 launch_prep_points(h.src, h.src_i8 ? CPMI_I8 : CPMI_F32, h.n, h.d, h.ld, prec, P[0].xs ? (void *)P[0].xs : nullptr,
                                    h.kpad, h.npad, (void *)P[0].shat, (float4 *)P[0].bmax, tile, &dres[0].flags,
-                                   h.perm, (uint2 *)P[0].fold, st);
+                                   h.perm, (uint2 *)P[0].fold, (float4 *)P[0].rowstat, st);
             }
             ScreenArgs a;
             memset(&a, 0, sizeof a);

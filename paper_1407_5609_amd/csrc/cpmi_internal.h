@@ -49,6 +49,8 @@ struct Prob {
     const int32_t *perm;   // screen row r holds source row perm[r] (reference-point order), or null
     int64_t na;            // two-set problem: rows of the first set
     const uint2 *fold;     // BF16 screens: per row, fold_words(s^) (the folded row scalar), else null
+    const float4 *rowstat; // radius searches (FP32 / BF16 screens): per screen row, that row's own
+                           // (s^, a, at, r) of bound.h, else null
 };
 
 // The folded row scalar of the BF16 256-row screen: c = -s^/4 split into three
@@ -178,7 +180,8 @@ struct SeriesJob {
     int32_t pad0;
     const int32_t *iperm;  // screen row of window w (reference order), or null for w itself
     uint2 *fold;           // BF16: per row fold_words(s^), else null
-    float4 *rowstat;       // with iperm: per-row maxima terms, reduced per block by launch_block_max
+    float4 *rowstat;       // per-row bound terms (null: not written); with iperm they are also what
+                           // launch_block_max reduces per block
 };
 
 // ---- launchers (defined in the .hip files) --------------------------------
@@ -190,10 +193,11 @@ void launch_reset_res(ResDev *r, int64_t n, hipStream_t st);
 void launch_calib_copy(const void *src, void *dst, int64_t n16, hipStream_t st);
 
 // Row preparation of points (float32 or int8): screen operand, row scalars,
-// per-block maxima (bmax must be zero on entry), flags.
+// per-block maxima (bmax must be zero on entry), flags, and (float input,
+// rowstat not null) each row's own bound terms.
 void launch_prep_points(const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, int prec, void *xs,
                         int32_t kpad, int64_t npad, void *shat, float4 *bmax, int tile, unsigned int *flags,
-                        const int32_t *perm, uint2 *fold, hipStream_t st);
+                        const int32_t *perm, uint2 *fold, float4 *rowstat, hipStream_t st);
 
 // Window builder of many series: canonical mean/sigma, z-normalised screen
 // operand, row scalars, block maxima (zero on entry), flags.

@@ -155,7 +155,7 @@ template <int PREC, bool INT8_IN>
 __global__ __launch_bounds__(256) void prep_points_kernel(const void *pts, int64_t n, int64_t d, int64_t ld,
                                                           void *xs, int32_t kpad, int64_t npad, void *shat,
                                                           float4 *bmax, int tile, unsigned int *flags,
-                                                          const int32_t *perm, uint2 *fold)
+                                                          const int32_t *perm, uint2 *fold, float4 *rowstat)
 {
     __shared__ float4 sh_bm[4];
     __shared__ unsigned int sh_f[4];
@@ -249,10 +249,12 @@ __global__ __launch_bounds__(256) void prep_points_kernel(const void *pts, int64
             if (lane == 0) {
                 ((float *)shat)[row] = (float)s;
                 if (fold) fold[row] = fold_words((float)s);
-                bm.x = fmaxf(bm.x, f32_up(s));
-                bm.y = fmaxf(bm.y, up_f32(sqrt(s)));
-                bm.z = fmaxf(bm.z, up_f32(sqrt(t2)));
-                bm.w = fmaxf(bm.w, up_f32(sqrt(r2)));
+                const float4 v = make_float4(f32_up(s), up_f32(sqrt(s)), up_f32(sqrt(t2)), up_f32(sqrt(r2)));
+                if (rowstat) rowstat[row] = v;
+                bm.x = fmaxf(bm.x, v.x);
+                bm.y = fmaxf(bm.y, v.y);
+                bm.z = fmaxf(bm.z, v.z);
+                bm.w = fmaxf(bm.w, v.w);
                 if (anybad) fl |= F_NONFINITE;
                 if (!(s < 0x1p100)) fl |= F_RANGE;
             }
@@ -286,18 +288,18 @@ __global__ __launch_bounds__(256) void prep_points_kernel(const void *pts, int64
 
 void launch_prep_points(const void *pts, int dtype, int64_t n, int64_t d, int64_t ld, int prec, void *xs,
                         int32_t kpad, int64_t npad, void *shat, float4 *bmax, int tile, unsigned int *flags,
-                        const int32_t *perm, uint2 *fold, hipStream_t st)
+                        const int32_t *perm, uint2 *fold, float4 *rowstat, hipStream_t st)
 {
     dim3 g((unsigned)(npad / PREP_ROWS)), b(256);
     if (dtype == 1)
         hipLaunchKernelGGL((prep_points_kernel<P_I8, true>), g, b, 0, st, pts, n, d, ld, xs, kpad, npad, shat, bmax,
-                           tile, flags, perm, nullptr);
+                           tile, flags, perm, nullptr, nullptr);
     else if (prec == P_BF16)
         hipLaunchKernelGGL((prep_points_kernel<P_BF16, false>), g, b, 0, st, pts, n, d, ld, xs, kpad, npad, shat,
-                           bmax, tile, flags, perm, fold);
+                           bmax, tile, flags, perm, fold, rowstat);
     else
         hipLaunchKernelGGL((prep_points_kernel<P_F32, false>), g, b, 0, st, pts, n, d, ld, xs, kpad, npad, shat,
-                           bmax, tile, flags, perm, nullptr);
+                           bmax, tile, flags, perm, nullptr, rowstat);
 }
 
 // ---------------------------------------------------------------------------
@@ -474,12 +476,10 @@ __global__ __launch_bounds__(256) void prep_series_kernel(const SeriesJob *jobs,
     // 2^-50 ||x|| for the reciprocal's rounding (the norms carry the 2^-40
     // widening of up_f32, which covers it)
     float4 v = make_float4(f32_up(s), up_f32(sqrt(s)), up_f32(sqrt(t2)), up_f32(sqrt(r2) + 0x1p-50 * sqrt(s)));
-    if (J.iperm) {
-        // windows in reference order land in any tile block: per-row terms,
-        // reduced per block afterwards (launch_block_max)
-        J.rowstat[row] = v;
-        return;
-    }
+    if (J.rowstat) J.rowstat[row] = v;
+    // windows in reference order land in any tile block: their per-row terms
+    // are reduced per block afterwards (launch_block_max)
+    if (J.iperm) return;
     // windows in position order: the block's SERIES_WPB rows lie in one tile
     // block; one set of atomics per work-group (per-window atomics on the few
     // block addresses in flight serialise)

@@ -804,6 +804,17 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                     if (pred && base + rank < cap) cand[base + rank] = cd;
                 }
             };
+            // Folded screen values: -2 v <= thr holds only where v >= -thr / 2,
+            // so a block whose maximum accumulator stays below that in every
+            // lane is passed over after one maximum (the threshold of that
+            // test is lowered by a margin, so it never passes over a hit).
+            S hthr = SINF;
+            if constexpr (FOLD) {
+                if (thr > -SINF) {
+                    hthr = -0.5f * thr;
+                    hthr -= fabsf(hthr) * 0x1p-20f + 0x1p-126f;
+                }
+            }
             // The blocks one after another in a loop that is not unrolled
             // (its accumulators picked by a switch): unrolled over all 256
             // elements, the emission outgrows the instruction cache and the
@@ -827,6 +838,12 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
                 int32_t ojb = 0;
                 if constexpr (!FOLD) sjb = sh_t[T256 + gj - (int32_t)(J * T256)];
                 if (pexcl) ojb = sh_ot[T256 + gj - (int32_t)(J * T256)];
+                if constexpr (FOLD) {
+                    S mx = v[0];
+#pragma unroll
+                    for (int r = 1; r < 16; ++r) mx = fmaxf(mx, v[r]);
+                    if (!__any(mx >= hthr)) continue;
+                }
                 S dv[16];
                 bool near_any = false;
 #pragma unroll
@@ -866,17 +883,20 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
             // each wave stores the minimum of its quarter of the tile
             best = wmin(best);
             if (fresh_lane() == 0) args.tile_min[4 * t + wave] = __builtin_bit_cast(uint32_t, best);
-            // Masked tiles read window positions, and int8 tiles their row
-            // scalars, from LDS at uneven times across the waves; the next
-            // tile's top prefetches the tile after it into this same half.
-            // (Folded full tiles read nothing from LDS here.)
-            if constexpr (MASKED || !FOLD) __builtin_amdgcn_s_barrier();
+            // Int8 tiles read their row scalars, and windows in reference
+            // order their positions, from LDS at uneven times across the
+            // waves; the next tile's top prefetches the tile after it into
+            // this same half, so no wave may start it before every wave is
+            // done here. (Folded tiles of rows in position order read
+            // nothing from LDS after the last slice.)
+            if constexpr (!FOLD) __builtin_amdgcn_s_barrier();
+            else if (pexcl) __builtin_amdgcn_s_barrier();
         } else {
-            // The emission reads this tile's row scalars and positions from
-            // LDS at uneven times across the waves; the next tile's top
-            // prefetches the tile after it into this same half. No wave may
-            // start it before every wave is done here.
-            __builtin_amdgcn_s_barrier();
+            // The same for the emission (and the dump): its reads of row
+            // scalars (int8) and window positions (reference order) must be
+            // done in every wave before the next tile's prefetch.
+            if constexpr (!FOLD || (MODE & M_DUMP)) __builtin_amdgcn_s_barrier();
+            else if (pexcl) __builtin_amdgcn_s_barrier();
         }
         t = tn;
     }

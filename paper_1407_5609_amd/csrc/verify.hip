@@ -402,7 +402,20 @@ __global__ __launch_bounds__(256) void verify_frnn_kernel(const Prob *probs, con
         uint32_t in = 0;
         if (c < m) {
             const Cand cd = cand[c];
-            if (cd.p != 0xffffffffu) {   // not an unused slot of a screen wave's slab
+            // not an unused slot of a screen wave's slab, nor a pair that the
+            // bound of its own two rows (tighter than the tile's, which
+            // emitted it) puts outside the radius: |D~ - d2| <= E_ij, so
+            // d2 <= R2 needs D~ - E_ij <= R2 (with the selection's margin)
+            bool live = cd.p != 0xffffffffu;
+            if (live && probs[cd.p].rowstat) {
+                const Prob &P = probs[cd.p];
+                const double E = tile_bound(P.rowstat[cd.i], P.rowstat[cd.j], P.kpad, P.d, prec, P.form);
+                const double dt = (double)cd.dt;
+                double lb = dt - E;
+                lb -= add_margin(dt, E);
+                live = lb <= P.r2;
+            }
+            if (live) {
                 const Prob &P = probs[cd.p];
                 int64_t a, b;
                 cand_rows(P, cd, a, b);
