@@ -764,16 +764,28 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             b.U = (const double *)ubits;
             launch_screen(prec, tile, M_EMIT, true, b,
                           std::min<int64_t>(std::max<int64_t>(ntiles, 1), tile == 256 ? c->ncu : 2048), st);
+            // windows: terms with two divisions each, usually few candidates
+            const bool windows = hp[0].motif != 0;
             if (want_cpp) {
-                launch_verify_cpp(dprobs, (const Cand *)W.candU.p, dcnt + C_U, capU, prec, tile,
-                                  (double *)W.cand_d2.p, dres, st);
+                if (windows)
+                    launch_verify_windows(false, dprobs, (const Cand *)W.candU.p, dcnt + C_U, capU, prec, tile,
+                                          (double *)W.cand_d2.p, nullptr, nullptr, nullptr, 0, dres, st);
+                else
+                    launch_verify_cpp(dprobs, (const Cand *)W.candU.p, dcnt + C_U, capU, prec, tile,
+                                      (double *)W.cand_d2.p, dres, st);
                 launch_pick_cpp(dprobs, (const Cand *)W.candU.p, dcnt + C_U, capU, (const double *)W.cand_d2.p,
                                 dres, st);
             }
-            if (want_frnn)
-                launch_verify_frnn(dprobs, (const Cand *)W.candR.p, dcnt + C_R, capR, prec, tile,
-                                   (uint64_t *)W.keys.p, (double *)W.vals.p, dcnt + C_OUT, count_mode ? 0 : capOut,
-                                   dres, st);
+            if (want_frnn) {
+                if (windows)
+                    launch_verify_windows(true, dprobs, (const Cand *)W.candR.p, dcnt + C_R, capR, prec, tile,
+                                          nullptr, (uint64_t *)W.keys.p, (double *)W.vals.p, dcnt + C_OUT,
+                                          count_mode ? 0 : capOut, dres, st);
+                else
+                    launch_verify_frnn(dprobs, (const Cand *)W.candR.p, dcnt + C_R, capR, prec, tile,
+                                       (uint64_t *)W.keys.p, (double *)W.vals.p, dcnt + C_OUT,
+                                       count_mode ? 0 : capOut, dres, st);
+            }
         };
 
         HIPCHK(c, hipEventRecord(c->ev0, st));

@@ -229,6 +229,13 @@ void launch_pick_cpp(const Prob *probs, const Cand *cand, const u64c *cnt, uint6
 void launch_verify_frnn(const Prob *probs, const Cand *cand, const u64c *cnt, uint64_t cap, int prec, int tile,
                         uint64_t *keys, double *vals, u64c *out_cnt, uint64_t out_cap, ResDev *res,
                         hipStream_t st);
+// The same verification for windows of series (closest pair: frnn = false,
+// cand_d2 and res as launch_verify_cpp, followed by launch_pick_cpp; radius:
+// frnn = true, keys/vals/out_cnt/out_cap as launch_verify_frnn): 16
+// candidates per work-group, their terms formed by 16 threads each.
+void launch_verify_windows(bool frnn, const Prob *probs, const Cand *cand, const u64c *cnt, uint64_t cap, int prec,
+                           int tile, double *cand_d2, uint64_t *keys, double *vals, u64c *out_cnt, uint64_t out_cap,
+                           ResDev *res, hipStream_t st);
 // Test of the screen bound on the hardware: for every element (row il,
 // column jl) of the m tiles of `tiles` dumped by the M_DUMP screen (rows and
 // columns past the problem's rows skipped), the canonical d2 (verifier

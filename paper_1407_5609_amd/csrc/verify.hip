@@ -454,6 +454,174 @@ __global__ __launch_bounds__(256) void verify_frnn_kernel(const Prob *probs, con
     }
 }
 
+// Windows of a series, few candidates (motifs, pruned searches): each term
+// of the canonical sum needs two FP64 divisions, and the sum is one chain of
+// d dependent additions. A lane per candidate leaves most of the chip idle
+// when there are only thousands of candidates; a wave per candidate spends
+// most of its instructions carrying the chain from lane to lane. Here a
+// work-group takes 16 candidates at a time: for each chunk of 64 terms, the
+// 16 threads of a candidate form 4 terms each into LDS, then one lane per
+// candidate adds the chunk in ascending k (terms past d are exact zeros,
+// which leave the sum as it is). The result is the canonical sum, bit for
+// bit. FRNN (cand_d2 null): pairs within R2 are written as keys and values,
+// candidates that the bound of their own two rows puts outside R2 are
+// dropped first. Closest pair (keys null): d2 per candidate and the least
+// one per problem, as verify_cpp_kernel.
+constexpr int VW_C = 16;  // candidates per work-group and round
+constexpr int VW_K = 64;  // terms per chunk
+
+template <bool FRNN>
+__global__ __launch_bounds__(256) void verify_windows_kernel(const Prob *probs, const Cand *cand, const u64c *cnt,
+                                                             uint64_t cap, int prec, int tile, double *cand_d2,
+                                                             uint64_t *keys, double *vals, u64c *out_cnt,
+                                                             uint64_t out_cap, ResDev *res)
+{
+    __shared__ double sh_t[VW_C][VW_K + 1];
+    __shared__ int32_t sh_live[VW_C];
+    __shared__ int64_t sh_d[VW_C];
+    const int64_t m = min((int64_t)*cnt, (int64_t)cap);
+    const int tid = threadIdx.x, slot = tid >> 4, sub = tid & 15;
+    ErrAcc ea;                       // chain lanes (tid < VW_C)
+    uint32_t bp = 0xffffffffu;       // closest pair: the chain lane's run of one problem
+    unsigned long long bbits = ~0ull;
+    const int64_t ngroups = (m + VW_C - 1) / VW_C;
+    for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        // this thread's candidate (slot), its rows and window statistics
+        const int64_t c = g * VW_C + slot;
+        bool live = c < m;
+        Cand cd{};
+        if (live) {
+            cd = cand[c];
+            live = cd.p != 0xffffffffu;   // not an unused slot of a screen wave's slab
+        }
+        if (FRNN && live && probs[cd.p].rowstat) {
+            const Prob &P = probs[cd.p];
+            const double E = tile_bound(P.rowstat[cd.i], P.rowstat[cd.j], P.kpad, P.d, prec, P.form);
+            const double dt = (double)cd.dt;
+            double lb = dt - E;
+            lb -= add_margin(dt, E);
+            live = lb <= P.r2;
+        }
+        const float *x = nullptr, *y = nullptr;
+        double mi = 0.0, si = 1.0, mj = 0.0, sj = 1.0;
+        int64_t d = 0;
+        bool motif = false;
+        if (live) {
+            const Prob &P = probs[cd.p];
+            int64_t a, b;
+            cand_rows(P, cd, a, b);
+            const float *T = (const float *)P.src;
+            d = P.d;
+            motif = P.motif != 0;
+            if (motif) {
+                x = T + a;
+                y = T + b;
+                mi = P.mu[a], si = P.sigma[a], mj = P.mu[b], sj = P.sigma[b];
+            } else {
+                x = T + a * P.ld;
+                y = T + b * P.ld;
+            }
+        }
+        if (sub == 0) {
+            sh_live[slot] = live;
+            sh_d[slot] = d;
+        }
+        __syncthreads();
+        int64_t dmax = 0;
+#pragma unroll
+        for (int q = 0; q < VW_C; ++q) dmax = max(dmax, sh_d[q]);
+        double acc = 0.0;   // chain lane tid: candidate g * VW_C + tid
+        for (int64_t c0 = 0; c0 < dmax; c0 += VW_K) {
+#pragma unroll
+            for (int v = 0; v < VW_K / 16; ++v) {
+                const int64_t k = c0 + sub + 16 * v;
+                double t = 0.0;
+                if (k < d)
+                    t = motif ? ((double)x[k] - mi) / si - ((double)y[k] - mj) / sj : (double)x[k] - (double)y[k];
+                sh_t[slot][sub + 16 * v] = t;
+            }
+            __syncthreads();
+            if (tid < VW_C) {
+#pragma unroll 16
+                for (int u = 0; u < VW_K; ++u) {
+                    const double tu = sh_t[tid][u];
+                    acc = fma(tu, tu, acc);
+                }
+            }
+            __syncthreads();
+        }
+        if (tid < 64) {
+            // wave 0; its lanes below VW_C hold the sums of the group
+            const int64_t cc = g * VW_C + tid;
+            const bool mine = tid < VW_C && sh_live[tid];
+            Cand ce{};
+            if (mine) ce = cand[cc];
+            const Prob *P = mine ? &probs[ce.p] : nullptr;
+            int64_t a = 0, b = 0;
+            if (mine) {
+                cand_rows(*P, ce, a, b);
+                ea.add(res, ce.p, (double)ce.dt, acc, tile_bound_of(*P, ce.i / tile, ce.j / tile, prec));
+            }
+            if constexpr (FRNN) {
+                const bool in = mine && acc <= P->r2;
+                const uint64_t k = wave_reserve(out_cnt, in);
+                if (in && k < out_cap) {
+                    keys[k] = ((uint64_t)(uint32_t)a << 32) | (uint32_t)b;
+                    vals[k] = acc;
+                }
+            } else if (tid < VW_C && cc < m) {
+                cand_d2[cc] = acc;
+                if (mine) {
+                    if (ce.p != bp) {
+                        if (bp != 0xffffffffu) atomicMin(&res[bp].best_d2, bbits);
+                        bp = ce.p;
+                        bbits = ~0ull;
+                    }
+                    const unsigned long long bits = (unsigned long long)__double_as_longlong(acc);
+                    bbits = bits < bbits ? bits : bbits;   // d2 >= 0: the bits order as the values
+                }
+            }
+        }
+        __syncthreads();   // sh_live, sh_d of the next group
+    }
+    if (tid < 64) {
+        // one problem in every chain lane (or none): merged in the wave first
+        const uint32_t p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)ea.p);
+        if (__all(ea.p == p0 || ea.p == 0xffffffffu)) {
+            float e = ea.err, r = ea.ratio, bd = ea.bound;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                e = fmaxf(e, __shfl_xor(e, o, 64));
+                r = fmaxf(r, __shfl_xor(r, o, 64));
+                bd = fmaxf(bd, __shfl_xor(bd, o, 64));
+            }
+            if (tid == 0 && p0 != 0xffffffffu) {
+                ea.p = p0;
+                ea.err = e;
+                ea.ratio = r;
+                ea.bound = bd;
+                ea.flush(res);
+            }
+        } else {
+            ea.flush(res);
+        }
+        if constexpr (!FRNN) {
+            const uint32_t q0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)bp);
+            if (__all(bp == q0 || bp == 0xffffffffu)) {
+                unsigned long long v = bbits;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    const unsigned long long w = __shfl_xor(v, o, 64);
+                    v = w < v ? w : v;
+                }
+                if (tid == 0 && q0 != 0xffffffffu && v != ~0ull) atomicMin(&res[q0].best_d2, v);
+            } else if (bp != 0xffffffffu) {
+                atomicMin(&res[bp].best_d2, bbits);
+            }
+        }
+    }
+}
+
 // One wave per dumped element (grid-stride over m tiles x tile^2 elements).
 __global__ __launch_bounds__(256) void sample_check_kernel(const Prob *probs, const uint64_t *tiles, int64_t m,
                                                            int tile, const void *dump, int prec, double *d2_out,
@@ -500,6 +668,18 @@ void launch_pick_cpp(const Prob *probs, const Cand *cand, const u64c *cnt, uint6
                      ResDev *res, hipStream_t st)
 {
     hipLaunchKernelGGL(pick_cpp_kernel, dim3(256), dim3(256), 0, st, probs, cand, cnt, cap, cand_d2, res);
+}
+
+void launch_verify_windows(bool frnn, const Prob *probs, const Cand *cand, const u64c *cnt, uint64_t cap, int prec,
+                           int tile, double *cand_d2, uint64_t *keys, double *vals, u64c *out_cnt, uint64_t out_cap,
+                           ResDev *res, hipStream_t st)
+{
+    if (frnn)
+        hipLaunchKernelGGL(verify_windows_kernel<true>, dim3(verify_grid()), dim3(256), 0, st, probs, cand, cnt, cap,
+                           prec, tile, nullptr, keys, vals, out_cnt, out_cap, res);
+    else
+        hipLaunchKernelGGL(verify_windows_kernel<false>, dim3(verify_grid()), dim3(256), 0, st, probs, cand, cnt, cap,
+                           prec, tile, cand_d2, nullptr, nullptr, nullptr, 0, res);
 }
 
 void launch_verify_frnn(const Prob *probs, const Cand *cand, const u64c *cnt, uint64_t cap, int prec, int tile,

@@ -76,3 +76,28 @@ def test_capacity_query_then_full_list(ctx, torch_dev):
     assert cnt == len(wp) > 10_000
     assert np.array_equal(pairs.cpu().numpy(), wp)
     assert np.array_equal(d2.cpu().numpy(), wd)
+
+
+@pytest.mark.parametrize("prec,q", [("bf16", 0), ("f32", 0), ("bf16", 4)])
+def test_window_radius_at_volume(ctx, torch_dev, prec, q):
+    """z-normalised windows (12,000-sample walk, l = 64) with a radius that
+    holds 457,249 pairs: the window verifier takes its candidates 16 to a
+    work-group in many rounds; the motif, the list and every d2 equal the
+    oracle's bit for bit, unpruned and with reference-point pruning."""
+    import workloads as W
+    rng = np.random.default_rng(4711)
+    T = W.random_walk(rng, 12000)
+    ell, R2 = 64, 12.8
+    Xhat, _, _ = oracle.znorm(T, ell)
+    want_best = oracle.closest_pair_lanes(Xhat, ell)
+    wp, wd = oracle.frnn(Xhat, R2, ell, lanes=True)
+    assert len(wp) == 457249
+    t = torch.from_numpy(T).to(torch_dev)
+    ctx.set_pruning(q, 10.0, seed=2)
+    try:
+        best, (p, d) = ctx.motif(t, ell, R2=R2, precision=prec, cap=1 << 20)
+    finally:
+        ctx.set_pruning(0)
+    assert (best.i, best.j, best.d2) == tuple(want_best)
+    assert np.array_equal(p.cpu().numpy(), wp)
+    assert np.array_equal(d.cpu().numpy(), wd)
