@@ -106,6 +106,9 @@ enum { C_R = 0, C_U = 1, C_SEL = 2, C_OUT = 3, C_IN = 4 };
 // search whose candidates exceed it is re-run in the counting form, which
 // gives the exact number of pairs without storing them.
 constexpr uint64_t CAND_MAX = 1ull << 28;
+// Radius lists longer than this are sorted by one radix sort; shorter ones by
+// the bitonic sort (one launch up to 2,048 pairs).
+constexpr int64_t RADIX_SORT_FROM = 1 << 14;
 
 }  // namespace
 
@@ -150,6 +153,8 @@ struct cpmi_ctx {
     DevBuf mtl, mseg, mscan, mout4;
     // neighbour lists (cpmi_pairs_to_csr): keys, counts, offsets; sort scratch
     DevBuf csrW, csrT;
+    // radius lists past RADIX_SORT_FROM pairs: sorted keys and values, sort scratch
+    DevBuf srtK, srtV, srtT;
     int64_t *plist = nullptr;
     // row order for radius queries with q >= 2: 0 = two references (buckets of
     // the first reference's distance, width prune_w times R, sorted by the
@@ -967,8 +972,24 @@ int finish_frnn(cpmi_ctx *c, const RunOut &ro, hipStream_t st, int64_t *pairs, d
             c->graph_key.clear();
         }
     }
-    launch_sort_pairs((uint64_t *)c->w.keys.p, (double *)c->w.vals.p, count, mpad, st);
-    launch_emit_pairs((const uint64_t *)c->w.keys.p, (const double *)c->w.vals.p, count, pairs, d2, st);
+    const uint64_t *sk = (const uint64_t *)c->w.keys.p;
+    const double *sv = (const double *)c->w.vals.p;
+    if ((int64_t)count > RADIX_SORT_FROM) {
+        // long lists: one radix sort, out of place
+        size_t tb = 0;
+        HIPCHK(c, sort_pairs_radix(nullptr, &tb, nullptr, nullptr, nullptr, nullptr, (int64_t)count, st));
+        int rc;
+        if ((rc = ensure(c, c->srtK, (size_t)count * 8))) return rc;
+        if ((rc = ensure(c, c->srtV, (size_t)count * 8))) return rc;
+        if ((rc = ensure(c, c->srtT, std::max<size_t>(tb, 1)))) return rc;
+        HIPCHK(c, sort_pairs_radix(c->srtT.p, &tb, sk, (uint64_t *)c->srtK.p, sv, (double *)c->srtV.p,
+                                   (int64_t)count, st));
+        sk = (const uint64_t *)c->srtK.p;
+        sv = (const double *)c->srtV.p;
+    } else {
+        launch_sort_pairs((uint64_t *)c->w.keys.p, (double *)c->w.vals.p, count, mpad, st);
+    }
+    launch_emit_pairs(sk, sv, count, pairs, d2, st);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(st));
     return CPMI_OK;
@@ -1304,7 +1325,7 @@ int cpmi_destroy(cpmi_ctx *c)
                       &c->w.sel,     &c->w.candR, &c->w.candU, &c->w.cand_d2, &c->w.keys, &c->w.vals, &c->w.cnt, &c->w.ubits,
                       &c->w.res,     &c->mD,    &c->mperm, &c->miperm, &c->mlo, &c->mhi, &c->mrefs, &c->msort, &c->w.mrowstat,
                       &c->mZ,      &c->mflag, &c->lbA, &c->lbT, &c->lbC, &c->lbP, &c->lbK, &c->mtl, &c->mseg,
-                      &c->mscan,   &c->mout4, &c->csrW, &c->csrT};
+                      &c->mscan,   &c->mout4, &c->csrW, &c->csrT, &c->srtK, &c->srtV, &c->srtT};
     for (DevBuf *b : bufs)
         if (b->p) hipFree(b->p);
     if (c->pinned) hipHostFree(c->pinned);

@@ -247,6 +247,10 @@ void launch_sample_check(const Prob *probs, const uint64_t *tiles, int64_t m, in
 // Sort m (key, value) pairs by key; arrays hold mpad >= m entries (mpad a power
 // of two), the tail is overwritten with sentinels.
 void launch_sort_pairs(uint64_t *keys, double *vals, int64_t m, int64_t mpad, hipStream_t st);
+// The same order by one radix sort, out of place (temp == nullptr: only sets
+// *temp_bytes).
+hipError_t sort_pairs_radix(void *temp, size_t *temp_bytes, const uint64_t *keys_in, uint64_t *keys_out,
+                            const double *vals_in, double *vals_out, int64_t m, hipStream_t st);
 // reference-point pruning (mpr.hip)
 void launch_ref_dist(const void *X, int dtype, int64_t n, int64_t d, int64_t ld, const int32_t *refs, int q,
                      double f, double *D, hipStream_t st);

@@ -14,6 +14,8 @@
 //
 // Compiled with -ffp-contract=off so the FP64 sequence matches the canonical
 // definition operation for operation.
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "bound.h"
 #include "cpmi_internal.h"
 
@@ -811,6 +813,15 @@ void launch_sort_pairs(uint64_t *keys, double *vals, int64_t m, int64_t mpad, hi
                 hipLaunchKernelGGL(bitonic_global_kernel, dim3(grid_of(mpad)), dim3(256), 0, st, keys, vals, mpad, k, j);
         }
     }
+}
+
+// Long lists: one rocPRIM radix sort of the (i << 32 | j) keys with the d2
+// values, out of place (temp == nullptr: only sets *temp_bytes).
+hipError_t sort_pairs_radix(void *temp, size_t *temp_bytes, const uint64_t *keys_in, uint64_t *keys_out,
+                            const double *vals_in, double *vals_out, int64_t m, hipStream_t st)
+{
+    return rocprim::radix_sort_pairs(temp, *temp_bytes, keys_in, keys_out, vals_in, vals_out, (unsigned int)m, 0, 64,
+                                     st);
 }
 
 __global__ void emit_pairs_kernel(const uint64_t *keys, const double *vals, int64_t m, int64_t *pairs, double *d2)
