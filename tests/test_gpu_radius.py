@@ -101,3 +101,28 @@ def test_window_radius_at_volume(ctx, torch_dev, prec, q):
     assert (best.i, best.j, best.d2) == tuple(want_best)
     assert np.array_equal(p.cpu().numpy(), wp)
     assert np.array_equal(d.cpu().numpy(), wd)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f32"])
+def test_window_count_beyond_one_list(ctx, torch_dev, prec):
+    """z-normalised windows have d2 = 2l(1 - rho) <= 4l: with R2 above that,
+    every admissible pair of a 40,000-sample walk (l = 16) is within the
+    radius, 798,780,465 of them, more than one call stores. The count from
+    the call with no room for pairs is exact (pairs proved inside by the
+    screen are counted, the band near R2 verified)."""
+    import ctypes as C
+    import paper_1407_5609_amd as cp
+    import workloads as W
+    rng = np.random.default_rng(4712)
+    T = W.random_walk(rng, 40000)
+    ell = 16
+    want = W.valid_pairs_motif(40000, ell, ell)
+    assert want > 2 ** 28
+    t = torch.from_numpy(T).to(torch_dev)
+    cnt = C.c_int64(0)
+    best = cp._CPair()
+    rc = cp._lib.cpmi_motif(ctx._h, C.c_void_p(t.data_ptr()), 40000, ell, 0, cp._prec(prec), 4.0 * ell + 1.0,
+                            cp._stream_ptr(None), C.byref(best), None, None, 0, C.byref(cnt))
+    assert rc == cp.ERR_CAPACITY
+    assert cnt.value == want
+    assert ctx.stats().frnn_pairs == want
