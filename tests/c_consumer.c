@@ -19,6 +19,9 @@ int main(void)
     bad |= cpmi_two_locus(NULL, NULL, 5, 5, 10, 10, 0, NULL, &mp) != CPMI_ERR_ARG;
     bad |= cpmi_strings_lightbulb(NULL, NULL, 10, 4, 4, 3, 0, 1, 2, 0, 16, NULL, &mp, &pairs) != CPMI_ERR_ARG;
     bad |= cpmi_set_pruning(NULL, 1, 10.0, 0) != CPMI_ERR_ARG;
+    bad |= cpmi_pairs_to_csr(NULL, NULL, 0, 10, NULL, NULL, NULL) != CPMI_ERR_ARG;
+    bad |= cpmi_closest_pair_noalloc(NULL, NULL, CPMI_F32, 10, 4, 4, CPMI_PREC_AUTO, NULL, &best) != CPMI_ERR_ARG;
+    bad |= cpmi_dbg_set_prune_order(NULL, 0, 1.0) != CPMI_ERR_ARG;
     bad |= cpmi_dbg_tile_list(10, 0, 128, NULL, 0) != CPMI_ERR_ARG;
     bad |= cpmi_version() != 10000;
     printf("%s\n", bad ? "FAIL" : "ok");
