@@ -438,13 +438,26 @@ def test_range_nonfinite_series_and_strided_int8(ctx, torch_dev):
 
 
 def test_repeat_calls_are_deterministic(ctx, torch_dev):
-    c = W.cfg_points_small()
-    t = _dev(c["X"], torch_dev)
+    """The result sets are identical over 5 runs although the candidates
+    reach their buffers in whatever order the atomics give: points with a
+    radius that holds tens of thousands of pairs, a motif with a radius, and
+    a batch of series."""
+    rng = np.random.default_rng(4713)
+    X = rng.normal(0, 1, (6000, 24)).astype(np.float32)
+    tx = _dev(X, torch_dev)
+    T = W.random_walk(rng, 20000)
+    tt = _dev(T, torch_dev)
+    series = [_dev(W.random_walk(rng, L), torch_dev) for L in (3000, 5000, 7000)]
     outs = []
-    for _ in range(3):
-        best, (p, d) = ctx.points(t, R2=c["R2"], precision="bf16")
-        outs.append((best.i, best.j, best.d2, p.cpu().numpy().tobytes(), d.cpu().numpy().tobytes()))
-    assert outs[0] == outs[1] == outs[2]
+    for _ in range(5):
+        best, (p, d) = ctx.points(tx, R2=18.0, precision="bf16", cap=1 << 17)
+        mb, (mp, md) = ctx.motif(tt, 64, R2=12.8, precision="bf16", cap=1 << 20)
+        bb = ctx.motif_batch(series, [64, 128, 100])
+        outs.append((best.i, best.j, best.d2, p.cpu().numpy().tobytes(), d.cpu().numpy().tobytes(),
+                     mb.i, mb.j, mb.d2, mp.cpu().numpy().tobytes(), md.cpu().numpy().tobytes(),
+                     tuple((q.i, q.j, q.d2) for q in bb)))
+    assert len(np.frombuffer(outs[0][3], dtype=np.int64)) > 2 * 10_000
+    assert all(o == outs[0] for o in outs[1:])
 
 
 # ---------------------------------------------------------------------------
