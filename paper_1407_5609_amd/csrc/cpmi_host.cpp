@@ -373,7 +373,8 @@ void load_tune_cache(cpmi_ctx *c, const char *path)
 // panels) and the full part is split into 8 contiguous chunks interleaved
 // slot by slot, so that the work-groups the dispatcher sends to one XCD
 // (slot % 8) walk one chunk and keep its panels in that XCD's L2. For several
-// problems (uneven costs) the tiles are listed most-expensive problem first.
+// problems (uneven costs) the tiles are listed most-expensive problem first,
+// each problem's full tiles chunked and interleaved the same way.
 // keep(I, J) (optional, single problem) drops tiles proved empty of answers;
 // jend[I] (optional) is a block column from which on every tile of row I is
 // dropped, so that the scan of a band can stop there. For the windows of a
@@ -383,6 +384,7 @@ void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t
                  const std::function<bool(int64_t, int64_t)> &keep = {}, const std::vector<int64_t> *jend = nullptr)
 {
     std::vector<uint64_t> L, part;
+    std::vector<size_t> runs;   // several problems: where each problem's full tiles start in L
     std::vector<size_t> order(hp.size());
     for (size_t p = 0; p < hp.size(); ++p) order[p] = p;
     if (hp.size() > 1)
@@ -394,6 +396,7 @@ void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t
         const HostProb &h = hp[p];
         const int64_t G = std::max(1, h.band);
         if (pairs_of(h) == 0) continue;
+        runs.push_back(L.size());
         const bool permuted = h.motif && h.perm;
         const int64_t nT = (h.n + tile - 1) / tile;
         if (h.split > 0) {
@@ -434,17 +437,20 @@ void build_tiles(const std::vector<HostProb> &hp, int tile, std::vector<uint64_t
                 }
         }
     }
+    // each problem's full tiles split into 8 contiguous chunks interleaved
+    // slot by slot (its run padded to a whole number of 8 slots, so that slot
+    // s of every run goes to XCD s % 8): every XCD walks an eighth of every
+    // problem, in band order
     out.clear();
-    if (hp.size() == 1) {
-        const int64_t T = (int64_t)L.size();
-        const int64_t C = (T + 7) / 8;
-        out.resize(C * 8, TILE_NONE);
+    runs.push_back(L.size());
+    for (size_t r = 0; r + 1 < runs.size(); ++r) {
+        const int64_t a = (int64_t)runs[r], T = (int64_t)runs[r + 1] - a;
+        const int64_t C = (T + 7) / 8, base = (int64_t)out.size();
+        out.resize(base + C * 8, TILE_NONE);
         for (int64_t s = 0; s < C * 8; ++s) {
             const int64_t src = (s % 8) * C + s / 8;
-            if (src < T) out[s] = L[src];
+            if (src < T) out[base + s] = L[a + src];
         }
-    } else {
-        out = L;
     }
     *nfull = (int64_t)out.size();
     out.insert(out.end(), part.begin(), part.end());
