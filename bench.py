@@ -36,7 +36,7 @@ GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
 TRAFFIC = os.path.join(ROOT, "profiles", "screen256_bf16_mixture_n262144_d512.traffic.json")
 # sources of the dominant kernel: the counters are only valid for this exact code
 SCREEN_SRCS = [os.path.join(ROOT, "paper_1407_5609_amd", "csrc", f)
-               for f in ("screen256.hip", "layout256.h", "bound.h", "cpmi_internal.h")]
+               for f in ("screen256.hip", "screen256_tile.inc", "layout256.h", "bound.h", "cpmi_internal.h")]
 
 
 def note(msg):

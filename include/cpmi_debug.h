@@ -88,7 +88,7 @@ double cpmi_dbg_tile_bound(const float *bI, const float *bJ, int32_t kpad, int64
 int cpmi_dbg_layout256(int wave, int q, int lane, int32_t *out4);
 
 /* Host only: byte offset of byte `byte` of row `row` in the screen operand
- * of the 256-row screen (rows of `rowbytes` bytes, a multiple of 256),
+ * of the 256-row screen (rows of `rowbytes` bytes, a multiple of 128),
  * which is stored slice-major per block of 256 rows; -1 for bad arguments. */
 int64_t cpmi_dbg_xs_offset256(int64_t row, int64_t byte, int64_t rowbytes);
 

@@ -224,12 +224,22 @@ int ensure_pinned(cpmi_ctx *c, size_t bytes)
 
 int elem_bytes(int prec) { return prec == P_F32 ? 4 : (prec == P_BF16 ? 2 : 1); }
 
-// Rows are padded to whole LDS slices: 128 bytes for the 128-tile screen, and
-// four 64-byte slices (one turn of the load ring) for the 256-tile screen.
+// Rows are padded to 128 bytes: whole LDS slices of the 128-tile screen, and
+// pairs of 64-byte slices of the 256-tile screen (whose load ring turns four
+// slices at a time; a launch with rows of 4k + 2 slices takes its K2 form).
 int32_t kpad_for(int prec, int64_t d, int tile)
 {
-    const int64_t per = (tile == 256 ? 256 : 128) / elem_bytes(prec);
+    (void)tile;
+    const int64_t per = 128 / elem_bytes(prec);
     return (int32_t)((d + per - 1) / per * per);
+}
+
+// Some problem's rows hold 4k + 2 slices of the 256-tile screen.
+bool needs_k2(const std::vector<HostProb> &hp, int prec)
+{
+    for (const HostProb &h : hp)
+        if (((int64_t)h.kpad * elem_bytes(prec) / 64) % 4 != 0) return true;
+    return false;
 }
 
 const char *prec_name(int prec) { return prec == P_F32 ? "f32" : (prec == P_BF16 ? "bf16" : "i8"); }
@@ -725,6 +735,7 @@ int run_search(cpmi_ctx *c, std::vector<HostProb> &hp, int prec, int tile, bool 
             a.probs = dprobs;
             a.tiles = (const uint64_t *)W.tiles.p;
             a.ntiles = ntiles;
+            a.k2 = tile == 256 && needs_k2(hp, prec);
             if (dump) {
                 // the listed tiles' screen values, checked against the canonical d2
                 ScreenArgs q = a;
@@ -2156,7 +2167,7 @@ int cpmi_dbg_tune(const char *cache_in, const char *cache_out, int ncu, int dtyp
 
 int64_t cpmi_dbg_xs_offset256(int64_t row, int64_t byte, int64_t rowbytes)
 {
-    if (row < 0 || byte < 0 || rowbytes <= 0 || rowbytes % (4 * l256::SLICE) || byte >= rowbytes) return -1;
+    if (row < 0 || byte < 0 || rowbytes <= 0 || rowbytes % (2 * l256::SLICE) || byte >= rowbytes) return -1;
     return l256::xs_offset(row, byte, rowbytes);
 }
 

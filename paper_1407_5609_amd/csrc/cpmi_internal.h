@@ -115,6 +115,9 @@ struct ScreenArgs {
     // M_DUMP: tile_edge^2 values per list entry, row-major within the tile
     // (float, or int32 for int8)
     void *dump;
+    // 256 tile: some problem's rows hold 4k + 2 K slices of 64 bytes (else
+    // every problem's a multiple of 4)
+    bool k2;
 };
 
 // Wave-aggregated reservation of n slots per lane (called by every lane of

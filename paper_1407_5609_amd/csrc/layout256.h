@@ -33,7 +33,7 @@ __host__ __device__ inline int dma_lds(int wave, int q, int lane) { return (wave
 __host__ __device__ inline int frag_lds(int row, int chunk) { return row * SLICE + ((chunk ^ swz(row)) << 4); }
 
 // Byte offset, in the screen operand read by the 256-row screen, of byte b of
-// row r (rows of `rowbytes` bytes, a multiple of 4 * SLICE). The operand is
+// row r (rows of `rowbytes` bytes, a multiple of 2 * SLICE). The operand is
 // stored slice-major per block of 256 rows: block I holds the 64-byte slice 0
 // of its 256 rows (16 KB), then slice 1, and so on. One direct-to-LDS load of
 // 16 rows of a slice then reads 1 KB of consecutive memory (whole 128-byte

@@ -9,7 +9,8 @@
 //   * K slices (64 bytes per row) go straight from global memory into LDS
 //     with global_load_lds_dwordx4 (no staging registers) through a ring of
 //     four stages: the loads run three slices ahead of the multiply, across
-//     tile boundaries, with one barrier per slice;
+//     tile boundaries, with one barrier per slice (rows of 4k + 2 slices: the
+//     K2 form, whose tiles start at stage 0 or 2);
 //   * each 16-row, 1 KB LDS block stores row r's 16-byte chunk c at slot
 //     c ^ ((r >> 2) & 3), so the fragment reads of 16 consecutive rows hit
 //     all 64 banks once (layout256.h);
@@ -247,6 +248,31 @@ __device__ __forceinline__ void read_group(Frags<PREC> &fa, Frags<PREC> &fb, con
         fb[m] = *(const u32x4 *)(st + OPB + l256::frag_lds(wn * WT256 + m * 32 + lrow, 2 * g + lhalf));
 }
 
+// k-group g of a stage, as read_group, through reads the compiler does not
+// track (they wait for themselves, in the same asm block): for a stage that
+// has landed on every path that reaches the read, where the compiler cannot
+// see that. Rows 32 apart share their slot swizzle, so the four blocks of an
+// operand sit 2 KB apart from one address.
+template <int PREC>
+__device__ __forceinline__ void read_group_landed(Frags<PREC> &fa, Frags<PREC> &fb, const unsigned char *st, int g,
+                                                  int wm, int wn, int lrow, int lhalf)
+{
+    const uint32_t pa = (uint32_t)(uintptr_t)(st + l256::frag_lds(wm * WT256 + lrow, 2 * g + lhalf));
+    const uint32_t pb = (uint32_t)(uintptr_t)(st + OPB + l256::frag_lds(wn * WT256 + lrow, 2 * g + lhalf));
+    asm volatile("ds_read_b128 %0, %8\n\t"
+                 "ds_read_b128 %1, %8 offset:2048\n\t"
+                 "ds_read_b128 %2, %8 offset:4096\n\t"
+                 "ds_read_b128 %3, %8 offset:6144\n\t"
+                 "ds_read_b128 %4, %9\n\t"
+                 "ds_read_b128 %5, %9 offset:2048\n\t"
+                 "ds_read_b128 %6, %9 offset:4096\n\t"
+                 "ds_read_b128 %7, %9 offset:6144\n\t"
+                 "s_waitcnt lgkmcnt(0)"
+                 : "=&v"(fa[0]), "=&v"(fa[1]), "=&v"(fa[2]), "=&v"(fa[3]), "=&v"(fb[0]), "=&v"(fb[1]), "=&v"(fb[2]),
+                   "=&v"(fb[3])
+                 : "v"(pa), "v"(pb));
+}
+
 template <int PREC>
 __device__ __forceinline__ void mma_group(typename A2<PREC>::T (&acc)[MB256][MB256], const Frags<PREC> &fa,
                                           const Frags<PREC> &fb)
@@ -270,7 +296,9 @@ __device__ __forceinline__ void mma_group(typename A2<PREC>::T (&acc)[MB256][MB2
 //      registers through the epilogue.)
 // The three stages arrive as restrict pointers: once inlined their accesses
 // carry distinct alias scopes, so LDS reads never wait for the loads in flight.
-template <int PREC>
+// LANDED: k-group 1 of `cur` is read by read_group_landed (the first step of a
+// tile that starts at stage 2).
+template <int PREC, bool LANDED = false>
 __device__ __forceinline__ void slice_step(typename A2<PREC>::T (&acc)[MB256][MB256], Frags<PREC> &f0a,
                                            Frags<PREC> &f0b, const TileAddr &ia, int is, int wave, int wm, int wn,
                                            int lrow, int lhalf, const unsigned char *__restrict__ cur,
@@ -279,7 +307,8 @@ __device__ __forceinline__ void slice_step(typename A2<PREC>::T (&acc)[MB256][MB
     constexpr int MPG = (PREC == P_F32 ? 4 : 1) * MB256 * MB256;  // MFMAs per k-group
     Frags<PREC> f1a, f1b;
     issue_slice(ia, is, wave, wr);
-    read_group<PREC>(f1a, f1b, cur, 1, wm, wn, lrow, lhalf);
+    if constexpr (LANDED) read_group_landed<PREC>(f1a, f1b, cur, 1, wm, wn, lrow, lhalf);
+    else read_group<PREC>(f1a, f1b, cur, 1, wm, wn, lrow, lhalf);
     mma_group<PREC>(acc, f0a, f0b);
 #pragma unroll
     for (int k = 0; k < 2 * MB256; ++k) {
@@ -326,7 +355,11 @@ __device__ __forceinline__ u32x4 fold_frag_words(uint32_t w0, uint32_t w1, bool 
 
 // MASKED = false: every pair of every listed tile is admissible (the host
 // lists such full tiles apart), so the epilogue carries no masking code.
-template <int PREC, int MODE, bool MASKED>
+// K2 = false: every listed problem's rows hold a multiple of four K slices, so
+// every tile starts at stage 0 of the ring. K2 = true: a multiple of two (rows
+// of 128 bytes, e.g. BF16 windows of 64 values, are not padded to 256), so a
+// tile starts at stage 0 or 2 and the slice loop turns two slices at a time.
+template <int PREC, int MODE, bool MASKED, bool K2>
 __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) void screen256_kernel(ScreenArgs args)
 {
     using AccT = typename A2<PREC>::T;
@@ -463,442 +496,19 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     // the first tile's scalars are older than the last 16 loads: landed
     __builtin_amdgcn_s_waitcnt(WAIT_SLICE);
     __builtin_amdgcn_s_barrier();
+    [[maybe_unused]] int ph = 0;   // K2: ring stage (0 or 2) of the current tile's first slice
+    // The tile loop; the tile body is included once per ring stage a tile may
+    // start at (one for K2 = false).
     while (t < count) {
-        // per-lane values are rebuilt from a fresh lane index at every tile,
-        // so that nothing lane-derived is held through the epilogue
-        const int lane_t = fresh_lane();
-        const int lrow = lane_t & 31, lhalf = lane_t >> 5;
-        const uint64_t ent = tiles[t];
-        const uint32_t p = tile_prob(ent);
-        const c_prob &P = ((c_prob *)args.probs)[p];
-        const int64_t I = tile_I(ent), J = tile_J(ent);
-        const int nst = (int)((int64_t)P.kpad * ESZ / SL);
-        const int32_t i0 = (int32_t)(I * T256) + wm * WT256, j0 = (int32_t)(J * T256) + wn * WT256;
-        // this tile's row scalars were loaded one tile ago (or before the
-        // loop) and are older than every slice waited for since
-        const S *sh_t = sh_s + (tcount & 1) * (2 * T256);
-        const uint32_t *shw_t = sh_w + (tcount & 1) * (2 * T256 * 2);   // BF16 fold words
-        const int32_t *sh_ot = sh_o + (tcount & 1) * (2 * T256);
-        const int32_t tn = next_valid(t + stride);
-        if (tn < count) load_scalars(tn, (tcount + 1) & 1);
-        ++tcount;
-
-        AccT acc[MB256][MB256];
-        if constexpr (FOLD) {
-            // the row scalars of this lane's rows: A block m row
-            // wm*128 + 32 m + lrow, B block m row wn*128 + 32 m + lrow
-            if constexpr (PREC == P_BF16) {
-                u32x4 a01, a23, b01, b23;
-                lds_landed_4x64(shw_t + 2 * (wm * WT256 + lrow), a01, a23);
-                lds_landed_4x64(shw_t + 2 * (T256 + wn * WT256 + lrow), b01, b23);
-                u32x4 fa[MB256], fb[MB256];
-                fa[0] = fold_frag_words(a01.x, a01.y, lhalf == 0);
-                fa[1] = fold_frag_words(a01.z, a01.w, lhalf == 0);
-                fa[2] = fold_frag_words(a23.x, a23.y, lhalf == 0);
-                fa[3] = fold_frag_words(a23.z, a23.w, lhalf == 0);
-                fb[0] = fold_frag_words(b01.x, b01.y, lhalf != 0);
-                fb[1] = fold_frag_words(b01.z, b01.w, lhalf != 0);
-                fb[2] = fold_frag_words(b23.x, b23.y, lhalf != 0);
-                fb[3] = fold_frag_words(b23.z, b23.w, lhalf != 0);
-#pragma unroll
-                for (int a = 0; a < MB256; ++a)
-#pragma unroll
-                    for (int b = 0; b < MB256; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, fa[a]),
-                                                                            __builtin_bit_cast(bf16x8, fb[b]),
-                                                                            AccT{}, 0, 0, 0);
-            } else {
-                const u32x4 sa = lds_landed_4x32(sh_t + wm * WT256 + lrow);
-                const u32x4 sb = lds_landed_4x32(sh_t + T256 + wn * WT256 + lrow);
-                const uint32_t sav[4] = {sa.x, sa.y, sa.z, sa.w};
-                const uint32_t sbv[4] = {sb.x, sb.y, sb.z, sb.w};
-                float fa[MB256], fb[MB256];
-#pragma unroll
-                for (int m = 0; m < MB256; ++m) {
-                    const float ca = -0.5f * __uint_as_float(sav[m]), cb = -0.5f * __uint_as_float(sbv[m]);
-                    fa[m] = lhalf == 0 ? ca : 1.0f;
-                    fb[m] = lhalf == 0 ? 1.0f : cb;
-                }
-#pragma unroll
-                for (int a = 0; a < MB256; ++a)
-#pragma unroll
-                    for (int b = 0; b < MB256; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[a], fb[b], AccT{}, 0, 0, 0);
-            }
+        if (!K2 || ph == 0) {
+#define CPMI_TILE_P0 0
+#include "screen256_tile.inc"
+#undef CPMI_TILE_P0
         } else {
-#pragma unroll
-            for (int a = 0; a < MB256; ++a)
-#pragma unroll
-                for (int b = 0; b < MB256; ++b) acc[a][b] = AccT{};
+#define CPMI_TILE_P0 2
+#include "screen256_tile.inc"
+#undef CPMI_TILE_P0
         }
-        // the folded operands are dead from here on
-        __builtin_amdgcn_sched_barrier(0);
-        // k-group 0 of the tile's first slice (every tile starts at stage 0,
-        // which landed before the previous slice step's barrier). Read here,
-        // not carried over from the previous tile, so that the fragments are
-        // not held in registers through the epilogue; the folded steps above
-        // run meanwhile.
-        Frags<PREC> f0a, f0b;
-        read_group<PREC>(f0a, f0b, stage_ptr<0>(), 0, wm, wn, lrow, lhalf);
-
-        // nst is a positive multiple of 4 (rows are padded to whole groups of
-        // four slices)
-        for (int s = 0; s < nst; s += 4) {
-            TileAddr cia = ia;
-            int cis = is;
-            advance();
-            slice_step<PREC>(acc, f0a, f0b, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<0>(), stage_ptr<1>(),
-                             stage_ptr<3>());
-            cia = ia;
-            cis = is;
-            advance();
-            slice_step<PREC>(acc, f0a, f0b, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<1>(), stage_ptr<2>(),
-                             stage_ptr<0>());
-            cia = ia;
-            cis = is;
-            advance();
-            slice_step<PREC>(acc, f0a, f0b, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<2>(), stage_ptr<3>(),
-                             stage_ptr<1>());
-            cia = ia;
-            cis = is;
-            advance();
-            slice_step<PREC>(acc, f0a, f0b, cia, cis, wave, wm, wn, lrow, lhalf, stage_ptr<3>(), stage_ptr<0>(),
-                             stage_ptr<2>());
-        }
-        // ---------------- epilogue ----------------
-        // 32-bit row/column indices (n < 2^31 is enforced by the host)
-        const int32_t n = (int32_t)P.n, excl = (int32_t)P.excl;
-        // windows in reference order: admissibility compares source positions
-        // (only masked tiles carry such problems; motifs are never int8)
-        const bool pexcl = MASKED && FOLD && P.perm && P.motif;
-        // two sets of int8 rows: pairs across the sets (masked tiles test every pair)
-        const bool twoset = MASKED && !FOLD && P.split > 0;
-        const bool full = !MASKED || (!pexcl && !twoset &&
-                                      ((int64_t)J * T256 - ((int64_t)I * T256 + T256 - 1) >= P.excl) &&
-                                      ((int64_t)I * T256 + T256 <= P.n) && ((int64_t)J * T256 + T256 <= P.n));
-        // source positions of this lane's 4 columns and, per block a, 16 rows
-        int32_t oj[MB256] = {0, 0, 0, 0};
-        if (pexcl) {
-            const u32x4 v = lds_landed_4x32(sh_ot + T256 + wn * WT256 + lrow);
-            oj[0] = (int32_t)v.x;
-            oj[1] = (int32_t)v.y;
-            oj[2] = (int32_t)v.z;
-            oj[3] = (int32_t)v.w;
-        }
-        auto load_oi = [&](int a, int32_t (&oi)[16]) {
-            u32x4 v[4];
-            lds_landed_4x128(sh_ot + wm * WT256 + a * 32 + 4 * lhalf, v[0], v[1], v[2], v[3]);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                oi[4 * q] = (int32_t)v[q].x;
-                oi[4 * q + 1] = (int32_t)v[q].y;
-                oi[4 * q + 2] = (int32_t)v[q].z;
-                oi[4 * q + 3] = (int32_t)v[q].w;
-            }
-        };
-        // Admissible pair of screen rows gi, gj (source positions oa, ob),
-        // evaluated without branches (bitwise, not short-circuit). Rows in
-        // position order: gj - gi >= excl and gj < n (which imply gi < gj <
-        // n). Rows in reference order: gi < gj < n and |ob - oa| >= excl,
-        // tested as (oa + excl - 1 - ob) >= 2 excl - 1 in unsigned 32-bit
-        // arithmetic (positions below 2^31, excl at most 2^30, checked by the
-        // host).
-        const uint32_t pspan = 2u * (uint32_t)excl - 1u;
-        auto far_apart = [&](int32_t oa, int32_t ob) {
-            return ((uint32_t)oa + (uint32_t)(excl - 1) - (uint32_t)ob) >= pspan;
-        };
-        auto adm_pos = [&](int32_t gi, int32_t gj) { return (gj - gi >= excl) & (gj < n); };
-        // two sets (the host lists only tiles with J >= split / 256, so gj >= split)
-        const int32_t na = (int32_t)P.na, split = P.split;
-        auto adm_two = [&](int32_t gi, int32_t gj) { return (gi < na) & (gj < n) & (gj - split != gi); };
-        auto adm_ref = [&](int32_t gi, int32_t gj, int32_t oa, int32_t ob) {
-            return far_apart(oa, ob) & (gj > gi) & (gj < n);
-        };
-        // screen value of accumulator element r of block (a, b)
-        S sj[MB256];
-        if constexpr (!FOLD) {
-            const u32x4 v = lds_landed_4x32(sh_t + T256 + wn * WT256 + lrow);
-            sj[0] = bits_as<S>(v.x);
-            sj[1] = bits_as<S>(v.y);
-            sj[2] = bits_as<S>(v.z);
-            sj[3] = bits_as<S>(v.w);
-        }
-        // rows of this lane in block a: 8*(r/4) + 4*lhalf + (r%4), four runs of 4 rows
-        auto load_si = [&](int a, S (&si)[16]) {
-            u32x4 v[4];
-            lds_landed_4x128(sh_t + wm * WT256 + a * 32 + 4 * lhalf, v[0], v[1], v[2], v[3]);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                si[4 * q] = bits_as<S>(v[q].x);
-                si[4 * q + 1] = bits_as<S>(v[q].y);
-                si[4 * q + 2] = bits_as<S>(v[q].z);
-                si[4 * q + 3] = bits_as<S>(v[q].w);
-            }
-        };
-        S best = SINF;
-        // pass 1: the wave's minimum over its admissible elements
-        if constexpr (MODE & M_MIN) {
-            if (full) {
-                if constexpr (FOLD) {
-                    // min of -2 acc = -2 max acc, one accumulator block at a
-                    // time: the opaque step closes each block's maximum, so the
-                    // compiler does not build one tree over (and copy out of the
-                    // accumulator registers) all 256 values at once
-                    S mx = -SINF;
-    #pragma unroll
-                    for (int a = 0; a < MB256; ++a) {
-                        S ma = -SINF;
-    #pragma unroll
-                        for (int r = 0; r < 16; ++r)
-    #pragma unroll
-                            for (int b = 0; b < MB256; ++b) ma = fmaxf(ma, acc[a][b][r]);
-                        asm volatile("" : "+v"(ma));
-                        mx = fmaxf(mx, ma);
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
-                    best = -2.0f * mx;
-                } else {
-    #pragma unroll
-                    for (int a = 0; a < MB256; ++a) {
-                        S si[16];
-                        load_si(a, si);
-    #pragma unroll
-                        for (int r = 0; r < 16; ++r) {
-                            S m0 = part(acc[a][0][r], sj[0]);
-    #pragma unroll
-                            for (int b = 1; b < MB256; ++b) m0 = smin(m0, part(acc[a][b][r], sj[b]));
-                            best = smin(best, (S)(si[r] + m0));
-                        }
-                        // one accumulator block at a time keeps the epilogue's registers few
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
-                }
-            } else if constexpr (MASKED) {
-                if constexpr (FOLD) {
-                    // max of acc over the admissible elements, one accumulator
-                    // block at a time (as above), every test a select. Three
-                    // forms, chosen per tile: rows in position order; rows in
-                    // reference order off the diagonal and the ragged edge
-                    // (positions alone decide); and the rest.
-                    const int form = !pexcl ? 0 : ((I != J) && ((int64_t)J * T256 + T256 <= P.n)) ? 1 : 2;
-                    S mx = -SINF;
-    #pragma unroll
-                    for (int a = 0; a < MB256; ++a) {
-                        int32_t oi[16] = {};
-                        if (form != 0) load_oi(a, oi);
-                        S ma = -SINF;
-                        // (a scheduling fence per row, and a row position the
-                        // compiler cannot share between the forms, keep the tests
-                        // next to their use: hoisted, they outgrow the free
-                        // registers)
-                        if (form == 1) {
-    #pragma unroll
-                            for (int r = 0; r < 16; ++r) {
-                                int32_t o = oi[r];
-                                asm volatile("" : "+v"(o));
-    #pragma unroll
-                                for (int b = 0; b < MB256; ++b)
-                                    ma = fmaxf(ma, far_apart(o, oj[b]) ? acc[a][b][r] : -SINF);
-                                __builtin_amdgcn_sched_barrier(0);
-                            }
-                        } else if (form == 0) {
-    #pragma unroll
-                            for (int r = 0; r < 16; ++r) {
-                                const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
-    #pragma unroll
-                                for (int b = 0; b < MB256; ++b)
-                                    ma = fmaxf(ma, adm_pos(gi, j0 + b * 32 + lrow) ? acc[a][b][r] : -SINF);
-                                __builtin_amdgcn_sched_barrier(0);
-                            }
-                        } else {
-    #pragma unroll
-                            for (int r = 0; r < 16; ++r) {
-                                const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
-    #pragma unroll
-                                for (int b = 0; b < MB256; ++b)
-                                    ma = fmaxf(ma, adm_ref(gi, j0 + b * 32 + lrow, oi[r], oj[b]) ? acc[a][b][r] : -SINF);
-                                __builtin_amdgcn_sched_barrier(0);
-                            }
-                        }
-                        asm volatile("" : "+v"(ma));
-                        mx = fmaxf(mx, ma);
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
-                    best = -2.0f * mx;
-                } else {
-                    // (one loop per admissibility rule: the rule is uniform per tile)
-                    auto masked_min = [&](auto adm) {
-    #pragma unroll
-                        for (int a = 0; a < MB256; ++a) {
-                            S si[16];
-                            load_si(a, si);
-    #pragma unroll
-                            for (int r = 0; r < 16; ++r) {
-                                const int32_t gi = i0 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
-    #pragma unroll
-                                for (int b = 0; b < MB256; ++b) {
-                                    const int32_t gj = j0 + b * 32 + lrow;
-                                    const S dv = (S)(si[r] + part(acc[a][b][r], sj[b]));
-                                    best = adm(gi, gj) ? smin(best, dv) : best;
-                                }
-                            }
-                            __builtin_amdgcn_sched_barrier(0);
-                        }
-                    };
-                    if (twoset) masked_min(adm_two);
-                    else masked_min(adm_pos);
-                }
-            }
-        }
-
-        if constexpr (MODE & M_DUMP) {
-            // every element's screen value, as the other modes form it
-            S *out = (S *)args.dump + (size_t)t * (T256 * T256);
-#pragma unroll
-            for (int a = 0; a < MB256; ++a) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int32_t il = wm * WT256 + a * 32 + 8 * (r >> 2) + 4 * lhalf + (r & 3);
-                    S si = 0;
-                    if constexpr (!FOLD) si = sh_t[il];
-#pragma unroll
-                    for (int b = 0; b < MB256; ++b) {
-                        S dv;
-                        if constexpr (FOLD) dv = -2.0f * acc[a][b][r];
-                        else dv = (S)(si + part(acc[a][b][r], sj[b]));
-                        out[il * T256 + wn * WT256 + b * 32 + lrow] = dv;
-                    }
-                }
-            }
-        }
-        if constexpr (MODE & M_EMIT) {
-            const double E = tile_bound(P.bmax[I], P.bmax[J], P.kpad, P.d, PREC,
-                                        FOLD ? SCREEN_FOLDED : SCREEN_EPILOGUE);
-            S thrU = -SINF, thrR = -SINF, thrIn = -SINF;
-            if (args.U) {
-                const double u = args.U[p];
-                if constexpr (PREC == P_I8) thrU = (S)fmin(u, 2147483646.0);
-                else thrU = f32_up(u + E + add_margin(u, E));
-            }
-            if (P.r2 >= 0.0) {
-                if constexpr (PREC == P_I8) thrR = (S)fmin(floor(P.r2), 2147483646.0);
-                else thrR = f32_up(P.r2 + E + add_margin(P.r2, E));
-                if (args.cntIn) {
-                    if constexpr (PREC == P_I8) thrIn = thrR;   // exact: no band
-                    else thrIn = f32_down(P.r2 - E - add_margin(P.r2, E));
-                }
-            }
-            const S thr = thrU > thrR ? thrU : thrR;
-            // Each element within the threshold in some lane is classified
-            // and emitted with one atomic add per wave and counter (ballot,
-            // then slots by rank; radius candidates in slabs, above).
-            auto emit = [&](bool pred, Cand *cand, u64c *cnt, uint64_t cap, const Cand &cd) {
-                const uint64_t m = __ballot(pred);
-                if (m != 0) {
-                    u64c base = 0;
-                    if (fresh_lane() == 0) base = atomicAdd(cnt, (u64c)__popcll(m));
-                    base = ((u64c)(uint32_t)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32) |
-                           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base);
-                    const uint32_t rank =
-                        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    if (pred && base + rank < cap) cand[base + rank] = cd;
-                }
-            };
-            // Folded screen values: -2 v <= thr holds only where v >= -thr / 2,
-            // so a block whose maximum accumulator stays below that in every
-            // lane is passed over after one maximum (the threshold of that
-            // test is lowered by a margin, so it never passes over a hit).
-            S hthr = SINF;
-            if constexpr (FOLD) {
-                if (thr > -SINF) {
-                    hthr = -0.5f * thr;
-                    hthr -= fabsf(hthr) * 0x1p-20f + 0x1p-126f;
-                }
-            }
-            // The blocks one after another in a loop that is not unrolled
-            // (its accumulators picked by a switch): unrolled over all 256
-            // elements, the emission outgrows the instruction cache and the
-            // pass runs many times slower than the screen itself.
-#pragma unroll 1
-            for (int blk = 0; blk < MB256 * MB256; ++blk) {
-                const int a = blk / MB256, b = blk % MB256;
-                AccT v;
-                switch (blk) {
-#define CPMI_ACC_CASE(k) \
-    case k: v = acc[(k) / MB256][(k) % MB256]; break;
-                    CPMI_ACC_CASE(0) CPMI_ACC_CASE(1) CPMI_ACC_CASE(2) CPMI_ACC_CASE(3)
-                    CPMI_ACC_CASE(4) CPMI_ACC_CASE(5) CPMI_ACC_CASE(6) CPMI_ACC_CASE(7)
-                    CPMI_ACC_CASE(8) CPMI_ACC_CASE(9) CPMI_ACC_CASE(10) CPMI_ACC_CASE(11)
-                    CPMI_ACC_CASE(12) CPMI_ACC_CASE(13) CPMI_ACC_CASE(14) default: v = acc[3][3]; break;
-#undef CPMI_ACC_CASE
-                }
-                // this lane's rows of block a and column of block b
-                const int32_t ib = i0 + a * 32 + 4 * lhalf, gj = j0 + b * 32 + lrow;
-                S sjb = 0;
-                int32_t ojb = 0;
-                if constexpr (!FOLD) sjb = sh_t[T256 + gj - (int32_t)(J * T256)];
-                if (pexcl) ojb = sh_ot[T256 + gj - (int32_t)(J * T256)];
-                if constexpr (FOLD) {
-                    S mx = v[0];
-#pragma unroll
-                    for (int r = 1; r < 16; ++r) mx = fmaxf(mx, v[r]);
-                    if (!__any(mx >= hthr)) continue;
-                }
-                S dv[16];
-                bool near_any = false;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    if constexpr (FOLD) {
-                        dv[r] = -2.0f * v[r];
-                    } else {
-                        const int32_t gi = ib + 8 * (r >> 2) + (r & 3);
-                        dv[r] = (S)(sh_t[gi - (int32_t)(I * T256)] + part(v[r], sjb));
-                    }
-                    near_any |= dv[r] <= thr;
-                }
-                if (!__any(near_any)) continue;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    if (__any(dv[r] <= thr)) {
-                        const int32_t gi = ib + 8 * (r >> 2) + (r & 3);
-                        int32_t oir = 0;
-                        if (pexcl) oir = sh_ot[gi - (int32_t)(I * T256)];
-                        const bool ok = full | (pexcl    ? adm_ref(gi, gj, oir, ojb)
-                                                : twoset ? adm_two(gi, gj)
-                                                         : adm_pos(gi, gj));
-                        Cand cd;
-                        cd.i = gi;
-                        cd.j = gj;
-                        cd.dt = (float)dv[r];
-                        cd.p = p;
-                        const bool in = ok & (dv[r] <= thrIn);
-                        nIn += in;
-                        emit(ok & (dv[r] <= thrU), args.candU, args.cntU, args.capU, cd);
-                        emit_r(ok & !in & (dv[r] <= thrR), cd);
-                    }
-                }
-            }
-        }
-        if constexpr (MODE & M_MIN) {
-            // each wave stores the minimum of its quarter of the tile
-            best = wmin(best);
-            if (fresh_lane() == 0) args.tile_min[4 * t + wave] = __builtin_bit_cast(uint32_t, best);
-            // Int8 tiles read their row scalars, and windows in reference
-            // order their positions, from LDS at uneven times across the
-            // waves; the next tile's top prefetches the tile after it into
-            // this same half, so no wave may start it before every wave is
-            // done here. (Folded tiles of rows in position order read
-            // nothing from LDS after the last slice.)
-            if constexpr (!FOLD) __builtin_amdgcn_s_barrier();
-            else if (pexcl) __builtin_amdgcn_s_barrier();
-        } else {
-            // The same for the emission (and the dump): its reads of row
-            // scalars (int8) and window positions (reference order) must be
-            // done in every wave before the next tile's prefetch.
-            if constexpr (!FOLD || (MODE & M_DUMP)) __builtin_amdgcn_s_barrier();
-            else if (pexcl) __builtin_amdgcn_s_barrier();
-        }
-        t = tn;
     }
     if constexpr (MODE & M_EMIT) {
         if (slab_used < SLAB) close_slab();
@@ -909,14 +519,21 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
     __builtin_amdgcn_s_waitcnt(0);
 }
 
+template <int PREC, bool K2>
+static void launch256k(int mode, bool masked, const ScreenArgs &a, int64_t grid, hipStream_t st)
+{
+    dim3 g((unsigned)grid), b(256);
+    if (mode == M_MIN && !masked) hipLaunchKernelGGL((screen256_kernel<PREC, M_MIN, false, K2>), g, b, 0, st, a);
+    else if (mode == M_MIN) hipLaunchKernelGGL((screen256_kernel<PREC, M_MIN, true, K2>), g, b, 0, st, a);
+    else if (mode == M_DUMP) hipLaunchKernelGGL((screen256_kernel<PREC, M_DUMP, true, K2>), g, b, 0, st, a);
+    else hipLaunchKernelGGL((screen256_kernel<PREC, M_EMIT, true, K2>), g, b, 0, st, a);
+}
+
 template <int PREC>
 static void launch256(int mode, bool masked, const ScreenArgs &a, int64_t grid, hipStream_t st)
 {
-    dim3 g((unsigned)grid), b(256);
-    if (mode == M_MIN && !masked) hipLaunchKernelGGL((screen256_kernel<PREC, M_MIN, false>), g, b, 0, st, a);
-    else if (mode == M_MIN) hipLaunchKernelGGL((screen256_kernel<PREC, M_MIN, true>), g, b, 0, st, a);
-    else if (mode == M_DUMP) hipLaunchKernelGGL((screen256_kernel<PREC, M_DUMP, true>), g, b, 0, st, a);
-    else hipLaunchKernelGGL((screen256_kernel<PREC, M_EMIT, true>), g, b, 0, st, a);
+    if (a.k2) launch256k<PREC, true>(mode, masked, a, grid, st);
+    else launch256k<PREC, false>(mode, masked, a, grid, st);
 }
 
 void launch_screen256(int prec, int mode, bool masked, const ScreenArgs &a, int64_t grid, hipStream_t st)

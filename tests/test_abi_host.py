@@ -374,11 +374,12 @@ def test_tune_cache_lookup_and_round_trip(lib, tmp_path):
     assert _tune(lib, c, F32, 2, 512, 10.0, cache_out=str(tmp_path / "no" / "dir.json"))[0] == -1
 
 
-@pytest.mark.parametrize("rowbytes", [256, 512, 1024])
+@pytest.mark.parametrize("rowbytes", [128, 256, 384, 512, 1024])
 def test_blocked_operand_layout_is_a_bijection_and_slices_are_contiguous(lib, rowbytes):
     """The 256-row screen's operand layout maps every (row, byte) of a padded
     operand to a distinct offset inside it, and the 16 rows x 64 bytes that
-    one direct-to-LDS load reads are one contiguous 1 KB run."""
+    one direct-to-LDS load reads are one contiguous 1 KB run (rows of 128
+    bytes and of 4k + 2 slices included: the screen's K2 form reads them)."""
     f = lib.cpmi_dbg_xs_offset256
     f.restype = C.c_int64
     f.argtypes = [C.c_int64, C.c_int64, C.c_int64]
@@ -390,7 +391,7 @@ def test_blocked_operand_layout_is_a_bijection_and_slices_are_contiguous(lib, ro
         for s in range(rowbytes // 64):
             run = np.sort(offs[r0:r0 + 16, 64 * s:64 * s + 64].ravel())
             assert run[-1] - run[0] == 1023 and np.all(np.diff(run) == 1)
-    assert f(0, rowbytes, rowbytes) == -1 and f(0, 0, 200) == -1
+    assert f(0, rowbytes, rowbytes) == -1 and f(0, 0, 200) == -1 and f(0, 0, 64) == -1
 
 
 # --------------------------------------------------------------------------
