@@ -103,6 +103,20 @@ class Workload:
     flops_per_pair = None          # algorithmic flops (int ops) per admissible pair
     graph = False                  # launches replayed from a captured graph (no per-launch events)
     roofline = True                # the step's dominant launch is a matrix-core screen
+    out_cap = 0                    # radius pairs a step's caller-owned output holds (0: no radius output)
+
+    def reserve(self, torch, steps):
+        """The radius outputs of the next `steps` steps, allocated before the
+        timed region: each step's outputs stay alive until they are checked
+        after it, so a step allocating its own would call the device
+        allocator inside the timed region."""
+        self._outs = [(torch.empty((self.out_cap, 2), dtype=torch.int64, device="cuda:0"),
+                       torch.empty(self.out_cap, dtype=torch.float64, device="cuda:0"))
+                      for _ in range(steps)] if self.out_cap else []
+
+    def _out(self):
+        outs = getattr(self, "_outs", None)
+        return outs.pop() if outs else None
 
 
 class Points(Workload):
@@ -119,6 +133,7 @@ class Points(Workload):
         return g
 
     query = "points"   # "cpp": the closest pair alone
+    out_cap = 1 << 16
 
     def step(self, ctx, prec):
         import numpy as np
@@ -126,7 +141,7 @@ class Points(Workload):
         if self.query == "cpp":
             best = ctx.closest_pair(self.X, precision=prec)
             return (best.i, best.j, best.d2) == wp
-        best, (p, dd) = ctx.points(self.X, R2=self.R2, precision=prec)
+        best, (p, dd) = ctx.points(self.X, R2=self.R2, precision=prec, out=self._out())
         # the radius pairs stay on the device; they are compared after the timed steps
         return lambda: ((best.i, best.j, best.d2) == wp and np.array_equal(p.cpu().numpy(), wpairs)
                         and np.array_equal(dd.cpu().numpy(), wd))
@@ -173,13 +188,14 @@ class MixtureRadius(Mixture):
         g = _golden("mixture_n262144_d512_radius.json")
         self.R2 = float.fromhex(g["R2"])
         self.count, self.sha = g["count"], g["sha256"]
+        self.out_cap = self.count
         self.config = dict(self.config, workload=f"mixture_n{self.n}_d{self.d}: exact closest pair + all "
                            f"{self.count} pairs within R = sqrt({self.R2:g}) (BF16 matrix-core screen, FP64 "
                            "verification)", R=self.R2 ** 0.5, radius_pairs=self.count)
 
     def step(self, ctx, prec):
         wp = self.want[0]
-        best, (p, dd) = ctx.points(self.X, R2=self.R2, precision=prec, cap=self.count)
+        best, (p, dd) = ctx.points(self.X, R2=self.R2, precision=prec, cap=self.count, out=self._out())
         return lambda: ((best.i, best.j, best.d2) == wp and len(p) == self.count
                         and _radius_digest(p.cpu().numpy(), dd.cpu().numpy()) == self.sha)
 
@@ -207,6 +223,7 @@ class Snp(Points):
 class Motif(Workload):
     name = "motif"
     query = "points"   # "cpp": the motif alone, no radius pairs
+    out_cap = 1 << 16
 
     def __init__(self, W, torch):
         self._setup(torch, W.cfg_motif(), "motif_L65536_l256.json")
@@ -227,7 +244,7 @@ class Motif(Workload):
         if self.query == "cpp":
             best, _ = ctx.motif(self.T, self.ell, excl=self.excl, precision=prec)
             return (best.i, best.j, best.d2) == wp
-        best, (p, dd) = ctx.motif(self.T, self.ell, excl=self.excl, R2=self.R2, precision=prec)
+        best, (p, dd) = ctx.motif(self.T, self.ell, excl=self.excl, R2=self.R2, precision=prec, out=self._out())
         # the radius pairs stay on the device; they are compared after the timed steps
         return lambda: ((best.i, best.j, best.d2) == wp and np.array_equal(p.cpu().numpy(), wpairs)
                         and np.array_equal(dd.cpu().numpy(), wd))
@@ -435,6 +452,7 @@ def main():
         if not isinstance(wl, (Points, Motif)):
             sys.exit("--query cpp applies to the point and single-series motif workloads only")
         wl.query = args.query
+        wl.out_cap = 0
         wl.config = dict(wl.config, query="closest pair only")
     elif args.query in ("most", "least"):
         if not isinstance(wl, Strings):
@@ -455,6 +473,7 @@ def main():
     def run(prec, steps, warmup):
         for _ in range(warmup):
             wl.step(ctx, prec)
+        wl.reserve(torch, steps)
         torch.cuda.synchronize()
         screen_ms, checks, t0 = [], [], time.perf_counter()
         for _ in range(steps):

@@ -270,9 +270,22 @@ class Context:
             raise TypeError("points must be float32 or int8")
         return dt, pts.shape[0], pts.shape[1], max(pts.stride(0), pts.shape[1])
 
-    def _radius_call(self, fn, cap):
-        """Two-call capacity protocol: try with `cap`, retry with the count."""
+    def _radius_call(self, fn, cap, out=None):
+        """Two-call capacity protocol: try with `cap`, retry with the count.
+        With `out` = (pairs, d2), caller-owned int64 (m, 2) and float64 (m,)
+        device tensors, the pairs go there (capacity m, no allocation and no
+        retry: a larger count raises the capacity error)."""
         import torch
+        if out is not None:
+            pairs, d2 = out
+            if pairs.dtype != torch.int64 or d2.dtype != torch.float64 or pairs.dim() != 2 or \
+                    pairs.shape[1] != 2 or d2.dim() != 1 or not pairs.is_contiguous() or not d2.is_contiguous() \
+                    or pairs.device.type != "cuda" or d2.device.type != "cuda":
+                raise ValueError("out must be a contiguous int64 (m, 2) and float64 (m,) pair of GPU tensors")
+            cap = min(pairs.shape[0], d2.shape[0])
+            cnt = C.c_int64(0)
+            rc = fn(pairs, d2, cap, cnt)
+            return rc, pairs[:min(cnt.value, cap)], d2[:min(cnt.value, cap)]
         cap = max(int(cap), 1)
         while True:
             pairs = torch.empty((cap, 2), dtype=torch.int64, device=f"cuda:{self.device}")
@@ -341,12 +354,12 @@ class Context:
                                                    _prec(precision), _stream_ptr(stream), C.byref(out)))
         return _pair(out)
 
-    def frnn(self, pts, R2: float, precision="auto", stream=None, cap: int = 1 << 16):
+    def frnn(self, pts, R2: float, precision="auto", stream=None, cap: int = 1 << 16, out=None):
         dt, n, d, ld = self._points_args(pts)
         rc, pairs, d2 = self._radius_call(
             lambda P, D, k, cnt: _lib.cpmi_frnn(self._h, C.c_void_p(pts.data_ptr()), dt, n, d, ld, float(R2),
                                                 _prec(precision), _stream_ptr(stream), C.c_void_p(P.data_ptr()),
-                                                C.c_void_p(D.data_ptr()), k, C.byref(cnt)), cap)
+                                                C.c_void_p(D.data_ptr()), k, C.byref(cnt)), cap, out)
         self._check(rc)
         return pairs, d2
 
@@ -362,7 +375,7 @@ class Context:
         return int(cnt.value)
 
     def points(self, pts, R2: float | None = None, precision="auto", stream=None, cap: int = 1 << 16,
-               want_pair: bool = True):
+               want_pair: bool = True, out=None):
         dt, n, d, ld = self._points_args(pts)
         best = _CPair() if want_pair else None
         r2 = -1.0 if R2 is None else float(R2)
@@ -375,12 +388,12 @@ class Context:
                                                   _prec(precision), r2, _stream_ptr(stream),
                                                   C.byref(best) if best is not None else None,
                                                   C.c_void_p(P.data_ptr()), C.c_void_p(D.data_ptr()), k,
-                                                  C.byref(cnt)), cap)
+                                                  C.byref(cnt)), cap, out)
         self._check(rc)
         return (_pair(best) if best is not None else None), (pairs, d2)
 
     def motif(self, series, ell: int, excl: int = 0, R2: float | None = None, precision="auto", stream=None,
-              cap: int = 1 << 16, want_pair: bool = True):
+              cap: int = 1 << 16, want_pair: bool = True, out=None):
         import torch
         if series.device.type != "cuda" or series.dtype != torch.float32 or series.dim() != 1 or \
                 series.stride(0) != 1:
@@ -397,7 +410,7 @@ class Context:
                                                  _prec(precision), float(R2), _stream_ptr(stream),
                                                  C.byref(best) if best is not None else None,
                                                  C.c_void_p(P.data_ptr()), C.c_void_p(D.data_ptr()), k,
-                                                 C.byref(cnt)), cap)
+                                                 C.byref(cnt)), cap, out)
         self._check(rc)
         return (_pair(best) if best is not None else None), (pairs, d2)
 

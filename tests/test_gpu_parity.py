@@ -139,6 +139,43 @@ def test_points_match_oracle(ctx, torch_dev, tile, prec, n, d):
     assert ctx.stats().max_err_over_bound <= 1.0
 
 
+def test_radius_pairs_into_caller_owned_outputs(ctx, torch_dev):
+    """`out=` hands the radius pairs to caller-owned tensors (no allocation
+    in the call): the same pairs as the allocating call, for points and for
+    windows; an output too small for the list raises the capacity error and
+    reports the count."""
+    import torch
+    import paper_1407_5609_amd as cp
+    rng = np.random.default_rng(5)
+    X = rng.normal(0, 1, (1500, 12)).astype(np.float32)
+    Xd = _dev(X, torch_dev)
+    best0, fr0 = ctx.points(Xd, R2=4.0, precision="bf16")
+    m = len(fr0[0])
+    assert m > 10
+    out = (torch.full((m + 7, 2), -1, dtype=torch.int64, device=torch_dev),
+           torch.full((m + 7,), -1.0, dtype=torch.float64, device=torch_dev))
+    best1, fr1 = ctx.points(Xd, R2=4.0, precision="bf16", out=out)
+    assert (best1.i, best1.j, best1.d2) == (best0.i, best0.j, best0.d2)
+    assert fr1[0].data_ptr() == out[0].data_ptr() and fr1[1].data_ptr() == out[1].data_ptr()
+    _check_frnn(fr1, (fr0[0].cpu().numpy(), fr0[1].cpu().numpy()))
+    _check_frnn(fr1, oracle.frnn(X, 4.0))
+    small = (torch.empty((m - 1, 2), dtype=torch.int64, device=torch_dev),
+             torch.empty((m - 1,), dtype=torch.float64, device=torch_dev))
+    with pytest.raises(cp.CpmiError, match="capacity"):
+        ctx.points(Xd, R2=4.0, precision="bf16", out=small)
+    with pytest.raises(ValueError):
+        ctx.points(Xd, R2=4.0, out=(out[0].float(), out[1]))
+    T = np.cumsum(rng.normal(0, 1, 3000)).astype(np.float32)
+    Td = _dev(T, torch_dev)
+    mb0, mf0 = ctx.motif(Td, 64, R2=9.0)
+    k = len(mf0[0])
+    out = (torch.empty((k + 3, 2), dtype=torch.int64, device=torch_dev),
+           torch.empty((k + 3,), dtype=torch.float64, device=torch_dev))
+    mb1, mf1 = ctx.motif(Td, 64, R2=9.0, out=out)
+    assert (mb1.i, mb1.j, mb1.d2) == (mb0.i, mb0.j, mb0.d2)
+    _check_frnn(mf1, (mf0[0].cpu().numpy(), mf0[1].cpu().numpy()))
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_points_strided_rows(ctx, torch_dev, prec):
     rng = np.random.default_rng(9)
