@@ -22,13 +22,13 @@ constexpr int NQ = 4;      // 16-row blocks per wave and operand
 __host__ __device__ inline int swz(int row) { return (row >> 2) & 3; }
 // Source of direct-to-LDS load (wave, q, lane): row within the tile and byte
 // column within the slice.
-__host__ __device__ inline int dma_row(int wave, int q, int lane) { return (wave * NQ + q) * 16 + (lane >> 2); }
+__host__ __device__ constexpr int dma_row(int wave, int q, int lane) { return (wave * NQ + q) * 16 + (lane >> 2); }
 __host__ __device__ inline int dma_col(int wave, int q, int lane)
 {
     return ((lane & 3) ^ swz(dma_row(wave, q, lane))) << 4;
 }
 // Destination byte in the slice's LDS block.
-__host__ __device__ inline int dma_lds(int wave, int q, int lane) { return (wave * NQ + q) * 16 * SLICE + lane * 16; }
+__host__ __device__ constexpr int dma_lds(int wave, int q, int lane) { return (wave * NQ + q) * 16 * SLICE + lane * 16; }
 // Byte position in the LDS block of (row, 16-byte chunk).
 __host__ __device__ inline int frag_lds(int row, int chunk) { return row * SLICE + ((chunk ^ swz(row)) << 4); }
 

@@ -90,6 +90,17 @@ __device__ __forceinline__ int fresh_lane()
     return l;
 }
 
+// 4 x this lane's index as a 64-bit value, both halves written by the
+// hardware at each use (so that no widened lane value is kept across loops).
+__device__ __forceinline__ uint64_t fresh_lane_bytes4()
+{
+    uint32_t lo, hi;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0\n\t"
+                 "v_lshlrev_b32 %0, 2, %0\n\tv_mov_b32 %1, 0"
+                 : "=&v"(lo), "=v"(hi));
+    return (uint64_t)hi << 32 | lo;
+}
+
 // Minimum over the wave, returned in every lane: within each row of 16 lanes
 // by DPP steps (lane pairs, then quad pairs, then row-half and row mirrors:
 // every lane ends with its row's minimum), then the four rows through
@@ -207,22 +218,31 @@ __device__ __forceinline__ TileAddr tile_addr(const ScreenArgs &args, uint64_t e
 // The 8 direct-to-LDS loads of one wave for K slice s of a tile (4 blocks of
 // 16 rows per operand). The operand is slice-major per 256-row block
 // (layout256.h: xs_offset), so slice s of the tile's rows is 16 KB of
-// consecutive memory and each load reads 1 KB of it.
+// consecutive memory and each load reads 1 KB of it. The wave's four blocks
+// lie 1 KB apart both in memory and in the stage, so they share one address
+// pair and differ in the instruction offset, which the hardware adds to the
+// global and to the LDS address alike.
 __device__ __forceinline__ void issue_slice(const TileAddr &ta, int s, int wave, unsigned char *__restrict__ wr)
 {
+    static_assert(l256::dma_lds(0, 1, 0) - l256::dma_lds(0, 0, 0) == 1024 &&
+                      (l256::dma_row(0, 1, 0) - l256::dma_row(0, 0, 0)) * SL == 1024 && l256::NQ == 4,
+                  "a wave's four blocks lie 1 KB apart in the stage and in the operand");
     unsigned char *la = wr;
     unsigned char *lb = wr + OPB;
     // (row within a 16-row block) * SL + swizzled column; the column swizzle
     // of a lane does not depend on the block (layout256.h)
     const int lane = fresh_lane();
     const uint32_t lane_off = (uint32_t)l256::dma_row(0, 0, lane) * SL + (uint32_t)l256::dma_col(0, 0, lane);
-#pragma unroll
-    for (int q = 0; q < l256::NQ; ++q) {
-        const uint32_t rb = (uint32_t)s * (T256 * SL) + (uint32_t)l256::dma_row(wave, q, 0) * SL;
-        const int ldst = l256::dma_lds(wave, q, 0);
-        __builtin_amdgcn_global_load_lds((g_void *)(ta.ga + rb + lane_off), (lds_void *)(la + ldst), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds((g_void *)(ta.gb + rb + lane_off), (lds_void *)(lb + ldst), 16, 0, 0);
-    }
+    const uint32_t rb = (uint32_t)s * (T256 * SL) + (uint32_t)l256::dma_row(wave, 0, 0) * SL;
+    const int ldst = l256::dma_lds(wave, 0, 0);
+    __builtin_amdgcn_global_load_lds((g_void *)(ta.ga + rb + lane_off), (lds_void *)(la + ldst), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((g_void *)(ta.ga + rb + lane_off), (lds_void *)(la + ldst), 16, 1024, 0);
+    __builtin_amdgcn_global_load_lds((g_void *)(ta.ga + rb + lane_off), (lds_void *)(la + ldst), 16, 2048, 0);
+    __builtin_amdgcn_global_load_lds((g_void *)(ta.ga + rb + lane_off), (lds_void *)(la + ldst), 16, 3072, 0);
+    __builtin_amdgcn_global_load_lds((g_void *)(ta.gb + rb + lane_off), (lds_void *)(lb + ldst), 16, 0, 0);
+    __builtin_amdgcn_global_load_lds((g_void *)(ta.gb + rb + lane_off), (lds_void *)(lb + ldst), 16, 1024, 0);
+    __builtin_amdgcn_global_load_lds((g_void *)(ta.gb + rb + lane_off), (lds_void *)(lb + ldst), 16, 2048, 0);
+    __builtin_amdgcn_global_load_lds((g_void *)(ta.gb + rb + lane_off), (lds_void *)(lb + ldst), 16, 3072, 0);
 }
 
 // Scheduling masks of __builtin_amdgcn_sched_group_barrier.
@@ -403,15 +423,14 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
             // 64 rows x 8 bytes of block I and of block J: two 256-byte loads each
             const unsigned char *fb = (const unsigned char *)Q.fold;
             uint32_t *dst = sh_w + half * (2 * T256 * 2);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                __builtin_amdgcn_global_load_lds(
-                    (g_void *)(fb + ((int64_t)tile_I(e) * T256 + wave * 64) * 8 + h * 256 + lo),
-                    (lds_void *)(dst + wave * 128 + h * 64), 4, 0, 0);
-                __builtin_amdgcn_global_load_lds(
-                    (g_void *)(fb + ((int64_t)tile_J(e) * T256 + wave * 64) * 8 + h * 256 + lo),
-                    (lds_void *)(dst + 2 * T256 + wave * 128 + h * 64), 4, 0, 0);
-            }
+            // (the second 256 bytes of each by the instruction offset, which
+            // moves the global and the LDS address alike)
+            const unsigned char *gi = fb + ((int64_t)tile_I(e) * T256 + wave * 64) * 8 + lo;
+            const unsigned char *gj = fb + ((int64_t)tile_J(e) * T256 + wave * 64) * 8 + lo;
+            __builtin_amdgcn_global_load_lds((g_void *)gi, (lds_void *)(dst + wave * 128), 4, 0, 0);
+            __builtin_amdgcn_global_load_lds((g_void *)gi, (lds_void *)(dst + wave * 128), 4, 256, 0);
+            __builtin_amdgcn_global_load_lds((g_void *)gj, (lds_void *)(dst + 2 * T256 + wave * 128), 4, 0, 0);
+            __builtin_amdgcn_global_load_lds((g_void *)gj, (lds_void *)(dst + 2 * T256 + wave * 128), 4, 256, 0);
         } else {
             const unsigned char *sb = (const unsigned char *)Q.shat;
             S *dst = sh_s + half * (2 * T256);
@@ -422,12 +441,16 @@ __global__ __launch_bounds__(256, 1) __attribute__((amdgpu_waves_per_eu(1, 1))) 
         }
         if constexpr (MASKED) {
             if (Q.perm && Q.motif) {
-                // the permutation is padded to whole blocks by the host
+                // the permutation is padded to whole blocks by the host; the
+                // lane's byte offset is rebuilt here as a 64-bit value (a
+                // widened one kept from elsewhere would be held, and spilled,
+                // across the tile loop)
                 const unsigned char *pb = (const unsigned char *)Q.perm;
                 int32_t *od = sh_o + half * (2 * T256);
-                __builtin_amdgcn_global_load_lds((g_void *)(pb + ((int64_t)tile_I(e) * T256 + wave * 64) * 4 + lo),
+                const uint64_t lo64 = fresh_lane_bytes4();
+                __builtin_amdgcn_global_load_lds((g_void *)(pb + ((int64_t)tile_I(e) * T256 + wave * 64) * 4 + lo64),
                                                  (lds_void *)(od + wave * 64), 4, 0, 0);
-                __builtin_amdgcn_global_load_lds((g_void *)(pb + ((int64_t)tile_J(e) * T256 + wave * 64) * 4 + lo),
+                __builtin_amdgcn_global_load_lds((g_void *)(pb + ((int64_t)tile_J(e) * T256 + wave * 64) * 4 + lo64),
                                                  (lds_void *)(od + T256 + wave * 64), 4, 0, 0);
             }
         }
