@@ -180,3 +180,32 @@ def test_bound_adversarial(ctx, torch_dev, kind, prec, tile):
     nT = (X.shape[0] + tile - 1) // tile
     tiles = [(I, J) for I in range(nT) for J in range(I, nT)]
     _check(ctx, kind, torch.from_numpy(X).to(torch_dev), _points_rows(X), tiles, tile, prec)
+
+
+@pytest.mark.parametrize("prec,d,dpad", [("bf16", 64, 128), ("f32", 32, 64), ("f32", 96, 128), ("i8", 100, 250)])
+def test_rows_of_two_slice_pairs_screen_like_zero_padded_rows(ctx, torch_dev, prec, d, dpad):
+    """Rows of 4k + 2 K slices of the 256-tile screen (its K2 form, whose
+    tiles start at either half of the load ring) give the same screen value in
+    every element as the same rows zero-padded by the caller to a whole number
+    of ring turns (the form without K2): the padding adds exact zero products.
+    600 listed tiles, so that most work-groups screen two or three of them in a
+    row and the ring stage alternates between tiles. The verifier's canonical
+    d2 of every pair is the same too (appended zeros add +0 to each term sum).
+    """
+    import torch
+    rng = np.random.default_rng(d * 7 + dpad)
+    n = 256 * 40
+    if prec == "i8":
+        X = rng.integers(0, 3, (n, d)).astype(np.int8)
+    else:
+        X = rng.normal(0, 1, (n, d)).astype(np.float32)
+    Xp = np.zeros((n, dpad), dtype=X.dtype)
+    Xp[:, :d] = X
+    tiles = _tiles(rng, n, 256, 600)
+    assert len(tiles) == 600
+    src = torch.from_numpy(X).to(torch_dev)
+    srcp = torch.from_numpy(Xp).to(torch_dev)
+    dump, d2, _, _ = ctx.dbg_screen_sample(src, tiles, 256, precision=prec)
+    dump_p, d2_p, _, _ = ctx.dbg_screen_sample(srcp, tiles, 256, precision=prec)
+    assert torch.equal(dump, dump_p)
+    assert torch.equal(torch.nan_to_num(d2, nan=-1.0), torch.nan_to_num(d2_p, nan=-1.0))
